@@ -1,0 +1,467 @@
+"""FP64 CPU oracle of the Reinforced-Dynamics neural-bias hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the package smoke check and
+the benchmark's CPU-baseline leg may import this module.  It is plain, slow
+and written to be checked by eye against the paper: numpy in float64, the
+batch axis vectorised, no blocking, fusion or reordering beyond what each
+definition states.  It shares no code with the GPU library.
+
+Paper: "RiD-kit: Software package designed to do enhanced sampling using
+reinforced dynamics" (arXiv 2408.14070).  Sections cited by name.  Where the
+paper does not print a formula the reading taken is stated in the function
+and listed (Z-numbers) with the other readings in the design notes.
+
+Functions and what pins them (tests/test_oracle_*.py):
+
+  dihedral            torsion CVs ("CV selection", torsion mode)
+                      pinned: closed-form geometry, NeRF round trip,
+                      rigid-motion invariance
+  dihedral_jacobian   ds/dr (chain rule the bias uses to reach atoms)
+                      pinned: central finite differences, zero net force and
+                      torque per dihedral
+  embed               [cos s | sin s] periodic input encoding
+                      pinned: 2pi periodicity of every downstream output
+  mlp_value_and_grad  free-energy MLP A(x) and dA/dx ("Training phase":
+                      MLP of `neurons` widths, tanh)
+                      pinned: closed forms for zero and one hidden layer,
+                      finite differences of A in x
+  ensemble_mean_force per-model mean force dA_k/ds (Box 2: F = grad_s A)
+                      pinned: closed form for a linear model, FD in s
+  model_deviation     ensemble standard deviation of the mean forces
+                      ("Development of the protocol"; "Training phase")
+                      pinned: identical members give exactly 0, K=2 closed
+                      form, permutation invariance
+  switch              trust-level switch ("Overall workflow setting")
+                      pinned: limits, midpoint, monotone, continuity
+  bias_force          whole path, atoms -> forces
+                      pinned: force = -grad E by FD (sigma frozen), zero
+                      total force and torque per walker
+  train_loss_grad     gradient of the mean-force loss in the weights
+                      pinned: central FD on every parameter; exact least-
+                      squares solution of the linear model has zero gradient
+  adam_step / lr_at   optimiser and exponential LR decay ("Training phase")
+                      pinned: one-step closed form; convergence on the linear
+                      model to the analytic optimum
+  mf_label            restrained-MD mean-force estimate ("Labeling phase")
+                      pinned: Gaussian-frame closed form within 4 sigma, the
+                      periodic wrap example, block standard error of iid
+                      blocks
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Default trust levels and optimiser schedule printed in the paper's example
+# configuration ("Overall workflow setting", "Training phase").
+TRUST_LVL_1 = 2.0
+TRUST_LVL_2 = 3.0
+INIT_LR = 8e-4
+DECAY_STEPS = 120
+DECAY_RATE = 0.96
+ADAM_B1, ADAM_B2, ADAM_EPS = 0.9, 0.999, 1e-8
+# Tolerance below which |n1|^2 or |n2|^2 marks a dihedral as degenerate (nm^4).
+DEGENERATE_TOL = 1e-12
+
+
+# --------------------------------------------------------------------------
+# a1: torsion collective variables
+# --------------------------------------------------------------------------
+def _gather(pos, quads):
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.asarray(quads, dtype=np.int64)
+    return pos[:, q[:, 0]], pos[:, q[:, 1]], pos[:, q[:, 2]], pos[:, q[:, 3]]
+
+
+def dihedral(pos, quads):
+    """Torsion angle s in (-pi, pi] of each quad (a, b, c, d), per walker.
+
+    The paper's torsion CVs are backbone phi/psi ("CV selection").  Convention
+    (IUPAC, as the MD engines use): b1 = r_b - r_a, b2 = r_c - r_b,
+    b3 = r_d - r_c, n1 = b1 x b2, n2 = b2 x b3,
+    s = atan2(|b2| b1 . n2, n1 . n2).
+
+    pos: [B][n_atoms][3]; quads: [n][4] 0-based.  Returns s [B][n].
+    """
+    ra, rb, rc, rd = _gather(pos, quads)
+    b1, b2, b3 = rb - ra, rc - rb, rd - rc
+    n1 = np.cross(b1, b2)
+    n2 = np.cross(b2, b3)
+    X = np.sum(n1 * n2, axis=-1)
+    Y = np.linalg.norm(b2, axis=-1) * np.sum(b1 * n2, axis=-1)
+    return np.arctan2(Y, X)
+
+
+def degenerate(pos, quads, tol=DEGENERATE_TOL):
+    """[B][n] bool: dihedral whose |n1|^2 or |n2|^2 is below ``tol``."""
+    ra, rb, rc, rd = _gather(pos, quads)
+    b1, b2, b3 = rb - ra, rc - rb, rd - rc
+    n1 = np.cross(b1, b2)
+    n2 = np.cross(b2, b3)
+    return (np.sum(n1 * n1, -1) < tol) | (np.sum(n2 * n2, -1) < tol)
+
+
+def dihedral_jacobian(pos, quads):
+    """ds/dr for the four atoms of every dihedral: [B][n][4][3].
+
+    Closed form of the torsion gradient (Blondel & Karplus 1996) written in
+    the b1, b2, b3 notation of ``dihedral``:
+      ds/dr_a = -|b2| n1 / |n1|^2
+      ds/dr_d = +|b2| n2 / |n2|^2
+      ds/dr_b = (|b2| + b1.b2/|b2|) n1/|n1|^2 + (b3.b2/|b2|) n2/|n2|^2
+      ds/dr_c = -(|b2| + b3.b2/|b2|) n2/|n2|^2 - (b1.b2/|b2|) n1/|n1|^2
+    Degenerate dihedrals (see ``degenerate``) get a zero Jacobian.
+    """
+    ra, rb, rc, rd = _gather(pos, quads)
+    b1, b2, b3 = rb - ra, rc - rb, rd - rc
+    n1 = np.cross(b1, b2)
+    n2 = np.cross(b2, b3)
+    nn1 = np.sum(n1 * n1, -1, keepdims=True)
+    nn2 = np.sum(n2 * n2, -1, keepdims=True)
+    bad = (nn1 < DEGENERATE_TOL) | (nn2 < DEGENERATE_TOL)
+    nn1 = np.where(bad, 1.0, nn1)
+    nn2 = np.where(bad, 1.0, nn2)
+    lb2 = np.linalg.norm(b2, axis=-1, keepdims=True)
+    p1 = np.sum(b1 * b2, -1, keepdims=True) / lb2
+    p3 = np.sum(b3 * b2, -1, keepdims=True) / lb2
+    ga = -lb2 * n1 / nn1
+    gd = lb2 * n2 / nn2
+    gb = (lb2 + p1) * n1 / nn1 + p3 * n2 / nn2
+    gc = -(lb2 + p3) * n2 / nn2 - p1 * n1 / nn1
+    J = np.stack([ga, gb, gc, gd], axis=2)
+    return np.where(bad[..., None], 0.0, J)
+
+
+def apply_cv_force(pos, quads, fcv, n_atoms=None):
+    """Atomic forces F_a = sum_i f_i ds_i/dr_a.  fcv: [B][n] -> [B][N][3]."""
+    pos = np.asarray(pos, dtype=np.float64)
+    B, N, _ = pos.shape
+    J = dihedral_jacobian(pos, quads)
+    F = np.zeros((B, N if n_atoms is None else n_atoms, 3))
+    q = np.asarray(quads, dtype=np.int64)
+    f = np.asarray(fcv, dtype=np.float64)
+    for i in range(q.shape[0]):          # plain accumulation, CV by CV
+        for slot in range(4):
+            F[:, q[i, slot]] += f[:, i, None] * J[:, i, slot]
+    return F
+
+
+# --------------------------------------------------------------------------
+# a2/a3: ensemble of MLP free-energy models
+# --------------------------------------------------------------------------
+def embed(s):
+    """Periodic input encoding x = [cos s_1..cos s_n | sin s_1..sin s_n]."""
+    s = np.asarray(s, dtype=np.float64)
+    return np.concatenate([np.cos(s), np.sin(s)], axis=-1)
+
+
+def mlp_value_and_grad(model, x):
+    """One free-energy model: A(x) and dA/dx.
+
+    model = (Ws, bs, wo, bo): h_0 = x, h_l = tanh(W_l h_{l-1} + b_l),
+    A = wo . h_L + bo.  Reverse sweep: u_L = wo, v_l = u_l * (1 - h_l^2),
+    u_{l-1} = W_l^T v_l; dA/dx = u_0.  x: [B][D] -> (A [B], u0 [B][D]).
+    """
+    Ws, bs, wo, bo = model
+    hs = [np.asarray(x, dtype=np.float64)]
+    for W, b in zip(Ws, bs):
+        hs.append(np.tanh(hs[-1] @ W.T + b))
+    A = hs[-1] @ wo + bo
+    u = np.broadcast_to(wo, hs[-1].shape)
+    for l in range(len(Ws), 0, -1):
+        v = u * (1.0 - hs[l] ** 2)
+        u = v @ Ws[l - 1]
+    return A, u
+
+
+def mean_force_from_input_grad(s, u0):
+    """Chain dA/dx to the angles: g_i = -sin s_i u0[i] + cos s_i u0[n+i]."""
+    s = np.asarray(s, dtype=np.float64)
+    n = s.shape[-1]
+    return -np.sin(s) * u0[..., :n] + np.cos(s) * u0[..., n:]
+
+
+def ensemble_mean_force(models, s):
+    """Per-model free energy and mean force (Box 2: F(s) = grad_s A(s)).
+
+    s: [B][n] -> (A [B][K], g [B][K][n])."""
+    x = embed(s)
+    As, gs = [], []
+    for m in models:
+        A, u0 = mlp_value_and_grad(m, x)
+        As.append(A)
+        gs.append(mean_force_from_input_grad(s, u0))
+    return np.stack(As, axis=1), np.stack(gs, axis=1)
+
+
+# --------------------------------------------------------------------------
+# a4/a5: model deviation and trust-level switch
+# --------------------------------------------------------------------------
+def model_deviation(g):
+    """Ensemble mean force and model deviation.
+
+    The paper takes the standard deviation of the ensemble's predictions as
+    the uncertainty indicator.  Reading: population standard deviation of
+    the K mean-force vectors, i.e. eps = sqrt((1/K) sum_k |g_k - gbar|^2),
+    evaluated with a shift by member 0 (d_k = g_k - g_0) so identical members
+    give exactly zero.  g: [B][K][n] -> (gbar [B][n], eps [B])."""
+    g = np.asarray(g, dtype=np.float64)
+    gbar = np.mean(g, axis=1)
+    d = g - g[:, :1, :]
+    dbar = np.mean(d, axis=1, keepdims=True)
+    eps = np.sqrt(np.mean(np.sum((d - dbar) ** 2, axis=-1), axis=1))
+    return gbar, eps
+
+
+def switch(eps, eps0, eps1):
+    """Trust-level switch sigma(eps) and regime r.
+
+    trust_lvl_1 (eps0) and trust_lvl_2 (eps1) bound the trust level; the bias
+    acts only where the uncertainty is low.  Reading: sigma = 1 below eps0,
+    0 at or above eps1, and 1/2 (1 + cos(pi (eps-eps0)/(eps1-eps0))) between.
+    Regime 0 = full bias, 1 = switching band (eps0 <= eps < eps1),
+    2 = unbiased."""
+    eps = np.asarray(eps, dtype=np.float64)
+    t = (eps - eps0) / (eps1 - eps0)
+    mid = 0.5 * (1.0 + np.cos(math.pi * t))
+    sigma = np.where(eps < eps0, 1.0, np.where(eps >= eps1, 0.0, mid))
+    regime = np.where(eps < eps0, 0, np.where(eps >= eps1, 2, 1)).astype(np.int8)
+    return sigma, regime
+
+
+def bias_force(pos, quads, models, eps0, eps1, n_atoms=None):
+    """Whole bias path for a batch of walkers.
+
+    Bias energy E = -sigma(eps) * Abar (the inverted predicted PMF, only where
+    the ensemble agrees); CV force f = sigma * gbar (sigma held fixed in the
+    step); atomic force F_a = sum_i f_i ds_i/dr_a.
+
+    Returns dict(F [B][N][3], E [B], eps [B], sigma [B], regime [B], s [B][n],
+    A [B][K], g [B][K][n], gbar [B][n], flags [B])."""
+    s = dihedral(pos, quads)
+    A, g = ensemble_mean_force(models, s)
+    gbar, eps = model_deviation(g)
+    sigma, regime = switch(eps, eps0, eps1)
+    E = -sigma * np.mean(A, axis=1)
+    fcv = sigma[:, None] * gbar
+    F = apply_cv_force(pos, quads, fcv, n_atoms)
+    flags = np.any(degenerate(pos, quads), axis=1).astype(np.uint8)
+    return dict(F=F, E=E, eps=eps, sigma=sigma, regime=regime, s=s, A=A, g=g,
+                gbar=gbar, flags=flags)
+
+
+def bias_energy_frozen(pos, quads, models, sigma):
+    """E(r) = -sigma Abar(s(r)) with sigma given (finite-difference target)."""
+    s = dihedral(pos, quads)
+    A, _ = ensemble_mean_force(models, s)
+    return -np.asarray(sigma) * np.mean(A, axis=1)
+
+
+# --------------------------------------------------------------------------
+# a7: mean-force fitting, double backward, Adam
+# --------------------------------------------------------------------------
+def train_loss_grad(model, s, F):
+    """Loss L = (1/B) sum_b |g(s_b) - F_b|^2 of one model and its gradient.
+
+    The models are trained to predict mean forces ("Training phase"), i.e.
+    the network's CV-gradient is fitted to the labels.  Since
+    dL = sum_b rho_b . dg_b with rho_b = 2 (g_b - F_b)/B, the parameter
+    gradient is that of the directional derivative J = sum_b rho_x,b . dA/dx
+    (rho_x = rho mapped to x: [-sin s rho | cos s rho]) with rho_x held fixed:
+      tangent:  hd_0 = rho_x, zd_l = W_l hd_{l-1}, hd_l = (1-h_l^2) zd_l,
+                J = wo . hd_L
+      adjoint:  lam_hd_L = wo, lam_h_L = 0; for l = L..1:
+                lam_zd = (1-h_l^2) lam_hd;  lam_h += -2 h_l zd_l lam_hd
+                lam_z  = (1-h_l^2) lam_h
+                dW_l = lam_z h_{l-1}^T + lam_zd hd_{l-1}^T;  db_l = lam_z
+                lam_hd_{l-1} = W_l^T lam_zd;  lam_h_{l-1} = W_l^T lam_z
+      dwo = hd_L;  dbo = 0 (the constant never reaches grad_s A).
+    Returns (loss, (dWs, dbs, dwo, dbo)), all summed over the batch.
+    """
+    Ws, bs, wo, bo = model
+    s = np.asarray(s, dtype=np.float64)
+    F = np.asarray(F, dtype=np.float64)
+    B, n = s.shape
+    x = embed(s)
+    A, u0 = mlp_value_and_grad(model, x)
+    g = mean_force_from_input_grad(s, u0)
+    r = g - F
+    loss = float(np.sum(r * r) / B)
+    rho = 2.0 * r / B
+    rho_x = np.concatenate([-np.sin(s) * rho, np.cos(s) * rho], axis=-1)
+    # primal activations
+    hs = [x]
+    for W, b in zip(Ws, bs):
+        hs.append(np.tanh(hs[-1] @ W.T + b))
+    # tangent forward
+    hds = [rho_x]
+    zds = [None]
+    for l, W in enumerate(Ws, start=1):
+        zd = hds[-1] @ W.T
+        zds.append(zd)
+        hds.append((1.0 - hs[l] ** 2) * zd)
+    L = len(Ws)
+    dWs = [None] * L
+    dbs = [None] * L
+    dwo = np.sum(hds[L], axis=0)
+    lam_hd = np.broadcast_to(wo, hds[L].shape)
+    lam_h = np.zeros_like(hs[L])
+    for l in range(L, 0, -1):
+        dl = 1.0 - hs[l] ** 2
+        lam_zd = dl * lam_hd
+        lam_h = lam_h - 2.0 * hs[l] * zds[l] * lam_hd
+        lam_z = dl * lam_h
+        dWs[l - 1] = lam_z.T @ hs[l - 1] + lam_zd.T @ hds[l - 1]
+        dbs[l - 1] = np.sum(lam_z, axis=0)
+        lam_hd = lam_zd @ Ws[l - 1]
+        lam_h = lam_z @ Ws[l - 1]
+    return loss, (dWs, dbs, dwo, 0.0)
+
+
+def train_loss(model, s, F):
+    """Loss only (finite-difference target)."""
+    A, g = ensemble_mean_force([model], s)
+    r = g[:, 0, :] - np.asarray(F, dtype=np.float64)
+    return float(np.sum(r * r) / r.shape[0])
+
+
+def lr_at(step, init_lr=INIT_LR, decay_steps=DECAY_STEPS, decay_rate=DECAY_RATE):
+    """Exponential learning-rate decay, continuous form:
+    lr = init_lr * decay_rate ** (step / decay_steps); step counts updates
+    already taken (0 for the first)."""
+    return init_lr * decay_rate ** (step / decay_steps)
+
+
+def adam_step(theta, grad, m, v, t, lr, b1=ADAM_B1, b2=ADAM_B2, eps=ADAM_EPS):
+    """One Adam update (bias-corrected); t is the 1-based update count.
+    Returns (theta', m', v')."""
+    theta = np.asarray(theta, dtype=np.float64)
+    grad = np.asarray(grad, dtype=np.float64)
+    m = b1 * m + (1.0 - b1) * grad
+    v = b2 * v + (1.0 - b2) * grad * grad
+    mhat = m / (1.0 - b1 ** t)
+    vhat = v / (1.0 - b2 ** t)
+    return theta - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def flat_grad(grads):
+    """Flatten a (dWs, dbs, dwo, dbo) tuple in the packed parameter order."""
+    dWs, dbs, dwo, dbo = grads
+    parts = []
+    for dW, db in zip(dWs, dbs):
+        parts += [np.ravel(dW), np.ravel(db)]
+    parts += [np.ravel(dwo), np.atleast_1d(float(dbo))]
+    return np.concatenate(parts)
+
+
+def flat_model(model):
+    Ws, bs, wo, bo = model
+    parts = []
+    for W, b in zip(Ws, bs):
+        parts += [np.ravel(W), np.ravel(b)]
+    parts += [np.ravel(wo), np.atleast_1d(float(bo))]
+    return np.concatenate(parts).astype(np.float64)
+
+
+def unflat_model(flat, n_in, widths):
+    p = np.asarray(flat, dtype=np.float64)
+    Ws, bs = [], []
+    off, prev = 0, n_in
+    for w in widths:
+        Ws.append(p[off:off + w * prev].reshape(w, prev)); off += w * prev
+        bs.append(p[off:off + w]); off += w
+        prev = w
+    wo = p[off:off + prev]; off += prev
+    bo = float(p[off])
+    return (Ws, bs, wo, bo)
+
+
+def train_step(models, s, F, states, lr):
+    """One mean-force fitting step for every member (same minibatch, models
+    independent).  states: list of (m, v, t) per model (t = updates done).
+    Returns (new_models, new_states, losses [K])."""
+    new_models, new_states, losses = [], [], []
+    widths = [W.shape[0] for W in models[0][0]]
+    n_in = models[0][0][0].shape[1] if models[0][0] else models[0][2].size
+    for model, (m, v, t) in zip(models, states):
+        loss, grads = train_loss_grad(model, s, F)
+        theta, m2, v2 = adam_step(flat_model(model), flat_grad(grads), m, v,
+                                  t + 1, lr)
+        new_models.append(unflat_model(theta, n_in, widths))
+        new_states.append((m2, v2, t + 1))
+        losses.append(loss)
+    return new_models, new_states, np.asarray(losses)
+
+
+# --------------------------------------------------------------------------
+# a8: restrained-MD mean-force labels
+# --------------------------------------------------------------------------
+def wrap_angle(d):
+    """Map a difference of two angles in (-2pi, 2pi) to (-pi, pi]."""
+    d = np.asarray(d, dtype=np.float64)
+    d = np.where(d > math.pi, d - 2.0 * math.pi, d)
+    return np.where(d <= -math.pi, d + 2.0 * math.pi, d)
+
+
+def _neumaier_sum(terms, axis):
+    """Compensated (Neumaier) summation along ``axis``, term by term."""
+    terms = np.moveaxis(np.asarray(terms, dtype=np.float64), axis, 0)
+    s = np.zeros(terms.shape[1:])
+    c = np.zeros(terms.shape[1:])
+    for t in terms:
+        tot = s + t
+        c += np.where(np.abs(s) >= np.abs(t), (s - tot) + t, (t - tot) + s)
+        s = tot
+    return s + c
+
+
+def mf_label(traj, s0, kappa, mask, std_threshold, n_blocks=10):
+    """Mean force from a restrained trajectory ("Labeling phase").
+
+    Under a stiff harmonic restraint kappa/2 (s - s0)^2 the mean force is the
+    average spring force: F_i = kappa_i * mean_t wrap(s0_i - s_{t,i}) (wrap to
+    (-pi, pi] for periodic CVs, mask 1).  Convergence: the frames are split
+    into n_blocks equal blocks of floor(T/n_blocks) frames (the tail frames
+    are left out of the blocks only); SE_i = std of the block means
+    (n_blocks - 1 in the denominator) / sqrt(n_blocks).  A configuration is
+    kept when max_i SE_i <= std_threshold.
+
+    traj [M][T][n], s0 [M][n], kappa [n], mask [n] ->
+    (F [M][n], SE [M][n], keep [M] uint8)."""
+    traj = np.asarray(traj, dtype=np.float64)
+    s0 = np.asarray(s0, dtype=np.float64)
+    kappa = np.asarray(kappa, dtype=np.float64)
+    mask = np.asarray(mask).astype(bool)
+    M, T, n = traj.shape
+    diff = s0[:, None, :] - traj
+    diff = np.where(mask, wrap_angle(diff), diff)
+    spring = kappa * diff
+    F = _neumaier_sum(spring, axis=1) / T
+    bsz = T // n_blocks
+    blocks = spring[:, :bsz * n_blocks].reshape(M, n_blocks, bsz, n)
+    bmean = _neumaier_sum(blocks, axis=2) / bsz
+    bbar = np.mean(bmean, axis=1, keepdims=True)
+    var = np.sum((bmean - bbar) ** 2, axis=1) / (n_blocks - 1)
+    SE = np.sqrt(var / n_blocks)
+    keep = (np.max(SE, axis=1) <= std_threshold).astype(np.uint8)
+    return F, SE, keep
+
+
+# --------------------------------------------------------------------------
+# comparison metrics
+# --------------------------------------------------------------------------
+def max_rel_err(test, ref):
+    """max over walkers of max|test - ref| / max|ref| (normwise per walker)."""
+    test = np.asarray(test, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    B = ref.shape[0]
+    d = np.abs(test - ref).reshape(B, -1).max(axis=1)
+    r = np.abs(ref).reshape(B, -1).max(axis=1)
+    return float(np.max(d / np.where(r > 0, r, 1.0)))
+
+
+def rms_rel_err(test, ref):
+    test = np.asarray(test, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(test - ref) / max(np.linalg.norm(ref), 1e-300))
