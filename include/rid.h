@@ -1,0 +1,251 @@
+/*
+ * rid.h - C ABI of the Reinforced-Dynamics neural-bias hot path on MI355X.
+ *
+ * Method: "RiD-kit: Software package designed to do enhanced sampling using
+ * reinforced dynamics" (arXiv 2408.14070).  Sections are cited by name.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units        nm, rad, kJ/mol (GROMACS units, as in the paper's examples).
+ * Pointers     d_* are DEVICE pointers (hipMalloc'd or torch CUDA tensors),
+ *              owned by the caller; the library never frees or retains them
+ *              beyond the call.  Host arrays are read during the call only.
+ * Layouts      row-major, contiguous, FP32 unless stated.  B = walkers (or
+ *              samples) in the call, n = number of CVs, K = ensemble size.
+ * Streams      rid_stream is a hipStream_t (NULL = legacy default stream).
+ *              Every call after *_create is asynchronous on that stream:
+ *              it validates its arguments on the host, enqueues kernels and
+ *              returns.  create/destroy/get/set synchronise.
+ * Work memory  a handle owns scratch memory for intermediates (grown on
+ *              demand, RID_ENOMEM on failure).  Calls that share a handle
+ *              must be ordered on one stream by the caller.
+ * Errors       no exception crosses the ABI.  A non-OK status leaves outputs
+ *              untouched and sets a thread-local message (rid_last_error).
+ *              Device-side conditions (degenerate dihedrals) are reported
+ *              through per-walker flags, never through the status.
+ * Precision    see rid_precision.  The ensemble-variance reduction and the
+ *              mean-force label averaging always run in FP64 on the device.
+ */
+#ifndef RID_H
+#define RID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RID_OK = 0,
+  RID_EINVAL = -1,        /* bad argument: NULL, size, threshold order, index */
+  RID_ENOMEM = -2,        /* device allocation failed                         */
+  RID_EDEVICE = -3,       /* HIP runtime error (launch, copy, no device)      */
+  RID_EDEGENERATE = -4,   /* reserved: degenerate geometry (flags are used)   */
+  RID_EUNSUPPORTED = -5   /* shape outside the compiled kernel family         */
+} rid_status;
+
+typedef enum {
+  RID_FP32 = 0,  /* every GEMM on FP32 MFMA, FP32 activations               */
+  RID_BF16 = 1,  /* hidden GEMMs on BF16 MFMA with FP32 accumulation; BF16
+                    weights and activations; CV geometry, tanh derivatives
+                    and the switch in FP32; ensemble variance in FP64        */
+  RID_FP16 = 2   /* as RID_BF16 with FP16 operands (same MFMA rate, 3 more
+                    mantissa bits); needs |weights|, |activations| < 65504   */
+} rid_precision;
+
+typedef struct rid_system_s* rid_system;
+typedef struct rid_ensemble_s* rid_ensemble;
+typedef void* rid_stream;
+
+/* Thread-local text of the last non-OK status of this thread. */
+const char* rid_last_error(void);
+
+/* Library version string. */
+const char* rid_version(void);
+
+/* ------------------------------------------------------------------------
+ * Systems: atoms and torsion CVs ("CV selection": backbone phi/psi of the
+ * selected residues, 2n-2 torsions for n residues, periodic over 2 pi).
+ *
+ * quads         host int32 [n_cv][4], 0-based atom indices (a, b, c, d) of
+ *               each torsion; the torsion is
+ *               s = atan2(|b2| b1.(b2 x b3), (b1 x b2).(b2 x b3)) with
+ *               b1 = r_b - r_a, b2 = r_c - r_b, b3 = r_d - r_c, in (-pi, pi].
+ * angular_mask  host uint8 [n_cv] or NULL (= all 1).  The torsion path
+ *               needs every entry 1 (RID_EUNSUPPORTED otherwise).
+ * Errors        RID_EINVAL for n_atoms < 1, n_cv < 1, an index outside
+ *               [0, n_atoms) or a quad that repeats an atom.
+ * ------------------------------------------------------------------------ */
+rid_status rid_system_create(int n_atoms, int n_cv, const int32_t* quads,
+                             const uint8_t* angular_mask, rid_system* out);
+void rid_system_destroy(rid_system sys);
+
+/* ------------------------------------------------------------------------
+ * Ensembles of MLP free-energy models ("Training phase": numb_models MLPs
+ * of `neurons` hidden widths, tanh; numb_models > 1 for a model deviation).
+ * Input of every model is the periodic encoding x = [cos s | sin s]
+ * (length 2 n_cv); output is the scalar free energy A.
+ *
+ * params  host FP32, packed: for each model k, for each hidden layer l,
+ *         W_l row-major [width_l][width_{l-1}] then b_l [width_l]; then
+ *         w_o [width_L] and b_o [1].  rid_packed_param_count gives the size.
+ *         The library re-lays the weights out on the device (MFMA fragment
+ *         order, zero-padded widths, BF16 copies) and keeps FP32 masters
+ *         plus Adam moments for training.
+ * Limits  1 <= n_hidden <= 6, 1 <= width <= 512, 1 <= n_models <= 64,
+ *         1 <= n_cv <= 256 (RID_EUNSUPPORTED outside).
+ * ------------------------------------------------------------------------ */
+size_t rid_packed_param_count(int n_cv, int n_models, int n_hidden,
+                              const int* widths);
+rid_status rid_ensemble_create(int n_cv, int n_models, int n_hidden,
+                               const int* widths, rid_precision prec,
+                               const float* params, rid_ensemble* out);
+/* Checkpoint: copy the FP32 master parameters out / in (packed layout).
+ * set_params also resets the Adam moments and step counter. */
+rid_status rid_ensemble_get_params(rid_ensemble ens, float* host_params);
+rid_status rid_ensemble_set_params(rid_ensemble ens, const float* host_params);
+/* Number of Adam updates taken so far. */
+int64_t rid_ensemble_step(rid_ensemble ens);
+void rid_ensemble_destroy(rid_ensemble ens);
+
+/* ------------------------------------------------------------------------
+ * rid_cv_eval - torsion CVs of B walkers ("CV selection").
+ *   d_pos  [B][n_atoms][3]   atom positions (whole molecules, no PBC)
+ *   d_s    [B][n_cv]         torsions in (-pi, pi]
+ *   d_x    [B][2 n_cv] or NULL: [cos s | sin s], computed from the geometry
+ *          (cos s = X/sqrt(X^2+Y^2), sin s = Y/sqrt(X^2+Y^2)).
+ * A degenerate torsion (|b1 x b2|^2 or |b2 x b3|^2 < 1e-12 nm^4) gives
+ * s = 0, x = (1, 0).
+ * ------------------------------------------------------------------------ */
+rid_status rid_cv_eval(rid_system sys, const float* d_pos, int B, float* d_s,
+                       float* d_x, rid_stream stream);
+
+/* ------------------------------------------------------------------------
+ * rid_model_dev - ensemble mean forces and model deviation at given CVs.
+ * Box 2 defines the mean force as F(s) = grad_s A(s); the uncertainty
+ * indicator is the standard deviation of the ensemble's predictions
+ * ("Development of the protocol", "Training phase"), taken here as
+ *   eps = sqrt( (1/K) sum_k |g_k - gbar|^2 ),  g_k = grad_s A_k(s),
+ * accumulated in FP64 (shifted by member 0, so identical members give 0).
+ *   d_s     [B][n_cv]  CVs (any real values; periodic)
+ *   d_eps   [B]        model deviation (required)
+ *   d_gbar  [B][n_cv]  ensemble-mean mean force, or NULL
+ *   d_A     [B][K]     per-model free energies, or NULL
+ *   d_g     [B][K][n_cv] per-model mean forces, or NULL
+ * ------------------------------------------------------------------------ */
+rid_status rid_model_dev(rid_ensemble ens, const float* d_s, int B,
+                         float* d_eps, float* d_gbar, float* d_A, float* d_g,
+                         rid_stream stream);
+
+/* ------------------------------------------------------------------------
+ * rid_bias_force - the per-MD-step neural bias of B walkers.
+ * The bias is the inverted predicted PMF, applied only where the ensemble
+ * agrees ("Development of the protocol"); trust_lvl_1/trust_lvl_2 bound the
+ * trust level ("Overall workflow setting").  With Abar, gbar the ensemble
+ * means and eps the model deviation (as rid_model_dev):
+ *   sigma = 1 (eps < eps0); 0 (eps >= eps1);
+ *           (1 + cos(pi (eps - eps0)/(eps1 - eps0)))/2 in between
+ *   E     = -sigma Abar                       (bias energy)
+ *   F_a   = sum_i sigma gbar_i ds_i/dr_a      (force, sigma held fixed)
+ *   d_pos    [B][n_atoms][3]  positions
+ *   d_force  [B][n_atoms][3]  OVERWRITTEN; atoms in no torsion get 0
+ *   d_energy [B] | NULL, d_eps [B] | NULL, d_sigma [B] | NULL
+ *   d_flags  [B] | NULL: 1 if any torsion of the walker is degenerate
+ *            (that torsion contributes no force), else 0.
+ * Errors: RID_EINVAL for eps0 < 0 or eps0 >= eps1, B < 1, NULL pos/force,
+ *         n_cv mismatch between system and ensemble.
+ * ------------------------------------------------------------------------ */
+rid_status rid_bias_force(rid_system sys, rid_ensemble ens, const float* d_pos,
+                          int B, float eps0, float eps1, float* d_force,
+                          float* d_energy, float* d_eps, float* d_sigma,
+                          uint8_t* d_flags, rid_stream stream);
+
+/* ------------------------------------------------------------------------
+ * rid_cv_apply_force - chain a CV-space force to the atoms alone:
+ *   F_a = sum_i f_i ds_i/dr_a.
+ *   d_fcv [B][n_cv]; d_force [B][n_atoms][3] OVERWRITTEN.
+ * ------------------------------------------------------------------------ */
+rid_status rid_cv_apply_force(rid_system sys, const float* d_pos,
+                              const float* d_fcv, int B, float* d_force,
+                              rid_stream stream);
+
+/* ------------------------------------------------------------------------
+ * rid_mf_train_step - one mean-force fitting step of every member
+ * ("Training phase": the models are trained to predict mean forces; the
+ * learning rate decays exponentially, see rid_lr_exponential).
+ * Loss of member k on the minibatch:
+ *   L_k = (1/B) sum_b |grad_s A_k(s_b) - F_b|^2,
+ * differentiated in the weights by a double-backward (tangent + adjoint)
+ * sweep in FP32, followed by one Adam update (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected) of the FP32 masters with step size lr.
+ *   d_s, d_F  [B][n_cv]   CVs and mean-force labels
+ *   d_loss    [K] | NULL  loss of each member BEFORE the update
+ * The step always runs in FP32 on the FP32 masters; a BF16/FP16 ensemble
+ * has its 16-bit copies refreshed before its next evaluation.
+ * ------------------------------------------------------------------------ */
+rid_status rid_mf_train_step(rid_ensemble ens, const float* d_s,
+                             const float* d_F, int B, float lr, float* d_loss,
+                             rid_stream stream);
+
+/* Gradient of the same loss, without updating anything:
+ *   d_loss [K] | NULL   per-member loss
+ *   d_grad [n_params]   dL/dtheta in the packed parameter layout (sum over
+ *                       members of the per-member losses; each member's
+ *                       block holds its own gradient; output bias entries 0)
+ */
+rid_status rid_mf_loss_grad(rid_ensemble ens, const float* d_s, const float* d_F,
+                            int B, float* d_loss, float* d_grad,
+                            rid_stream stream);
+
+/* Vector-Jacobian product of the mean forces (the backward of
+ * rid_model_dev's d_g output): for an upstream gradient
+ * d_rho [B][K][n_cv], writes d_grad [n_params] =
+ *   d/dtheta sum_b sum_k rho[b][k] . grad_s A_k(s_b)
+ * in the packed parameter layout (double backward through the MLPs). */
+rid_status rid_mf_grad(rid_ensemble ens, const float* d_s, const float* d_rho,
+                       int B, float* d_grad, rid_stream stream);
+
+/* Exponential decay of the paper's training schedule:
+ * init_lr * decay_rate^(step / decay_steps) (continuous). */
+double rid_lr_exponential(int64_t step, double init_lr, int decay_steps,
+                          double decay_rate);
+
+/* ------------------------------------------------------------------------
+ * rid_mf_label - mean-force labels from restrained-MD CV trajectories
+ * ("Labeling phase", restrained method: harmonic restraints of stiffness
+ * kappas; the mean force is the average spring force; std_threshold drops
+ * labels that have not converged).  In FP64 on the device:
+ *   F_i  = kappa_i (1/T) sum_t wrap(s0_i - s_{t,i})  (wrap to (-pi, pi]
+ *          where angular_mask_i = 1)
+ *   SE_i = std over 10 blocks of floor(T/10) frames of the block-mean
+ *          spring force (denominator 9) / sqrt(10)
+ *   keep = max_i SE_i <= std_threshold
+ *   d_traj [M][T][n] FP32, d_s0 [M][n] FP32, kappa host [n],
+ *   angular_mask host [n] | NULL (= all 1),
+ *   d_F [M][n] FP64, d_se [M][n] FP64 | NULL, d_keep [M] | NULL.
+ * Errors: RID_EINVAL for T < 10, M < 1, n < 1 or n > 256.
+ * ------------------------------------------------------------------------ */
+rid_status rid_mf_label(const float* d_traj, const float* d_s0,
+                        const float* kappa, const uint8_t* angular_mask,
+                        int M, int T, int n, float std_threshold, double* d_F,
+                        double* d_se, uint8_t* d_keep, rid_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing for benchmarks.  While enabled, every kernel the library
+ * launches is bracketed by two hipEvents recorded on the launching stream
+ * (no synchronisation at record time).  rid_profile_enable(1) clears and
+ * starts collection, rid_profile_enable(0) stops and clears it.
+ * rid_profile_read synchronises the device and returns, for one kernel
+ * family, the summed event-measured duration (ms) and the launch count
+ * since collection started.  Families: 0 torsion CVs, 1 fused ensemble MLP,
+ * 2 deviation/switch/atom-force scatter, 3 ensemble reduction,
+ * 4 CV embedding, 5 training step kernels, 6 mean-force labels.
+ * ------------------------------------------------------------------------ */
+void rid_profile_enable(int on);
+rid_status rid_profile_read(int kind, double* total_ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RID_H */

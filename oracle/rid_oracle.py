@@ -279,16 +279,24 @@ def train_loss_grad(model, s, F):
       dwo = hd_L;  dbo = 0 (the constant never reaches grad_s A).
     Returns (loss, (dWs, dbs, dwo, dbo)), all summed over the batch.
     """
-    Ws, bs, wo, bo = model
     s = np.asarray(s, dtype=np.float64)
     F = np.asarray(F, dtype=np.float64)
     B, n = s.shape
-    x = embed(s)
-    A, u0 = mlp_value_and_grad(model, x)
+    A, u0 = mlp_value_and_grad(model, embed(s))
     g = mean_force_from_input_grad(s, u0)
     r = g - F
     loss = float(np.sum(r * r) / B)
-    rho = 2.0 * r / B
+    return loss, mean_force_vjp(model, s, 2.0 * r / B)
+
+
+def mean_force_vjp(model, s, rho):
+    """Gradient in the parameters of J = sum_b rho_b . g(s_b) for a given
+    rho [B][n] (the tangent + adjoint sweep described in train_loss_grad).
+    Returns (dWs, dbs, dwo, dbo)."""
+    Ws, bs, wo, bo = model
+    s = np.asarray(s, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    x = embed(s)
     rho_x = np.concatenate([-np.sin(s) * rho, np.cos(s) * rho], axis=-1)
     # primal activations
     hs = [x]
@@ -316,7 +324,7 @@ def train_loss_grad(model, s, F):
         dbs[l - 1] = np.sum(lam_z, axis=0)
         lam_hd = lam_zd @ Ws[l - 1]
         lam_h = lam_z @ Ws[l - 1]
-    return loss, (dWs, dbs, dwo, 0.0)
+    return (dWs, dbs, dwo, 0.0)
 
 
 def train_loss(model, s, F):

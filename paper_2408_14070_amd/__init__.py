@@ -1,0 +1,363 @@
+"""Reinforced-Dynamics neural-bias hot path on MI355X (gfx950).
+
+Thin Python binding of the C ABI in include/rid.h: argument marshalling
+only.  Every step of the path runs in the HIP kernels of librid.so; tensors
+are torch CUDA (ROCm) tensors used for device memory and streams.  There is
+no CPU fallback: importing works without a GPU (the library loads and its
+symbols resolve), but every compute call needs the device.
+
+Paper: "RiD-kit: Software package designed to do enhanced sampling using
+reinforced dynamics" (arXiv 2408.14070).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librid.so")
+
+RID_OK, RID_EINVAL, RID_ENOMEM, RID_EDEVICE, RID_EDEGENERATE, RID_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+RID_FP32, RID_BF16, RID_FP16 = 0, 1, 2
+_STATUS = {0: "RID_OK", -1: "RID_EINVAL", -2: "RID_ENOMEM", -3: "RID_EDEVICE",
+           -4: "RID_EDEGENERATE", -5: "RID_EUNSUPPORTED"}
+
+# Every symbol include/rid.h declares.
+EXPORTS = (
+    "rid_last_error", "rid_version", "rid_system_create", "rid_system_destroy",
+    "rid_packed_param_count", "rid_ensemble_create", "rid_ensemble_get_params",
+    "rid_ensemble_set_params", "rid_ensemble_step", "rid_ensemble_destroy",
+    "rid_cv_eval", "rid_model_dev", "rid_bias_force", "rid_cv_apply_force",
+    "rid_mf_train_step", "rid_lr_exponential", "rid_mf_label",
+    "rid_profile_enable", "rid_profile_read", "rid_mf_loss_grad", "rid_mf_grad",
+)
+PROF_CV, PROF_MLP, PROF_SCATTER, PROF_REDUCE, PROF_EMBED, PROF_TRAIN, PROF_LABEL = range(7)
+
+
+class RidError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load librid.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} missing: run __graft_entry__.build() or "
+                          "python -m paper_2408_14070_amd.build first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, f, d, sz, i64 = (ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
+                           ctypes.c_double, ctypes.c_size_t, ctypes.c_int64)
+    P = ctypes.POINTER
+    sig = {
+        "rid_last_error": (ctypes.c_char_p, []),
+        "rid_version": (ctypes.c_char_p, []),
+        "rid_system_create": (i, [i, i, vp, vp, P(vp)]),
+        "rid_system_destroy": (None, [vp]),
+        "rid_packed_param_count": (sz, [i, i, i, vp]),
+        "rid_ensemble_create": (i, [i, i, i, vp, i, vp, P(vp)]),
+        "rid_ensemble_get_params": (i, [vp, vp]),
+        "rid_ensemble_set_params": (i, [vp, vp]),
+        "rid_ensemble_step": (i64, [vp]),
+        "rid_ensemble_destroy": (None, [vp]),
+        "rid_cv_eval": (i, [vp, vp, i, vp, vp, vp]),
+        "rid_model_dev": (i, [vp, vp, i, vp, vp, vp, vp, vp]),
+        "rid_bias_force": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
+        "rid_cv_apply_force": (i, [vp, vp, vp, i, vp, vp]),
+        "rid_mf_train_step": (i, [vp, vp, vp, i, f, vp, vp]),
+        "rid_lr_exponential": (d, [i64, d, i, d]),
+        "rid_mf_label": (i, [vp, vp, vp, vp, i, i, i, f, vp, vp, vp, vp]),
+        "rid_profile_enable": (None, [i]),
+        "rid_profile_read": (i, [i, P(d), P(i64)]),
+        "rid_mf_loss_grad": (i, [vp, vp, vp, i, vp, vp, vp]),
+        "rid_mf_grad": (i, [vp, vp, vp, i, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != RID_OK:
+        msg = lib().rid_last_error()
+        raise RidError(status, msg.decode() if msg else "")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device (CUDA/ROCm) tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _f32(t, shape, name):
+    if t.dtype != _torch().float32:
+        raise TypeError(f"{name} must be float32")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+class System:
+    """Atoms and torsion CVs (rid_system_create)."""
+
+    def __init__(self, n_atoms: int, quads, angular_mask=None):
+        q = np.ascontiguousarray(np.asarray(quads, dtype=np.int32))
+        if q.ndim != 2 or q.shape[1] != 4:
+            raise ValueError("quads must be [n_cv][4]")
+        m = None
+        if angular_mask is not None:
+            m = np.ascontiguousarray(np.asarray(angular_mask, dtype=np.uint8))
+        h = ctypes.c_void_p()
+        _check(lib().rid_system_create(int(n_atoms), int(q.shape[0]),
+                                       q.ctypes.data_as(ctypes.c_void_p),
+                                       None if m is None else m.ctypes.data_as(ctypes.c_void_p),
+                                       ctypes.byref(h)))
+        self.handle = h
+        self.n_atoms = int(n_atoms)
+        self.n_cv = int(q.shape[0])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().rid_system_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+class Ensemble:
+    """Ensemble of MLP free-energy models (rid_ensemble_create)."""
+
+    def __init__(self, n_cv: int, widths, n_models: int, params, precision=RID_FP32):
+        w = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        need = lib().rid_packed_param_count(int(n_cv), int(n_models), int(w.size),
+                                            w.ctypes.data_as(ctypes.c_void_p))
+        if p.size != need:
+            raise ValueError(f"params has {p.size} values, expected {need}")
+        h = ctypes.c_void_p()
+        _check(lib().rid_ensemble_create(int(n_cv), int(n_models), int(w.size),
+                                         w.ctypes.data_as(ctypes.c_void_p), int(precision),
+                                         p.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        self.handle = h
+        self.n_cv, self.K, self.widths = int(n_cv), int(n_models), [int(v) for v in w]
+        self.precision = int(precision)
+        self.n_params = int(need)
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().rid_ensemble_get_params(self.handle, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if p.size != self.n_params:
+            raise ValueError("wrong parameter count")
+        _check(lib().rid_ensemble_set_params(self.handle, p.ctypes.data_as(ctypes.c_void_p)))
+
+    @property
+    def step(self) -> int:
+        return int(lib().rid_ensemble_step(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().rid_ensemble_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+
+def cv_eval(system: System, pos, stream=None, with_x=True):
+    """rid_cv_eval: pos [B][n_atoms][3] -> (s [B][n], x [B][2n] or None)."""
+    torch = _torch()
+    B = pos.shape[0]
+    _f32(pos, (B, system.n_atoms, 3), "pos")
+    s = torch.empty((B, system.n_cv), dtype=torch.float32, device=pos.device)
+    x = torch.empty((B, 2 * system.n_cv), dtype=torch.float32, device=pos.device) if with_x else None
+    _check(lib().rid_cv_eval(system.handle, _ptr(pos), B, _ptr(s), _ptr(x), _stream(stream)))
+    return s, x
+
+
+def model_dev(ens: Ensemble, s, stream=None, want_g=True):
+    """rid_model_dev: s [B][n] -> (eps [B], gbar [B][n], A [B][K], g [B][K][n])."""
+    torch = _torch()
+    B = s.shape[0]
+    _f32(s, (B, ens.n_cv), "s")
+    dev = s.device
+    eps = torch.empty(B, dtype=torch.float32, device=dev)
+    gbar = torch.empty((B, ens.n_cv), dtype=torch.float32, device=dev)
+    A = torch.empty((B, ens.K), dtype=torch.float32, device=dev) if want_g else None
+    g = torch.empty((B, ens.K, ens.n_cv), dtype=torch.float32, device=dev) if want_g else None
+    _check(lib().rid_model_dev(ens.handle, _ptr(s), B, _ptr(eps), _ptr(gbar), _ptr(A),
+                               _ptr(g), _stream(stream)))
+    return eps, gbar, A, g
+
+
+def bias_force(system: System, ens: Ensemble, pos, eps0: float, eps1: float,
+               stream=None, out=None):
+    """rid_bias_force: pos [B][n_atoms][3] -> dict(F, E, eps, sigma, flags)."""
+    torch = _torch()
+    B = pos.shape[0]
+    _f32(pos, (B, system.n_atoms, 3), "pos")
+    dev = pos.device
+    if out is None:
+        out = dict(
+            F=torch.empty((B, system.n_atoms, 3), dtype=torch.float32, device=dev),
+            E=torch.empty(B, dtype=torch.float32, device=dev),
+            eps=torch.empty(B, dtype=torch.float32, device=dev),
+            sigma=torch.empty(B, dtype=torch.float32, device=dev),
+            flags=torch.empty(B, dtype=torch.uint8, device=dev),
+        )
+    _check(lib().rid_bias_force(system.handle, ens.handle, _ptr(pos), B, float(eps0),
+                                float(eps1), _ptr(out["F"]), _ptr(out.get("E")),
+                                _ptr(out.get("eps")), _ptr(out.get("sigma")),
+                                _ptr(out.get("flags")), _stream(stream)))
+    return out
+
+
+def cv_apply_force(system: System, pos, fcv, stream=None):
+    """rid_cv_apply_force: F_a = sum_i f_i ds_i/dr_a."""
+    torch = _torch()
+    B = pos.shape[0]
+    _f32(pos, (B, system.n_atoms, 3), "pos")
+    _f32(fcv, (B, system.n_cv), "fcv")
+    F = torch.empty((B, system.n_atoms, 3), dtype=torch.float32, device=pos.device)
+    _check(lib().rid_cv_apply_force(system.handle, _ptr(pos), _ptr(fcv), B, _ptr(F),
+                                    _stream(stream)))
+    return F
+
+
+def mf_train_step(ens: Ensemble, s, F, lr: float, stream=None):
+    """rid_mf_train_step: one double-backward + Adam step; returns loss [K]."""
+    torch = _torch()
+    B = s.shape[0]
+    _f32(s, (B, ens.n_cv), "s")
+    _f32(F, (B, ens.n_cv), "F")
+    loss = torch.empty(ens.K, dtype=torch.float32, device=s.device)
+    _check(lib().rid_mf_train_step(ens.handle, _ptr(s), _ptr(F), B, float(lr), _ptr(loss),
+                                   _stream(stream)))
+    return loss
+
+
+def mf_loss_grad(ens: Ensemble, s, F, stream=None):
+    """rid_mf_loss_grad: (loss [K], grad [n_params] packed) without update."""
+    torch = _torch()
+    B = s.shape[0]
+    _f32(s, (B, ens.n_cv), "s")
+    _f32(F, (B, ens.n_cv), "F")
+    loss = torch.empty(ens.K, dtype=torch.float32, device=s.device)
+    grad = torch.empty(ens.n_params, dtype=torch.float32, device=s.device)
+    _check(lib().rid_mf_loss_grad(ens.handle, _ptr(s), _ptr(F), B, _ptr(loss), _ptr(grad),
+                                  _stream(stream)))
+    return loss, grad
+
+
+def mf_grad(ens: Ensemble, s, rho, stream=None):
+    """rid_mf_grad: d/dtheta sum rho . g for rho [B][K][n] -> grad [n_params]."""
+    torch = _torch()
+    B = s.shape[0]
+    _f32(s, (B, ens.n_cv), "s")
+    _f32(rho, (B, ens.K, ens.n_cv), "rho")
+    grad = torch.empty(ens.n_params, dtype=torch.float32, device=s.device)
+    _check(lib().rid_mf_grad(ens.handle, _ptr(s), _ptr(rho), B, _ptr(grad), _stream(stream)))
+    return grad
+
+
+def _make_mean_force_fn():
+    torch = _torch()
+
+    class MeanForce(torch.autograd.Function):
+        """g = grad_s A_k(s) of every member as a differentiable function of
+        the ensemble's packed parameters.  forward calls rid_model_dev;
+        backward calls the double-backward kernels (rid_mf_grad).  The
+        ``params`` tensor stands for the ensemble's FP32 masters (it carries
+        the gradient); keep it in sync with Ensemble.set_params."""
+
+        @staticmethod
+        def forward(ctx, s, params, ens):
+            ctx.ens = ens
+            ctx.save_for_backward(s)
+            _, _, _, g = model_dev(ens, s.contiguous())
+            return g
+
+        @staticmethod
+        def backward(ctx, gout):
+            (s,) = ctx.saved_tensors
+            grad = mf_grad(ctx.ens, s.contiguous(), gout.contiguous())
+            return None, grad, None
+
+    return MeanForce
+
+
+_MEAN_FORCE = None
+
+
+def mean_force(s, params, ens: Ensemble):
+    """Differentiable per-member mean forces g [B][K][n] (see MeanForce)."""
+    global _MEAN_FORCE
+    if _MEAN_FORCE is None:
+        _MEAN_FORCE = _make_mean_force_fn()
+    return _MEAN_FORCE.apply(s, params, ens)
+
+
+def profile_enable(on: bool = True):
+    """Start (clear) or stop per-kernel HIP-event timing inside the library."""
+    lib().rid_profile_enable(1 if on else 0)
+
+
+def profile_read(kind: int):
+    """(total_ms, launches) of a kernel family since profile_enable(True)."""
+    tot = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(lib().rid_profile_read(int(kind), ctypes.byref(tot), ctypes.byref(cnt)))
+    return tot.value, cnt.value
+
+
+def lr_exponential(step: int, init_lr=8e-4, decay_steps=120, decay_rate=0.96) -> float:
+    return float(lib().rid_lr_exponential(int(step), float(init_lr), int(decay_steps),
+                                          float(decay_rate)))
+
+
+def mf_label(traj, s0, kappa, angular_mask=None, std_threshold=5.0, stream=None):
+    """rid_mf_label: traj [M][T][n], s0 [M][n] -> (F [M][n] f64, SE, keep)."""
+    torch = _torch()
+    M, T, n = traj.shape
+    _f32(traj, (M, T, n), "traj")
+    _f32(s0, (M, n), "s0")
+    k = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, np.float32), (n,)))
+    m = None if angular_mask is None else np.ascontiguousarray(np.asarray(angular_mask, np.uint8))
+    dev = traj.device
+    F = torch.empty((M, n), dtype=torch.float64, device=dev)
+    se = torch.empty((M, n), dtype=torch.float64, device=dev)
+    keep = torch.empty(M, dtype=torch.uint8, device=dev)
+    _check(lib().rid_mf_label(_ptr(traj), _ptr(s0), k.ctypes.data_as(ctypes.c_void_p),
+                              None if m is None else m.ctypes.data_as(ctypes.c_void_p),
+                              M, T, n, float(std_threshold), _ptr(F), _ptr(se), _ptr(keep),
+                              _stream(stream)))
+    return F, se, keep

@@ -1,0 +1,470 @@
+// C ABI of the library (declarations and contracts: include/rid.h).
+// Host-side validation, handle construction and kernel sequencing only; all
+// arithmetic of the path runs in the kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "rid_internal.h"
+
+struct rid_system_s {
+  rid::rid_system_impl impl;
+};
+struct rid_ensemble_s {
+  rid::rid_ensemble_impl impl;
+};
+
+namespace rid {
+
+static thread_local std::string g_err;
+
+rid_status fail(rid_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+rid_status DevBuf::ensure(size_t need) {
+  if (need <= bytes && ptr) return RID_OK;
+  release();
+  if (need == 0) need = 256;
+  if (hipMalloc(&ptr, need) != hipSuccess) {
+    ptr = nullptr;
+    bytes = 0;
+    (void)hipGetLastError();
+    return fail(RID_ENOMEM, "device allocation of scratch memory failed");
+  }
+  bytes = need;
+  return RID_OK;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+// ---- kernel timing -------------------------------------------------------
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+struct ProfPair {
+  int kind;
+  hipEvent_t a, b;
+};
+static std::vector<ProfPair> g_prof;
+static std::vector<hipEvent_t> g_pool;
+
+bool prof_enabled() { return g_prof_on; }
+
+hipEvent_t prof_record(hipStream_t st) {
+  hipEvent_t e = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_pool.empty()) {
+      e = g_pool.back();
+      g_pool.pop_back();
+    }
+  }
+  if (!e && hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventRecord(e, st) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_push(int kind, hipEvent_t a, hipEvent_t b) {
+  if (!a || !b) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back({kind, a, b});
+}
+
+static void prof_recycle_locked() {
+  for (auto& p : g_prof) {
+    g_pool.push_back(p.a);
+    g_pool.push_back(p.b);
+  }
+  g_prof.clear();
+}
+
+template <class T>
+static rid_status dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(RID_ENOMEM, "device allocation failed");
+  }
+  return RID_OK;
+}
+
+template <class T>
+static void dev_free(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+static size_t per_model_count(int n_cv, int L, const int* widths) {
+  size_t per = 0;
+  int prev = 2 * n_cv;
+  for (int l = 0; l < L; ++l) {
+    per += (size_t)widths[l] * prev + widths[l];
+    prev = widths[l];
+  }
+  return per + prev + 1;
+}
+
+static void free_system(rid_system_impl& s) {
+  dev_free(s.d_uniq);
+  dev_free(s.d_lquads);
+  dev_free(s.d_csr_ptr);
+  dev_free(s.d_csr_ent);
+  dev_free(s.d_atom_local);
+}
+
+static void free_ensemble(rid_ensemble_impl& e) {
+  dev_free(e.d_master);
+  dev_free(e.d_m);
+  dev_free(e.d_v);
+  dev_free(e.d_frag);
+  dev_free(e.d_bias);
+  dev_free(e.d_wo);
+  dev_free(e.d_bo);
+  e.ws_x.release();
+  e.ws_A.release();
+  e.ws_g.release();
+  e.ws_train.release();
+}
+
+}  // namespace rid
+
+using namespace rid;
+
+extern "C" {
+
+const char* rid_last_error(void) { return g_err.c_str(); }
+
+const char* rid_version(void) { return "rid-mi355x 0.1 (gfx950)"; }
+
+rid_status rid_system_create(int n_atoms, int n_cv, const int32_t* quads,
+                             const uint8_t* angular_mask, rid_system* out) {
+  if (!out) return fail(RID_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_atoms < 1 || n_cv < 1 || !quads)
+    return fail(RID_EINVAL, "need n_atoms >= 1, n_cv >= 1 and a quad table");
+  if (n_cv > 256) return fail(RID_EUNSUPPORTED, "at most 256 torsion CVs");
+  for (int i = 0; i < n_cv; ++i) {
+    for (int j = 0; j < 4; ++j) {
+      const int a = quads[4 * i + j];
+      if (a < 0 || a >= n_atoms)
+        return fail(RID_EINVAL, "quad " + std::to_string(i) + " has an atom index out of range");
+      for (int j2 = 0; j2 < j; ++j2)
+        if (quads[4 * i + j2] == a)
+          return fail(RID_EINVAL, "quad " + std::to_string(i) + " repeats an atom");
+    }
+    if (angular_mask && angular_mask[i] != 1)
+      return fail(RID_EUNSUPPORTED, "torsion CVs must be periodic (angular_mask 1)");
+  }
+  rid_system_s* h = new (std::nothrow) rid_system_s();
+  if (!h) return fail(RID_ENOMEM, "host allocation failed");
+  rid_system_impl& s = h->impl;
+  s.n_atoms = n_atoms;
+  s.n_cv = n_cv;
+  s.quads.assign(quads, quads + 4 * (size_t)n_cv);
+  s.uniq = s.quads;
+  std::sort(s.uniq.begin(), s.uniq.end());
+  s.uniq.erase(std::unique(s.uniq.begin(), s.uniq.end()), s.uniq.end());
+  s.n_uniq = (int)s.uniq.size();
+  std::vector<int32_t> atom_local(n_atoms, -1);
+  for (int u = 0; u < s.n_uniq; ++u) atom_local[s.uniq[u]] = u;
+  std::vector<int32_t> lq(4 * (size_t)n_cv);
+  for (size_t e = 0; e < lq.size(); ++e) lq[e] = atom_local[s.quads[e]];
+  // CSR inverse map in (cv, slot) order
+  std::vector<int32_t> ptr(s.n_uniq + 1, 0), ent(4 * (size_t)n_cv);
+  for (size_t e = 0; e < lq.size(); ++e) ptr[lq[e] + 1]++;
+  for (int u = 0; u < s.n_uniq; ++u) {
+    s.max_deg = std::max(s.max_deg, ptr[u + 1]);
+    ptr[u + 1] += ptr[u];
+  }
+  std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+  for (size_t e = 0; e < lq.size(); ++e) ent[fill[lq[e]]++] = (int32_t)e;
+  rid_status st = RID_OK;
+  if ((st = dev_alloc(&s.d_uniq, s.n_uniq)) != RID_OK ||
+      (st = dev_alloc(&s.d_lquads, lq.size())) != RID_OK ||
+      (st = dev_alloc(&s.d_csr_ptr, ptr.size())) != RID_OK ||
+      (st = dev_alloc(&s.d_csr_ent, ent.size())) != RID_OK ||
+      (st = dev_alloc(&s.d_atom_local, atom_local.size())) != RID_OK) {
+    free_system(s);
+    delete h;
+    return st;
+  }
+  hipError_t e = hipSuccess;
+  e = e ? e : hipMemcpy(s.d_uniq, s.uniq.data(), 4 * s.uniq.size(), hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(s.d_lquads, lq.data(), 4 * lq.size(), hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(s.d_csr_ptr, ptr.data(), 4 * ptr.size(), hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(s.d_csr_ent, ent.data(), 4 * ent.size(), hipMemcpyHostToDevice);
+  e = e ? e : hipMemcpy(s.d_atom_local, atom_local.data(), 4 * atom_local.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_system(s);
+    delete h;
+    return hip_fail(e, "rid_system_create upload");
+  }
+  *out = h;
+  return RID_OK;
+}
+
+void rid_system_destroy(rid_system sys) {
+  if (!sys) return;
+  (void)hipDeviceSynchronize();
+  free_system(sys->impl);
+  delete sys;
+}
+
+size_t rid_packed_param_count(int n_cv, int n_models, int n_hidden,
+                              const int* widths) {
+  if (n_cv < 1 || n_models < 1 || n_hidden < 0 || (n_hidden > 0 && !widths)) return 0;
+  return per_model_count(n_cv, n_hidden, widths) * (size_t)n_models;
+}
+
+rid_status rid_ensemble_create(int n_cv, int n_models, int n_hidden,
+                               const int* widths, rid_precision prec,
+                               const float* params, rid_ensemble* out) {
+  if (!out) return fail(RID_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!params || !widths) return fail(RID_EINVAL, "params and widths are required");
+  if (prec != RID_FP32 && prec != RID_BF16 && prec != RID_FP16)
+    return fail(RID_EINVAL, "unknown precision");
+  if (n_cv < 1 || n_cv > 256) return fail(RID_EUNSUPPORTED, "n_cv must be in [1, 256]");
+  if (n_models < 1 || n_models > 64) return fail(RID_EUNSUPPORTED, "n_models must be in [1, 64]");
+  if (n_hidden < 1 || n_hidden > kMaxHidden)
+    return fail(RID_EUNSUPPORTED, "n_hidden must be in [1, 6]");
+  int wmax = 0;
+  for (int l = 0; l < n_hidden; ++l) {
+    if (widths[l] < 1 || widths[l] > kMaxWidth)
+      return fail(RID_EUNSUPPORTED, "hidden widths must be in [1, 512]");
+    wmax = std::max(wmax, widths[l]);
+  }
+  rid_ensemble_s* h = new (std::nothrow) rid_ensemble_s();
+  if (!h) return fail(RID_ENOMEM, "host allocation failed");
+  rid_ensemble_impl& e = h->impl;
+  e.n_cv = n_cv;
+  e.K = n_models;
+  e.L = n_hidden;
+  e.widths.assign(widths, widths + n_hidden);
+  e.prec = prec;
+  e.KF = kf_of(prec);
+  e.NP = round_up(wmax, 64);
+  e.XP = round_up(2 * n_cv, e.KF);
+  e.per_model = per_model_count(n_cv, n_hidden, widths);
+  e.n_params = e.per_model * n_models;
+  e.layers.resize(n_hidden);
+  size_t off = 0;
+  for (int l = 0; l < n_hidden; ++l) {
+    LayerDev& ld = e.layers[l];
+    ld.kin_pad = l == 0 ? e.XP : e.NP;
+    ld.fwd_off = off;
+    off += (size_t)(ld.kin_pad / e.KF) * (e.NP / 16) * kFragBytes;
+    ld.bwd_off = off;
+    off += (size_t)(e.NP / e.KF) * (ld.kin_pad / 16) * kFragBytes;
+  }
+  e.frag_bytes_per_model = off;
+  rid_status st = RID_OK;
+  if ((st = dev_alloc(&e.d_master, e.n_params)) != RID_OK ||
+      (st = dev_alloc(&e.d_m, e.n_params)) != RID_OK ||
+      (st = dev_alloc(&e.d_v, e.n_params)) != RID_OK ||
+      (st = dev_alloc(&e.d_frag, e.frag_bytes_per_model * n_models)) != RID_OK ||
+      (st = dev_alloc(&e.d_bias, (size_t)n_models * n_hidden * e.NP)) != RID_OK ||
+      (st = dev_alloc(&e.d_wo, (size_t)n_models * e.NP)) != RID_OK ||
+      (st = dev_alloc(&e.d_bo, (size_t)n_models)) != RID_OK) {
+    free_ensemble(e);
+    delete h;
+    return st;
+  }
+  hipError_t he = hipMemcpy(e.d_master, params, e.n_params * 4, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemset(e.d_m, 0, e.n_params * 4);
+  if (he == hipSuccess) he = hipMemset(e.d_v, 0, e.n_params * 4);
+  if (he != hipSuccess) {
+    free_ensemble(e);
+    delete h;
+    return hip_fail(he, "rid_ensemble_create upload");
+  }
+  st = pack_ensemble_weights(e, nullptr);
+  if (st == RID_OK) {
+    he = hipStreamSynchronize(nullptr);
+    if (he != hipSuccess) st = hip_fail(he, "rid_ensemble_create pack");
+  }
+  if (st != RID_OK) {
+    free_ensemble(e);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return RID_OK;
+}
+
+rid_status rid_ensemble_get_params(rid_ensemble ens, float* host_params) {
+  if (!ens || !host_params) return fail(RID_EINVAL, "NULL argument");
+  RID_HIP(hipDeviceSynchronize());
+  RID_HIP(hipMemcpy(host_params, ens->impl.d_master, ens->impl.n_params * 4,
+                    hipMemcpyDeviceToHost));
+  return RID_OK;
+}
+
+rid_status rid_ensemble_set_params(rid_ensemble ens, const float* host_params) {
+  if (!ens || !host_params) return fail(RID_EINVAL, "NULL argument");
+  rid_ensemble_impl& e = ens->impl;
+  RID_HIP(hipDeviceSynchronize());
+  RID_HIP(hipMemcpy(e.d_master, host_params, e.n_params * 4, hipMemcpyHostToDevice));
+  RID_HIP(hipMemset(e.d_m, 0, e.n_params * 4));
+  RID_HIP(hipMemset(e.d_v, 0, e.n_params * 4));
+  e.step = 0;
+  rid_status st = pack_ensemble_weights(e, nullptr);
+  if (st != RID_OK) return st;
+  RID_HIP(hipStreamSynchronize(nullptr));
+  return RID_OK;
+}
+
+int64_t rid_ensemble_step(rid_ensemble ens) { return ens ? ens->impl.step : -1; }
+
+void rid_ensemble_destroy(rid_ensemble ens) {
+  if (!ens) return;
+  (void)hipDeviceSynchronize();
+  free_ensemble(ens->impl);
+  delete ens;
+}
+
+rid_status rid_cv_eval(rid_system sys, const float* d_pos, int B, float* d_s,
+                       float* d_x, rid_stream stream) {
+  if (!sys || !d_pos || !d_s) return fail(RID_EINVAL, "NULL argument");
+  if (B < 1) return fail(RID_EINVAL, "B must be >= 1");
+  return launch_cv_eval(sys->impl, d_pos, B, d_s, d_x, (hipStream_t)stream);
+}
+
+rid_status rid_model_dev(rid_ensemble ens, const float* d_s, int B, float* d_eps,
+                         float* d_gbar, float* d_A, float* d_g,
+                         rid_stream stream) {
+  if (!ens || !d_s || !d_eps) return fail(RID_EINVAL, "NULL argument");
+  if (B < 1) return fail(RID_EINVAL, "B must be >= 1");
+  rid_ensemble_impl& e = ens->impl;
+  const hipStream_t st = (hipStream_t)stream;
+  rid_status r;
+  if ((r = e.ws_x.ensure(sizeof(float) * 2 * e.n_cv * (size_t)B)) != RID_OK) return r;
+  if ((r = e.ws_A.ensure(sizeof(float) * e.K * (size_t)B)) != RID_OK) return r;
+  if ((r = e.ws_g.ensure(sizeof(float) * e.K * (size_t)B * e.n_cv)) != RID_OK) return r;
+  if ((r = launch_embed(d_s, B, e.n_cv, e.ws_x.as<float>(), st)) != RID_OK) return r;
+  if (e.frag_dirty) {
+    if ((r = pack_ensemble_weights(e, st)) != RID_OK) return r;
+    e.frag_dirty = false;
+  }
+  if ((r = launch_mlp(e, e.ws_x.as<float>(), B, e.ws_A.as<float>(), e.ws_g.as<float>(), st)) != RID_OK)
+    return r;
+  return launch_ensemble_reduce(e.K, e.n_cv, B, e.ws_A.as<float>(), e.ws_g.as<float>(),
+                                d_eps, d_gbar, d_A, d_g, st);
+}
+
+rid_status rid_bias_force(rid_system sys, rid_ensemble ens, const float* d_pos,
+                          int B, float eps0, float eps1, float* d_force,
+                          float* d_energy, float* d_eps, float* d_sigma,
+                          uint8_t* d_flags, rid_stream stream) {
+  if (!sys || !ens || !d_pos || !d_force) return fail(RID_EINVAL, "NULL argument");
+  if (B < 1) return fail(RID_EINVAL, "B must be >= 1");
+  if (!(eps0 >= 0.f) || !(eps0 < eps1))
+    return fail(RID_EINVAL, "trust levels need 0 <= eps0 < eps1");
+  rid_system_impl& s = sys->impl;
+  rid_ensemble_impl& e = ens->impl;
+  if (s.n_cv != e.n_cv) return fail(RID_EINVAL, "system and ensemble disagree on n_cv");
+  const hipStream_t st = (hipStream_t)stream;
+  rid_status r;
+  if ((r = e.ws_x.ensure(sizeof(float) * 2 * e.n_cv * (size_t)B)) != RID_OK) return r;
+  if ((r = e.ws_A.ensure(sizeof(float) * e.K * (size_t)B)) != RID_OK) return r;
+  if ((r = e.ws_g.ensure(sizeof(float) * e.K * (size_t)B * e.n_cv)) != RID_OK) return r;
+  if ((r = launch_cv_eval(s, d_pos, B, nullptr, e.ws_x.as<float>(), st)) != RID_OK) return r;
+  if (e.frag_dirty) {
+    if ((r = pack_ensemble_weights(e, st)) != RID_OK) return r;
+    e.frag_dirty = false;
+  }
+  if ((r = launch_mlp(e, e.ws_x.as<float>(), B, e.ws_A.as<float>(), e.ws_g.as<float>(), st)) != RID_OK)
+    return r;
+  return launch_bias_scatter(s, e.K, d_pos, B, e.ws_A.as<float>(), e.ws_g.as<float>(),
+                             nullptr, eps0, eps1, d_force, d_energy, d_eps, d_sigma,
+                             d_flags, st);
+}
+
+rid_status rid_cv_apply_force(rid_system sys, const float* d_pos,
+                              const float* d_fcv, int B, float* d_force,
+                              rid_stream stream) {
+  if (!sys || !d_pos || !d_fcv || !d_force) return fail(RID_EINVAL, "NULL argument");
+  if (B < 1) return fail(RID_EINVAL, "B must be >= 1");
+  return launch_bias_scatter(sys->impl, 0, d_pos, B, nullptr, nullptr, d_fcv, 0.0f,
+                             1.0f, d_force, nullptr, nullptr, nullptr, nullptr,
+                             (hipStream_t)stream);
+}
+
+rid_status rid_mf_train_step(rid_ensemble ens, const float* d_s, const float* d_F,
+                             int B, float lr, float* d_loss, rid_stream stream) {
+  if (!ens || !d_s || !d_F) return fail(RID_EINVAL, "NULL argument");
+  if (B < 1) return fail(RID_EINVAL, "B must be >= 1");
+  if (!(lr >= 0.f)) return fail(RID_EINVAL, "lr must be >= 0");
+  return launch_train_step(ens->impl, d_s, d_F, B, lr, d_loss, (hipStream_t)stream);
+}
+
+void rid_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_recycle_locked();
+  g_prof_on = on != 0;
+}
+
+rid_status rid_profile_read(int kind, double* total_ms, int64_t* count) {
+  if (!total_ms || !count || kind < 0 || kind >= kProfKinds)
+    return fail(RID_EINVAL, "bad profile query");
+  RID_HIP(hipDeviceSynchronize());
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double tot = 0.0;
+  int64_t n = 0;
+  for (auto& p : g_prof) {
+    if (p.kind != kind) continue;
+    float ms = 0.f;
+    RID_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    tot += ms;
+    ++n;
+  }
+  *total_ms = tot;
+  *count = n;
+  return RID_OK;
+}
+
+rid_status rid_mf_loss_grad(rid_ensemble ens, const float* d_s, const float* d_F,
+                            int B, float* d_loss, float* d_grad, rid_stream stream) {
+  if (!ens || !d_s || !d_F || !d_grad) return fail(RID_EINVAL, "NULL argument");
+  if (B < 1) return fail(RID_EINVAL, "B must be >= 1");
+  float* used = nullptr;
+  return launch_mf_grad(ens->impl, d_s, d_F, nullptr, B, d_loss, d_grad, &used,
+                        (hipStream_t)stream);
+}
+
+rid_status rid_mf_grad(rid_ensemble ens, const float* d_s, const float* d_rho,
+                       int B, float* d_grad, rid_stream stream) {
+  if (!ens || !d_s || !d_rho || !d_grad) return fail(RID_EINVAL, "NULL argument");
+  if (B < 1) return fail(RID_EINVAL, "B must be >= 1");
+  float* used = nullptr;
+  return launch_mf_grad(ens->impl, d_s, nullptr, d_rho, B, nullptr, d_grad, &used,
+                        (hipStream_t)stream);
+}
+
+double rid_lr_exponential(int64_t step, double init_lr, int decay_steps,
+                          double decay_rate) {
+  if (decay_steps <= 0) return init_lr;
+  return init_lr * std::pow(decay_rate, (double)step / (double)decay_steps);
+}
+
+rid_status rid_mf_label(const float* d_traj, const float* d_s0, const float* kappa,
+                        const uint8_t* angular_mask, int M, int T, int n,
+                        float std_threshold, double* d_F, double* d_se,
+                        uint8_t* d_keep, rid_stream stream) {
+  if (!d_traj || !d_s0 || !kappa || !d_F) return fail(RID_EINVAL, "NULL argument");
+  if (M < 1 || n < 1 || n > 256 || T < 10)
+    return fail(RID_EINVAL, "need M >= 1, 1 <= n <= 256 and T >= 10");
+  return launch_mf_label_impl(d_traj, d_s0, kappa, angular_mask, M, T, n,
+                              std_threshold, d_F, d_se, d_keep, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,493 @@
+// Ensemble MLP free-energy models: fused forward + input-gradient kernel and
+// the on-device weight packer.
+//
+// Method ("Training phase"): each ensemble member is an MLP with tanh hidden
+// layers and a scalar output A(x); the bias needs the mean force
+// g = dA/ds (Box 2), obtained by one reverse sweep through the same layers.
+// x = [cos s | sin s].
+//
+// Kernel design (gfx950):
+//  * One workgroup owns R = 16*RT walkers of ONE member.  Its waves split the
+//    hidden columns; each wave streams its columns' weight fragments straight
+//    from L2 into VGPRs (no weight reuse inside a workgroup, so no LDS hop).
+//  * The activation tile (the MFMA A operand, shared by all waves) lives in
+//    LDS, ping-ponged between two buffers so each layer needs one barrier;
+//    it holds x, then h_1 .. h_L, then the reverse-sweep vectors v_l.
+//  * tanh'(z_l) = 1 - h_l^2 is kept in FP32 VGPRs for the reverse sweep:
+//    nothing is written to HBM between layers.
+//  * Blocks are mapped XCD-aware: when K divides 8, member k runs on XCDs
+//    {k*8/K, ...}, so each XCD's L2 holds only its members' weights.
+#include "rid_internal.h"
+
+namespace rid {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+struct F32 {
+  using T = float;
+  static constexpr int KF = 16;
+  __device__ static inline void mma(const uint4& a, const uint4& b, f4& c) {
+    f4 av = __builtin_bit_cast(f4, a);
+    f4 bv = __builtin_bit_cast(f4, b);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0], bv[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1], bv[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2], bv[2], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[3], bv[3], c, 0, 0, 0);
+  }
+  __device__ static inline T from_float(float v) { return v; }
+};
+
+struct BF16 {
+  using T = __bf16;
+  static constexpr int KF = 32;
+  __device__ static inline void mma(const uint4& a, const uint4& b, f4& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                __builtin_bit_cast(bf8, b), c,
+                                                0, 0, 0);
+  }
+  __device__ static inline T from_float(float v) { return (__bf16)v; }
+};
+
+struct F16 {
+  using T = _Float16;
+  static constexpr int KF = 32;
+  __device__ static inline void mma(const uint4& a, const uint4& b, f4& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a),
+                                               __builtin_bit_cast(h8, b), c,
+                                               0, 0, 0);
+  }
+  __device__ static inline T from_float(float v) { return (_Float16)v; }
+};
+
+// tanh and its derivative from one exponential and one reciprocal:
+// with r = 1 / (1 + exp(2z)):  tanh z = 1 - 2r,  1 - tanh^2 z = 4 r (1 - r).
+// Saturates cleanly (exp -> inf gives r = 0; exp -> 0 gives r = 1).  Absolute
+// error of a few 1e-7, below the FP32 rounding of the GEMM that feeds it.
+__device__ inline float tanh_and_grad(float z, float& d) {
+  const float e = __expf(2.f * z);
+  const float r = __builtin_amdgcn_rcpf(1.f + e);
+  d = 4.f * r * (1.f - r);
+  return 1.f - 2.f * r;
+}
+
+struct MlpArgs {
+  const float* x;      // [B][2n]
+  int B, n, K, L, XP, n_tiles, xcd_grp;
+  const unsigned char* frag;
+  unsigned long long frag_model_bytes;
+  unsigned fwd_off[kMaxHidden];
+  unsigned bwd_off[kMaxHidden];
+  const float* bias;   // [K][L][NP]
+  const float* wo;     // [K][NP]
+  const float* bo;     // [K]
+  float* A_out;        // [K][B]
+  float* g_out;        // [K][B][n]
+};
+
+__device__ inline void map_block(int b, int K, int grp, int& k, int& tile) {
+  if (grp > 0) {
+    int x = b & 7;
+    k = x / grp;
+    tile = (b >> 3) * grp + (x % grp);
+  } else {
+    k = b % K;
+    tile = b / K;
+  }
+}
+
+// acc[rt][c] += act[rows of rt][0:KL] * frag(:, col tile jt0 + c)
+template <class P, int RT, int CT>
+__device__ inline void gemm_tiles(f4 (&acc)[RT][CT], const typename P::T* act,
+                                  int as, const uint4* frag, int JT, int jt0,
+                                  int n_kt, int lane) {
+  constexpr int KF = P::KF;
+  const int r = lane & 15, g = lane >> 4;
+  uint4 bc[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) bc[c] = frag[(size_t)(jt0 + c) * 64 + lane];
+  for (int kt = 0; kt < n_kt; ++kt) {
+    uint4 bn[CT];
+    const int ktn = kt + 1 < n_kt ? kt + 1 : kt;
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+      bn[c] = frag[((size_t)ktn * JT + jt0 + c) * 64 + lane];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const uint4 a = *reinterpret_cast<const uint4*>(
+          act + (rt * 16 + r) * as + kt * KF + g * (KF / 4));
+#pragma unroll
+      for (int c = 0; c < CT; ++c) P::mma(a, bc[c], acc[rt][c]);
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) bc[c] = bn[c];
+  }
+}
+
+template <class P, int NP, int RT, int NW, int LM>
+__global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(MlpArgs p) {
+  using T = typename P::T;
+  constexpr int KF = P::KF;
+  constexpr int CT = NP / (16 * NW);
+  constexpr int R = 16 * RT;
+  constexpr int JT = NP / 16;
+  static_assert(CT >= 1 && CT * 16 * NW == NP, "width/wave split");
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int k, tile;
+  map_block(blockIdx.x, p.K, p.xcd_grp, k, tile);
+  if (tile >= p.n_tiles) return;
+  const int row0 = tile * R;
+  const int n = p.n, L = p.L, XP = p.XP;
+  const int AW = NP > XP ? NP : XP;           // activation tile width
+  const int AS = AW + 16 / (int)sizeof(T);    // row stride (+16 bytes)
+  const int BUF = R * AS;                     // elements per ping-pong buffer
+  T* act = reinterpret_cast<T*>(smem);
+  float* u0 = reinterpret_cast<float*>(smem + (size_t)2 * BUF * sizeof(T));
+  const int US = XP + 4;
+  float* red = u0 + R * US;                   // [NW][R]
+
+  const unsigned char* fbase = p.frag + (size_t)k * p.frag_model_bytes;
+  const float* bias = p.bias + (size_t)k * L * NP;
+  const float* wo = p.wo + (size_t)k * NP;
+
+  // x tile -> buffer 0 (rows past B and columns past 2n are zero)
+  for (int e = threadIdx.x; e < R * XP; e += NW * 64) {
+    int i = e / XP, c = e - i * XP;
+    int row = row0 + i;
+    float v = (row < p.B && c < 2 * n) ? p.x[(size_t)row * 2 * n + c] : 0.f;
+    act[i * AS + c] = P::from_float(v);
+  }
+  __syncthreads();
+
+  const int jt0 = wave * CT;
+  const int colL = lane & 15, rq = 4 * (lane >> 4);
+  f4 st[LM][RT][CT];      // tanh' of every hidden layer, this wave's tiles
+  f4 acc[RT][CT];
+  int cur = 0;
+
+  // ---------------- forward: h_l = tanh(W_l h_{l-1} + b_l) ----------------
+#pragma unroll
+  for (int l = 0; l < LM; ++l) {
+    if (l < L) {
+      const T* in = act + cur * BUF;
+      T* out = act + (cur ^ 1) * BUF;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[rt][c] = f4{0.f, 0.f, 0.f, 0.f};
+      const uint4* fr = reinterpret_cast<const uint4*>(fbase + p.fwd_off[l]);
+      gemm_tiles<P, RT, CT>(acc, in, AS, fr, JT, jt0, (l == 0 ? XP : NP) / KF, lane);
+      const bool last = (l == L - 1);
+      float apart[RT][4];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) apart[rt][q] = 0.f;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = (jt0 + c) * 16 + colL;
+        const float b = bias[l * NP + col];
+        const float w = last ? wo[col] : 0.f;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          f4 d;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            float dq;
+            const float h = tanh_and_grad(acc[rt][c][q] + b, dq);
+            d[q] = dq;
+            const int i = rt * 16 + rq + q;
+            if (last) {
+              apart[rt][q] += w * h;
+              out[i * AS + col] = P::from_float(w * dq);   // v_L
+            } else {
+              out[i * AS + col] = P::from_float(h);
+            }
+          }
+          st[l][rt][c] = d;
+        }
+      }
+      if (last) {
+        // A = wo . h_L + bo: reduce over the 16 column lanes, then waves
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            float v = apart[rt][q];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 8);
+            if (colL == 0) red[wave * R + rt * 16 + rq + q] = v;
+          }
+      }
+      cur ^= 1;
+      __syncthreads();
+    }
+  }
+  // A output
+  for (int i = threadIdx.x; i < R; i += NW * 64) {
+    float a = p.bo[k];
+    for (int w = 0; w < NW; ++w) a += red[w * R + i];
+    if (row0 + i < p.B) p.A_out[(size_t)k * p.B + row0 + i] = a;
+  }
+
+  // ------------- reverse sweep: v_{l-1} = (W_l^T v_l) * tanh'_{l-1} -------------
+#pragma unroll
+  for (int l = LM - 1; l >= 1; --l) {
+    if (l < L) {
+      const T* in = act + cur * BUF;
+      T* out = act + (cur ^ 1) * BUF;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[rt][c] = f4{0.f, 0.f, 0.f, 0.f};
+      const uint4* fr = reinterpret_cast<const uint4*>(fbase + p.bwd_off[l]);
+      gemm_tiles<P, RT, CT>(acc, in, AS, fr, JT, jt0, NP / KF, lane);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = (jt0 + c) * 16 + colL;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          const f4 d = st[l - 1][rt][c];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            out[(rt * 16 + rq + q) * AS + col] = P::from_float(acc[rt][c][q] * d[q]);
+        }
+      }
+      cur ^= 1;
+      __syncthreads();
+    }
+  }
+  // layer 1 backward: u0 = W_1^T v_1, XP columns spread over the waves
+  {
+    const T* in = act + cur * BUF;
+    const uint4* fr = reinterpret_cast<const uint4*>(fbase + p.bwd_off[0]);
+    const int JT0 = XP / 16;
+    for (int t = wave; t < JT0; t += NW) {
+      f4 a1[RT][1];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) a1[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
+      gemm_tiles<P, RT, 1>(a1, in, AS, fr, JT0, t, NP / KF, lane);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          u0[(rt * 16 + rq + q) * US + t * 16 + colL] = a1[rt][0][q];
+    }
+  }
+  __syncthreads();
+  // chain to the angles: g_i = -sin s_i u0[i] + cos s_i u0[n+i]
+  for (int e = threadIdx.x; e < R * n; e += NW * 64) {
+    const int i = e / n, c = e - i * n;
+    const int row = row0 + i;
+    if (row < p.B) {
+      const float cs = p.x[(size_t)row * 2 * n + c];
+      const float sn = p.x[(size_t)row * 2 * n + n + c];
+      const float gv = -sn * u0[i * US + c] + cs * u0[i * US + n + c];
+      p.g_out[((size_t)k * p.B + row) * n + c] = gv;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// weight packer: FP32 masters (packed layout) -> MFMA fragments, biases
+// ---------------------------------------------------------------------------
+struct PackLayer {
+  unsigned w_off, b_off;  // float offsets inside one model's packed block
+  int in, out;            // real widths
+  int kin_pad;            // padded input width
+  unsigned fwd_off, bwd_off;  // byte offsets inside one model's fragments
+};
+
+template <class P>
+__global__ void pack_layer_kernel(const float* master, size_t per_model, int K,
+                                  PackLayer pl, int NP, int dir,
+                                  unsigned char* frag, size_t frag_model_bytes) {
+  using T = typename P::T;
+  constexpr int KF = P::KF;
+  constexpr int E = 16 / sizeof(T);
+  // dir 0: contraction = input (kin_pad), columns = NP (outputs)
+  // dir 1: contraction = NP (outputs), columns = kin_pad (inputs)
+  const int kc = dir == 0 ? pl.kin_pad : NP;
+  const int nc = dir == 0 ? NP : pl.kin_pad;
+  const int JT = nc / 16, KT = kc / KF;
+  const size_t total = (size_t)K * KT * JT * 64;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * blockDim.x) {
+    const int lane = t % 64;
+    size_t f = t / 64;
+    const int jt = f % JT; f /= JT;
+    const int kt = f % KT;
+    const int k = (int)(f / KT);
+    const float* W = master + (size_t)k * per_model + pl.w_off;
+    const int col = jt * 16 + (lane & 15);
+    T out[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kk = kt * KF + (KF / 4) * (lane >> 4) + e;
+      // W is [out][in]; forward: B[kk=in][col=out]; backward: B[kk=out][col=in]
+      const int o = dir == 0 ? col : kk;
+      const int i = dir == 0 ? kk : col;
+      const float v = (o < pl.out && i < pl.in) ? W[(size_t)o * pl.in + i] : 0.f;
+      out[e] = P::from_float(v);
+    }
+    unsigned char* dst = frag + (size_t)k * frag_model_bytes +
+                         (dir == 0 ? pl.fwd_off : pl.bwd_off) +
+                         (((size_t)kt * JT + jt) * 64 + lane) * 16;
+    *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(out);
+  }
+}
+
+struct VecArgs {
+  unsigned b_off[kMaxHidden];
+  int out[kMaxHidden];
+  unsigned wo_off;
+  int last_w;
+};
+
+__global__ void pack_vec_kernel(const float* master, size_t per_model, int L,
+                                int NP, VecArgs va, float* bias, float* wo,
+                                float* bo) {
+  const int k = blockIdx.x;
+  const float* m = master + (size_t)k * per_model;
+  for (int l = 0; l < L; ++l)
+    for (int j = threadIdx.x; j < NP; j += blockDim.x)
+      bias[((size_t)k * L + l) * NP + j] = j < va.out[l] ? m[va.b_off[l] + j] : 0.f;
+  for (int j = threadIdx.x; j < NP; j += blockDim.x)
+    wo[(size_t)k * NP + j] = j < va.last_w ? m[va.wo_off + j] : 0.f;
+  if (threadIdx.x == 0) bo[k] = m[va.wo_off + va.last_w];
+}
+
+template <class P, int NP, int RT, int NW, int LM>
+rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
+                   float* A_out, float* g_out, hipStream_t st) {
+  static bool attr_done = false;
+  constexpr int R = 16 * RT;
+  using T = typename P::T;
+  const int AW = NP > e.XP ? NP : e.XP;
+  const int AS = AW + 16 / (int)sizeof(T);
+  const size_t lds = (size_t)2 * R * AS * sizeof(T) + (size_t)R * (e.XP + 4) * 4 +
+                     (size_t)NW * R * 4;
+  if (lds > 160 * 1024)
+    return fail(RID_EUNSUPPORTED, "ensemble too wide for the fused kernel's LDS");
+  auto kern = mlp_fused_kernel<P, NP, RT, NW, LM>;
+  if (!attr_done && lds > 64 * 1024) {
+    RID_HIP(hipFuncSetAttribute((const void*)kern,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    attr_done = true;
+  }
+  MlpArgs a{};
+  a.x = x; a.B = B; a.n = e.n_cv; a.K = e.K; a.L = e.L; a.XP = e.XP;
+  a.n_tiles = (B + R - 1) / R;
+  a.xcd_grp = (8 % e.K == 0) ? 8 / e.K : 0;
+  a.frag = e.d_frag; a.frag_model_bytes = e.frag_bytes_per_model;
+  for (int l = 0; l < e.L; ++l) {
+    a.fwd_off[l] = (unsigned)e.layers[l].fwd_off;
+    a.bwd_off[l] = (unsigned)e.layers[l].bwd_off;
+  }
+  a.bias = e.d_bias; a.wo = e.d_wo; a.bo = e.d_bo;
+  a.A_out = A_out; a.g_out = g_out;
+  int grid;
+  if (a.xcd_grp > 0)
+    grid = 8 * ((a.n_tiles + a.xcd_grp - 1) / a.xcd_grp);
+  else
+    grid = a.n_tiles * e.K;
+  ProfScope ps(kProfMlp, st);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, st, a);
+  RID_HIP(hipGetLastError());
+  return RID_OK;
+}
+
+template <class P>
+rid_status launch_16bit(const rid_ensemble_impl& e, const float* x, int B,
+                        float* A_out, float* g_out, hipStream_t st) {
+  if (e.L <= 4) {
+    switch (e.NP) {
+      case 64:  return run_mlp<P, 64, 2, 4, 4>(e, x, B, A_out, g_out, st);
+      case 128: return run_mlp<P, 128, 2, 4, 4>(e, x, B, A_out, g_out, st);
+      case 256: return run_mlp<P, 256, 2, 4, 4>(e, x, B, A_out, g_out, st);
+      case 512: return run_mlp<P, 512, 2, 8, 4>(e, x, B, A_out, g_out, st);
+    }
+  } else {
+    switch (e.NP) {
+      case 64:  return run_mlp<P, 64, 1, 4, 6>(e, x, B, A_out, g_out, st);
+      case 128: return run_mlp<P, 128, 1, 4, 6>(e, x, B, A_out, g_out, st);
+      case 256: return run_mlp<P, 256, 1, 4, 6>(e, x, B, A_out, g_out, st);
+      case 512: return run_mlp<P, 512, 1, 8, 6>(e, x, B, A_out, g_out, st);
+    }
+  }
+  return fail(RID_EUNSUPPORTED, "no kernel for this padded width");
+}
+
+}  // namespace
+
+// Kernel family: (precision, padded width, depth) -> instantiation.
+// FP32: 16 walkers per workgroup (MFMA f32 is 16x slower per FLOP, so the
+// L2 weight stream is not the limit); 16-bit: 32 walkers per workgroup to
+// halve the weight traffic per FLOP; depth <= 4 keeps the FP32 tanh' stash
+// small, deeper networks take 16 walkers per workgroup.
+rid_status launch_mlp(const rid_ensemble_impl& e, const float* x, int B,
+                      float* A_out, float* g_out, hipStream_t st) {
+  if (e.prec == RID_FP32) {
+    switch (e.NP) {
+      case 64:  return run_mlp<F32, 64, 1, 4, 6>(e, x, B, A_out, g_out, st);
+      case 128: return run_mlp<F32, 128, 1, 4, 6>(e, x, B, A_out, g_out, st);
+      case 256: return run_mlp<F32, 256, 1, 4, 6>(e, x, B, A_out, g_out, st);
+      case 512: return run_mlp<F32, 512, 1, 8, 6>(e, x, B, A_out, g_out, st);
+    }
+    return fail(RID_EUNSUPPORTED, "no kernel for this padded width");
+  }
+  if (e.prec == RID_BF16) return launch_16bit<BF16>(e, x, B, A_out, g_out, st);
+  return launch_16bit<F16>(e, x, B, A_out, g_out, st);
+}
+
+rid_status pack_ensemble_weights(rid_ensemble_impl& e, hipStream_t st) {
+  const int L = e.L;
+  VecArgs va{};
+  unsigned off = 0;
+  int prev = 2 * e.n_cv;
+  for (int l = 0; l < L; ++l) {
+    PackLayer pl{};
+    pl.w_off = off;
+    pl.in = prev;
+    pl.out = e.widths[l];
+    off += (unsigned)(pl.out * pl.in);
+    pl.b_off = off;
+    va.b_off[l] = off;
+    va.out[l] = pl.out;
+    off += (unsigned)pl.out;
+    pl.kin_pad = e.layers[l].kin_pad;
+    pl.fwd_off = (unsigned)e.layers[l].fwd_off;
+    pl.bwd_off = (unsigned)e.layers[l].bwd_off;
+    for (int dir = 0; dir < 2; ++dir) {
+      if (e.prec == RID_FP32)
+        hipLaunchKernelGGL(pack_layer_kernel<F32>, dim3(512), dim3(256), 0, st,
+                           e.d_master, e.per_model, e.K, pl, e.NP, dir,
+                           e.d_frag, e.frag_bytes_per_model);
+      else if (e.prec == RID_BF16)
+        hipLaunchKernelGGL(pack_layer_kernel<BF16>, dim3(512), dim3(256), 0, st,
+                           e.d_master, e.per_model, e.K, pl, e.NP, dir,
+                           e.d_frag, e.frag_bytes_per_model);
+      else
+        hipLaunchKernelGGL(pack_layer_kernel<F16>, dim3(512), dim3(256), 0, st,
+                           e.d_master, e.per_model, e.K, pl, e.NP, dir,
+                           e.d_frag, e.frag_bytes_per_model);
+      RID_HIP(hipGetLastError());
+    }
+    prev = pl.out;
+  }
+  va.wo_off = off;
+  va.last_w = prev;
+  hipLaunchKernelGGL(pack_vec_kernel, dim3(e.K), dim3(256), 0, st, e.d_master,
+                     e.per_model, L, e.NP, va, e.d_bias, e.d_wo, e.d_bo);
+  RID_HIP(hipGetLastError());
+  return RID_OK;
+}
+
+}  // namespace rid

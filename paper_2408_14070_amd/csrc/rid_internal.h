@@ -1,0 +1,156 @@
+// Internal declarations shared by the library's translation units.
+// Not part of the public ABI (include/rid.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rid.h"
+
+namespace rid {
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+rid_status fail(rid_status st, const std::string& msg);
+inline rid_status hip_fail(hipError_t e, const char* what) {
+  return fail(RID_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define RID_HIP(expr)                                        \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return ::rid::hip_fail(e_, #expr); \
+  } while (0)
+
+// Device buffer that grows on demand (never shrinks until destroyed).
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  rid_status ensure(size_t need);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+// ---------------------------------------------------------------------------
+// optional kernel timing (rid_profile_enable): a pair of hipEvents around a
+// launch on the launching stream; no synchronisation at record time.
+// ---------------------------------------------------------------------------
+enum ProfKind {
+  kProfCv = 0, kProfMlp = 1, kProfScatter = 2, kProfReduce = 3, kProfEmbed = 4,
+  kProfTrain = 5, kProfLabel = 6, kProfKinds = 7
+};
+bool prof_enabled();
+hipEvent_t prof_record(hipStream_t st);
+void prof_push(int kind, hipEvent_t a, hipEvent_t b);
+struct ProfScope {
+  int kind;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(int k, hipStream_t s) : kind(k), st(s) {
+    if (prof_enabled()) a = prof_record(st);
+  }
+  ~ProfScope() {
+    if (a) prof_push(kind, a, prof_record(st));
+  }
+};
+
+// ---------------------------------------------------------------------------
+// MFMA fragment geometry shared by the weight packer and the kernels.
+// A "fragment" covers 16 output columns x KF contraction indices and is
+// stored as 64 lanes x 16 bytes: lane l holds column (l % 16) and the KF/4
+// consecutive contraction indices starting at (KF/4) * (l / 16).
+//   FP32 (v_mfma_f32_16x16x4_f32 issued four times): KF = 16, 4 floats/lane
+//   BF16 (v_mfma_f32_16x16x32_bf16):                KF = 32, 8 bf16/lane
+// ---------------------------------------------------------------------------
+constexpr int kFragBytes = 1024;
+inline int kf_of(rid_precision p) { return p == RID_FP32 ? 16 : 32; }
+inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+constexpr int kMaxHidden = 6;
+constexpr int kMaxWidth = 512;
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct LayerDev {
+  // forward fragments: contraction = padded input width, columns = NP
+  // backward fragments: contraction = NP, columns = padded input width
+  size_t fwd_off = 0, bwd_off = 0;   // byte offsets inside frag buffer
+  int kin_pad = 0;                   // padded input width of this layer
+};
+
+struct rid_system_impl {
+  int n_atoms = 0, n_cv = 0;
+  std::vector<int32_t> quads;        // host copy [n_cv][4]
+  // unique atoms touched by torsions (sorted) and quads in local indices
+  std::vector<int32_t> uniq;
+  int n_uniq = 0;
+  int32_t* d_uniq = nullptr;         // [n_uniq]
+  int32_t* d_lquads = nullptr;       // [n_cv][4] local indices into uniq
+  // inverse map local atom -> (cv, slot) entries, CSR, fixed order
+  int32_t* d_csr_ptr = nullptr;      // [n_uniq + 1]
+  int32_t* d_csr_ent = nullptr;      // [4 n_cv] entry = cv * 4 + slot
+  int32_t* d_atom_local = nullptr;   // [n_atoms] local index or -1
+  int max_deg = 0;
+};
+
+struct rid_ensemble_impl {
+  int n_cv = 0, K = 0, L = 0;
+  std::vector<int> widths;
+  rid_precision prec = RID_FP32;
+  int NP = 0;        // padded hidden width (multiple of 64)
+  int XP = 0;        // padded input width (multiple of KF)
+  int KF = 16;
+  size_t n_params = 0;          // packed count (all models)
+  size_t per_model = 0;         // packed count of one model
+  // FP32 masters in packed layout + Adam moments (device)
+  float* d_master = nullptr;
+  float* d_m = nullptr;
+  float* d_v = nullptr;
+  int64_t step = 0;
+  // kernel-layout parameters
+  std::vector<LayerDev> layers;
+  size_t frag_bytes_per_model = 0;
+  unsigned char* d_frag = nullptr;   // [K][frag_bytes_per_model]
+  float* d_bias = nullptr;           // [K][L][NP] zero padded
+  float* d_wo = nullptr;             // [K][NP]
+  float* d_bo = nullptr;             // [K]
+  // scratch
+  bool frag_dirty = false;           // masters changed since the last pack
+  DevBuf ws_x, ws_A, ws_g, ws_train;
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+rid_status launch_cv_eval(const rid_system_impl& s, const float* pos, int B,
+                          float* d_s, float* d_x, hipStream_t st);
+rid_status launch_embed(const float* s, int B, int n, float* x, hipStream_t st);
+rid_status launch_mlp(const rid_ensemble_impl& e, const float* x, int B,
+                      float* A_out, float* g_out, hipStream_t st);
+rid_status launch_ensemble_reduce(int K, int n, int B, const float* A,
+                                  const float* g, float* eps, float* gbar,
+                                  float* A_t, float* g_t, hipStream_t st);
+rid_status launch_bias_scatter(const rid_system_impl& s, int K, const float* pos,
+                               int B, const float* A, const float* g,
+                               const float* fcv, float eps0, float eps1,
+                               float* force, float* energy, float* eps,
+                               float* sigma, uint8_t* flags, hipStream_t st);
+rid_status pack_ensemble_weights(rid_ensemble_impl& e, hipStream_t st);
+rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
+                          const float* rho, int B, float* loss, float* grad_out,
+                          float** grad_used, hipStream_t st);
+rid_status launch_train_step(rid_ensemble_impl& e, const float* s,
+                             const float* F, int B, float lr, float* loss,
+                             hipStream_t st);
+rid_status launch_mf_label_impl(const float* traj, const float* s0,
+                                const float* kappa, const uint8_t* mask, int M,
+                                int T, int n, float thr, double* F, double* se,
+                                uint8_t* keep, hipStream_t st);
+
+}  // namespace rid

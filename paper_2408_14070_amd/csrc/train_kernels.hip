@@ -1,0 +1,530 @@
+// Mean-force fitting step ("Training phase"): the models' CV gradients are
+// fitted to mean-force labels, so the loss gradient in the weights needs the
+// derivative of dA/ds -- a double backward.
+//
+// With rho_b = 2 (g_b - F_b) / B mapped to the input x (rho_x), the weight
+// gradient of L = (1/B) sum_b |g_b - F_b|^2 equals the gradient of
+// J = sum_b rho_x,b . dA/dx with rho_x held fixed:
+//   primal   h_l = tanh(W_l h_{l-1} + b_l)                 (h_0 = x)
+//   backward v_L = w_o (1-h_L^2), u_{l-1} = W_l^T v_l, v_l = u_l (1-h_l^2)
+//   tangent  zd_l = W_l hd_{l-1}, hd_l = (1-h_l^2) zd_l     (hd_0 = rho_x)
+//   adjoint  lam_hd_L = w_o, lam_h_L = 0; for l = L..1:
+//            lam_zd = (1-h_l^2) lam_hd, lam_h -= 2 h_l zd_l lam_hd,
+//            lam_z = (1-h_l^2) lam_h,
+//            dW_l = lam_z^T h_{l-1} + lam_zd^T hd_{l-1}, db_l = sum lam_z,
+//            [lam_h ; lam_hd]_{l-1} = [lam_z ; lam_zd] W_l
+//   dw_o = sum hd_L, db_o = 0.
+// Then one Adam step on the FP32 masters.
+//
+// Layout: batched over the K members; "stacked" tensors hold the primal
+// quantity in rows [0, B) and the tangent one in rows [B, 2B) of each
+// member's slab, so one GEMM moves both halves, and the weight gradient is a
+// single contraction over 2B rows.  All GEMMs are one hand-written FP32-MFMA
+// kernel (64x64 tiles, LDS double buffering, arbitrary strides, fused
+// epilogues); the weight-gradient GEMM is split along the batch with a
+// fixed-order reduction, so the whole step is deterministic.
+#include "rid_internal.h"
+
+namespace rid {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, LDK = BK + 4;
+constexpr int kThreads = 256;
+
+enum Epi {
+  EPI_STORE = 0,      // C = acc
+  EPI_BIAS_TANH = 1,  // C = tanh(acc + bias[n])
+  EPI_MUL_DTANH = 2,  // C = acc * (1 - aux^2)
+  EPI_TANGENT = 3     // C = acc, C2 = acc * (1 - aux^2)
+};
+
+struct GemmArgs {
+  const float* A;
+  long long sAb, sAm, sAk;
+  const float* Bm;
+  long long sBb, sBk, sBn;
+  float* C;
+  long long sCb, sCm, sCn, sCs;   // sCs: split-K slab stride
+  float* C2;                      // second output (EPI_TANGENT): C's row and
+  long long sC2b;                 // column strides, own batch stride
+  const float* bias;
+  long long sBiasb;
+  const float* aux;               // same strides as C (sXb, sXm, sXn)
+  long long sXb, sXm, sXn;
+  int M, N, Kc, batch, ksplit, kchunk, mode;
+};
+
+__device__ inline float tanh_fast(float z) {
+  const float e = __expf(2.f * z);
+  return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + e);
+}
+
+// C[b] = A[b] (M x Kc) * B[b] (Kc x N), tiles of 64 x 64, 4 waves of 32 x 32.
+__global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) float As[2][BM][LDK];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BN][LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int b = blockIdx.z / g.ksplit, s = blockIdx.z % g.ksplit;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int k_begin = s * g.kchunk;
+  const int k_end = min(g.Kc, k_begin + g.kchunk);
+  const float* A = g.A + b * g.sAb;
+  const float* Bp = g.Bm + b * g.sBb;
+  const bool a_kfast = g.sAk == 1;
+  const bool b_kfast = g.sBk == 1;
+
+  float ra[4], rb[4];
+  auto load = [&](int kb) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int idx = tid + kThreads * j;
+      int m, k;
+      if (a_kfast) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
+      const int gm = m0 + m, gk = kb + k;
+      ra[j] = (gm < g.M && gk < k_end) ? A[gm * g.sAm + gk * g.sAk] : 0.f;
+      int n, k2;
+      if (b_kfast) { k2 = idx % BK; n = idx / BK; } else { n = idx % BN; k2 = idx / BN; }
+      const int gn = n0 + n, gk2 = kb + k2;
+      rb[j] = (gn < g.N && gk2 < k_end) ? Bp[gk2 * g.sBk + gn * g.sBn] : 0.f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int idx = tid + kThreads * j;
+      int m, k;
+      if (a_kfast) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
+      As[buf][m][k] = ra[j];
+      int n, k2;
+      if (b_kfast) { k2 = idx % BK; n = idx / BK; } else { n = idx % BN; k2 = idx / BN; }
+      Bs[buf][n][k2] = rb[j];
+    }
+  };
+
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int r = lane & 15, gq = lane >> 4;
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  int buf = 0;
+  load(k_begin);
+  store(0);
+  __syncthreads();
+  for (int kb = k_begin; kb < k_end; kb += BK) {
+    const bool more = kb + BK < k_end;
+    if (more) load(kb + BK);
+    f4 a[2], bb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      a[i] = *reinterpret_cast<const f4*>(&As[buf][wm + i * 16 + r][4 * gq]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      bb[j] = *reinterpret_cast<const f4*>(&Bs[buf][wn + j * 16 + r][4 * gq]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][e], bb[j][e], acc[i][j], 0, 0, 0);
+    if (more) {
+      store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  float* C = g.C + b * g.sCb + s * g.sCs;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn + j * 16 + r;
+      if (n >= g.N) continue;
+      const float bias = g.mode == EPI_BIAS_TANH ? g.bias[b * g.sBiasb + n] : 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm + i * 16 + 4 * gq + q;
+        if (m >= g.M) continue;
+        const float v = acc[i][j][q];
+        const long long ci = m * g.sCm + n * g.sCn;
+        if (g.mode == EPI_STORE) {
+          C[ci] = v;
+        } else if (g.mode == EPI_BIAS_TANH) {
+          C[ci] = tanh_fast(v + bias);
+        } else {
+          const float h = g.aux[b * g.sXb + m * g.sXm + n * g.sXn];
+          const float d = 1.f - h * h;
+          if (g.mode == EPI_MUL_DTANH) {
+            C[ci] = v * d;
+          } else {
+            C[ci] = v;
+            g.C2[b * g.sC2b + ci] = v * d;
+          }
+        }
+      }
+    }
+}
+
+// x = [cos s | sin s] into the primal half of every member's stacked slab
+__global__ void train_embed_kernel(const float* s, int B, int n, int K,
+                                   float* HH0, long long slab) {
+  const long long total = (long long)K * B * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(e / ((long long)B * n));
+    const long long r = e - (long long)k * B * n;
+    const int b = (int)(r / n), i = (int)(r - (long long)b * n);
+    float sn, cs;
+    sincosf(s[(long long)b * n + i], &sn, &cs);
+    float* row = HH0 + k * slab + (long long)b * 2 * n;
+    row[i] = cs;
+    row[n + i] = sn;
+  }
+}
+
+// v_L = w_o (1 - h_L^2)
+__global__ void vlast_kernel(const float* HHL, long long slab, const float* master,
+                             long long per_model, int wo_off, int w, int B, int K,
+                             float* V) {
+  const long long total = (long long)K * B * w;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(e / ((long long)B * w));
+    const long long r = e - (long long)k * B * w;
+    const int j = (int)(r % w);
+    const float h = HHL[k * slab + r];
+    V[e] = master[k * per_model + wo_off + j] * (1.f - h * h);
+  }
+}
+
+// g = chain(u0, s); residual; per-row squared residual; rho_x into the
+// tangent half of the stacked input slab.  With an upstream gradient
+// rho [B][K][n] given instead of labels, rho_x is built from it directly.
+__global__ void residual_kernel(const float* s, const float* F, const float* rho_in,
+                                const float* U0, int B, int n, int K, float* HH0,
+                                long long slab, float* loss_rows) {
+  const long long total = (long long)K * B;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(e / B), b = (int)(e - (long long)k * B);
+    const float* u = U0 + e * 2 * n;
+    float* rx = HH0 + k * slab + ((long long)B + b) * 2 * n;
+    float acc = 0.f;
+    for (int i = 0; i < n; ++i) {
+      float sn, cs;
+      sincosf(s[(long long)b * n + i], &sn, &cs);
+      float rho;
+      if (rho_in) {
+        rho = rho_in[((long long)b * K + k) * n + i];
+      } else {
+        const float gi = -sn * u[i] + cs * u[n + i];
+        const float ri = gi - F[(long long)b * n + i];
+        acc += ri * ri;
+        rho = 2.f * ri / (float)B;
+      }
+      rx[i] = -sn * rho;
+      rx[n + i] = cs * rho;
+    }
+    if (loss_rows) loss_rows[e] = acc;
+  }
+}
+
+// Adjoint stage of layer l: given h_l, zd_l and (lam_h, lam_hd) produce the
+// stacked (lam_z ; lam_zd).  For the top layer lam_hd = w_o, lam_h = 0.
+__global__ void adjoint_kernel(const float* HHl, long long slab_h, const float* Zd,
+                               const float* LAM, long long slab_lam,
+                               const float* master, long long per_model, int wo_off,
+                               int top, int w, int B, int K, float* S,
+                               long long slab_s) {
+  const long long total = (long long)K * B * w;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(e / ((long long)B * w));
+    const long long r = e - (long long)k * B * w;   // row-major offset inside the primal half
+    const int j = (int)(r % w);
+    const float h = HHl[k * slab_h + r];
+    const float zd = Zd[e];
+    float lh, lhd;
+    if (top) {
+      lh = 0.f;
+      lhd = master[k * per_model + wo_off + j];
+    } else {
+      lh = LAM[k * slab_lam + r];
+      lhd = LAM[k * slab_lam + (long long)B * w + r];
+    }
+    const float d = 1.f - h * h;
+    const float lzd = d * lhd;
+    lh -= 2.f * h * zd * lhd;
+    S[k * slab_s + r] = d * lh;                       // lam_z
+    S[k * slab_s + (long long)B * w + r] = lzd;       // lam_zd
+  }
+}
+
+// out[k][j] = sum_b X[k][b][j] (fixed order), written into the gradient
+// buffer at dst + k*per_model + j.
+__global__ void colsum_kernel(const float* X, long long slab, int B, int w, int K,
+                              float* grad, long long per_model, int dst_off) {
+  const int total = K * w;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int k = e / w, j = e - k * w;
+    const float* p = X + k * slab + j;
+    float acc = 0.f;
+    for (int b = 0; b < B; ++b) acc += p[(long long)b * w];
+    grad[k * per_model + dst_off + j] = acc;
+  }
+}
+
+// dW[k] = sum over split-K slabs (fixed order) -> gradient buffer
+__global__ void splitk_reduce_kernel(const float* part, long long slab_s, int ks,
+                                     int out, int in, int K, float* grad,
+                                     long long per_model, int w_off) {
+  const long long total = (long long)K * out * in;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    float acc = 0.f;
+    for (int s = 0; s < ks; ++s) acc += part[s * slab_s + e];
+    const int k = (int)(e / ((long long)out * in));
+    const long long r = e - (long long)k * out * in;
+    grad[k * per_model + w_off + r] = acc;
+  }
+}
+
+__global__ void loss_reduce_kernel(const float* rows, int B, float* loss) {
+  __shared__ float red[256];
+  const int k = blockIdx.x;
+  float acc = 0.f;
+  for (int b = threadIdx.x; b < B; b += 256) acc += rows[(long long)k * B + b];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) loss[k] = red[0] / (float)B;
+}
+
+__global__ void set_zero_kernel(float* grad, long long per_model, int off, int K) {
+  for (int k = threadIdx.x; k < K; k += blockDim.x) grad[k * per_model + off] = 0.f;
+}
+
+__global__ void adam_kernel(float* theta, float* m, float* v, const float* g,
+                            long long n, float lr, float c1, float c2) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const float gi = g[e];
+    const float mi = 0.9f * m[e] + 0.1f * gi;
+    const float vi = 0.999f * v[e] + 0.001f * gi * gi;
+    m[e] = mi;
+    v[e] = vi;
+    theta[e] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+  }
+}
+
+inline int grid1d(long long total) {
+  return (int)std::min<long long>((total + 255) / 256, 4096);
+}
+
+rid_status gemm(const GemmArgs& g0, hipStream_t st) {
+  GemmArgs g = g0;
+  if (g.ksplit < 1) g.ksplit = 1;
+  if (g.kchunk <= 0) g.kchunk = round_up(g.Kc, BK);
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * g.ksplit);
+  hipLaunchKernelGGL(gemm_f32_kernel, grid, dim3(kThreads), 0, st, g);
+  RID_HIP(hipGetLastError());
+  return RID_OK;
+}
+
+}  // namespace
+
+// Gradient in the packed parameter layout of
+//   F given:   L = sum_k (1/B) sum_b |g_k(s_b) - F_b|^2      (loss[k] written)
+//   rho given: J = sum_k sum_b rho[b][k] . g_k(s_b)
+// into grad_out (or the workspace's gradient slot when grad_out is null).
+// Returns the gradient pointer through *grad_used.
+rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
+                          const float* rho, int B, float* loss, float* grad_out,
+                          float** grad_used, hipStream_t st) {
+  const int K = e.K, L = e.L, n = e.n_cv, X = 2 * n;
+  std::vector<int> w(L + 1);
+  w[0] = X;
+  for (int l = 0; l < L; ++l) w[l + 1] = e.widths[l];
+  int wmax = X;
+  for (int v : w) wmax = std::max(wmax, v);
+  // packed offsets inside one model's block
+  std::vector<long long> w_off(L), b_off(L);
+  long long off = 0;
+  for (int l = 0; l < L; ++l) {
+    w_off[l] = off;
+    off += (long long)w[l + 1] * w[l];
+    b_off[l] = off;
+    off += w[l + 1];
+  }
+  const long long wo_off = off;
+  const long long pm = (long long)e.per_model;
+
+  // split of the 2B-row weight-gradient contraction
+  int tiles_max = 0;
+  for (int l = 0; l < L; ++l)
+    tiles_max = std::max(tiles_max, ((w[l + 1] + BM - 1) / BM) * ((w[l] + BN - 1) / BN));
+  int ks = 1;
+  while (ks < 64 && (long long)K * tiles_max * ks < 1024 && 2LL * B / (ks * 2) >= 256) ks *= 2;
+  const int kchunk = round_up((2 * B + ks - 1) / ks, BK);
+
+  // workspace (floats)
+  std::vector<long long> hh(L + 1), zd(L + 1);
+  long long tot = 0;
+  for (int l = 0; l <= L; ++l) {
+    hh[l] = tot;
+    tot += (long long)K * 2 * B * w[l];
+  }
+  for (int l = 1; l <= L; ++l) {
+    zd[l] = tot;
+    tot += (long long)K * B * w[l];
+  }
+  const long long vA = tot; tot += (long long)K * B * wmax;
+  const long long vB = tot; tot += (long long)K * B * wmax;
+  const long long lamA = tot; tot += (long long)K * 2 * B * wmax;
+  const long long lamB = tot; tot += (long long)K * 2 * B * wmax;
+  const long long sbuf = tot; tot += (long long)K * 2 * B * wmax;
+  long long part_slab = 0;
+  for (int l = 0; l < L; ++l) part_slab = std::max(part_slab, (long long)K * w[l + 1] * w[l]);
+  const long long part = tot; tot += part_slab * ks;
+  const long long grad = tot; tot += (long long)e.n_params;
+  const long long lrows = tot; tot += (long long)K * B;
+  rid_status rs = e.ws_train.ensure(sizeof(float) * tot);
+  if (rs != RID_OK) return rs;
+  float* W = e.ws_train.as<float>();
+  float* P = e.d_master;
+  float* G = grad_out ? grad_out : W + grad;
+  *grad_used = G;
+  ProfScope ps(kProfTrain, st);
+
+  auto slab = [&](int l) { return 2LL * B * w[l]; };
+  // ---- primal forward ----
+  hipLaunchKernelGGL(train_embed_kernel, dim3(grid1d((long long)K * B * n)), dim3(256), 0, st,
+                     s, B, n, K, W + hh[0], slab(0));
+  RID_HIP(hipGetLastError());
+  for (int l = 1; l <= L; ++l) {
+    GemmArgs g{};
+    g.A = W + hh[l - 1]; g.sAb = slab(l - 1); g.sAm = w[l - 1]; g.sAk = 1;
+    g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = 1; g.sBn = w[l - 1];
+    g.C = W + hh[l]; g.sCb = slab(l); g.sCm = w[l]; g.sCn = 1;
+    g.bias = P + b_off[l - 1]; g.sBiasb = pm;
+    g.M = B; g.N = w[l]; g.Kc = w[l - 1]; g.batch = K; g.mode = EPI_BIAS_TANH;
+    if ((rs = gemm(g, st)) != RID_OK) return rs;
+  }
+  // ---- primal backward to u0 ----
+  hipLaunchKernelGGL(vlast_kernel, dim3(grid1d((long long)K * B * w[L])), dim3(256), 0, st,
+                     W + hh[L], slab(L), P, pm, (int)wo_off, w[L], B, K, W + vA);
+  RID_HIP(hipGetLastError());
+  long long vin = vA, vout = vB;
+  for (int l = L; l >= 1; --l) {
+    GemmArgs g{};
+    g.A = W + vin; g.sAb = (long long)B * w[l]; g.sAm = w[l]; g.sAk = 1;
+    g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = w[l - 1]; g.sBn = 1;
+    g.C = W + vout; g.sCb = (long long)B * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
+    g.M = B; g.N = w[l - 1]; g.Kc = w[l]; g.batch = K;
+    if (l > 1) {
+      g.mode = EPI_MUL_DTANH;
+      g.aux = W + hh[l - 1]; g.sXb = slab(l - 1); g.sXm = w[l - 1]; g.sXn = 1;
+    } else {
+      g.mode = EPI_STORE;
+    }
+    if ((rs = gemm(g, st)) != RID_OK) return rs;
+    std::swap(vin, vout);
+  }
+  // vin now holds u0 [K][B][2n]
+  hipLaunchKernelGGL(residual_kernel, dim3(grid1d((long long)K * B)), dim3(256), 0, st,
+                     s, F, rho, W + vin, B, n, K, W + hh[0], slab(0),
+                     rho ? nullptr : W + lrows);
+  RID_HIP(hipGetLastError());
+  if (!rho) {
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(K), dim3(256), 0, st, W + lrows, B, loss);
+    RID_HIP(hipGetLastError());
+  }
+  // ---- tangent forward: zd_l = W_l hd_{l-1}, hd_l = (1-h_l^2) zd_l ----
+  for (int l = 1; l <= L; ++l) {
+    GemmArgs g{};
+    g.A = W + hh[l - 1] + (long long)B * w[l - 1]; g.sAb = slab(l - 1); g.sAm = w[l - 1]; g.sAk = 1;
+    g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = 1; g.sBn = w[l - 1];
+    g.C = W + zd[l]; g.sCb = (long long)B * w[l]; g.sCm = w[l]; g.sCn = 1;
+    g.C2 = W + hh[l] + (long long)B * w[l]; g.sC2b = slab(l);
+    g.aux = W + hh[l]; g.sXb = slab(l); g.sXm = w[l]; g.sXn = 1;
+    g.M = B; g.N = w[l]; g.Kc = w[l - 1]; g.batch = K; g.mode = EPI_TANGENT;
+    if ((rs = gemm(g, st)) != RID_OK) return rs;
+  }
+  // ---- adjoint sweep with weight gradients ----
+  long long lin = lamA, lout = lamB;
+  for (int l = L; l >= 1; --l) {
+    hipLaunchKernelGGL(adjoint_kernel, dim3(grid1d((long long)K * B * w[l])), dim3(256), 0, st,
+                       W + hh[l], slab(l), W + zd[l], W + lin, 2LL * B * w[l], P, pm,
+                       (int)wo_off, l == L ? 1 : 0, w[l], B, K, W + sbuf, 2LL * B * w[l]);
+    RID_HIP(hipGetLastError());
+    // dW_l = S^T [h_{l-1}; hd_{l-1}]  (contraction over 2B rows, split)
+    {
+      GemmArgs g{};
+      g.A = W + sbuf; g.sAb = 2LL * B * w[l]; g.sAm = 1; g.sAk = w[l];
+      g.Bm = W + hh[l - 1]; g.sBb = slab(l - 1); g.sBk = w[l - 1]; g.sBn = 1;
+      g.C = W + part; g.sCb = (long long)w[l] * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
+      g.sCs = (long long)K * w[l] * w[l - 1];
+      g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * B; g.batch = K; g.ksplit = ks; g.kchunk = kchunk;
+      g.mode = EPI_STORE;
+      if ((rs = gemm(g, st)) != RID_OK) return rs;
+      hipLaunchKernelGGL(splitk_reduce_kernel,
+                         dim3(grid1d((long long)K * w[l] * w[l - 1])), dim3(256), 0, st,
+                         W + part, (long long)K * w[l] * w[l - 1], ks, w[l], w[l - 1], K,
+                         G, pm, (int)w_off[l - 1]);
+      RID_HIP(hipGetLastError());
+    }
+    // db_l = sum_b lam_z
+    hipLaunchKernelGGL(colsum_kernel, dim3(grid1d((long long)K * w[l])), dim3(256), 0, st,
+                       W + sbuf, 2LL * B * w[l], B, w[l], K, G, pm, (int)b_off[l - 1]);
+    RID_HIP(hipGetLastError());
+    if (l > 1) {
+      // [lam_h ; lam_hd]_{l-1} = [lam_z ; lam_zd] W_l
+      GemmArgs g{};
+      g.A = W + sbuf; g.sAb = 2LL * B * w[l]; g.sAm = w[l]; g.sAk = 1;
+      g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = w[l - 1]; g.sBn = 1;
+      g.C = W + lout; g.sCb = 2LL * B * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
+      g.M = 2 * B; g.N = w[l - 1]; g.Kc = w[l]; g.batch = K; g.mode = EPI_STORE;
+      if ((rs = gemm(g, st)) != RID_OK) return rs;
+      std::swap(lin, lout);
+    }
+  }
+  // dw_o = sum_b hd_L ; db_o = 0
+  hipLaunchKernelGGL(colsum_kernel, dim3(grid1d((long long)K * w[L])), dim3(256), 0, st,
+                     W + hh[L] + (long long)B * w[L], slab(L), B, w[L], K, G, pm,
+                     (int)wo_off);
+  RID_HIP(hipGetLastError());
+  // the output bias never reaches grad_s A: its gradient entry is zero
+  hipLaunchKernelGGL(set_zero_kernel, dim3(1), dim3(64), 0, st, G, pm,
+                     (int)(wo_off + w[L]), K);
+  RID_HIP(hipGetLastError());
+  return RID_OK;
+}
+
+rid_status launch_train_step(rid_ensemble_impl& e, const float* s, const float* F,
+                             int B, float lr, float* loss, hipStream_t st) {
+  float* G = nullptr;
+  rid_status rs = launch_mf_grad(e, s, F, nullptr, B, loss, nullptr, &G, st);
+  if (rs != RID_OK) return rs;
+  // ---- Adam ----
+  const int t = (int)(e.step + 1);
+  const float c1 = 1.f - std::pow(0.9f, (float)t);
+  const float c2 = 1.f - std::pow(0.999f, (float)t);
+  ProfScope ps(kProfTrain, st);
+  hipLaunchKernelGGL(adam_kernel, dim3(grid1d((long long)e.n_params)), dim3(256), 0, st,
+                     e.d_master, e.d_m, e.d_v, G, (long long)e.n_params, lr, c1, c2);
+  RID_HIP(hipGetLastError());
+  e.step += 1;
+  e.frag_dirty = true;
+  return RID_OK;
+}
+
+}  // namespace rid

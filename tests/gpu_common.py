@@ -1,0 +1,68 @@
+"""Shared helpers of the GPU parity tests: seeded workloads and tolerances.
+
+Errors are measured against the FP64 oracle on the same FP32-rounded inputs;
+"max" is the max over walkers of the normwise per-walker relative error
+(max |dF| / max |F| over the walker's atoms), "rms" is |dF|_2 / |F|_2 over
+the batch.
+
+FP32 path: max <= 1e-5.
+16-bit forms (tolerance derived from the arithmetic): every one of the 8
+GEMM stages of a 4-layer forward + reverse sweep rounds both MFMA operands
+to the 16-bit format, a relative perturbation of about sqrt(2) u per stage
+(u = 2^-9 for BF16, 2^-12 for FP16), independent across stages, so the
+mean force carries about sqrt(8 stages x 2 operands) u = 4u rms relative error:
+7.8e-3 for BF16 and 1e-3 for FP16.  The per-walker max over thousands of
+walkers runs to about 3x the rms.  Bounds: BF16 max 2.5e-2, rms 1e-2;
+FP16 max 1e-2, rms 2e-3."""
+from __future__ import annotations
+
+import numpy as np
+
+import ridgen
+from oracle import rid_oracle as O
+
+FP32_TOL = 1e-5
+HALF_TOL = {"bf16": (2.5e-2, 1e-2), "fp16": (1e-2, 2e-3)}   # (max, rms)
+
+
+def workload(kind: str, B: int, seed: int = 1, K=None, widths=None, bias_std=0.0,
+             wseed=1000):
+    """(system, pos f32 [B][N][3], params f32, widths, K) for a named shape."""
+    if kind == "dipeptide":
+        sys_ = ridgen.system_dipeptide()
+        K = K or 4
+        widths = widths or [100, 100, 100]
+    elif kind == "peptide20":
+        sys_ = ridgen.system_peptide20()
+        K = K or 4
+        widths = widths or [256] * 4
+    elif kind == "peptide61":
+        sys_ = ridgen.system_peptide61()
+        K = K or 4
+        widths = widths or [512] * 4
+    else:
+        raise ValueError(kind)
+    pos = ridgen.f32(ridgen.chain_coords(sys_, B, seed))
+    params = ridgen.xavier_ensemble(2 * sys_.n_cv, widths, K, wseed, bias_std)
+    return sys_, pos, params, list(widths), K
+
+
+def oracle_models(params, n_cv, widths, K):
+    return ridgen.unpack_params(params, 2 * n_cv, widths, K)
+
+
+def wrapped_diff(a, b):
+    d = np.asarray(a, np.float64) - np.asarray(b, np.float64)
+    return (d + np.pi) % (2 * np.pi) - np.pi
+
+
+def assert_forces(F_gpu, F_ref, tol, what="force"):
+    """tol: max bound, or (max bound, rms bound)."""
+    tmax, trms = (tol, None) if np.isscalar(tol) else tol
+    err = O.max_rel_err(F_gpu, F_ref)
+    rms = O.rms_rel_err(F_gpu, F_ref)
+    print(f"{what}: max_rel={err:.3e} rms_rel={rms:.3e} (tol {tol})", flush=True)
+    assert err <= tmax, f"{what} max rel err {err:.3e} > {tmax}"
+    if trms is not None:
+        assert rms <= trms, f"{what} rms rel err {rms:.3e} > {trms}"
+    return err, rms

@@ -1,0 +1,98 @@
+"""The C ABI library loads, exports every symbol include/rid.h declares, and
+rejects bad arguments on the host (no compute calls: no GPU here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2408_14070_amd as rid
+import ridgen
+from oracle import rid_oracle as O
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "rid.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rid_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = rid.lib()
+    names = _declared()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(rid.EXPORTS)
+
+
+def test_version_string():
+    assert b"gfx950" in rid.lib().rid_version()
+
+
+def test_packed_param_count_matches_layout():
+    w = np.array([256, 256, 256, 256], np.int32)
+    n = rid.lib().rid_packed_param_count(38, 4, 4, w.ctypes.data_as(ctypes.c_void_p))
+    assert n == ridgen.packed_size(76, [256] * 4, 4) == 4 * 217345
+    w2 = np.array([100, 100, 100], np.int32)
+    assert rid.lib().rid_packed_param_count(2, 4, 3, w2.ctypes.data_as(ctypes.c_void_p)) == \
+        ridgen.packed_size(4, [100] * 3, 4)
+
+
+def test_lr_schedule_matches_oracle():
+    for step in (0, 1, 119, 120, 1000, 16000):
+        assert abs(rid.lr_exponential(step) - O.lr_at(step)) <= 1e-18 + 1e-15 * O.lr_at(step)
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_system_create_rejects_bad_quads_on_host():
+    L = rid.lib()
+    h = ctypes.c_void_p()
+    q = np.array([[0, 1, 2, 30]], np.int32)    # index out of range
+    assert L.rid_system_create(22, 1, q.ctypes.data_as(ctypes.c_void_p), None,
+                               ctypes.byref(h)) == rid.RID_EINVAL
+    assert b"out of range" in L.rid_last_error()
+    q = np.array([[0, 1, 1, 3]], np.int32)     # repeated atom
+    assert L.rid_system_create(22, 1, q.ctypes.data_as(ctypes.c_void_p), None,
+                               ctypes.byref(h)) == rid.RID_EINVAL
+    q = np.array([[0, 1, 2, 3]], np.int32)
+    m = np.array([0], np.uint8)                # non-periodic CV on the torsion path
+    assert L.rid_system_create(22, 1, q.ctypes.data_as(ctypes.c_void_p),
+                               m.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) == rid.RID_EUNSUPPORTED
+    assert L.rid_system_create(0, 1, q.ctypes.data_as(ctypes.c_void_p), None,
+                               ctypes.byref(h)) == rid.RID_EINVAL
+
+
+def test_ensemble_create_rejects_unsupported_shapes_on_host():
+    L = rid.lib()
+    h = ctypes.c_void_p()
+    p = np.zeros(10, np.float32)
+    for widths, nh in (([600], 1), ([8] * 7, 7), ([0], 1)):
+        w = np.array(widths, np.int32)
+        st = L.rid_ensemble_create(2, 4, nh, w.ctypes.data_as(ctypes.c_void_p), 0,
+                                   p.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
+        assert st == rid.RID_EUNSUPPORTED
+    w = np.array([8], np.int32)
+    assert L.rid_ensemble_create(2, 4, 1, w.ctypes.data_as(ctypes.c_void_p), 7,
+                                 p.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) == rid.RID_EINVAL
+
+
+def test_compute_calls_reject_null_handles():
+    L = rid.lib()
+    assert L.rid_bias_force(None, None, None, 4, 2.0, 3.0, None, None, None, None, None, None) == rid.RID_EINVAL
+    assert L.rid_cv_eval(None, None, 4, None, None, None) == rid.RID_EINVAL
+    assert L.rid_model_dev(None, None, 4, None, None, None, None, None) == rid.RID_EINVAL
+    assert L.rid_mf_train_step(None, None, None, 4, 0.1, None, None) == rid.RID_EINVAL
+    assert L.rid_mf_label(None, None, None, None, 1, 10, 1, 1.0, None, None, None, None) == rid.RID_EINVAL
+    assert L.rid_cv_apply_force(None, None, None, 4, None, None) == rid.RID_EINVAL
+
+
+def test_python_binding_validates_shapes_before_calling():
+    with pytest.raises(ValueError):
+        rid.System(22, np.zeros((3, 3), np.int32))

@@ -1,0 +1,149 @@
+"""GPU parity of the mean-force fitting step (double backward + Adam) and of
+the autograd wrapper, against the FP64 oracle.
+
+Gradient tolerance: the weight gradient is a sum over 2B rows of products of
+FP32 activations that each carry ~1e-6 relative error after the forward,
+primal-backward, tangent and adjoint sweeps; 1e-4 normwise per member (max
+abs error over the member's gradient / its max magnitude) leaves a factor
+~10 over the error measured at the full batch."""
+import numpy as np
+import pytest
+
+import ridgen
+from oracle import rid_oracle as O
+
+pytestmark = pytest.mark.gpu
+GRAD_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def rid():
+    import paper_2408_14070_amd as r
+    r.lib()
+    return r
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _grad_ref(params, n, widths, K, s, F):
+    models = ridgen.unpack_params(params, 2 * n, widths, K)
+    losses, grads = [], []
+    for m in models:
+        loss, g = O.train_loss_grad(m, s.astype(np.float64), F.astype(np.float64))
+        losses.append(loss)
+        grads.append(O.flat_grad(g))
+    return np.array(losses), np.stack(grads)
+
+
+def _per_member_err(grad_gpu, grad_ref):
+    K = grad_ref.shape[0]
+    g = grad_gpu.reshape(K, -1).astype(np.float64)
+    return max(np.max(np.abs(g[k] - grad_ref[k])) / np.max(np.abs(grad_ref[k])) for k in range(K))
+
+
+@pytest.mark.parametrize("n,widths,K,B", [(3, [5, 4], 2, 4), (38, [256] * 4, 4, 4096),
+                                          (7, [100, 33, 70], 3, 257), (2, [100] * 3, 4, 1000)])
+def test_loss_grad_parity(torch, rid, n, widths, K, B):
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 1000, bias_std=0.1)
+    s, F, _ = ridgen.mf_training_set(B, n)
+    E = rid.Ensemble(n, widths, K, params)
+    loss, grad = rid.mf_loss_grad(E, _dev(torch, s), _dev(torch, F))
+    torch.cuda.synchronize()
+    loss_ref, grad_ref = _grad_ref(params, n, widths, K, s, F)
+    lerr = np.max(np.abs(loss.cpu().numpy() - loss_ref) / loss_ref)
+    gerr = _per_member_err(grad.cpu().numpy(), grad_ref)
+    print(f"n={n} widths={widths} K={K} B={B}: loss rel err {lerr:.2e}, grad err {gerr:.2e}")
+    assert lerr <= 1e-5
+    assert gerr <= GRAD_TOL
+    # output-bias entries are exactly zero
+    per = grad_ref.shape[1]
+    assert np.all(grad.cpu().numpy().reshape(K, per)[:, -1] == 0.0)
+
+
+def test_vjp_parity_and_autograd(torch, rid):
+    n, widths, K, B = 6, [64, 48], 3, 77
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 7, bias_std=0.1)
+    s = ridgen.f32(ridgen.torus_samples(B, n, 4))
+    rho = ridgen.f32(np.random.default_rng(5).normal(size=(B, K, n)))
+    E = rid.Ensemble(n, widths, K, params)
+    grad = rid.mf_grad(E, _dev(torch, s), _dev(torch, rho))
+    models = ridgen.unpack_params(params, 2 * n, widths, K)
+    ref = np.stack([O.flat_grad(O.mean_force_vjp(m, s.astype(np.float64), rho[:, k, :]))
+                    for k, m in enumerate(models)])
+    assert _per_member_err(grad.cpu().numpy(), ref) <= GRAD_TOL
+    # autograd wrapper: loss = sum(rho * g) -> params.grad equals the VJP
+    P = _dev(torch, params).requires_grad_(True)
+    g = rid.mean_force(_dev(torch, s), P, E)
+    (g * _dev(torch, rho)).sum().backward()
+    torch.cuda.synchronize()
+    assert torch.equal(P.grad, grad)
+    _, g_ref = O.ensemble_mean_force(models, s.astype(np.float64))
+    assert O.max_rel_err(g.detach().cpu().numpy(), g_ref) <= 1e-5
+
+
+def test_train_steps_follow_oracle(torch, rid):
+    n, widths, K, B = 38, [256] * 4, 4, 4096
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 1000)
+    s_all, F_all, _ = ridgen.mf_training_set(3 * B, n)
+    E = rid.Ensemble(n, widths, K, params)
+    models = ridgen.unpack_params(params, 2 * n, widths, K)
+    states = [(np.zeros(O.flat_model(m).size), np.zeros(O.flat_model(m).size), 0) for m in models]
+    for step in range(3):
+        sl = slice(step * B, (step + 1) * B)
+        lr = O.lr_at(step)
+        loss = rid.mf_train_step(E, _dev(torch, s_all[sl]), _dev(torch, F_all[sl]), lr)
+        models, states, loss_ref = O.train_step(models, s_all[sl], F_all[sl], states, lr)
+        torch.cuda.synchronize()
+        lerr = np.max(np.abs(loss.cpu().numpy() - loss_ref) / loss_ref)
+        print(f"step {step}: loss {loss.cpu().numpy()} rel err {lerr:.2e}")
+        assert lerr <= 1e-4
+    assert E.step == 3
+    got = E.get_params().astype(np.float64).reshape(K, -1)
+    ref = np.stack([O.flat_model(m) for m in models])
+    # Adam moves every weight by about lr per step; entries whose gradient is
+    # near zero may take the other sign, so compare against the step size.
+    step_scale = 3 * O.INIT_LR
+    d = np.abs(got - ref)
+    assert np.quantile(d, 0.99) <= 0.05 * step_scale
+    assert d.max() <= 2.5 * step_scale
+
+
+def test_trained_ensemble_is_used_by_the_bias_path(torch, rid):
+    sys_ = ridgen.system_dipeptide()
+    n, widths, K = sys_.n_cv, [32, 32], 2
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 3, bias_std=0.1)
+    E = rid.Ensemble(n, widths, K, params)
+    S = rid.System(sys_.n_atoms, sys_.quads)
+    s, F, _ = ridgen.mf_training_set(256, n)
+    for step in range(5):
+        rid.mf_train_step(E, _dev(torch, s), _dev(torch, F), 1e-2)
+    new = E.get_params()
+    assert not np.array_equal(new, params)
+    pos = ridgen.f32(ridgen.chain_coords(sys_, 16, 2))
+    out = rid.bias_force(S, E, _dev(torch, pos), 2.0, 3.0)
+    torch.cuda.synchronize()
+    ref = O.bias_force(pos.astype(np.float64), sys_.quads,
+                       ridgen.unpack_params(new, 2 * n, widths, K), 2.0, 3.0)
+    assert O.max_rel_err(out["F"].cpu().numpy(), ref["F"]) <= 1e-5
+
+
+def test_training_is_deterministic(torch, rid):
+    n, widths, K, B = 38, [256] * 4, 4, 2048
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 11)
+    s, F, _ = ridgen.mf_training_set(B, n)
+    S_, F_ = _dev(torch, s), _dev(torch, F)
+    out = []
+    for _ in range(2):
+        E = rid.Ensemble(n, widths, K, params)
+        for step in range(2):
+            rid.mf_train_step(E, S_, F_, 1e-3)
+        out.append(E.get_params())
+    assert np.array_equal(out[0], out[1])

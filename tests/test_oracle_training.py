@@ -39,6 +39,25 @@ def test_training_gradient_finite_differences():
     assert g[-1] == 0.0  # output bias never reaches grad_s A
 
 
+def test_mean_force_vjp_finite_differences():
+    n, widths = 4, [6, 5, 3]
+    model = _model(2 * n, widths, 9)
+    rng = np.random.default_rng(10)
+    s = rng.uniform(-3, 3, size=(5, n))
+    rho = rng.normal(size=(5, n))
+    g = O.flat_grad(O.mean_force_vjp(model, s, rho))
+    theta = O.flat_model(model)
+
+    def J(th):
+        _, gg = O.ensemble_mean_force([O.unflat_model(th, 2 * n, widths)], s)
+        return float(np.sum(rho * gg[:, 0, :]))
+
+    h = 1e-6
+    fd = np.array([(J(theta + h * e) - J(theta - h * e)) / (2 * h)
+                   for e in np.eye(theta.size)])
+    assert np.max(np.abs(fd - g)) < 1e-6 * np.max(np.abs(g))
+
+
 def _linear_problem(n=4, m=64):
     rng = np.random.default_rng(3)
     a = rng.uniform(0.5, 5.0, size=n)
