@@ -39,6 +39,17 @@ rid_status DevBuf::ensure(size_t need) {
   return RID_OK;
 }
 
+rid_status DevBuf::ensure_zeroed(size_t need) {
+  if (need <= bytes && ptr) return RID_OK;
+  rid_status st = ensure(need);
+  if (st != RID_OK) return st;
+  if (hipMemset(ptr, 0, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(RID_EDEVICE, "zeroing scratch memory failed");
+  }
+  return RID_OK;
+}
+
 void DevBuf::release() {
   if (ptr) (void)hipFree(ptr);
   ptr = nullptr;
@@ -133,6 +144,7 @@ static void free_ensemble(rid_ensemble_impl& e) {
   e.ws_A.release();
   e.ws_g.release();
   e.ws_train.release();
+  e.ws_cnt.release();
 }
 
 }  // namespace rid
@@ -374,15 +386,14 @@ rid_status rid_bias_force(rid_system sys, rid_ensemble ens, const float* d_pos,
   if (s.n_cv != e.n_cv) return fail(RID_EINVAL, "system and ensemble disagree on n_cv");
   const hipStream_t st = (hipStream_t)stream;
   rid_status r;
-  if ((r = e.ws_x.ensure(sizeof(float) * 2 * e.n_cv * (size_t)B)) != RID_OK) return r;
   if ((r = e.ws_A.ensure(sizeof(float) * e.K * (size_t)B)) != RID_OK) return r;
   if ((r = e.ws_g.ensure(sizeof(float) * e.K * (size_t)B * e.n_cv)) != RID_OK) return r;
-  if ((r = launch_cv_eval(s, d_pos, B, nullptr, e.ws_x.as<float>(), st)) != RID_OK) return r;
   if (e.frag_dirty) {
     if ((r = pack_ensemble_weights(e, st)) != RID_OK) return r;
     e.frag_dirty = false;
   }
-  if ((r = launch_mlp(e, e.ws_x.as<float>(), B, e.ws_A.as<float>(), e.ws_g.as<float>(), st)) != RID_OK)
+  const TorsionInput tin{&s, d_pos};
+  if ((r = launch_mlp_from_pos(e, tin, B, e.ws_A.as<float>(), e.ws_g.as<float>(), st)) != RID_OK)
     return r;
   return launch_bias_scatter(s, e.K, d_pos, B, e.ws_A.as<float>(), e.ws_g.as<float>(),
                              nullptr, eps0, eps1, d_force, d_energy, d_eps, d_sigma,

@@ -1,5 +1,5 @@
-// Ensemble MLP free-energy models: fused forward + input-gradient kernel and
-// the on-device weight packer.
+// Ensemble MLP free-energy models: the fused forward + input-gradient kernel
+// (fed straight from atom positions on the bias path) and the weight packer.
 //
 // Method ("Training phase"): each ensemble member is an MLP with tanh hidden
 // layers and a scalar output A(x); the bias needs the mean force
@@ -17,10 +17,18 @@
 //    nothing is written to HBM between layers.
 //  * Blocks are mapped XCD-aware: when K divides 8, member k runs on XCDs
 //    {k*8/K, ...}, so each XCD's L2 holds only its members' weights.
-#include "rid_internal.h"
+//  * On the bias path each workgroup computes the torsions of its walkers
+//    itself from the positions (the encoding never goes through HBM).  The
+//    FP64 deviation, switch and chain rule run in a second kernel: handing
+//    the members' results to one workgroup inside this launch needs
+//    device-scope fences, which on gfx950 write back and invalidate the
+//    whole per-XCD L2 and so evict the weights the other workgroups stream.
+#include "device_common.h"
 
 namespace rid {
 namespace {
+
+using namespace dev;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -74,7 +82,7 @@ __device__ inline float tanh_and_grad(float z, float& d) {
 }
 
 struct MlpArgs {
-  const float* x;      // [B][2n]
+  const float* x;      // [B][2n] input encoding (plain kernel)
   int B, n, K, L, XP, n_tiles, xcd_grp;
   const unsigned char* frag;
   unsigned long long frag_model_bytes;
@@ -85,6 +93,11 @@ struct MlpArgs {
   const float* bo;     // [K]
   float* A_out;        // [K][B]
   float* g_out;        // [K][B][n]
+  // LDS layout (byte offsets; the activation buffers start at 0)
+  unsigned off_u0, off_red, off_xs, off_ph0;
+  // torsion input (bias path)
+  SysView sv;
+  const float* pos;    // [B][n_atoms][3]
 };
 
 __device__ inline void map_block(int b, int K, int grp, int& k, int& tile) {
@@ -96,6 +109,11 @@ __device__ inline void map_block(int b, int K, int grp, int& k, int& tile) {
     k = b % K;
     tile = b / K;
   }
+}
+
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 // acc[rt][c] += act[rows of rt][0:KL] * frag(:, col tile jt0 + c)
@@ -126,8 +144,8 @@ __device__ inline void gemm_tiles(f4 (&acc)[RT][CT], const typename P::T* act,
   }
 }
 
-template <class P, int NP, int RT, int NW, int LM>
-__global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(MlpArgs p) {
+template <class P, int NP, int RT, int NW, int LM, bool FROM_POS>
+__global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   using T = typename P::T;
   constexpr int KF = P::KF;
   constexpr int CT = NP / (16 * NW);
@@ -141,25 +159,58 @@ __global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(MlpArgs p) {
   map_block(blockIdx.x, p.K, p.xcd_grp, k, tile);
   if (tile >= p.n_tiles) return;
   const int row0 = tile * R;
-  const int n = p.n, L = p.L, XP = p.XP;
+  const int n = p.n, L = p.L, XP = p.XP, X2 = 2 * p.n;
   const int AW = NP > XP ? NP : XP;           // activation tile width
   const int AS = AW + 16 / (int)sizeof(T);    // row stride (+16 bytes)
   const int BUF = R * AS;                     // elements per ping-pong buffer
   T* act = reinterpret_cast<T*>(smem);
-  float* u0 = reinterpret_cast<float*>(smem + (size_t)2 * BUF * sizeof(T));
+  float* u0 = reinterpret_cast<float*>(smem + p.off_u0);
   const int US = XP + 4;
-  float* red = u0 + R * US;                   // [NW][R]
+  float* red = reinterpret_cast<float*>(smem + p.off_red);   // [NW][R]
+  float* xs = reinterpret_cast<float*>(smem + p.off_xs);     // [R][2n] FP32 cos|sin
 
   const unsigned char* fbase = p.frag + (size_t)k * p.frag_model_bytes;
   const float* bias = p.bias + (size_t)k * L * NP;
   const float* wo = p.wo + (size_t)k * NP;
 
-  // x tile -> buffer 0 (rows past B and columns past 2n are zero)
-  for (int e = threadIdx.x; e < R * XP; e += NW * 64) {
-    int i = e / XP, c = e - i * XP;
-    int row = row0 + i;
-    float v = (row < p.B && c < 2 * n) ? p.x[(size_t)row * 2 * n + c] : 0.f;
-    act[i * AS + c] = P::from_float(v);
+  // ---------------- input tile: x = [cos s | sin s] -> buffer 0 ----------------
+  if constexpr (FROM_POS) {
+    // torsions of the tile's walkers: one gather pass over all R walkers
+    // (every load in flight at once), then one thread per (walker, torsion)
+    float* sp = reinterpret_cast<float*>(smem + p.off_ph0);   // [R][U][3]
+    const int U3 = 3 * p.sv.U;
+    for (int e = threadIdx.x; e < R * U3; e += NW * 64) {
+      const int i = e / U3, j = e - i * U3;
+      const int row = row0 + i;
+      const int u = j / 3;
+      sp[e] = row < p.B ? p.pos[((size_t)row * p.sv.n_atoms + p.sv.uniq[u]) * 3 + (j - 3 * u)]
+                        : 0.f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < R * n; e += NW * 64) {
+      const int i = e / n, c = e - i * n;
+      float cs = 0.f, sn = 0.f;
+      if (row0 + i < p.B) {
+        const Torsion t = torsion(sp + i * U3, p.sv.lq + 4 * c);
+        torsion_cos_sin(t, cs, sn);
+      }
+      xs[i * X2 + c] = cs;
+      xs[i * X2 + n + c] = sn;
+      act[i * AS + c] = P::from_float(cs);
+      act[i * AS + n + c] = P::from_float(sn);
+    }
+    for (int e = threadIdx.x; e < R * (XP - X2); e += NW * 64) {
+      const int i = e / (XP - X2), c = X2 + e - i * (XP - X2);
+      act[i * AS + c] = P::from_float(0.f);
+    }
+  } else {
+    for (int e = threadIdx.x; e < R * XP; e += NW * 64) {
+      const int i = e / XP, c = e - i * XP;
+      const int row = row0 + i;
+      const float v = (row < p.B && c < X2) ? p.x[(size_t)row * X2 + c] : 0.f;
+      act[i * AS + c] = P::from_float(v);
+      if (c < X2) xs[i * X2 + c] = v;
+    }
   }
   __syncthreads();
 
@@ -286,12 +337,13 @@ __global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(MlpArgs p) {
     const int i = e / n, c = e - i * n;
     const int row = row0 + i;
     if (row < p.B) {
-      const float cs = p.x[(size_t)row * 2 * n + c];
-      const float sn = p.x[(size_t)row * 2 * n + n + c];
+      const float cs = xs[i * X2 + c];
+      const float sn = xs[i * X2 + n + c];
       const float gv = -sn * u0[i * US + c] + cs * u0[i * US + n + c];
       p.g_out[((size_t)k * p.B + row) * n + c] = gv;
     }
   }
+
 }
 
 // ---------------------------------------------------------------------------
@@ -363,26 +415,42 @@ __global__ void pack_vec_kernel(const float* master, size_t per_model, int L,
   if (threadIdx.x == 0) bo[k] = m[va.wo_off + va.last_w];
 }
 
+inline unsigned align16(size_t v) { return (unsigned)((v + 15) / 16 * 16); }
+
 template <class P, int NP, int RT, int NW, int LM>
 rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
-                   float* A_out, float* g_out, hipStream_t st) {
-  static bool attr_done = false;
+                   float* A_out, float* g_out, const TorsionInput* tail,
+                   hipStream_t st) {
+  static size_t attr_bytes[2] = {0, 0};   // dynamic-LDS limit set per kernel
   constexpr int R = 16 * RT;
   using T = typename P::T;
+  const bool fused = tail != nullptr;
   const int AW = NP > e.XP ? NP : e.XP;
   const int AS = AW + 16 / (int)sizeof(T);
-  const size_t lds = (size_t)2 * R * AS * sizeof(T) + (size_t)R * (e.XP + 4) * 4 +
-                     (size_t)NW * R * 4;
-  if (lds > 160 * 1024)
-    return fail(RID_EUNSUPPORTED, "ensemble too wide for the fused kernel's LDS");
-  auto kern = mlp_fused_kernel<P, NP, RT, NW, LM>;
-  if (!attr_done && lds > 64 * 1024) {
-    RID_HIP(hipFuncSetAttribute((const void*)kern,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-    attr_done = true;
-  }
   MlpArgs a{};
+  // LDS layout
+  const size_t buf = (size_t)R * AS * sizeof(T);
+  a.off_u0 = align16(2 * buf);
+  a.off_red = align16(a.off_u0 + (size_t)R * (e.XP + 4) * 4);
+  a.off_xs = align16(a.off_red + (size_t)NW * R * 4);
+  size_t lds = a.off_xs + (size_t)R * 2 * e.n_cv * 4;
+  if (fused) {
+    const size_t ph0 = (size_t)R * 3 * tail->sys->n_uniq * 4;
+    if (ph0 <= a.off_xs - buf) {
+      a.off_ph0 = (unsigned)buf;           // inside buffer 1 / u0 / red
+    } else {
+      a.off_ph0 = align16(lds);
+      lds = a.off_ph0 + ph0;
+    }
+  }
+  if (lds > 160 * 1024)
+    return fail(RID_EUNSUPPORTED, "shape too large for the fused kernel's LDS");
+  auto kern = fused ? mlp_kernel<P, NP, RT, NW, LM, true> : mlp_kernel<P, NP, RT, NW, LM, false>;
+  if (lds > 64 * 1024 && lds > attr_bytes[fused]) {
+    RID_HIP(hipFuncSetAttribute((const void*)kern,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr_bytes[fused] = lds;
+  }
   a.x = x; a.B = B; a.n = e.n_cv; a.K = e.K; a.L = e.L; a.XP = e.XP;
   a.n_tiles = (B + R - 1) / R;
   a.xcd_grp = (8 % e.K == 0) ? 8 / e.K : 0;
@@ -393,6 +461,12 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
   }
   a.bias = e.d_bias; a.wo = e.d_wo; a.bo = e.d_bo;
   a.A_out = A_out; a.g_out = g_out;
+  if (fused) {
+    const rid_system_impl& s = *tail->sys;
+    a.sv = SysView{s.n_atoms, s.n_uniq, s.n_cv, s.d_uniq, s.d_lquads, s.d_csr_ptr,
+                   s.d_csr_ent, s.d_atom_local};
+    a.pos = tail->pos;
+  }
   int grid;
   if (a.xcd_grp > 0)
     grid = 8 * ((a.n_tiles + a.xcd_grp - 1) / a.xcd_grp);
@@ -406,23 +480,38 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
 
 template <class P>
 rid_status launch_16bit(const rid_ensemble_impl& e, const float* x, int B,
-                        float* A_out, float* g_out, hipStream_t st) {
+                        float* A_out, float* g_out, const TorsionInput* t, hipStream_t st) {
   if (e.L <= 4) {
     switch (e.NP) {
-      case 64:  return run_mlp<P, 64, 2, 4, 4>(e, x, B, A_out, g_out, st);
-      case 128: return run_mlp<P, 128, 2, 4, 4>(e, x, B, A_out, g_out, st);
-      case 256: return run_mlp<P, 256, 2, 4, 4>(e, x, B, A_out, g_out, st);
-      case 512: return run_mlp<P, 512, 2, 8, 4>(e, x, B, A_out, g_out, st);
+      case 64:  return run_mlp<P, 64, 2, 4, 4>(e, x, B, A_out, g_out, t, st);
+      case 128: return run_mlp<P, 128, 2, 4, 4>(e, x, B, A_out, g_out, t, st);
+      case 256: return run_mlp<P, 256, 2, 4, 4>(e, x, B, A_out, g_out, t, st);
+      case 512: return run_mlp<P, 512, 2, 8, 4>(e, x, B, A_out, g_out, t, st);
     }
   } else {
     switch (e.NP) {
-      case 64:  return run_mlp<P, 64, 1, 4, 6>(e, x, B, A_out, g_out, st);
-      case 128: return run_mlp<P, 128, 1, 4, 6>(e, x, B, A_out, g_out, st);
-      case 256: return run_mlp<P, 256, 1, 4, 6>(e, x, B, A_out, g_out, st);
-      case 512: return run_mlp<P, 512, 1, 8, 6>(e, x, B, A_out, g_out, st);
+      case 64:  return run_mlp<P, 64, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
+      case 128: return run_mlp<P, 128, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
+      case 256: return run_mlp<P, 256, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
+      case 512: return run_mlp<P, 512, 1, 8, 6>(e, x, B, A_out, g_out, t, st);
     }
   }
   return fail(RID_EUNSUPPORTED, "no kernel for this padded width");
+}
+
+rid_status dispatch(const rid_ensemble_impl& e, const float* x, int B, float* A_out,
+                    float* g_out, const TorsionInput* t, hipStream_t st) {
+  if (e.prec == RID_FP32) {
+    switch (e.NP) {
+      case 64:  return run_mlp<F32, 64, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
+      case 128: return run_mlp<F32, 128, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
+      case 256: return run_mlp<F32, 256, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
+      case 512: return run_mlp<F32, 512, 1, 8, 6>(e, x, B, A_out, g_out, t, st);
+    }
+    return fail(RID_EUNSUPPORTED, "no kernel for this padded width");
+  }
+  if (e.prec == RID_BF16) return launch_16bit<BF16>(e, x, B, A_out, g_out, t, st);
+  return launch_16bit<F16>(e, x, B, A_out, g_out, t, st);
 }
 
 }  // namespace
@@ -434,17 +523,17 @@ rid_status launch_16bit(const rid_ensemble_impl& e, const float* x, int B,
 // small, deeper networks take 16 walkers per workgroup.
 rid_status launch_mlp(const rid_ensemble_impl& e, const float* x, int B,
                       float* A_out, float* g_out, hipStream_t st) {
-  if (e.prec == RID_FP32) {
-    switch (e.NP) {
-      case 64:  return run_mlp<F32, 64, 1, 4, 6>(e, x, B, A_out, g_out, st);
-      case 128: return run_mlp<F32, 128, 1, 4, 6>(e, x, B, A_out, g_out, st);
-      case 256: return run_mlp<F32, 256, 1, 4, 6>(e, x, B, A_out, g_out, st);
-      case 512: return run_mlp<F32, 512, 1, 8, 6>(e, x, B, A_out, g_out, st);
-    }
-    return fail(RID_EUNSUPPORTED, "no kernel for this padded width");
-  }
-  if (e.prec == RID_BF16) return launch_16bit<BF16>(e, x, B, A_out, g_out, st);
-  return launch_16bit<F16>(e, x, B, A_out, g_out, st);
+  return dispatch(e, x, B, A_out, g_out, nullptr, st);
+}
+
+rid_status launch_mlp_from_pos(const rid_ensemble_impl& e, const TorsionInput& tail,
+                               int B, float* A_out, float* g_out, hipStream_t st) {
+  return dispatch(e, nullptr, B, A_out, g_out, &tail, st);
+}
+
+int mlp_rows_per_tile(const rid_ensemble_impl& e) {
+  if (e.prec == RID_FP32) return 16;
+  return e.L <= 4 ? 32 : 16;
 }
 
 rid_status pack_ensemble_weights(rid_ensemble_impl& e, hipStream_t st) {

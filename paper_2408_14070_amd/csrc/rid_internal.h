@@ -32,6 +32,7 @@ struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
   rid_status ensure(size_t need);
+  rid_status ensure_zeroed(size_t need);  // new memory is zero-filled
   void release();
   template <class T> T* as() const { return static_cast<T*>(ptr); }
 };
@@ -122,7 +123,7 @@ struct rid_ensemble_impl {
   float* d_bo = nullptr;             // [K]
   // scratch
   bool frag_dirty = false;           // masters changed since the last pack
-  DevBuf ws_x, ws_A, ws_g, ws_train;
+  DevBuf ws_x, ws_A, ws_g, ws_train, ws_cnt;
 };
 
 // ---------------------------------------------------------------------------
@@ -131,6 +132,14 @@ struct rid_ensemble_impl {
 rid_status launch_cv_eval(const rid_system_impl& s, const float* pos, int B,
                           float* d_s, float* d_x, hipStream_t st);
 rid_status launch_embed(const float* s, int B, int n, float* x, hipStream_t st);
+// Ensemble MLP fed straight from atom positions (torsions computed in-kernel).
+struct TorsionInput {
+  const rid_system_impl* sys;
+  const float* pos;
+};
+rid_status launch_mlp_from_pos(const rid_ensemble_impl& e, const TorsionInput& tin,
+                               int B, float* A_out, float* g_out, hipStream_t st);
+int mlp_rows_per_tile(const rid_ensemble_impl& e);
 rid_status launch_mlp(const rid_ensemble_impl& e, const float* x, int B,
                       float* A_out, float* g_out, hipStream_t st);
 rid_status launch_ensemble_reduce(int K, int n, int B, const float* A,
