@@ -232,6 +232,62 @@ rid_status rid_mf_label(const float* d_traj, const float* d_s0,
                         double* d_se, uint8_t* d_keep, rid_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Serving loop: continuous batching of bias-force requests from many
+ * walkers of different systems, ensembles and precisions on one GPU (the
+ * exploration phase runs many walkers at once, "Overall workflow setting":
+ * numb_walkers).  Ensemble weights and system tables stay resident on the
+ * device.  A scheduler thread takes the oldest waiting request plus every
+ * later waiting request of the same model (up to max_batch_walkers), admits
+ * the batch only when its device memory fits the HBM budget, and runs it on
+ * one of n_streams streams (copies in, bias kernels, copies out).  Requests
+ * that arrive while others run are admitted as slots and memory free up.
+ * A request's results do not depend on the batch it lands in (each walker
+ * is computed independently with a fixed reduction order).
+ *
+ * rid_server_create    hbm_budget_bytes is allocated at once and is the
+ *                      admission budget; flags: RID_SERVE_FIFO = serve one
+ *                      request at a time on one stream (baseline).
+ * rid_server_register  model = (system, ensemble, trust levels); the handles
+ *                      must outlive the server and must not be trained while
+ *                      registered.  Returns a model id.
+ * rid_server_submit    copies host_pos [n_walkers][n_atoms][3] into pinned
+ *                      staging (blocks while staging memory is full) and
+ *                      queues the request; RID_ENOMEM if it can never fit the
+ *                      budget.  Thread-safe.
+ * rid_server_wait      blocks until the request is done and copies its
+ *                      results to the host arrays (any may be NULL):
+ *                      force [n_walkers][n_atoms][3], energy/eps/sigma
+ *                      [n_walkers]; latency_us = arrival (submit) to results
+ *                      visible in host memory.  Each ticket is waited once.
+ * rid_server_stats     latency percentiles and throughput of the requests
+ *                      waited since creation or the last reset.
+ * rid_server_destroy   stops the threads after in-flight batches finish; call
+ *                      after every submitted request has been waited.
+ * ------------------------------------------------------------------------ */
+typedef struct rid_server_s* rid_server;
+#define RID_SERVE_FIFO 1
+typedef struct {
+  int64_t requests_done, walkers_done, batches, admission_waits;
+  int64_t max_inflight_batches;
+  double mean_batch_walkers;
+  double p50_us, p99_us, mean_us, max_us;
+  double walker_steps_per_s;   /* walkers done / (last done - first arrival) */
+} rid_server_stats_t;
+
+rid_status rid_server_create(size_t hbm_budget_bytes, int n_streams,
+                             int max_batch_walkers, int flags, rid_server* out);
+rid_status rid_server_register(rid_server srv, rid_system sys, rid_ensemble ens,
+                               float eps0, float eps1, int* model_id);
+rid_status rid_server_submit(rid_server srv, int model_id, const float* host_pos,
+                             int n_walkers, int64_t* ticket);
+rid_status rid_server_wait(rid_server srv, int64_t ticket, float* host_force,
+                           float* host_energy, float* host_eps, float* host_sigma,
+                           double* latency_us);
+rid_status rid_server_stats(rid_server srv, rid_server_stats_t* out);
+void rid_server_reset_stats(rid_server srv);
+void rid_server_destroy(rid_server srv);
+
+/* ------------------------------------------------------------------------
  * Kernel timing for benchmarks.  While enabled, every kernel the library
  * launches is bracketed by two hipEvents recorded on the launching stream
  * (no synchronisation at record time).  rid_profile_enable(1) clears and

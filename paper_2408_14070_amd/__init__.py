@@ -32,7 +32,19 @@ EXPORTS = (
     "rid_cv_eval", "rid_model_dev", "rid_bias_force", "rid_cv_apply_force",
     "rid_mf_train_step", "rid_lr_exponential", "rid_mf_label",
     "rid_profile_enable", "rid_profile_read", "rid_mf_loss_grad", "rid_mf_grad",
+    "rid_server_create", "rid_server_register", "rid_server_submit", "rid_server_wait",
+    "rid_server_stats", "rid_server_reset_stats", "rid_server_destroy",
 )
+RID_SERVE_FIFO = 1
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("requests_done", ctypes.c_int64), ("walkers_done", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("admission_waits", ctypes.c_int64),
+                ("max_inflight_batches", ctypes.c_int64),
+                ("mean_batch_walkers", ctypes.c_double), ("p50_us", ctypes.c_double),
+                ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double),
+                ("max_us", ctypes.c_double), ("walker_steps_per_s", ctypes.c_double)]
 PROF_CV, PROF_MLP, PROF_SCATTER, PROF_REDUCE, PROF_EMBED, PROF_TRAIN, PROF_LABEL = range(7)
 
 
@@ -79,6 +91,13 @@ def lib():
         "rid_profile_read": (i, [i, P(d), P(i64)]),
         "rid_mf_loss_grad": (i, [vp, vp, vp, i, vp, vp, vp]),
         "rid_mf_grad": (i, [vp, vp, vp, i, vp, vp]),
+        "rid_server_create": (i, [sz, i, i, i, P(vp)]),
+        "rid_server_register": (i, [vp, vp, vp, f, f, P(i)]),
+        "rid_server_submit": (i, [vp, i, vp, i, P(i64)]),
+        "rid_server_wait": (i, [vp, i64, vp, vp, vp, vp, P(d)]),
+        "rid_server_stats": (i, [vp, P(ServerStats)]),
+        "rid_server_reset_stats": (None, [vp]),
+        "rid_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -144,9 +163,9 @@ class System:
         self.n_cv = int(q.shape[0])
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().rid_system_destroy(self.handle)
-            self.handle = None
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.rid_system_destroy(self.handle)
+        self.handle = None
 
     __del__ = close
 
@@ -186,9 +205,9 @@ class Ensemble:
         return int(lib().rid_ensemble_step(self.handle))
 
     def close(self):
-        if getattr(self, "handle", None):
-            lib().rid_ensemble_destroy(self.handle)
-            self.handle = None
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.rid_ensemble_destroy(self.handle)
+        self.handle = None
 
     __del__ = close
 
@@ -324,6 +343,68 @@ def mean_force(s, params, ens: Ensemble):
     if _MEAN_FORCE is None:
         _MEAN_FORCE = _make_mean_force_fn()
     return _MEAN_FORCE.apply(s, params, ens)
+
+
+class Server:
+    """Continuous-batching bias-force server (rid_server_*).  Host arrays in,
+    host arrays out; submit() and wait() may be called from several threads
+    (the C calls release the GIL)."""
+
+    def __init__(self, hbm_budget_bytes: int, n_streams: int = 4,
+                 max_batch_walkers: int = 4096, fifo: bool = False):
+        h = ctypes.c_void_p()
+        _check(lib().rid_server_create(int(hbm_budget_bytes), int(n_streams),
+                                       int(max_batch_walkers),
+                                       RID_SERVE_FIFO if fifo else 0, ctypes.byref(h)))
+        self.handle = h
+        self._models = []        # keep registered handles alive
+        self._tickets = {}
+
+    def register(self, system: System, ensemble: Ensemble, eps0: float, eps1: float) -> int:
+        mid = ctypes.c_int()
+        _check(lib().rid_server_register(self.handle, system.handle, ensemble.handle,
+                                         float(eps0), float(eps1), ctypes.byref(mid)))
+        self._models.append((system, ensemble))
+        return mid.value
+
+    def submit(self, model_id: int, pos) -> int:
+        p = np.ascontiguousarray(np.asarray(pos, dtype=np.float32))
+        system = self._models[model_id][0]
+        if p.ndim != 3 or p.shape[1:] != (system.n_atoms, 3):
+            raise ValueError("pos must be [n_walkers][n_atoms][3]")
+        t = ctypes.c_int64()
+        _check(lib().rid_server_submit(self.handle, int(model_id),
+                                       p.ctypes.data_as(ctypes.c_void_p), int(p.shape[0]),
+                                       ctypes.byref(t)))
+        self._tickets[t.value] = (p.shape[0], system.n_atoms)
+        return t.value
+
+    def wait(self, ticket: int):
+        w, N = self._tickets.pop(ticket)
+        F = np.empty((w, N, 3), np.float32)
+        E = np.empty(w, np.float32)
+        eps = np.empty(w, np.float32)
+        sig = np.empty(w, np.float32)
+        lat = ctypes.c_double()
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        _check(lib().rid_server_wait(self.handle, ctypes.c_int64(ticket), vp(F), vp(E),
+                                     vp(eps), vp(sig), ctypes.byref(lat)))
+        return dict(F=F, E=E, eps=eps, sigma=sig, latency_us=lat.value)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().rid_server_stats(self.handle, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        lib().rid_server_reset_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.rid_server_destroy(self.handle)
+        self.handle = None
+
+    __del__ = close
 
 
 def profile_enable(on: bool = True):

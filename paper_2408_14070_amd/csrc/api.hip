@@ -9,13 +9,6 @@
 
 #include "rid_internal.h"
 
-struct rid_system_s {
-  rid::rid_system_impl impl;
-};
-struct rid_ensemble_s {
-  rid::rid_ensemble_impl impl;
-};
-
 namespace rid {
 
 static thread_local std::string g_err;
@@ -36,17 +29,6 @@ rid_status DevBuf::ensure(size_t need) {
     return fail(RID_ENOMEM, "device allocation of scratch memory failed");
   }
   bytes = need;
-  return RID_OK;
-}
-
-rid_status DevBuf::ensure_zeroed(size_t need) {
-  if (need <= bytes && ptr) return RID_OK;
-  rid_status st = ensure(need);
-  if (st != RID_OK) return st;
-  if (hipMemset(ptr, 0, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(RID_EDEVICE, "zeroing scratch memory failed");
-  }
   return RID_OK;
 }
 
@@ -144,7 +126,6 @@ static void free_ensemble(rid_ensemble_impl& e) {
   e.ws_A.release();
   e.ws_g.release();
   e.ws_train.release();
-  e.ws_cnt.release();
 }
 
 }  // namespace rid
@@ -393,8 +374,14 @@ rid_status rid_bias_force(rid_system sys, rid_ensemble ens, const float* d_pos,
     e.frag_dirty = false;
   }
   const TorsionInput tin{&s, d_pos};
-  if ((r = launch_mlp_from_pos(e, tin, B, e.ws_A.as<float>(), e.ws_g.as<float>(), st)) != RID_OK)
-    return r;
+  r = launch_mlp_from_pos(e, tin, B, e.ws_A.as<float>(), e.ws_g.as<float>(), st);
+  if (r == RID_EUNSUPPORTED) {
+    // too many torsion atoms for the in-kernel gather: encode in HBM first
+    if ((r = e.ws_x.ensure(sizeof(float) * 2 * e.n_cv * (size_t)B)) != RID_OK) return r;
+    if ((r = launch_cv_eval(s, d_pos, B, nullptr, e.ws_x.as<float>(), st)) != RID_OK) return r;
+    r = launch_mlp(e, e.ws_x.as<float>(), B, e.ws_A.as<float>(), e.ws_g.as<float>(), st);
+  }
+  if (r != RID_OK) return r;
   return launch_bias_scatter(s, e.K, d_pos, B, e.ws_A.as<float>(), e.ws_g.as<float>(),
                              nullptr, eps0, eps1, d_force, d_energy, d_eps, d_sigma,
                              d_flags, st);

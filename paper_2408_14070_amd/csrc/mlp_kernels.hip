@@ -8,13 +8,18 @@
 //
 // Kernel design (gfx950):
 //  * One workgroup owns R = 16*RT walkers of ONE member.  Its waves split the
-//    hidden columns; each wave streams its columns' weight fragments straight
+//    hidden units; each wave streams its units' weight fragments straight
 //    from L2 into VGPRs (no weight reuse inside a workgroup, so no LDS hop).
-//  * The activation tile (the MFMA A operand, shared by all waves) lives in
-//    LDS, ping-ponged between two buffers so each layer needs one barrier;
-//    it holds x, then h_1 .. h_L, then the reverse-sweep vectors v_l.
-//  * tanh'(z_l) = 1 - h_l^2 is kept in FP32 VGPRs for the reverse sweep:
-//    nothing is written to HBM between layers.
+//    The weights are the MFMA A operand and the activations the B operand, so
+//    each lane ends up holding 4 consecutive units of one walker: one packed
+//    LDS store per 4 outputs, and the bias enters as the accumulator's
+//    initial value.
+//  * The activation tile (shared by all waves) lives in LDS, ping-ponged
+//    between two buffers so each layer needs one barrier; it holds x, then
+//    h_1 .. h_L, then the reverse-sweep vectors v_l.
+//  * tanh'(z_l) = 1 - h_l^2 is kept in VGPRs for the reverse sweep (FP32 for
+//    the FP32 path; the operand format for the 16-bit paths, whose 64-walker
+//    tiles would not fit an FP32 copy): nothing goes to HBM between layers.
 //  * Blocks are mapped XCD-aware: when K divides 8, member k runs on XCDs
 //    {k*8/K, ...}, so each XCD's L2 holds only its members' weights.
 //  * On the bias path each workgroup computes the torsions of its walkers
@@ -37,6 +42,7 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 struct F32 {
   using T = float;
   static constexpr int KF = 16;
+  // a: 16 rows x 16 contraction, b: 16 contraction x 16 columns (4 steps)
   __device__ static inline void mma(const uint4& a, const uint4& b, f4& c) {
     f4 av = __builtin_bit_cast(f4, a);
     f4 bv = __builtin_bit_cast(f4, b);
@@ -70,6 +76,36 @@ struct F16 {
   __device__ static inline T from_float(float v) { return (_Float16)v; }
 };
 
+// Four consecutive elements of type T as one register group.
+template <class T> struct Pack4;
+template <> struct Pack4<float> {
+  f4 v;
+  __device__ inline void set(const f4& x) { v = x; }
+  __device__ inline f4 get() const { return v; }
+  __device__ inline void store(float* dst) const { *reinterpret_cast<f4*>(dst) = v; }
+};
+template <class H> struct Pack16 {
+  uint2 v;
+  __device__ inline void set(const f4& x) {
+    const H a = (H)x[0], b = (H)x[1], c = (H)x[2], d = (H)x[3];
+    v.x = (uint32_t)__builtin_bit_cast(unsigned short, a) |
+          ((uint32_t)__builtin_bit_cast(unsigned short, b) << 16);
+    v.y = (uint32_t)__builtin_bit_cast(unsigned short, c) |
+          ((uint32_t)__builtin_bit_cast(unsigned short, d) << 16);
+  }
+  __device__ inline f4 get() const {
+    f4 r;
+    r[0] = (float)__builtin_bit_cast(H, (unsigned short)(v.x & 0xffffu));
+    r[1] = (float)__builtin_bit_cast(H, (unsigned short)(v.x >> 16));
+    r[2] = (float)__builtin_bit_cast(H, (unsigned short)(v.y & 0xffffu));
+    r[3] = (float)__builtin_bit_cast(H, (unsigned short)(v.y >> 16));
+    return r;
+  }
+  __device__ inline void store(H* dst) const { *reinterpret_cast<uint2*>(dst) = v; }
+};
+template <> struct Pack4<__bf16> : Pack16<__bf16> {};
+template <> struct Pack4<_Float16> : Pack16<_Float16> {};
+
 // tanh and its derivative from one exponential and one reciprocal:
 // with r = 1 / (1 + exp(2z)):  tanh z = 1 - 2r,  1 - tanh^2 z = 4 r (1 - r).
 // Saturates cleanly (exp -> inf gives r = 0; exp -> 0 gives r = 1).  Absolute
@@ -93,8 +129,9 @@ struct MlpArgs {
   const float* bo;     // [K]
   float* A_out;        // [K][B]
   float* g_out;        // [K][B][n]
-  // LDS layout (byte offsets; the activation buffers start at 0)
+  // LDS layout (byte offsets; activation buffer 0 starts at 0)
   unsigned off_u0, off_red, off_xs, off_ph0;
+  int rc;              // walkers per torsion-gather pass (bias path)
   // torsion input (bias path)
   SysView sv;
   const float* pos;    // [B][n_atoms][3]
@@ -111,42 +148,57 @@ __device__ inline void map_block(int b, int K, int grp, int& k, int& tile) {
   }
 }
 
-__device__ inline void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// acc[rt][c] += act[rows of rt][0:KL] * frag(:, col tile jt0 + c)
+// acc[rt][c] += W(units of tile jt0 + c, 0:KL) * act(walkers of rt, 0:KL)^T
+// (output tile: 16 units x 16 walkers; lane holds units 4(lane/16)+q of
+// walker lane%16)
+// Weight fragments are prefetched PD k-steps ahead through a ring of PD+1
+// register slots (the k loop is unrolled by PD+1 so slot indices are static).
+#ifndef RID_PD_FP32
+#define RID_PD_FP32 1
+#endif
+#ifndef RID_PD_16
+#define RID_PD_16 1
+#endif
 template <class P, int RT, int CT>
 __device__ inline void gemm_tiles(f4 (&acc)[RT][CT], const typename P::T* act,
                                   int as, const uint4* frag, int JT, int jt0,
                                   int n_kt, int lane) {
   constexpr int KF = P::KF;
+  constexpr int PD = sizeof(typename P::T) == 4 ? RID_PD_FP32 : RID_PD_16;
+  constexpr int S = PD + 1;
   const int r = lane & 15, g = lane >> 4;
-  uint4 bc[CT];
+  uint4 w[S][CT];
 #pragma unroll
-  for (int c = 0; c < CT; ++c) bc[c] = frag[(size_t)(jt0 + c) * 64 + lane];
-  for (int kt = 0; kt < n_kt; ++kt) {
-    uint4 bn[CT];
-    const int ktn = kt + 1 < n_kt ? kt + 1 : kt;
+  for (int s = 0; s < PD; ++s)
+    if (s < n_kt)
 #pragma unroll
-    for (int c = 0; c < CT; ++c)
-      bn[c] = frag[((size_t)ktn * JT + jt0 + c) * 64 + lane];
+      for (int c = 0; c < CT; ++c) w[s][c] = frag[((size_t)s * JT + jt0 + c) * 64 + lane];
+  for (int kb = 0; kb < n_kt; kb += S) {
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      const uint4 a = *reinterpret_cast<const uint4*>(
-          act + (rt * 16 + r) * as + kt * KF + g * (KF / 4));
+    for (int s = 0; s < S; ++s) {
+      const int kt = kb + s;
+      if (kt < n_kt) {
+        const int kp = kt + PD;
+        if (kp < n_kt)
 #pragma unroll
-      for (int c = 0; c < CT; ++c) P::mma(a, bc[c], acc[rt][c]);
+          for (int c = 0; c < CT; ++c)
+            w[(s + PD) % S][c] = frag[((size_t)kp * JT + jt0 + c) * 64 + lane];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          const uint4 a = *reinterpret_cast<const uint4*>(
+              act + (rt * 16 + r) * as + kt * KF + g * (KF / 4));
+#pragma unroll
+          for (int c = 0; c < CT; ++c) P::mma(w[s][c], a, acc[rt][c]);
+        }
+      }
     }
-#pragma unroll
-    for (int c = 0; c < CT; ++c) bc[c] = bn[c];
   }
 }
 
 template <class P, int NP, int RT, int NW, int LM, bool FROM_POS>
 __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   using T = typename P::T;
+  using SP = Pack4<T>;
   constexpr int KF = P::KF;
   constexpr int CT = NP / (16 * NW);
   constexpr int R = 16 * RT;
@@ -175,29 +227,35 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
 
   // ---------------- input tile: x = [cos s | sin s] -> buffer 0 ----------------
   if constexpr (FROM_POS) {
-    // torsions of the tile's walkers: one gather pass over all R walkers
-    // (every load in flight at once), then one thread per (walker, torsion)
-    float* sp = reinterpret_cast<float*>(smem + p.off_ph0);   // [R][U][3]
+    // torsions of the tile's walkers, p.rc walkers per pass (the gather
+    // scratch lives in buffer 1): one gather pass with every load in
+    // flight, then one thread per (walker, torsion)
+    float* sp = reinterpret_cast<float*>(smem + p.off_ph0);   // [rc][U][3]
     const int U3 = 3 * p.sv.U;
-    for (int e = threadIdx.x; e < R * U3; e += NW * 64) {
-      const int i = e / U3, j = e - i * U3;
-      const int row = row0 + i;
-      const int u = j / 3;
-      sp[e] = row < p.B ? p.pos[((size_t)row * p.sv.n_atoms + p.sv.uniq[u]) * 3 + (j - 3 * u)]
-                        : 0.f;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < R * n; e += NW * 64) {
-      const int i = e / n, c = e - i * n;
-      float cs = 0.f, sn = 0.f;
-      if (row0 + i < p.B) {
-        const Torsion t = torsion(sp + i * U3, p.sv.lq + 4 * c);
-        torsion_cos_sin(t, cs, sn);
+    for (int c0 = 0; c0 < R; c0 += p.rc) {
+      const int rc = R - c0 < p.rc ? R - c0 : p.rc;
+      for (int e = threadIdx.x; e < rc * U3; e += NW * 64) {
+        const int i = e / U3, j = e - i * U3;
+        const int row = row0 + c0 + i;
+        const int u = j / 3;
+        sp[e] = row < p.B
+                    ? p.pos[((size_t)row * p.sv.n_atoms + p.sv.uniq[u]) * 3 + (j - 3 * u)]
+                    : 0.f;
       }
-      xs[i * X2 + c] = cs;
-      xs[i * X2 + n + c] = sn;
-      act[i * AS + c] = P::from_float(cs);
-      act[i * AS + n + c] = P::from_float(sn);
+      __syncthreads();
+      for (int e = threadIdx.x; e < rc * n; e += NW * 64) {
+        const int il = e / n, c = e - il * n, i = c0 + il;
+        float cs = 0.f, sn = 0.f;
+        if (row0 + i < p.B) {
+          const Torsion t = torsion(sp + il * U3, p.sv.lq + 4 * c);
+          torsion_cos_sin(t, cs, sn);
+        }
+        xs[i * X2 + c] = cs;
+        xs[i * X2 + n + c] = sn;
+        act[i * AS + c] = P::from_float(cs);
+        act[i * AS + n + c] = P::from_float(sn);
+      }
+      __syncthreads();
     }
     for (int e = threadIdx.x; e < R * (XP - X2); e += NW * 64) {
       const int i = e / (XP - X2), c = X2 + e - i * (XP - X2);
@@ -215,8 +273,9 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   __syncthreads();
 
   const int jt0 = wave * CT;
-  const int colL = lane & 15, rq = 4 * (lane >> 4);
-  f4 st[LM][RT][CT];      // tanh' of every hidden layer, this wave's tiles
+  const int wl = lane & 15;          // walker within a 16-walker tile
+  const int uq = 4 * (lane >> 4);    // first of this lane's 4 units in a tile
+  SP st[LM][RT][CT];                 // tanh' of every hidden layer
   f4 acc[RT][CT];
   int cur = 0;
 
@@ -227,54 +286,51 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       const T* in = act + cur * BUF;
       T* out = act + (cur ^ 1) * BUF;
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
+      for (int c = 0; c < CT; ++c) {
+        const f4 b4 = *reinterpret_cast<const f4*>(bias + l * NP + (jt0 + c) * 16 + uq);
 #pragma unroll
-        for (int c = 0; c < CT; ++c) acc[rt][c] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int rt = 0; rt < RT; ++rt) acc[rt][c] = b4;
+      }
       const uint4* fr = reinterpret_cast<const uint4*>(fbase + p.fwd_off[l]);
       gemm_tiles<P, RT, CT>(acc, in, AS, fr, JT, jt0, (l == 0 ? XP : NP) / KF, lane);
       const bool last = (l == L - 1);
-      float apart[RT][4];
+      float apart[RT];
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) apart[rt][q] = 0.f;
+      for (int rt = 0; rt < RT; ++rt) apart[rt] = 0.f;
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
-        const int col = (jt0 + c) * 16 + colL;
-        const float b = bias[l * NP + col];
-        const float w = last ? wo[col] : 0.f;
+        const int u = (jt0 + c) * 16 + uq;
+        f4 w4 = f4{0.f, 0.f, 0.f, 0.f};
+        if (last) w4 = *reinterpret_cast<const f4*>(wo + u);
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-          f4 d;
+          f4 h, d;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             float dq;
-            const float h = tanh_and_grad(acc[rt][c][q] + b, dq);
+            h[q] = tanh_and_grad(acc[rt][c][q], dq);
             d[q] = dq;
-            const int i = rt * 16 + rq + q;
-            if (last) {
-              apart[rt][q] += w * h;
-              out[i * AS + col] = P::from_float(w * dq);   // v_L
-            } else {
-              out[i * AS + col] = P::from_float(h);
-            }
           }
-          st[l][rt][c] = d;
+          SP o;
+          if (last) {
+            apart[rt] += w4[0] * h[0] + w4[1] * h[1] + w4[2] * h[2] + w4[3] * h[3];
+            o.set(w4 * d);                                  // v_L
+          } else {
+            o.set(h);
+          }
+          o.store(out + (rt * 16 + wl) * AS + u);
+          st[l][rt][c].set(d);
         }
       }
       if (last) {
-        // A = wo . h_L + bo: reduce over the 16 column lanes, then waves
+        // A = wo . h_L + bo: reduce over the 4 unit groups, then the waves
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            float v = apart[rt][q];
-            v += __shfl_xor(v, 1);
-            v += __shfl_xor(v, 2);
-            v += __shfl_xor(v, 4);
-            v += __shfl_xor(v, 8);
-            if (colL == 0) red[wave * R + rt * 16 + rq + q] = v;
-          }
+        for (int rt = 0; rt < RT; ++rt) {
+          float v = apart[rt];
+          v += __shfl_xor(v, 16);
+          v += __shfl_xor(v, 32);
+          if (lane < 16) red[wave * R + rt * 16 + wl] = v;
+        }
       }
       cur ^= 1;
       __syncthreads();
@@ -301,20 +357,20 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       gemm_tiles<P, RT, CT>(acc, in, AS, fr, JT, jt0, NP / KF, lane);
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
-        const int col = (jt0 + c) * 16 + colL;
+        const int u = (jt0 + c) * 16 + uq;
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-          const f4 d = st[l - 1][rt][c];
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            out[(rt * 16 + rq + q) * AS + col] = P::from_float(acc[rt][c][q] * d[q]);
+          SP o;
+          o.set(acc[rt][c] * st[l - 1][rt][c].get());
+          o.store(out + (rt * 16 + wl) * AS + u);
         }
       }
       cur ^= 1;
       __syncthreads();
     }
   }
-  // layer 1 backward: u0 = W_1^T v_1, XP columns spread over the waves
+  // layer 1 backward: u0 = W_1^T v_1, XP columns spread over the waves.
+  // v_1 sits in buffer 1 (2L-1 buffer flips), so u0 may alias buffer 0.
   {
     const T* in = act + cur * BUF;
     const uint4* fr = reinterpret_cast<const uint4*>(fbase + p.bwd_off[0]);
@@ -326,9 +382,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       gemm_tiles<P, RT, 1>(a1, in, AS, fr, JT0, t, NP / KF, lane);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          u0[(rt * 16 + rq + q) * US + t * 16 + colL] = a1[rt][0][q];
+        *reinterpret_cast<f4*>(u0 + (rt * 16 + wl) * US + t * 16 + uq) = a1[rt][0];
     }
   }
   __syncthreads();
@@ -343,7 +397,6 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       p.g_out[((size_t)k * p.B + row) * n + c] = gv;
     }
   }
-
 }
 
 // ---------------------------------------------------------------------------
@@ -363,8 +416,8 @@ __global__ void pack_layer_kernel(const float* master, size_t per_model, int K,
   using T = typename P::T;
   constexpr int KF = P::KF;
   constexpr int E = 16 / sizeof(T);
-  // dir 0: contraction = input (kin_pad), columns = NP (outputs)
-  // dir 1: contraction = NP (outputs), columns = kin_pad (inputs)
+  // dir 0: contraction = input (kin_pad), rows = NP (outputs)
+  // dir 1: contraction = NP (outputs), rows = kin_pad (inputs)
   const int kc = dir == 0 ? pl.kin_pad : NP;
   const int nc = dir == 0 ? NP : pl.kin_pad;
   const int JT = nc / 16, KT = kc / KF;
@@ -382,7 +435,8 @@ __global__ void pack_layer_kernel(const float* master, size_t per_model, int K,
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int kk = kt * KF + (KF / 4) * (lane >> 4) + e;
-      // W is [out][in]; forward: B[kk=in][col=out]; backward: B[kk=out][col=in]
+      // W is [out][in]; forward: (unit col = out, contraction kk = in);
+      // backward: (unit col = in, contraction kk = out)
       const int o = dir == 0 ? col : kk;
       const int i = dir == 0 ? kk : col;
       const float v = (o < pl.out && i < pl.in) ? W[(size_t)o * pl.in + i] : 0.f;
@@ -417,39 +471,65 @@ __global__ void pack_vec_kernel(const float* master, size_t per_model, int L,
 
 inline unsigned align16(size_t v) { return (unsigned)((v + 15) / 16 * 16); }
 
+// LDS layout of one instantiation; returns the total bytes.
+size_t mlp_layout(int R, int NW, int AS, size_t tsize, int XP, int n, int U,
+                  bool from_pos, MlpArgs& a) {
+  const size_t buf = (size_t)R * AS * tsize;
+  size_t off = 2 * buf;
+  const size_t u0_bytes = (size_t)R * (XP + 4) * 4;
+  if (u0_bytes <= buf) {
+    a.off_u0 = 0;                       // buffer 0 is free in the last GEMM
+  } else {
+    a.off_u0 = align16(off);
+    off = a.off_u0 + u0_bytes;
+  }
+  a.off_red = align16(off);
+  off = a.off_red + (size_t)NW * R * 4;
+  a.off_xs = align16(off);
+  off = a.off_xs + (size_t)R * 2 * n * 4;
+  if (from_pos) {
+    // gather scratch in buffer 1 (free before layer 1), in passes of rc
+    // walkers; a shape with no room for one walker reports 0 passes
+    a.off_ph0 = (unsigned)buf;
+    const size_t per_walker = (size_t)3 * U * 4;
+    a.rc = (int)std::min<size_t>((size_t)R, buf / per_walker);
+  }
+  return off;
+}
+
+template <class P, int NP, int RT, int NW, int LM>
+size_t lds_bytes(const rid_ensemble_impl& e, const TorsionInput* tin) {
+  using T = typename P::T;
+  MlpArgs a{};
+  const int AW = NP > e.XP ? NP : e.XP;
+  const int AS = AW + 16 / (int)sizeof(T);
+  return mlp_layout(16 * RT, NW, AS, sizeof(T), e.XP, e.n_cv,
+                    tin ? tin->sys->n_uniq : 0, tin != nullptr, a);
+}
+
 template <class P, int NP, int RT, int NW, int LM>
 rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
-                   float* A_out, float* g_out, const TorsionInput* tail,
+                   float* A_out, float* g_out, const TorsionInput* tin,
                    hipStream_t st) {
   static size_t attr_bytes[2] = {0, 0};   // dynamic-LDS limit set per kernel
   constexpr int R = 16 * RT;
   using T = typename P::T;
-  const bool fused = tail != nullptr;
+  const bool from_pos = tin != nullptr;
   const int AW = NP > e.XP ? NP : e.XP;
   const int AS = AW + 16 / (int)sizeof(T);
   MlpArgs a{};
-  // LDS layout
-  const size_t buf = (size_t)R * AS * sizeof(T);
-  a.off_u0 = align16(2 * buf);
-  a.off_red = align16(a.off_u0 + (size_t)R * (e.XP + 4) * 4);
-  a.off_xs = align16(a.off_red + (size_t)NW * R * 4);
-  size_t lds = a.off_xs + (size_t)R * 2 * e.n_cv * 4;
-  if (fused) {
-    const size_t ph0 = (size_t)R * 3 * tail->sys->n_uniq * 4;
-    if (ph0 <= a.off_xs - buf) {
-      a.off_ph0 = (unsigned)buf;           // inside buffer 1 / u0 / red
-    } else {
-      a.off_ph0 = align16(lds);
-      lds = a.off_ph0 + ph0;
-    }
-  }
+  const size_t lds = mlp_layout(R, NW, AS, sizeof(T), e.XP, e.n_cv,
+                                from_pos ? tin->sys->n_uniq : 0, from_pos, a);
   if (lds > 160 * 1024)
-    return fail(RID_EUNSUPPORTED, "shape too large for the fused kernel's LDS");
-  auto kern = fused ? mlp_kernel<P, NP, RT, NW, LM, true> : mlp_kernel<P, NP, RT, NW, LM, false>;
-  if (lds > 64 * 1024 && lds > attr_bytes[fused]) {
+    return fail(RID_EUNSUPPORTED, "shape too large for the MLP kernel's LDS");
+  if (from_pos && a.rc < 1)
+    return fail(RID_EUNSUPPORTED, "too many torsion atoms to gather in-kernel");
+  auto kern = from_pos ? mlp_kernel<P, NP, RT, NW, LM, true>
+                       : mlp_kernel<P, NP, RT, NW, LM, false>;
+  if (lds > 64 * 1024 && lds > attr_bytes[from_pos]) {
     RID_HIP(hipFuncSetAttribute((const void*)kern,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr_bytes[fused] = lds;
+    attr_bytes[from_pos] = lds;
   }
   a.x = x; a.B = B; a.n = e.n_cv; a.K = e.K; a.L = e.L; a.XP = e.XP;
   a.n_tiles = (B + R - 1) / R;
@@ -461,11 +541,11 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
   }
   a.bias = e.d_bias; a.wo = e.d_wo; a.bo = e.d_bo;
   a.A_out = A_out; a.g_out = g_out;
-  if (fused) {
-    const rid_system_impl& s = *tail->sys;
+  if (from_pos) {
+    const rid_system_impl& s = *tin->sys;
     a.sv = SysView{s.n_atoms, s.n_uniq, s.n_cv, s.d_uniq, s.d_lquads, s.d_csr_ptr,
                    s.d_csr_ent, s.d_atom_local};
-    a.pos = tail->pos;
+    a.pos = tin->pos;
   }
   int grid;
   if (a.xcd_grp > 0)
@@ -478,23 +558,27 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
   return RID_OK;
 }
 
+// 16-bit family: 64 walkers per workgroup when the tile fits LDS, else 32;
+// deeper networks (5-6 hidden layers) take 32.
+template <class P, int NP, int NW>
+rid_status run_16bit(const rid_ensemble_impl& e, const float* x, int B, float* A_out,
+                     float* g_out, const TorsionInput* t, hipStream_t st) {
+  if (e.L <= 4) {
+    if (lds_bytes<P, NP, 4, NW, 4>(e, t) <= 160 * 1024)
+      return run_mlp<P, NP, 4, NW, 4>(e, x, B, A_out, g_out, t, st);
+    return run_mlp<P, NP, 2, NW, 4>(e, x, B, A_out, g_out, t, st);
+  }
+  return run_mlp<P, NP, 2, NW, 6>(e, x, B, A_out, g_out, t, st);
+}
+
 template <class P>
 rid_status launch_16bit(const rid_ensemble_impl& e, const float* x, int B,
                         float* A_out, float* g_out, const TorsionInput* t, hipStream_t st) {
-  if (e.L <= 4) {
-    switch (e.NP) {
-      case 64:  return run_mlp<P, 64, 2, 4, 4>(e, x, B, A_out, g_out, t, st);
-      case 128: return run_mlp<P, 128, 2, 4, 4>(e, x, B, A_out, g_out, t, st);
-      case 256: return run_mlp<P, 256, 2, 4, 4>(e, x, B, A_out, g_out, t, st);
-      case 512: return run_mlp<P, 512, 2, 8, 4>(e, x, B, A_out, g_out, t, st);
-    }
-  } else {
-    switch (e.NP) {
-      case 64:  return run_mlp<P, 64, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
-      case 128: return run_mlp<P, 128, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
-      case 256: return run_mlp<P, 256, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
-      case 512: return run_mlp<P, 512, 1, 8, 6>(e, x, B, A_out, g_out, t, st);
-    }
+  switch (e.NP) {
+    case 64:  return run_16bit<P, 64, 1>(e, x, B, A_out, g_out, t, st);
+    case 128: return run_16bit<P, 128, 2>(e, x, B, A_out, g_out, t, st);
+    case 256: return run_16bit<P, 256, 4>(e, x, B, A_out, g_out, t, st);
+    case 512: return run_16bit<P, 512, 8>(e, x, B, A_out, g_out, t, st);
   }
   return fail(RID_EUNSUPPORTED, "no kernel for this padded width");
 }
@@ -503,8 +587,8 @@ rid_status dispatch(const rid_ensemble_impl& e, const float* x, int B, float* A_
                     float* g_out, const TorsionInput* t, hipStream_t st) {
   if (e.prec == RID_FP32) {
     switch (e.NP) {
-      case 64:  return run_mlp<F32, 64, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
-      case 128: return run_mlp<F32, 128, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
+      case 64:  return run_mlp<F32, 64, 1, 1, 6>(e, x, B, A_out, g_out, t, st);
+      case 128: return run_mlp<F32, 128, 1, 2, 6>(e, x, B, A_out, g_out, t, st);
       case 256: return run_mlp<F32, 256, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
       case 512: return run_mlp<F32, 512, 1, 8, 6>(e, x, B, A_out, g_out, t, st);
     }
@@ -517,23 +601,17 @@ rid_status dispatch(const rid_ensemble_impl& e, const float* x, int B, float* A_
 }  // namespace
 
 // Kernel family: (precision, padded width, depth) -> instantiation.
-// FP32: 16 walkers per workgroup (MFMA f32 is 16x slower per FLOP, so the
-// L2 weight stream is not the limit); 16-bit: 32 walkers per workgroup to
-// halve the weight traffic per FLOP; depth <= 4 keeps the FP32 tanh' stash
-// small, deeper networks take 16 walkers per workgroup.
+// FP32: 16 walkers per workgroup, 4 unit tiles (64 units) per wave.
+// 16-bit: 64 walkers per workgroup (32 for deep networks or wide inputs) to
+// cut the L2 weight stream per FLOP; 64 units per wave.
 rid_status launch_mlp(const rid_ensemble_impl& e, const float* x, int B,
                       float* A_out, float* g_out, hipStream_t st) {
   return dispatch(e, x, B, A_out, g_out, nullptr, st);
 }
 
-rid_status launch_mlp_from_pos(const rid_ensemble_impl& e, const TorsionInput& tail,
+rid_status launch_mlp_from_pos(const rid_ensemble_impl& e, const TorsionInput& tin,
                                int B, float* A_out, float* g_out, hipStream_t st) {
-  return dispatch(e, nullptr, B, A_out, g_out, &tail, st);
-}
-
-int mlp_rows_per_tile(const rid_ensemble_impl& e) {
-  if (e.prec == RID_FP32) return 16;
-  return e.L <= 4 ? 32 : 16;
+  return dispatch(e, nullptr, B, A_out, g_out, &tin, st);
 }
 
 rid_status pack_ensemble_weights(rid_ensemble_impl& e, hipStream_t st) {

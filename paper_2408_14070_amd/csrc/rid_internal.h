@@ -32,7 +32,6 @@ struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
   rid_status ensure(size_t need);
-  rid_status ensure_zeroed(size_t need);  // new memory is zero-filled
   void release();
   template <class T> T* as() const { return static_cast<T*>(ptr); }
 };
@@ -123,7 +122,7 @@ struct rid_ensemble_impl {
   float* d_bo = nullptr;             // [K]
   // scratch
   bool frag_dirty = false;           // masters changed since the last pack
-  DevBuf ws_x, ws_A, ws_g, ws_train, ws_cnt;
+  DevBuf ws_x, ws_A, ws_g, ws_train;
 };
 
 // ---------------------------------------------------------------------------
@@ -139,7 +138,6 @@ struct TorsionInput {
 };
 rid_status launch_mlp_from_pos(const rid_ensemble_impl& e, const TorsionInput& tin,
                                int B, float* A_out, float* g_out, hipStream_t st);
-int mlp_rows_per_tile(const rid_ensemble_impl& e);
 rid_status launch_mlp(const rid_ensemble_impl& e, const float* x, int B,
                       float* A_out, float* g_out, hipStream_t st);
 rid_status launch_ensemble_reduce(int K, int n, int B, const float* A,
@@ -163,3 +161,11 @@ rid_status launch_mf_label_impl(const float* traj, const float* s0,
                                 uint8_t* keep, hipStream_t st);
 
 }  // namespace rid
+
+// Public handle types (opaque in include/rid.h).
+struct rid_system_s {
+  rid::rid_system_impl impl;
+};
+struct rid_ensemble_s {
+  rid::rid_ensemble_impl impl;
+};

@@ -1,0 +1,482 @@
+// Serving loop: continuous batching of bias-force requests from many
+// walkers of different systems and ensembles on one GPU.
+//
+// A request is a block of walkers of one registered model (system +
+// ensemble + trust levels).  Ensemble weights and system tables stay
+// resident; each request's positions are staged in pinned host memory.  A
+// scheduler thread forms batches (serve_core.h policy), admits them against
+// an HBM arena of fixed budget, and runs each batch on one of several
+// streams: host-to-device copies of the member requests, the MLP kernel fed
+// from positions, the deviation/switch/chain-rule kernel, and device-to-host
+// copies of every request's results, then an event.  A completion thread
+// polls the events, frees the batch's memory and wakes waiters and the
+// scheduler, so requests that arrive while batches are on the GPU are
+// admitted as slots and memory free up.  Results do not depend on the
+// batch a request lands in: every kernel computes each walker's row
+// independently, with a fixed reduction order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "rid_internal.h"
+#include "serve_core.h"
+
+namespace rid {
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+struct ServeModel {
+  rid_system_impl* sys;
+  rid_ensemble_impl* ens;
+  float eps0, eps1;
+  serve::ModelShape shape;
+};
+
+struct Req {
+  int model = 0;
+  int walkers = 0;
+  size_t pin_off = 0;
+  float* pin = nullptr;          // [w][N][3] positions, then outputs
+  bool own_pin = false;          // pinned block outside the staging arena
+  clk::time_point arrival, done_at;
+  bool done = false;
+  rid_status status = RID_OK;
+};
+
+struct Batch {
+  std::vector<int64_t> tickets;
+  int model = 0, walkers = 0, slot = 0;
+  size_t dev_off = 0;
+};
+
+// Pinned layout of one request: positions, forces, energy, eps, sigma.
+inline size_t pin_bytes(int w, int n_atoms) {
+  return serve::align_up((size_t)w * n_atoms * 3 * 4) * 2 + serve::align_up((size_t)w * 4) * 3;
+}
+
+}  // namespace
+
+struct Server {
+  int device = 0;
+  size_t budget = 0;
+  int n_slots = 1, max_batch = 4096;
+  bool fifo = false;
+  void* dev_base = nullptr;
+  void* pin_base = nullptr;
+  serve::Arena dev, pin;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  std::vector<bool> slot_busy;
+  std::vector<ServeModel> models;
+
+  std::mutex mu;
+  std::condition_variable cv_sched, cv_done;
+  std::deque<serve::Waiting> waiting;
+  std::unordered_map<int64_t, Req> reqs;
+  std::vector<Batch> inflight;
+  int64_t next_ticket = 1;
+  bool stop = false;
+  rid_status fatal = RID_OK;
+  std::thread sched, poller;
+
+  // statistics
+  std::vector<double> lat_us;
+  int64_t walkers_done = 0, requests_done = 0, batches = 0, batch_walkers = 0;
+  int64_t admission_waits = 0, max_inflight = 0;
+  bool have_first = false;
+  clk::time_point first_arrival, last_done;
+
+  void run_scheduler();
+  void run_poller();
+  rid_status launch(Batch& b);
+};
+
+rid_status Server::launch(Batch& b) {
+  ServeModel& m = models[b.model];
+  const int W = b.walkers, N = m.sys->n_atoms, n = m.sys->n_cv, K = m.ens->K;
+  unsigned char* base = static_cast<unsigned char*>(dev_base) + b.dev_off;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base + off;
+    off += serve::align_up(bytes);
+    return p;
+  };
+  float* pos = reinterpret_cast<float*>(take((size_t)W * N * 3 * 4));
+  float* force = reinterpret_cast<float*>(take((size_t)W * N * 3 * 4));
+  float* energy = reinterpret_cast<float*>(take((size_t)W * 4));
+  float* eps = reinterpret_cast<float*>(take((size_t)W * 4));
+  float* sigma = reinterpret_cast<float*>(take((size_t)W * 4));
+  uint8_t* flags = reinterpret_cast<uint8_t*>(take((size_t)W));
+  float* A = reinterpret_cast<float*>(take((size_t)W * K * 4));
+  float* g = reinterpret_cast<float*>(take((size_t)W * K * n * 4));
+  hipStream_t st = streams[b.slot];
+  int wo = 0;
+  for (int64_t t : b.tickets) {
+    Req& r = reqs[t];
+    RID_HIP(hipMemcpyAsync(pos + (size_t)wo * N * 3, r.pin, (size_t)r.walkers * N * 3 * 4,
+                           hipMemcpyHostToDevice, st));
+    wo += r.walkers;
+  }
+  float* x = reinterpret_cast<float*>(take((size_t)W * 2 * n * 4));
+  const TorsionInput tin{m.sys, pos};
+  rid_status rs = launch_mlp_from_pos(*m.ens, tin, W, A, g, st);
+  if (rs == RID_EUNSUPPORTED) {   // too many torsion atoms for the in-kernel gather
+    rs = launch_cv_eval(*m.sys, pos, W, nullptr, x, st);
+    if (rs == RID_OK) rs = launch_mlp(*m.ens, x, W, A, g, st);
+  }
+  if (rs != RID_OK) return rs;
+  rs = launch_bias_scatter(*m.sys, K, pos, W, A, g, nullptr, m.eps0, m.eps1, force, energy,
+                           eps, sigma, flags, st);
+  if (rs != RID_OK) return rs;
+  wo = 0;
+  for (int64_t t : b.tickets) {
+    Req& r = reqs[t];
+    const int w = r.walkers;
+    unsigned char* out = reinterpret_cast<unsigned char*>(r.pin) +
+                         serve::align_up((size_t)w * N * 3 * 4);
+    RID_HIP(hipMemcpyAsync(out, force + (size_t)wo * N * 3, (size_t)w * N * 3 * 4,
+                           hipMemcpyDeviceToHost, st));
+    out += serve::align_up((size_t)w * N * 3 * 4);
+    RID_HIP(hipMemcpyAsync(out, energy + wo, (size_t)w * 4, hipMemcpyDeviceToHost, st));
+    out += serve::align_up((size_t)w * 4);
+    RID_HIP(hipMemcpyAsync(out, eps + wo, (size_t)w * 4, hipMemcpyDeviceToHost, st));
+    out += serve::align_up((size_t)w * 4);
+    RID_HIP(hipMemcpyAsync(out, sigma + wo, (size_t)w * 4, hipMemcpyDeviceToHost, st));
+    wo += w;
+  }
+  RID_HIP(hipEventRecord(events[b.slot], st));
+  return RID_OK;
+}
+
+void Server::run_scheduler() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  while (!stop) {
+    int slot = -1;
+    for (int s = 0; s < n_slots; ++s)
+      if (!slot_busy[s]) {
+        slot = s;
+        break;
+      }
+    if (waiting.empty() || slot < 0) {
+      cv_sched.wait(lk);
+      continue;
+    }
+    std::vector<size_t> pick = serve::form_batch(waiting, max_batch, fifo);
+    Batch b;
+    b.model = waiting[pick.front()].model;
+    size_t off = 0;
+    if (!serve::admit(waiting, pick, models[b.model].shape, dev, &off, &b.walkers)) {
+      // admission: wait for an in-flight batch to finish and free memory
+      ++admission_waits;
+      if (inflight.empty()) {
+        // the arena is empty and the oldest request still does not fit
+        // (submission checks this, so only reachable on a logic error)
+        Req& r = reqs[waiting.front().ticket];
+        r.status = RID_ENOMEM;
+        r.done = true;
+        r.done_at = clk::now();
+        waiting.pop_front();
+        cv_done.notify_all();
+        continue;
+      }
+      cv_sched.wait(lk);
+      continue;
+    }
+    b.dev_off = off;
+    b.slot = slot;
+    for (size_t i : pick) b.tickets.push_back(waiting[i].ticket);
+    for (auto it = pick.rbegin(); it != pick.rend(); ++it) waiting.erase(waiting.begin() + *it);
+    slot_busy[slot] = true;
+    rid_status rs = launch(b);
+    if (rs != RID_OK) {
+      fatal = rs;
+      for (int64_t t : b.tickets) {
+        reqs[t].status = rs;
+        reqs[t].done = true;
+        reqs[t].done_at = clk::now();
+      }
+      dev.release(off);
+      slot_busy[slot] = false;
+      cv_done.notify_all();
+      continue;
+    }
+    ++batches;
+    batch_walkers += b.walkers;
+    inflight.push_back(std::move(b));
+    max_inflight = std::max<int64_t>(max_inflight, (int64_t)inflight.size());
+  }
+}
+
+void Server::run_poller() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  while (!stop || !inflight.empty()) {
+    bool any = false;
+    for (size_t i = 0; i < inflight.size();) {
+      Batch& b = inflight[i];
+      if (hipEventQuery(events[b.slot]) == hipSuccess) {
+        const auto now = clk::now();
+        for (int64_t t : b.tickets) {
+          Req& r = reqs[t];
+          r.done = true;
+          r.done_at = now;
+        }
+        dev.release(b.dev_off);
+        slot_busy[b.slot] = false;
+        inflight.erase(inflight.begin() + i);
+        any = true;
+      } else {
+        ++i;
+      }
+    }
+    if (any) {
+      cv_done.notify_all();
+      cv_sched.notify_all();
+    }
+    if (inflight.empty()) {
+      if (stop) break;
+      cv_done.wait_for(lk, std::chrono::milliseconds(2));
+    } else if (!any) {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(5));
+      lk.lock();
+    }
+  }
+}
+
+}  // namespace rid
+
+using namespace rid;
+
+struct rid_server_s {
+  Server s;
+};
+
+extern "C" {
+
+rid_status rid_server_create(size_t hbm_budget_bytes, int n_streams,
+                             int max_batch_walkers, int flags, rid_server* out) {
+  if (!out) return fail(RID_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (hbm_budget_bytes < (1u << 20) || n_streams < 1 || n_streams > 16 || max_batch_walkers < 1)
+    return fail(RID_EINVAL, "need budget >= 1 MiB, 1 <= n_streams <= 16, max_batch_walkers >= 1");
+  rid_server_s* h = new (std::nothrow) rid_server_s();
+  if (!h) return fail(RID_ENOMEM, "host allocation failed");
+  Server& s = h->s;
+  (void)hipGetDevice(&s.device);
+  s.fifo = (flags & RID_SERVE_FIFO) != 0;
+  s.n_slots = s.fifo ? 1 : n_streams;
+  s.max_batch = max_batch_walkers;
+  s.budget = hbm_budget_bytes;
+  const size_t pin_cap = (size_t)256 << 20;   // pinned staging arena
+  if (hipMalloc(&s.dev_base, hbm_budget_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete h;
+    return fail(RID_ENOMEM, "HBM budget allocation failed");
+  }
+  if (hipHostMalloc(&s.pin_base, pin_cap, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(s.dev_base);
+    delete h;
+    return fail(RID_ENOMEM, "pinned staging allocation failed");
+  }
+  s.dev.reset(hbm_budget_bytes);
+  s.pin.reset(pin_cap);
+  s.streams.resize(s.n_slots);
+  s.events.resize(s.n_slots);
+  s.slot_busy.assign(s.n_slots, false);
+  for (int i = 0; i < s.n_slots; ++i) {
+    if (hipStreamCreateWithFlags(&s.streams[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s.events[i], hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      for (int j = 0; j < i; ++j) {
+        (void)hipStreamDestroy(s.streams[j]);
+        (void)hipEventDestroy(s.events[j]);
+      }
+      (void)hipFree(s.dev_base);
+      (void)hipHostFree(s.pin_base);
+      delete h;
+      return fail(RID_EDEVICE, "stream creation failed");
+    }
+  }
+  s.sched = std::thread([&s] { s.run_scheduler(); });
+  s.poller = std::thread([&s] { s.run_poller(); });
+  *out = h;
+  return RID_OK;
+}
+
+rid_status rid_server_register(rid_server srv, rid_system sys, rid_ensemble ens,
+                               float eps0, float eps1, int* model_id) {
+  if (!srv || !sys || !ens || !model_id) return fail(RID_EINVAL, "NULL argument");
+  if (!(eps0 >= 0.f) || !(eps0 < eps1)) return fail(RID_EINVAL, "trust levels need 0 <= eps0 < eps1");
+  if (sys->impl.n_cv != ens->impl.n_cv) return fail(RID_EINVAL, "system and ensemble disagree on n_cv");
+  Server& s = srv->s;
+  rid_ensemble_impl& e = ens->impl;
+  if (e.frag_dirty) {
+    rid_status rs = pack_ensemble_weights(e, nullptr);
+    if (rs != RID_OK) return rs;
+    RID_HIP(hipStreamSynchronize(nullptr));
+    e.frag_dirty = false;
+  }
+  std::lock_guard<std::mutex> lk(s.mu);
+  ServeModel m{&sys->impl, &e, eps0, eps1, {}};
+  m.shape.n_atoms = sys->impl.n_atoms;
+  m.shape.n_cv = sys->impl.n_cv;
+  m.shape.K = e.K;
+  s.models.push_back(m);
+  *model_id = (int)s.models.size() - 1;
+  return RID_OK;
+}
+
+rid_status rid_server_submit(rid_server srv, int model_id, const float* host_pos,
+                             int n_walkers, int64_t* ticket) {
+  if (!srv || !host_pos || !ticket) return fail(RID_EINVAL, "NULL argument");
+  Server& s = srv->s;
+  std::unique_lock<std::mutex> lk(s.mu);
+  if (model_id < 0 || model_id >= (int)s.models.size()) return fail(RID_EINVAL, "unknown model id");
+  if (n_walkers < 1) return fail(RID_EINVAL, "n_walkers must be >= 1");
+  if (s.fatal != RID_OK) return fail(s.fatal, "server stopped after a device error");
+  const ServeModel& m = s.models[model_id];
+  if (m.shape.batch_bytes(n_walkers) > s.dev.capacity())
+    return fail(RID_ENOMEM, "request larger than the HBM budget");
+  const size_t pb = pin_bytes(n_walkers, m.shape.n_atoms);
+  size_t poff = 0;
+  Req r;
+  r.model = model_id;
+  r.walkers = n_walkers;
+  if (s.pin.alloc(pb, &poff)) {
+    r.pin_off = poff;
+    r.pin = reinterpret_cast<float*>(static_cast<unsigned char*>(s.pin_base) + poff);
+  } else {
+    // staging arena full (many requests outstanding): a pinned block of its
+    // own, so a client that submits many requests before waiting never
+    // blocks here
+    void* p = nullptr;
+    if (hipHostMalloc(&p, pb, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(RID_ENOMEM, "pinned staging allocation failed");
+    }
+    r.pin = static_cast<float*>(p);
+    r.own_pin = true;
+  }
+  std::memcpy(r.pin, host_pos, (size_t)n_walkers * m.shape.n_atoms * 3 * 4);
+  r.arrival = clk::now();
+  if (!s.have_first) {
+    s.first_arrival = r.arrival;
+    s.have_first = true;
+  }
+  const int64_t t = s.next_ticket++;
+  s.reqs.emplace(t, r);
+  s.waiting.push_back({t, model_id, n_walkers});
+  *ticket = t;
+  s.cv_sched.notify_all();
+  return RID_OK;
+}
+
+rid_status rid_server_wait(rid_server srv, int64_t ticket, float* host_force,
+                           float* host_energy, float* host_eps, float* host_sigma,
+                           double* latency_us) {
+  if (!srv) return fail(RID_EINVAL, "NULL argument");
+  Server& s = srv->s;
+  std::unique_lock<std::mutex> lk(s.mu);
+  if (s.reqs.find(ticket) == s.reqs.end()) return fail(RID_EINVAL, "unknown ticket");
+  // look the request up again after every wake-up: other threads' submits
+  // may rehash the table (references stay valid, iterators do not)
+  Req& r = s.reqs.find(ticket)->second;
+  s.cv_done.wait(lk, [&] { return r.done; });
+  const rid_status st = r.status;
+  if (st == RID_OK) {
+    const int w = r.walkers, N = s.models[r.model].shape.n_atoms;
+    const unsigned char* out = reinterpret_cast<const unsigned char*>(r.pin) +
+                               serve::align_up((size_t)w * N * 3 * 4);
+    if (host_force) std::memcpy(host_force, out, (size_t)w * N * 3 * 4);
+    out += serve::align_up((size_t)w * N * 3 * 4);
+    if (host_energy) std::memcpy(host_energy, out, (size_t)w * 4);
+    out += serve::align_up((size_t)w * 4);
+    if (host_eps) std::memcpy(host_eps, out, (size_t)w * 4);
+    out += serve::align_up((size_t)w * 4);
+    if (host_sigma) std::memcpy(host_sigma, out, (size_t)w * 4);
+    const double us = std::chrono::duration<double, std::micro>(r.done_at - r.arrival).count();
+    if (latency_us) *latency_us = us;
+    s.lat_us.push_back(us);
+    s.walkers_done += w;
+    s.requests_done += 1;
+    if (r.done_at > s.last_done) s.last_done = r.done_at;
+  }
+  if (r.own_pin)
+    (void)hipHostFree(r.pin);
+  else
+    s.pin.release(r.pin_off);
+  s.reqs.erase(ticket);
+  if (st != RID_OK) return fail(st, "request failed");
+  return RID_OK;
+}
+
+rid_status rid_server_stats(rid_server srv, rid_server_stats_t* out) {
+  if (!srv || !out) return fail(RID_EINVAL, "NULL argument");
+  Server& s = srv->s;
+  std::lock_guard<std::mutex> lk(s.mu);
+  std::memset(out, 0, sizeof(*out));
+  out->requests_done = s.requests_done;
+  out->walkers_done = s.walkers_done;
+  out->batches = s.batches;
+  out->admission_waits = s.admission_waits;
+  out->max_inflight_batches = s.max_inflight;
+  out->mean_batch_walkers = s.batches ? (double)s.batch_walkers / s.batches : 0.0;
+  if (!s.lat_us.empty()) {
+    std::vector<double> v = s.lat_us;
+    std::sort(v.begin(), v.end());
+    auto q = [&](double f) { return v[std::min(v.size() - 1, (size_t)(f * (v.size() - 1) + 0.5))]; };
+    out->p50_us = q(0.50);
+    out->p99_us = q(0.99);
+    out->max_us = v.back();
+    double sum = 0;
+    for (double x : v) sum += x;
+    out->mean_us = sum / v.size();
+    const double span = std::chrono::duration<double>(s.last_done - s.first_arrival).count();
+    out->walker_steps_per_s = span > 0 ? s.walkers_done / span : 0.0;
+  }
+  return RID_OK;
+}
+
+void rid_server_reset_stats(rid_server srv) {
+  if (!srv) return;
+  Server& s = srv->s;
+  std::lock_guard<std::mutex> lk(s.mu);
+  s.lat_us.clear();
+  s.walkers_done = s.requests_done = s.batches = s.batch_walkers = 0;
+  s.admission_waits = s.max_inflight = 0;
+  s.have_first = false;
+}
+
+void rid_server_destroy(rid_server srv) {
+  if (!srv) return;
+  Server& s = srv->s;
+  {
+    std::lock_guard<std::mutex> lk(s.mu);
+    s.stop = true;
+  }
+  s.cv_sched.notify_all();
+  s.cv_done.notify_all();
+  if (s.sched.joinable()) s.sched.join();
+  if (s.poller.joinable()) s.poller.join();
+  for (auto st : s.streams) (void)hipStreamSynchronize(st);
+  for (auto st : s.streams) (void)hipStreamDestroy(st);
+  for (auto ev : s.events) (void)hipEventDestroy(ev);
+  if (s.dev_base) (void)hipFree(s.dev_base);
+  if (s.pin_base) (void)hipHostFree(s.pin_base);
+  delete srv;
+}
+
+}  // extern "C"

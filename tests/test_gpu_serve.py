@@ -1,0 +1,158 @@
+"""GPU tests of the serving form: continuous batching of requests from three
+system classes and two precisions.  Each request's result must be the same
+alone (a direct rid_bias_force call on just its walkers) and in the mix,
+bitwise; FP32 requests also match the FP64 oracle."""
+import threading
+
+import numpy as np
+import pytest
+
+import ridgen
+from oracle import rid_oracle as O
+from tests.gpu_common import FP32_TOL, assert_forces
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def rid():
+    import paper_2408_14070_amd as r
+    r.lib()
+    return r
+
+
+CLASSES = [
+    ("dipeptide", ridgen.system_dipeptide, [100, 100, 100]),
+    ("peptide20", ridgen.system_peptide20, [256] * 4),
+    ("peptide61", ridgen.system_peptide61, [512] * 4),
+]
+
+
+def _models(rid):
+    out = []
+    for ci, (name, mk, widths) in enumerate(CLASSES):
+        sys_ = mk()
+        S = rid.System(sys_.n_atoms, sys_.quads)
+        for prec in (rid.RID_FP32, rid.RID_BF16):
+            K = 8 if (widths[0] == 512 and prec == rid.RID_BF16) else 4
+            params = ridgen.xavier_ensemble(2 * sys_.n_cv, widths, K, 1000 + 10 * ci, 0.05)
+            E = rid.Ensemble(sys_.n_cv, widths, K, params, prec)
+            out.append(dict(sys=sys_, S=S, E=E, params=params, widths=widths, K=K, prec=prec,
+                            name=f"{name}-{'fp32' if prec == 0 else 'bf16'}"))
+    return out
+
+
+def _direct(torch, rid, m, pos, e0, e1):
+    o = rid.bias_force(m["S"], m["E"], torch.from_numpy(pos).cuda(), e0, e1)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in o.items()}
+
+
+def test_single_request_matches_direct_call(torch, rid):
+    ms = _models(rid)
+    srv = rid.Server(1 << 30, n_streams=2)
+    m = ms[2]
+    mid = srv.register(m["S"], m["E"], 2.0, 3.0)
+    pos = ridgen.f32(ridgen.chain_coords(m["sys"], 37, 3))
+    t = srv.submit(mid, pos)
+    got = srv.wait(t)
+    ref = _direct(torch, rid, m, pos, 2.0, 3.0)
+    assert np.array_equal(got["F"], ref["F"])
+    assert np.array_equal(got["eps"], ref["eps"])
+    assert np.array_equal(got["E"], ref["E"])
+    assert got["latency_us"] > 0
+    srv.close()
+
+
+def test_mixed_stream_is_batch_invariant(torch, rid):
+    ms = _models(rid)
+    srv = rid.Server(2 << 30, n_streams=4, max_batch_walkers=2048)
+    ids = [srv.register(m["S"], m["E"], 2.0, 3.0) for m in ms]
+    rng = np.random.default_rng(7)
+    reqs = []
+    for r in range(90):
+        mi = int(rng.integers(0, len(ms)))
+        w = int(np.clip(np.floor(np.exp(rng.uniform(0, np.log(257)))), 1, 256))
+        pos = ridgen.f32(ridgen.chain_coords(ms[mi]["sys"], w, 100 + r))
+        reqs.append((mi, pos))
+    results = [None] * len(reqs)
+
+    def client(part):
+        # submit everything first so requests of several clients overlap on
+        # the device and share batches, then collect
+        tickets = [(i, srv.submit(ids[reqs[i][0]], reqs[i][1])) for i in part]
+        for i, t in tickets:
+            results[i] = srv.wait(t)
+
+    threads = [threading.Thread(target=client, args=(range(k, len(reqs), 4),)) for k in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    st = srv.stats()
+    print("serve stats:", st)
+    assert st["requests_done"] == len(reqs)
+    assert st["batches"] <= len(reqs)
+    for i, (mi, pos) in enumerate(reqs):
+        ref = _direct(torch, rid, ms[mi], pos, 2.0, 3.0)
+        assert np.array_equal(results[i]["F"], ref["F"]), (i, ms[mi]["name"])
+        assert np.array_equal(results[i]["sigma"], ref["sigma"])
+    # FP32 requests against the oracle (a few)
+    checked = 0
+    for i, (mi, pos) in enumerate(reqs):
+        m = ms[mi]
+        if m["prec"] != rid.RID_FP32 or checked >= 4:
+            continue
+        models = ridgen.unpack_params(m["params"], 2 * m["sys"].n_cv, m["widths"], m["K"])
+        ref = O.bias_force(pos.astype(np.float64), m["sys"].quads, models, 2.0, 3.0)
+        assert_forces(results[i]["F"], ref["F"], FP32_TOL, f"served {m['name']}")
+        checked += 1
+    assert checked > 0
+    srv.close()
+
+
+def test_tight_budget_admits_as_memory_frees(torch, rid):
+    ms = _models(rid)
+    m = ms[4]                       # 1000-atom class, FP32
+    srv = rid.Server(8 << 20, n_streams=4, max_batch_walkers=4096)
+    mid = srv.register(m["S"], m["E"], 2.0, 3.0)
+    poss = [ridgen.f32(ridgen.chain_coords(m["sys"], 200, 40 + i)) for i in range(12)]
+    tickets = [srv.submit(mid, p) for p in poss]
+    outs = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    print("tight budget stats:", st)
+    assert st["requests_done"] == 12
+    for p, o in zip(poss, outs):
+        assert np.array_equal(o["F"], _direct(torch, rid, m, p, 2.0, 3.0)["F"])
+    srv.close()
+
+
+def test_request_larger_than_budget_is_rejected(torch, rid):
+    ms = _models(rid)
+    m = ms[4]
+    srv = rid.Server(2 << 20, n_streams=1)
+    mid = srv.register(m["S"], m["E"], 2.0, 3.0)
+    with pytest.raises(rid.RidError) as ei:
+        srv.submit(mid, ridgen.f32(ridgen.chain_coords(m["sys"], 256, 1)))
+    assert ei.value.status == rid.RID_ENOMEM
+    srv.close()
+
+
+def test_fifo_baseline_mode(torch, rid):
+    ms = _models(rid)
+    srv = rid.Server(1 << 30, fifo=True)
+    ids = [srv.register(m["S"], m["E"], 2.0, 3.0) for m in ms[:2]]
+    poss = [ridgen.f32(ridgen.chain_coords(ms[i % 2]["sys"], 5 + i, i)) for i in range(6)]
+    ts = [srv.submit(ids[i % 2], p) for i, p in enumerate(poss)]
+    outs = [srv.wait(t) for t in ts]
+    st = srv.stats()
+    assert st["batches"] == 6 and st["mean_batch_walkers"] == np.mean([p.shape[0] for p in poss])
+    for i, o in enumerate(outs):
+        assert np.array_equal(o["F"], _direct(torch, rid, ms[i % 2], poss[i], 2.0, 3.0)["F"])
+    srv.close()
