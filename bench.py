@@ -1,23 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the RiD neural-bias hot path on one MI355X.
 
-Workload (the metric's configuration): a 20-residue peptide-shaped chain
+Headline (the metric's configuration): a 20-residue peptide-shaped chain
 (200 atoms, 38 backbone torsion CVs), an ensemble of 4 tanh MLPs
 76 -> [256 x 4] -> 1 in FP32, 1024 walkers, trust levels 2 / 3.  One step is
 one rid_bias_force call: torsion CVs, ensemble forward + input gradient,
 model deviation, switch, chain rule to atomic forces.  Inputs are resident
 in HBM before the timed region; synthetic seeded data.
 
-The JSON line also carries the precision form (BF16, 8 x [512 x 4],
-16384 walkers) and the other rows of the path as extra fields.
+The same JSON line carries the other rows of the path as extra fields:
+the 16-bit precision forms (8 x [512 x 4], 16384 walkers, BF16 and FP16),
+the mean-force training step (4 x [256 x 4], batch 4096), the
+restrained-trajectory label reduction, and the serving form (p50/p99
+latency and throughput of a Poisson request stream against the one-at-a-
+time FP32 baseline).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -29,24 +35,36 @@ import ridgen  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
-BF16_PEAK_TFLOPS = 2500.0
+BF16_PEAK_TFLOPS = 2500.0     # dense; FP16 has the same dense peak
+
+
+def log(msg):
+    """Progress on stderr; stdout carries only the JSON line."""
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+def layer_flops(n_cv, widths):
+    """2 * in * out summed over the hidden layers."""
+    f, prev = 0, 2 * n_cv
+    for w in widths:
+        f += 2 * prev * w
+        prev = w
+    return f
 
 
 def mlp_flops_per_walker(n_cv, widths, K):
     """Algorithmic FLOPs of the ensemble forward + input-gradient sweep:
     2*in*out per layer forward and the same backward, plus the output dot."""
-    f = 0
-    prev = 2 * n_cv
-    for w in widths:
-        f += 2 * prev * w
-        prev = w
-    f += 2 * prev                 # output layer A = wo . h_L
-    bwd = 0
-    prev = 2 * n_cv
-    for w in widths:
-        bwd += 2 * prev * w
-        prev = w
-    return K * (f + bwd)
+    return K * (2 * layer_flops(n_cv, widths) + 2 * widths[-1])
+
+
+def train_flops_per_sample(n_cv, widths, K):
+    """Forward, primal backward, tangent forward (3 sweeps), adjoint
+    propagation through layers 2..L (2 products each) and the two weight-
+    gradient products of every layer."""
+    F = layer_flops(n_cv, widths)
+    F1 = 2 * (2 * n_cv) * widths[0]
+    return K * (3 * F + 2 * (F - F1) + 2 * F + 2 * widths[-1])
 
 
 def build_case(rid, torch, sys_, B, K, widths, prec, seed=1):
@@ -66,7 +84,18 @@ def build_case(rid, torch, sys_, B, K, widths, prec, seed=1):
                 widths=widths)
 
 
+def read_kernels(rid, kinds):
+    kern = {}
+    for name, kind in kinds:
+        tot, cnt = rid.profile_read(kind)
+        if cnt:
+            kern[name] = tot / cnt     # ms per launch
+    return kern
+
+
 def time_bias(rid, torch, case, steps, warmup, eps0=2.0, eps1=3.0):
+    """Timed region: `steps` bias-force calls; the library brackets every
+    kernel with HIP events on the launching stream meanwhile."""
     S, E, P, out = case["S"], case["E"], case["P"], case["out"]
     for _ in range(warmup):
         rid.bias_force(S, E, P, eps0, eps1, out=out)
@@ -77,12 +106,8 @@ def time_bias(rid, torch, case, steps, warmup, eps0=2.0, eps1=3.0):
         rid.bias_force(S, E, P, eps0, eps1, out=out)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kern = {}
-    for name, kind in (("cv_eval", rid.PROF_CV), ("mlp", rid.PROF_MLP),
-                       ("scatter", rid.PROF_SCATTER)):
-        tot, cnt = rid.profile_read(kind)
-        if cnt:
-            kern[name] = tot / cnt
+    kern = read_kernels(rid, (("cv_eval", rid.PROF_CV), ("mlp", rid.PROF_MLP),
+                              ("scatter", rid.PROF_SCATTER)))
     rid.profile_enable(False)
     return (t1 - t0), kern
 
@@ -91,7 +116,7 @@ def kernel_source_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2408_14070_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.startswith("mlp_kernels"):
+        if f.startswith("mlp_kernels") or f == "device_common.h":
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -112,6 +137,93 @@ def traffic_for(kernel_key):
     return None
 
 
+PMC_COPY_BYTES = 256 << 20      # bytes read (and written) by the calibration copy
+
+
+def pmc_workload(rid, torch, reps=3):
+    """A short program for the rocprofv3 counter passes: a plain elementwise
+    copy of known size (y = x * 1, reads and writes PMC_COPY_BYTES), then the
+    bias path on the 200-atom chain: 4 x [256 x 4] FP32 with 1024 walkers and
+    8 x [512 x 4] BF16 and FP16 with 16384 walkers, `reps` launches each."""
+    x = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    del x, y
+    sys20 = ridgen.system_peptide20()
+    for prec, B, K, widths in ((rid.RID_FP32, 1024, 4, [256] * 4),
+                               (rid.RID_BF16, 16384, 8, [512] * 4),
+                               (rid.RID_FP16, 16384, 8, [512] * 4)):
+        c = build_case(rid, torch, sys20, B, K, widths, prec)
+        for _ in range(reps):
+            rid.bias_force(c["S"], c["E"], c["P"], 2.0, 3.0, out=c["out"])
+        torch.cuda.synchronize()
+        del c
+    print("pmc workload done", flush=True)
+
+
+def _read_counters(d, counter):
+    """{kernel name: [value per dispatch]} from a rocprofv3 --pmc CSV."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    out = {}
+    for f in files:
+        for row in csv.DictReader(open(f)):
+            if row.get("Counter_Name") != counter:
+                continue
+            out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def pmc_summary(fetch_dir, write_dir, out_path):
+    """Turn the two counter passes over --pmc-workload into HBM bytes per
+    launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of each kernel,
+    scaled by what the same counter reads for the calibration copy."""
+    import re
+    fetch = _read_counters(fetch_dir, "FETCH_SIZE")
+    write = _read_counters(write_dir, "WRITE_SIZE")
+
+    def is_copy(name):
+        return "MulFunctor" in name or "mul_kernel" in name
+
+    def classify(name):
+        m = re.search(r"mlp_kernel<[^<>]*?\b(BF16|F16|F32)\b\s*,\s*(\d+)", name)
+        if not m:
+            return None
+        return {"F32": "mlp_fp32_4x256_b1024", "BF16": "mlp_bf16_8x512_b16384", "F16": "mlp_fp16_8x512_b16384"}[m.group(1)]
+
+    def mean_of(table, pick):
+        vals = [v for k, vs in table.items() if pick(k) for v in vs]
+        return sum(vals) / len(vals) if vals else None
+
+    cf, cw = mean_of(fetch, is_copy), mean_of(write, is_copy)
+    if not cf or not cw:
+        raise SystemExit("calibration copy not found in the counter output")
+    f_scale = PMC_COPY_BYTES / (cf * 1024.0)
+    w_scale = PMC_COPY_BYTES / (cw * 1024.0)
+    res = {"_calibration": {"copy_bytes": PMC_COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
+                            "fetch_scale": f_scale, "write_scale": w_scale},
+           "_source": "rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE over "
+                      "bench.py --pmc-workload"}
+    for key in ("mlp_fp32_4x256_b1024", "mlp_bf16_8x512_b16384", "mlp_fp16_8x512_b16384"):
+        fk = mean_of(fetch, lambda n, key=key: classify(n) == key)
+        wk = mean_of(write, lambda n, key=key: classify(n) == key)
+        if fk is None or wk is None:
+            continue
+        res[key] = {"fetch_kib": fk, "write_kib": wk,
+                    "fetch_bytes": fk * 1024.0 * f_scale,
+                    "write_bytes": wk * 1024.0 * w_scale,
+                    "bytes_per_launch": fk * 1024.0 * f_scale + wk * 1024.0 * w_scale,
+                    "source_hash": kernel_source_hash()}
+    with open(out_path, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res, indent=1))
+
+
 def cpu_baseline(case, budget_s=12.0):
     """The FP64 oracle on the same batch, repeated for about budget_s."""
     from oracle import rid_oracle as O
@@ -122,8 +234,7 @@ def cpu_baseline(case, budget_s=12.0):
         cores = os.cpu_count()
     sys_ = case["sys"]
     models = ridgen.unpack_params(case["params"], 2 * sys_.n_cv, case["widths"], case["K"])
-    pos = case["pos"].astype(np.float64)
-    sub = pos[:256]
+    sub = case["pos"][:256].astype(np.float64)
     reps, walkers = 0, 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
@@ -137,6 +248,167 @@ def cpu_baseline(case, budget_s=12.0):
                       f"{dt:.1f} s)"}
 
 
+def bench_precision(rid, torch, sys20, prec, name, steps, warmup):
+    Bb, Kb, wb = 16384, 8, [512] * 4
+    cb = build_case(rid, torch, sys20, Bb, Kb, wb, prec)
+    el, kern = time_bias(rid, torch, cb, steps, warmup)
+    fl = mlp_flops_per_walker(sys20.n_cv, wb, Kb) * Bb
+    ach = fl / (kern["mlp"] * 1e-3) / 1e12
+    return {
+        "workload": f"same chain; ensemble 8 x [512 x 4], {name} MFMA / FP32 accumulate / "
+                    "FP32 tanh' and switch / FP64 variance; 16384 walkers",
+        "value": Bb * steps / el, "unit": "walker-steps/s", "ms_per_step": 1e3 * el / steps,
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS,
+                     "traffic": traffic_for(f"mlp_{name.lower()}_8x512_b16384"),
+                     "avg_launch_us": kern["mlp"] * 1e3, "flop_per_launch": fl},
+        "kernels_us": {k: v * 1e3 for k, v in kern.items()},
+    }
+
+
+def bench_training(rid, torch, steps=20, warmup=3):
+    n, widths, K, B = 38, [256] * 4, 4, 4096
+    s_all, F_all, _ = ridgen.mf_training_set(200_000, n)
+    S = torch.from_numpy(s_all).cuda()
+    F = torch.from_numpy(F_all).cuda()
+    E = rid.Ensemble(n, widths, K, ridgen.xavier_ensemble(2 * n, widths, K, 1000))
+    perm = torch.from_numpy(np.random.default_rng(6).permutation(200_000)).cuda()
+    batches = [(S[perm[i * B:(i + 1) * B]].contiguous(), F[perm[i * B:(i + 1) * B]].contiguous())
+               for i in range(steps + warmup)]
+    for i in range(warmup):
+        rid.mf_train_step(E, *batches[i], rid.lr_exponential(E.step))
+    torch.cuda.synchronize()
+    rid.profile_enable(True)
+    t0 = time.perf_counter()
+    losses = []
+    for i in range(steps):
+        losses.append(rid.mf_train_step(E, *batches[warmup + i], rid.lr_exponential(E.step)))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tot, cnt = rid.profile_read(rid.PROF_TRAIN)
+    rid.profile_enable(False)
+    fl = train_flops_per_sample(n, widths, K) * B
+    step_s = (t1 - t0) / steps
+    return {
+        "workload": "mean-force fitting, 38 CVs, ensemble 4 x [256 x 4], batch 4096 from "
+                    "200k resident samples, double backward + Adam, FP32",
+        "value": B / step_s, "unit": "samples/s", "ms_per_step": 1e3 * step_s,
+        "flop_per_step": fl,
+        "achieved_tflops": fl / step_s / 1e12, "frac_fp32_peak": fl / step_s / 1e12 / FP32_PEAK_TFLOPS,
+        "loss_first_last": [float(losses[0].mean()), float(losses[-1].mean())],
+    }
+
+
+def bench_labels(rid, torch, reps=20):
+    M, T, n = 1024, 500, 38
+    traj, s0, _ = ridgen.restrained_traj(M, T, n, 500.0, seed=9)
+    tr = torch.from_numpy(traj).cuda()
+    s0d = torch.from_numpy(s0).cuda()
+    kappa = np.full(n, 500.0, np.float32)
+    for _ in range(3):
+        rid.mf_label(tr, s0d, kappa, None, 5.0)
+    torch.cuda.synchronize()
+    rid.profile_enable(True)
+    for _ in range(reps):
+        rid.mf_label(tr, s0d, kappa, None, 5.0)
+    torch.cuda.synchronize()
+    tot, cnt = rid.profile_read(rid.PROF_LABEL)
+    rid.profile_enable(False)
+    us = 1e3 * tot / cnt
+    byts = M * T * n * 4 + M * n * 4 + 2 * M * n * 8 + M
+    return {"workload": "restrained-MD mean-force labels, 1024 configs x 500 frames x 38 CVs, "
+                        "FP64 accumulation",
+            "avg_launch_us": us, "bytes_per_launch": byts,
+            "roofline": {"bound": "hbm", "achieved": byts / (us * 1e-6) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": byts / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}}
+
+
+SERVE_CLASSES = [("dipeptide", ridgen.system_dipeptide, [100] * 3),
+                 ("peptide20", ridgen.system_peptide20, [256] * 4),
+                 ("peptide61", ridgen.system_peptide61, [512] * 4)]
+
+
+def _serve_models(rid, fp32_only):
+    models = []
+    for ci, (name, mk, widths) in enumerate(SERVE_CLASSES):
+        sys_ = mk()
+        S = rid.System(sys_.n_atoms, sys_.quads)
+        precs = [rid.RID_FP32] if fp32_only else [rid.RID_FP32, rid.RID_BF16]
+        for prec in precs:
+            K = 8 if (widths[0] == 512 and prec == rid.RID_BF16) else 4
+            E = rid.Ensemble(sys_.n_cv, widths, K,
+                             ridgen.xavier_ensemble(2 * sys_.n_cv, widths, K, 1000 + ci), prec)
+            models.append((sys_, S, E))
+    return models
+
+
+def run_trace(rid, models, fifo, n_req, rate_hz, seed=5):
+    """Open-loop Poisson stream: a submitter thread releases requests at
+    their arrival times, a collector waits them in order."""
+    srv = rid.Server(64 << 30 if not fifo else 8 << 30, n_streams=4, max_batch_walkers=8192,
+                     fifo=fifo)
+    ids = [srv.register(S, E, 2.0, 3.0) for (_, S, E) in models]
+    trace = ridgen.poisson_trace(n_req, rate_hz, len(models), seed=seed)
+    poss = [ridgen.f32(ridgen.chain_coords(models[r.model_class][0], r.n_walkers, 7 + i))
+            for i, r in enumerate(trace)]
+    # warm every model once (first-use kernel setup is not part of serving)
+    for mi, (sys_, _, _) in enumerate(models):
+        srv.wait(srv.submit(ids[mi], ridgen.f32(ridgen.chain_coords(sys_, 4, 1))))
+    srv.reset_stats()
+    tickets = [None] * n_req
+    ready = threading.Semaphore(0)
+
+    def submitter():
+        t0 = time.perf_counter()
+        for i, r in enumerate(trace):
+            dt = r.arrival_s - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets[i] = srv.submit(ids[r.model_class], poss[i])
+            ready.release()
+
+    th = threading.Thread(target=submitter)
+    t_start = time.perf_counter()
+    th.start()
+    for i in range(n_req):
+        ready.acquire()
+        srv.wait(tickets[i])
+    th.join()
+    wall = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.close()
+    walkers = sum(r.n_walkers for r in trace)
+    return {"p50_us": st["p50_us"], "p99_us": st["p99_us"], "mean_us": st["mean_us"],
+            "walker_steps_per_s": walkers / wall, "requests": n_req,
+            "offered_req_per_s": rate_hz, "batches": st["batches"],
+            "mean_batch_walkers": st["mean_batch_walkers"],
+            "max_inflight_batches": st["max_inflight_batches"]}
+
+
+def bench_serving(rid, n_req=1500):
+    mixed = _serve_models(rid, fp32_only=False)
+    # closed-loop capacity: everything offered at once
+    cap = run_trace(rid, mixed, False, n_req, 1e9)
+    # requests/s the batched server sustained in the closed loop
+    mean_w = np.mean([r.n_walkers for r in ridgen.poisson_trace(n_req, 1.0, len(mixed), 5)])
+    cap_req_s = cap["walker_steps_per_s"] / mean_w
+    load = run_trace(rid, mixed, False, n_req, 0.5 * cap_req_s)
+    fp32 = _serve_models(rid, fp32_only=True)
+    base_cap = run_trace(rid, fp32, True, n_req // 3, 1e9)
+    base_req_s = base_cap["walker_steps_per_s"] / mean_w
+    base = run_trace(rid, fp32, True, n_req // 3, 0.5 * base_req_s)
+    return {
+        "workload": "Poisson requests over 3 system classes (2 CVs/22 atoms, 38/200, "
+                    "120/1000) x widths 100/256/512 x FP32/BF16 (K=8 for 512-BF16), "
+                    "1-256 walkers log-uniform, weights resident, HBM budget 64 GB",
+        "batched_capacity": cap, "batched_at_half_capacity": load,
+        "fifo_fp32_capacity": base_cap, "fifo_fp32_at_half_capacity": base,
+        "p50_us": load["p50_us"], "p99_us": load["p99_us"],
+        "walker_steps_per_s": cap["walker_steps_per_s"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,7 +416,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--pmc-workload", action="store_true",
+                    help="run the short program the counter passes profile")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
+                    help="summarize two rocprofv3 --pmc passes into HBM bytes per launch")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(walkers shard with no exchange; see the design notes). Use --gpus 1.",
@@ -155,22 +435,26 @@ def main():
     import paper_2408_14070_amd as rid
     rid.lib()
     assert torch.cuda.is_available(), "needs an MI355X"
+    log("library loaded")
+    if args.pmc_workload:
+        pmc_workload(rid, torch)
+        return
 
     sys20 = ridgen.system_peptide20()
     B, K, widths = 1024, 4, [256] * 4
     case = build_case(rid, torch, sys20, B, K, widths, rid.RID_FP32)
     elapsed, kern = time_bias(rid, torch, case, args.steps, args.warmup)
     ms_step = 1e3 * elapsed / args.steps
+    log(f"headline: {ms_step * 1e3:.1f} us per step")
     value = B * args.steps / elapsed
     flop_launch = mlp_flops_per_walker(sys20.n_cv, widths, K) * B
-    mlp_s = kern["mlp"] * 1e-3
-    achieved = flop_launch / mlp_s / 1e12
+    achieved = flop_launch / (kern["mlp"] * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-            "traffic": traffic_for("mlp_fp32_c2"),
-            "kernel": "mlp_kernel<F32,256,fused bias> (whole bias path in one launch)",
-            "avg_launch_us": kern["mlp"] * 1e3,
-            "flop_per_launch": flop_launch}
+            "traffic": traffic_for("mlp_fp32_4x256_b1024"),
+            "kernel": "mlp_kernel<F32,256> (torsions in-kernel + ensemble forward + "
+                      "input-gradient sweep)",
+            "avg_launch_us": kern["mlp"] * 1e3, "flop_per_launch": flop_launch}
     rec = {
         "metric": "bias-force walker-steps/s",
         "value": value,
@@ -194,26 +478,22 @@ def main():
         "latency_us_per_call": ms_step * 1e3,
     }
     if not args.no_extra:
-        # precision form: BF16 MFMA, 8 x [512 x 4], 16384 walkers
-        Bb, Kb, wb = 16384, 8, [512] * 4
-        cb = build_case(rid, torch, sys20, Bb, Kb, wb, rid.RID_BF16)
         steps_b = max(10, args.steps // 10)
-        el_b, kern_b = time_bias(rid, torch, cb, steps_b, max(3, args.warmup // 4))
-        fl_b = mlp_flops_per_walker(sys20.n_cv, wb, Kb) * Bb
-        ach_b = fl_b / (kern_b["mlp"] * 1e-3) / 1e12
-        rec["precision_form"] = {
-            "workload": "same chain; ensemble 8 x [512 x 4], BF16 MFMA / FP32 accumulate / "
-                        "FP64 variance; 16384 walkers",
-            "value": Bb * steps_b / el_b, "unit": "walker-steps/s",
-            "ms_per_step": 1e3 * el_b / steps_b,
-            "roofline": {"bound": "mfma", "achieved": ach_b, "peak": BF16_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": ach_b / BF16_PEAK_TFLOPS,
-                         "traffic": traffic_for("mlp_bf16_c3"),
-                         "avg_launch_us": kern_b["mlp"] * 1e3, "flop_per_launch": fl_b},
-            "kernels_us": {k: v * 1e3 for k, v in kern_b.items()},
-        }
-        del cb
+        wb = max(3, args.warmup // 4)
+        log("precision forms")
+        rec["precision_form"] = bench_precision(rid, torch, sys20, rid.RID_BF16, "BF16",
+                                                steps_b, wb)
+        rec["precision_form_fp16"] = bench_precision(rid, torch, sys20, rid.RID_FP16, "FP16",
+                                                     steps_b, wb)
+        log("training")
+        rec["training"] = bench_training(rid, torch)
+        log("labels")
+        rec["labels"] = bench_labels(rid, torch)
+        if not args.no_serve:
+            log("serving")
+            rec["serving"] = bench_serving(rid)
     if not args.no_cpu_baseline:
+        log("cpu baseline")
         rec["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(rec), flush=True)
 

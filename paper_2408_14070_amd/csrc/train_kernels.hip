@@ -266,18 +266,40 @@ __global__ void adjoint_kernel(const float* HHl, long long slab_h, const float* 
   }
 }
 
-// out[k][j] = sum_b X[k][b][j] (fixed order), written into the gradient
-// buffer at dst + k*per_model + j.
-__global__ void colsum_kernel(const float* X, long long slab, int B, int w, int K,
-                              float* grad, long long per_model, int dst_off) {
-  const int total = K * w;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-    const int k = e / w, j = e - k * w;
+// Column sums out[k][j] = sum_b X[k][b][j] in two fixed-order stages.
+// Stage 1: block (column tile of 64, row chunk of kColRows, member); lanes
+// are columns (coalesced rows), the 4 waves take interleaved rows and are
+// combined in wave order -> part[chunk][k][j].
+constexpr int kColRows = 256;
+__global__ __launch_bounds__(256) void colsum_partial_kernel(const float* X, long long slab,
+                                                             int B, int w, float* part, int K) {
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  const int chunk = blockIdx.y, k = blockIdx.z;
+  const int r0 = chunk * kColRows, r1 = min(B, r0 + kColRows);
+  float acc = 0.f;
+  if (j < w) {
     const float* p = X + k * slab + j;
-    float acc = 0.f;
-    for (int b = 0; b < B; ++b) acc += p[(long long)b * w];
-    grad[k * per_model + dst_off + j] = acc;
+    for (int b = r0 + wave; b < r1; b += 4) acc += p[(long long)b * w];
   }
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && j < w)
+    part[((long long)chunk * K + k) * w + j] =
+        ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// Stage 2: sum the chunks in order into the gradient buffer at
+// grad + k*per_model + dst_off + j.
+__global__ void colsum_final_kernel(const float* part, int chunks, int w, int K, float* grad,
+                                    long long per_model, int dst_off) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= K * w) return;
+  const int k = e / w, j = e - k * w;
+  float acc = 0.f;
+  for (int c = 0; c < chunks; ++c) acc += part[((long long)c * K + k) * w + j];
+  grad[k * per_model + dst_off + j] = acc;
 }
 
 // dW[k] = sum over split-K slabs (fixed order) -> gradient buffer
@@ -340,6 +362,19 @@ rid_status gemm(const GemmArgs& g0, hipStream_t st) {
   return RID_OK;
 }
 
+// out[k][j] = sum_{b<B} X[k*slab + b*w + j] -> grad[k*per_model + dst_off + j]
+rid_status colsum(const float* X, long long slab, int B, int w, int K, float* part,
+                  float* grad, long long per_model, int dst_off, hipStream_t st) {
+  const int chunks = (B + kColRows - 1) / kColRows;
+  hipLaunchKernelGGL(colsum_partial_kernel, dim3((w + 63) / 64, chunks, K), dim3(256), 0, st,
+                     X, slab, B, w, part, K);
+  RID_HIP(hipGetLastError());
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((K * w + 255) / 256), dim3(256), 0, st, part,
+                     chunks, w, K, grad, per_model, dst_off);
+  RID_HIP(hipGetLastError());
+  return RID_OK;
+}
+
 }  // namespace
 
 // Gradient in the packed parameter layout of
@@ -397,6 +432,7 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   const long long part = tot; tot += part_slab * ks;
   const long long grad = tot; tot += (long long)e.n_params;
   const long long lrows = tot; tot += (long long)K * B;
+  const long long cpart = tot; tot += (long long)((B + kColRows - 1) / kColRows) * K * wmax;
   rid_status rs = e.ws_train.ensure(sizeof(float) * tot);
   if (rs != RID_OK) return rs;
   float* W = e.ws_train.as<float>();
@@ -483,9 +519,9 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
       RID_HIP(hipGetLastError());
     }
     // db_l = sum_b lam_z
-    hipLaunchKernelGGL(colsum_kernel, dim3(grid1d((long long)K * w[l])), dim3(256), 0, st,
-                       W + sbuf, 2LL * B * w[l], B, w[l], K, G, pm, (int)b_off[l - 1]);
-    RID_HIP(hipGetLastError());
+    if ((rs = colsum(W + sbuf, 2LL * B * w[l], B, w[l], K, W + cpart, G, pm,
+                     (int)b_off[l - 1], st)) != RID_OK)
+      return rs;
     if (l > 1) {
       // [lam_h ; lam_hd]_{l-1} = [lam_z ; lam_zd] W_l
       GemmArgs g{};
@@ -498,10 +534,9 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
     }
   }
   // dw_o = sum_b hd_L ; db_o = 0
-  hipLaunchKernelGGL(colsum_kernel, dim3(grid1d((long long)K * w[L])), dim3(256), 0, st,
-                     W + hh[L] + (long long)B * w[L], slab(L), B, w[L], K, G, pm,
-                     (int)wo_off);
-  RID_HIP(hipGetLastError());
+  if ((rs = colsum(W + hh[L] + (long long)B * w[L], slab(L), B, w[L], K, W + cpart, G, pm,
+                   (int)wo_off, st)) != RID_OK)
+    return rs;
   // the output bias never reaches grad_s A: its gradient entry is zero
   hipLaunchKernelGGL(set_zero_kernel, dim3(1), dim3(64), 0, st, G, pm,
                      (int)(wo_off + w[L]), K);
