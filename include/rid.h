@@ -289,16 +289,17 @@ void rid_server_destroy(rid_server srv);
 
 /* ------------------------------------------------------------------------
  * Kernel timing for benchmarks.  While enabled, every kernel the library
- * launches is bracketed by two hipEvents recorded on the launching stream
- * (no synchronisation at record time).  rid_profile_enable(1) clears and
- * starts collection, rid_profile_enable(0) stops and clears it.
- * rid_profile_read synchronises the device and returns, for one kernel
- * family, the summed event-measured duration (ms) and the launch count
- * since collection started.  Families: 0 torsion CVs, 1 fused ensemble MLP,
+ * launches carries two hipEvents that take its start and end timestamps
+ * from the dispatch itself (no synchronisation at launch).  Modes of
+ * rid_profile_enable: 1 clears the collected timings and starts, 2 resumes
+ * without clearing (to sample some launches of a longer run), 0 pauses and
+ * keeps what was collected.  rid_profile_read synchronises the device and
+ * returns, for one kernel family, the summed event-measured duration (ms)
+ * and the launch count since the last clear.  Families: 0 torsion CVs, 1 fused ensemble MLP,
  * 2 deviation/switch/atom-force scatter, 3 ensemble reduction,
  * 4 CV embedding, 5 training step kernels, 6 mean-force labels.
  * ------------------------------------------------------------------------ */
-void rid_profile_enable(int on);
+void rid_profile_enable(int mode);
 rid_status rid_profile_read(int kind, double* total_ms, int64_t* count);
 
 #ifdef __cplusplus

@@ -407,13 +407,15 @@ class Server:
     __del__ = close
 
 
-def profile_enable(on: bool = True):
-    """Start (clear) or stop per-kernel HIP-event timing inside the library."""
-    lib().rid_profile_enable(1 if on else 0)
+def profile_enable(on: bool = True, keep: bool = False):
+    """Per-kernel HIP-event timing inside the library: on=True clears and
+    starts (keep=True resumes without clearing); on=False pauses and keeps
+    what was collected."""
+    lib().rid_profile_enable((2 if keep else 1) if on else 0)
 
 
 def profile_read(kind: int):
-    """(total_ms, launches) of a kernel family since profile_enable(True)."""
+    """(total_ms, launches) of a kernel family since the last clear."""
     tot = ctypes.c_double()
     cnt = ctypes.c_int64()
     _check(lib().rid_profile_read(int(kind), ctypes.byref(tot), ctypes.byref(cnt)))

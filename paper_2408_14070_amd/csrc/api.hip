@@ -50,7 +50,7 @@ static std::vector<hipEvent_t> g_pool;
 
 bool prof_enabled() { return g_prof_on; }
 
-hipEvent_t prof_record(hipStream_t st) {
+hipEvent_t prof_event() {
   hipEvent_t e = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -60,7 +60,12 @@ hipEvent_t prof_record(hipStream_t st) {
     }
   }
   if (!e && hipEventCreate(&e) != hipSuccess) return nullptr;
-  if (hipEventRecord(e, st) != hipSuccess) return nullptr;
+  return e;
+}
+
+hipEvent_t prof_record(hipStream_t st) {
+  hipEvent_t e = prof_event();
+  if (!e || hipEventRecord(e, st) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -354,6 +359,14 @@ rid_status rid_model_dev(rid_ensemble ens, const float* d_s, int B, float* d_eps
                                 d_eps, d_gbar, d_A, d_g, st);
 }
 
+// Batches up to this many walkers gather torsion atoms inside the MLP kernel
+// (one launch less); larger ones encode the CVs once into HBM first, so the
+// K members' workgroups read a compact [B][2n] encoding instead of each
+// re-reading the positions.
+#ifndef RID_FROM_POS_MAX_B
+#define RID_FROM_POS_MAX_B 4096
+#endif
+
 rid_status rid_bias_force(rid_system sys, rid_ensemble ens, const float* d_pos,
                           int B, float eps0, float eps1, float* d_force,
                           float* d_energy, float* d_eps, float* d_sigma,
@@ -374,9 +387,12 @@ rid_status rid_bias_force(rid_system sys, rid_ensemble ens, const float* d_pos,
     e.frag_dirty = false;
   }
   const TorsionInput tin{&s, d_pos};
-  r = launch_mlp_from_pos(e, tin, B, e.ws_A.as<float>(), e.ws_g.as<float>(), st);
+  r = B <= RID_FROM_POS_MAX_B
+          ? launch_mlp_from_pos(e, tin, B, e.ws_A.as<float>(), e.ws_g.as<float>(), st)
+          : RID_EUNSUPPORTED;
   if (r == RID_EUNSUPPORTED) {
-    // too many torsion atoms for the in-kernel gather: encode in HBM first
+    // large batch, or too many torsion atoms for the in-kernel gather:
+    // encode in HBM first
     if ((r = e.ws_x.ensure(sizeof(float) * 2 * e.n_cv * (size_t)B)) != RID_OK) return r;
     if ((r = launch_cv_eval(s, d_pos, B, nullptr, e.ws_x.as<float>(), st)) != RID_OK) return r;
     r = launch_mlp(e, e.ws_x.as<float>(), B, e.ws_A.as<float>(), e.ws_g.as<float>(), st);
@@ -405,10 +421,10 @@ rid_status rid_mf_train_step(rid_ensemble ens, const float* d_s, const float* d_
   return launch_train_step(ens->impl, d_s, d_F, B, lr, d_loss, (hipStream_t)stream);
 }
 
-void rid_profile_enable(int on) {
+void rid_profile_enable(int mode) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  prof_recycle_locked();
-  g_prof_on = on != 0;
+  if (mode == 1) prof_recycle_locked();
+  g_prof_on = mode != 0;
 }
 
 rid_status rid_profile_read(int kind, double* total_ms, int64_t* count) {

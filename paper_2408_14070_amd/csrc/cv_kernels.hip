@@ -98,9 +98,8 @@ __global__ void scatter_kernel(ScatterArgs a) {
 rid_status launch_cv_eval(const rid_system_impl& s, const float* pos, int B,
                           float* d_s, float* d_x, hipStream_t st) {
   const size_t lds = sizeof(float) * 3 * s.n_uniq;
-  ProfScope ps(kProfCv, st);
-  hipLaunchKernelGGL(cv_eval_kernel, dim3(B), dim3(kWave), lds, st, pos,
-                     s.n_atoms, s.d_uniq, s.n_uniq, s.d_lquads, s.n_cv, d_s, d_x);
+  launch_timed(kProfCv, cv_eval_kernel, dim3(B), dim3(kWave), (uint32_t)lds, st, pos,
+               s.n_atoms, s.d_uniq, s.n_uniq, s.d_lquads, s.n_cv, d_s, d_x);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }
@@ -108,8 +107,7 @@ rid_status launch_cv_eval(const rid_system_impl& s, const float* pos, int B,
 rid_status launch_embed(const float* s, int B, int n, float* x, hipStream_t st) {
   const size_t total = (size_t)B * n;
   const int grid = (int)std::min<size_t>((total + 255) / 256, 8192);
-  ProfScope ps(kProfEmbed, st);
-  hipLaunchKernelGGL(embed_kernel, dim3(grid), dim3(256), 0, st, s, B, n, x);
+  launch_timed(kProfEmbed, embed_kernel, dim3(grid), dim3(256), 0, st, s, B, n, x);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }
@@ -117,9 +115,8 @@ rid_status launch_embed(const float* s, int B, int n, float* x, hipStream_t st) 
 rid_status launch_ensemble_reduce(int K, int n, int B, const float* A,
                                   const float* g, float* eps, float* gbar,
                                   float* A_t, float* g_t, hipStream_t st) {
-  ProfScope ps(kProfReduce, st);
-  hipLaunchKernelGGL(reduce_kernel, dim3(B), dim3(kWave), sizeof(float) * n, st,
-                     K, n, B, A, g, eps, gbar, A_t, g_t);
+  launch_timed(kProfReduce, reduce_kernel, dim3(B), dim3(kWave),
+               (uint32_t)(sizeof(float) * n), st, K, n, B, A, g, eps, gbar, A_t, g_t);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }
@@ -146,8 +143,7 @@ rid_status launch_bias_scatter(const rid_system_impl& s, int K, const float* pos
   a.sigma = sigma;
   a.flags = flags;
   const size_t lds = sizeof(float) * scatter_lds_floats(s.n_uniq, s.n_cv);
-  ProfScope ps(kProfScatter, st);
-  hipLaunchKernelGGL(scatter_kernel, dim3(B), dim3(kWave), lds, st, a);
+  launch_timed(kProfScatter, scatter_kernel, dim3(B), dim3(kWave), (uint32_t)lds, st, a);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }

@@ -127,8 +127,7 @@ rid_status launch_mf_label_impl(const float* traj, const float* s0,
   a.se = se;
   a.keep = keep;
   const size_t lds = sizeof(double) * (kBlocks + 1) * (size_t)n;
-  ProfScope ps(kProfLabel, st);
-  hipLaunchKernelGGL(label_kernel, dim3(M), dim3(kThreads), lds, st, a);
+  launch_timed(kProfLabel, label_kernel, dim3(M), dim3(kThreads), (uint32_t)lds, st, a);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }

@@ -85,13 +85,13 @@ template <> struct Pack4<float> {
   __device__ inline void store(float* dst) const { *reinterpret_cast<f4*>(dst) = v; }
 };
 template <class H> struct Pack16 {
+  typedef H h2 __attribute__((ext_vector_type(2)));
+  typedef float fl2 __attribute__((ext_vector_type(2)));
   uint2 v;
+  // two packed round-to-nearest-even conversions (v_cvt_pk_*_f32)
   __device__ inline void set(const f4& x) {
-    const H a = (H)x[0], b = (H)x[1], c = (H)x[2], d = (H)x[3];
-    v.x = (uint32_t)__builtin_bit_cast(unsigned short, a) |
-          ((uint32_t)__builtin_bit_cast(unsigned short, b) << 16);
-    v.y = (uint32_t)__builtin_bit_cast(unsigned short, c) |
-          ((uint32_t)__builtin_bit_cast(unsigned short, d) << 16);
+    v.x = __builtin_bit_cast(uint32_t, __builtin_convertvector((fl2{x[0], x[1]}), h2));
+    v.y = __builtin_bit_cast(uint32_t, __builtin_convertvector((fl2{x[2], x[3]}), h2));
   }
   __device__ inline f4 get() const {
     f4 r;
@@ -107,14 +107,15 @@ template <> struct Pack4<__bf16> : Pack16<__bf16> {};
 template <> struct Pack4<_Float16> : Pack16<_Float16> {};
 
 // tanh and its derivative from one exponential and one reciprocal:
-// with r = 1 / (1 + exp(2z)):  tanh z = 1 - 2r,  1 - tanh^2 z = 4 r (1 - r).
+// with r = 1 / (1 + exp(2z)):  tanh z = 1 - 2r,  1 - tanh^2 z = (1 - h)(1 + h).
 // Saturates cleanly (exp -> inf gives r = 0; exp -> 0 gives r = 1).  Absolute
 // error of a few 1e-7, below the FP32 rounding of the GEMM that feeds it.
 __device__ inline float tanh_and_grad(float z, float& d) {
-  const float e = __expf(2.f * z);
+  const float e = __builtin_amdgcn_exp2f(z * 2.885390081777927f);   // exp(2z)
   const float r = __builtin_amdgcn_rcpf(1.f + e);
-  d = 4.f * r * (1.f - r);
-  return 1.f - 2.f * r;
+  const float h = __builtin_fmaf(-2.f, r, 1.f);
+  d = __builtin_fmaf(-h, h, 1.f);
+  return h;
 }
 
 struct MlpArgs {
@@ -151,45 +152,84 @@ __device__ inline void map_block(int b, int K, int grp, int& k, int& tile) {
 // acc[rt][c] += W(units of tile jt0 + c, 0:KL) * act(walkers of rt, 0:KL)^T
 // (output tile: 16 units x 16 walkers; lane holds units 4(lane/16)+q of
 // walker lane%16)
-// Weight fragments are prefetched PD k-steps ahead through a ring of PD+1
-// register slots (the k loop is unrolled by PD+1 so slot indices are static).
+// Software pipeline: weight fragments (from L2/HBM) are loaded PD k-steps
+// ahead through a ring of PD+1 register slots; activation fragments (LDS)
+// either one k-step ahead through two slots (ADB) or next to their use.
+// Scheduling barriers pin "issue next loads -> MFMAs of this step", so the
+// compiler cannot sink a global load next to its first use and expose the
+// memory latency; without ADB they let LDS reads and ALU work move freely.
 #ifndef RID_PD_FP32
-#define RID_PD_FP32 1
+#define RID_PD_FP32 2
 #endif
 #ifndef RID_PD_16
 #define RID_PD_16 1
 #endif
+#ifndef RID_ADB_FP32
+#define RID_ADB_FP32 1
+#endif
+#ifndef RID_ADB_16
+#define RID_ADB_16 1
+#endif
+#ifndef RID_SCHED
+#define RID_SCHED 1
+#endif
+template <bool ALL>
+__device__ inline void sched_fence() {
+#if RID_SCHED
+  // mask: instruction classes allowed to cross (ALU, VALU, SALU, MFMA, DS,
+  // transcendental) -- everything except vector-memory loads and stores
+  __builtin_amdgcn_sched_barrier(ALL ? 0 : 0x078F);
+#endif
+}
+
 template <class P, int RT, int CT>
 __device__ inline void gemm_tiles(f4 (&acc)[RT][CT], const typename P::T* act,
                                   int as, const uint4* frag, int JT, int jt0,
                                   int n_kt, int lane) {
   constexpr int KF = P::KF;
-  constexpr int PD = sizeof(typename P::T) == 4 ? RID_PD_FP32 : RID_PD_16;
+  constexpr bool WIDE = sizeof(typename P::T) == 4;
+  constexpr int PD = WIDE ? RID_PD_FP32 : RID_PD_16;
+  constexpr bool ADB = WIDE ? RID_ADB_FP32 : RID_ADB_16;
   constexpr int S = PD + 1;
+  constexpr int U = (S % 2) ? 2 * S : S;      // unroll: static ring indices
   const int r = lane & 15, g = lane >> 4;
+  const typename P::T* arow = act + r * as + g * (KF / 4);
+  const uint4* fw = frag + (size_t)jt0 * 64;    // wave-uniform base
   uint4 w[S][CT];
+  uint4 a[ADB ? 2 : 1][RT];
 #pragma unroll
   for (int s = 0; s < PD; ++s)
     if (s < n_kt)
 #pragma unroll
-      for (int c = 0; c < CT; ++c) w[s][c] = frag[((size_t)s * JT + jt0 + c) * 64 + lane];
-  for (int kb = 0; kb < n_kt; kb += S) {
+      for (int c = 0; c < CT; ++c) w[s][c] = fw[((size_t)s * JT + c) * 64 + lane];
+  if (ADB && n_kt > 0)
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int kt = kb + s;
+    for (int rt = 0; rt < RT; ++rt)
+      a[0][rt] = *reinterpret_cast<const uint4*>(arow + rt * 16 * as);
+  for (int kb = 0; kb < n_kt; kb += U) {
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      const int kt = kb + i;
       if (kt < n_kt) {
         const int kp = kt + PD;
         if (kp < n_kt)
 #pragma unroll
           for (int c = 0; c < CT; ++c)
-            w[(s + PD) % S][c] = frag[((size_t)kp * JT + jt0 + c) * 64 + lane];
+            w[(i + PD) % S][c] = fw[((size_t)kp * JT + c) * 64 + lane];
+        if (ADB && kt + 1 < n_kt)
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt)
+            a[(i + 1) % 2][rt] =
+                *reinterpret_cast<const uint4*>(arow + rt * 16 * as + (kt + 1) * KF);
+        sched_fence<ADB>();
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-          const uint4 a = *reinterpret_cast<const uint4*>(
-              act + (rt * 16 + r) * as + kt * KF + g * (KF / 4));
+          const uint4 av = ADB ? a[i % 2][rt]
+                               : *reinterpret_cast<const uint4*>(arow + rt * 16 * as + kt * KF);
 #pragma unroll
-          for (int c = 0; c < CT; ++c) P::mma(w[s][c], a, acc[rt][c]);
+          for (int c = 0; c < CT; ++c) P::mma(w[i % S][c], av, acc[rt][c]);
         }
+        sched_fence<ADB>();
       }
     }
   }
@@ -206,7 +246,8 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   static_assert(CT >= 1 && CT * 16 * NW == NP, "width/wave split");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int k, tile;
   map_block(blockIdx.x, p.K, p.xcd_grp, k, tile);
   if (tile >= p.n_tiles) return;
@@ -552,8 +593,7 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
     grid = 8 * ((a.n_tiles + a.xcd_grp - 1) / a.xcd_grp);
   else
     grid = a.n_tiles * e.K;
-  ProfScope ps(kProfMlp, st);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), lds, st, a);
+  launch_timed(kProfMlp, kern, dim3(grid), dim3(NW * 64), (uint32_t)lds, st, a);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }
@@ -583,13 +623,17 @@ rid_status launch_16bit(const rid_ensemble_impl& e, const float* x, int B,
   return fail(RID_EUNSUPPORTED, "no kernel for this padded width");
 }
 
+#ifndef RID_F32_NW256
+#define RID_F32_NW256 8
+#endif
+
 rid_status dispatch(const rid_ensemble_impl& e, const float* x, int B, float* A_out,
                     float* g_out, const TorsionInput* t, hipStream_t st) {
   if (e.prec == RID_FP32) {
     switch (e.NP) {
       case 64:  return run_mlp<F32, 64, 1, 1, 6>(e, x, B, A_out, g_out, t, st);
       case 128: return run_mlp<F32, 128, 1, 2, 6>(e, x, B, A_out, g_out, t, st);
-      case 256: return run_mlp<F32, 256, 1, 4, 6>(e, x, B, A_out, g_out, t, st);
+      case 256: return run_mlp<F32, 256, 1, RID_F32_NW256, 6>(e, x, B, A_out, g_out, t, st);
       case 512: return run_mlp<F32, 512, 1, 8, 6>(e, x, B, A_out, g_out, t, st);
     }
     return fail(RID_EUNSUPPORTED, "no kernel for this padded width");

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <hip/hip_bf16.h>
 
 #include <cstddef>
@@ -45,8 +46,27 @@ enum ProfKind {
   kProfTrain = 5, kProfLabel = 6, kProfKinds = 7
 };
 bool prof_enabled();
+hipEvent_t prof_event();                 // from the pool, not yet recorded
 hipEvent_t prof_record(hipStream_t st);
 void prof_push(int kind, hipEvent_t a, hipEvent_t b);
+
+// Launch one kernel; when timing is on, its start and end timestamps are
+// taken by the dispatch itself (hipExtLaunchKernelGGL events), so the
+// measured time is the kernel's own and no marker packets sit between
+// launches.
+template <typename K, typename... Args>
+inline void launch_timed(int kind, K kern, dim3 grid, dim3 block, uint32_t lds,
+                         hipStream_t st, Args... args) {
+  if (prof_enabled()) {
+    hipEvent_t a = prof_event(), b = prof_event();
+    if (a && b) {
+      hipExtLaunchKernelGGL(kern, grid, block, lds, st, a, b, 0, args...);
+      prof_push(kind, a, b);
+      return;
+    }
+  }
+  hipLaunchKernelGGL(kern, grid, block, lds, st, args...);
+}
 struct ProfScope {
   int kind;
   hipStream_t st;
