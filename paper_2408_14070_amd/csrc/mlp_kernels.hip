@@ -131,7 +131,7 @@ struct MlpArgs {
   float* A_out;        // [K][B]
   float* g_out;        // [K][B][n]
   // LDS layout (byte offsets; activation buffer 0 starts at 0)
-  unsigned off_u0, off_red, off_xs, off_ph0;
+  unsigned off_u0, off_red, off_xs, off_ph0, off_wo;
   int rc;              // walkers per torsion-gather pass (bias path)
   // torsion input (bias path)
   SysView sv;
@@ -182,26 +182,77 @@ __device__ inline void sched_fence() {
 #endif
 }
 
-template <class P, int RT, int CT>
-__device__ inline void gemm_tiles(f4 (&acc)[RT][CT], const typename P::T* act,
-                                  int as, const uint4* frag, int JT, int jt0,
-                                  int n_kt, int lane) {
+// Activation rows are padded by this many bytes (bank spread of the
+// row-strided LDS accesses).
+#ifndef RID_ACT_PAD_BYTES
+#define RID_ACT_PAD_BYTES 16
+#endif
+
+// Hidden-layer GEMMs: passes over the contraction and weight pipeline depth
+// (PD+1 must divide passes * k-steps: 1 or 3).
+#ifndef RID_NPASS_FP32
+#define RID_NPASS_FP32 1
+#endif
+#ifndef RID_NPASS_16
+#define RID_NPASS_16 1
+#endif
+#ifndef RID_PDH_FP32
+#define RID_PDH_FP32 3
+#endif
+#ifndef RID_PDH_16
+#define RID_PDH_16 1
+#endif
+
+// Where a wave's weight fragments come from: a buffer resource over one
+// member's fragments (range-checked by the hardware), the byte offset of
+// k-chunk 0 of the wave's first unit tile, and the bytes per k-chunk.  A
+// load is one buffer_load_dwordx4 with the lane's 16 bytes as the only
+// vector offset; the k-chunk goes into the scalar offset and the tile into
+// the instruction's immediate, so no vector registers hold addresses.
+struct WSrc {
+  __amdgpu_buffer_rsrc_t r;
+  int soff, kstride;
+  __device__ inline uint4 ld(int kk, int c, int lane) const {
+    return __builtin_bit_cast(
+        uint4, __builtin_amdgcn_raw_buffer_load_b128(r, lane * 16 + c * kFragBytes,
+                                                     soff + kk * kstride, 0));
+  }
+  __device__ inline WSrc tiles_from(int c) const {
+    return WSrc{r, soff + c * kFragBytes, kstride};
+  }
+};
+
+// Weight ring: slot kt % (PD+1) holds the fragments of k-step kt.
+template <int PD, int CT>
+struct WRing {
+  uint4 w[PD + 1][CT];
+};
+
+// Issue the loads of k-steps 0..PD-1 of a layer into the ring.
+template <int PD, int CT>
+__device__ inline void ring_preload(WRing<PD, CT>& wr, const WSrc& src, int n_kt, int lane) {
+#pragma unroll
+  for (int s = 0; s < PD; ++s)
+    if (s < n_kt)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) wr.w[s][c] = src.ld(s, c, lane);
+}
+
+// The k-loop of a GEMM with a run-time contraction length (first layer,
+// input-gradient GEMM).  On entry the ring holds the first PD k-steps; the
+// following ones are issued PD steps ahead.
+template <class P, int RT, int CT, int PD>
+__device__ inline void gemm_run(f4 (&acc)[RT][CT], WRing<PD, CT>& wr,
+                                const typename P::T* act, int as, const WSrc& src, int n_kt,
+                                int lane) {
   constexpr int KF = P::KF;
   constexpr bool WIDE = sizeof(typename P::T) == 4;
-  constexpr int PD = WIDE ? RID_PD_FP32 : RID_PD_16;
   constexpr bool ADB = WIDE ? RID_ADB_FP32 : RID_ADB_16;
   constexpr int S = PD + 1;
   constexpr int U = (S % 2) ? 2 * S : S;      // unroll: static ring indices
   const int r = lane & 15, g = lane >> 4;
   const typename P::T* arow = act + r * as + g * (KF / 4);
-  const uint4* fw = frag + (size_t)jt0 * 64;    // wave-uniform base
-  uint4 w[S][CT];
   uint4 a[ADB ? 2 : 1][RT];
-#pragma unroll
-  for (int s = 0; s < PD; ++s)
-    if (s < n_kt)
-#pragma unroll
-      for (int c = 0; c < CT; ++c) w[s][c] = fw[((size_t)s * JT + c) * 64 + lane];
   if (ADB && n_kt > 0)
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -215,7 +266,7 @@ __device__ inline void gemm_tiles(f4 (&acc)[RT][CT], const typename P::T* act,
         if (kp < n_kt)
 #pragma unroll
           for (int c = 0; c < CT; ++c)
-            w[(i + PD) % S][c] = fw[((size_t)kp * JT + c) * 64 + lane];
+            wr.w[(i + PD) % S][c] = src.ld(kp, c, lane);
         if (ADB && kt + 1 < n_kt)
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt)
@@ -227,11 +278,68 @@ __device__ inline void gemm_tiles(f4 (&acc)[RT][CT], const typename P::T* act,
           const uint4 av = ADB ? a[i % 2][rt]
                                : *reinterpret_cast<const uint4*>(arow + rt * 16 * as + kt * KF);
 #pragma unroll
-          for (int c = 0; c < CT; ++c) P::mma(w[i % S][c], av, acc[rt][c]);
+          for (int c = 0; c < CT; ++c) P::mma(wr.w[i % S][c], av, acc[rt][c]);
         }
         sched_fence<ADB>();
       }
     }
+  }
+}
+
+template <class P, int RT, int CT, int PD>
+__device__ inline void gemm_tiles(f4 (&acc)[RT][CT], const typename P::T* act, int as,
+                                  const WSrc& src, int n_kt, int lane) {
+  WRing<PD, CT> wr;
+  ring_preload<PD, CT>(wr, src, n_kt, lane);
+  gemm_run<P, RT, CT, PD>(acc, wr, act, as, src, n_kt, lane);
+}
+
+// Hidden-layer GEMM (contraction length NK k-steps, known at compile time),
+// in NPASS passes over the contraction, each computing CT/NPASS of the
+// wave's unit tiles (two passes halve the weight registers per k-step at
+// the price of reading the activations from LDS once per pass).  The
+// weight ring streams all passes as one sequence of NPASS*NK steps, and
+// after the last MFMA it already issues the next layer's first PD steps
+// (weights do not depend on activations), so a layer starts with its
+// weights in flight through the previous epilogue and barrier.  Slot
+// numbering stays step % S across layers because S divides NPASS*NK.
+template <class P, int RT, int CT, int NPASS, int PD, int NK>
+__device__ inline void gemm_hidden(f4 (&acc)[RT][CT], WRing<PD, CT / NPASS>& wr,
+                                   const typename P::T* act, int as, const WSrc& src,
+                                   bool has_next, const WSrc& next, int lane) {
+  constexpr int KF = P::KF;
+  constexpr int S = PD + 1;
+  constexpr int CH = CT / NPASS;
+  constexpr int NV = NPASS * NK;
+  static_assert(CH * NPASS == CT && NV % S == 0, "ring slots must line up across layers");
+  const int r = lane & 15, g = lane >> 4;
+  const typename P::T* arow = act + r * as + g * (KF / 4);
+  uint4 a[2][RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) a[0][rt] = *reinterpret_cast<const uint4*>(arow + rt * 16 * as);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int vp = v + PD;                     // weight step issued now
+    if (vp < NV) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) wr.w[vp % S][c] = src.ld(vp % NK, (vp / NK) * CH + c, lane);
+    } else if (has_next) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) wr.w[vp % S][c] = next.ld(vp - NV, c, lane);
+    }
+    if (v + 1 < NV) {
+      const int kn = (v + 1) % NK;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        a[(v + 1) % 2][rt] = *reinterpret_cast<const uint4*>(arow + rt * 16 * as + kn * KF);
+    }
+    sched_fence<true>();
+    const int cb = (v / NK) * CH;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int c = 0; c < CH; ++c) P::mma(wr.w[v % S][c], a[v % 2][rt], acc[rt][cb + c]);
+    sched_fence<true>();
   }
 }
 
@@ -254,17 +362,44 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   const int row0 = tile * R;
   const int n = p.n, L = p.L, XP = p.XP, X2 = 2 * p.n;
   const int AW = NP > XP ? NP : XP;           // activation tile width
-  const int AS = AW + 16 / (int)sizeof(T);    // row stride (+16 bytes)
+  const int AS = AW + RID_ACT_PAD_BYTES / (int)sizeof(T);    // row stride (+16 bytes)
   const int BUF = R * AS;                     // elements per ping-pong buffer
   T* act = reinterpret_cast<T*>(smem);
   float* u0 = reinterpret_cast<float*>(smem + p.off_u0);
   const int US = XP + 4;
   float* red = reinterpret_cast<float*>(smem + p.off_red);   // [NW][R]
   float* xs = reinterpret_cast<float*>(smem + p.off_xs);     // [R][2n] FP32 cos|sin
+  float* wos = reinterpret_cast<float*>(smem + p.off_wo);    // [NP] output weights
 
   const unsigned char* fbase = p.frag + (size_t)k * p.frag_model_bytes;
   const float* bias = p.bias + (size_t)k * L * NP;
   const float* wo = p.wo + (size_t)k * NP;
+
+  // first forward layer's weights and biases go in flight before the input
+  // tile is built
+  constexpr int PD = sizeof(T) == 4 ? RID_PD_FP32 : RID_PD_16;
+  constexpr bool WIDE = sizeof(T) == 4;
+  constexpr int NPASS = WIDE ? RID_NPASS_FP32 : RID_NPASS_16;
+  constexpr int CH = CT / NPASS;     // unit tiles per pass of a hidden-layer GEMM
+  constexpr int NK = NP / KF;        // k-steps of a hidden-layer GEMM
+  constexpr int PDH = WIDE ? RID_PDH_FP32 : RID_PDH_16;   // its weight pipeline depth
+  const int jt0 = wave * CT;
+  const int uq = 4 * (lane >> 4);    // first of this lane's 4 units in a tile
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<unsigned char*>(fbase), (short)0, (int)p.frag_model_bytes, 0x00020000);
+  // fragments of one layer (byte offset off) for this wave's unit tiles
+  auto wsrc = [&](unsigned off) {
+    return WSrc{rsrc, (int)off + jt0 * kFragBytes, JT * kFragBytes};
+  };
+  WRing<PD, CT> wr;                  // first layer
+  WRing<PDH, CH> wh;                 // hidden layers (passes of CH tiles)
+  ring_preload<PD, CT>(wr, wsrc(p.fwd_off[0]), XP / KF, lane);
+  f4 bnext[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c)
+    bnext[c] = *reinterpret_cast<const f4*>(bias + (jt0 + c) * 16 + uq);
+
+  for (int i = threadIdx.x; i < NP; i += NW * 64) wos[i] = wo[i];   // published below
 
   // ---------------- input tile: x = [cos s | sin s] -> buffer 0 ----------------
   if constexpr (FROM_POS) {
@@ -303,109 +438,194 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       act[i * AS + c] = P::from_float(0.f);
     }
   } else {
-    for (int e = threadIdx.x; e < R * XP; e += NW * 64) {
-      const int i = e / XP, c = e - i * XP;
-      const int row = row0 + i;
-      const float v = (row < p.B && c < X2) ? p.x[(size_t)row * X2 + c] : 0.f;
-      act[i * AS + c] = P::from_float(v);
-      if (c < X2) xs[i * X2 + c] = v;
+    // the tile's rows are one contiguous run of R*X2 floats (16-byte
+    // aligned: R is a multiple of 16); 4 float4 loads per thread in flight
+    // per pass, then the scatter into the padded activation rows
+    constexpr int NT = NW * 64;
+    const long long base = (long long)row0 * X2;
+    const long long lim = (long long)p.B * X2;
+    const int nq = R * X2 / 4;
+    for (int q0 = threadIdx.x; q0 < nq; q0 += 4 * NT) {
+      f4 v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = q0 + j * NT;
+        const long long g0 = base + 4LL * q;
+        v[j] = f4{0.f, 0.f, 0.f, 0.f};
+        if (q < nq) {
+          if (g0 + 4 <= lim) {
+            v[j] = *reinterpret_cast<const f4*>(p.x + g0);
+          } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (g0 + t < lim) v[j][t] = p.x[g0 + t];
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = q0 + j * NT;
+        if (q < nq) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int f = 4 * q + t, i = f / X2, c = f - i * X2;
+            act[i * AS + c] = P::from_float(v[j][t]);
+            xs[f] = v[j][t];
+          }
+        }
+      }
+    }
+    for (int e = threadIdx.x; e < R * (XP - X2); e += NW * 64) {
+      const int i = e / (XP - X2), c = X2 + e - i * (XP - X2);
+      act[i * AS + c] = P::from_float(0.f);
     }
   }
   __syncthreads();
 
-  const int jt0 = wave * CT;
   const int wl = lane & 15;          // walker within a 16-walker tile
-  const int uq = 4 * (lane >> 4);    // first of this lane's 4 units in a tile
-  SP st[LM][RT][CT];                 // tanh' of every hidden layer
-  f4 acc[RT][CT];
+  SP st[LM - 1][RT][CT];             // tanh' of hidden layers 1..L-1
   int cur = 0;
 
   // ---------------- forward: h_l = tanh(W_l h_{l-1} + b_l) ----------------
+  // tile epilogues: tanh and its derivative; a layer before the last stores
+  // h_l into the other buffer and stashes tanh'; the last layer stores
+  // v_L = w_o * tanh' and accumulates the lane's part of A = w_o . h_L
+  float apart[RT];
 #pragma unroll
-  for (int l = 0; l < LM; ++l) {
-    if (l < L) {
+  for (int rt = 0; rt < RT; ++rt) apart[rt] = 0.f;
+  auto mid_tile = [&](int l, int rt, int c, const f4& z, T* out) {
+    f4 h, d;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float dq;
+      h[q] = tanh_and_grad(z[q], dq);
+      d[q] = dq;
+    }
+    SP o;
+    o.set(h);
+    o.store(out + (rt * 16 + wl) * AS + (jt0 + c) * 16 + uq);
+    st[l][rt][c].set(d);
+  };
+  auto last_tile = [&](int rt, int c, const f4& z, T* out) {
+    const int u = (jt0 + c) * 16 + uq;
+    const f4 w4 = *reinterpret_cast<const f4*>(wos + u);
+    f4 h, d;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float dq;
+      h[q] = tanh_and_grad(z[q], dq);
+      d[q] = dq;
+    }
+    apart[rt] += w4[0] * h[0] + w4[1] * h[1] + w4[2] * h[2] + w4[3] * h[3];
+    SP o;
+    o.set(w4 * d);
+    o.store(out + (rt * 16 + wl) * AS + u);
+  };
+  // the GEMM after forward layer l: forward layer l+1, or the first backward
+  auto next_after_fwd = [&](int l) {
+    return wsrc(l + 1 < L ? p.fwd_off[l + 1] : p.bwd_off[L > 1 ? L - 1 : 0]);
+  };
+  auto load_bias = [&](int l) {
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+      bnext[c] = *reinterpret_cast<const f4*>(bias + l * NP + (jt0 + c) * 16 + uq);
+  };
+
+  {  // layer 1 (input width XP): one pass over all CT tiles
+    T* out = act + BUF;
+    f4 acc[RT][CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt][c] = bnext[c];
+    gemm_run<P, RT, CT, PD>(acc, wr, act, AS, wsrc(p.fwd_off[0]), XP / KF, lane);
+    if (L > 1) {
+      ring_preload<PDH, CH>(wh, next_after_fwd(0), NK, lane);
+      load_bias(1);
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) mid_tile(0, rt, c, acc[rt][c], out);
+    } else {
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) last_tile(rt, c, acc[rt][c], out);
+    }
+    cur = 1;
+    __syncthreads();
+  }
+  // hidden layers before the last
+#pragma unroll
+  for (int l = 1; l < LM - 1; ++l) {
+    if (l < L - 1) {
       const T* in = act + cur * BUF;
       T* out = act + (cur ^ 1) * BUF;
+      f4 acc[RT][CT];
 #pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const f4 b4 = *reinterpret_cast<const f4*>(bias + l * NP + (jt0 + c) * 16 + uq);
+      for (int c = 0; c < CT; ++c)
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt][c] = b4;
-      }
-      const uint4* fr = reinterpret_cast<const uint4*>(fbase + p.fwd_off[l]);
-      gemm_tiles<P, RT, CT>(acc, in, AS, fr, JT, jt0, (l == 0 ? XP : NP) / KF, lane);
-      const bool last = (l == L - 1);
-      float apart[RT];
+        for (int rt = 0; rt < RT; ++rt) acc[rt][c] = bnext[c];
+      gemm_hidden<P, RT, CT, NPASS, PDH, NK>(acc, wh, in, AS, wsrc(p.fwd_off[l]), true,
+                                             next_after_fwd(l), lane);
+      load_bias(l + 1);
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) apart[rt] = 0.f;
+      for (int c = 0; c < CT; ++c)
 #pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int u = (jt0 + c) * 16 + uq;
-        f4 w4 = f4{0.f, 0.f, 0.f, 0.f};
-        if (last) w4 = *reinterpret_cast<const f4*>(wo + u);
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          f4 h, d;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            float dq;
-            h[q] = tanh_and_grad(acc[rt][c][q], dq);
-            d[q] = dq;
-          }
-          SP o;
-          if (last) {
-            apart[rt] += w4[0] * h[0] + w4[1] * h[1] + w4[2] * h[2] + w4[3] * h[3];
-            o.set(w4 * d);                                  // v_L
-          } else {
-            o.set(h);
-          }
-          o.store(out + (rt * 16 + wl) * AS + u);
-          st[l][rt][c].set(d);
-        }
-      }
-      if (last) {
-        // A = wo . h_L + bo: reduce over the 4 unit groups, then the waves
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          float v = apart[rt];
-          v += __shfl_xor(v, 16);
-          v += __shfl_xor(v, 32);
-          if (lane < 16) red[wave * R + rt * 16 + wl] = v;
-        }
-      }
+        for (int rt = 0; rt < RT; ++rt) mid_tile(l, rt, c, acc[rt][c], out);
       cur ^= 1;
       __syncthreads();
     }
   }
-  // A output
-  for (int i = threadIdx.x; i < R; i += NW * 64) {
-    float a = p.bo[k];
-    for (int w = 0; w < NW; ++w) a += red[w * R + i];
-    if (row0 + i < p.B) p.A_out[(size_t)k * p.B + row0 + i] = a;
+  if (L > 1) {  // the last hidden layer (index L-1)
+    const T* in = act + cur * BUF;
+    T* out = act + (cur ^ 1) * BUF;
+    f4 acc[RT][CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt][c] = bnext[c];
+    gemm_hidden<P, RT, CT, NPASS, PDH, NK>(acc, wh, in, AS, wsrc(p.fwd_off[L - 1]), true,
+                                           wsrc(p.bwd_off[L - 1]), lane);
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) last_tile(rt, c, acc[rt][c], out);
+    cur ^= 1;
+    __syncthreads();
+  }
+  // A = w_o . h_L + b_o: the lanes' partials reduced over the 4 unit groups,
+  // then (after the last barrier) over the waves
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    float v = apart[rt];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    if (lane < 16) red[wave * R + rt * 16 + wl] = v;
   }
 
   // ------------- reverse sweep: v_{l-1} = (W_l^T v_l) * tanh'_{l-1} -------------
+  auto bwd_tile = [&](int l, int rt, int c, const f4& y, T* out) {
+    SP o;
+    o.set(y * st[l - 1][rt][c].get());
+    o.store(out + (rt * 16 + wl) * AS + (jt0 + c) * 16 + uq);
+  };
 #pragma unroll
   for (int l = LM - 1; l >= 1; --l) {
     if (l < L) {
       const T* in = act + cur * BUF;
       T* out = act + (cur ^ 1) * BUF;
+      f4 acc[RT][CT];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[rt][c] = f4{0.f, 0.f, 0.f, 0.f};
-      const uint4* fr = reinterpret_cast<const uint4*>(fbase + p.bwd_off[l]);
-      gemm_tiles<P, RT, CT>(acc, in, AS, fr, JT, jt0, NP / KF, lane);
+      gemm_hidden<P, RT, CT, NPASS, PDH, NK>(acc, wh, in, AS, wsrc(p.bwd_off[l]), l >= 2,
+                                             wsrc(p.bwd_off[l >= 2 ? l - 1 : l]), lane);
 #pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int u = (jt0 + c) * 16 + uq;
+      for (int c = 0; c < CT; ++c)
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          SP o;
-          o.set(acc[rt][c] * st[l - 1][rt][c].get());
-          o.store(out + (rt * 16 + wl) * AS + u);
-        }
-      }
+        for (int rt = 0; rt < RT; ++rt) bwd_tile(l, rt, c, acc[rt][c], out);
       cur ^= 1;
       __syncthreads();
     }
@@ -414,19 +634,26 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   // v_1 sits in buffer 1 (2L-1 buffer flips), so u0 may alias buffer 0.
   {
     const T* in = act + cur * BUF;
-    const uint4* fr = reinterpret_cast<const uint4*>(fbase + p.bwd_off[0]);
     const int JT0 = XP / 16;
     for (int t = wave; t < JT0; t += NW) {
       f4 a1[RT][1];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) a1[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
-      gemm_tiles<P, RT, 1>(a1, in, AS, fr, JT0, t, NP / KF, lane);
+      gemm_tiles<P, RT, 1, 4>(a1, in, AS,
+                              WSrc{rsrc, (int)p.bwd_off[0] + t * kFragBytes, JT0 * kFragBytes},
+                              NP / KF, lane);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
         *reinterpret_cast<f4*>(u0 + (rt * 16 + wl) * US + t * 16 + uq) = a1[rt][0];
     }
   }
   __syncthreads();
+  // A = sum of the waves' partial dot products + b_o
+  for (int i = threadIdx.x; i < R; i += NW * 64) {
+    float a = p.bo[k];
+    for (int w = 0; w < NW; ++w) a += red[w * R + i];
+    if (row0 + i < p.B) p.A_out[(size_t)k * p.B + row0 + i] = a;
+  }
   // chain to the angles: g_i = -sin s_i u0[i] + cos s_i u0[n+i]
   for (int e = threadIdx.x; e < R * n; e += NW * 64) {
     const int i = e / n, c = e - i * n;
@@ -514,7 +741,7 @@ inline unsigned align16(size_t v) { return (unsigned)((v + 15) / 16 * 16); }
 
 // LDS layout of one instantiation; returns the total bytes.
 size_t mlp_layout(int R, int NW, int AS, size_t tsize, int XP, int n, int U,
-                  bool from_pos, MlpArgs& a) {
+                  bool from_pos, int NPw, MlpArgs& a) {
   const size_t buf = (size_t)R * AS * tsize;
   size_t off = 2 * buf;
   const size_t u0_bytes = (size_t)R * (XP + 4) * 4;
@@ -528,6 +755,8 @@ size_t mlp_layout(int R, int NW, int AS, size_t tsize, int XP, int n, int U,
   off = a.off_red + (size_t)NW * R * 4;
   a.off_xs = align16(off);
   off = a.off_xs + (size_t)R * 2 * n * 4;
+  a.off_wo = align16(off);              // output weights w_o [NP]
+  off = a.off_wo + (size_t)NPw * 4;
   if (from_pos) {
     // gather scratch in buffer 1 (free before layer 1), in passes of rc
     // walkers; a shape with no room for one walker reports 0 passes
@@ -543,9 +772,9 @@ size_t lds_bytes(const rid_ensemble_impl& e, const TorsionInput* tin) {
   using T = typename P::T;
   MlpArgs a{};
   const int AW = NP > e.XP ? NP : e.XP;
-  const int AS = AW + 16 / (int)sizeof(T);
+  const int AS = AW + RID_ACT_PAD_BYTES / (int)sizeof(T);
   return mlp_layout(16 * RT, NW, AS, sizeof(T), e.XP, e.n_cv,
-                    tin ? tin->sys->n_uniq : 0, tin != nullptr, a);
+                    tin ? tin->sys->n_uniq : 0, tin != nullptr, NP, a);
 }
 
 template <class P, int NP, int RT, int NW, int LM>
@@ -557,10 +786,10 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
   using T = typename P::T;
   const bool from_pos = tin != nullptr;
   const int AW = NP > e.XP ? NP : e.XP;
-  const int AS = AW + 16 / (int)sizeof(T);
+  const int AS = AW + RID_ACT_PAD_BYTES / (int)sizeof(T);
   MlpArgs a{};
   const size_t lds = mlp_layout(R, NW, AS, sizeof(T), e.XP, e.n_cv,
-                                from_pos ? tin->sys->n_uniq : 0, from_pos, a);
+                                from_pos ? tin->sys->n_uniq : 0, from_pos, NP, a);
   if (lds > 160 * 1024)
     return fail(RID_EUNSUPPORTED, "shape too large for the MLP kernel's LDS");
   if (from_pos && a.rc < 1)
@@ -611,6 +840,10 @@ rid_status run_16bit(const rid_ensemble_impl& e, const float* x, int B, float* A
   return run_mlp<P, NP, 2, NW, 6>(e, x, B, A_out, g_out, t, st);
 }
 
+#ifndef RID_16_NW512
+#define RID_16_NW512 8
+#endif
+
 template <class P>
 rid_status launch_16bit(const rid_ensemble_impl& e, const float* x, int B,
                         float* A_out, float* g_out, const TorsionInput* t, hipStream_t st) {
@@ -618,7 +851,7 @@ rid_status launch_16bit(const rid_ensemble_impl& e, const float* x, int B,
     case 64:  return run_16bit<P, 64, 1>(e, x, B, A_out, g_out, t, st);
     case 128: return run_16bit<P, 128, 2>(e, x, B, A_out, g_out, t, st);
     case 256: return run_16bit<P, 256, 4>(e, x, B, A_out, g_out, t, st);
-    case 512: return run_16bit<P, 512, 8>(e, x, B, A_out, g_out, t, st);
+    case 512: return run_16bit<P, 512, RID_16_NW512>(e, x, B, A_out, g_out, t, st);
   }
   return fail(RID_EUNSUPPORTED, "no kernel for this padded width");
 }
