@@ -104,14 +104,33 @@ template <class H> struct Pack16 {
   __device__ inline void store(H* dst) const { *reinterpret_cast<uint2*>(dst) = v; }
 };
 template <> struct Pack4<__bf16> : Pack16<__bf16> {};
+
+// two consecutive elements of type T (one 4- or 8-byte LDS store)
+template <class T> struct Pack2 {
+  typedef T t2 __attribute__((ext_vector_type(2)));
+  typedef float fl2 __attribute__((ext_vector_type(2)));
+  __device__ static inline void store(T* dst, float a, float b) {
+    *reinterpret_cast<t2*>(dst) = __builtin_convertvector((fl2{a, b}), t2);
+  }
+};
+template <> struct Pack2<float> {
+  __device__ static inline void store(float* dst, float a, float b) {
+    *reinterpret_cast<float2*>(dst) = make_float2(a, b);
+  }
+};
 template <> struct Pack4<_Float16> : Pack16<_Float16> {};
 
-// tanh and its derivative from one exponential and one reciprocal:
-// with r = 1 / (1 + exp(2z)):  tanh z = 1 - 2r,  1 - tanh^2 z = (1 - h)(1 + h).
-// Saturates cleanly (exp -> inf gives r = 0; exp -> 0 gives r = 1).  Absolute
-// error of a few 1e-7, below the FP32 rounding of the GEMM that feeds it.
-__device__ inline float tanh_and_grad(float z, float& d) {
-  const float e = __builtin_amdgcn_exp2f(z * 2.885390081777927f);   // exp(2z)
+// Forward weights and biases are stored multiplied by 2/ln 2, so a forward
+// GEMM yields y = 2 z / ln 2 and exp(2z) = 2^y takes no multiply.
+constexpr float kTanhPrescale = 2.8853900817779268f;
+
+// tanh and its derivative from one exponential and one reciprocal, given the
+// pre-scaled pre-activation y: with r = 1 / (1 + 2^y):  tanh z = 1 - 2r,
+// 1 - tanh^2 z = (1 - h)(1 + h).  Saturates cleanly (2^y -> inf gives r = 0;
+// 2^y -> 0 gives r = 1).  Absolute error of a few 1e-7, below the FP32
+// rounding of the GEMM that feeds it.
+__device__ inline float tanh_and_grad(float y, float& d) {
+  const float e = __builtin_amdgcn_exp2f(y);
   const float r = __builtin_amdgcn_rcpf(1.f + e);
   const float h = __builtin_fmaf(-2.f, r, 1.f);
   d = __builtin_fmaf(-h, h, 1.f);
@@ -382,7 +401,8 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   constexpr int NPASS = WIDE ? RID_NPASS_FP32 : RID_NPASS_16;
   constexpr int CH = CT / NPASS;     // unit tiles per pass of a hidden-layer GEMM
   constexpr int NK = NP / KF;        // k-steps of a hidden-layer GEMM
-  constexpr int PDH = WIDE ? RID_PDH_FP32 : RID_PDH_16;   // its weight pipeline depth
+  constexpr int PDW = WIDE ? RID_PDH_FP32 : RID_PDH_16;
+  constexpr int PDH = (NPASS * NK) % (PDW + 1) == 0 ? PDW : 1;   // its weight pipeline depth
   const int jt0 = wave * CT;
   const int uq = 4 * (lane >> 4);    // first of this lane's 4 units in a tile
   const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
@@ -404,80 +424,66 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   // ---------------- input tile: x = [cos s | sin s] -> buffer 0 ----------------
   if constexpr (FROM_POS) {
     // torsions of the tile's walkers, p.rc walkers per pass (the gather
-    // scratch lives in buffer 1): one gather pass with every load in
-    // flight, then one thread per (walker, torsion)
+    // scratch lives in buffer 1).  Gather: a lane owns coordinates
+    // j = lane + 64m of the unique-atom list and copies them for the walkers
+    // of its wave (walkers to the waves in turn); then a lane per torsion.
     float* sp = reinterpret_cast<float*>(smem + p.off_ph0);   // [rc][U][3]
     const int U3 = 3 * p.sv.U;
     for (int c0 = 0; c0 < R; c0 += p.rc) {
       const int rc = R - c0 < p.rc ? R - c0 : p.rc;
-      for (int e = threadIdx.x; e < rc * U3; e += NW * 64) {
-        const int i = e / U3, j = e - i * U3;
-        const int row = row0 + c0 + i;
+      for (int j = lane; j < U3; j += 64) {
         const int u = j / 3;
-        sp[e] = row < p.B
-                    ? p.pos[((size_t)row * p.sv.n_atoms + p.sv.uniq[u]) * 3 + (j - 3 * u)]
-                    : 0.f;
-      }
-      __syncthreads();
-      for (int e = threadIdx.x; e < rc * n; e += NW * 64) {
-        const int il = e / n, c = e - il * n, i = c0 + il;
-        float cs = 0.f, sn = 0.f;
-        if (row0 + i < p.B) {
-          const Torsion t = torsion(sp + il * U3, p.sv.lq + 4 * c);
-          torsion_cos_sin(t, cs, sn);
+        const size_t a = (size_t)p.sv.uniq[u] * 3 + (j - 3 * u);
+#pragma unroll 4
+        for (int il = wave; il < rc; il += NW) {
+          const int row = row0 + c0 + il;
+          sp[il * U3 + j] = row < p.B ? p.pos[(size_t)row * p.sv.n_atoms * 3 + a] : 0.f;
         }
-        xs[i * X2 + c] = cs;
-        xs[i * X2 + n + c] = sn;
-        act[i * AS + c] = P::from_float(cs);
-        act[i * AS + n + c] = P::from_float(sn);
+      }
+      __syncthreads();
+      for (int il = wave; il < rc; il += NW) {
+        const int i = c0 + il;
+        for (int c = lane; c < n; c += 64) {
+          float cs = 0.f, sn = 0.f;
+          if (row0 + i < p.B) {
+            const Torsion t = torsion(sp + il * U3, p.sv.lq + 4 * c);
+            torsion_cos_sin(t, cs, sn);
+          }
+          xs[i * X2 + c] = cs;
+          xs[i * X2 + n + c] = sn;
+          act[i * AS + c] = P::from_float(cs);
+          act[i * AS + n + c] = P::from_float(sn);
+        }
       }
       __syncthreads();
     }
-    for (int e = threadIdx.x; e < R * (XP - X2); e += NW * 64) {
-      const int i = e / (XP - X2), c = X2 + e - i * (XP - X2);
-      act[i * AS + c] = P::from_float(0.f);
-    }
+    for (int i = wave; i < R; i += NW)
+      for (int c = X2 + lane; c < XP; c += 64) act[i * AS + c] = P::from_float(0.f);
   } else {
-    // the tile's rows are one contiguous run of R*X2 floats (16-byte
-    // aligned: R is a multiple of 16); 4 float4 loads per thread in flight
-    // per pass, then the scatter into the padded activation rows
-    constexpr int NT = NW * 64;
-    const long long base = (long long)row0 * X2;
-    const long long lim = (long long)p.B * X2;
-    const int nq = R * X2 / 4;
-    for (int q0 = threadIdx.x; q0 < nq; q0 += 4 * NT) {
-      f4 v[4];
+    // rows of the tile go to the waves in turn; a wave's lanes cover the row
+    // in float2 columns (X2 is even), padding columns [X2, XP) get zeros.
+    // All of a wave's loads are issued before any is used.
+    constexpr int RW = R / NW;                // rows per wave (R = 16 RT)
+    static_assert(RW * NW == R, "rows per wave");
+    const int h2 = X2 / 2, hp = XP / 2;
+    for (int cb = 0; cb < hp; cb += 64) {
+      const int col = cb + lane;              // float2 column
+      float2 v[RW];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int q = q0 + j * NT;
-        const long long g0 = base + 4LL * q;
-        v[j] = f4{0.f, 0.f, 0.f, 0.f};
-        if (q < nq) {
-          if (g0 + 4 <= lim) {
-            v[j] = *reinterpret_cast<const f4*>(p.x + g0);
-          } else {
+      for (int j = 0; j < RW; ++j) {
+        const int row = row0 + wave * RW + j;
+        v[j] = (col < h2 && row < p.B)
+                   ? *reinterpret_cast<const float2*>(p.x + (size_t)row * X2 + 2 * col)
+                   : make_float2(0.f, 0.f);
+      }
+      if (col < hp) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-              if (g0 + t < lim) v[j][t] = p.x[g0 + t];
-          }
+        for (int j = 0; j < RW; ++j) {
+          const int i = wave * RW + j;
+          Pack2<T>::store(act + i * AS + 2 * col, v[j].x, v[j].y);
+          if (col < h2) *reinterpret_cast<float2*>(xs + i * X2 + 2 * col) = v[j];
         }
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int q = q0 + j * NT;
-        if (q < nq) {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int f = 4 * q + t, i = f / X2, c = f - i * X2;
-            act[i * AS + c] = P::from_float(v[j][t]);
-            xs[f] = v[j][t];
-          }
-        }
-      }
-    }
-    for (int e = threadIdx.x; e < R * (XP - X2); e += NW * 64) {
-      const int i = e / (XP - X2), c = X2 + e - i * (XP - X2);
-      act[i * AS + c] = P::from_float(0.f);
     }
   }
   __syncthreads();
@@ -639,7 +645,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       f4 a1[RT][1];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) a1[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
-      gemm_tiles<P, RT, 1, 4>(a1, in, AS,
+      gemm_tiles<P, RT, 1, 7>(a1, in, AS,
                               WSrc{rsrc, (int)p.bwd_off[0] + t * kFragBytes, JT0 * kFragBytes},
                               NP / KF, lane);
 #pragma unroll
@@ -707,7 +713,8 @@ __global__ void pack_layer_kernel(const float* master, size_t per_model, int K,
       // backward: (unit col = in, contraction kk = out)
       const int o = dir == 0 ? col : kk;
       const int i = dir == 0 ? kk : col;
-      const float v = (o < pl.out && i < pl.in) ? W[(size_t)o * pl.in + i] : 0.f;
+      float v = (o < pl.out && i < pl.in) ? W[(size_t)o * pl.in + i] : 0.f;
+      if (dir == 0) v *= kTanhPrescale;
       out[e] = P::from_float(v);
     }
     unsigned char* dst = frag + (size_t)k * frag_model_bytes +
@@ -731,7 +738,8 @@ __global__ void pack_vec_kernel(const float* master, size_t per_model, int L,
   const float* m = master + (size_t)k * per_model;
   for (int l = 0; l < L; ++l)
     for (int j = threadIdx.x; j < NP; j += blockDim.x)
-      bias[((size_t)k * L + l) * NP + j] = j < va.out[l] ? m[va.b_off[l] + j] : 0.f;
+      bias[((size_t)k * L + l) * NP + j] =
+          j < va.out[l] ? kTanhPrescale * m[va.b_off[l] + j] : 0.f;
   for (int j = threadIdx.x; j < NP; j += blockDim.x)
     wo[(size_t)k * NP + j] = j < va.last_w ? m[va.wo_off + j] : 0.f;
   if (threadIdx.x == 0) bo[k] = m[va.wo_off + va.last_w];
