@@ -21,14 +21,28 @@ namespace {
 
 using namespace dev;
 
-__global__ void cv_eval_kernel(const float* pos, int n_atoms, const int* uniq,
-                               int U, const int* lq, int n, float* s, float* x) {
-  extern __shared__ float sp[];
-  const int w = blockIdx.x;
-  gather_atoms(sp, pos + (size_t)w * n_atoms * 3, uniq, U, threadIdx.x, blockDim.x);
+// kCvWaves walkers per block (one wave each); the unique-atom list and the
+// local quads are copied into LDS once per block.
+constexpr int kCvWaves = 4;
+
+__global__ __launch_bounds__(kCvWaves * kWave) void cv_eval_kernel(
+    const float* pos, int n_atoms, const int* uniq, int U, const int* lq, int n, int B,
+    float* s, float* x) {
+  extern __shared__ float smc[];
+  int* t_uniq = reinterpret_cast<int*>(smc);
+  int* t_lq = t_uniq + U;
+  for (int i = threadIdx.x; i < U; i += kCvWaves * kWave) t_uniq[i] = uniq[i];
+  for (int i = threadIdx.x; i < 4 * n; i += kCvWaves * kWave) t_lq[i] = lq[i];
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const Torsion t = torsion(sp, lq + 4 * i);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int w = blockIdx.x * kCvWaves + wave;
+  if (w >= B) return;
+  float* sp = smc + U + 4 * n + wave * 3 * U;
+  gather_atoms(sp, pos + (size_t)w * n_atoms * 3, t_uniq, U, lane, kWave);
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  for (int i = lane; i < n; i += kWave) {
+    const Torsion t = torsion(sp, t_lq + 4 * i);
     float cs, sn;
     torsion_cos_sin(t, cs, sn);
     const float sv = t.deg ? 0.f : atan2f(t.Y, t.X);
@@ -87,19 +101,57 @@ struct ScatterArgs {
   uint8_t* flags;
 };
 
-__global__ void scatter_kernel(ScatterArgs a) {
+// The system's small index tables (unique atoms, local quads, CSR inverse
+// map and, when it fits, the atom -> local map) are copied into LDS once per
+// block and shared by its kScatterWaves walkers (one wave each), so the
+// per-walker chain has no dependent global index loads.
+constexpr int kScatterWaves = 4;
+constexpr int kLocalMapMaxAtoms = 4096;
+
+__host__ __device__ inline int scatter_table_ints(int U, int n, int n_atoms) {
+  return U + 4 * n + (U + 1) + 4 * n + (n_atoms <= kLocalMapMaxAtoms ? n_atoms : 0);
+}
+
+__global__ __launch_bounds__(kScatterWaves * kWave) void scatter_kernel(ScatterArgs a) {
   extern __shared__ float sm[];
-  scatter_walker(a.sv, a.pos, blockIdx.x, a.K, a.B, a.A, a.g, a.fcv, a.eps0, a.eps1,
-                 a.force, a.energy, a.eps, a.sigma, a.flags, sm, threadIdx.x);
+  const SysView& g = a.sv;
+  const int U = g.U, n = g.n;
+  const bool loc_lds = g.n_atoms <= kLocalMapMaxAtoms;
+  int* t = reinterpret_cast<int*>(sm);
+  int* t_uniq = t;
+  int* t_lq = t_uniq + U;
+  int* t_ptr = t_lq + 4 * n;
+  int* t_ent = t_ptr + U + 1;
+  int* t_loc = t_ent + 4 * n;
+  const int nt = kScatterWaves * kWave;
+  for (int i = threadIdx.x; i < U; i += nt) t_uniq[i] = g.uniq[i];
+  for (int i = threadIdx.x; i < 4 * n; i += nt) {
+    t_lq[i] = g.lq[i];
+    t_ent[i] = g.csr_ent[i];
+  }
+  for (int i = threadIdx.x; i <= U; i += nt) t_ptr[i] = g.csr_ptr[i];
+  if (loc_lds)
+    for (int i = threadIdx.x; i < g.n_atoms; i += nt) t_loc[i] = g.atom_local[i];
+  __syncthreads();
+  const SysView lv{g.n_atoms, U, n, t_uniq, t_lq, t_ptr, t_ent,
+                   loc_lds ? t_loc : g.atom_local};
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int w = blockIdx.x * kScatterWaves + wave;
+  float* ws = sm + scatter_table_ints(U, n, g.n_atoms) + wave * scatter_lds_floats(U, n);
+  if (w < a.B)
+    scatter_walker(lv, a.pos, w, a.K, a.B, a.A, a.g, a.fcv, a.eps0, a.eps1, a.force,
+                   a.energy, a.eps, a.sigma, a.flags, ws, lane);
 }
 
 }  // namespace
 
 rid_status launch_cv_eval(const rid_system_impl& s, const float* pos, int B,
                           float* d_s, float* d_x, hipStream_t st) {
-  const size_t lds = sizeof(float) * 3 * s.n_uniq;
-  launch_timed(kProfCv, cv_eval_kernel, dim3(B), dim3(kWave), (uint32_t)lds, st, pos,
-               s.n_atoms, s.d_uniq, s.n_uniq, s.d_lquads, s.n_cv, d_s, d_x);
+  const size_t lds = sizeof(float) * (s.n_uniq + 4 * s.n_cv + kCvWaves * 3 * (size_t)s.n_uniq);
+  if (lds > 64 * 1024) return fail(RID_EUNSUPPORTED, "too many torsion atoms for cv_eval");
+  launch_timed(kProfCv, cv_eval_kernel, dim3((B + kCvWaves - 1) / kCvWaves),
+               dim3(kCvWaves * kWave), (uint32_t)lds, st, pos, s.n_atoms, s.d_uniq, s.n_uniq,
+               s.d_lquads, s.n_cv, B, d_s, d_x);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }
@@ -142,8 +194,18 @@ rid_status launch_bias_scatter(const rid_system_impl& s, int K, const float* pos
   a.eps = eps;
   a.sigma = sigma;
   a.flags = flags;
-  const size_t lds = sizeof(float) * scatter_lds_floats(s.n_uniq, s.n_cv);
-  launch_timed(kProfScatter, scatter_kernel, dim3(B), dim3(kWave), (uint32_t)lds, st, a);
+  const size_t lds =
+      sizeof(float) * (scatter_table_ints(s.n_uniq, s.n_cv, s.n_atoms) +
+                       (size_t)kScatterWaves * scatter_lds_floats(s.n_uniq, s.n_cv));
+  if (lds > 160 * 1024) return fail(RID_EUNSUPPORTED, "too many torsion atoms for the scatter");
+  static size_t attr = 0;
+  if (lds > 64 * 1024 && lds > attr) {
+    RID_HIP(hipFuncSetAttribute((const void*)scatter_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = lds;
+  }
+  launch_timed(kProfScatter, scatter_kernel, dim3((B + kScatterWaves - 1) / kScatterWaves),
+               dim3(kScatterWaves * kWave), (uint32_t)lds, st, a);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }
