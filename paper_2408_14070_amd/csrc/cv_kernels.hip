@@ -99,6 +99,7 @@ struct ScatterArgs {
   float* eps;
   float* sigma;
   uint8_t* flags;
+  size_t fstride, ostride;
 };
 
 // The system's small index tables (unique atoms, local quads, CSR inverse
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(kScatterWaves * kWave) void scatter_kernel(ScatterA
   float* ws = sm + scatter_table_ints(U, n, g.n_atoms) + wave * scatter_lds_floats(U, n);
   if (w < a.B)
     scatter_walker(lv, a.pos, w, a.K, a.B, a.A, a.g, a.fcv, a.eps0, a.eps1, a.force,
-                   a.energy, a.eps, a.sigma, a.flags, ws, lane);
+                   a.energy, a.eps, a.sigma, a.flags, ws, lane, a.fstride, a.ostride);
 }
 
 }  // namespace
@@ -177,7 +178,8 @@ rid_status launch_bias_scatter(const rid_system_impl& s, int K, const float* pos
                                int B, const float* A, const float* g,
                                const float* fcv, float eps0, float eps1,
                                float* force, float* energy, float* eps,
-                               float* sigma, uint8_t* flags, hipStream_t st) {
+                               float* sigma, uint8_t* flags, hipStream_t st,
+                               int rec_stride) {
   ScatterArgs a{};
   a.sv = SysView{s.n_atoms, s.n_uniq, s.n_cv, s.d_uniq, s.d_lquads, s.d_csr_ptr,
                  s.d_csr_ent, s.d_atom_local};
@@ -194,6 +196,8 @@ rid_status launch_bias_scatter(const rid_system_impl& s, int K, const float* pos
   a.eps = eps;
   a.sigma = sigma;
   a.flags = flags;
+  a.fstride = rec_stride > 0 ? (size_t)rec_stride : (size_t)s.n_atoms * 3;
+  a.ostride = rec_stride > 0 ? (size_t)rec_stride : 1;
   const size_t lds =
       sizeof(float) * (scatter_table_ints(s.n_uniq, s.n_cv, s.n_atoms) +
                        (size_t)kScatterWaves * scatter_lds_floats(s.n_uniq, s.n_cv));

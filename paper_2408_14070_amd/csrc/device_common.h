@@ -127,12 +127,13 @@ __host__ __device__ inline int scatter_lds_floats(int U, int n) { return 6 * U +
 // deviation, switch, bias energy, torsion Jacobians and the fixed-order CSR
 // assembly of atomic forces, written densely (zeros for atoms in no torsion).
 // With g == nullptr the CV force is fcv[w] and sigma = 1 (no statistics).
+// Outputs: forces at force + w * fstride, energy/eps/sigma at index w * ostride.
 __device__ inline void scatter_walker(const SysView& sv, const float* pos, int w,
                                       int K, int B, const float* A, const float* g,
                                       const float* fcv, double eps0, double eps1,
                                       float* force, float* energy, float* eps_out,
                                       float* sigma_out, uint8_t* flags, float* sm,
-                                      int lane) {
+                                      int lane, size_t fstride, size_t ostride) {
   const int U = sv.U, n = sv.n;
   float* sp = sm;                 // [U][3] positions
   float* fc = sp + 3 * U;         // [n] CV force
@@ -147,9 +148,9 @@ __device__ inline void scatter_walker(const SysView& sv, const float* pos, int w
     abar /= K;
     sig = switch_sigma(e, eps0, eps1);
     if (lane == 0) {
-      if (energy) energy[w] = -sig * (float)abar;
-      if (eps_out) eps_out[w] = (float)e;
-      if (sigma_out) sigma_out[w] = sig;
+      if (energy) energy[w * ostride] = -sig * (float)abar;
+      if (eps_out) eps_out[w * ostride] = (float)e;
+      if (sigma_out) sigma_out[w * ostride] = sig;
     }
   } else {
     for (int i = lane; i < n; i += kWave) fc[i] = fcv[(size_t)w * n + i];
@@ -200,7 +201,7 @@ __device__ inline void scatter_walker(const SysView& sv, const float* pos, int w
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  float* out = force + (size_t)w * sv.n_atoms * 3;
+  float* out = force + (size_t)w * fstride;
   for (int e = lane; e < 3 * sv.n_atoms; e += kWave) {
     const int atom = e / 3;
     const int loc = sv.atom_local[atom];

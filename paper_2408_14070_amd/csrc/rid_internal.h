@@ -167,7 +167,10 @@ rid_status launch_bias_scatter(const rid_system_impl& s, int K, const float* pos
                                int B, const float* A, const float* g,
                                const float* fcv, float eps0, float eps1,
                                float* force, float* energy, float* eps,
-                               float* sigma, uint8_t* flags, hipStream_t st);
+                               float* sigma, uint8_t* flags, hipStream_t st,
+                               int rec_stride = 0);
+// rec_stride > 0: walker records -- walker w's forces start at
+// force + w * rec_stride and energy/eps/sigma use the same stride.
 rid_status pack_ensemble_weights(rid_ensemble_impl& e, hipStream_t st);
 rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
                           const float* rho, int B, float* loss, float* grad_out,

@@ -6,9 +6,11 @@
 // resident; each request's positions are staged in pinned host memory.  A
 // scheduler thread forms batches (serve_core.h policy), admits them against
 // an HBM arena of fixed budget, and runs each batch on one of several
-// streams: host-to-device copies of the member requests, the MLP kernel fed
-// from positions, the deviation/switch/chain-rule kernel, and device-to-host
-// copies of every request's results, then an event.  A completion thread
+// streams: one host-to-device copy per member request, the MLP kernel fed
+// from positions, the deviation/switch/chain-rule kernel writing one record
+// per walker (forces, then energy, eps, sigma), and one device-to-host copy
+// per request, then an event.  HIP calls and host copies run outside the
+// server lock.  A completion thread
 // polls the events, frees the batch's memory and wakes waiters and the
 // scheduler, so requests that arrive while batches are on the GPU are
 // admitted as slots and memory free up.  Results do not depend on the
@@ -46,7 +48,7 @@ struct Req {
   int model = 0;
   int walkers = 0;
   size_t pin_off = 0;
-  float* pin = nullptr;          // [w][N][3] positions, then outputs
+  float* pin = nullptr;          // [w][N][3] positions, then [w] output records
   bool own_pin = false;          // pinned block outside the staging arena
   clk::time_point arrival, done_at;
   bool done = false;
@@ -55,13 +57,20 @@ struct Req {
 
 struct Batch {
   std::vector<int64_t> tickets;
+  std::vector<std::pair<float*, int>> parts;   // each request's pinned block, walkers
   int model = 0, walkers = 0, slot = 0;
   size_t dev_off = 0;
 };
 
-// Pinned layout of one request: positions, forces, energy, eps, sigma.
+// One walker's output record: 3N forces, energy, eps, sigma.
+inline int rec_floats(int n_atoms) { return 3 * n_atoms + 3; }
+
+// Pinned layout of one request: positions, then the output records.
+inline size_t pin_pos_bytes(int w, int n_atoms) {
+  return serve::align_up((size_t)w * n_atoms * 3 * 4);
+}
 inline size_t pin_bytes(int w, int n_atoms) {
-  return serve::align_up((size_t)w * n_atoms * 3 * 4) * 2 + serve::align_up((size_t)w * 4) * 3;
+  return pin_pos_bytes(w, n_atoms) + (size_t)w * rec_floats(n_atoms) * 4;
 }
 
 }  // namespace
@@ -85,6 +94,7 @@ struct Server {
   std::unordered_map<int64_t, Req> reqs;
   std::vector<Batch> inflight;
   int64_t next_ticket = 1;
+  int launching = 0;               // batches being launched outside the lock
   bool stop = false;
   rid_status fatal = RID_OK;
   std::thread sched, poller;
@@ -98,12 +108,12 @@ struct Server {
 
   void run_scheduler();
   void run_poller();
-  rid_status launch(Batch& b);
+  rid_status launch(const Batch& b, const ServeModel& m);
 };
 
-rid_status Server::launch(Batch& b) {
-  ServeModel& m = models[b.model];
+rid_status Server::launch(const Batch& b, const ServeModel& m) {
   const int W = b.walkers, N = m.sys->n_atoms, n = m.sys->n_cv, K = m.ens->K;
+  const int RF = rec_floats(N);
   unsigned char* base = static_cast<unsigned char*>(dev_base) + b.dev_off;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -112,22 +122,18 @@ rid_status Server::launch(Batch& b) {
     return p;
   };
   float* pos = reinterpret_cast<float*>(take((size_t)W * N * 3 * 4));
-  float* force = reinterpret_cast<float*>(take((size_t)W * N * 3 * 4));
-  float* energy = reinterpret_cast<float*>(take((size_t)W * 4));
-  float* eps = reinterpret_cast<float*>(take((size_t)W * 4));
-  float* sigma = reinterpret_cast<float*>(take((size_t)W * 4));
+  float* rec = reinterpret_cast<float*>(take((size_t)W * RF * 4));
   uint8_t* flags = reinterpret_cast<uint8_t*>(take((size_t)W));
   float* A = reinterpret_cast<float*>(take((size_t)W * K * 4));
   float* g = reinterpret_cast<float*>(take((size_t)W * K * n * 4));
+  float* x = reinterpret_cast<float*>(take((size_t)W * 2 * n * 4));
   hipStream_t st = streams[b.slot];
   int wo = 0;
-  for (int64_t t : b.tickets) {
-    Req& r = reqs[t];
-    RID_HIP(hipMemcpyAsync(pos + (size_t)wo * N * 3, r.pin, (size_t)r.walkers * N * 3 * 4,
+  for (const auto& pr : b.parts) {
+    RID_HIP(hipMemcpyAsync(pos + (size_t)wo * N * 3, pr.first, (size_t)pr.second * N * 3 * 4,
                            hipMemcpyHostToDevice, st));
-    wo += r.walkers;
+    wo += pr.second;
   }
-  float* x = reinterpret_cast<float*>(take((size_t)W * 2 * n * 4));
   const TorsionInput tin{m.sys, pos};
   rid_status rs = launch_mlp_from_pos(*m.ens, tin, W, A, g, st);
   if (rs == RID_EUNSUPPORTED) {   // too many torsion atoms for the in-kernel gather
@@ -135,24 +141,15 @@ rid_status Server::launch(Batch& b) {
     if (rs == RID_OK) rs = launch_mlp(*m.ens, x, W, A, g, st);
   }
   if (rs != RID_OK) return rs;
-  rs = launch_bias_scatter(*m.sys, K, pos, W, A, g, nullptr, m.eps0, m.eps1, force, energy,
-                           eps, sigma, flags, st);
+  rs = launch_bias_scatter(*m.sys, K, pos, W, A, g, nullptr, m.eps0, m.eps1, rec, rec + 3 * N,
+                           rec + 3 * N + 1, rec + 3 * N + 2, flags, st, RF);
   if (rs != RID_OK) return rs;
   wo = 0;
-  for (int64_t t : b.tickets) {
-    Req& r = reqs[t];
-    const int w = r.walkers;
-    unsigned char* out = reinterpret_cast<unsigned char*>(r.pin) +
-                         serve::align_up((size_t)w * N * 3 * 4);
-    RID_HIP(hipMemcpyAsync(out, force + (size_t)wo * N * 3, (size_t)w * N * 3 * 4,
+  for (const auto& pr : b.parts) {
+    unsigned char* out = reinterpret_cast<unsigned char*>(pr.first) + pin_pos_bytes(pr.second, N);
+    RID_HIP(hipMemcpyAsync(out, rec + (size_t)wo * RF, (size_t)pr.second * RF * 4,
                            hipMemcpyDeviceToHost, st));
-    out += serve::align_up((size_t)w * N * 3 * 4);
-    RID_HIP(hipMemcpyAsync(out, energy + wo, (size_t)w * 4, hipMemcpyDeviceToHost, st));
-    out += serve::align_up((size_t)w * 4);
-    RID_HIP(hipMemcpyAsync(out, eps + wo, (size_t)w * 4, hipMemcpyDeviceToHost, st));
-    out += serve::align_up((size_t)w * 4);
-    RID_HIP(hipMemcpyAsync(out, sigma + wo, (size_t)w * 4, hipMemcpyDeviceToHost, st));
-    wo += w;
+    wo += pr.second;
   }
   RID_HIP(hipEventRecord(events[b.slot], st));
   return RID_OK;
@@ -195,10 +192,20 @@ void Server::run_scheduler() {
     }
     b.dev_off = off;
     b.slot = slot;
-    for (size_t i : pick) b.tickets.push_back(waiting[i].ticket);
+    for (size_t i : pick) {
+      const int64_t t = waiting[i].ticket;
+      b.tickets.push_back(t);
+      const Req& r = reqs[t];
+      b.parts.emplace_back(r.pin, r.walkers);
+    }
     for (auto it = pick.rbegin(); it != pick.rend(); ++it) waiting.erase(waiting.begin() + *it);
     slot_busy[slot] = true;
-    rid_status rs = launch(b);
+    const ServeModel m = models[b.model];   // register() may grow the table meanwhile
+    ++launching;
+    lk.unlock();
+    rid_status rs = launch(b, m);
+    lk.lock();
+    --launching;
     if (rs != RID_OK) {
       fatal = rs;
       for (int64_t t : b.tickets) {
@@ -221,7 +228,7 @@ void Server::run_scheduler() {
 void Server::run_poller() {
   (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
-  while (!stop || !inflight.empty()) {
+  while (!stop || !inflight.empty() || launching > 0) {
     bool any = false;
     for (size_t i = 0; i < inflight.size();) {
       Batch& b = inflight[i];
@@ -245,7 +252,7 @@ void Server::run_poller() {
       cv_sched.notify_all();
     }
     if (inflight.empty()) {
-      if (stop) break;
+      if (stop && launching == 0) break;
       cv_done.wait_for(lk, std::chrono::milliseconds(2));
     } else if (!any) {
       lk.unlock();
@@ -350,7 +357,8 @@ rid_status rid_server_submit(rid_server srv, int model_id, const float* host_pos
   const ServeModel& m = s.models[model_id];
   if (m.shape.batch_bytes(n_walkers) > s.dev.capacity())
     return fail(RID_ENOMEM, "request larger than the HBM budget");
-  const size_t pb = pin_bytes(n_walkers, m.shape.n_atoms);
+  const int N = m.shape.n_atoms;
+  const size_t pb = pin_bytes(n_walkers, N);
   size_t poff = 0;
   Req r;
   r.model = model_id;
@@ -362,15 +370,19 @@ rid_status rid_server_submit(rid_server srv, int model_id, const float* host_pos
     // staging arena full (many requests outstanding): a pinned block of its
     // own, so a client that submits many requests before waiting never
     // blocks here
+    lk.unlock();
     void* p = nullptr;
-    if (hipHostMalloc(&p, pb, hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(RID_ENOMEM, "pinned staging allocation failed");
-    }
+    const bool ok = hipHostMalloc(&p, pb, hipHostMallocDefault) == hipSuccess;
+    if (!ok) (void)hipGetLastError();
+    lk.lock();
+    if (!ok) return fail(RID_ENOMEM, "pinned staging allocation failed");
     r.pin = static_cast<float*>(p);
     r.own_pin = true;
   }
-  std::memcpy(r.pin, host_pos, (size_t)n_walkers * m.shape.n_atoms * 3 * 4);
+  // the block is ours until the request is enqueued: copy without the lock
+  lk.unlock();
+  std::memcpy(r.pin, host_pos, (size_t)n_walkers * N * 3 * 4);
+  lk.lock();
   r.arrival = clk::now();
   if (!s.have_first) {
     s.first_arrival = r.arrival;
@@ -396,28 +408,32 @@ rid_status rid_server_wait(rid_server srv, int64_t ticket, float* host_force,
   Req& r = s.reqs.find(ticket)->second;
   s.cv_done.wait(lk, [&] { return r.done; });
   const rid_status st = r.status;
+  const Req done = r;   // this waiter owns the finished request from here on
+  const int N = s.models[r.model].shape.n_atoms;
+  lk.unlock();
   if (st == RID_OK) {
-    const int w = r.walkers, N = s.models[r.model].shape.n_atoms;
-    const unsigned char* out = reinterpret_cast<const unsigned char*>(r.pin) +
-                               serve::align_up((size_t)w * N * 3 * 4);
-    if (host_force) std::memcpy(host_force, out, (size_t)w * N * 3 * 4);
-    out += serve::align_up((size_t)w * N * 3 * 4);
-    if (host_energy) std::memcpy(host_energy, out, (size_t)w * 4);
-    out += serve::align_up((size_t)w * 4);
-    if (host_eps) std::memcpy(host_eps, out, (size_t)w * 4);
-    out += serve::align_up((size_t)w * 4);
-    if (host_sigma) std::memcpy(host_sigma, out, (size_t)w * 4);
-    const double us = std::chrono::duration<double, std::micro>(r.done_at - r.arrival).count();
+    const int w = done.walkers, RF = rec_floats(N);
+    const float* rec = reinterpret_cast<const float*>(
+        reinterpret_cast<const unsigned char*>(done.pin) + pin_pos_bytes(w, N));
+    for (int i = 0; i < w; ++i) {
+      const float* ri = rec + (size_t)i * RF;
+      if (host_force) std::memcpy(host_force + (size_t)i * 3 * N, ri, (size_t)3 * N * 4);
+      if (host_energy) host_energy[i] = ri[3 * N];
+      if (host_eps) host_eps[i] = ri[3 * N + 1];
+      if (host_sigma) host_sigma[i] = ri[3 * N + 2];
+    }
+  }
+  if (done.own_pin) (void)hipHostFree(done.pin);
+  lk.lock();
+  if (st == RID_OK) {
+    const double us = std::chrono::duration<double, std::micro>(done.done_at - done.arrival).count();
     if (latency_us) *latency_us = us;
     s.lat_us.push_back(us);
-    s.walkers_done += w;
+    s.walkers_done += done.walkers;
     s.requests_done += 1;
-    if (r.done_at > s.last_done) s.last_done = r.done_at;
+    if (done.done_at > s.last_done) s.last_done = done.done_at;
   }
-  if (r.own_pin)
-    (void)hipHostFree(r.pin);
-  else
-    s.pin.release(r.pin_off);
+  if (!done.own_pin) s.pin.release(done.pin_off);
   s.reqs.erase(ticket);
   if (st != RID_OK) return fail(st, "request failed");
   return RID_OK;

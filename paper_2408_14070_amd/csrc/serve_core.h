@@ -102,8 +102,8 @@ struct ModelShape {
   int n_atoms = 0, n_cv = 0, K = 0;
   size_t batch_bytes(int walkers) const {
     const size_t w = (size_t)walkers;
-    return align_up(w * n_atoms * 3 * 4) * 2   // positions, forces
-           + align_up(w * 4) * 3               // energy, eps, sigma
+    return align_up(w * n_atoms * 3 * 4)       // positions
+           + align_up(w * (3 * n_atoms + 3) * 4)  // records: forces, energy, eps, sigma
            + align_up(w)                       // flags
            + align_up(w * K * 4)               // per-member A
            + align_up(w * K * n_cv * 4)        // per-member g

@@ -30,7 +30,7 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16, LDK = BK + 4;
+constexpr int BM = 64, BN = 64, BK = 16, LDK = BK + 4;   // BM, BN: split-K sizing
 constexpr int kThreads = 256;
 
 enum Epi {
@@ -61,13 +61,20 @@ __device__ inline float tanh_fast(float z) {
   return 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + e);
 }
 
-// C[b] = A[b] (M x Kc) * B[b] (Kc x N), tiles of 64 x 64, 4 waves of 32 x 32.
+// C[b] = A[b] (M x Kc) * B[b] (Kc x N) on FP32 MFMA, tiles of TM x TN with
+// 4 waves of (TM/2) x (TN/2); operands staged through double-buffered LDS.
+// 128 x 128 tiles (16 accumulator tiles per wave) reuse each LDS operand
+// fragment four times; 64 x 64 tiles serve narrow shapes.
+template <int TM, int TN>
 __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) float As[2][BM][LDK];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BN][LDK];
+  constexpr int WM = TM / 2, WN = TN / 2;           // wave tile
+  constexpr int TI = WM / 16, TJ = WN / 16;         // 16 x 16 MFMA tiles per wave
+  constexpr int LA = TM * BK / kThreads, LB = TN * BK / kThreads;
+  __shared__ __attribute__((aligned(16))) float As[2][TM][LDK];
+  __shared__ __attribute__((aligned(16))) float Bs[2][TN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int b = blockIdx.z / g.ksplit, s = blockIdx.z % g.ksplit;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   const int k_begin = s * g.kchunk;
   const int k_end = min(g.Kc, k_begin + g.kchunk);
   const float* A = g.A + b * g.sAb;
@@ -75,41 +82,49 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
   const bool a_kfast = g.sAk == 1;
   const bool b_kfast = g.sBk == 1;
 
-  float ra[4], rb[4];
+  float ra[LA], rb[LB];
   auto load = [&](int kb) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < LA; ++j) {
       const int idx = tid + kThreads * j;
       int m, k;
-      if (a_kfast) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
+      if (a_kfast) { k = idx % BK; m = idx / BK; } else { m = idx % TM; k = idx / TM; }
       const int gm = m0 + m, gk = kb + k;
       ra[j] = (gm < g.M && gk < k_end) ? A[gm * g.sAm + gk * g.sAk] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < LB; ++j) {
+      const int idx = tid + kThreads * j;
       int n, k2;
-      if (b_kfast) { k2 = idx % BK; n = idx / BK; } else { n = idx % BN; k2 = idx / BN; }
+      if (b_kfast) { k2 = idx % BK; n = idx / BK; } else { n = idx % TN; k2 = idx / TN; }
       const int gn = n0 + n, gk2 = kb + k2;
       rb[j] = (gn < g.N && gk2 < k_end) ? Bp[gk2 * g.sBk + gn * g.sBn] : 0.f;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < LA; ++j) {
       const int idx = tid + kThreads * j;
       int m, k;
-      if (a_kfast) { k = idx % BK; m = idx / BK; } else { m = idx % BM; k = idx / BM; }
+      if (a_kfast) { k = idx % BK; m = idx / BK; } else { m = idx % TM; k = idx / TM; }
       As[buf][m][k] = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < LB; ++j) {
+      const int idx = tid + kThreads * j;
       int n, k2;
-      if (b_kfast) { k2 = idx % BK; n = idx / BK; } else { n = idx % BN; k2 = idx / BN; }
+      if (b_kfast) { k2 = idx % BK; n = idx / BK; } else { n = idx % TN; k2 = idx / TN; }
       Bs[buf][n][k2] = rb[j];
     }
   };
 
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
   const int r = lane & 15, gq = lane >> 4;
-  f4 acc[2][2];
+  f4 acc[TI][TJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   int buf = 0;
   load(k_begin);
@@ -118,19 +133,19 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
   for (int kb = k_begin; kb < k_end; kb += BK) {
     const bool more = kb + BK < k_end;
     if (more) load(kb + BK);
-    f4 a[2], bb[2];
+    f4 a[TI], bb[TJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
       a[i] = *reinterpret_cast<const f4*>(&As[buf][wm + i * 16 + r][4 * gq]);
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TJ; ++j)
       bb[j] = *reinterpret_cast<const f4*>(&Bs[buf][wn + j * 16 + r][4 * gq]);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int j = 0; j < TJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][e], bb[j][e], acc[i][j], 0, 0, 0);
     if (more) {
       store(buf ^ 1);
@@ -141,9 +156,9 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
 
   float* C = g.C + b * g.sCb + s * g.sCs;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < TJ; ++j) {
       const int n = n0 + wn + j * 16 + r;
       if (n >= g.N) continue;
       const float bias = g.mode == EPI_BIAS_TANH ? g.bias[b * g.sBiasb + n] : 0.f;
@@ -356,8 +371,17 @@ rid_status gemm(const GemmArgs& g0, hipStream_t st) {
   GemmArgs g = g0;
   if (g.ksplit < 1) g.ksplit = 1;
   if (g.kchunk <= 0) g.kchunk = round_up(g.Kc, BK);
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * g.ksplit);
-  hipLaunchKernelGGL(gemm_f32_kernel, grid, dim3(kThreads), 0, st, g);
+  // 128 x 128 tiles only when they still give every CU several workgroups
+  // (one 4-wave workgroup per CU leaves one wave per SIMD to hide latency)
+  const long long tiles128 =
+      (long long)((g.N + 127) / 128) * ((g.M + 127) / 128) * g.batch * g.ksplit;
+  if (g.M >= 128 && g.N >= 128 && tiles128 >= 1024) {
+    dim3 grid((g.N + 127) / 128, (g.M + 127) / 128, g.batch * g.ksplit);
+    hipLaunchKernelGGL((gemm_f32_kernel<128, 128>), grid, dim3(kThreads), 0, st, g);
+  } else {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.batch * g.ksplit);
+    hipLaunchKernelGGL((gemm_f32_kernel<64, 64>), grid, dim3(kThreads), 0, st, g);
+  }
   RID_HIP(hipGetLastError());
   return RID_OK;
 }
