@@ -54,6 +54,67 @@ struct GemmArgs {
   const float* aux;               // same strides as C (sXb, sXm, sXn)
   long long sXb, sXm, sXn;
   int M, N, Kc, batch, ksplit, kchunk, mode;
+  int modeA, modeB;               // operand load modes (TileLoad), set by gemm()
+};
+
+// One operand tile of TR rows x BK contraction into LDS [row][k].  Element
+// (r, k) of the operand is at X[r * sR + k * sK].  Modes: 0 scalar loads,
+// k fastest; 1 scalar, rows fastest; 2 float4 along k (sK == 1); 3 float4
+// along rows (sR == 1).  The float4 modes need 16-byte alignment and an
+// extent along the vector that is a multiple of 4 (gemm() checks).
+template <int TR>
+struct TileLoad {
+  static constexpr int NS = TR * BK / kThreads;   // elements per thread
+  float v[NS];
+  __device__ inline void load(const float* X, long long sR, long long sK, int mode, int r0,
+                              int R, int kb, int k_end, int tid) {
+    if (mode >= 2) {
+#pragma unroll
+      for (int j = 0; j < NS / 4; ++j) {
+        const int idx = tid + kThreads * j;
+        int r, k;
+        if (mode == 2) { r = idx / (BK / 4); k = (idx % (BK / 4)) * 4; }
+        else { k = idx / (TR / 4); r = (idx % (TR / 4)) * 4; }
+        const int gr = r0 + r, gk = kb + k;
+        f4 x = f4{0.f, 0.f, 0.f, 0.f};
+        if (gr < R && gk < k_end) x = *reinterpret_cast<const f4*>(X + gr * sR + gk * sK);
+        v[4 * j] = x[0]; v[4 * j + 1] = x[1]; v[4 * j + 2] = x[2]; v[4 * j + 3] = x[3];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        const int idx = tid + kThreads * j;
+        int r, k;
+        if (mode == 0) { k = idx % BK; r = idx / BK; } else { r = idx % TR; k = idx / TR; }
+        const int gr = r0 + r, gk = kb + k;
+        v[j] = (gr < R && gk < k_end) ? X[gr * sR + gk * sK] : 0.f;
+      }
+    }
+  }
+  __device__ inline void store(float (*S)[LDK], int mode, int tid) const {
+    if (mode >= 2) {
+#pragma unroll
+      for (int j = 0; j < NS / 4; ++j) {
+        const int idx = tid + kThreads * j;
+        if (mode == 2) {
+          const int r = idx / (BK / 4), k = (idx % (BK / 4)) * 4;
+          *reinterpret_cast<f4*>(&S[r][k]) = f4{v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]};
+        } else {
+          const int k = idx / (TR / 4), r = (idx % (TR / 4)) * 4;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) S[r + e][k] = v[4 * j + e];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        const int idx = tid + kThreads * j;
+        int r, k;
+        if (mode == 0) { k = idx % BK; r = idx / BK; } else { r = idx % TR; k = idx / TR; }
+        S[r][k] = v[j];
+      }
+    }
+  }
 };
 
 __device__ inline float tanh_fast(float z) {
@@ -69,7 +130,6 @@ template <int TM, int TN>
 __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
   constexpr int WM = TM / 2, WN = TN / 2;           // wave tile
   constexpr int TI = WM / 16, TJ = WN / 16;         // 16 x 16 MFMA tiles per wave
-  constexpr int LA = TM * BK / kThreads, LB = TN * BK / kThreads;
   __shared__ __attribute__((aligned(16))) float As[2][TM][LDK];
   __shared__ __attribute__((aligned(16))) float Bs[2][TN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -79,43 +139,15 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
   const int k_end = min(g.Kc, k_begin + g.kchunk);
   const float* A = g.A + b * g.sAb;
   const float* Bp = g.Bm + b * g.sBb;
-  const bool a_kfast = g.sAk == 1;
-  const bool b_kfast = g.sBk == 1;
-
-  float ra[LA], rb[LB];
+  TileLoad<TM> ta;
+  TileLoad<TN> tb;
   auto load = [&](int kb) {
-#pragma unroll
-    for (int j = 0; j < LA; ++j) {
-      const int idx = tid + kThreads * j;
-      int m, k;
-      if (a_kfast) { k = idx % BK; m = idx / BK; } else { m = idx % TM; k = idx / TM; }
-      const int gm = m0 + m, gk = kb + k;
-      ra[j] = (gm < g.M && gk < k_end) ? A[gm * g.sAm + gk * g.sAk] : 0.f;
-    }
-#pragma unroll
-    for (int j = 0; j < LB; ++j) {
-      const int idx = tid + kThreads * j;
-      int n, k2;
-      if (b_kfast) { k2 = idx % BK; n = idx / BK; } else { n = idx % TN; k2 = idx / TN; }
-      const int gn = n0 + n, gk2 = kb + k2;
-      rb[j] = (gn < g.N && gk2 < k_end) ? Bp[gk2 * g.sBk + gn * g.sBn] : 0.f;
-    }
+    ta.load(A, g.sAm, g.sAk, g.modeA, m0, g.M, kb, k_end, tid);
+    tb.load(Bp, g.sBn, g.sBk, g.modeB, n0, g.N, kb, k_end, tid);
   };
   auto store = [&](int buf) {
-#pragma unroll
-    for (int j = 0; j < LA; ++j) {
-      const int idx = tid + kThreads * j;
-      int m, k;
-      if (a_kfast) { k = idx % BK; m = idx / BK; } else { m = idx % TM; k = idx / TM; }
-      As[buf][m][k] = ra[j];
-    }
-#pragma unroll
-    for (int j = 0; j < LB; ++j) {
-      const int idx = tid + kThreads * j;
-      int n, k2;
-      if (b_kfast) { k2 = idx % BK; n = idx / BK; } else { n = idx % TN; k2 = idx / TN; }
-      Bs[buf][n][k2] = rb[j];
-    }
+    ta.store(As[buf], g.modeA, tid);
+    tb.store(Bs[buf], g.modeB, tid);
   };
 
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
@@ -367,10 +399,21 @@ inline int grid1d(long long total) {
   return (int)std::min<long long>((total + 255) / 256, 4096);
 }
 
+// Load mode of one operand (see TileLoad): float4 along the unit-stride
+// dimension when alignment and extents allow, else scalar.
+int load_mode(const float* X, long long sR, long long sK, long long sBatch, int R, int Kc) {
+  const bool al = (reinterpret_cast<uintptr_t>(X) % 16 == 0) && sBatch % 4 == 0;
+  if (sK == 1) return (al && sR % 4 == 0 && Kc % 4 == 0) ? 2 : 0;
+  if (sR == 1) return (al && sK % 4 == 0 && R % 4 == 0) ? 3 : 1;
+  return 0;
+}
+
 rid_status gemm(const GemmArgs& g0, hipStream_t st) {
   GemmArgs g = g0;
   if (g.ksplit < 1) g.ksplit = 1;
   if (g.kchunk <= 0) g.kchunk = round_up(g.Kc, BK);
+  g.modeA = load_mode(g.A, g.sAm, g.sAk, g.sAb, g.M, g.Kc);
+  g.modeB = load_mode(g.Bm, g.sBn, g.sBk, g.sBb, g.N, g.Kc);
   // 128 x 128 tiles only when they still give every CU several workgroups
   // (one 4-wave workgroup per CU leaves one wave per SIMD to hide latency)
   const long long tiles128 =
