@@ -112,11 +112,8 @@ static size_t per_model_count(int n_cv, int L, const int* widths) {
 }
 
 static void free_system(rid_system_impl& s) {
-  dev_free(s.d_uniq);
-  dev_free(s.d_lquads);
-  dev_free(s.d_csr_ptr);
-  dev_free(s.d_csr_ent);
-  dev_free(s.d_atom_local);
+  dev_free(s.d_tables);
+  s.d_uniq = s.d_lquads = s.d_csr_ptr = s.d_csr_ent = s.d_atom_local = nullptr;
 }
 
 static void free_ensemble(rid_ensemble_impl& e) {
@@ -185,22 +182,26 @@ rid_status rid_system_create(int n_atoms, int n_cv, const int32_t* quads,
   }
   std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
   for (size_t e = 0; e < lq.size(); ++e) ent[fill[lq[e]]++] = (int32_t)e;
-  rid_status st = RID_OK;
-  if ((st = dev_alloc(&s.d_uniq, s.n_uniq)) != RID_OK ||
-      (st = dev_alloc(&s.d_lquads, lq.size())) != RID_OK ||
-      (st = dev_alloc(&s.d_csr_ptr, ptr.size())) != RID_OK ||
-      (st = dev_alloc(&s.d_csr_ent, ent.size())) != RID_OK ||
-      (st = dev_alloc(&s.d_atom_local, atom_local.size())) != RID_OK) {
-    free_system(s);
+  // one allocation: uniq | lquads | csr_ptr | csr_ent | atom_local
+  std::vector<int32_t> tab;
+  tab.reserve(s.uniq.size() + lq.size() + ptr.size() + ent.size() + atom_local.size());
+  tab.insert(tab.end(), s.uniq.begin(), s.uniq.end());
+  tab.insert(tab.end(), lq.begin(), lq.end());
+  tab.insert(tab.end(), ptr.begin(), ptr.end());
+  tab.insert(tab.end(), ent.begin(), ent.end());
+  tab.insert(tab.end(), atom_local.begin(), atom_local.end());
+  rid_status st = dev_alloc(&s.d_tables, tab.size());
+  if (st != RID_OK) {
     delete h;
     return st;
   }
-  hipError_t e = hipSuccess;
-  e = e ? e : hipMemcpy(s.d_uniq, s.uniq.data(), 4 * s.uniq.size(), hipMemcpyHostToDevice);
-  e = e ? e : hipMemcpy(s.d_lquads, lq.data(), 4 * lq.size(), hipMemcpyHostToDevice);
-  e = e ? e : hipMemcpy(s.d_csr_ptr, ptr.data(), 4 * ptr.size(), hipMemcpyHostToDevice);
-  e = e ? e : hipMemcpy(s.d_csr_ent, ent.data(), 4 * ent.size(), hipMemcpyHostToDevice);
-  e = e ? e : hipMemcpy(s.d_atom_local, atom_local.data(), 4 * atom_local.size(), hipMemcpyHostToDevice);
+  s.d_uniq = s.d_tables;
+  s.d_lquads = s.d_uniq + s.uniq.size();
+  s.d_csr_ptr = s.d_lquads + lq.size();
+  s.d_csr_ent = s.d_csr_ptr + ptr.size();
+  s.d_atom_local = s.d_csr_ent + ent.size();
+  const hipError_t e =
+      hipMemcpy(s.d_tables, tab.data(), 4 * tab.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     free_system(s);
     delete h;

@@ -31,8 +31,8 @@ __global__ __launch_bounds__(kCvWaves * kWave) void cv_eval_kernel(
   extern __shared__ float smc[];
   int* t_uniq = reinterpret_cast<int*>(smc);
   int* t_lq = t_uniq + U;
-  for (int i = threadIdx.x; i < U; i += kCvWaves * kWave) t_uniq[i] = uniq[i];
-  for (int i = threadIdx.x; i < 4 * n; i += kCvWaves * kWave) t_lq[i] = lq[i];
+  // the system's tables are one array that starts uniq | lquads
+  copy_ints(t_uniq, uniq, U + 4 * n, threadIdx.x, kCvWaves * kWave);
   __syncthreads();
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int w = blockIdx.x * kCvWaves + wave;
@@ -105,7 +105,11 @@ struct ScatterArgs {
 // The system's small index tables (unique atoms, local quads, CSR inverse
 // map and, when it fits, the atom -> local map) are copied into LDS once per
 // block and shared by its kScatterWaves walkers (one wave each), so the
-// per-walker chain has no dependent global index loads.
+// per-walker chain has no dependent global index loads.  REG: each wave first
+// issues the loads of its walker's member results (held in registers), the
+// table copy runs while they are in flight, and the atom gather follows the
+// barrier, so a walker waits on memory twice in all; otherwise the members'
+// results are read inside the statistics (any K and n).
 constexpr int kScatterWaves = 4;
 constexpr int kLocalMapMaxAtoms = 4096;
 
@@ -113,35 +117,86 @@ __host__ __device__ inline int scatter_table_ints(int U, int n, int n_atoms) {
   return U + 4 * n + (U + 1) + 4 * n + (n_atoms <= kLocalMapMaxAtoms ? n_atoms : 0);
 }
 
+template <bool REG>
 __global__ __launch_bounds__(kScatterWaves * kWave) void scatter_kernel(ScatterArgs a) {
   extern __shared__ float sm[];
   const SysView& g = a.sv;
   const int U = g.U, n = g.n;
   const bool loc_lds = g.n_atoms <= kLocalMapMaxAtoms;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int w = blockIdx.x * kScatterWaves + wave;
+  const bool live = w < a.B;
   int* t = reinterpret_cast<int*>(sm);
   int* t_uniq = t;
   int* t_lq = t_uniq + U;
   int* t_ptr = t_lq + 4 * n;
   int* t_ent = t_ptr + U + 1;
   int* t_loc = t_ent + 4 * n;
-  const int nt = kScatterWaves * kWave;
-  for (int i = threadIdx.x; i < U; i += nt) t_uniq[i] = g.uniq[i];
-  for (int i = threadIdx.x; i < 4 * n; i += nt) {
-    t_lq[i] = g.lq[i];
-    t_ent[i] = g.csr_ent[i];
+  // the system's tables are one array in this order; the first
+  // kGatherBatch entries per thread are loaded before the walker's own
+  // loads and stored after them, so all of them are in flight together
+  constexpr int nt = kScatterWaves * kWave;
+  const int n_tab = scatter_table_ints(U, n, g.n_atoms);
+  int ti[kGatherBatch], tv[kGatherBatch];
+#pragma unroll
+  for (int m = 0; m < kGatherBatch; ++m) {
+    ti[m] = min((int)threadIdx.x + m * nt, n_tab - 1);
+    tv[m] = g.uniq[ti[m]];
   }
-  for (int i = threadIdx.x; i <= U; i += nt) t_ptr[i] = g.csr_ptr[i];
-  if (loc_lds)
-    for (int i = threadIdx.x; i < g.n_atoms; i += nt) t_loc[i] = g.atom_local[i];
+  WalkerRegs r;
+  if (REG && live) walker_prefetch(r, a.A, a.g, a.fcv, a.K, a.B, n, w, lane);
+#pragma unroll
+  for (int m = 0; m < kGatherBatch; ++m) t[ti[m]] = tv[m];
+  if (n_tab > kGatherBatch * nt)
+    copy_ints(t, g.uniq, n_tab, threadIdx.x + kGatherBatch * nt, nt);
   __syncthreads();
   const SysView lv{g.n_atoms, U, n, t_uniq, t_lq, t_ptr, t_ent,
                    loc_lds ? t_loc : g.atom_local};
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int w = blockIdx.x * kScatterWaves + wave;
+  if (!live) return;
   float* ws = sm + scatter_table_ints(U, n, g.n_atoms) + wave * scatter_lds_floats(U, n);
-  if (w < a.B)
+  if (!REG) {
     scatter_walker(lv, a.pos, w, a.K, a.B, a.A, a.g, a.fcv, a.eps0, a.eps1, a.force,
                    a.energy, a.eps, a.sigma, a.flags, ws, lane, a.fstride, a.ostride);
+    return;
+  }
+  float* sp = ws;                 // [U][3] positions
+  float* fc = sp + 3 * U;         // [n] CV force
+  float* ct = fc + n;             // [n][4][3] per-slot force contributions
+  float* fl = ct + 12 * n;        // [U][3] assembled forces
+  // the atom gather: when it is one batch (3U <= kGatherBatch * 64) its
+  // loads stay in flight through the statistics below
+  const float* pw = a.pos + (size_t)w * g.n_atoms * 3;
+  const int n3 = 3 * U;
+  const bool one = n3 <= kGatherBatch * kWave;
+  int jc[kGatherBatch];
+  float pv[kGatherBatch];
+  if (one) {
+#pragma unroll
+    for (int m = 0; m < kGatherBatch; ++m) {
+      jc[m] = min(lane + m * kWave, n3 - 1);
+      const int u = jc[m] / 3;
+      pv[m] = pw[3 * t_uniq[u] + (jc[m] - 3 * u)];
+    }
+  } else {
+    gather_atoms(sp, pw, t_uniq, U, lane, kWave);
+  }
+  float sig = 1.f;
+  if (a.g) {
+    double abar;
+    const double e = scatter_stats_reg(r, a.K, n, fc, abar, lane);
+    sig = switch_outputs(e, abar, a.eps0, a.eps1, w, a.energy, a.eps, a.sigma, lane,
+                         a.ostride);
+  } else {
+#pragma unroll
+    for (int p = 0; p < kRegPasses; ++p)
+      if (lane + p * kWave < n) fc[lane + p * kWave] = r.g[p][0];
+  }
+  if (one)
+#pragma unroll
+    for (int m = 0; m < kGatherBatch; ++m) sp[jc[m]] = pv[m];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  scatter_forces(lv, sp, fc, ct, fl, sig, w, a.force, a.flags, lane, a.fstride);
 }
 
 }  // namespace
@@ -202,13 +257,16 @@ rid_status launch_bias_scatter(const rid_system_impl& s, int K, const float* pos
       sizeof(float) * (scatter_table_ints(s.n_uniq, s.n_cv, s.n_atoms) +
                        (size_t)kScatterWaves * scatter_lds_floats(s.n_uniq, s.n_cv));
   if (lds > 160 * 1024) return fail(RID_EUNSUPPORTED, "too many torsion atoms for the scatter");
-  static size_t attr = 0;
-  if (lds > 64 * 1024 && lds > attr) {
-    RID_HIP(hipFuncSetAttribute((const void*)scatter_kernel,
+  static size_t attr[2] = {0, 0};
+  // members' results in registers when they fit (K <= 8, n <= 128)
+  const bool reg = (g == nullptr || K <= kRegMembers) && s.n_cv <= kRegPasses * kWave;
+  auto kern = reg ? scatter_kernel<true> : scatter_kernel<false>;
+  if (lds > 64 * 1024 && lds > attr[reg]) {
+    RID_HIP(hipFuncSetAttribute((const void*)kern,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr = lds;
+    attr[reg] = lds;
   }
-  launch_timed(kProfScatter, scatter_kernel, dim3((B + kScatterWaves - 1) / kScatterWaves),
+  launch_timed(kProfScatter, kern, dim3((B + kScatterWaves - 1) / kScatterWaves),
                dim3(kScatterWaves * kWave), (uint32_t)lds, st, a);
   RID_HIP(hipGetLastError());
   return RID_OK;

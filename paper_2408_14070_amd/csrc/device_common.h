@@ -22,12 +22,46 @@ __device__ inline float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b
 __device__ inline V3 ld3(const float* p, int a) { return {p[3 * a], p[3 * a + 1], p[3 * a + 2]}; }
 
 // Positions of the torsion atoms of one walker into sp[U][3]; threads
-// [t0, t0 + nt) cooperate (a wave or a whole workgroup).
+// [t0, t0 + nt) cooperate (a wave or a whole workgroup).  Coordinates go in
+// chunks of kGatherBatch per thread: a chunk's index loads are all issued
+// before its coordinate loads, and those before the first store, so a chunk
+// costs two memory round trips rather than two per coordinate.
+constexpr int kGatherBatch = 4;
 __device__ inline void gather_atoms(float* sp, const float* pw, const int* uniq,
                                     int U, int t0, int nt) {
-  for (int j = t0; j < 3 * U; j += nt) {
-    const int u = j / 3;
-    sp[j] = pw[3 * uniq[u] + (j - 3 * u)];
+  const int n3 = 3 * U;
+  for (int j0 = t0; j0 < n3; j0 += kGatherBatch * nt) {
+    // slots past the end are clamped to the last coordinate: they load and
+    // store that coordinate's own value again, so nothing sits behind a
+    // branch (the compiler would sink a guarded load next to its store)
+    int jc[kGatherBatch], a[kGatherBatch];
+#pragma unroll
+    for (int m = 0; m < kGatherBatch; ++m) {
+      jc[m] = min(j0 + m * nt, n3 - 1);
+      const int u = jc[m] / 3;
+      a[m] = 3 * uniq[u] + (jc[m] - 3 * u);
+    }
+    float v[kGatherBatch];
+#pragma unroll
+    for (int m = 0; m < kGatherBatch; ++m) v[m] = pw[a[m]];
+#pragma unroll
+    for (int m = 0; m < kGatherBatch; ++m) sp[jc[m]] = v[m];
+  }
+}
+
+// count ints from global memory into LDS, threads [t0, t0 + nt), with
+// kGatherBatch loads per thread in flight (slots past the end are clamped to
+// the last element and write its own value again).
+__device__ inline void copy_ints(int* dst, const int* src, int count, int t0, int nt) {
+  for (int i0 = t0; i0 < count; i0 += kGatherBatch * nt) {
+    int ic[kGatherBatch], v[kGatherBatch];
+#pragma unroll
+    for (int m = 0; m < kGatherBatch; ++m) {
+      ic[m] = min(i0 + m * nt, count - 1);
+      v[m] = src[ic[m]];
+    }
+#pragma unroll
+    for (int m = 0; m < kGatherBatch; ++m) dst[ic[m]] = v[m];
   }
 }
 
@@ -68,10 +102,33 @@ __device__ inline void torsion_cos_sin(const Torsion& t, float& cs, float& sn) {
   sn = t.Y / r;
 }
 
+// One DPP lane move of an FP64 value (both halves), all lanes active.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes (all active), returned in every lane: DPP moves
+// within each row of 16 lanes (quad swaps, then the half-row and row
+// mirrors pair the partial sums), then the four row sums in row order.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m);
-  return v;
+  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+  v += dpp_f64<0x141>(v);   // row_half_mirror: quad 0 <-> quad 1 of 8 lanes
+  v += dpp_f64<0x140>(v);   // row_mirror: half 0 <-> half 1 of 16 lanes
+  double r = readlane_f64(v, 0) + readlane_f64(v, 16);
+  r += readlane_f64(v, 32);
+  r += readlane_f64(v, 48);
+  return r;
 }
 
 // Ensemble statistics of walker w from g [K][B][n] (FP32) in FP64, one wave:
@@ -123,40 +180,16 @@ struct SysView {
 // LDS floats one wave needs for scatter_walker.
 __host__ __device__ inline int scatter_lds_floats(int U, int n) { return 6 * U + 13 * n; }
 
-// Whole tail of the bias for walker w, executed by ONE wave (lane 0..63):
-// deviation, switch, bias energy, torsion Jacobians and the fixed-order CSR
-// assembly of atomic forces, written densely (zeros for atoms in no torsion).
-// With g == nullptr the CV force is fcv[w] and sigma = 1 (no statistics).
-// Outputs: forces at force + w * fstride, energy/eps/sigma at index w * ostride.
-__device__ inline void scatter_walker(const SysView& sv, const float* pos, int w,
-                                      int K, int B, const float* A, const float* g,
-                                      const float* fcv, double eps0, double eps1,
-                                      float* force, float* energy, float* eps_out,
-                                      float* sigma_out, uint8_t* flags, float* sm,
-                                      int lane, size_t fstride, size_t ostride) {
+// Chain rule of walker w with its CV force fc[n] (in LDS) scaled by sig and
+// its torsion atoms in sp[U][3]: torsion Jacobians, the fixed-order CSR
+// assembly of atomic forces, written densely (zeros for atoms in no torsion)
+// at force + w * fstride, and the walker's degenerate-torsion flag.  ct and
+// fl are the wave's LDS scratch ([n][4][3] and [U][3]).  One wave.
+__device__ inline void scatter_forces(const SysView& sv, const float* sp, const float* fc,
+                                      float* ct, float* fl, float sig, int w,
+                                      float* force, uint8_t* flags, int lane,
+                                      size_t fstride) {
   const int U = sv.U, n = sv.n;
-  float* sp = sm;                 // [U][3] positions
-  float* fc = sp + 3 * U;         // [n] CV force
-  float* ct = fc + n;             // [n][4][3] per-slot force contributions
-  float* fl = ct + 12 * n;        // [U][3] assembled forces
-  gather_atoms(sp, pos + (size_t)w * sv.n_atoms * 3, sv.uniq, U, lane, kWave);
-  float sig = 1.f;
-  if (g) {
-    const double e = ensemble_stats(g, K, B, n, w, fc, lane);
-    double abar = 0.0;
-    for (int k = 0; k < K; ++k) abar += (double)A[(size_t)k * B + w];
-    abar /= K;
-    sig = switch_sigma(e, eps0, eps1);
-    if (lane == 0) {
-      if (energy) energy[w * ostride] = -sig * (float)abar;
-      if (eps_out) eps_out[w * ostride] = (float)e;
-      if (sigma_out) sigma_out[w * ostride] = sig;
-    }
-  } else {
-    for (int i = lane; i < n; i += kWave) fc[i] = fcv[(size_t)w * n + i];
-  }
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   bool deg_any = false;
   for (int i = lane; i < n; i += kWave) {
     const Torsion t = torsion(sp, sv.lq + 4 * i);
@@ -187,9 +220,25 @@ __device__ inline void scatter_walker(const SysView& sv, const float* pos, int w
   if (flags && lane == 0) flags[w] = any ? 1 : 0;
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // every unique atom has at least one entry; the first kCsrBatch entries
+  // of an atom are read in one batch (indices clamped to its last entry,
+  // contributions past the end are zero), any further ones in order
+  constexpr int kCsrBatch = 4;
   for (int u = lane; u < U; u += kWave) {
+    const int e0 = sv.csr_ptr[u], e1 = sv.csr_ptr[u + 1];
+    int ent[kCsrBatch];
+#pragma unroll
+    for (int j = 0; j < kCsrBatch; ++j) ent[j] = sv.csr_ent[min(e0 + j, e1 - 1)];
     float fx = 0.f, fy = 0.f, fz = 0.f;
-    for (int e = sv.csr_ptr[u]; e < sv.csr_ptr[u + 1]; ++e) {
+#pragma unroll
+    for (int j = 0; j < kCsrBatch; ++j) {
+      const float* c = ct + 3 * ent[j];
+      const bool on = e0 + j < e1;
+      fx += on ? c[0] : 0.f;
+      fy += on ? c[1] : 0.f;
+      fz += on ? c[2] : 0.f;
+    }
+    for (int e = e0 + kCsrBatch; e < e1; ++e) {
       const float* c = ct + 3 * sv.csr_ent[e];
       fx += c[0];
       fy += c[1];
@@ -201,12 +250,144 @@ __device__ inline void scatter_walker(const SysView& sv, const float* pos, int w
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // a lane writes whole atoms, kGatherBatch of them per batch of LDS reads
+  // (atoms past the end are clamped to the last one and write its values
+  // again)
   float* out = force + (size_t)w * fstride;
-  for (int e = lane; e < 3 * sv.n_atoms; e += kWave) {
-    const int atom = e / 3;
-    const int loc = sv.atom_local[atom];
-    out[e] = loc >= 0 ? fl[3 * loc + (e - 3 * atom)] : 0.f;
+  const int na = sv.n_atoms;
+  for (int a0 = lane; a0 < na; a0 += kGatherBatch * kWave) {
+    int ac[kGatherBatch], loc[kGatherBatch];
+#pragma unroll
+    for (int m = 0; m < kGatherBatch; ++m) {
+      ac[m] = min(a0 + m * kWave, na - 1);
+      loc[m] = sv.atom_local[ac[m]];
+    }
+#pragma unroll
+    for (int m = 0; m < kGatherBatch; ++m) {
+      const int l3 = 3 * max(loc[m], 0);
+      const float x = fl[l3], y = fl[l3 + 1], z = fl[l3 + 2];
+      const bool on = loc[m] >= 0;
+      out[3 * ac[m]] = on ? x : 0.f;
+      out[3 * ac[m] + 1] = on ? y : 0.f;
+      out[3 * ac[m] + 2] = on ? z : 0.f;
+    }
   }
+}
+
+// Writes the walker's energy, deviation and sigma (lane 0) and returns sigma.
+__device__ inline float switch_outputs(double e, double abar, double eps0, double eps1,
+                                       int w, float* energy, float* eps_out,
+                                       float* sigma_out, int lane, size_t ostride) {
+  const float sig = switch_sigma(e, eps0, eps1);
+  if (lane == 0) {
+    if (energy) energy[w * ostride] = -sig * (float)abar;
+    if (eps_out) eps_out[w * ostride] = (float)e;
+    if (sigma_out) sigma_out[w * ostride] = sig;
+  }
+  return sig;
+}
+
+// Whole tail of the bias for walker w, executed by ONE wave (lane 0..63):
+// deviation, switch, bias energy and the chain rule to atoms.  With
+// g == nullptr the CV force is fcv[w] and sigma = 1 (no statistics).
+// Outputs: forces at force + w * fstride, energy/eps/sigma at index w * ostride.
+// Reads the members' results with dependent loads; scatter kernels that can
+// hold them in registers use scatter_stats_reg instead.
+__device__ inline void scatter_walker(const SysView& sv, const float* pos, int w,
+                                      int K, int B, const float* A, const float* g,
+                                      const float* fcv, double eps0, double eps1,
+                                      float* force, float* energy, float* eps_out,
+                                      float* sigma_out, uint8_t* flags, float* sm,
+                                      int lane, size_t fstride, size_t ostride) {
+  const int U = sv.U, n = sv.n;
+  float* sp = sm;                 // [U][3] positions
+  float* fc = sp + 3 * U;         // [n] CV force
+  float* ct = fc + n;             // [n][4][3] per-slot force contributions
+  float* fl = ct + 12 * n;        // [U][3] assembled forces
+  gather_atoms(sp, pos + (size_t)w * sv.n_atoms * 3, sv.uniq, U, lane, kWave);
+  float sig = 1.f;
+  if (g) {
+    const double e = ensemble_stats(g, K, B, n, w, fc, lane);
+    double abar = 0.0;
+    for (int k = 0; k < K; ++k) abar += (double)A[(size_t)k * B + w];
+    abar /= K;
+    sig = switch_outputs(e, abar, eps0, eps1, w, energy, eps_out, sigma_out, lane, ostride);
+  } else {
+    for (int i = lane; i < n; i += kWave) fc[i] = fcv[(size_t)w * n + i];
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  scatter_forces(sv, sp, fc, ct, fl, sig, w, force, flags, lane, fstride);
+}
+
+// Register-resident form of the per-walker statistics for K <= kRegMembers
+// and n <= kRegPasses * 64: a lane loads its CVs' values of every member
+// (g [K][B][n], or fcv when g is null) and the members' A into registers in
+// one batch, before anything waits on memory.  Indices past K or n are
+// clamped to valid ones (loaded, never used), so no load is guarded by a
+// branch.  The arithmetic is ensemble_stats' in the same order.
+constexpr int kRegMembers = 8;
+constexpr int kRegPasses = 2;
+struct WalkerRegs {
+  float g[kRegPasses][kRegMembers];
+  float a[kRegMembers];
+};
+
+__device__ inline void walker_prefetch(WalkerRegs& r, const float* A, const float* g,
+                                       const float* fcv, int K, int B, int n, int w,
+                                       int lane) {
+  // one branch-free load pattern for both forms: the CV force fcv [B][n] is
+  // g with one member; without g the A loads re-read that array (unused)
+  const float* src = g ? g : fcv;
+  const int Ke = g ? K : 1;
+  const float* ab = g ? A : fcv;
+#pragma unroll
+  for (int p = 0; p < kRegPasses; ++p) {
+    const int i = min(lane + p * kWave, n - 1);
+#pragma unroll
+    for (int k = 0; k < kRegMembers; ++k)
+      r.g[p][k] = src[((size_t)min(k, Ke - 1) * B + w) * n + i];
+  }
+#pragma unroll
+  for (int k = 0; k < kRegMembers; ++k) r.a[k] = ab[(size_t)min(k, Ke - 1) * B + w];
+}
+
+// Deviation, mean force into fc[n] and A-bar from the prefetched registers.
+__device__ inline double scatter_stats_reg(const WalkerRegs& r, int K, int n, float* fc,
+                                           double& abar, int lane) {
+  double ss = 0.0;
+#pragma unroll
+  for (int p = 0; p < kRegPasses; ++p) {
+    const int i = lane + p * kWave;
+    if (i < n) {
+      const double g0 = r.g[p][0];
+      double dsum = 0.0, gsum = g0;
+#pragma unroll
+      for (int k = 1; k < kRegMembers; ++k)
+        if (k < K) {
+          const double gk = r.g[p][k];
+          dsum += gk - g0;
+          gsum += gk;
+        }
+      const double dbar = dsum / K;
+      double q = dbar * dbar;
+#pragma unroll
+      for (int k = 1; k < kRegMembers; ++k)
+        if (k < K) {
+          const double dk = (double)r.g[p][k] - g0 - dbar;
+          q += dk * dk;
+        }
+      ss += q;
+      fc[i] = (float)(gsum / K);
+    }
+  }
+  ss = wave_sum(ss);
+  abar = 0.0;
+#pragma unroll
+  for (int k = 0; k < kRegMembers; ++k)
+    if (k < K) abar += (double)r.a[k];
+  abar /= K;
+  return sqrt(ss / K);
 }
 
 }  // namespace dev

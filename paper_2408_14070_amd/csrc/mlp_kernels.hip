@@ -9,21 +9,27 @@
 // Kernel design (gfx950):
 //  * One workgroup owns R = 16*RT walkers of ONE member.  Its waves split the
 //    hidden units; each wave streams its units' weight fragments straight
-//    from L2 into VGPRs (no weight reuse inside a workgroup, so no LDS hop).
-//    The weights are the MFMA A operand and the activations the B operand, so
-//    each lane ends up holding 4 consecutive units of one walker: one packed
-//    LDS store per 4 outputs, and the bias enters as the accumulator's
-//    initial value.
+//    from L2 into VGPRs (no weight reuse inside a workgroup, so no LDS hop)
+//    with buffer loads whose k-chunk offset sits in a scalar register.  The
+//    loads run a few k-steps ahead of the MFMAs through a register ring that
+//    scheduling barriers keep in order, and continue across layers (weights
+//    do not depend on activations).  The weights are the MFMA A operand and
+//    the activations the B operand, so each lane ends up holding 4
+//    consecutive units of one walker: one packed LDS store per 4 outputs,
+//    and the bias enters as the accumulator's initial value.
 //  * The activation tile (shared by all waves) lives in LDS, ping-ponged
 //    between two buffers so each layer needs one barrier; it holds x, then
 //    h_1 .. h_L, then the reverse-sweep vectors v_l.
 //  * tanh'(z_l) = 1 - h_l^2 is kept in VGPRs for the reverse sweep (FP32 for
 //    the FP32 path; the operand format for the 16-bit paths, whose 64-walker
 //    tiles would not fit an FP32 copy): nothing goes to HBM between layers.
+//  * Forward weights and biases are stored pre-multiplied by 2/ln 2, so the
+//    epilogue evaluates tanh from exp2 of the GEMM output and one reciprocal.
 //  * Blocks are mapped XCD-aware: when K divides 8, member k runs on XCDs
 //    {k*8/K, ...}, so each XCD's L2 holds only its members' weights.
-//  * On the bias path each workgroup computes the torsions of its walkers
-//    itself from the positions (the encoding never goes through HBM).  The
+//  * On the bias path each workgroup can compute the torsions of its walkers
+//    itself from the positions (small batches: the encoding never goes
+//    through HBM; large batches encode once in a separate kernel).  The
 //    FP64 deviation, switch and chain rule run in a second kernel: handing
 //    the members' results to one workgroup inside this launch needs
 //    device-scope fences, which on gfx950 write back and invalidate the
@@ -362,6 +368,14 @@ __device__ inline void gemm_hidden(f4 (&acc)[RT][CT], WRing<PD, CT / NPASS>& wr,
   }
 }
 
+// Parts the input-gradient GEMM's contraction is cut into: 4 for FP32 (it
+// divides the NP/16 k-steps of every padded width); the 16-bit kernels keep
+// one (their tiles are 4x wider, and the partials would cost registers).
+template <class P, int NP>
+__host__ __device__ constexpr int u0_split() {
+  return sizeof(typename P::T) == 4 ? 4 : 1;
+}
+
 template <class P, int NP, int RT, int NW, int LM, bool FROM_POS>
 __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   using T = typename P::T;
@@ -401,6 +415,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   constexpr int NPASS = WIDE ? RID_NPASS_FP32 : RID_NPASS_16;
   constexpr int CH = CT / NPASS;     // unit tiles per pass of a hidden-layer GEMM
   constexpr int NK = NP / KF;        // k-steps of a hidden-layer GEMM
+  constexpr int U0_SPLIT = u0_split<P, NP>();
   constexpr int PDW = WIDE ? RID_PDH_FP32 : RID_PDH_16;
   constexpr int PDH = (NPASS * NK) % (PDW + 1) == 0 ? PDW : 1;   // its weight pipeline depth
   const int jt0 = wave * CT;
@@ -427,17 +442,45 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
     // scratch lives in buffer 1).  Gather: a lane owns coordinates
     // j = lane + 64m of the unique-atom list and copies them for the walkers
     // of its wave (walkers to the waves in turn); then a lane per torsion.
+    // Coordinates go in chunks of kGatherBatch per lane: the chunk's index
+    // loads, then its coordinate loads for all of the wave's walkers, then
+    // the stores.  Slots past the end are clamped to the last coordinate or
+    // walker of the pass (they store that slot's own value again), so no
+    // load sits behind a branch; walkers past B get zeros.
     float* sp = reinterpret_cast<float*>(smem + p.off_ph0);   // [rc][U][3]
     const int U3 = 3 * p.sv.U;
+    constexpr int WPW = (R + NW - 1) / NW;    // walkers per wave and pass, at most
+    constexpr int QB = WPW < 4 ? WPW : 4;     // walkers per batch of loads
+    static_assert(WPW % QB == 0, "walker batches");
+    const size_t wstride = (size_t)p.sv.n_atoms * 3;
     for (int c0 = 0; c0 < R; c0 += p.rc) {
       const int rc = R - c0 < p.rc ? R - c0 : p.rc;
-      for (int j = lane; j < U3; j += 64) {
-        const int u = j / 3;
-        const size_t a = (size_t)p.sv.uniq[u] * 3 + (j - 3 * u);
-#pragma unroll 4
-        for (int il = wave; il < rc; il += NW) {
-          const int row = row0 + c0 + il;
-          sp[il * U3 + j] = row < p.B ? p.pos[(size_t)row * p.sv.n_atoms * 3 + a] : 0.f;
+      for (int j0 = lane; j0 < U3; j0 += kGatherBatch * 64) {
+        int jc[kGatherBatch], a[kGatherBatch];
+#pragma unroll
+        for (int m = 0; m < kGatherBatch; ++m) {
+          jc[m] = min(j0 + m * 64, U3 - 1);
+          const int u = jc[m] / 3;
+          a[m] = 3 * p.sv.uniq[u] + (jc[m] - 3 * u);
+        }
+#pragma unroll 1
+        for (int q0 = 0; q0 < WPW && wave + q0 * NW < rc; q0 += QB) {
+          float v[QB][kGatherBatch];
+#pragma unroll
+          for (int q = 0; q < QB; ++q) {
+            const int il = min(wave + (q0 + q) * NW, rc - 1);
+            const int row = min(row0 + c0 + il, p.B - 1);
+#pragma unroll
+            for (int m = 0; m < kGatherBatch; ++m) v[q][m] = p.pos[row * wstride + a[m]];
+          }
+#pragma unroll
+          for (int q = 0; q < QB; ++q) {
+            const int il = min(wave + (q0 + q) * NW, rc - 1);
+            const bool in_b = row0 + c0 + il < p.B;
+#pragma unroll
+            for (int m = 0; m < kGatherBatch; ++m)
+              sp[il * U3 + jc[m]] = in_b ? v[q][m] : 0.f;
+          }
         }
       }
       __syncthreads();
@@ -636,24 +679,38 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       __syncthreads();
     }
   }
-  // layer 1 backward: u0 = W_1^T v_1, XP columns spread over the waves.
+  // layer 1 backward: u0 = W_1^T v_1.  Its XP/16 column tiles are too few
+  // to spread evenly over the waves, so each tile's contraction is cut into
+  // U0_SPLIT parts; the parts' partial sums go to LDS (u0 part q at
+  // u0 + q * R * US) and are added in part order when u0 is read.
   // v_1 sits in buffer 1 (2L-1 buffer flips), so u0 may alias buffer 0.
   {
     const T* in = act + cur * BUF;
     const int JT0 = XP / 16;
-    for (int t = wave; t < JT0; t += NW) {
+    constexpr int KQ = NK / U0_SPLIT;         // k-steps per part
+    for (int it = wave; it < JT0 * U0_SPLIT; it += NW) {
+      const int t = it / U0_SPLIT, q = it - t * U0_SPLIT;
       f4 a1[RT][1];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) a1[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
-      gemm_tiles<P, RT, 1, 7>(a1, in, AS,
-                              WSrc{rsrc, (int)p.bwd_off[0] + t * kFragBytes, JT0 * kFragBytes},
-                              NP / KF, lane);
+      gemm_tiles<P, RT, 1, 7>(
+          a1, in + q * KQ * KF, AS,
+          WSrc{rsrc, (int)p.bwd_off[0] + t * kFragBytes + q * KQ * JT0 * kFragBytes,
+               JT0 * kFragBytes},
+          KQ, lane);
+      float* uq0 = u0 + q * R * US;
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
-        *reinterpret_cast<f4*>(u0 + (rt * 16 + wl) * US + t * 16 + uq) = a1[rt][0];
+        *reinterpret_cast<f4*>(uq0 + (rt * 16 + wl) * US + t * 16 + uq) = a1[rt][0];
     }
   }
   __syncthreads();
+  auto u0_at = [&](int i, int c) {
+    float v = u0[i * US + c];
+#pragma unroll
+    for (int q = 1; q < U0_SPLIT; ++q) v += u0[q * R * US + i * US + c];
+    return v;
+  };
   // A = sum of the waves' partial dot products + b_o
   for (int i = threadIdx.x; i < R; i += NW * 64) {
     float a = p.bo[k];
@@ -667,7 +724,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
     if (row < p.B) {
       const float cs = xs[i * X2 + c];
       const float sn = xs[i * X2 + n + c];
-      const float gv = -sn * u0[i * US + c] + cs * u0[i * US + n + c];
+      const float gv = -sn * u0_at(i, c) + cs * u0_at(i, n + c);
       p.g_out[((size_t)k * p.B + row) * n + c] = gv;
     }
   }
@@ -749,10 +806,10 @@ inline unsigned align16(size_t v) { return (unsigned)((v + 15) / 16 * 16); }
 
 // LDS layout of one instantiation; returns the total bytes.
 size_t mlp_layout(int R, int NW, int AS, size_t tsize, int XP, int n, int U,
-                  bool from_pos, int NPw, MlpArgs& a) {
+                  bool from_pos, int NPw, int u0_parts, MlpArgs& a) {
   const size_t buf = (size_t)R * AS * tsize;
   size_t off = 2 * buf;
-  const size_t u0_bytes = (size_t)R * (XP + 4) * 4;
+  const size_t u0_bytes = (size_t)u0_parts * R * (XP + 4) * 4;
   if (u0_bytes <= buf) {
     a.off_u0 = 0;                       // buffer 0 is free in the last GEMM
   } else {
@@ -782,7 +839,7 @@ size_t lds_bytes(const rid_ensemble_impl& e, const TorsionInput* tin) {
   const int AW = NP > e.XP ? NP : e.XP;
   const int AS = AW + RID_ACT_PAD_BYTES / (int)sizeof(T);
   return mlp_layout(16 * RT, NW, AS, sizeof(T), e.XP, e.n_cv,
-                    tin ? tin->sys->n_uniq : 0, tin != nullptr, NP, a);
+                    tin ? tin->sys->n_uniq : 0, tin != nullptr, NP, u0_split<P, NP>(), a);
 }
 
 template <class P, int NP, int RT, int NW, int LM>
@@ -797,7 +854,8 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
   const int AS = AW + RID_ACT_PAD_BYTES / (int)sizeof(T);
   MlpArgs a{};
   const size_t lds = mlp_layout(R, NW, AS, sizeof(T), e.XP, e.n_cv,
-                                from_pos ? tin->sys->n_uniq : 0, from_pos, NP, a);
+                                from_pos ? tin->sys->n_uniq : 0, from_pos, NP,
+                                u0_split<P, NP>(), a);
   if (lds > 160 * 1024)
     return fail(RID_EUNSUPPORTED, "shape too large for the MLP kernel's LDS");
   if (from_pos && a.rc < 1)

@@ -110,6 +110,10 @@ struct rid_system_impl {
   // unique atoms touched by torsions (sorted) and quads in local indices
   std::vector<int32_t> uniq;
   int n_uniq = 0;
+  // The device tables below are consecutive pieces of ONE allocation, in
+  // this order (uniq | lquads | csr_ptr | csr_ent | atom_local), so a kernel
+  // can copy any prefix of them into LDS as one flat array.
+  int32_t* d_tables = nullptr;
   int32_t* d_uniq = nullptr;         // [n_uniq]
   int32_t* d_lquads = nullptr;       // [n_cv][4] local indices into uniq
   // inverse map local atom -> (cv, slot) entries, CSR, fixed order
