@@ -167,6 +167,40 @@ def test_bias_force_network_shapes(torch, rid, widths, K):
         assert np.all(out["eps"].cpu().numpy() == 0.0)
 
 
+def _scatter_shape(shape):
+    if shape == "K10":
+        return workload("peptide20", 24, seed=8, K=10, widths=[64, 64], bias_std=0.1)
+    if shape == "peptide61":
+        return workload("peptide61", 24, seed=8, widths=[64, 64], bias_std=0.1)
+    sys_ = ridgen.chain_system(70, 10)          # 138 torsions, 700 atoms
+    pos = ridgen.f32(ridgen.chain_coords(sys_, 24, 8))
+    params = ridgen.xavier_ensemble(2 * sys_.n_cv, [64, 64], 4, 1000, 0.1)
+    return sys_, pos, params, [64, 64], 4
+
+
+# The scatter keeps a walker's member results in registers for up to 8
+# members and 128 CVs and reads them from memory beyond that, and gathers
+# the torsion atoms in one batch only while 3U <= 256 coordinates.  These
+# shapes take the other branches: 10 members; 120 CVs (several gather
+# batches, also in the MLP kernel's own gather); 138 CVs.
+@pytest.mark.parametrize("shape", ["K10", "peptide61", "cv138"])
+def test_bias_force_scatter_variants(torch, rid, shape):
+    sys_, pos, params, widths, K = _scatter_shape(shape)
+    S, E = _make(rid, sys_, params, widths, K)
+    ref = _bias_ref(sys_, pos, params, widths, K, 2.0, 3.0)
+    out = rid.bias_force(S, E, _dev(torch, pos), 2.0, 3.0)
+    torch.cuda.synchronize()
+    assert_forces(out["F"].cpu().numpy(), ref["F"], FP32_TOL, shape)
+    scale = np.abs(ref["g"]).max()
+    assert np.max(np.abs(out["eps"].cpu().numpy() - ref["eps"])) <= FP32_TOL * scale
+    if shape == "cv138":   # the CV-force form with more CVs than registers hold
+        fcv = ridgen.f32(np.random.default_rng(2).normal(size=(len(pos), sys_.n_cv)))
+        F = rid.cv_apply_force(S, _dev(torch, pos), _dev(torch, fcv))
+        torch.cuda.synchronize()
+        ref2 = O.apply_cv_force(pos.astype(np.float64), sys_.quads, fcv.astype(np.float64))
+        assert_forces(F.cpu().numpy(), ref2, FP32_TOL, "apply_force 138 CVs")
+
+
 def test_identical_members_have_exactly_zero_deviation(torch, rid):
     sys_, pos, p1, widths, _ = workload("peptide20", 64, seed=7, K=1, bias_std=0.1)
     params = np.concatenate([p1] * 4)
