@@ -922,8 +922,10 @@ rid_status launch_16bit(const rid_ensemble_impl& e, const float* x, int B,
   return fail(RID_EUNSUPPORTED, "no kernel for this padded width");
 }
 
+// FP32 at width 256: 16 waves of one unit tile each (4 per SIMD) hide the
+// latencies of the short stages better than 8 waves of two tiles.
 #ifndef RID_F32_NW256
-#define RID_F32_NW256 8
+#define RID_F32_NW256 16
 #endif
 
 rid_status dispatch(const rid_ensemble_impl& e, const float* x, int B, float* A_out,
