@@ -36,6 +36,15 @@ Functions and what pins them (tests/test_oracle_*.py):
   bias_force          whole path, atoms -> forces
                       pinned: force = -grad E by FD (sigma frozen), zero
                       total force and torque per walker
+  mlp_input_hvp       Hessian-vector product of a model in its input
+                      pinned: central FD of dA/dx along the vector
+  deviation_gradient  d eps / d s (conservative switching)
+                      pinned: central FD of eps in s
+  bias_force_conservative
+                      -grad of E = -sigma(eps) Abar with the switch
+                      differentiated too
+                      pinned: force = -grad E by FD inside the switching
+                      band; equals bias_force where sigma is 0 or 1
   train_loss_grad     gradient of the mean-force loss in the weights
                       pinned: central FD on every parameter; exact least-
                       squares solution of the linear model has zero gradient
@@ -256,6 +265,94 @@ def bias_energy_frozen(pos, quads, models, sigma):
     s = dihedral(pos, quads)
     A, _ = ensemble_mean_force(models, s)
     return -np.asarray(sigma) * np.mean(A, axis=1)
+
+
+# --------------------------------------------------------------------------
+# conservative switching: the switch differentiated as well
+# --------------------------------------------------------------------------
+def switch_slope(eps, eps0, eps1):
+    """d sigma / d eps of the cosine switch: -pi/(2 (eps1-eps0)) sin(pi t)
+    inside the band (eps0 <= eps < eps1), 0 outside."""
+    eps = np.asarray(eps, dtype=np.float64)
+    t = (eps - eps0) / (eps1 - eps0)
+    slope = -0.5 * math.pi / (eps1 - eps0) * np.sin(math.pi * t)
+    return np.where((eps >= eps0) & (eps < eps1), slope, 0.0)
+
+
+def mlp_input_hvp(model, x, rho):
+    """Hessian-vector product of one model in its input: H(x) rho with
+    H = d^2 A / dx^2, as the forward-mode derivative of the reverse sweep
+    of ``mlp_value_and_grad`` along rho.  Forward: h_l and its tangent
+    hd_l = (1 - h_l^2) W_l hd_{l-1} (hd_0 = rho).  Reverse: v_L = wo (1 -
+    h_L^2), u_{l-1} = W_l^T v_l, v_l = u_l (1 - h_l^2); its tangent uses
+    d(1 - h^2) = -2 h hd.  x, rho: [B][D] -> [B][D]."""
+    Ws, bs, wo, bo = model
+    hs = [np.asarray(x, dtype=np.float64)]
+    hds = [np.asarray(rho, dtype=np.float64)]
+    for W, b in zip(Ws, bs):
+        h = np.tanh(hs[-1] @ W.T + b)
+        hds.append((1.0 - h ** 2) * (hds[-1] @ W.T))
+        hs.append(h)
+    u = np.broadcast_to(wo, hs[-1].shape)
+    ud = np.zeros_like(hs[-1])
+    for l in range(len(Ws), 0, -1):
+        v = u * (1.0 - hs[l] ** 2)
+        vd = ud * (1.0 - hs[l] ** 2) - 2.0 * u * hs[l] * hds[l]
+        u = v @ Ws[l - 1]
+        ud = vd @ Ws[l - 1]
+    return ud
+
+
+def deviation_gradient(models, s):
+    """d eps / d s of the model deviation (the reading of model_deviation).
+
+    With w_k = (g_k - gbar) / (K eps), d eps/ds = sum_k H_k w_k, where H_k is
+    the Hessian of A_k in s.  In the input x = [cos s | sin s], with
+    J = dx/ds and rho = J w: H_k w = J^T H_x rho + (d rho/ds)^T dA/dx, the
+    second term being -cos s_i w_i u0[i] - sin s_i w_i u0[n+i].  eps = 0
+    gives 0.  s: [B][n] -> (eps [B], deps_ds [B][n])."""
+    s = np.asarray(s, dtype=np.float64)
+    n = s.shape[-1]
+    x = embed(s)
+    _, g = ensemble_mean_force(models, s)
+    gbar, eps = model_deviation(g)
+    K = len(models)
+    out = np.zeros_like(s)
+    safe = np.where(eps > 0, eps, 1.0)
+    for k, m in enumerate(models):
+        w = (g[:, k, :] - gbar) / (K * safe[:, None])
+        rho = np.concatenate([-np.sin(s) * w, np.cos(s) * w], axis=-1)
+        _, u0 = mlp_value_and_grad(m, x)
+        hx = mlp_input_hvp(m, x, rho)
+        out += (-np.sin(s) * hx[:, :n] + np.cos(s) * hx[:, n:]
+                - w * (np.cos(s) * u0[:, :n] + np.sin(s) * u0[:, n:]))
+    out[eps == 0] = 0.0
+    return eps, out
+
+
+def bias_force_conservative(pos, quads, models, eps0, eps1, n_atoms=None):
+    """Bias force that is exactly -grad E with E = -sigma(eps) Abar,
+    including the switching band: f = sigma gbar + Abar sigma'(eps) deps/ds.
+    Outside the band it equals bias_force.  Same outputs as bias_force."""
+    out = bias_force(pos, quads, models, eps0, eps1, n_atoms)
+    s = out["s"]
+    _, deps = deviation_gradient(models, s)
+    Abar = np.mean(out["A"], axis=1)
+    fcv = out["sigma"][:, None] * out["gbar"] + \
+        (Abar * switch_slope(out["eps"], eps0, eps1))[:, None] * deps
+    out["fcv"] = fcv
+    out["F"] = apply_cv_force(pos, quads, fcv, n_atoms)
+    return out
+
+
+def bias_energy(pos, quads, models, eps0, eps1):
+    """E(r) = -sigma(eps(s(r))) Abar(s(r)), the switch evaluated at r
+    (finite-difference target of the conservative force)."""
+    s = dihedral(pos, quads)
+    A, g = ensemble_mean_force(models, s)
+    _, eps = model_deviation(g)
+    sigma, _ = switch(eps, eps0, eps1)
+    return -sigma * np.mean(A, axis=1)
 
 
 # --------------------------------------------------------------------------
