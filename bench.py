@@ -58,6 +58,14 @@ def mlp_flops_per_walker(n_cv, widths, K):
     return K * (2 * layer_flops(n_cv, widths) + 2 * widths[-1])
 
 
+def conservative_flops_per_walker(n_cv, widths, K):
+    """The frozen-switch path, plus the input-mode sweeps of every member:
+    forward, primal backward, tangent forward (one layer product set each)
+    and the adjoint propagation of the stacked primal/tangent rows down to
+    the input (two per layer)."""
+    return mlp_flops_per_walker(n_cv, widths, K) + K * 5 * layer_flops(n_cv, widths)
+
+
 def train_flops_per_sample(n_cv, widths, K):
     """Forward, primal backward, tangent forward (3 sweeps), adjoint
     propagation through layers 2..L (2 products each) and the two weight-
@@ -313,6 +321,38 @@ def bench_training(rid, torch, steps=20, warmup=3):
     }
 
 
+def bench_conservative(rid, torch, case, steps=40, warmup=5):
+    """Conservative switching on the headline workload, with the band placed
+    over the ensemble's deviations so every walker takes the switch's own
+    gradient; the frozen-switch path at the same thresholds for comparison."""
+    S, E, P, out, B = case["S"], case["E"], case["P"], case["out"], case["B"]
+    rid.bias_force(S, E, P, 1e29, 2e29, out=out)
+    torch.cuda.synchronize()
+    eps = out["eps"].cpu().numpy()
+    e0, e1 = 0.5 * float(eps.min()), 2.0 * float(eps.max())
+    res = {}
+    for name, cons in (("frozen", False), ("conservative", True)):
+        for _ in range(warmup):
+            rid.bias_force(S, E, P, e0, e1, out=out, conservative=cons)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rid.bias_force(S, E, P, e0, e1, out=out, conservative=cons)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / steps
+    sys_ = case["sys"]
+    fl = conservative_flops_per_walker(sys_.n_cv, case["widths"], case["K"]) * B
+    st = res["conservative"]
+    return {"workload": "conservative switching (force = -grad E inside the band: "
+                        "Abar sigma'(eps) d eps/ds added through per-member Hessian-vector "
+                        "products), same chain / ensemble / 1024 walkers, band over all "
+                        "walkers, FP32",
+            "value": B / st, "unit": "walker-steps/s", "ms_per_step": 1e3 * st,
+            "frozen_ms_per_step": 1e3 * res["frozen"],
+            "flop_per_step": fl, "achieved_tflops": fl / st / 1e12,
+            "frac_fp32_peak": fl / st / 1e12 / FP32_PEAK_TFLOPS}
+
+
 def bench_labels(rid, torch, reps=20):
     M, T, n = 1024, 500, 38
     traj, s0, _ = ridgen.restrained_traj(M, T, n, 500.0, seed=9)
@@ -500,6 +540,8 @@ def main():
                                                 steps_b, wb)
         rec["precision_form_fp16"] = bench_precision(rid, torch, sys20, rid.RID_FP16, "FP16",
                                                      steps_b, wb)
+        log("conservative switching")
+        rec["conservative"] = bench_conservative(rid, torch, case)
         log("training")
         rec["training"] = bench_training(rid, torch)
         log("labels")

@@ -162,6 +162,30 @@ rid_status rid_bias_force(rid_system sys, rid_ensemble ens, const float* d_pos,
                           uint8_t* d_flags, rid_stream stream);
 
 /* ------------------------------------------------------------------------
+ * rid_bias_force_conservative - the same bias with the switch differentiated
+ * too, so the force is exactly -grad E of E = -sigma(eps) Abar everywhere,
+ * including the switching band ("Overall workflow setting": trust levels;
+ * "Development of the protocol": bias only where the ensemble agrees):
+ *   f_i = sigma gbar_i + Abar sigma'(eps) d eps/ds_i,
+ *   d eps/ds = sum_k H_k (g_k - gbar) / (K eps)   (H_k: Hessian of A_k in s)
+ *   F_a = sum_i f_i ds_i/dr_a.
+ * Where sigma' = 0 (eps < eps0 or eps >= eps1) the force equals
+ * rid_bias_force's up to rounding.  The Hessian-vector products come from
+ * FP32 tangent and adjoint sweeps of the members' FP32 master weights (also
+ * for 16-bit ensembles, whose A and g come from the 16-bit kernels); they
+ * cost several forward passes, over every walker.
+ * Arguments, outputs, errors and flags as rid_bias_force.  Uses the
+ * ensemble's training workspace: not concurrent with training or gradient
+ * calls on the same ensemble.
+ * ------------------------------------------------------------------------ */
+rid_status rid_bias_force_conservative(rid_system sys, rid_ensemble ens,
+                                       const float* d_pos, int B, float eps0,
+                                       float eps1, float* d_force,
+                                       float* d_energy, float* d_eps,
+                                       float* d_sigma, uint8_t* d_flags,
+                                       rid_stream stream);
+
+/* ------------------------------------------------------------------------
  * rid_cv_apply_force - chain a CV-space force to the atoms alone:
  *   F_a = sum_i f_i ds_i/dr_a.
  *   d_fcv [B][n_cv]; d_force [B][n_atoms][3] OVERWRITTEN.

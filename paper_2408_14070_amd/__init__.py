@@ -29,7 +29,8 @@ EXPORTS = (
     "rid_last_error", "rid_version", "rid_system_create", "rid_system_destroy",
     "rid_packed_param_count", "rid_ensemble_create", "rid_ensemble_get_params",
     "rid_ensemble_set_params", "rid_ensemble_step", "rid_ensemble_destroy",
-    "rid_cv_eval", "rid_model_dev", "rid_bias_force", "rid_cv_apply_force",
+    "rid_cv_eval", "rid_model_dev", "rid_bias_force", "rid_bias_force_conservative",
+    "rid_cv_apply_force",
     "rid_mf_train_step", "rid_lr_exponential", "rid_mf_label",
     "rid_profile_enable", "rid_profile_read", "rid_mf_loss_grad", "rid_mf_grad",
     "rid_server_create", "rid_server_register", "rid_server_submit", "rid_server_wait",
@@ -83,6 +84,7 @@ def lib():
         "rid_cv_eval": (i, [vp, vp, i, vp, vp, vp]),
         "rid_model_dev": (i, [vp, vp, i, vp, vp, vp, vp, vp]),
         "rid_bias_force": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
+        "rid_bias_force_conservative": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
         "rid_cv_apply_force": (i, [vp, vp, vp, i, vp, vp]),
         "rid_mf_train_step": (i, [vp, vp, vp, i, f, vp, vp]),
         "rid_lr_exponential": (d, [i64, d, i, d]),
@@ -239,8 +241,9 @@ def model_dev(ens: Ensemble, s, stream=None, want_g=True):
 
 
 def bias_force(system: System, ens: Ensemble, pos, eps0: float, eps1: float,
-               stream=None, out=None):
-    """rid_bias_force: pos [B][n_atoms][3] -> dict(F, E, eps, sigma, flags)."""
+               stream=None, out=None, conservative=False):
+    """rid_bias_force (or rid_bias_force_conservative when ``conservative``):
+    pos [B][n_atoms][3] -> dict(F, E, eps, sigma, flags)."""
     torch = _torch()
     B = pos.shape[0]
     _f32(pos, (B, system.n_atoms, 3), "pos")
@@ -253,10 +256,10 @@ def bias_force(system: System, ens: Ensemble, pos, eps0: float, eps1: float,
             sigma=torch.empty(B, dtype=torch.float32, device=dev),
             flags=torch.empty(B, dtype=torch.uint8, device=dev),
         )
-    _check(lib().rid_bias_force(system.handle, ens.handle, _ptr(pos), B, float(eps0),
-                                float(eps1), _ptr(out["F"]), _ptr(out.get("E")),
-                                _ptr(out.get("eps")), _ptr(out.get("sigma")),
-                                _ptr(out.get("flags")), _stream(stream)))
+    fn = lib().rid_bias_force_conservative if conservative else lib().rid_bias_force
+    _check(fn(system.handle, ens.handle, _ptr(pos), B, float(eps0), float(eps1),
+              _ptr(out["F"]), _ptr(out.get("E")), _ptr(out.get("eps")),
+              _ptr(out.get("sigma")), _ptr(out.get("flags")), _stream(stream)))
     return out
 
 

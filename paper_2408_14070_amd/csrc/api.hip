@@ -128,6 +128,7 @@ static void free_ensemble(rid_ensemble_impl& e) {
   e.ws_A.release();
   e.ws_g.release();
   e.ws_train.release();
+  e.ws_cons.release();
 }
 
 }  // namespace rid
@@ -402,6 +403,21 @@ rid_status rid_bias_force(rid_system sys, rid_ensemble ens, const float* d_pos,
   return launch_bias_scatter(s, e.K, d_pos, B, e.ws_A.as<float>(), e.ws_g.as<float>(),
                              nullptr, eps0, eps1, d_force, d_energy, d_eps, d_sigma,
                              d_flags, st);
+}
+
+rid_status rid_bias_force_conservative(rid_system sys, rid_ensemble ens,
+                                       const float* d_pos, int B, float eps0,
+                                       float eps1, float* d_force, float* d_energy,
+                                       float* d_eps, float* d_sigma, uint8_t* d_flags,
+                                       rid_stream stream) {
+  if (!sys || !ens || !d_pos || !d_force) return fail(RID_EINVAL, "NULL argument");
+  if (B < 1) return fail(RID_EINVAL, "B must be >= 1");
+  if (!(eps0 >= 0.f) || !(eps0 < eps1))
+    return fail(RID_EINVAL, "trust levels need 0 <= eps0 < eps1");
+  if (sys->impl.n_cv != ens->impl.n_cv)
+    return fail(RID_EINVAL, "system and ensemble disagree on n_cv");
+  return launch_bias_conservative(sys->impl, ens->impl, d_pos, B, eps0, eps1, d_force,
+                                  d_energy, d_eps, d_sigma, d_flags, (hipStream_t)stream);
 }
 
 rid_status rid_cv_apply_force(rid_system sys, const float* d_pos,

@@ -146,7 +146,7 @@ struct rid_ensemble_impl {
   float* d_bo = nullptr;             // [K]
   // scratch
   bool frag_dirty = false;           // masters changed since the last pack
-  DevBuf ws_x, ws_A, ws_g, ws_train;
+  DevBuf ws_x, ws_A, ws_g, ws_train, ws_cons;
 };
 
 // ---------------------------------------------------------------------------
@@ -176,9 +176,23 @@ rid_status launch_bias_scatter(const rid_system_impl& s, int K, const float* pos
 // rec_stride > 0: walker records -- walker w's forces start at
 // force + w * rec_stride and energy/eps/sigma use the same stride.
 rid_status pack_ensemble_weights(rid_ensemble_impl& e, hipStream_t st);
+// Input mode of the mean-force sweeps: with an upstream gradient rho
+// [B][K][n], J_k = sum_b rho_kb . g_k(s_b) differentiated in the network
+// input x with rho_x held fixed.  Results point into the ensemble's training
+// workspace: lam_x [K][2B][2n] (rows [0, B) of member k hold d J_k / dx,
+// member stride slab_lam) and u0 [K][B][2n] (dA_k/dx).
+struct InputHvp {
+  const float* lam_x = nullptr;
+  const float* u0 = nullptr;
+  long long slab_lam = 0;
+};
 rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
                           const float* rho, int B, float* loss, float* grad_out,
-                          float** grad_used, hipStream_t st);
+                          float** grad_used, hipStream_t st, InputHvp* hvp = nullptr);
+rid_status launch_bias_conservative(const rid_system_impl& s, rid_ensemble_impl& e,
+                                    const float* pos, int B, float eps0, float eps1,
+                                    float* force, float* energy, float* eps, float* sigma,
+                                    uint8_t* flags, hipStream_t st);
 rid_status launch_train_step(rid_ensemble_impl& e, const float* s,
                              const float* F, int B, float lr, float* loss,
                              hipStream_t st);

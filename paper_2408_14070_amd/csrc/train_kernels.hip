@@ -451,7 +451,12 @@ rid_status colsum(const float* X, long long slab, int B, int w, int K, float* pa
 // Returns the gradient pointer through *grad_used.
 rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
                           const float* rho, int B, float* loss, float* grad_out,
-                          float** grad_used, hipStream_t st) {
+                          float** grad_used, hipStream_t st, InputHvp* hvp) {
+  // input mode (hvp != null, rho given): the same primal, tangent and
+  // adjoint sweeps, but the adjoint runs down to the input instead of
+  // forming weight gradients
+  const bool input_mode = hvp != nullptr;
+  if (input_mode && !rho) return fail(RID_EINVAL, "input mode needs an upstream gradient");
   const int K = e.K, L = e.L, n = e.n_cv, X = 2 * n;
   std::vector<int> w(L + 1);
   w[0] = X;
@@ -505,7 +510,7 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   float* W = e.ws_train.as<float>();
   float* P = e.d_master;
   float* G = grad_out ? grad_out : W + grad;
-  *grad_used = G;
+  if (grad_used) *grad_used = G;
   ProfScope ps(kProfTrain, st);
 
   auto slab = [&](int l) { return 2LL * B * w[l]; };
@@ -562,7 +567,7 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
     g.M = B; g.N = w[l]; g.Kc = w[l - 1]; g.batch = K; g.mode = EPI_TANGENT;
     if ((rs = gemm(g, st)) != RID_OK) return rs;
   }
-  // ---- adjoint sweep with weight gradients ----
+  // ---- adjoint sweep with weight gradients (or down to the input) ----
   long long lin = lamA, lout = lamB;
   for (int l = L; l >= 1; --l) {
     hipLaunchKernelGGL(adjoint_kernel, dim3(grid1d((long long)K * B * w[l])), dim3(256), 0, st,
@@ -570,7 +575,7 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
                        (int)wo_off, l == L ? 1 : 0, w[l], B, K, W + sbuf, 2LL * B * w[l]);
     RID_HIP(hipGetLastError());
     // dW_l = S^T [h_{l-1}; hd_{l-1}]  (contraction over 2B rows, split)
-    {
+    if (!input_mode) {
       GemmArgs g{};
       g.A = W + sbuf; g.sAb = 2LL * B * w[l]; g.sAm = 1; g.sAk = w[l];
       g.Bm = W + hh[l - 1]; g.sBb = slab(l - 1); g.sBk = w[l - 1]; g.sBn = 1;
@@ -586,10 +591,11 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
       RID_HIP(hipGetLastError());
     }
     // db_l = sum_b lam_z
-    if ((rs = colsum(W + sbuf, 2LL * B * w[l], B, w[l], K, W + cpart, G, pm,
+    if (!input_mode &&
+        (rs = colsum(W + sbuf, 2LL * B * w[l], B, w[l], K, W + cpart, G, pm,
                      (int)b_off[l - 1], st)) != RID_OK)
       return rs;
-    if (l > 1) {
+    if (l > 1 || input_mode) {
       // [lam_h ; lam_hd]_{l-1} = [lam_z ; lam_zd] W_l
       GemmArgs g{};
       g.A = W + sbuf; g.sAb = 2LL * B * w[l]; g.sAm = w[l]; g.sAk = 1;
@@ -599,6 +605,13 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
       if ((rs = gemm(g, st)) != RID_OK) return rs;
       std::swap(lin, lout);
     }
+  }
+  if (input_mode) {
+    // lin: [lam_h0 ; lam_hd0] per member (rows [0, B): d J / dx); vin: u0
+    hvp->lam_x = W + lin;
+    hvp->u0 = W + vin;
+    hvp->slab_lam = 2LL * B * X;
+    return RID_OK;
   }
   // dw_o = sum_b hd_L ; db_o = 0
   if ((rs = colsum(W + hh[L] + (long long)B * w[L], slab(L), B, w[L], K, W + cpart, G, pm,
