@@ -66,3 +66,50 @@ def assert_forces(F_gpu, F_ref, tol, what="force"):
     if trms is not None:
         assert rms <= trms, f"{what} rms rel err {rms:.3e} > {trms}"
     return err, rms
+
+
+def basin_fitted_ensemble(n=38, K=8, widths=(512, 512, 512, 512), n_fit=300, n_eval=4096,
+                          seed=31):
+    """A trained-like ensemble with the deviation structure of a real RiD
+    ensemble, built without the GPU path: each member keeps its own Xavier
+    hidden layers and gets output weights fitted (ridge least squares, FP64)
+    to mean-force labels drawn inside one basin (every CV within 1 rad of a
+    seeded centre; labels = -grad of the analytic PMF + noise 0.5).  The mean
+    force is linear in the output weights, so the fit is closed form: members
+    agree inside the basin and extrapolate differently outside it.
+
+    Returns (params f32 packed, evaluation CVs [n_eval][n] f32 at seeded
+    distances 0.3..pi from the centre, oracle eps of those CVs)."""
+    widths = list(widths)
+    models = ridgen.unpack_params(ridgen.xavier_ensemble(2 * n, widths, K, 1000),
+                                  2 * n, widths, K)
+    pmf = ridgen.analytic_pmf(n, 3)
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(-np.pi, np.pi, n)
+
+    def wrap(a):
+        return np.mod(a + np.pi, 2 * np.pi) - np.pi
+
+    s = wrap(mu + rng.uniform(-1.0, 1.0, (n_fit, n)))
+    F = -pmf.grad(s) + rng.normal(0.0, 0.5, s.shape)
+    fitted = []
+    idx = np.arange(n)
+    for Ws, bs, _, _ in models:
+        # d h_L / d s_i for every CV i (forward-mode through the layers)
+        h = O.embed(s)
+        hd = np.zeros((n_fit, n, 2 * n))
+        hd[:, idx, idx] = -np.sin(s)
+        hd[:, idx, n + idx] = np.cos(s)
+        for W, b in zip(Ws, bs):
+            h = np.tanh(h @ W.T + b)
+            hd = (1.0 - h ** 2)[:, None, :] * (hd @ W.T)
+        J = hd.reshape(n_fit * n, -1)
+        wo = np.linalg.solve(J.T @ J + 1e-3 * np.eye(J.shape[1]), J.T @ F.reshape(-1))
+        fitted.append((Ws, bs, wo, 0.0))
+    params = ridgen.f32(ridgen.pack_params(fitted))
+    r = rng.uniform(0.3, np.pi, (n_eval, 1))
+    s_eval = ridgen.f32(wrap(mu + r * rng.uniform(-1.0, 1.0, (n_eval, n))))
+    models32 = ridgen.unpack_params(params, 2 * n, widths, K)
+    _, g = O.ensemble_mean_force(models32, s_eval.astype(np.float64))
+    _, eps = O.model_deviation(g)
+    return params, s_eval, eps
