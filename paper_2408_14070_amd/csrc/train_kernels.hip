@@ -68,6 +68,7 @@ struct TileLoad {
   float v[NS];
   __device__ inline void load(const float* X, long long sR, long long sK, int mode, int r0,
                               int R, int kb, int k_end, int tid) {
+    if (NS < 4 && mode >= 2) mode -= 2;   // too few elements per thread for float4
     if (mode >= 2) {
 #pragma unroll
       for (int j = 0; j < NS / 4; ++j) {
@@ -92,6 +93,7 @@ struct TileLoad {
     }
   }
   __device__ inline void store(float (*S)[LDK], int mode, int tid) const {
+    if (NS < 4 && mode >= 2) mode -= 2;
     if (mode >= 2) {
 #pragma unroll
       for (int j = 0; j < NS / 4; ++j) {
@@ -253,32 +255,38 @@ __global__ void vlast_kernel(const float* HHL, long long slab, const float* mast
 // g = chain(u0, s); residual; per-row squared residual; rho_x into the
 // tangent half of the stacked input slab.  With an upstream gradient
 // rho [B][K][n] given instead of labels, rho_x is built from it directly.
-__global__ void residual_kernel(const float* s, const float* F, const float* rho_in,
-                                const float* U0, int B, int n, int K, float* HH0,
-                                long long slab, float* loss_rows) {
-  const long long total = (long long)K * B;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int k = (int)(e / B), b = (int)(e - (long long)k * B);
-    const float* u = U0 + e * 2 * n;
-    float* rx = HH0 + k * slab + ((long long)B + b) * 2 * n;
-    float acc = 0.f;
-    for (int i = 0; i < n; ++i) {
-      float sn, cs;
-      sincosf(s[(long long)b * n + i], &sn, &cs);
-      float rho;
-      if (rho_in) {
-        rho = rho_in[((long long)b * K + k) * n + i];
-      } else {
-        const float gi = -sn * u[i] + cs * u[n + i];
-        const float ri = gi - F[(long long)b * n + i];
-        acc += ri * ri;
-        rho = 2.f * ri / (float)B;
-      }
-      rx[i] = -sn * rho;
-      rx[n + i] = cs * rho;
+// One wave per (member, sample) row, lanes over the CVs; the row's squared
+// residual is a fixed-order shuffle sum over the lanes.
+constexpr int kResWaves = 4;
+__global__ __launch_bounds__(kResWaves * 64) void residual_kernel(
+    const float* s, const float* F, const float* rho_in, const float* U0, int B, int n,
+    int K, float* HH0, long long slab, float* loss_rows) {
+  const long long e = (long long)blockIdx.x * kResWaves + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (e >= (long long)K * B) return;
+  const int k = (int)(e / B), b = (int)(e - (long long)k * B);
+  const float* u = U0 + e * 2 * n;
+  float* rx = HH0 + k * slab + ((long long)B + b) * 2 * n;
+  float acc = 0.f;
+  for (int i = lane; i < n; i += 64) {
+    float sn, cs;
+    sincosf(s[(long long)b * n + i], &sn, &cs);
+    float rho;
+    if (rho_in) {
+      rho = rho_in[((long long)b * K + k) * n + i];
+    } else {
+      const float gi = -sn * u[i] + cs * u[n + i];
+      const float ri = gi - F[(long long)b * n + i];
+      acc += ri * ri;
+      rho = 2.f * ri / (float)B;
     }
-    if (loss_rows) loss_rows[e] = acc;
+    rx[i] = -sn * rho;
+    rx[n + i] = cs * rho;
+  }
+  if (loss_rows) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+    if (lane == 0) loss_rows[e] = acc;
   }
 }
 
@@ -415,12 +423,18 @@ rid_status gemm(const GemmArgs& g0, hipStream_t st) {
   g.modeA = load_mode(g.A, g.sAm, g.sAk, g.sAb, g.M, g.Kc);
   g.modeB = load_mode(g.Bm, g.sBn, g.sBk, g.sBb, g.N, g.Kc);
   // 128 x 128 tiles only when they still give every CU several workgroups
-  // (one 4-wave workgroup per CU leaves one wave per SIMD to hide latency)
+  // (one 4-wave workgroup per CU leaves one wave per SIMD to hide latency);
+  // 32 x 64 tiles when 64 x 64 would leave CUs with fewer than two
   const long long tiles128 =
       (long long)((g.N + 127) / 128) * ((g.M + 127) / 128) * g.batch * g.ksplit;
+  const long long tiles64 =
+      (long long)((g.N + 63) / 64) * ((g.M + 63) / 64) * g.batch * g.ksplit;
   if (g.M >= 128 && g.N >= 128 && tiles128 >= 1024) {
     dim3 grid((g.N + 127) / 128, (g.M + 127) / 128, g.batch * g.ksplit);
     hipLaunchKernelGGL((gemm_f32_kernel<128, 128>), grid, dim3(kThreads), 0, st, g);
+  } else if (g.M > 32 && tiles64 < 512) {
+    dim3 grid((g.N + 63) / 64, (g.M + 31) / 32, g.batch * g.ksplit);
+    hipLaunchKernelGGL((gemm_f32_kernel<32, 64>), grid, dim3(kThreads), 0, st, g);
   } else {
     dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.batch * g.ksplit);
     hipLaunchKernelGGL((gemm_f32_kernel<64, 64>), grid, dim3(kThreads), 0, st, g);
@@ -548,7 +562,9 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
     std::swap(vin, vout);
   }
   // vin now holds u0 [K][B][2n]
-  hipLaunchKernelGGL(residual_kernel, dim3(grid1d((long long)K * B)), dim3(256), 0, st,
+  hipLaunchKernelGGL(residual_kernel,
+                     dim3((unsigned)(((long long)K * B + kResWaves - 1) / kResWaves)),
+                     dim3(kResWaves * 64), 0, st,
                      s, F, rho, W + vin, B, n, K, W + hh[0], slab(0),
                      rho ? nullptr : W + lrows);
   RID_HIP(hipGetLastError());
