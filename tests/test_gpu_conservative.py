@@ -83,6 +83,19 @@ def test_conservative_force_parity_in_the_band(torch, rid, kind, widths, K):
     assert O.max_rel_err(frozen, ref["F"]) > 1e-2
 
 
+def test_conservative_full_size_bench_config(torch, rid):
+    # the benchmarked configuration: 1024 walkers, headline ensemble, the band
+    # placed over every walker's deviation
+    sys_, pos, params, widths, K = workload("peptide20", 1024, seed=1)
+    models = oracle_models(params, sys_.n_cv, widths, K)
+    ref1 = O.bias_force(pos.astype(np.float64), sys_.quads, models, 1e30, 2e30)
+    e0, e1 = 0.5 * ref1["eps"].min(), 2.0 * ref1["eps"].max()
+    ref = O.bias_force_conservative(pos.astype(np.float64), sys_.quads, models, e0, e1)
+    out = _run(torch, rid, sys_, pos, params, widths, K, e0, e1, True)
+    bound = walker_bounds(out["eps"].astype(np.float64), ref["eps"], e0, e1)
+    assert_walkers(out["F"], ref["F"], bound, "conservative, 1024 walkers")
+
+
 def test_conservative_equals_frozen_outside_the_band(torch, rid):
     sys_, pos, params, widths, K = workload("peptide20", 40, seed=22, bias_std=0.1)
     a = _run(torch, rid, sys_, pos, params, widths, K, 2.0, 3.0, True)     # all sigma = 1

@@ -24,7 +24,9 @@ def rid():
     return r
 
 
-@pytest.mark.parametrize("M,T,n", [(64, 500, 38), (7, 123, 5), (3, 10, 1), (16, 2000, 120)])
+# (1024, 500, 38) is the benchmarked size, compared in full
+@pytest.mark.parametrize("M,T,n", [(64, 500, 38), (7, 123, 5), (3, 10, 1), (16, 2000, 120),
+                                   (1024, 500, 38)])
 def test_label_parity(torch, rid, M, T, n):
     traj, s0, _ = ridgen.restrained_traj(M, T, n, 500.0, seed=M + T)
     mask = np.ones(n, np.uint8)
