@@ -51,6 +51,13 @@ Functions and what pins them (tests/test_oracle_*.py):
   adam_step / lr_at   optimiser and exponential LR decay ("Training phase")
                       pinned: one-step closed form; convergence on the linear
                       model to the analytic optimum
+  philox4x32          counter-based generator of the MCMC
+                      pinned: the published known-answer vectors
+  mcmc_run            MCMC on the ensemble free energy ("Dimension
+                      reduction phase"), histograms, pmf_from_histogram
+                      pinned: infinite temperature is the plain random walk
+                      of the generator; a one-CV closed-form model samples
+                      exp(-A/kT); the PMF of that histogram recovers A
   mf_label            restrained-MD mean-force estimate ("Labeling phase")
                       pinned: Gaussian-frame closed form within 4 sigma, the
                       periodic wrap example, block standard error of iid
@@ -497,6 +504,124 @@ def train_step(models, s, F, states, lr):
         new_states.append((m2, v2, t + 1))
         losses.append(loss)
     return new_models, new_states, np.asarray(losses)
+
+
+# --------------------------------------------------------------------------
+# MCMC on the learned free energy ("Dimension reduction phase")
+# --------------------------------------------------------------------------
+BOLTZMANN_KJ_MOL_K = 0.0083144626   # k_B in kJ/mol/K (GROMACS units)
+
+PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+
+
+def philox4x32(ctr, key):
+    """Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers:
+    as easy as 1, 2, 3", SC 2011), a counter-based generator: ten rounds of
+    two 32x32->64 multiplications; the key is bumped by the Weyl constants
+    between rounds.  ctr: [..., 4] integers < 2^32; key: (k0, k1).
+    Returns [..., 4] uint32."""
+    c = np.asarray(ctr, dtype=np.uint64) & np.uint64(0xFFFFFFFF)
+    c0, c1, c2, c3 = (c[..., i].copy() for i in range(4))
+    k0, k1 = int(key[0]) & 0xFFFFFFFF, int(key[1]) & 0xFFFFFFFF
+    mask = np.uint64(0xFFFFFFFF)
+    for _ in range(10):
+        p0 = np.uint64(PHILOX_M[0]) * c0
+        p1 = np.uint64(PHILOX_M[1]) * c2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
+        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
+        c0, c1, c2, c3 = (hi1 ^ c1 ^ np.uint64(k0)), lo1, (hi0 ^ c3 ^ np.uint64(k1)), lo0
+        k0 = (k0 + PHILOX_W[0]) & 0xFFFFFFFF
+        k1 = (k1 + PHILOX_W[1]) & 0xFFFFFFFF
+    return np.stack([c0, c1, c2, c3], axis=-1).astype(np.uint32)
+
+
+def mcmc_uniforms(walkers, t, count, seed):
+    """The uniforms of MCMC step t for the given walkers: word 4j+i of the
+    Philox block with counter (walker, t mod 2^32, t div 2^32, j) and key
+    (seed mod 2^32, seed div 2^32); a 32-bit word x gives
+    u = (2 (x >> 9) + 1) 2^-24, exactly representable in FP32, in (0, 1).
+    Returns [len(walkers)][count] float64."""
+    w = np.asarray(walkers, dtype=np.uint64)
+    nblk = (count + 3) // 4
+    t = int(t)
+    ctr = np.zeros((len(w), nblk, 4), dtype=np.uint64)
+    ctr[:, :, 0] = w[:, None]
+    ctr[:, :, 1] = t & 0xFFFFFFFF
+    ctr[:, :, 2] = t >> 32
+    ctr[:, :, 3] = np.arange(nblk, dtype=np.uint64)[None, :]
+    x = philox4x32(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
+    x = x.reshape(len(w), nblk * 4)[:, :count].astype(np.float64)
+    return (2.0 * np.floor(x / 512.0) + 1.0) * 2.0 ** -24
+
+
+def wrap_torus(s):
+    """Map angles to [-pi, pi)."""
+    s = np.asarray(s, dtype=np.float64)
+    return s - 2.0 * math.pi * np.floor((s + math.pi) / (2.0 * math.pi))
+
+
+def cv_bins(s, nbins):
+    """Histogram bin of angles in [-pi, pi): floor((s + pi) nbins / 2pi),
+    clamped to [0, nbins - 1]."""
+    b = np.floor((np.asarray(s, np.float64) + math.pi) * (nbins / (2.0 * math.pi)))
+    return np.clip(b, 0, nbins - 1).astype(np.int64)
+
+
+def ensemble_energy(models, s):
+    """Abar(s): the ensemble mean of the members' free energies."""
+    A, _ = ensemble_mean_force(models, s)
+    return np.mean(A, axis=1)
+
+
+def mcmc_run(models, s0, n_steps, kT, step, seed, t0=0, proj=(0, 1), nbins=101,
+             keep_path=False):
+    """Metropolis MCMC in CV space on the ensemble's free energy, the
+    dimension-reduction phase: many walkers, a temperature, histograms of
+    every CV and of one projected pair, PMF = -kT ln p.  Readings (the paper
+    names walkers, steps, temperature, bins and projected indices only):
+    target density exp(-Abar(s)/kT) with Abar the ensemble mean; proposal
+    s' = wrap(s + step (2u - 1)) on every CV at once (u from mcmc_uniforms,
+    words 0..n-1); accept when u_n < exp(-(Abar(s') - Abar(s))/kT) (word n);
+    after each step the walker's current state is counted in the 1D
+    histograms of every CV and the 2D histogram of the pair ``proj``.
+    s0: [W][n].  Returns dict(s, A, hist1 [n][nbins], hist2 [nbins][nbins],
+    accepted, path [n_steps][W][n] when keep_path)."""
+    s = wrap_torus(s0)
+    W, n = s.shape
+    A = ensemble_energy(models, s)
+    hist1 = np.zeros((n, nbins), dtype=np.int64)
+    hist2 = np.zeros((nbins, nbins), dtype=np.int64)
+    accepted = 0
+    path = []
+    walkers = np.arange(W)
+    for t in range(t0, t0 + n_steps):
+        u = mcmc_uniforms(walkers, t, n + 1, seed)
+        sp = wrap_torus(s + step * (2.0 * u[:, :n] - 1.0))
+        Ap = ensemble_energy(models, sp)
+        acc = u[:, n] < np.exp(-(Ap - A) / kT)
+        s = np.where(acc[:, None], sp, s)
+        A = np.where(acc, Ap, A)
+        accepted += int(np.sum(acc))
+        b = cv_bins(s, nbins)
+        for i in range(n):
+            hist1[i] += np.bincount(b[:, i], minlength=nbins)
+        np.add.at(hist2, (b[:, proj[0]], b[:, proj[1]]), 1)
+        if keep_path:
+            path.append(s.copy())
+    out = dict(s=s, A=A, hist1=hist1, hist2=hist2, accepted=accepted)
+    if keep_path:
+        out["path"] = np.stack(path)
+    return out
+
+
+def pmf_from_histogram(hist, kT):
+    """Projected PMF -kT ln p of a histogram, shifted to a minimum of 0;
+    empty bins give +inf."""
+    h = np.asarray(hist, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        f = -kT * np.log(h / h.sum())
+    return f - np.min(f[np.isfinite(f)])
 
 
 # --------------------------------------------------------------------------
