@@ -353,6 +353,29 @@ def bench_conservative(rid, torch, case, steps=40, warmup=5):
             "frac_fp32_peak": fl / st / 1e12 / FP32_PEAK_TFLOPS}
 
 
+def bench_mcmc(rid, torch, steps=400, warmup=20):
+    """MCMC on the ensemble free energy with the dimension-reduction phase's
+    walker count, temperature and binning (2000 walkers, 300 K, 101 bins,
+    pair (0, 1)) on the headline chain's 38 CVs and ensemble."""
+    n, widths, K, W = 38, [256] * 4, 4, 2000
+    E = rid.Ensemble(n, widths, K, ridgen.xavier_ensemble(2 * n, widths, K, 1000))
+    s = torch.from_numpy(ridgen.f32(ridgen.torus_samples(W, n, 8))).cuda()
+    kT = 0.0083144626 * 300.0
+    out = rid.mcmc_run(E, s, warmup, kT, 0.3, 2024)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = rid.mcmc_run(E, s, steps, kT, 0.3, 2024, step0=warmup, hist1=out["hist1"],
+                       hist2=out["hist2"], accepted=out["accepted"])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"workload": "MCMC in CV space on the ensemble free energy: 2000 walkers, 38 torsion "
+                        "CVs, ensemble 4 x [256 x 4] FP32, 300 K, step 0.3 rad, 1D histograms "
+                        "of every CV + 2D of CVs (0, 1), 101 bins",
+            "value": W / dt, "unit": "walker-steps/s", "us_per_step": 1e6 * dt,
+            "acceptance": int(out["accepted"].item()) / (W * (steps + warmup)),
+            "seconds_for_1e6_steps": 1e6 * dt}
+
+
 def bench_labels(rid, torch, reps=20):
     M, T, n = 1024, 500, 38
     traj, s0, _ = ridgen.restrained_traj(M, T, n, 500.0, seed=9)
@@ -542,6 +565,8 @@ def main():
                                                      steps_b, wb)
         log("conservative switching")
         rec["conservative"] = bench_conservative(rid, torch, case)
+        log("mcmc")
+        rec["mcmc"] = bench_mcmc(rid, torch)
         log("training")
         rec["training"] = bench_training(rid, torch)
         log("labels")

@@ -186,6 +186,36 @@ rid_status rid_bias_force_conservative(rid_system sys, rid_ensemble ens,
                                        rid_stream stream);
 
 /* ------------------------------------------------------------------------
+ * rid_mcmc_run - Metropolis MCMC in CV space on the ensemble's free energy
+ * ("Dimension reduction phase": numb_walkers walkers, numb_steps steps, a
+ * temperature, histograms of every CV and of the projected pair
+ * proj_cv_index; the projected PMF is -kT ln p).  Torsion CVs only.
+ * Per step t and walker w: s' = wrap(s + step_size (2u - 1)) on every CV,
+ * accepted when u_n < exp(-(Abar(s') - Abar(s))/kT), Abar the ensemble
+ * mean free energy (kJ/mol) from the ensemble's kernels at its precision,
+ * the decision in FP64; then the current state is counted.  Uniforms:
+ * Philox4x32-10, counter (w, t mod 2^32, t div 2^32, j), key (seed mod 2^32,
+ * seed div 2^32), word 4j+i -> u = (2 (x >> 9) + 1) 2^-24; words 0..n-1 drive
+ * the proposal, word n the acceptance.  Steps step0 .. step0+n_steps-1, so
+ * consecutive calls with consecutive step0 continue one chain.
+ *   d_s        [W][n_cv] angles, in/out (wrapped to [-pi, pi) on entry)
+ *   kT         k_B T in kJ/mol (> 0); step_size in (0, pi]
+ *   nbins      bins over [-pi, pi) per CV (>= 1)
+ *   d_hist1    [n_cv][nbins] uint32 counts, ACCUMULATED (caller zeroes)
+ *   d_hist2    [nbins][nbins] uint32 counts of (s[proj0], s[proj1]),
+ *              accumulated, or NULL
+ *   d_accepted [1] uint64 accepted-move count, accumulated, or NULL
+ * Uses the ensemble's scratch: not concurrent with other calls on it.
+ * Errors: RID_EINVAL for NULL ens/d_s/d_hist1, W < 1, n_steps < 0,
+ *         step0 < 0, kT <= 0, step_size outside (0, pi], nbins < 1, proj
+ *         index outside [0, n_cv).
+ * ------------------------------------------------------------------------ */
+rid_status rid_mcmc_run(rid_ensemble ens, float* d_s, int W, int64_t n_steps,
+                        int64_t step0, double kT, float step_size, uint64_t seed,
+                        int proj0, int proj1, int nbins, uint32_t* d_hist1,
+                        uint32_t* d_hist2, uint64_t* d_accepted, rid_stream stream);
+
+/* ------------------------------------------------------------------------
  * rid_cv_apply_force - chain a CV-space force to the atoms alone:
  *   F_a = sum_i f_i ds_i/dr_a.
  *   d_fcv [B][n_cv]; d_force [B][n_atoms][3] OVERWRITTEN.

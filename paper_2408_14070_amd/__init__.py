@@ -30,6 +30,7 @@ EXPORTS = (
     "rid_packed_param_count", "rid_ensemble_create", "rid_ensemble_get_params",
     "rid_ensemble_set_params", "rid_ensemble_step", "rid_ensemble_destroy",
     "rid_cv_eval", "rid_model_dev", "rid_bias_force", "rid_bias_force_conservative",
+    "rid_mcmc_run",
     "rid_cv_apply_force",
     "rid_mf_train_step", "rid_lr_exponential", "rid_mf_label",
     "rid_profile_enable", "rid_profile_read", "rid_mf_loss_grad", "rid_mf_grad",
@@ -85,6 +86,8 @@ def lib():
         "rid_model_dev": (i, [vp, vp, i, vp, vp, vp, vp, vp]),
         "rid_bias_force": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
         "rid_bias_force_conservative": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
+        "rid_mcmc_run": (i, [vp, vp, i, i64, i64, ctypes.c_double, f, ctypes.c_uint64, i, i, i,
+                             vp, vp, vp, vp]),
         "rid_cv_apply_force": (i, [vp, vp, vp, i, vp, vp]),
         "rid_mf_train_step": (i, [vp, vp, vp, i, f, vp, vp]),
         "rid_lr_exponential": (d, [i64, d, i, d]),
@@ -261,6 +264,31 @@ def bias_force(system: System, ens: Ensemble, pos, eps0: float, eps1: float,
               _ptr(out["F"]), _ptr(out.get("E")), _ptr(out.get("eps")),
               _ptr(out.get("sigma")), _ptr(out.get("flags")), _stream(stream)))
     return out
+
+
+def mcmc_run(ens: Ensemble, s, n_steps: int, kT: float, step_size: float, seed: int,
+             step0: int = 0, proj=(0, 1), nbins: int = 101, hist1=None, hist2=None,
+             accepted=None, stream=None):
+    """rid_mcmc_run: Metropolis MCMC of W walkers in CV space; s [W][n] float32
+    on the device is updated in place.  The uint32 counts are held in int32
+    tensors (hist1 [n][nbins], hist2 [nbins][nbins]), accepted in an int64
+    tensor; pass them back in to accumulate.  Returns dict(hist1, hist2,
+    accepted)."""
+    torch = _torch()
+    W = s.shape[0]
+    _f32(s, (W, ens.n_cv), "s")
+    dev = s.device
+    if hist1 is None:
+        hist1 = torch.zeros((ens.n_cv, nbins), dtype=torch.int32, device=dev)
+    if hist2 is None:
+        hist2 = torch.zeros((nbins, nbins), dtype=torch.int32, device=dev)
+    if accepted is None:
+        accepted = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check(lib().rid_mcmc_run(ens.handle, _ptr(s), W, int(n_steps), int(step0), float(kT),
+                              float(step_size), int(seed) & 0xFFFFFFFFFFFFFFFF, int(proj[0]),
+                              int(proj[1]), int(nbins), _ptr(hist1), _ptr(hist2),
+                              _ptr(accepted), _stream(stream)))
+    return dict(hist1=hist1, hist2=hist2, accepted=accepted)
 
 
 def cv_apply_force(system: System, pos, fcv, stream=None):

@@ -420,6 +420,23 @@ rid_status rid_bias_force_conservative(rid_system sys, rid_ensemble ens,
                                   d_energy, d_eps, d_sigma, d_flags, (hipStream_t)stream);
 }
 
+rid_status rid_mcmc_run(rid_ensemble ens, float* d_s, int W, int64_t n_steps,
+                        int64_t step0, double kT, float step_size, uint64_t seed,
+                        int proj0, int proj1, int nbins, uint32_t* d_hist1,
+                        uint32_t* d_hist2, uint64_t* d_accepted, rid_stream stream) {
+  if (!ens || !d_s || !d_hist1) return fail(RID_EINVAL, "NULL argument");
+  if (W < 1 || n_steps < 0 || step0 < 0) return fail(RID_EINVAL, "need W >= 1, steps >= 0");
+  if (!(kT > 0.0)) return fail(RID_EINVAL, "kT must be > 0");
+  if (!(step_size > 0.f) || step_size > 3.14159265358979f)
+    return fail(RID_EINVAL, "step_size must be in (0, pi]");
+  const int n = ens->impl.n_cv;
+  if (nbins < 1 || proj0 < 0 || proj0 >= n || proj1 < 0 || proj1 >= n)
+    return fail(RID_EINVAL, "need nbins >= 1 and projected indices in [0, n_cv)");
+  return launch_mcmc(ens->impl, d_s, W, n_steps, step0, kT, step_size, seed, proj0, proj1,
+                     nbins, d_hist1, d_hist2, reinterpret_cast<unsigned long long*>(d_accepted),
+                     (hipStream_t)stream);
+}
+
 rid_status rid_cv_apply_force(rid_system sys, const float* d_pos,
                               const float* d_fcv, int B, float* d_force,
                               rid_stream stream) {

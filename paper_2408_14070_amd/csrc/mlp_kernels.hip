@@ -376,7 +376,9 @@ __host__ __device__ constexpr int u0_split() {
   return sizeof(typename P::T) == 4 ? 4 : 1;
 }
 
-template <class P, int NP, int RT, int NW, int LM, bool FROM_POS>
+// GRAD = false: the free energies only (the forward sweep, no tanh' stash,
+// no reverse sweep, no g output).
+template <class P, int NP, int RT, int NW, int LM, bool FROM_POS, bool GRAD>
 __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   using T = typename P::T;
   using SP = Pack4<T>;
@@ -553,7 +555,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
     SP o;
     o.set(h);
     o.store(out + (rt * 16 + wl) * AS + (jt0 + c) * 16 + uq);
-    st[l][rt][c].set(d);
+    if constexpr (GRAD) st[l][rt][c].set(d);
   };
   auto last_tile = [&](int rt, int c, const f4& z, T* out) {
     const int u = (jt0 + c) * 16 + uq;
@@ -566,9 +568,11 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       d[q] = dq;
     }
     apart[rt] += w4[0] * h[0] + w4[1] * h[1] + w4[2] * h[2] + w4[3] * h[3];
-    SP o;
-    o.set(w4 * d);
-    o.store(out + (rt * 16 + wl) * AS + u);
+    if constexpr (GRAD) {
+      SP o;
+      o.set(w4 * d);
+      o.store(out + (rt * 16 + wl) * AS + u);
+    }
   };
   // the GEMM after forward layer l: forward layer l+1, or the first backward
   auto next_after_fwd = [&](int l) {
@@ -634,7 +638,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
     for (int c = 0; c < CT; ++c)
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) acc[rt][c] = bnext[c];
-    gemm_hidden<P, RT, CT, NPASS, PDH, NK>(acc, wh, in, AS, wsrc(p.fwd_off[L - 1]), true,
+    gemm_hidden<P, RT, CT, NPASS, PDH, NK>(acc, wh, in, AS, wsrc(p.fwd_off[L - 1]), GRAD,
                                            wsrc(p.bwd_off[L - 1]), lane);
 #pragma unroll
     for (int c = 0; c < CT; ++c)
@@ -651,6 +655,15 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
     if (lane < 16) red[wave * R + rt * 16 + wl] = v;
+  }
+  if constexpr (!GRAD) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < R; i += NW * 64) {
+      float a = p.bo[k];
+      for (int w = 0; w < NW; ++w) a += red[w * R + i];
+      if (row0 + i < p.B) p.A_out[(size_t)k * p.B + row0 + i] = a;
+    }
+    return;
   }
 
   // ------------- reverse sweep: v_{l-1} = (W_l^T v_l) * tanh'_{l-1} -------------
@@ -846,7 +859,7 @@ template <class P, int NP, int RT, int NW, int LM>
 rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
                    float* A_out, float* g_out, const TorsionInput* tin,
                    hipStream_t st) {
-  static size_t attr_bytes[2] = {0, 0};   // dynamic-LDS limit set per kernel
+  static size_t attr_bytes[3] = {0, 0, 0};   // dynamic-LDS limit set per kernel
   constexpr int R = 16 * RT;
   using T = typename P::T;
   const bool from_pos = tin != nullptr;
@@ -860,12 +873,17 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
     return fail(RID_EUNSUPPORTED, "shape too large for the MLP kernel's LDS");
   if (from_pos && a.rc < 1)
     return fail(RID_EUNSUPPORTED, "too many torsion atoms to gather in-kernel");
-  auto kern = from_pos ? mlp_kernel<P, NP, RT, NW, LM, true>
-                       : mlp_kernel<P, NP, RT, NW, LM, false>;
-  if (lds > 64 * 1024 && lds > attr_bytes[from_pos]) {
+  // without g_out only the free energies are computed (plain input only)
+  const bool grad = g_out != nullptr;
+  if (!grad && from_pos) return fail(RID_EUNSUPPORTED, "energy-only path takes the encoding");
+  auto kern = !grad    ? mlp_kernel<P, NP, RT, NW, LM, false, false>
+              : from_pos ? mlp_kernel<P, NP, RT, NW, LM, true, true>
+                         : mlp_kernel<P, NP, RT, NW, LM, false, true>;
+  const int ki = grad ? (from_pos ? 1 : 0) : 2;
+  if (lds > 64 * 1024 && lds > attr_bytes[ki]) {
     RID_HIP(hipFuncSetAttribute((const void*)kern,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr_bytes[from_pos] = lds;
+    attr_bytes[ki] = lds;
   }
   a.x = x; a.B = B; a.n = e.n_cv; a.K = e.K; a.L = e.L; a.XP = e.XP;
   a.n_tiles = (B + R - 1) / R;
@@ -946,9 +964,10 @@ rid_status dispatch(const rid_ensemble_impl& e, const float* x, int B, float* A_
 }  // namespace
 
 // Kernel family: (precision, padded width, depth) -> instantiation.
-// FP32: 16 walkers per workgroup, 4 unit tiles (64 units) per wave.
-// 16-bit: 64 walkers per workgroup (32 for deep networks or wide inputs) to
-// cut the L2 weight stream per FLOP; 64 units per wave.
+// FP32: 16 walkers per workgroup, the units split over the waves (16 waves of
+// one 16-unit tile at width 256).  16-bit: 64 walkers per workgroup (32 for
+// deep networks or wide inputs) to cut the L2 weight stream per FLOP; 64
+// units per wave.  g_out == nullptr: free energies only.
 rid_status launch_mlp(const rid_ensemble_impl& e, const float* x, int B,
                       float* A_out, float* g_out, hipStream_t st) {
   return dispatch(e, x, B, A_out, g_out, nullptr, st);

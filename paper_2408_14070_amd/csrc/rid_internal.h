@@ -162,6 +162,7 @@ struct TorsionInput {
 };
 rid_status launch_mlp_from_pos(const rid_ensemble_impl& e, const TorsionInput& tin,
                                int B, float* A_out, float* g_out, hipStream_t st);
+// g_out == nullptr: the free energies only (no reverse sweep).
 rid_status launch_mlp(const rid_ensemble_impl& e, const float* x, int B,
                       float* A_out, float* g_out, hipStream_t st);
 rid_status launch_ensemble_reduce(int K, int n, int B, const float* A,
@@ -189,6 +190,10 @@ struct InputHvp {
 rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
                           const float* rho, int B, float* loss, float* grad_out,
                           float** grad_used, hipStream_t st, InputHvp* hvp = nullptr);
+rid_status launch_mcmc(rid_ensemble_impl& e, float* s, int W, long long n_steps, long long t0,
+                       double kT, float step, unsigned long long seed, int proj0, int proj1,
+                       int nbins, unsigned* hist1, unsigned* hist2,
+                       unsigned long long* accepted, hipStream_t st);
 rid_status launch_bias_conservative(const rid_system_impl& s, rid_ensemble_impl& e,
                                     const float* pos, int B, float eps0, float eps1,
                                     float* force, float* energy, float* eps, float* sigma,
