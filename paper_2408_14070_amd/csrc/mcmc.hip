@@ -11,6 +11,12 @@
 // its i-th uniform of the step, u = (2 (x >> 9) + 1) 2^-24 (exact in FP32).
 // Words 0..n-1 drive the proposal, word n the acceptance.  Histogram counts
 // are integer atomics, so the result does not depend on their order.
+//
+// One wave per walker, lanes over CVs.  A step kernel issues every load it
+// needs (member energies, the current state and the proposal, the walker's
+// acceptance count) before it waits, keeps the updated state in registers
+// for the counts and the next proposal, and counts acceptances per walker:
+// one atomic per workgroup adds them to the caller's total at the end.
 #include "device_common.h"
 
 namespace rid {
@@ -71,12 +77,14 @@ struct McmcArgs {
   unsigned* hist1;          // [n][nbins]
   unsigned* hist2;          // [nbins][nbins] or null
   unsigned long long* accepted;
+  unsigned long long* acc_count;   // [W] acceptances of this call, per walker
 };
 
-__device__ inline double member_mean(const McmcArgs& a, int w) {
-  double m = 0.0;
-  for (int k = 0; k < a.K; ++k) m += (double)a.A[(size_t)k * a.W + w];
-  return m / a.K;
+// Abar of walker w: lane k holds member k (K <= 64); the sum is in FP64, so
+// its order does not matter at FP32 inputs.  Every lane of the wave calls it.
+__device__ inline double member_mean(const McmcArgs& a, int w, int lane) {
+  const float ak = lane < a.K ? a.A[(size_t)lane * a.W + w] : 0.f;
+  return wave_sum((double)ak) / a.K;
 }
 
 // Proposal of step t for walker w (one wave, lanes over CVs) and its encoding.
@@ -96,6 +104,7 @@ __device__ inline void propose(const McmcArgs& a, int w, long long t, int lane) 
 __global__ __launch_bounds__(kMcmcWaves * kWave) void mcmc_encode_kernel(McmcArgs a) {
   const int w = blockIdx.x * kMcmcWaves + threadIdx.x / kWave, lane = threadIdx.x % kWave;
   if (w >= a.W) return;
+  if (lane == 0) a.acc_count[w] = 0ull;
   for (int i = lane; i < a.n; i += kWave) {
     const float s0 = a.s[(size_t)w * a.n + i];   // any real angle
     const float v = wrap_pi(s0 - kTwoPi * floorf((s0 + kPi) / kTwoPi));
@@ -112,7 +121,8 @@ __global__ __launch_bounds__(kMcmcWaves * kWave) void mcmc_start_kernel(McmcArgs
                                                                         long long t) {
   const int w = blockIdx.x * kMcmcWaves + threadIdx.x / kWave, lane = threadIdx.x % kWave;
   if (w >= a.W) return;
-  if (lane == 0) a.acur[w] = member_mean(a, w);
+  const double m = member_mean(a, w, lane);
+  if (lane == 0) a.acur[w] = m;
   propose(a, w, t, lane);
 }
 
@@ -121,28 +131,71 @@ __global__ __launch_bounds__(kMcmcWaves * kWave) void mcmc_step_kernel(McmcArgs 
                                                                        int last) {
   const int w = blockIdx.x * kMcmcWaves + threadIdx.x / kWave, lane = threadIdx.x % kWave;
   if (w >= a.W) return;
-  const double ap = member_mean(a, w);
-  const float un = mcmc_uniform(w, t, a.n, a.seed);
-  const bool acc = (double)un < exp(-(ap - a.acur[w]) / a.kT);
-  if (acc) {
-    for (int i = lane; i < a.n; i += kWave) a.s[(size_t)w * a.n + i] = a.sp[(size_t)w * a.n + i];
+  const int n = a.n;
+  const size_t row = (size_t)w * n;
+  // every load first: member energies (lane k), the walker's Abar and count,
+  // the first chunk of the state and of the proposal
+  const float ak = lane < a.K ? a.A[(size_t)lane * a.W + w] : 0.f;
+  const double acur = a.acur[w];
+  const unsigned long long cnt = a.acc_count[w];
+  const int i0c = min(lane, n - 1);
+  float sc = a.s[row + i0c], spc = a.sp[row + i0c];
+  // the random numbers do not depend on the loads
+  const float un = mcmc_uniform(w, t, n, a.seed);
+  float unext = last ? 0.f : mcmc_uniform(w, t + 1, i0c, a.seed);
+  const double ap = wave_sum((double)ak) / a.K;
+  const bool acc = (double)un < exp(-(ap - acur) / a.kT);
+  float p0 = 0.f, p1 = 0.f;
+  for (int i0 = 0; i0 < n; i0 += kWave) {
+    const int i = i0 + lane;
+    if (i0 > 0) {
+      const int ic = min(i, n - 1);
+      sc = a.s[row + ic];
+      spc = a.sp[row + ic];
+      if (!last) unext = mcmc_uniform(w, t + 1, ic, a.seed);
+    }
+    const float v = acc ? spc : sc;
+    if (a.hist2) {
+      if (a.proj0 >= i0 && a.proj0 < i0 + kWave) p0 = __shfl(v, a.proj0 - i0);
+      if (a.proj1 >= i0 && a.proj1 < i0 + kWave) p1 = __shfl(v, a.proj1 - i0);
+    }
+    if (i < n) {
+      if (acc) a.s[row + i] = v;
+      atomicAdd(&a.hist1[(size_t)i * a.nbins + cv_bin(v, a.nbins)], 1u);
+      if (!last) {
+        const float vp = wrap_pi(v + a.step * (2.f * unext - 1.f));
+        a.sp[row + i] = vp;
+        float sn, cs;
+        sincosf(vp, &sn, &cs);
+        a.xp[2 * row + i] = cs;
+        a.xp[2 * row + n + i] = sn;
+      }
+    }
   }
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   if (lane == 0) {
     if (acc) {
       a.acur[w] = ap;
-      if (a.accepted) atomicAdd(a.accepted, 1ull);
+      a.acc_count[w] = cnt + 1ull;
     }
-    if (a.hist2) {
-      const int b0 = cv_bin(a.s[(size_t)w * a.n + a.proj0], a.nbins);
-      const int b1 = cv_bin(a.s[(size_t)w * a.n + a.proj1], a.nbins);
-      atomicAdd(&a.hist2[(size_t)b0 * a.nbins + b1], 1u);
-    }
+    if (a.hist2)
+      atomicAdd(&a.hist2[(size_t)cv_bin(p0, a.nbins) * a.nbins + cv_bin(p1, a.nbins)], 1u);
   }
-  for (int i = lane; i < a.n; i += kWave)
-    atomicAdd(&a.hist1[(size_t)i * a.nbins + cv_bin(a.s[(size_t)w * a.n + i], a.nbins)], 1u);
-  if (!last) propose(a, w, t + 1, lane);
+}
+
+// Adds the call's per-walker acceptance counts to the caller's total.
+__global__ __launch_bounds__(256) void mcmc_count_kernel(const unsigned long long* cnt, int W,
+                                                         unsigned long long* total) {
+  __shared__ unsigned long long part[256 / kWave];
+  unsigned long long v = 0;
+  for (int w = blockIdx.x * 256 + threadIdx.x; w < W; w += gridDim.x * 256) v += cnt[w];
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o);
+  if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int q = 0; q < 256 / kWave; ++q) s += part[q];
+    if (s) atomicAdd(total, s);
+  }
 }
 
 }  // namespace
@@ -154,8 +207,9 @@ rid_status launch_mcmc(rid_ensemble_impl& e, float* s, int W, long long n_steps,
   const int n = e.n_cv, K = e.K;
   rid_status r;
   const size_t wn = (size_t)W * n;
-  // workspace: proposal [W][n], its encoding [W][2n], Abar (FP64) [W]
-  if ((r = e.ws_cons.ensure(sizeof(float) * 3 * wn + sizeof(double) * (size_t)W + 256)) !=
+  // workspace: Abar (FP64) [W], acceptance counts [W], proposal [W][n], its
+  // encoding [W][2n]
+  if ((r = e.ws_cons.ensure(2 * sizeof(double) * (size_t)W + sizeof(float) * 3 * wn + 256)) !=
       RID_OK)
     return r;
   if ((r = e.ws_A.ensure(sizeof(float) * K * (size_t)W)) != RID_OK) return r;
@@ -167,7 +221,8 @@ rid_status launch_mcmc(rid_ensemble_impl& e, float* s, int W, long long n_steps,
   McmcArgs a{};
   a.s = s;
   a.acur = reinterpret_cast<double*>(base);
-  a.sp = reinterpret_cast<float*>(base + sizeof(double) * (size_t)W);
+  a.acc_count = reinterpret_cast<unsigned long long*>(base + sizeof(double) * (size_t)W);
+  a.sp = reinterpret_cast<float*>(base + 2 * sizeof(double) * (size_t)W);
   a.xp = a.sp + wn;
   a.A = e.ws_A.as<float>();
   a.W = W;
@@ -193,6 +248,11 @@ rid_status launch_mcmc(rid_ensemble_impl& e, float* s, int W, long long n_steps,
     if ((r = launch_mlp(e, a.xp, W, e.ws_A.as<float>(), nullptr, st)) != RID_OK) return r;
     hipLaunchKernelGGL(mcmc_step_kernel, grid, block, 0, st, a, t,
                        (int)(t + 1 == t0 + n_steps));
+    RID_HIP(hipGetLastError());
+  }
+  if (accepted) {
+    hipLaunchKernelGGL(mcmc_count_kernel, dim3(std::min((W + 255) / 256, 1024)), dim3(256), 0,
+                       st, a.acc_count, W, accepted);
     RID_HIP(hipGetLastError());
   }
   return RID_OK;
