@@ -59,11 +59,18 @@ def mlp_flops_per_walker(n_cv, widths, K):
 
 
 def conservative_flops_per_walker(n_cv, widths, K):
-    """The frozen-switch path, plus the input-mode sweeps of every member:
-    forward, primal backward, tangent forward (one layer product set each)
-    and the adjoint propagation of the stacked primal/tangent rows down to
-    the input (two per layer)."""
-    return mlp_flops_per_walker(n_cv, widths, K) + K * 5 * layer_flops(n_cv, widths)
+    """Algorithmic minimum of conservative switching: the frozen-switch path
+    (forward + input-gradient sweep) plus, per member, the tangent of the
+    forward sweep and the tangent of the reverse sweep (one layer product
+    set each)."""
+    return mlp_flops_per_walker(n_cv, widths, K) + K * 2 * layer_flops(n_cv, widths)
+
+
+def hvp_kernel_flops_per_walker(n_cv, widths, K):
+    """What the fused Hessian-vector kernel executes: it recomputes the
+    primal forward and reverse sweeps from the encoding next to their
+    tangents (4 layer product sets per member)."""
+    return K * 4 * layer_flops(n_cv, widths)
 
 
 def train_flops_per_sample(n_cv, widths, K):
@@ -340,17 +347,30 @@ def bench_conservative(rid, torch, case, steps=40, warmup=5):
             rid.bias_force(S, E, P, e0, e1, out=out, conservative=cons)
         torch.cuda.synchronize()
         res[name] = (time.perf_counter() - t0) / steps
+    # kernel timing (dispatch events) on separate calls
+    rid.profile_enable(True)
+    for _ in range(steps):
+        rid.bias_force(S, E, P, e0, e1, out=out, conservative=True)
+    kern = read_kernels(rid, [("mlp", rid.PROF_MLP), ("hvp", rid.PROF_HVP)])
+    rid.profile_enable(False)
     sys_ = case["sys"]
     fl = conservative_flops_per_walker(sys_.n_cv, case["widths"], case["K"]) * B
     st = res["conservative"]
-    return {"workload": "conservative switching (force = -grad E inside the band: "
-                        "Abar sigma'(eps) d eps/ds added through per-member Hessian-vector "
-                        "products), same chain / ensemble / 1024 walkers, band over all "
-                        "walkers, FP32",
-            "value": B / st, "unit": "walker-steps/s", "ms_per_step": 1e3 * st,
-            "frozen_ms_per_step": 1e3 * res["frozen"],
-            "flop_per_step": fl, "achieved_tflops": fl / st / 1e12,
-            "frac_fp32_peak": fl / st / 1e12 / FP32_PEAK_TFLOPS}
+    r = {"workload": "conservative switching (force = -grad E inside the band: "
+                     "Abar sigma'(eps) d eps/ds added through per-member Hessian-vector "
+                     "products), same chain / ensemble / 1024 walkers, band over all "
+                     "walkers, FP32",
+         "value": B / st, "unit": "walker-steps/s", "ms_per_step": 1e3 * st,
+         "frozen_ms_per_step": 1e3 * res["frozen"],
+         "flop_per_step": fl, "achieved_tflops": fl / st / 1e12,
+         "frac_fp32_peak": fl / st / 1e12 / FP32_PEAK_TFLOPS,
+         "kernels_us": {k: 1e3 * v for k, v in kern.items()}}
+    if "hvp" in kern:
+        kf = hvp_kernel_flops_per_walker(sys_.n_cv, case["widths"], case["K"]) * B
+        r["hvp_kernel"] = {"flop_per_launch": kf, "avg_launch_us": 1e3 * kern["hvp"],
+                           "achieved_tflops": kf / (kern["hvp"] * 1e-3) / 1e12,
+                           "frac_fp32_peak": kf / (kern["hvp"] * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}
+    return r
 
 
 def bench_mcmc(rid, torch, steps=400, warmup=20):

@@ -351,7 +351,8 @@ void rid_server_destroy(rid_server srv);
  * returns, for one kernel family, the summed event-measured duration (ms)
  * and the launch count since the last clear.  Families: 0 torsion CVs, 1 fused ensemble MLP,
  * 2 deviation/switch/atom-force scatter, 3 ensemble reduction,
- * 4 CV embedding, 5 training step kernels, 6 mean-force labels.
+ * 4 CV embedding, 5 training step kernels, 6 mean-force labels,
+ * 7 Hessian-vector products of conservative switching.
  * ------------------------------------------------------------------------ */
 void rid_profile_enable(int mode);
 rid_status rid_profile_read(int kind, double* total_ms, int64_t* count);

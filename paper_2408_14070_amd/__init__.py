@@ -47,7 +47,7 @@ class ServerStats(ctypes.Structure):
                 ("mean_batch_walkers", ctypes.c_double), ("p50_us", ctypes.c_double),
                 ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double),
                 ("max_us", ctypes.c_double), ("walker_steps_per_s", ctypes.c_double)]
-PROF_CV, PROF_MLP, PROF_SCATTER, PROF_REDUCE, PROF_EMBED, PROF_TRAIN, PROF_LABEL = range(7)
+PROF_CV, PROF_MLP, PROF_SCATTER, PROF_REDUCE, PROF_EMBED, PROF_TRAIN, PROF_LABEL, PROF_HVP = range(8)
 
 
 class RidError(RuntimeError):

@@ -3,10 +3,12 @@
 // the walker through the model deviation:
 //   f = sigma gbar + Abar sigma'(eps) d eps/ds,
 //   d eps/ds = sum_k H_k w_k,  w_k = (g_k - gbar) / (K eps),
-// with H_k the Hessian of member k's free energy in s.  H_k w_k comes from
-// the mean-force sweeps of the training path in input mode: with
-// rho_x = (dx/ds) w_k held fixed, the tangent and adjoint sweeps give
-// d(rho_x . dA_k/dx)/dx; the angle chain adds (d rho_x/ds)^T dA_k/dx.
+// with H_k the Hessian of member k's free energy in s.  FP32 ensembles of
+// padded width <= 256 get H_k w_k from one fused forward-over-reverse
+// kernel (hvp_kernel: primal and tangent rows share every weight fragment).
+// Other ensembles use the mean-force sweeps of the training path in input
+// mode: with rho_x = (dx/ds) w_k held fixed, the tangent and adjoint sweeps
+// give d(rho_x . dA_k/dx)/dx; the angle chain adds (d rho_x/ds)^T dA_k/dx.
 // The frozen-switch path (rid_bias_force) is the same where sigma' = 0.
 #include "device_common.h"
 
@@ -81,6 +83,23 @@ __global__ void cons_combine_kernel(const float* s, const float* rho, const floa
   }
 }
 
+// The same with the fused kernel's per-member terms T [K][B][n] (read only
+// where coef is nonzero: the kernel skips tiles outside the band).
+__global__ void cons_combine_terms_kernel(const float* T, const float* gbar, const float* coef,
+                                          const float* sig_w, int K, int B, int n,
+                                          float* fcv) {
+  const long long total = (long long)B * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(e / n);
+    const float cb = coef[b];
+    float de = 0.f;
+    if (cb != 0.f)
+      for (int k = 0; k < K; ++k) de += T[k * total + e];
+    fcv[e] = sig_w[b] * gbar[e] + cb * de;
+  }
+}
+
 }  // namespace
 
 rid_status launch_bias_conservative(const rid_system_impl& s, rid_ensemble_impl& e,
@@ -89,9 +108,12 @@ rid_status launch_bias_conservative(const rid_system_impl& s, rid_ensemble_impl&
                                     uint8_t* flags, hipStream_t st) {
   const int K = e.K, n = e.n_cv;
   rid_status r;
-  // workspace: s [B][n], gbar [B][n], fcv [B][n], rho [B][K][n], coef [B], sigma [B]
+  // workspace: s [B][n], gbar [B][n], fcv [B][n], rho [B][K][n], coef [B],
+  // sigma [B], and the fused kernel's terms [K][B][n]
   const size_t nb = (size_t)B * n;
-  if ((r = e.ws_cons.ensure(sizeof(float) * (3 * nb + nb * K + 2 * (size_t)B))) != RID_OK)
+  const bool fused = hvp_fused_supported(e);
+  if ((r = e.ws_cons.ensure(sizeof(float) * (3 * nb + nb * K * (fused ? 2 : 1) +
+                                             2 * (size_t)B))) != RID_OK)
     return r;
   float* d_s = e.ws_cons.as<float>();
   float* d_gbar = d_s + nb;
@@ -114,11 +136,20 @@ rid_status launch_bias_conservative(const rid_system_impl& s, rid_ensemble_impl&
                      dim3(kPrepWaves * kWave), 0, st, A, g, K, B, n, (double)eps0,
                      (double)eps1, d_gbar, d_rho, d_coef, d_sig, energy, eps, sigma);
   RID_HIP(hipGetLastError());
+  const int grid = (int)std::min<size_t>((nb + 255) / 256, 4096);
+  if (fused) {
+    float* d_T = d_sig + B;
+    if ((r = launch_hvp(e, e.ws_x.as<float>(), d_rho, d_coef, B, d_T, st)) != RID_OK) return r;
+    hipLaunchKernelGGL(cons_combine_terms_kernel, dim3(grid), dim3(256), 0, st, d_T, d_gbar,
+                       d_coef, d_sig, K, B, n, d_fcv);
+    RID_HIP(hipGetLastError());
+    return launch_bias_scatter(s, 0, pos, B, nullptr, nullptr, d_fcv, 0.0f, 1.0f, force,
+                               nullptr, nullptr, nullptr, flags, st);
+  }
   InputHvp hvp;
   if ((r = launch_mf_grad(e, d_s, nullptr, d_rho, B, nullptr, nullptr, nullptr, st, &hvp)) !=
       RID_OK)
     return r;
-  const int grid = (int)std::min<size_t>((nb + 255) / 256, 4096);
   hipLaunchKernelGGL(cons_combine_kernel, dim3(grid), dim3(256), 0, st, d_s, d_rho, hvp.lam_x,
                      hvp.slab_lam, hvp.u0, d_gbar, d_coef, d_sig, K, B, n, d_fcv);
   RID_HIP(hipGetLastError());

@@ -744,6 +744,251 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
 }
 
 // ---------------------------------------------------------------------------
+// Hessian-vector products for conservative switching (FP32 ensembles).
+// For walker w and member k, with rho_x = (dx/ds) w_k (w_k the walker's
+// deviation direction, zero outside the switching band):
+//   u0  = dA_k/dx                          (reverse sweep, as in mlp_kernel)
+//   u0d = H_x rho_x = d/dt u0(x + t rho_x)  (forward-over-reverse)
+// and the member's term of d eps/ds, chained to the angles:
+//   T_k[i] = -sin s_i u0d[i] + cos s_i u0d[n+i] - w_ki (cos s_i u0[i] + sin s_i u0[n+i]).
+// Tangent recurrences: zd_1 = W_1 rho_x, hd_l = tanh'_l zd_l,
+// zd_{l+1} = W_{l+1} hd_l, dd_l = -2 h_l hd_l (tangent of tanh'),
+// vd_L = w_o dd_L, vd_{l-1} = (W_l^T vd_l) tanh'_{l-1} + (W_l^T v_l) dd_{l-1},
+// u0d = W_1^T vd_1.
+// One workgroup owns 16 walkers of one member.  Rows 0-15 of its activation
+// tile are the walkers' primal vectors and rows 16-31 their tangents, so
+// every weight fragment streamed from L2 feeds both (the MFMA B operand
+// spans two 16-row tiles), and tanh' and its tangent stay in registers
+// between the sweeps.  One 16-unit tile per wave.
+// ---------------------------------------------------------------------------
+struct HvpArgs {
+  const float* x;      // [B][2n] encoding cos s | sin s
+  const float* rho;    // [B][K][n] w_k
+  const float* coef;   // [B] Abar sigma'(eps): a tile whose walkers are all 0 is skipped
+  float* T_out;        // [K][B][n]
+  int B, n, K, L, XP, n_tiles, xcd_grp;
+  const unsigned char* frag;
+  unsigned long long frag_model_bytes;
+  unsigned fwd_off[kMaxHidden];
+  unsigned bwd_off[kMaxHidden];
+  const float* bias;   // [K][L][NP], pre-scaled like the forward weights
+  const float* wo;     // [K][NP]
+  unsigned off_u0, off_xs, off_rs, off_wo;   // LDS byte offsets
+};
+
+// ln 2 / 2: undoes the forward pre-scale on the tangent rows (no bias there)
+constexpr float kTanhUnscale = 0.34657359027997264f;
+
+template <int NP, int NW, int LM>
+__global__ __launch_bounds__(NW * 64) void hvp_kernel(HvpArgs p) {
+  using P = F32;
+  constexpr int KF = P::KF;
+  constexpr int RT = 2;                       // primal rows, tangent rows
+  constexpr int CT = NP / (16 * NW);
+  static_assert(CT == 1 && 16 * NW == NP, "one unit tile per wave");
+  constexpr int R = 16 * RT;
+  constexpr int JT = NP / 16;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int k, tile;
+  map_block(blockIdx.x, p.K, p.xcd_grp, k, tile);
+  if (tile >= p.n_tiles) return;
+  const int row0 = tile * 16;
+  // every wave takes the same vote, so a skipped tile leaves as a whole
+  if (!__any(p.coef[min(row0 + (lane & 15), p.B - 1)] != 0.f)) return;
+
+  const int n = p.n, L = p.L, XP = p.XP, X2 = 2 * p.n;
+  const int AW = NP > XP ? NP : XP;
+  const int AS = AW + RID_ACT_PAD_BYTES / 4;
+  const int BUF = R * AS;
+  float* act = reinterpret_cast<float*>(smem);
+  float* u0 = reinterpret_cast<float*>(smem + p.off_u0);
+  const int US = XP + 4;
+  float* xs = reinterpret_cast<float*>(smem + p.off_xs);    // [16][2n]
+  float* rs = reinterpret_cast<float*>(smem + p.off_rs);    // [16][n] w_k
+  float* wos = reinterpret_cast<float*>(smem + p.off_wo);   // [NP]
+
+  const unsigned char* fbase = p.frag + (size_t)k * p.frag_model_bytes;
+  const float* bias = p.bias + (size_t)k * L * NP;
+  const float* wo = p.wo + (size_t)k * NP;
+  constexpr int PD = RID_PD_FP32;
+  constexpr int NK = NP / KF;
+  constexpr int U0_SPLIT = u0_split<P, NP>();
+  constexpr int PDH = NK % (RID_PDH_FP32 + 1) == 0 ? RID_PDH_FP32 : 1;
+  const int jt0 = wave;
+  const int wl = lane & 15;
+  const int uq = 4 * (lane >> 4);
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<unsigned char*>(fbase), (short)0, (int)p.frag_model_bytes, 0x00020000);
+  auto wsrc = [&](unsigned off) {
+    return WSrc{rsrc, (int)off + jt0 * kFragBytes, JT * kFragBytes};
+  };
+  WRing<PD, 1> wr;
+  WRing<PDH, 1> wh;
+  ring_preload<PD, 1>(wr, wsrc(p.fwd_off[0]), XP / KF, lane);
+  f4 bnext = *reinterpret_cast<const f4*>(bias + jt0 * 16 + uq);
+  for (int i = threadIdx.x; i < NP; i += NW * 64) wos[i] = wo[i];
+
+  // input tile: rows 0-15 x, rows 16-31 rho_x = [-sin s w | cos s w],
+  // columns [2n, XP) zero; walkers past B are zero rows
+  for (int e = threadIdx.x; e < 16 * XP; e += NW * 64) {
+    const int i = e / XP, c = e - i * XP;
+    const int row = row0 + i;
+    float xv = 0.f, tv = 0.f;
+    if (row < p.B && c < X2) {
+      const int ci = c < n ? c : c - n;
+      xv = p.x[(size_t)row * X2 + c];
+      const float other = p.x[(size_t)row * X2 + (c < n ? c + n : c - n)];
+      const float w = p.rho[((size_t)row * p.K + k) * n + ci];
+      tv = c < n ? -other * w : other * w;
+      xs[i * X2 + c] = xv;
+      if (c < n) rs[i * n + c] = w;
+    }
+    act[i * AS + c] = xv;
+    act[(16 + i) * AS + c] = tv;
+  }
+  __syncthreads();
+
+  f4 sd[LM - 1], sdd[LM - 1];   // tanh' and its tangent, hidden layers 1..L-1
+  int cur = 0;
+  auto store_pair = [&](float* out, const f4& prim, const f4& tang) {
+    *reinterpret_cast<f4*>(out + wl * AS + jt0 * 16 + uq) = prim;
+    *reinterpret_cast<f4*>(out + (16 + wl) * AS + jt0 * 16 + uq) = tang;
+  };
+  // forward epilogue: y, yd are the pre-scaled GEMM outputs of the two rows
+  auto fwd_core = [&](const f4& y, const f4& yd, f4& h, f4& d, f4& hd, f4& dd) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float dq;
+      h[q] = tanh_and_grad(y[q], dq);
+      d[q] = dq;
+      hd[q] = dq * (yd[q] * kTanhUnscale);
+      dd[q] = -2.f * h[q] * hd[q];
+    }
+  };
+  auto mid_epi = [&](int l, const f4& y, const f4& yd, float* out) {
+    f4 h, d, hd, dd;
+    fwd_core(y, yd, h, d, hd, dd);
+    store_pair(out, h, hd);
+    sd[l] = d;
+    sdd[l] = dd;
+  };
+  auto last_epi = [&](const f4& y, const f4& yd, float* out) {
+    const f4 w4 = *reinterpret_cast<const f4*>(wos + jt0 * 16 + uq);
+    f4 h, d, hd, dd;
+    fwd_core(y, yd, h, d, hd, dd);
+    store_pair(out, w4 * d, w4 * dd);    // v_L, vd_L
+  };
+  auto next_after_fwd = [&](int l) {
+    return wsrc(l + 1 < L ? p.fwd_off[l + 1] : p.bwd_off[L > 1 ? L - 1 : 0]);
+  };
+  auto init_fwd = [&](f4 (&acc)[RT][1]) {
+    acc[0][0] = bnext;
+    acc[1][0] = f4{0.f, 0.f, 0.f, 0.f};
+  };
+
+  {  // layer 1
+    float* out = act + BUF;
+    f4 acc[RT][1];
+    init_fwd(acc);
+    gemm_run<P, RT, 1, PD>(acc, wr, act, AS, wsrc(p.fwd_off[0]), XP / KF, lane);
+    if (L > 1) {
+      ring_preload<PDH, 1>(wh, next_after_fwd(0), NK, lane);
+      bnext = *reinterpret_cast<const f4*>(bias + NP + jt0 * 16 + uq);
+      mid_epi(0, acc[0][0], acc[1][0], out);
+    } else {
+      last_epi(acc[0][0], acc[1][0], out);
+    }
+    cur = 1;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int l = 1; l < LM - 1; ++l) {
+    if (l < L - 1) {
+      const float* in = act + cur * BUF;
+      float* out = act + (cur ^ 1) * BUF;
+      f4 acc[RT][1];
+      init_fwd(acc);
+      gemm_hidden<P, RT, 1, 1, PDH, NK>(acc, wh, in, AS, wsrc(p.fwd_off[l]), true,
+                                        next_after_fwd(l), lane);
+      bnext = *reinterpret_cast<const f4*>(bias + (l + 1) * NP + jt0 * 16 + uq);
+      mid_epi(l, acc[0][0], acc[1][0], out);
+      cur ^= 1;
+      __syncthreads();
+    }
+  }
+  if (L > 1) {
+    const float* in = act + cur * BUF;
+    float* out = act + (cur ^ 1) * BUF;
+    f4 acc[RT][1];
+    init_fwd(acc);
+    gemm_hidden<P, RT, 1, 1, PDH, NK>(acc, wh, in, AS, wsrc(p.fwd_off[L - 1]), true,
+                                      wsrc(p.bwd_off[L - 1]), lane);
+    last_epi(acc[0][0], acc[1][0], out);
+    cur ^= 1;
+    __syncthreads();
+  }
+  // reverse: v_{l-1} = y tanh'_{l-1}, vd_{l-1} = yd tanh'_{l-1} + y dd_{l-1}
+#pragma unroll
+  for (int l = LM - 1; l >= 1; --l) {
+    if (l < L) {
+      const float* in = act + cur * BUF;
+      float* out = act + (cur ^ 1) * BUF;
+      f4 acc[RT][1];
+      acc[0][0] = f4{0.f, 0.f, 0.f, 0.f};
+      acc[1][0] = f4{0.f, 0.f, 0.f, 0.f};
+      gemm_hidden<P, RT, 1, 1, PDH, NK>(acc, wh, in, AS, wsrc(p.bwd_off[l]), l >= 2,
+                                        wsrc(p.bwd_off[l >= 2 ? l - 1 : l]), lane);
+      const f4 y = acc[0][0], yd = acc[1][0];
+      store_pair(out, y * sd[l - 1], yd * sd[l - 1] + y * sdd[l - 1]);
+      cur ^= 1;
+      __syncthreads();
+    }
+  }
+  // u0 | u0d = W_1^T [v_1 | vd_1], contraction split as in mlp_kernel; the
+  // vectors sit in buffer 1 (2L-1 flips), so u0 may alias buffer 0
+  {
+    const float* in = act + cur * BUF;
+    const int JT0 = XP / 16;
+    constexpr int KQ = NK / U0_SPLIT;
+    for (int it = wave; it < JT0 * U0_SPLIT; it += NW) {
+      const int t = it / U0_SPLIT, q = it - t * U0_SPLIT;
+      f4 a1[RT][1];
+      a1[0][0] = f4{0.f, 0.f, 0.f, 0.f};
+      a1[1][0] = f4{0.f, 0.f, 0.f, 0.f};
+      gemm_tiles<P, RT, 1, 7>(
+          a1, in + q * KQ * KF, AS,
+          WSrc{rsrc, (int)p.bwd_off[0] + t * kFragBytes + q * KQ * JT0 * kFragBytes,
+               JT0 * kFragBytes},
+          KQ, lane);
+      float* uq0 = u0 + q * R * US;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        *reinterpret_cast<f4*>(uq0 + (rt * 16 + wl) * US + t * 16 + uq) = a1[rt][0];
+    }
+  }
+  __syncthreads();
+  auto u0_at = [&](int i, int c) {
+    float v = u0[i * US + c];
+#pragma unroll
+    for (int q = 1; q < U0_SPLIT; ++q) v += u0[q * R * US + i * US + c];
+    return v;
+  };
+  for (int e = threadIdx.x; e < 16 * n; e += NW * 64) {
+    const int i = e / n, c = e - i * n;
+    const int row = row0 + i;
+    if (row < p.B) {
+      const float cs = xs[i * X2 + c], sn = xs[i * X2 + n + c];
+      const float hv = -sn * u0_at(16 + i, c) + cs * u0_at(16 + i, n + c);
+      const float cu = cs * u0_at(i, c) + sn * u0_at(i, n + c);
+      p.T_out[((size_t)k * p.B + row) * n + c] = hv - rs[i * n + c] * cu;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // weight packer: FP32 masters (packed layout) -> MFMA fragments, biases
 // ---------------------------------------------------------------------------
 struct PackLayer {
@@ -961,6 +1206,58 @@ rid_status dispatch(const rid_ensemble_impl& e, const float* x, int B, float* A_
   return launch_16bit<F16>(e, x, B, A_out, g_out, t, st);
 }
 
+size_t hvp_layout(int NP, int XP, int n, HvpArgs& a) {
+  constexpr int R = 32;
+  const int AS = (NP > XP ? NP : XP) + RID_ACT_PAD_BYTES / 4;
+  const size_t buf = (size_t)R * AS * 4;
+  size_t off = 2 * buf;
+  // the u0 partials (u0_split gives 4 parts at every FP32 width)
+  const size_t u0_bytes = (size_t)u0_split<F32, 64>() * R * (XP + 4) * 4;
+  if (u0_bytes <= buf) {
+    a.off_u0 = 0;                       // buffer 0 is free in the last GEMM
+  } else {
+    a.off_u0 = align16(off);
+    off = a.off_u0 + u0_bytes;
+  }
+  a.off_xs = align16(off);
+  off = a.off_xs + (size_t)16 * 2 * n * 4;
+  a.off_rs = align16(off);
+  off = a.off_rs + (size_t)16 * n * 4;
+  a.off_wo = align16(off);
+  return a.off_wo + (size_t)NP * 4;
+}
+
+template <int NP>
+rid_status run_hvp(const rid_ensemble_impl& e, const float* x, const float* rho,
+                   const float* coef, int B, float* T, hipStream_t st) {
+  constexpr int NW = NP / 16;
+  static size_t attr = 0;
+  HvpArgs a{};
+  const size_t lds = hvp_layout(NP, e.XP, e.n_cv, a);
+  if (lds > 160 * 1024) return fail(RID_EUNSUPPORTED, "shape too large for the HVP kernel");
+  auto kern = hvp_kernel<NP, NW, kMaxHidden>;
+  if (lds > 64 * 1024 && lds > attr) {
+    RID_HIP(hipFuncSetAttribute((const void*)kern,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = lds;
+  }
+  a.x = x; a.rho = rho; a.coef = coef; a.T_out = T;
+  a.B = B; a.n = e.n_cv; a.K = e.K; a.L = e.L; a.XP = e.XP;
+  a.n_tiles = (B + 15) / 16;
+  a.xcd_grp = (8 % e.K == 0) ? 8 / e.K : 0;
+  a.frag = e.d_frag; a.frag_model_bytes = e.frag_bytes_per_model;
+  for (int l = 0; l < e.L; ++l) {
+    a.fwd_off[l] = (unsigned)e.layers[l].fwd_off;
+    a.bwd_off[l] = (unsigned)e.layers[l].bwd_off;
+  }
+  a.bias = e.d_bias; a.wo = e.d_wo;
+  const int grid = a.xcd_grp > 0 ? 8 * ((a.n_tiles + a.xcd_grp - 1) / a.xcd_grp)
+                                  : a.n_tiles * e.K;
+  launch_timed(kProfHvp, kern, dim3(grid), dim3(NW * 64), (uint32_t)lds, st, a);
+  RID_HIP(hipGetLastError());
+  return RID_OK;
+}
+
 }  // namespace
 
 // Kernel family: (precision, padded width, depth) -> instantiation.
@@ -971,6 +1268,24 @@ rid_status dispatch(const rid_ensemble_impl& e, const float* x, int B, float* A_
 rid_status launch_mlp(const rid_ensemble_impl& e, const float* x, int B,
                       float* A_out, float* g_out, hipStream_t st) {
   return dispatch(e, x, B, A_out, g_out, nullptr, st);
+}
+
+bool hvp_fused_supported(const rid_ensemble_impl& e) {
+  if (e.prec != RID_FP32 || e.NP > 256 || e.L > kMaxHidden) return false;
+  HvpArgs a{};
+  return hvp_layout(e.NP, e.XP, e.n_cv, a) <= 160 * 1024;
+}
+
+rid_status launch_hvp(const rid_ensemble_impl& e, const float* x, const float* rho,
+                      const float* coef, int B, float* T, hipStream_t st) {
+  if (e.prec == RID_FP32) {
+    switch (e.NP) {
+      case 64:  return run_hvp<64>(e, x, rho, coef, B, T, st);
+      case 128: return run_hvp<128>(e, x, rho, coef, B, T, st);
+      case 256: return run_hvp<256>(e, x, rho, coef, B, T, st);
+    }
+  }
+  return fail(RID_EUNSUPPORTED, "no fused HVP kernel for this ensemble");
 }
 
 rid_status launch_mlp_from_pos(const rid_ensemble_impl& e, const TorsionInput& tin,

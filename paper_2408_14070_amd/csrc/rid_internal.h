@@ -43,7 +43,7 @@ struct DevBuf {
 // ---------------------------------------------------------------------------
 enum ProfKind {
   kProfCv = 0, kProfMlp = 1, kProfScatter = 2, kProfReduce = 3, kProfEmbed = 4,
-  kProfTrain = 5, kProfLabel = 6, kProfKinds = 7
+  kProfTrain = 5, kProfLabel = 6, kProfHvp = 7, kProfKinds = 8
 };
 bool prof_enabled();
 hipEvent_t prof_event();                 // from the pool, not yet recorded
@@ -165,6 +165,14 @@ rid_status launch_mlp_from_pos(const rid_ensemble_impl& e, const TorsionInput& t
 // g_out == nullptr: the free energies only (no reverse sweep).
 rid_status launch_mlp(const rid_ensemble_impl& e, const float* x, int B,
                       float* A_out, float* g_out, hipStream_t st);
+// Fused Hessian-vector products of conservative switching: per member k the
+// term T [K][B][n] of d eps/ds, from the encoding x [B][2n], w_k in
+// rho [B][K][n] and the walkers' Abar sigma' in coef [B] (tiles with no
+// walker in the band are skipped and their T left unwritten).  FP32
+// ensembles of padded width <= 256 only (hvp_fused_supported).
+bool hvp_fused_supported(const rid_ensemble_impl& e);
+rid_status launch_hvp(const rid_ensemble_impl& e, const float* x, const float* rho,
+                      const float* coef, int B, float* T, hipStream_t st);
 rid_status launch_ensemble_reduce(int K, int n, int B, const float* A,
                                   const float* g, float* eps, float* gbar,
                                   float* A_t, float* g_t, hipStream_t st);

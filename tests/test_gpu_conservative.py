@@ -63,8 +63,10 @@ def _run(torch, rid, sys_, pos, params, widths, K, e0, e1, conservative, prec=0)
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
+# FP32 ensembles of padded width <= 256 take the fused Hessian-vector kernel,
+# wider ones (and 16-bit ensembles) the training sweeps in input mode.
 @pytest.mark.parametrize("kind,widths,K", [("peptide20", [256] * 4, 4), ("dipeptide", [100] * 3, 4),
-                                           ("peptide20", [64, 64], 3)])
+                                           ("peptide20", [64, 64], 3), ("peptide20", [512] * 2, 2)])
 def test_conservative_force_parity_in_the_band(torch, rid, kind, widths, K):
     sys_, pos, params, widths, K = workload(kind, 48, seed=21, K=K, widths=widths, bias_std=0.1)
     models = oracle_models(params, sys_.n_cv, widths, K)
@@ -94,6 +96,29 @@ def test_conservative_full_size_bench_config(torch, rid):
     out = _run(torch, rid, sys_, pos, params, widths, K, e0, e1, True)
     bound = walker_bounds(out["eps"].astype(np.float64), ref["eps"], e0, e1)
     assert_walkers(out["F"], ref["F"], bound, "conservative, 1024 walkers")
+
+
+def test_conservative_band_on_one_tile_ragged_batch(torch, rid):
+    # walkers sorted by deviation, the band between the 16th and the 32nd:
+    # the first 16 walkers sit below it (sigma = 1, no switch gradient), the
+    # next 16 inside, the last 13 above it (sigma = 0), so the fused kernel
+    # skips two of its three 16-walker tiles, and the last tile is ragged
+    sys_, pos, params, widths, K = workload("peptide20", 45, seed=24, bias_std=0.1)
+    models = oracle_models(params, sys_.n_cv, widths, K)
+    ref1 = O.bias_force(pos.astype(np.float64), sys_.quads, models, 1e30, 2e30)
+    order = np.argsort(ref1["eps"])
+    pos = np.ascontiguousarray(pos[order])
+    ev = ref1["eps"][order]
+    e0, e1 = 0.5 * (ev[15] + ev[16]), 0.5 * (ev[31] + ev[32])
+    ref = O.bias_force_conservative(pos.astype(np.float64), sys_.quads, models, e0, e1)
+    assert np.all(ref["sigma"][:16] == 1.0) and np.all(ref["sigma"][32:] == 0.0)
+    assert np.all((ref["sigma"][16:32] > 0) & (ref["sigma"][16:32] < 1))
+    out = _run(torch, rid, sys_, pos, params, widths, K, e0, e1, True)
+    bound = walker_bounds(out["eps"].astype(np.float64), ref["eps"], e0, e1)
+    assert_walkers(out["F"], ref["F"], bound, "band on the middle tile")
+    frozen = _run(torch, rid, sys_, pos, params, widths, K, e0, e1, False)
+    assert_forces(out["F"][:16], frozen["F"][:16], FP32_TOL, "below the band = frozen")
+    assert np.all(out["F"][32:] == 0.0)
 
 
 def test_conservative_equals_frozen_outside_the_band(torch, rid):
