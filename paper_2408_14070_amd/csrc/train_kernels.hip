@@ -325,7 +325,7 @@ __global__ void adjoint_kernel(const float* HHl, long long slab_h, const float* 
 // Stage 1: block (column tile of 64, row chunk of kColRows, member); lanes
 // are columns (coalesced rows), the 4 waves take interleaved rows and are
 // combined in wave order -> part[chunk][k][j].
-constexpr int kColRows = 256;
+constexpr int kColRows = 64;     // 4 row chunks per 256 rows: enough workgroups in flight
 __global__ __launch_bounds__(256) void colsum_partial_kernel(const float* X, long long slab,
                                                              int B, int w, float* part, int K) {
   __shared__ float red[4][64];
@@ -336,6 +336,7 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(const float* X, lon
   float acc = 0.f;
   if (j < w) {
     const float* p = X + k * slab + j;
+#pragma unroll 4
     for (int b = r0 + wave; b < r1; b += 4) acc += p[(long long)b * w];
   }
   red[wave][lane] = acc;
