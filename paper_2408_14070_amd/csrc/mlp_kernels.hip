@@ -989,6 +989,341 @@ __global__ __launch_bounds__(NW * 64) void hvp_kernel(HvpArgs p) {
 }
 
 // ---------------------------------------------------------------------------
+// Mean-force training sweeps (FP32 ensembles), one workgroup per 16 samples
+// and member.  Loss L = (1/B) sum_b |g(s_b) - F_b|^2 with g = dA/ds.  Its
+// parameter gradient is the gradient of J = sum_b rho_b . g(s_b), with
+// rho = 2 (g - F) / B held fixed (or an upstream rho given by the caller),
+// and J is the tangent of A along rho_x = (dx/ds) rho.  The kernel runs,
+// from LDS and registers:
+//   primal forward      h_l = tanh(W_l h_{l-1} + b_l)            rows 0-15
+//   primal reverse      v_L = w_o tanh'_L, v_{l-1} = (W_l^T v_l) tanh'_{l-1},
+//                       u0 = W_1^T v_1, g, residual, rho_x       rows 0-15
+//   tangent forward     zd_l = W_l hd_{l-1}, hd_l = tanh'_l zd_l  rows 16-31
+//   adjoint of J        lam_zd = tanh' lam_hd,
+//                       lam_z = tanh' (lam_h - 2 h zd lam_hd),
+//                       [lam_h ; lam_hd]_{l-1} = W_l^T [lam_z ; lam_zd]_l,
+//                       top: lam_hd = w_o, lam_h = 0             rows 0-31
+// and writes what the batch-reduced weight gradients need: [h ; hd] of
+// every layer input (x ; rho_x first) and [lam_z ; lam_zd] of every layer,
+// each as [K][2B][width], plus the samples' squared residuals.  h and zd
+// of this lane's units stay in VGPRs between the sweeps.
+// ---------------------------------------------------------------------------
+struct TrainArgs {
+  const float* s;      // [B][n]
+  const float* F;      // [B][n] labels (null when rho is given)
+  const float* rho;    // [B][K][n] upstream gradient of g, or null
+  float* hh[kMaxHidden + 1];   // [K][2B][wd[j]]
+  float* sl[kMaxHidden];       // [K][2B][wd[j+1]]
+  float* loss_rows;    // [K][B] or null
+  int B, n, K, L, XP, n_tiles, xcd_grp;
+  int wd[kMaxHidden + 1];      // 2n, then the hidden widths
+  const unsigned char* frag;
+  unsigned long long frag_model_bytes;
+  unsigned fwd_off[kMaxHidden];
+  unsigned bwd_off[kMaxHidden];
+  const float* bias;   // [K][L][NP], pre-scaled
+  const float* wo;     // [K][NP]
+  unsigned off_u0, off_xs, off_wo;
+};
+
+template <int NP, int NW, int LM>
+__global__ __launch_bounds__(NW * 64) void train_kernel(TrainArgs p) {
+  using P = F32;
+  constexpr int KF = P::KF;
+  static_assert(16 * NW == NP, "one unit tile per wave");
+  constexpr int JT = NP / 16;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int k, tile;
+  map_block(blockIdx.x, p.K, p.xcd_grp, k, tile);
+  if (tile >= p.n_tiles) return;
+  const int row0 = tile * 16;
+  const int n = p.n, L = p.L, XP = p.XP, X2 = 2 * p.n, B = p.B;
+  const int AW = NP > XP ? NP : XP;
+  const int AS = AW + RID_ACT_PAD_BYTES / 4;
+  const int BUF = 32 * AS;
+  float* act = reinterpret_cast<float*>(smem);
+  float* u0 = reinterpret_cast<float*>(smem + p.off_u0);
+  const int US = XP + 4;
+  float* xs = reinterpret_cast<float*>(smem + p.off_xs);    // [16][2n]
+  float* wos = reinterpret_cast<float*>(smem + p.off_wo);   // [NP]
+
+  const unsigned char* fbase = p.frag + (size_t)k * p.frag_model_bytes;
+  const float* bias = p.bias + (size_t)k * L * NP;
+  const float* wo = p.wo + (size_t)k * NP;
+  constexpr int PD = RID_PD_FP32;
+  constexpr int NK = NP / KF;
+  constexpr int U0_SPLIT = u0_split<P, NP>();
+  constexpr int PDH = NK % (RID_PDH_FP32 + 1) == 0 ? RID_PDH_FP32 : 1;
+  const int jt0 = wave;
+  const int wl = lane & 15;
+  const int uq = 4 * (lane >> 4);
+  const int u = jt0 * 16 + uq;       // this lane's first unit
+  const int brow = row0 + wl;        // this lane's sample
+  const bool in_b = brow < B;
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<unsigned char*>(fbase), (short)0, (int)p.frag_model_bytes, 0x00020000);
+  auto wsrc = [&](unsigned off) {
+    return WSrc{rsrc, (int)off + jt0 * kFragBytes, JT * kFragBytes};
+  };
+  WRing<PD, 1> wr;
+  WRing<PDH, 1> wh;
+  ring_preload<PD, 1>(wr, wsrc(p.fwd_off[0]), XP / KF, lane);
+  f4 bnext = *reinterpret_cast<const f4*>(bias + u);
+  for (int i = threadIdx.x; i < NP; i += NW * 64) wos[i] = wo[i];
+
+  // 4 units of row r (0 .. 2B-1) of a [K][2B][w] array; units past w are
+  // padding and stay unwritten
+  auto put4 = [&](float* base, int w, int r, const f4& v) {
+    if (u >= w) return;
+    float* dst = base + ((size_t)k * 2 * B + r) * w + u;
+    if ((w & 3) == 0) {
+      *reinterpret_cast<f4*>(dst) = v;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (u + q < w) dst[q] = v[q];
+    }
+  };
+  auto lds4 = [&](float* buf, int r, const f4& v) {
+    *reinterpret_cast<f4*>(buf + r * AS + u) = v;
+  };
+
+  // input tile: x = [cos s | sin s] in rows 0-15 (and to hh[0]), zeros past
+  // 2n and past B
+  for (int e = threadIdx.x; e < 16 * XP; e += NW * 64) {
+    const int i = e / XP, c = e - i * XP;
+    const int row = row0 + i;
+    float v = 0.f;
+    if (row < B && c < X2) {
+      float sn, cs;
+      sincosf(p.s[(size_t)row * n + (c < n ? c : c - n)], &sn, &cs);
+      v = c < n ? cs : sn;
+      xs[i * X2 + c] = v;
+      p.hh[0][((size_t)k * 2 * B + row) * X2 + c] = v;
+    }
+    act[i * AS + c] = v;
+  }
+  __syncthreads();
+
+  f4 hs[LM];        // h of layers 0..L-1
+  f4 zs[LM - 1];    // zd of layers 0..L-2
+  int cur = 0;
+  auto next_after_fwd = [&](int j) {
+    return wsrc(j + 1 < L ? p.fwd_off[j + 1] : p.bwd_off[L > 1 ? L - 1 : 0]);
+  };
+  // primal forward epilogue of layer j: h to the next buffer (and HBM), or
+  // v_L = w_o tanh'_L at the top
+  auto fwd_epi = [&](int j, f4& hj, const f4& y, float* out) {
+    f4 h, d;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float dq;
+      h[q] = tanh_and_grad(y[q], dq);
+      d[q] = dq;
+    }
+    hj = h;
+    if (j < L - 1) {
+      lds4(out, wl, h);
+      if (in_b) put4(p.hh[j + 1], p.wd[j + 1], brow, h);
+    } else {
+      lds4(out, wl, *reinterpret_cast<const f4*>(wos + u) * d);
+    }
+  };
+
+  // ---------------- primal forward ----------------
+  {
+    float* out = act + BUF;
+    f4 acc[1][1];
+    acc[0][0] = bnext;
+    gemm_run<P, 1, 1, PD>(acc, wr, act, AS, wsrc(p.fwd_off[0]), XP / KF, lane);
+    if (L > 1) {
+      ring_preload<PDH, 1>(wh, next_after_fwd(0), NK, lane);
+      bnext = *reinterpret_cast<const f4*>(bias + NP + u);
+    }
+    fwd_epi(0, hs[0], acc[0][0], out);
+    cur = 1;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 1; j < LM; ++j) {
+    if (j < L) {
+      const float* in = act + cur * BUF;
+      float* out = act + (cur ^ 1) * BUF;
+      f4 acc[1][1];
+      acc[0][0] = bnext;
+      gemm_hidden<P, 1, 1, 1, PDH, NK>(acc, wh, in, AS, wsrc(p.fwd_off[j]), true,
+                                       next_after_fwd(j), lane);
+      if (j + 1 < L) bnext = *reinterpret_cast<const f4*>(bias + (j + 1) * NP + u);
+      fwd_epi(j, hs[j], acc[0][0], out);
+      cur ^= 1;
+      __syncthreads();
+    }
+  }
+  // ---------------- primal reverse to u0 ----------------
+#pragma unroll
+  for (int j = LM - 1; j >= 1; --j) {
+    if (j < L) {
+      const float* in = act + cur * BUF;
+      float* out = act + (cur ^ 1) * BUF;
+      f4 acc[1][1];
+      acc[0][0] = f4{0.f, 0.f, 0.f, 0.f};
+      gemm_hidden<P, 1, 1, 1, PDH, NK>(acc, wh, in, AS, wsrc(p.bwd_off[j]), j >= 2,
+                                       wsrc(p.bwd_off[j >= 2 ? j - 1 : j]), lane);
+      const f4 h = hs[j - 1];
+      lds4(out, wl, acc[0][0] * (1.f - h * h));
+      cur ^= 1;
+      __syncthreads();
+    }
+  }
+  // u0 = W_1^T v_1 (v_1 in buffer 1 after 2L-1 flips; the partials may
+  // alias buffer 0)
+  {
+    const float* in = act + cur * BUF;
+    const int JT0 = XP / 16;
+    constexpr int KQ = NK / U0_SPLIT;
+    for (int it = wave; it < JT0 * U0_SPLIT; it += NW) {
+      const int t = it / U0_SPLIT, q = it - t * U0_SPLIT;
+      f4 a1[1][1];
+      a1[0][0] = f4{0.f, 0.f, 0.f, 0.f};
+      gemm_tiles<P, 1, 1, 7>(
+          a1, in + q * KQ * KF, AS,
+          WSrc{rsrc, (int)p.bwd_off[0] + t * kFragBytes + q * KQ * JT0 * kFragBytes,
+               JT0 * kFragBytes},
+          KQ, lane);
+      *reinterpret_cast<f4*>(u0 + q * 16 * US + wl * US + t * 16 + uq) = a1[0][0];
+    }
+  }
+  ring_preload<PD, 1>(wr, wsrc(p.fwd_off[0]), XP / KF, lane);   // tangent layer 1
+  __syncthreads();
+  auto u0_at = [&](int i, int c) {
+    float v = u0[i * US + c];
+#pragma unroll
+    for (int q = 1; q < U0_SPLIT; ++q) v += u0[q * 16 * US + i * US + c];
+    return v;
+  };
+  // ---------------- residual and rho_x (a wave per sample) ----------------
+  // rho_x goes to rows 16-31 of the buffer holding v_1 (its rows 0-15 are
+  // dead after the u0 GEMM) and to the tangent half of hh[0]
+  float* tin = act + cur * BUF + 16 * AS;
+  for (int i = wave; i < 16; i += NW) {
+    const int row = row0 + i;
+    float acc = 0.f;
+    for (int c = lane; c < n; c += 64) {
+      float rx0 = 0.f, rx1 = 0.f;
+      if (row < B) {
+        const float cs = xs[i * X2 + c], sn = xs[i * X2 + n + c];
+        float rho;
+        if (p.rho) {
+          rho = p.rho[((size_t)row * p.K + k) * n + c];
+        } else {
+          const float gi = -sn * u0_at(i, c) + cs * u0_at(i, n + c);
+          const float ri = gi - p.F[(size_t)row * n + c];
+          acc += ri * ri;
+          rho = 2.f * ri / (float)B;
+        }
+        rx0 = -sn * rho;
+        rx1 = cs * rho;
+        float* h0 = p.hh[0] + ((size_t)k * 2 * B + B + row) * X2;
+        h0[c] = rx0;
+        h0[n + c] = rx1;
+      }
+      tin[i * AS + c] = rx0;
+      tin[i * AS + n + c] = rx1;
+    }
+    for (int c = X2 + lane; c < XP; c += 64) tin[i * AS + c] = 0.f;
+    if (p.loss_rows && row < B) {
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+      if (lane == 0) p.loss_rows[(size_t)k * B + row] = acc;
+    }
+  }
+  __syncthreads();
+
+  // ---------------- tangent forward, then the adjoint's top ----------------
+  // layer j epilogue: hd = tanh'_j zd; below the top hd goes on (rows 16-31)
+  // and zd is kept; at the top the adjoint starts:
+  // lam_zd = tanh'_L w_o, lam_z = tanh'_L (-2 h_L zd_L w_o)
+  auto tan_epi = [&](int j, const f4& h, f4& zj, const f4& y, float* out) {
+    const f4 zd = y * kTanhUnscale;
+    const f4 d = 1.f - h * h;
+    const f4 hd = d * zd;
+    if (in_b) put4(p.hh[j + 1], p.wd[j + 1], B + brow, hd);
+    if (j < L - 1) {
+      lds4(out, 16 + wl, hd);
+      zj = zd;
+    } else {
+      const f4 w4 = *reinterpret_cast<const f4*>(wos + u);
+      const f4 lzd = d * w4;
+      const f4 lz = d * (-2.f * h * zd * w4);
+      lds4(out, wl, lz);
+      lds4(out, 16 + wl, lzd);
+      if (in_b) {
+        put4(p.sl[j], p.wd[j + 1], brow, lz);
+        put4(p.sl[j], p.wd[j + 1], B + brow, lzd);
+      }
+    }
+  };
+  {
+    const float* in = act + cur * BUF + 16 * AS;
+    float* out = act + (cur ^ 1) * BUF;
+    f4 acc[1][1];
+    acc[0][0] = f4{0.f, 0.f, 0.f, 0.f};
+    gemm_run<P, 1, 1, PD>(acc, wr, in, AS, wsrc(p.fwd_off[0]), XP / KF, lane);
+    if (L > 1) ring_preload<PDH, 1>(wh, next_after_fwd(0), NK, lane);
+    f4 dummy;
+    tan_epi(0, hs[0], L > 1 ? zs[0] : dummy, acc[0][0], out);
+    cur ^= 1;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 1; j < LM; ++j) {
+    if (j < L) {
+      const float* in = act + cur * BUF + 16 * AS;
+      float* out = act + (cur ^ 1) * BUF;
+      f4 acc[1][1];
+      acc[0][0] = f4{0.f, 0.f, 0.f, 0.f};
+      gemm_hidden<P, 1, 1, 1, PDH, NK>(acc, wh, in, AS, wsrc(p.fwd_off[j]), true,
+                                       next_after_fwd(j), lane);
+      f4 dummy;
+      tan_epi(j, hs[j], j < LM - 1 ? zs[j < LM - 1 ? j : 0] : dummy, acc[0][0], out);
+      cur ^= 1;
+      __syncthreads();
+    }
+  }
+  // ---------------- adjoint reverse (primal and tangent rows together) ----------------
+#pragma unroll
+  for (int j = LM - 1; j >= 1; --j) {
+    if (j < L) {
+      const float* in = act + cur * BUF;
+      float* out = act + (cur ^ 1) * BUF;
+      f4 acc[2][1];
+      acc[0][0] = f4{0.f, 0.f, 0.f, 0.f};
+      acc[1][0] = f4{0.f, 0.f, 0.f, 0.f};
+      gemm_hidden<P, 2, 1, 1, PDH, NK>(acc, wh, in, AS, wsrc(p.bwd_off[j]), j >= 2,
+                                       wsrc(p.bwd_off[j >= 2 ? j - 1 : j]), lane);
+      const f4 h = hs[j - 1], zd = zs[j - 1];
+      const f4 d = 1.f - h * h;
+      const f4 lhd = acc[1][0];
+      const f4 lzd = d * lhd;
+      const f4 lz = d * (acc[0][0] - 2.f * h * zd * lhd);
+      if (j >= 2) {
+        lds4(out, wl, lz);
+        lds4(out, 16 + wl, lzd);
+      }
+      if (in_b) {
+        put4(p.sl[j - 1], p.wd[j], brow, lz);
+        put4(p.sl[j - 1], p.wd[j], B + brow, lzd);
+      }
+      cur ^= 1;
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // weight packer: FP32 masters (packed layout) -> MFMA fragments, biases
 // ---------------------------------------------------------------------------
 struct PackLayer {
@@ -1258,6 +1593,58 @@ rid_status run_hvp(const rid_ensemble_impl& e, const float* x, const float* rho,
   return RID_OK;
 }
 
+size_t train_layout(int NP, int XP, int n, TrainArgs& a) {
+  const int AS = (NP > XP ? NP : XP) + RID_ACT_PAD_BYTES / 4;
+  const size_t buf = (size_t)32 * AS * 4;
+  size_t off = 2 * buf;
+  // the u0 partials of 16 rows (4 parts at every FP32 width)
+  const size_t u0_bytes = (size_t)u0_split<F32, 64>() * 16 * (XP + 4) * 4;
+  if (u0_bytes <= buf) {
+    a.off_u0 = 0;                       // buffer 0 is free in the u0 GEMM
+  } else {
+    a.off_u0 = align16(off);
+    off = a.off_u0 + u0_bytes;
+  }
+  a.off_xs = align16(off);
+  off = a.off_xs + (size_t)16 * 2 * n * 4;
+  a.off_wo = align16(off);
+  return a.off_wo + (size_t)NP * 4;
+}
+
+template <int NP>
+rid_status run_train(const rid_ensemble_impl& e, const TrainIo& io, int B, hipStream_t st) {
+  constexpr int NW = NP / 16;
+  static size_t attr = 0;
+  TrainArgs a{};
+  const size_t lds = train_layout(NP, e.XP, e.n_cv, a);
+  if (lds > 160 * 1024) return fail(RID_EUNSUPPORTED, "shape too large for the training kernel");
+  auto kern = train_kernel<NP, NW, kMaxHidden>;
+  if (lds > 64 * 1024 && lds > attr) {
+    RID_HIP(hipFuncSetAttribute((const void*)kern,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = lds;
+  }
+  a.s = io.s; a.F = io.F; a.rho = io.rho; a.loss_rows = io.loss_rows;
+  for (int j = 0; j <= e.L; ++j) a.hh[j] = io.hh[j];
+  for (int j = 0; j < e.L; ++j) a.sl[j] = io.sl[j];
+  a.B = B; a.n = e.n_cv; a.K = e.K; a.L = e.L; a.XP = e.XP;
+  a.n_tiles = (B + 15) / 16;
+  a.xcd_grp = (8 % e.K == 0) ? 8 / e.K : 0;
+  a.wd[0] = 2 * e.n_cv;
+  for (int j = 0; j < e.L; ++j) a.wd[j + 1] = e.widths[j];
+  a.frag = e.d_frag; a.frag_model_bytes = e.frag_bytes_per_model;
+  for (int l = 0; l < e.L; ++l) {
+    a.fwd_off[l] = (unsigned)e.layers[l].fwd_off;
+    a.bwd_off[l] = (unsigned)e.layers[l].bwd_off;
+  }
+  a.bias = e.d_bias; a.wo = e.d_wo;
+  const int grid = a.xcd_grp > 0 ? 8 * ((a.n_tiles + a.xcd_grp - 1) / a.xcd_grp)
+                                  : a.n_tiles * e.K;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), (uint32_t)lds, st, a);
+  RID_HIP(hipGetLastError());
+  return RID_OK;
+}
+
 }  // namespace
 
 // Kernel family: (precision, padded width, depth) -> instantiation.
@@ -1286,6 +1673,24 @@ rid_status launch_hvp(const rid_ensemble_impl& e, const float* x, const float* r
     }
   }
   return fail(RID_EUNSUPPORTED, "no fused HVP kernel for this ensemble");
+}
+
+bool train_fused_supported(const rid_ensemble_impl& e) {
+  if (e.prec != RID_FP32 || e.NP > 256 || e.L > kMaxHidden) return false;
+  TrainArgs a{};
+  return train_layout(e.NP, e.XP, e.n_cv, a) <= 160 * 1024;
+}
+
+rid_status launch_train_sweeps(const rid_ensemble_impl& e, const TrainIo& io, int B,
+                               hipStream_t st) {
+  if (e.prec == RID_FP32) {
+    switch (e.NP) {
+      case 64:  return run_train<64>(e, io, B, st);
+      case 128: return run_train<128>(e, io, B, st);
+      case 256: return run_train<256>(e, io, B, st);
+    }
+  }
+  return fail(RID_EUNSUPPORTED, "no fused training kernel for this ensemble");
 }
 
 rid_status launch_mlp_from_pos(const rid_ensemble_impl& e, const TorsionInput& tin,

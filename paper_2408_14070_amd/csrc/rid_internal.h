@@ -173,6 +173,24 @@ rid_status launch_mlp(const rid_ensemble_impl& e, const float* x, int B,
 bool hvp_fused_supported(const rid_ensemble_impl& e);
 rid_status launch_hvp(const rid_ensemble_impl& e, const float* x, const float* rho,
                       const float* coef, int B, float* T, hipStream_t st);
+// Fused sweeps of one mean-force training step (FP32 ensembles of padded
+// width <= 256, train_fused_supported): from the samples s [B][n] and labels
+// F [B][n] (or an upstream gradient rho [B][K][n] of the g outputs), writes
+// hh[j] = [h_j ; hd_j] (j = 0: [x ; rho_x]) and sl[j] = [lam_z ; lam_zd] of
+// layer j, each [K][2B][width], and the squared residual per sample
+// loss_rows [K][B] (labels only).  The fragments must be packed from the
+// current masters.
+struct TrainIo {
+  const float* s;
+  const float* F;
+  const float* rho;
+  float* hh[kMaxHidden + 1];
+  float* sl[kMaxHidden];
+  float* loss_rows;
+};
+bool train_fused_supported(const rid_ensemble_impl& e);
+rid_status launch_train_sweeps(const rid_ensemble_impl& e, const TrainIo& io, int B,
+                               hipStream_t st);
 rid_status launch_ensemble_reduce(int K, int n, int B, const float* A,
                                   const float* g, float* eps, float* gbar,
                                   float* A_t, float* g_t, hipStream_t st);

@@ -457,6 +457,87 @@ rid_status colsum(const float* X, long long slab, int B, int w, int K, float* pa
   return RID_OK;
 }
 
+// The training step with the sweeps fused into one kernel (train_kernel):
+// it writes [h ; hd] of every layer input and [lam_z ; lam_zd] of every
+// layer, then the batch reductions run as before: dW_l = S_l^T [h ; hd]_{l-1}
+// (split over the 2B rows), db_l = column sums of lam_z, dw_o = column sums
+// of hd_L.  Workspace regions are 256-byte aligned (the kernel stores float4).
+rid_status mf_grad_fused(rid_ensemble_impl& e, const float* s, const float* F,
+                         const float* rho, int B, float* loss, float* grad_out,
+                         float** grad_used, hipStream_t st, const std::vector<int>& w,
+                         const std::vector<long long>& w_off,
+                         const std::vector<long long>& b_off, long long wo_off, int ks,
+                         int kchunk) {
+  const int K = e.K, L = e.L;
+  int wmax = 0;
+  for (int v : w) wmax = std::max(wmax, v);
+  auto al = [](long long v) { return (v + 63) / 64 * 64; };
+  std::vector<long long> hh(L + 1), sl(L);
+  long long tot = 0;
+  for (int l = 0; l <= L; ++l) {
+    hh[l] = tot;
+    tot = al(tot + (long long)K * 2 * B * w[l]);
+  }
+  for (int l = 1; l <= L; ++l) {
+    sl[l - 1] = tot;
+    tot = al(tot + (long long)K * 2 * B * w[l]);
+  }
+  long long part_slab = 0;
+  for (int l = 0; l < L; ++l) part_slab = std::max(part_slab, (long long)K * w[l + 1] * w[l]);
+  const long long part = tot; tot = al(tot + part_slab * ks);
+  const long long grad = tot; tot = al(tot + (long long)e.n_params);
+  const long long lrows = tot; tot = al(tot + (long long)K * B);
+  const long long cpart = tot; tot = al(tot + (long long)((B + kColRows - 1) / kColRows) * K * wmax);
+  rid_status rs = e.ws_train.ensure(sizeof(float) * tot);
+  if (rs != RID_OK) return rs;
+  float* W = e.ws_train.as<float>();
+  const long long pm = (long long)e.per_model;
+  float* G = grad_out ? grad_out : W + grad;
+  if (grad_used) *grad_used = G;
+  ProfScope ps(kProfTrain, st);
+  if (e.frag_dirty) {
+    if ((rs = pack_ensemble_weights(e, st)) != RID_OK) return rs;
+    e.frag_dirty = false;
+  }
+  TrainIo io{};
+  io.s = s;
+  io.F = rho ? nullptr : F;
+  io.rho = rho;
+  io.loss_rows = rho ? nullptr : W + lrows;
+  for (int l = 0; l <= L; ++l) io.hh[l] = W + hh[l];
+  for (int l = 0; l < L; ++l) io.sl[l] = W + sl[l];
+  if ((rs = launch_train_sweeps(e, io, B, st)) != RID_OK) return rs;
+  if (!rho) {
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(K), dim3(256), 0, st, W + lrows, B, loss);
+    RID_HIP(hipGetLastError());
+  }
+  for (int l = L; l >= 1; --l) {
+    GemmArgs g{};
+    g.A = W + sl[l - 1]; g.sAb = 2LL * B * w[l]; g.sAm = 1; g.sAk = w[l];
+    g.Bm = W + hh[l - 1]; g.sBb = 2LL * B * w[l - 1]; g.sBk = w[l - 1]; g.sBn = 1;
+    g.C = W + part; g.sCb = (long long)w[l] * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
+    g.sCs = (long long)K * w[l] * w[l - 1];
+    g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * B; g.batch = K; g.ksplit = ks; g.kchunk = kchunk;
+    g.mode = EPI_STORE;
+    if ((rs = gemm(g, st)) != RID_OK) return rs;
+    hipLaunchKernelGGL(splitk_reduce_kernel,
+                       dim3(grid1d((long long)K * w[l] * w[l - 1])), dim3(256), 0, st,
+                       W + part, (long long)K * w[l] * w[l - 1], ks, w[l], w[l - 1], K,
+                       G, pm, (int)w_off[l - 1]);
+    RID_HIP(hipGetLastError());
+    if ((rs = colsum(W + sl[l - 1], 2LL * B * w[l], B, w[l], K, W + cpart, G, pm,
+                     (int)b_off[l - 1], st)) != RID_OK)
+      return rs;
+  }
+  if ((rs = colsum(W + hh[L] + (long long)B * w[L], 2LL * B * w[L], B, w[L], K, W + cpart, G,
+                   pm, (int)wo_off, st)) != RID_OK)
+    return rs;
+  hipLaunchKernelGGL(set_zero_kernel, dim3(1), dim3(64), 0, st, G, pm,
+                     (int)(wo_off + w[L]), K);
+  RID_HIP(hipGetLastError());
+  return RID_OK;
+}
+
 }  // namespace
 
 // Gradient in the packed parameter layout of
@@ -497,6 +578,10 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   int ks = 1;
   while (ks < 64 && (long long)K * tiles_max * ks < 1024 && 2LL * B / (ks * 2) >= 256) ks *= 2;
   const int kchunk = round_up((2 * B + ks - 1) / ks, BK);
+
+  if (!input_mode && train_fused_supported(e))
+    return mf_grad_fused(e, s, F, rho, B, loss, grad_out, grad_used, st, w, w_off, b_off,
+                         wo_off, ks, kchunk);
 
   // workspace (floats)
   std::vector<long long> hh(L + 1), zd(L + 1);
