@@ -1333,19 +1333,51 @@ struct PackLayer {
   unsigned fwd_off, bwd_off;  // byte offsets inside one model's fragments
 };
 
+struct VecArgs {
+  unsigned b_off[kMaxHidden];
+  int out[kMaxHidden];
+  unsigned wo_off;
+  int last_w;
+};
+
+struct PackAll {
+  PackLayer layer[kMaxHidden];
+  VecArgs va;
+  int L, K, NP;
+};
+
+// One launch packs a whole ensemble: block row y < 2L packs layer y/2 in
+// direction y%2 (0: forward fragments, contraction = the layer input,
+// pre-scaled by 2/ln 2; 1: backward, contraction = the layer output); row
+// 2L packs the biases (pre-scaled), w_o and b_o, zero-padded to NP.
 template <class P>
-__global__ void pack_layer_kernel(const float* master, size_t per_model, int K,
-                                  PackLayer pl, int NP, int dir,
-                                  unsigned char* frag, size_t frag_model_bytes) {
+__global__ void pack_kernel(const float* master, size_t per_model, PackAll pa,
+                            unsigned char* frag, size_t frag_model_bytes, float* bias,
+                            float* wo, float* bo) {
   using T = typename P::T;
   constexpr int KF = P::KF;
   constexpr int E = 16 / sizeof(T);
-  // dir 0: contraction = input (kin_pad), rows = NP (outputs)
-  // dir 1: contraction = NP (outputs), rows = kin_pad (inputs)
+  const int NP = pa.NP;
+  if ((int)blockIdx.y == 2 * pa.L) {
+    const VecArgs& va = pa.va;
+    for (int k = blockIdx.x; k < pa.K; k += gridDim.x) {
+      const float* m = master + (size_t)k * per_model;
+      for (int l = 0; l < pa.L; ++l)
+        for (int j = threadIdx.x; j < NP; j += blockDim.x)
+          bias[((size_t)k * pa.L + l) * NP + j] =
+              j < va.out[l] ? kTanhPrescale * m[va.b_off[l] + j] : 0.f;
+      for (int j = threadIdx.x; j < NP; j += blockDim.x)
+        wo[(size_t)k * NP + j] = j < va.last_w ? m[va.wo_off + j] : 0.f;
+      if (threadIdx.x == 0) bo[k] = m[va.wo_off + va.last_w];
+    }
+    return;
+  }
+  const PackLayer& pl = pa.layer[blockIdx.y >> 1];
+  const int dir = blockIdx.y & 1;
   const int kc = dir == 0 ? pl.kin_pad : NP;
   const int nc = dir == 0 ? NP : pl.kin_pad;
   const int JT = nc / 16, KT = kc / KF;
-  const size_t total = (size_t)K * KT * JT * 64;
+  const size_t total = (size_t)pa.K * KT * JT * 64;
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total;
        t += (size_t)gridDim.x * blockDim.x) {
     const int lane = t % 64;
@@ -1372,27 +1404,6 @@ __global__ void pack_layer_kernel(const float* master, size_t per_model, int K,
                          (((size_t)kt * JT + jt) * 64 + lane) * 16;
     *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(out);
   }
-}
-
-struct VecArgs {
-  unsigned b_off[kMaxHidden];
-  int out[kMaxHidden];
-  unsigned wo_off;
-  int last_w;
-};
-
-__global__ void pack_vec_kernel(const float* master, size_t per_model, int L,
-                                int NP, VecArgs va, float* bias, float* wo,
-                                float* bo) {
-  const int k = blockIdx.x;
-  const float* m = master + (size_t)k * per_model;
-  for (int l = 0; l < L; ++l)
-    for (int j = threadIdx.x; j < NP; j += blockDim.x)
-      bias[((size_t)k * L + l) * NP + j] =
-          j < va.out[l] ? kTanhPrescale * m[va.b_off[l] + j] : 0.f;
-  for (int j = threadIdx.x; j < NP; j += blockDim.x)
-    wo[(size_t)k * NP + j] = j < va.last_w ? m[va.wo_off + j] : 0.f;
-  if (threadIdx.x == 0) bo[k] = m[va.wo_off + va.last_w];
 }
 
 inline unsigned align16(size_t v) { return (unsigned)((v + 15) / 16 * 16); }
@@ -1700,43 +1711,39 @@ rid_status launch_mlp_from_pos(const rid_ensemble_impl& e, const TorsionInput& t
 
 rid_status pack_ensemble_weights(rid_ensemble_impl& e, hipStream_t st) {
   const int L = e.L;
-  VecArgs va{};
+  PackAll pa{};
+  pa.L = L;
+  pa.K = e.K;
+  pa.NP = e.NP;
   unsigned off = 0;
   int prev = 2 * e.n_cv;
   for (int l = 0; l < L; ++l) {
-    PackLayer pl{};
+    PackLayer& pl = pa.layer[l];
     pl.w_off = off;
     pl.in = prev;
     pl.out = e.widths[l];
     off += (unsigned)(pl.out * pl.in);
     pl.b_off = off;
-    va.b_off[l] = off;
-    va.out[l] = pl.out;
+    pa.va.b_off[l] = off;
+    pa.va.out[l] = pl.out;
     off += (unsigned)pl.out;
     pl.kin_pad = e.layers[l].kin_pad;
     pl.fwd_off = (unsigned)e.layers[l].fwd_off;
     pl.bwd_off = (unsigned)e.layers[l].bwd_off;
-    for (int dir = 0; dir < 2; ++dir) {
-      if (e.prec == RID_FP32)
-        hipLaunchKernelGGL(pack_layer_kernel<F32>, dim3(512), dim3(256), 0, st,
-                           e.d_master, e.per_model, e.K, pl, e.NP, dir,
-                           e.d_frag, e.frag_bytes_per_model);
-      else if (e.prec == RID_BF16)
-        hipLaunchKernelGGL(pack_layer_kernel<BF16>, dim3(512), dim3(256), 0, st,
-                           e.d_master, e.per_model, e.K, pl, e.NP, dir,
-                           e.d_frag, e.frag_bytes_per_model);
-      else
-        hipLaunchKernelGGL(pack_layer_kernel<F16>, dim3(512), dim3(256), 0, st,
-                           e.d_master, e.per_model, e.K, pl, e.NP, dir,
-                           e.d_frag, e.frag_bytes_per_model);
-      RID_HIP(hipGetLastError());
-    }
     prev = pl.out;
   }
-  va.wo_off = off;
-  va.last_w = prev;
-  hipLaunchKernelGGL(pack_vec_kernel, dim3(e.K), dim3(256), 0, st, e.d_master,
-                     e.per_model, L, e.NP, va, e.d_bias, e.d_wo, e.d_bo);
+  pa.va.wo_off = off;
+  pa.va.last_w = prev;
+  const dim3 grid(256, 2 * L + 1), block(256);
+  if (e.prec == RID_FP32)
+    hipLaunchKernelGGL(pack_kernel<F32>, grid, block, 0, st, e.d_master, e.per_model, pa,
+                       e.d_frag, e.frag_bytes_per_model, e.d_bias, e.d_wo, e.d_bo);
+  else if (e.prec == RID_BF16)
+    hipLaunchKernelGGL(pack_kernel<BF16>, grid, block, 0, st, e.d_master, e.per_model, pa,
+                       e.d_frag, e.frag_bytes_per_model, e.d_bias, e.d_wo, e.d_bo);
+  else
+    hipLaunchKernelGGL(pack_kernel<F16>, grid, block, 0, st, e.d_master, e.per_model, pa,
+                       e.d_frag, e.frag_bytes_per_model, e.d_bias, e.d_wo, e.d_bo);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }

@@ -346,16 +346,30 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(const float* X, lon
         ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-// Stage 2: sum the chunks in order into the gradient buffer at
-// grad + k*per_model + dst_off + j.
-__global__ void colsum_final_kernel(const float* part, int chunks, int w, int K, float* grad,
-                                    long long per_model, int dst_off) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= K * w) return;
-  const int k = e / w, j = e - k * w;
+// Stage 2: out[k][j] = the chunk partials summed in chunk order, into the
+// gradient buffer at grad + k*per_model + dst_off + j.  A block covers 64
+// outputs; each of its 4 waves sums a quarter of the chunks (in order) and
+// the quarters are combined in wave order.
+__global__ __launch_bounds__(256) void colsum_final_kernel(const float* part, int chunks, int w,
+                                                           int K, float* grad,
+                                                           long long per_model, int dst_off) {
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;     // output k*w + j
+  const int cq = (chunks + 3) / 4;
+  const int c0 = wave * cq, c1 = min(chunks, c0 + cq);
   float acc = 0.f;
-  for (int c = 0; c < chunks; ++c) acc += part[((long long)c * K + k) * w + j];
-  grad[k * per_model + dst_off + j] = acc;
+  if (e < K * w) {
+#pragma unroll 4
+    for (int c = c0; c < c1; ++c) acc += part[(long long)c * K * w + e];
+  }
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && e < K * w) {
+    const int k = e / w, j = e - k * w;
+    grad[k * per_model + dst_off + j] =
+        ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  }
 }
 
 // dW[k] = sum over split-K slabs (fixed order) -> gradient buffer
@@ -451,7 +465,7 @@ rid_status colsum(const float* X, long long slab, int B, int w, int K, float* pa
   hipLaunchKernelGGL(colsum_partial_kernel, dim3((w + 63) / 64, chunks, K), dim3(256), 0, st,
                      X, slab, B, w, part, K);
   RID_HIP(hipGetLastError());
-  hipLaunchKernelGGL(colsum_final_kernel, dim3((K * w + 255) / 256), dim3(256), 0, st, part,
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((K * w + 63) / 64), dim3(256), 0, st, part,
                      chunks, w, K, grad, per_model, dst_off);
   RID_HIP(hipGetLastError());
   return RID_OK;
