@@ -89,7 +89,7 @@ struct Server {
   std::vector<ServeModel> models;
 
   std::mutex mu;
-  std::condition_variable cv_sched, cv_done;
+  std::condition_variable cv_sched, cv_done, cv_poll;   // cv_poll: a batch went in flight
   std::deque<serve::Waiting> waiting;
   std::unordered_map<int64_t, Req> reqs;
   std::vector<Batch> inflight;
@@ -222,6 +222,7 @@ void Server::run_scheduler() {
     batch_walkers += b.walkers;
     inflight.push_back(std::move(b));
     max_inflight = std::max<int64_t>(max_inflight, (int64_t)inflight.size());
+    cv_poll.notify_one();
   }
 }
 
@@ -253,10 +254,13 @@ void Server::run_poller() {
     }
     if (inflight.empty()) {
       if (stop && launching == 0) break;
-      cv_done.wait_for(lk, std::chrono::milliseconds(2));
+      cv_poll.wait_for(lk, std::chrono::milliseconds(2));
     } else if (!any) {
+      // poll again in ~10 us (a sleep this short would overshoot by the
+      // timer slack, tens of microseconds)
       lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(5));
+      const auto until = clk::now() + std::chrono::microseconds(10);
+      while (clk::now() < until) std::this_thread::yield();
       lk.lock();
     }
   }
@@ -286,7 +290,7 @@ rid_status rid_server_create(size_t hbm_budget_bytes, int n_streams,
   s.n_slots = s.fifo ? 1 : n_streams;
   s.max_batch = max_batch_walkers;
   s.budget = hbm_budget_bytes;
-  const size_t pin_cap = (size_t)256 << 20;   // pinned staging arena
+  const size_t pin_cap = (size_t)1 << 30;     // pinned staging arena
   if (hipMalloc(&s.dev_base, hbm_budget_bytes) != hipSuccess) {
     (void)hipGetLastError();
     delete h;
@@ -485,6 +489,7 @@ void rid_server_destroy(rid_server srv) {
   }
   s.cv_sched.notify_all();
   s.cv_done.notify_all();
+  s.cv_poll.notify_all();
   if (s.sched.joinable()) s.sched.join();
   if (s.poller.joinable()) s.poller.join();
   for (auto st : s.streams) (void)hipStreamSynchronize(st);
