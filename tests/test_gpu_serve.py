@@ -156,3 +156,27 @@ def test_fifo_baseline_mode(torch, rid):
     for i, o in enumerate(outs):
         assert np.array_equal(o["F"], _direct(torch, rid, ms[i % 2], poss[i], 2.0, 3.0)["F"])
     srv.close()
+
+
+def test_completion_is_signalled_without_a_poll_timeout(torch, rid):
+    # The completion thread must wake when a batch is launched, not on its
+    # idle timeout (2 ms): a 4-walker request's round trip is tens of
+    # microseconds of kernels and copies.  The bound leaves a wide margin for
+    # a loaded host while staying below the timeout.
+    import time
+    sys_ = ridgen.system_dipeptide()
+    S = rid.System(sys_.n_atoms, sys_.quads)
+    E = rid.Ensemble(sys_.n_cv, [100] * 3, 4, ridgen.xavier_ensemble(2 * sys_.n_cv, [100] * 3, 4, 5))
+    srv = rid.Server(1 << 30, n_streams=2)
+    mid = srv.register(S, E, 2.0, 3.0)
+    pos = ridgen.f32(ridgen.chain_coords(sys_, 4, 1))
+    srv.wait(srv.submit(mid, pos))
+    rt = []
+    for _ in range(50):
+        t0 = time.perf_counter()
+        srv.wait(srv.submit(mid, pos))
+        rt.append(time.perf_counter() - t0)
+    srv.close()
+    med = float(np.median(rt))
+    print(f"round trip median {1e6 * med:.0f} us", flush=True)
+    assert med < 1e-3
