@@ -62,6 +62,13 @@ Functions and what pins them (tests/test_oracle_*.py):
                       pinned: Gaussian-frame closed form within 4 sigma, the
                       periodic wrap example, block standard error of iid
                       blocks
+  leader_cluster      threshold clustering of CV frames ("Selection" phase;
+  adapt_threshold     cluster threshold, cluster-count window, max_selection)
+  select_frames       pinned: a hand-worked periodic example, brute-force
+                      first-match and leader-separation checks, the two
+                      threshold limits, a masked run equal to the run on
+                      the kept subset, the window reached on well-separated
+                      synthetic clusters
 """
 from __future__ import annotations
 
@@ -695,3 +702,106 @@ def rms_rel_err(test, ref):
     test = np.asarray(test, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     return float(np.linalg.norm(test - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+# --------------------------------------------------------------------------
+# next-3: selection ("Selection" phase; "SelectorConfig": cluster_threshold,
+# numb_cluster_lower/upper, max_selection)
+# --------------------------------------------------------------------------
+def frame_deviation(models, s):
+    """Model deviation eps of CV frames s [B][n] (the uncertainty the
+    selection filters on): model_deviation of the ensemble's mean forces."""
+    _, g = ensemble_mean_force(models, s)
+    return model_deviation(g)[1]
+
+
+def cv_distance_sq_f32(a, b):
+    """Squared periodic distance between CV vectors a, b [..., n] (angles in
+    [-pi, pi]) in the FP32 arithmetic the clustering decides in: per CV the
+    FP32 difference wrapped to (-pi, pi] with FP32 constants, then the
+    squares summed in CV order, every product and sum rounded to FP32 (no
+    fused multiply-add)."""
+    a = np.asarray(a, dtype=np.float32)
+    b = np.asarray(b, dtype=np.float32)
+    pi = np.float32(math.pi)
+    two_pi = np.float32(2.0 * math.pi)
+    acc = np.zeros(np.broadcast(a[..., 0], b[..., 0]).shape, dtype=np.float32)
+    for i in range(a.shape[-1]):
+        d = (a[..., i] - b[..., i]).astype(np.float32)
+        d = np.where(d > pi, (d - two_pi).astype(np.float32), d)
+        d = np.where(d <= -pi, (d + two_pi).astype(np.float32), d)
+        acc = (acc + (d * d).astype(np.float32)).astype(np.float32)
+    return acc
+
+
+def leader_cluster(s, threshold, keep=None, max_clusters=None):
+    """Threshold clustering of CV frames.  Reading (the paper names a cluster
+    threshold and a window for the cluster count, not the algorithm): frames
+    are taken in order; a kept frame joins the first cluster, in founding
+    order, whose leader lies within the threshold (squared FP32 periodic
+    distance <= threshold^2 in FP32), otherwise it founds a cluster and is
+    its leader (the cluster's representative).  Frames not kept get label
+    -2.  With max_clusters, a frame that would found cluster number
+    max_clusters gets label -1 and the count is reported as
+    max_clusters + 1 ("more than the cap").
+    Returns (labels [B] int64, leaders [frame indices], n_clusters)."""
+    s = np.asarray(s, dtype=np.float32)
+    B = s.shape[0]
+    t = np.float32(threshold)
+    t2 = np.float32(t * t)
+    labels = np.full(B, -2, dtype=np.int64)
+    leaders = []
+    over = False
+    for f in range(B):
+        if keep is not None and not keep[f]:
+            continue
+        if leaders:
+            hit = np.nonzero(cv_distance_sq_f32(s[leaders], s[f][None, :]) <= t2)[0]
+            if hit.size:
+                labels[f] = hit[0]
+                continue
+        if max_clusters is not None and len(leaders) >= max_clusters:
+            labels[f] = -1
+            over = True
+            continue
+        labels[f] = len(leaders)
+        leaders.append(f)
+    return labels, leaders, len(leaders) + (1 if over else 0)
+
+
+THRESHOLD_FACTOR = np.float32(1.1)
+
+
+def adapt_threshold(s, threshold, lower, upper, keep=None, max_clusters=None, max_iter=100):
+    """Reading of the threshold adjustment (first iteration only; the rule is
+    not printed): while the cluster count is above `upper` the threshold is
+    multiplied by 1.1, while below `lower` divided by 1.1 (FP32), at most
+    max_iter adjustments.  Returns (threshold, leader_cluster result)."""
+    t = np.float32(threshold)
+    for it in range(max_iter + 1):
+        res = leader_cluster(s, t, keep, max_clusters)
+        n = res[2]
+        if lower <= n <= upper or it == max_iter:
+            return t, res
+        t = np.float32(t * THRESHOLD_FACTOR) if n > upper else np.float32(t / THRESHOLD_FACTOR)
+    return t, res
+
+
+def select_frames(models, s, eps0, threshold, lower, upper, max_selection, adapt=True,
+                  max_iter=100):
+    """Selection: the frames whose model deviation reaches the lower trust
+    level (eps >= eps0, reading: "high model deviation" relative to the
+    trust level) are clustered, the threshold adapted into [lower, upper]
+    when `adapt`, and the leaders of the first max_selection clusters are
+    the selected frames.  Returns dict(eps, keep, threshold, labels,
+    leaders, n_clusters, selected)."""
+    eps = frame_deviation(models, s)
+    keep = eps >= eps0
+    cap = max(upper, max_selection) + 1
+    if adapt:
+        t, (labels, leaders, n) = adapt_threshold(s, threshold, lower, upper, keep, cap, max_iter)
+    else:
+        t = np.float32(threshold)
+        labels, leaders, n = leader_cluster(s, t, keep, cap)
+    return dict(eps=eps, keep=keep, threshold=t, labels=labels, leaders=leaders,
+                n_clusters=n, selected=list(leaders[:max_selection]))

@@ -319,3 +319,26 @@ def poisson_trace(n_req: int, rate_hz: float, n_classes: int, seed: int = 5,
     w = np.floor(np.exp(rng.uniform(0.0, math.log(max_walkers + 1), size=n_req)))
     w = np.clip(w, 1, max_walkers).astype(int)
     return [Request(float(t[i]), int(cls[i]), int(w[i])) for i in range(n_req)]
+
+
+def exploration_frames(walkers: int, frames: int, n: int, n_basins: int, spread: float,
+                       seed: int) -> np.ndarray:
+    """CV frames [walkers * frames][n] (float32, angles in [-pi, pi)) shaped
+    like an exploration phase's output: each walker starts in a random basin
+    (centre uniform on the torus) and records a random walk around it that
+    hops to another basin with probability 0.01 per frame; frames are listed
+    walker by walker, in time order."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(-math.pi, math.pi, size=(n_basins, n))
+    out = np.empty((walkers * frames, n))
+    for w in range(walkers):
+        c = rng.integers(n_basins)
+        x = centres[c] + rng.normal(0.0, spread, size=n)
+        for t in range(frames):
+            if rng.uniform() < 0.01:
+                c = rng.integers(n_basins)
+                x = centres[c] + rng.normal(0.0, spread, size=n)
+            x = 0.7 * x + 0.3 * centres[c] + rng.normal(0.0, 0.5 * spread, size=n)
+            out[w * frames + t] = x
+    out = out - 2.0 * math.pi * np.floor((out + math.pi) / (2.0 * math.pi))
+    return out.astype(np.float32)
