@@ -139,6 +139,53 @@ rid_status rid_model_dev(rid_ensemble ens, const float* d_s, int B,
                          rid_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Selection phase ("Selection"; "SelectorConfig": cluster_threshold,
+ * numb_cluster_lower / numb_cluster_upper, max_selection).  The paper has
+ * the exploration's CV frames clustered, the frames of high model deviation
+ * kept by the trust level, the threshold adjusted in the first iteration
+ * until the cluster count falls in [lower, upper], and at most max_selection
+ * clusters sent on, one representative each.
+ *
+ * rid_cluster_frames - threshold clustering of CV frames.  Frames are taken
+ * in order; a frame joins the first cluster (in founding order) whose
+ * leader lies within `threshold`, otherwise it founds a cluster and is its
+ * leader (the representative).  Distance: sqrt(sum_i wrap(a_i - b_i)^2),
+ * differences wrapped to (-pi, pi], decided as d^2 <= threshold^2 in FP32
+ * with the squares summed in CV order (no fused multiply-add), so the
+ * labels are reproducible bit for bit.
+ *   d_s        [B][n_cv] device  frames, angles in [-pi, pi]
+ *   d_eps      [B] device or NULL  frames with eps < eps0 are left out
+ *   adapt      nonzero: while the count is above `upper` the threshold is
+ *              multiplied by 1.1, while below `lower` divided by 1.1 (FP32),
+ *              at most 100 times; *threshold_used (nullable) gets the last
+ *   max_clusters  cap: a frame that would found one more cluster gets label
+ *              -1 and *n_clusters reports max_clusters + 1
+ *   d_labels   [B] device  OUT: cluster index, -1 (over the cap), -2 (left out)
+ *   d_leaders  [max_clusters] device  OUT: frame index of each leader
+ *   n_clusters host  OUT: clusters founded (+1 when the cap was hit)
+ * Synchronises the stream; allocates and frees its scratch per call.
+ * Errors: RID_EINVAL (NULL pointer, B < 1, n_cv outside [1, 256], threshold
+ * not positive and finite, max_clusters < 1, adapt with lower < 1 or
+ * upper < lower).
+ *
+ * rid_select - the selection phase: eps of every frame (as rid_model_dev)
+ * into d_eps [B]; the frames with eps >= eps0 clustered as above with the
+ * cap max(upper, max_selection) + 1 and the threshold adapted when adapt is
+ * nonzero (the workflow's first iteration); the leaders of the first
+ * max_selection clusters in d_selected [max_selection] (frame indices,
+ * *n_selected of them).  d_labels, n_clusters, threshold_used as above.
+ * Synchronises the stream.  Errors: as above, and max_selection < 1.
+ * ------------------------------------------------------------------------ */
+rid_status rid_cluster_frames(const float* d_s, int B, int n_cv, const float* d_eps,
+                              float eps0, float threshold, int adapt, int lower, int upper,
+                              int max_clusters, int* d_labels, int* d_leaders,
+                              int* n_clusters, float* threshold_used, rid_stream stream);
+rid_status rid_select(rid_ensemble ens, const float* d_s, int B, float eps0, float threshold,
+                      int adapt, int lower, int upper, int max_selection, float* d_eps,
+                      int* d_labels, int* d_selected, int* n_selected, int* n_clusters,
+                      float* threshold_used, rid_stream stream);
+
+/* ------------------------------------------------------------------------
  * rid_bias_force - the per-MD-step neural bias of B walkers.
  * The bias is the inverted predicted PMF, applied only where the ensemble
  * agrees ("Development of the protocol"); trust_lvl_1/trust_lvl_2 bound the

@@ -29,8 +29,8 @@ EXPORTS = (
     "rid_last_error", "rid_version", "rid_system_create", "rid_system_destroy",
     "rid_packed_param_count", "rid_ensemble_create", "rid_ensemble_get_params",
     "rid_ensemble_set_params", "rid_ensemble_step", "rid_ensemble_destroy",
-    "rid_cv_eval", "rid_model_dev", "rid_bias_force", "rid_bias_force_conservative",
-    "rid_mcmc_run",
+    "rid_cv_eval", "rid_model_dev", "rid_cluster_frames", "rid_select", "rid_bias_force",
+    "rid_bias_force_conservative", "rid_mcmc_run",
     "rid_cv_apply_force",
     "rid_mf_train_step", "rid_lr_exponential", "rid_mf_label",
     "rid_profile_enable", "rid_profile_read", "rid_mf_loss_grad", "rid_mf_grad",
@@ -84,6 +84,8 @@ def lib():
         "rid_ensemble_destroy": (None, [vp]),
         "rid_cv_eval": (i, [vp, vp, i, vp, vp, vp]),
         "rid_model_dev": (i, [vp, vp, i, vp, vp, vp, vp, vp]),
+        "rid_cluster_frames": (i, [vp, i, i, vp, f, f, i, i, i, i, vp, vp, P(i), P(f), vp]),
+        "rid_select": (i, [vp, vp, i, f, f, i, i, i, i, vp, vp, vp, P(i), P(i), P(f), vp]),
         "rid_bias_force": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
         "rid_bias_force_conservative": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
         "rid_mcmc_run": (i, [vp, vp, i, i64, i64, ctypes.c_double, f, ctypes.c_uint64, i, i, i,
@@ -241,6 +243,48 @@ def model_dev(ens: Ensemble, s, stream=None, want_g=True):
     _check(lib().rid_model_dev(ens.handle, _ptr(s), B, _ptr(eps), _ptr(gbar), _ptr(A),
                                _ptr(g), _stream(stream)))
     return eps, gbar, A, g
+
+
+def cluster_frames(s, threshold: float, eps=None, eps0: float = 0.0, max_clusters: int = 4096,
+                   adapt: bool = False, lower: int = 1, upper: int = 1, stream=None):
+    """rid_cluster_frames: s [B][n] (cuda float32) -> dict(labels [B] int32,
+    leaders [n] int32 frame indices, n_clusters, threshold)."""
+    torch = _torch()
+    B, n = s.shape
+    _f32(s, (B, n), "s")
+    if eps is not None:
+        _f32(eps, (B,), "eps")
+    labels = torch.empty(B, dtype=torch.int32, device=s.device)
+    leaders = torch.empty(max_clusters, dtype=torch.int32, device=s.device)
+    nc = ctypes.c_int()
+    tu = ctypes.c_float()
+    _check(lib().rid_cluster_frames(_ptr(s), B, n, _ptr(eps), float(eps0), float(threshold),
+                                    int(bool(adapt)), int(lower), int(upper), int(max_clusters),
+                                    _ptr(labels), _ptr(leaders), ctypes.byref(nc),
+                                    ctypes.byref(tu), _stream(stream)))
+    nl = min(nc.value, max_clusters)
+    return dict(labels=labels, leaders=leaders[:nl], n_clusters=nc.value, threshold=tu.value)
+
+
+def select(ens: Ensemble, s, eps0: float, threshold: float, lower: int, upper: int,
+           max_selection: int, adapt: bool = True, stream=None):
+    """rid_select: the selection phase on CV frames s [B][n] -> dict(eps [B],
+    labels [B], selected [<= max_selection] frame indices, n_clusters,
+    threshold)."""
+    torch = _torch()
+    B = s.shape[0]
+    _f32(s, (B, ens.n_cv), "s")
+    eps = torch.empty(B, dtype=torch.float32, device=s.device)
+    labels = torch.empty(B, dtype=torch.int32, device=s.device)
+    sel = torch.empty(max_selection, dtype=torch.int32, device=s.device)
+    ns, nc = ctypes.c_int(), ctypes.c_int()
+    tu = ctypes.c_float()
+    _check(lib().rid_select(ens.handle, _ptr(s), B, float(eps0), float(threshold),
+                            int(bool(adapt)), int(lower), int(upper), int(max_selection),
+                            _ptr(eps), _ptr(labels), _ptr(sel), ctypes.byref(ns),
+                            ctypes.byref(nc), ctypes.byref(tu), _stream(stream)))
+    return dict(eps=eps, labels=labels, selected=sel[:ns.value], n_clusters=nc.value,
+                threshold=tu.value)
 
 
 def bias_force(system: System, ens: Ensemble, pos, eps0: float, eps1: float,

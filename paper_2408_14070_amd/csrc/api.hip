@@ -361,6 +361,41 @@ rid_status rid_model_dev(rid_ensemble ens, const float* d_s, int B, float* d_eps
                                 d_eps, d_gbar, d_A, d_g, st);
 }
 
+rid_status rid_cluster_frames(const float* d_s, int B, int n_cv, const float* d_eps,
+                              float eps0, float threshold, int adapt, int lower, int upper,
+                              int max_clusters, int* d_labels, int* d_leaders,
+                              int* n_clusters, float* threshold_used, rid_stream stream) {
+  if (!d_s || !d_labels || !d_leaders || !n_clusters) return fail(RID_EINVAL, "NULL argument");
+  if (B < 1) return fail(RID_EINVAL, "B must be >= 1");
+  if (n_cv < 1 || n_cv > 256) return fail(RID_EINVAL, "n_cv must be in [1, 256]");
+  if (!(threshold > 0.f) || !std::isfinite(threshold))
+    return fail(RID_EINVAL, "threshold must be positive and finite");
+  if (max_clusters < 1) return fail(RID_EINVAL, "max_clusters must be >= 1");
+  if (adapt && (lower < 1 || upper < lower)) return fail(RID_EINVAL, "need 1 <= lower <= upper");
+  return launch_cluster(d_s, B, n_cv, d_eps, eps0, threshold, lower, upper, adapt, max_clusters,
+                        d_labels, d_leaders, max_clusters, nullptr, n_clusters, threshold_used,
+                        (hipStream_t)stream);
+}
+
+rid_status rid_select(rid_ensemble ens, const float* d_s, int B, float eps0, float threshold,
+                      int adapt, int lower, int upper, int max_selection, float* d_eps,
+                      int* d_labels, int* d_selected, int* n_selected, int* n_clusters,
+                      float* threshold_used, rid_stream stream) {
+  if (!ens || !d_s || !d_eps || !d_labels || !d_selected || !n_selected || !n_clusters)
+    return fail(RID_EINVAL, "NULL argument");
+  if (B < 1) return fail(RID_EINVAL, "B must be >= 1");
+  if (!(threshold > 0.f) || !std::isfinite(threshold))
+    return fail(RID_EINVAL, "threshold must be positive and finite");
+  if (lower < 1 || upper < lower) return fail(RID_EINVAL, "need 1 <= lower <= upper");
+  if (max_selection < 1) return fail(RID_EINVAL, "max_selection must be >= 1");
+  rid_status r = rid_model_dev(ens, d_s, B, d_eps, nullptr, nullptr, nullptr, stream);
+  if (r != RID_OK) return r;
+  const int cap = std::max(upper, max_selection) + 1;
+  return launch_cluster(d_s, B, ens->impl.n_cv, d_eps, eps0, threshold, lower, upper, adapt, cap,
+                        d_labels, d_selected, max_selection, n_selected, n_clusters,
+                        threshold_used, (hipStream_t)stream);
+}
+
 // Batches up to this many walkers gather torsion atoms inside the MLP kernel
 // (one launch less); larger ones encode the CVs once into HBM first, so the
 // K members' workgroups read a compact [B][2n] encoding instead of each

@@ -1,0 +1,304 @@
+// Selection phase ("Selection"; "SelectorConfig": cluster_threshold,
+// numb_cluster_lower / numb_cluster_upper, max_selection): the CV frames
+// whose model deviation reaches the lower trust level are clustered with a
+// distance threshold, the threshold is adapted until the cluster count lies
+// in the window, and one representative per cluster is selected.
+//
+// Clustering (the paper names a threshold, not the algorithm): frames in
+// order; a frame joins the first cluster, in founding order, whose leader is
+// within the threshold, otherwise it founds a cluster and leads it.  The
+// distance is periodic in every CV (differences wrapped to (-pi, pi]) and the
+// decision d^2 <= t^2 is taken in FP32 with the squares summed in CV order,
+// contraction off, so the labels do not depend on the launch shape.
+//
+// GPU form of the sequential rule, exact: frames go in chunks.  A parallel
+// kernel compares every frame of the chunk with all leaders founded before
+// it (one wave per frame, lanes over leaders, first hit by ballot); one wave
+// then walks the chunk's unmatched frames in order against the leaders
+// founded inside the chunk (kept in LDS) and founds new ones.  A frame's
+// first match among the earlier leaders is its first match overall, because
+// later leaders only append.  Chunks grow from 64 frames, so the first
+// leaders are found by the single wave over few frames and most frames are
+// then resolved by the parallel kernel.
+#include "device_common.h"
+
+namespace rid {
+namespace {
+
+using namespace dev;
+
+constexpr int kPending = -3;       // unmatched after the parallel pass
+constexpr int kFiltered = -2;      // eps below eps0
+constexpr int kOverCap = -1;       // would found a cluster past the cap
+constexpr int kMatchWaves = 4;
+constexpr int kMaxSelCv = 256;
+constexpr int kChunkMax = 8192;
+constexpr int kLdsRows = 16384;    // floats for the new leaders, and again for a frame group
+
+struct ClusterArgs {
+  const float* s;        // [B][n] frames
+  const float* eps;      // [B] or null (no filter)
+  float eps0, t2;
+  int B, n, cap, chunk;
+  float* LT;             // [n][cap] leaders' CVs, CV-major
+  int* leader;           // [cap] frame index of each leader
+  int* state;            // [0] leaders so far, [1] next frame, [2] over the cap
+  int* labels;           // [B]
+  unsigned long long* pend;   // [ceil(B/64)] bit f%64 of word f/64: frame f unmatched
+};
+
+// Squared periodic distance leader - frame, the leader's CV i at lead[i * ls],
+// the frame's at x[i]; FP32, CV order, no fused multiply-add.
+__device__ inline float leader_d2(const float* lead, long long ls, const float* x, int n) {
+#pragma clang fp contract(off)
+  constexpr float kPi = 3.14159265358979f;
+  constexpr float kTwoPi = 6.28318530717959f;
+  float acc = 0.f;
+  for (int i = 0; i < n; ++i) {
+    float d = lead[i * ls] - x[i];
+    if (d > kPi) d = d - kTwoPi;
+    if (d <= -kPi) d = d + kTwoPi;
+    acc = acc + d * d;
+  }
+  return acc;
+}
+
+__global__ void sel_init_kernel(int* state, unsigned long long* pend, int words) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < 3) state[t] = 0;
+  for (int w = t; w < words; w += gridDim.x * blockDim.x) pend[w] = 0ull;
+}
+
+// Frames [f_next, f_next + chunk): filtered, matched to the first earlier
+// leader within the threshold, or marked unmatched in the bit mask.
+__global__ __launch_bounds__(kMatchWaves * kWave) void sel_match_kernel(ClusterArgs a) {
+  __shared__ float xs[kMatchWaves][kMaxSelCv];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int f0 = a.state[1];
+  const int f = f0 + blockIdx.x * kMatchWaves + wave;
+  if (f >= min(a.B, f0 + a.chunk)) return;
+  if (a.eps && !(a.eps[f] >= a.eps0)) {
+    if (lane == 0) a.labels[f] = kFiltered;
+    return;
+  }
+  const int n = a.n;
+  for (int i = lane; i < n; i += kWave) xs[wave][i] = a.s[(size_t)f * n + i];
+  __builtin_amdgcn_wave_barrier();
+  const int nl = a.state[0];
+  int lab = kPending;
+  for (int j0 = 0; j0 < nl; j0 += kWave) {
+    const int j = j0 + lane;
+    const bool hit = j < nl && leader_d2(a.LT + j, a.cap, xs[wave], n) <= a.t2;
+    const unsigned long long m = __ballot(hit);
+    if (m) {
+      lab = j0 + __ffsll((long long)m) - 1;
+      break;
+    }
+  }
+  if (lane == 0) {
+    a.labels[f] = lab;
+    if (lab == kPending) atomicOr(&a.pend[f >> 6], 1ull << (f & 63));
+  }
+}
+
+// One wave walks the chunk's unmatched frames in order, against the leaders
+// founded in this chunk (LDS, nlmax at most), and founds new ones.  The
+// chunk's mask words come in one batch of loads, and the unmatched frames'
+// CVs in groups of up to gmax frames per batch.  If the LDS holds nlmax new
+// leaders when another is due, the walk stops at that frame and the next
+// chunk starts there.  The mask words read are cleared for the next round.
+__global__ __launch_bounds__(kWave) void sel_resolve_kernel(ClusterArgs a, int nlmax, int gmax) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int lane = threadIdx.x;
+  const int f0 = a.state[1];
+  if (f0 >= a.B) return;
+  const int n = a.n;
+  const int f_end = min(a.B, f0 + a.chunk);
+  const int n_start = a.state[0];
+  const int w0 = f0 >> 6, w1 = (f_end - 1) >> 6;     // mask words of the chunk
+  const int nw = w1 - w0 + 1;                         // <= kChunkMax / 64 + 1
+  unsigned long long* pm = reinterpret_cast<unsigned long long*>(smem);   // [nw]
+  int* grp = reinterpret_cast<int*>(pm + (kChunkMax / 64 + 2));          // [gmax]
+  float* NL = reinterpret_cast<float*>(grp + gmax);                     // [nlmax][n]
+  float* XB = NL + (size_t)nlmax * n;                                    // [gmax][n]
+  for (int w = lane; w < nw; w += kWave) {
+    unsigned long long m = a.pend[w0 + w];
+    const int lo = (w0 + w) << 6;
+    if (lo < f0) m &= ~0ull << (f0 - lo);                   // frames before the chunk
+    if (lo + 64 > f_end) m &= (f_end - lo >= 64) ? ~0ull : ((1ull << (f_end - lo)) - 1ull);
+    pm[w] = m;
+    a.pend[w0 + w] = 0ull;
+  }
+  __builtin_amdgcn_wave_barrier();
+  int n_new = 0, over = a.state[2], stop = f_end;
+  int w = 0;
+  unsigned long long cur = nw > 0 ? pm[0] : 0ull;
+  while (stop == f_end) {
+    // next group of unmatched frames, in order
+    int g = 0;
+    while (g < gmax) {
+      while (cur == 0ull && w + 1 < nw) cur = pm[++w];
+      if (cur == 0ull) break;
+      const int b = __ffsll((long long)cur) - 1;
+      cur &= cur - 1;
+      if (lane == 0) grp[g] = ((w0 + w) << 6) + b;
+      ++g;
+    }
+    if (g == 0) break;
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < g * n; e += kWave) {
+      const int q = e / n, i = e - q * n;
+      XB[e] = a.s[(size_t)grp[q] * n + i];
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int q = 0; q < g; ++q) {
+      const int fq = grp[q];
+      const float* xq = XB + (size_t)q * n;
+      int hitj = -1;
+      for (int j0 = 0; j0 < n_new && hitj < 0; j0 += kWave) {
+        const int j = j0 + lane;
+        const bool hit = j < n_new && leader_d2(NL + (size_t)j * n, 1, xq, n) <= a.t2;
+        const unsigned long long m = __ballot(hit);
+        if (m) hitj = j0 + __ffsll((long long)m) - 1;
+      }
+      int out;
+      if (hitj >= 0) {
+        out = n_start + hitj;
+      } else if (n_start + n_new >= a.cap) {
+        out = kOverCap;
+        over = 1;
+      } else if (n_new >= nlmax) {
+        stop = fq;
+        break;
+      } else {
+        out = n_start + n_new;
+        for (int i = lane; i < n; i += kWave) {
+          NL[(size_t)n_new * n + i] = xq[i];
+          a.LT[(size_t)i * a.cap + out] = xq[i];
+        }
+        if (lane == 0) a.leader[out] = fq;
+        ++n_new;
+      }
+      if (lane == 0) a.labels[fq] = out;
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  if (lane == 0) {
+    a.state[0] = n_start + n_new;
+    a.state[1] = stop;
+    a.state[2] = over;
+  }
+}
+
+size_t resolve_lds(int n, int nlmax, int gmax) {
+  return sizeof(unsigned long long) * (kChunkMax / 64 + 2) + sizeof(int) * (size_t)gmax +
+         sizeof(float) * ((size_t)nlmax + gmax) * n;
+}
+
+// Device memory of one clustering call.
+struct ClusterWs {
+  float* LT = nullptr;
+  int* leader = nullptr;
+  int* state = nullptr;
+  unsigned long long* pend = nullptr;
+  ~ClusterWs() {
+    if (LT) (void)hipFree(LT);
+    if (leader) (void)hipFree(leader);
+    if (state) (void)hipFree(state);
+    if (pend) (void)hipFree(pend);
+  }
+};
+
+// One clustering at threshold t; synchronises the stream.  On return
+// state_h = {leaders, next frame, over the cap}.
+rid_status cluster_once(ClusterArgs a, float t, int nlmax, int gmax, hipStream_t st,
+                        int state_h[3]) {
+  a.t2 = t * t;
+  const int words = (a.B + 63) / 64;
+  hipLaunchKernelGGL(sel_init_kernel, dim3(std::min((words + 255) / 256 + 1, 1024)), dim3(256), 0,
+                     st, a.state, a.pend, words);
+  RID_HIP(hipGetLastError());
+  const size_t lds = resolve_lds(a.n, nlmax, gmax);
+  static size_t attr = 0;
+  if (lds > 64 * 1024 && lds > attr) {
+    RID_HIP(hipFuncSetAttribute((const void*)sel_resolve_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = lds;
+  }
+  // rounds: chunks growing from 64 frames until they cover B, then one full
+  // chunk per possible LDS stop (each stop founds nlmax leaders) and one more
+  long long covered = 0;
+  int c = 64;
+  std::vector<int> chunks;
+  while (covered < a.B) {
+    chunks.push_back(c);
+    covered += c;
+    c = std::min(2 * c, kChunkMax);
+  }
+  const int stops = (a.cap + nlmax - 1) / nlmax;
+  for (int i = 0; i <= stops; ++i) chunks.push_back(kChunkMax);
+  for (int ch : chunks) {
+    a.chunk = ch;
+    hipLaunchKernelGGL(sel_match_kernel, dim3((ch + kMatchWaves - 1) / kMatchWaves),
+                       dim3(kMatchWaves * kWave), 0, st, a);
+    RID_HIP(hipGetLastError());
+    hipLaunchKernelGGL(sel_resolve_kernel, dim3(1), dim3(kWave), (uint32_t)lds, st, a, nlmax,
+                       gmax);
+    RID_HIP(hipGetLastError());
+  }
+  RID_HIP(hipMemcpyAsync(state_h, a.state, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+  RID_HIP(hipStreamSynchronize(st));
+  if (state_h[1] < a.B) return fail(RID_EDEVICE, "clustering did not reach the last frame");
+  return RID_OK;
+}
+
+}  // namespace
+
+rid_status launch_cluster(const float* s, int B, int n, const float* eps, float eps0,
+                          float threshold, int lower, int upper, int adapt, int cap,
+                          int* labels, int* leaders, int leaders_out, int* n_leaders,
+                          int* n_clusters, float* t_used, hipStream_t st) {
+  ClusterWs ws;
+  RID_HIP(hipMalloc(&ws.LT, sizeof(float) * (size_t)n * cap));
+  RID_HIP(hipMalloc(&ws.leader, sizeof(int) * (size_t)cap));
+  RID_HIP(hipMalloc(&ws.state, sizeof(int) * 4));
+  RID_HIP(hipMalloc(&ws.pend, sizeof(unsigned long long) * (size_t)((B + 63) / 64)));
+  ClusterArgs a{};
+  a.s = s;
+  a.eps = eps;
+  a.eps0 = eps0;
+  a.B = B;
+  a.n = n;
+  a.cap = cap;
+  a.LT = ws.LT;
+  a.leader = ws.leader;
+  a.state = ws.state;
+  a.labels = labels;
+  a.pend = ws.pend;
+  const int nlmax = kLdsRows / n;                       // >= 64 for n <= 256
+  const int gmax = std::min(256, kLdsRows / n);
+  // threshold adjustment (first iteration of the workflow): x1.1 while
+  // above the window, /1.1 while below, at most 100 adjustments
+  constexpr int kMaxAdjust = 100;
+  float t = threshold;
+  int state_h[3] = {0, 0, 0};
+  int count = 0;
+  for (int it = 0;; ++it) {
+    rid_status r = cluster_once(a, t, nlmax, gmax, st, state_h);
+    if (r != RID_OK) return r;
+    count = state_h[0] + (state_h[2] ? 1 : 0);
+    if (!adapt || (count >= lower && count <= upper) || it == kMaxAdjust) break;
+    t = count > upper ? t * 1.1f : t / 1.1f;
+  }
+  const int nl = std::min(state_h[0], leaders_out);
+  if (leaders && nl > 0)
+    RID_HIP(hipMemcpyAsync(leaders, ws.leader, sizeof(int) * (size_t)nl,
+                           hipMemcpyDeviceToDevice, st));
+  RID_HIP(hipStreamSynchronize(st));
+  if (n_leaders) *n_leaders = nl;
+  *n_clusters = count;
+  if (t_used) *t_used = t;
+  return RID_OK;
+}
+
+}  // namespace rid

@@ -1,0 +1,121 @@
+"""GPU parity of the selection phase (rid_cluster_frames, rid_select)
+against the oracle, through the C ABI.  Cluster labels, leaders, counts and
+adapted thresholds are integer / FP32-decided results: both sides decide
+d^2 <= t^2 in the same FP32 arithmetic, so they must agree exactly."""
+import numpy as np
+import pytest
+
+import ridgen
+from oracle import rid_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def rid():
+    import paper_2408_14070_amd as r
+    r.lib()
+    return r
+
+
+def _gpu_cluster(torch, rid, s, t, **kw):
+    eps = kw.pop("eps", None)
+    out = rid.cluster_frames(torch.from_numpy(s).cuda(), t,
+                             eps=None if eps is None else torch.from_numpy(eps).cuda(), **kw)
+    torch.cuda.synchronize()
+    return (out["labels"].cpu().numpy().astype(np.int64), out["leaders"].cpu().numpy().tolist(),
+            out["n_clusters"], out["threshold"])
+
+
+@pytest.mark.parametrize("t", [0.8, 1.5, 3.0])
+def test_cluster_matches_oracle_exactly(torch, rid, t):
+    # 3000 frames of 38 CVs from 20 walkers over 30 basins: spans the growing
+    # chunks (64, 128, ... frames) and a ragged last chunk
+    s = ridgen.exploration_frames(20, 150, 38, 30, 0.3, seed=11)
+    labels, leaders, n = O.leader_cluster(s, t)
+    gl, gld, gn, _ = _gpu_cluster(torch, rid, s, t)
+    print(f"t={t}: {n} clusters", flush=True)
+    assert gn == n and gld == leaders
+    assert np.array_equal(gl, labels)
+
+
+def test_cluster_filter_and_cap(torch, rid):
+    s = ridgen.exploration_frames(8, 100, 38, 20, 0.3, seed=12)
+    eps = np.random.default_rng(3).uniform(0.0, 1.0, size=len(s)).astype(np.float32)
+    keep = eps >= np.float32(0.4)
+    labels, leaders, n = O.leader_cluster(s, 1.0, keep)
+    gl, gld, gn, _ = _gpu_cluster(torch, rid, s, 1.0, eps=eps, eps0=0.4)
+    assert gn == n and gld == leaders and np.array_equal(gl, labels)
+    assert np.all(gl[~keep] == -2)
+    # cap: 10 clusters at most, the count says "more"
+    labels, leaders, n = O.leader_cluster(s, 0.5, keep, max_clusters=10)
+    gl, gld, gn, _ = _gpu_cluster(torch, rid, s, 0.5, eps=eps, eps0=0.4, max_clusters=10)
+    assert n == 11 and gn == 11 and gld == leaders and np.array_equal(gl, labels)
+    assert np.any(gl == -1)
+
+
+def test_cluster_many_leaders_restarts_chunks(torch, rid):
+    # 256 CVs leave room for 64 new leaders per chunk in LDS; uniform frames
+    # at a small threshold found hundreds, so the walk stops and restarts
+    s = ridgen.torus_samples(600, 256, 13).astype(np.float32)
+    labels, leaders, n = O.leader_cluster(s, 20.0)
+    assert n > 300
+    gl, gld, gn, _ = _gpu_cluster(torch, rid, s, 20.0)
+    assert gn == n and gld == leaders and np.array_equal(gl, labels)
+
+
+@pytest.mark.parametrize("t0", [0.05, 40.0])
+def test_threshold_adaptation_matches_oracle(torch, rid, t0):
+    s = ridgen.exploration_frames(40, 30, 6, 40, 0.05, seed=7)
+    t, (labels, leaders, n) = O.adapt_threshold(s, t0, 30, 45)
+    gl, gld, gn, gt = _gpu_cluster(torch, rid, s, t0, adapt=True, lower=30, upper=45)
+    assert np.float32(gt) == t and gn == n and gld == leaders and np.array_equal(gl, labels)
+    assert 30 <= gn <= 45
+
+
+def test_select_matches_oracle(torch, rid):
+    n, widths, K = 38, [64, 64], 4
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 21, bias_std=0.1)
+    models = ridgen.unpack_params(params, 2 * n, widths, K)
+    s = ridgen.exploration_frames(16, 125, n, 30, 0.3, seed=14)
+    eps_ref = O.frame_deviation(models, s.astype(np.float64))
+    # eps0 in the widest gap of the deviations around the median, so the FP32
+    # deviation cannot fall on the other side
+    e = np.sort(eps_ref)
+    mid = len(e) // 2
+    lo, hi = mid - 200, mid + 200
+    k = lo + int(np.argmax(np.diff(e[lo:hi])))
+    eps0 = 0.5 * (e[k] + e[k + 1])
+    gap = e[k + 1] - e[k]
+    assert gap > 1e-4 * e[k]
+    ref = O.select_frames(models, s, eps0, 0.5, 30, 45, 50, adapt=True)
+    E = rid.Ensemble(n, widths, K, params)
+    out = rid.select(E, torch.from_numpy(s).cuda(), eps0, 0.5, 30, 45, 50, adapt=True)
+    torch.cuda.synchronize()
+    eps = out["eps"].cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(eps - eps_ref) / eps_ref) < 1e-4
+    assert np.min(np.abs(eps - eps0)) > 0.25 * gap
+    print(f"selected {len(ref['selected'])} of {ref['n_clusters']} clusters, "
+          f"threshold {ref['threshold']}", flush=True)
+    assert np.float32(out["threshold"]) == ref["threshold"]
+    assert out["n_clusters"] == ref["n_clusters"]
+    assert out["selected"].cpu().numpy().tolist() == ref["selected"]
+    assert np.array_equal(out["labels"].cpu().numpy().astype(np.int64), ref["labels"])
+
+
+def test_cluster_rejects_bad_arguments(torch, rid):
+    s = torch.zeros((10, 300), dtype=torch.float32, device="cuda")
+    with pytest.raises(rid.RidError):
+        rid.cluster_frames(s, 1.0)
+    s = torch.zeros((10, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(rid.RidError):
+        rid.cluster_frames(s, 0.0)
+    with pytest.raises(rid.RidError):
+        rid.cluster_frames(s, 1.0, adapt=True, lower=5, upper=4)
