@@ -396,6 +396,44 @@ def bench_mcmc(rid, torch, steps=400, warmup=20):
             "seconds_for_1e6_steps": 1e6 * dt}
 
 
+def bench_selection(rid, torch):
+    """Selection phase with the paper's SelectorConfig (cluster_threshold 2.6,
+    window [30, 45], max_selection 50) on 20 walkers x 1000 exploration frames
+    of the headline chain's 38 CVs, eps from the headline ensemble; eps0 at
+    the median deviation (the random-initialised ensemble has no trained
+    scale for the trust level)."""
+    n, widths, K = 38, [256] * 4, 4
+    E = rid.Ensemble(n, widths, K, ridgen.xavier_ensemble(2 * n, widths, K, 1000))
+    s = torch.from_numpy(ridgen.exploration_frames(20, 1000, n, 60, 0.3, seed=15)).cuda()
+    B = s.shape[0]
+    eps, _, _, _ = rid.model_dev(E, s, want_g=False)
+    eps0 = float(torch.quantile(eps, 0.5))
+    rid.select(E, s, eps0, 2.6, 30, 45, 50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = rid.select(E, s, eps0, 2.6, 30, 45, 50)
+    t_sel = time.perf_counter() - t0
+    # one clustering pass at the adapted threshold, and the deviation alone
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        c = rid.cluster_frames(s, out["threshold"], eps=eps, eps0=eps0, max_clusters=51)
+    t_clu = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rid.model_dev(E, s, want_g=False)
+    torch.cuda.synchronize()
+    t_dev = (time.perf_counter() - t0) / reps
+    return {"workload": "selection: 20 walkers x 1000 exploration frames of 38 torsion CVs, "
+                        "eps from the ensemble 4 x [256 x 4] FP32, eps0 at the median, "
+                        "threshold 2.6 adapted into [30, 45], max_selection 50",
+            "value": B / t_sel, "unit": "frames/s", "ms_per_call": 1e3 * t_sel,
+            "threshold_used": out["threshold"], "clusters": out["n_clusters"],
+            "selected": int(out["selected"].numel()),
+            "ms_per_clustering_pass": 1e3 * t_clu, "ms_model_dev": 1e3 * t_dev,
+            "clusters_at_that_threshold": c["n_clusters"]}
+
+
 def bench_labels(rid, torch, reps=20):
     M, T, n = 1024, 500, 38
     traj, s0, _ = ridgen.restrained_traj(M, T, n, 500.0, seed=9)
@@ -594,6 +632,8 @@ def main():
         rec["training"] = bench_training(rid, torch)
         log("labels")
         rec["labels"] = bench_labels(rid, torch)
+        log("selection")
+        rec["selection"] = bench_selection(rid, torch)
         if not args.no_serve:
             log("serving")
             rec["serving"] = bench_serving(rid)

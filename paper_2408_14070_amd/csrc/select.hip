@@ -13,9 +13,10 @@
 //
 // GPU form of the sequential rule, exact: frames go in chunks.  A parallel
 // kernel compares every frame of the chunk with all leaders founded before
-// it (one wave per frame, lanes over leaders, first hit by ballot); one wave
-// then walks the chunk's unmatched frames in order against the leaders
-// founded inside the chunk (kept in LDS) and founds new ones.  A frame's
+// it (one wave per frame, lanes over leaders, first hit by ballot); a
+// single workgroup then resolves the chunk's unmatched frames in order
+// against the leaders founded inside the chunk (kept in LDS) and founds new
+// ones.  A frame's
 // first match among the earlier leaders is its first match overall, because
 // later leaders only append.  Chunks grow from 64 frames, so the first
 // leaders are found by the single wave over few frames and most frames are
@@ -54,7 +55,8 @@ __device__ inline float leader_d2(const float* lead, long long ls, const float* 
   constexpr float kPi = 3.14159265358979f;
   constexpr float kTwoPi = 6.28318530717959f;
   float acc = 0.f;
-  for (int i = 0; i < n; ++i) {
+#pragma unroll 8
+  for (int i = 0; i < n; ++i) {   // unrolled: loads issue ahead, sum order unchanged
     float d = lead[i * ls] - x[i];
     if (d > kPi) d = d - kTwoPi;
     if (d <= -kPi) d = d + kTwoPi;
@@ -70,7 +72,8 @@ __global__ void sel_init_kernel(int* state, unsigned long long* pend, int words)
 }
 
 // Frames [f_next, f_next + chunk): filtered, matched to the first earlier
-// leader within the threshold, or marked unmatched in the bit mask.
+// leader within the threshold, over the cap (no match and no room for a new
+// cluster), or marked unmatched in the bit mask.
 __global__ __launch_bounds__(kMatchWaves * kWave) void sel_match_kernel(ClusterArgs a) {
   __shared__ float xs[kMatchWaves][kMaxSelCv];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -96,20 +99,31 @@ __global__ __launch_bounds__(kMatchWaves * kWave) void sel_match_kernel(ClusterA
     }
   }
   if (lane == 0) {
+    if (lab == kPending && nl >= a.cap) {   // the cap is full: nothing left to found
+      lab = kOverCap;
+      a.state[2] = 1;
+    }
     a.labels[f] = lab;
     if (lab == kPending) atomicOr(&a.pend[f >> 6], 1ull << (f & 63));
   }
 }
 
-// One wave walks the chunk's unmatched frames in order, against the leaders
-// founded in this chunk (LDS, nlmax at most), and founds new ones.  The
-// chunk's mask words come in one batch of loads, and the unmatched frames'
-// CVs in groups of up to gmax frames per batch.  If the LDS holds nlmax new
-// leaders when another is due, the walk stops at that frame and the next
-// chunk starts there.  The mask words read are cleared for the next round.
-__global__ __launch_bounds__(kWave) void sel_resolve_kernel(ClusterArgs a, int nlmax, int gmax) {
+// The chunk's unmatched frames, in order, against the leaders founded in
+// this chunk (LDS, nlmax at most); new leaders are founded here.  The chunk's
+// mask words come in one batch of loads, the unmatched frames' CVs in groups
+// of up to gmax frames.  Per group, the four waves first match every frame
+// against the chunk's leaders founded before the group (its first match
+// overall if any, since later leaders only append); wave 0 then walks the
+// group in order, comparing the rest with the leaders founded inside the
+// group and founding new ones.  If the LDS holds nlmax new leaders when
+// another is due, the walk stops at that frame and the next chunk starts
+// there.  The mask words read are cleared for the next round.
+constexpr int kResolveWaves = 4;
+__global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(ClusterArgs a,
+                                                                            int nlmax, int gmax) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int lane = threadIdx.x;
+  __shared__ int sh[3];             // new leaders so far, stop frame, over the cap
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   const int f0 = a.state[1];
   if (f0 >= a.B) return;
   const int n = a.n;
@@ -119,9 +133,10 @@ __global__ __launch_bounds__(kWave) void sel_resolve_kernel(ClusterArgs a, int n
   const int nw = w1 - w0 + 1;                         // <= kChunkMax / 64 + 1
   unsigned long long* pm = reinterpret_cast<unsigned long long*>(smem);   // [nw]
   int* grp = reinterpret_cast<int*>(pm + (kChunkMax / 64 + 2));          // [gmax]
-  float* NL = reinterpret_cast<float*>(grp + gmax);                     // [nlmax][n]
+  int* gm = grp + gmax;                                                  // [gmax]
+  float* NL = reinterpret_cast<float*>(gm + gmax);                      // [nlmax][n]
   float* XB = NL + (size_t)nlmax * n;                                    // [gmax][n]
-  for (int w = lane; w < nw; w += kWave) {
+  for (int w = tid; w < nw; w += kResolveWaves * kWave) {
     unsigned long long m = a.pend[w0 + w];
     const int lo = (w0 + w) << 6;
     if (lo < f0) m &= ~0ull << (f0 - lo);                   // frames before the chunk
@@ -129,69 +144,95 @@ __global__ __launch_bounds__(kWave) void sel_resolve_kernel(ClusterArgs a, int n
     pm[w] = m;
     a.pend[w0 + w] = 0ull;
   }
-  __builtin_amdgcn_wave_barrier();
-  int n_new = 0, over = a.state[2], stop = f_end;
-  int w = 0;
-  unsigned long long cur = nw > 0 ? pm[0] : 0ull;
-  while (stop == f_end) {
-    // next group of unmatched frames, in order
+  if (tid == 0) {
+    sh[0] = 0;
+    sh[1] = f_end;
+    sh[2] = a.state[2];
+  }
+  __syncthreads();
+  // every thread walks the mask words identically
+  int wi = 0;
+  unsigned long long cur = pm[0];
+  for (;;) {
+    const int n_new0 = sh[0];
+    if (sh[1] != f_end) break;
     int g = 0;
     while (g < gmax) {
-      while (cur == 0ull && w + 1 < nw) cur = pm[++w];
+      while (cur == 0ull && wi + 1 < nw) cur = pm[++wi];
       if (cur == 0ull) break;
       const int b = __ffsll((long long)cur) - 1;
       cur &= cur - 1;
-      if (lane == 0) grp[g] = ((w0 + w) << 6) + b;
+      if (tid == 0) grp[g] = ((w0 + wi) << 6) + b;
       ++g;
     }
     if (g == 0) break;
-    __builtin_amdgcn_wave_barrier();
-    for (int e = lane; e < g * n; e += kWave) {
+    __syncthreads();
+    for (int e = tid; e < g * n; e += kResolveWaves * kWave) {
       const int q = e / n, i = e - q * n;
       XB[e] = a.s[(size_t)grp[q] * n + i];
     }
-    __builtin_amdgcn_wave_barrier();
-    for (int q = 0; q < g; ++q) {
-      const int fq = grp[q];
-      const float* xq = XB + (size_t)q * n;
+    __syncthreads();
+    for (int q = wave; q < g; q += kResolveWaves) {
       int hitj = -1;
-      for (int j0 = 0; j0 < n_new && hitj < 0; j0 += kWave) {
+      for (int j0 = 0; j0 < n_new0 && hitj < 0; j0 += kWave) {
         const int j = j0 + lane;
-        const bool hit = j < n_new && leader_d2(NL + (size_t)j * n, 1, xq, n) <= a.t2;
+        const bool hit = j < n_new0 && leader_d2(NL + (size_t)j * n, 1, XB + (size_t)q * n, n) <= a.t2;
         const unsigned long long m = __ballot(hit);
         if (m) hitj = j0 + __ffsll((long long)m) - 1;
       }
-      int out;
-      if (hitj >= 0) {
-        out = n_start + hitj;
-      } else if (n_start + n_new >= a.cap) {
-        out = kOverCap;
-        over = 1;
-      } else if (n_new >= nlmax) {
-        stop = fq;
-        break;
-      } else {
-        out = n_start + n_new;
-        for (int i = lane; i < n; i += kWave) {
-          NL[(size_t)n_new * n + i] = xq[i];
-          a.LT[(size_t)i * a.cap + out] = xq[i];
-        }
-        if (lane == 0) a.leader[out] = fq;
-        ++n_new;
-      }
-      if (lane == 0) a.labels[fq] = out;
-      __builtin_amdgcn_wave_barrier();
+      if (lane == 0) gm[q] = hitj;
     }
+    __syncthreads();
+    if (wave == 0) {
+      int n_new = n_new0, over = sh[2], stop = f_end;
+      for (int q = 0; q < g; ++q) {
+        const int fq = grp[q];
+        const float* xq = XB + (size_t)q * n;
+        int hitj = gm[q];
+        for (int j0 = n_new0; j0 < n_new && hitj < 0; j0 += kWave) {
+          const int j = j0 + lane;
+          const bool hit = j < n_new && leader_d2(NL + (size_t)j * n, 1, xq, n) <= a.t2;
+          const unsigned long long m = __ballot(hit);
+          if (m) hitj = j0 + __ffsll((long long)m) - 1;
+        }
+        int out;
+        if (hitj >= 0) {
+          out = n_start + hitj;
+        } else if (n_start + n_new >= a.cap) {
+          out = kOverCap;
+          over = 1;
+        } else if (n_new >= nlmax) {
+          stop = fq;
+          break;
+        } else {
+          out = n_start + n_new;
+          for (int i = lane; i < n; i += kWave) {
+            NL[(size_t)n_new * n + i] = xq[i];
+            a.LT[(size_t)i * a.cap + out] = xq[i];
+          }
+          if (lane == 0) a.leader[out] = fq;
+          ++n_new;
+        }
+        if (lane == 0) a.labels[fq] = out;
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (lane == 0) {
+        sh[0] = n_new;
+        sh[1] = stop;
+        sh[2] = over;
+      }
+    }
+    __syncthreads();
   }
-  if (lane == 0) {
-    a.state[0] = n_start + n_new;
-    a.state[1] = stop;
-    a.state[2] = over;
+  if (tid == 0) {
+    a.state[0] = n_start + sh[0];
+    a.state[1] = sh[1];
+    a.state[2] = sh[2];
   }
 }
 
 size_t resolve_lds(int n, int nlmax, int gmax) {
-  return sizeof(unsigned long long) * (kChunkMax / 64 + 2) + sizeof(int) * (size_t)gmax +
+  return sizeof(unsigned long long) * (kChunkMax / 64 + 2) + 2 * sizeof(int) * (size_t)gmax +
          sizeof(float) * ((size_t)nlmax + gmax) * n;
 }
 
@@ -242,8 +283,8 @@ rid_status cluster_once(ClusterArgs a, float t, int nlmax, int gmax, hipStream_t
     hipLaunchKernelGGL(sel_match_kernel, dim3((ch + kMatchWaves - 1) / kMatchWaves),
                        dim3(kMatchWaves * kWave), 0, st, a);
     RID_HIP(hipGetLastError());
-    hipLaunchKernelGGL(sel_resolve_kernel, dim3(1), dim3(kWave), (uint32_t)lds, st, a, nlmax,
-                       gmax);
+    hipLaunchKernelGGL(sel_resolve_kernel, dim3(1), dim3(kResolveWaves * kWave), (uint32_t)lds,
+                       st, a, nlmax, gmax);
     RID_HIP(hipGetLastError());
   }
   RID_HIP(hipMemcpyAsync(state_h, a.state, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
