@@ -1543,7 +1543,12 @@ rid_status dispatch(const rid_ensemble_impl& e, const float* x, int B, float* A_
     switch (e.NP) {
       case 64:  return run_mlp<F32, 64, 1, 1, 6>(e, x, B, A_out, g_out, t, st);
       case 128: return run_mlp<F32, 128, 1, 2, 6>(e, x, B, A_out, g_out, t, st);
-      case 256: return run_mlp<F32, 256, 1, RID_F32_NW256, 6>(e, x, B, A_out, g_out, t, st);
+      case 256:
+        // free energies only (MCMC): 32-walker tiles feed two MFMA tiles from
+        // each weight fragment, taken while they still keep 3/4 of the CUs busy
+        if (!g_out && !t && (long long)((B + 31) / 32) * e.K >= 192)
+          return run_mlp<F32, 256, 2, RID_F32_NW256, 6>(e, x, B, A_out, g_out, t, st);
+        return run_mlp<F32, 256, 1, RID_F32_NW256, 6>(e, x, B, A_out, g_out, t, st);
       case 512: return run_mlp<F32, 512, 1, 8, 6>(e, x, B, A_out, g_out, t, st);
     }
     return fail(RID_EUNSUPPORTED, "no kernel for this padded width");

@@ -59,12 +59,16 @@ def test_infinite_temperature_walk_matches_the_generator(torch, rid):
 
 # 300 K (the paper's temperature) accepts nearly every move of a random-init
 # ensemble; kT = 0.01 kJ/mol rejects about half of them
-@pytest.mark.parametrize("kT", [KT_300K, 0.01])
-def test_metropolis_decisions_step_by_step(torch, rid, kT):
+# The second case is the headline ensemble at 2048 walkers, where the free
+# energies come from 32-walker tiles (the energy-only kernel's large-batch form).
+@pytest.mark.parametrize("kT,widths,W,T", [(KT_300K, (128, 128), 256, 25),
+                                           (0.01, (128, 128), 256, 25),
+                                           (0.01, (256, 256, 256, 256), 2048, 8)])
+def test_metropolis_decisions_step_by_step(torch, rid, kT, widths, W, T):
     # one call per step; a walker may only leave the oracle's chain at a step
     # whose acceptance margin |ln u_n + dAbar/kT| is at rounding level
-    E, models = _ensemble(rid, widths=(128, 128), K=4)
-    W, T, step, seed, n = 256, 25, 0.35, 77, 38
+    E, models = _ensemble(rid, widths=widths, K=4)
+    step, seed, n = 0.35, 77, 38
     s0 = ridgen.f32(ridgen.torus_samples(W, n, 5))
     ref = O.mcmc_run(models, s0.astype(np.float64), T, kT, step, seed, nbins=31,
                      keep_path=True)
