@@ -65,8 +65,8 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} missing: run __graft_entry__.build() or "
-                          "python -m paper_2408_14070_amd.build first")
+        raise ImportError(f"{LIB_PATH} missing: build it first "
+                          "(python -m paper_2408_14070_amd.build)")
     L = ctypes.CDLL(LIB_PATH)
     vp, i, f, d, sz, i64 = (ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
                            ctypes.c_double, ctypes.c_size_t, ctypes.c_int64)
