@@ -114,15 +114,17 @@ __global__ __launch_bounds__(kMatchWaves * kWave) void sel_match_kernel(ClusterA
 // of up to gmax frames.  Per group, the four waves first match every frame
 // against the chunk's leaders founded before the group (its first match
 // overall if any, since later leaders only append); wave 0 then walks the
-// group in order, comparing the rest with the leaders founded inside the
-// group and founding new ones.  If the LDS holds nlmax new leaders when
+// group in order and founds a leader at the first frame still unmatched,
+// after which the rest of the group is matched in parallel against that
+// leader before the walk resumes, so every frame meets the leaders founded
+// before it in founding order.  If the LDS holds nlmax new leaders when
 // another is due, the walk stops at that frame and the next chunk starts
 // there.  The mask words read are cleared for the next round.
 constexpr int kResolveWaves = 4;
 __global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(ClusterArgs a,
                                                                             int nlmax, int gmax) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ int sh[3];             // new leaders so far, stop frame, over the cap
+  __shared__ int sh[4];             // new leaders so far, stop frame, over the cap, walk start
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   const int f0 = a.state[1];
   if (f0 >= a.B) return;
@@ -183,44 +185,54 @@ __global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(Clus
       if (lane == 0) gm[q] = hitj;
     }
     __syncthreads();
-    if (wave == 0) {
-      int n_new = n_new0, over = sh[2], stop = f_end;
-      for (int q = 0; q < g; ++q) {
-        const int fq = grp[q];
-        const float* xq = XB + (size_t)q * n;
-        int hitj = gm[q];
-        for (int j0 = n_new0; j0 < n_new && hitj < 0; j0 += kWave) {
-          const int j = j0 + lane;
-          const bool hit = j < n_new && leader_d2(NL + (size_t)j * n, 1, xq, n) <= a.t2;
-          const unsigned long long m = __ballot(hit);
-          if (m) hitj = j0 + __ffsll((long long)m) - 1;
-        }
-        int out;
-        if (hitj >= 0) {
-          out = n_start + hitj;
-        } else if (n_start + n_new >= a.cap) {
-          out = kOverCap;
-          over = 1;
-        } else if (n_new >= nlmax) {
-          stop = fq;
-          break;
-        } else {
-          out = n_start + n_new;
-          for (int i = lane; i < n; i += kWave) {
-            NL[(size_t)n_new * n + i] = xq[i];
-            a.LT[(size_t)i * a.cap + out] = xq[i];
+    // ordered walk: wave 0 labels matched frames and founds a leader at the
+    // first unmatched one; the rest of the group is then matched in parallel
+    // (a thread per frame) against that new leader before the walk goes on
+    int start = 0;
+    for (;;) {
+      if (wave == 0) {
+        int n_new = sh[0], over = sh[2], stop = f_end, next = g, founded = 0;
+        for (int q = start; q < g; ++q) {
+          const int fq = grp[q];
+          int out;
+          if (gm[q] >= 0) {
+            out = n_start + gm[q];
+          } else if (n_start + n_new >= a.cap) {
+            out = kOverCap;
+            over = 1;
+          } else if (n_new >= nlmax) {
+            stop = fq;
+            break;
+          } else {
+            out = n_start + n_new;
+            const float* xq = XB + (size_t)q * n;
+            for (int i = lane; i < n; i += kWave) {
+              NL[(size_t)n_new * n + i] = xq[i];
+              a.LT[(size_t)i * a.cap + out] = xq[i];
+            }
+            if (lane == 0) a.leader[out] = fq;
+            ++n_new;
+            founded = 1;
+            next = q + 1;
           }
-          if (lane == 0) a.leader[out] = fq;
-          ++n_new;
+          if (lane == 0) a.labels[fq] = out;
+          if (founded) break;
         }
-        if (lane == 0) a.labels[fq] = out;
-        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+          sh[0] = n_new;
+          sh[1] = stop;
+          sh[2] = over;
+          sh[3] = founded ? next : g;
+        }
       }
-      if (lane == 0) {
-        sh[0] = n_new;
-        sh[1] = stop;
-        sh[2] = over;
-      }
+      __syncthreads();
+      start = sh[3];
+      if (sh[1] != f_end || start >= g) break;
+      const int jn = sh[0] - 1;                  // the leader just founded
+      for (int q = start + tid; q < g; q += kResolveWaves * kWave)
+        if (gm[q] < 0 && leader_d2(NL + (size_t)jn * n, 1, XB + (size_t)q * n, n) <= a.t2)
+          gm[q] = jn;
+      __syncthreads();
     }
     __syncthreads();
   }
