@@ -34,6 +34,8 @@
 //    the members' results to one workgroup inside this launch needs
 //    device-scope fences, which on gfx950 write back and invalidate the
 //    whole per-XCD L2 and so evict the weights the other workgroups stream.
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace rid {
@@ -157,6 +159,7 @@ struct MlpArgs {
   float* g_out;        // [K][B][n]
   // LDS layout (byte offsets; activation buffer 0 starts at 0)
   unsigned off_u0, off_red, off_xs, off_ph0, off_wo;
+  int u0p;             // parts of the input-gradient contraction (u0_split or 1)
   int rc;              // walkers per torsion-gather pass (bias path)
   // torsion input (bias path)
   SysView sv;
@@ -694,15 +697,18 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   }
   // layer 1 backward: u0 = W_1^T v_1.  Its XP/16 column tiles are too few
   // to spread evenly over the waves, so each tile's contraction is cut into
-  // U0_SPLIT parts; the parts' partial sums go to LDS (u0 part q at
+  // p.u0p parts (U0_SPLIT, or 1 when that many partial tiles would not fit
+  // the LDS); the parts' partial sums go to LDS (u0 part q at
   // u0 + q * R * US) and are added in part order when u0 is read.
   // v_1 sits in buffer 1 (2L-1 buffer flips), so u0 may alias buffer 0.
-  {
+  // PARTS is U0_SPLIT (the common case, compile-time loops) or 1
+  auto u0_stage = [&](auto parts_c) {
+    constexpr int PARTS = decltype(parts_c)::value;
     const T* in = act + cur * BUF;
     const int JT0 = XP / 16;
-    constexpr int KQ = NK / U0_SPLIT;         // k-steps per part
-    for (int it = wave; it < JT0 * U0_SPLIT; it += NW) {
-      const int t = it / U0_SPLIT, q = it - t * U0_SPLIT;
+    constexpr int KQ = NK / PARTS;            // k-steps per part
+    for (int it = wave; it < JT0 * PARTS; it += NW) {
+      const int t = it / PARTS, q = it - t * PARTS;
       f4 a1[RT][1];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) a1[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
@@ -716,14 +722,13 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       for (int rt = 0; rt < RT; ++rt)
         *reinterpret_cast<f4*>(uq0 + (rt * 16 + wl) * US + t * 16 + uq) = a1[rt][0];
     }
-  }
-  __syncthreads();
-  auto u0_at = [&](int i, int c) {
-    float v = u0[i * US + c];
-#pragma unroll
-    for (int q = 1; q < U0_SPLIT; ++q) v += u0[q * R * US + i * US + c];
-    return v;
   };
+  const bool full = U0_SPLIT == 1 || p.u0p == U0_SPLIT;
+  if (full)
+    u0_stage(std::integral_constant<int, U0_SPLIT>{});
+  else
+    u0_stage(std::integral_constant<int, 1>{});
+  __syncthreads();
   // A = sum of the waves' partial dot products + b_o
   for (int i = threadIdx.x; i < R; i += NW * 64) {
     float a = p.bo[k];
@@ -731,16 +736,29 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
     if (row0 + i < p.B) p.A_out[(size_t)k * p.B + row0 + i] = a;
   }
   // chain to the angles: g_i = -sin s_i u0[i] + cos s_i u0[n+i]
-  for (int e = threadIdx.x; e < R * n; e += NW * 64) {
-    const int i = e / n, c = e - i * n;
-    const int row = row0 + i;
-    if (row < p.B) {
-      const float cs = xs[i * X2 + c];
-      const float sn = xs[i * X2 + n + c];
-      const float gv = -sn * u0_at(i, c) + cs * u0_at(i, n + c);
-      p.g_out[((size_t)k * p.B + row) * n + c] = gv;
+  auto chain = [&](auto parts_c) {
+    constexpr int PARTS = decltype(parts_c)::value;
+    auto u0_at = [&](int i, int c) {
+      float v = u0[i * US + c];
+#pragma unroll
+      for (int q = 1; q < PARTS; ++q) v += u0[q * R * US + i * US + c];
+      return v;
+    };
+    for (int e = threadIdx.x; e < R * n; e += NW * 64) {
+      const int i = e / n, c = e - i * n;
+      const int row = row0 + i;
+      if (row < p.B) {
+        const float cs = xs[i * X2 + c];
+        const float sn = xs[i * X2 + n + c];
+        const float gv = -sn * u0_at(i, c) + cs * u0_at(i, n + c);
+        p.g_out[((size_t)k * p.B + row) * n + c] = gv;
+      }
     }
-  }
+  };
+  if (full)
+    chain(std::integral_constant<int, U0_SPLIT>{});
+  else
+    chain(std::integral_constant<int, 1>{});
 }
 
 // ---------------------------------------------------------------------------
@@ -1457,9 +1475,16 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
   const int AW = NP > e.XP ? NP : e.XP;
   const int AS = AW + RID_ACT_PAD_BYTES / (int)sizeof(T);
   MlpArgs a{};
-  const size_t lds = mlp_layout(R, NW, AS, sizeof(T), e.XP, e.n_cv,
-                                from_pos ? tin->sys->n_uniq : 0, from_pos, NP,
-                                u0_split<P, NP>(), a);
+  a.u0p = u0_split<P, NP>();
+  size_t lds = mlp_layout(R, NW, AS, sizeof(T), e.XP, e.n_cv,
+                          from_pos ? tin->sys->n_uniq : 0, from_pos, NP, a.u0p, a);
+  if (lds > 160 * 1024 && a.u0p > 1) {
+    // wide inputs: one part, which fits the free activation buffer
+    a = MlpArgs{};
+    a.u0p = 1;
+    lds = mlp_layout(R, NW, AS, sizeof(T), e.XP, e.n_cv,
+                     from_pos ? tin->sys->n_uniq : 0, from_pos, NP, 1, a);
+  }
   if (lds > 160 * 1024)
     return fail(RID_EUNSUPPORTED, "shape too large for the MLP kernel's LDS");
   if (from_pos && a.rc < 1)
@@ -1502,17 +1527,22 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
   return RID_OK;
 }
 
-// 16-bit family: 64 walkers per workgroup when the tile fits LDS, else 32;
-// deeper networks (5-6 hidden layers) take 32.
+// 16-bit family: 64 walkers per workgroup when the tile fits LDS, else 32,
+// else 16 (the widest inputs); deeper networks (5-6 hidden layers) take 32
+// or 16.
 template <class P, int NP, int NW>
 rid_status run_16bit(const rid_ensemble_impl& e, const float* x, int B, float* A_out,
                      float* g_out, const TorsionInput* t, hipStream_t st) {
   if (e.L <= 4) {
     if (lds_bytes<P, NP, 4, NW, 4>(e, t) <= 160 * 1024)
       return run_mlp<P, NP, 4, NW, 4>(e, x, B, A_out, g_out, t, st);
-    return run_mlp<P, NP, 2, NW, 4>(e, x, B, A_out, g_out, t, st);
+    if (lds_bytes<P, NP, 2, NW, 4>(e, t) <= 160 * 1024)
+      return run_mlp<P, NP, 2, NW, 4>(e, x, B, A_out, g_out, t, st);
+    return run_mlp<P, NP, 1, NW, 6>(e, x, B, A_out, g_out, t, st);
   }
-  return run_mlp<P, NP, 2, NW, 6>(e, x, B, A_out, g_out, t, st);
+  if (lds_bytes<P, NP, 2, NW, 6>(e, t) <= 160 * 1024)
+    return run_mlp<P, NP, 2, NW, 6>(e, x, B, A_out, g_out, t, st);
+  return run_mlp<P, NP, 1, NW, 6>(e, x, B, A_out, g_out, t, st);
 }
 
 #ifndef RID_16_NW512

@@ -74,8 +74,8 @@ class ChainSystem:
 
 def chain_system(n_res: int, apr: int, n_extra: int = 0) -> ChainSystem:
     """Torsion table psi_1, (phi_2, psi_2), ..., phi_n for an n_res chain."""
-    if n_res < 2 or apr < 4:
-        raise ValueError("need n_res >= 2 and apr >= 4")
+    if n_res < 2 or apr < 5:   # N, CA = N + 2, C = N + apr - 2 must be distinct
+        raise ValueError("need n_res >= 2 and apr >= 5")
     N = lambda r: r * apr
     CA = lambda r: r * apr + 2
     C = lambda r: r * apr + apr - 2

@@ -364,3 +364,38 @@ def test_switch_decisions_on_basin_fitted_ensemble(torch, rid, basin_fixture, pr
           f"{away.mean():.4f} outside the guard band", flush=True)
     assert np.array_equal(reg[away], reg_ref[away])
     assert agree >= min_agree
+
+
+# The ABI's maxima: 256 CVs (a 129-residue chain; the FP32 kernel then sums
+# the input gradient in one part, the BF16 kernel takes 16-walker tiles),
+# 64 members, and six hidden layers of width 512, on tiny ragged batches.
+@pytest.mark.parametrize("case", ["cv256_k64", "w512_l6", "cv256_bf16_w512"])
+@pytest.mark.parametrize("B", [1, 7])
+def test_bias_force_maximum_sizes(torch, rid, case, B):
+    prec, tol = 0, FP32_TOL
+    if case == "cv256_k64":
+        sys_ = ridgen.chain_system(129, 5)
+        assert sys_.n_cv == 256
+        widths, K = [64, 64], 64
+    elif case == "w512_l6":
+        sys_ = ridgen.system_peptide20()
+        widths, K = [512] * 6, 2
+    else:
+        sys_ = ridgen.chain_system(129, 5)
+        widths, K, prec, tol = [512, 512], 4, rid.RID_BF16, HALF_TOL["bf16"]
+    pos = ridgen.f32(ridgen.chain_coords(sys_, B, 9))
+    params = ridgen.xavier_ensemble(2 * sys_.n_cv, widths, K, 1000, 0.1)
+    S, E = _make(rid, sys_, params, widths, K, prec)
+    models = ridgen.unpack_params(params, 2 * sys_.n_cv, widths, K)
+    ref1 = O.bias_force(pos.astype(np.float64), sys_.quads, models, 1e30, 2e30)
+    e0, e1 = 0.5 * float(ref1["eps"].min()), 2.0 * float(ref1["eps"].max())
+    ref = O.bias_force(pos.astype(np.float64), sys_.quads, models, e0, e1)
+    out = rid.bias_force(S, E, _dev(torch, pos), e0, e1)
+    torch.cuda.synchronize()
+    sig = out["sigma"].cpu().numpy().astype(np.float64)
+    assert np.all((ref["sigma"] > 0) & (ref["sigma"] < 1))
+    eps_tol = 1e-5 if prec == 0 else 5e-2
+    assert np.max(np.abs(out["eps"].cpu().numpy() - ref["eps"]) / ref["eps"]) <= eps_tol
+    # the force over sigma is the mean force chained to atoms
+    assert_forces(out["F"].cpu().numpy() / sig[:, None, None],
+                  ref["F"] / ref["sigma"][:, None, None], tol, f"{case} B={B}")
