@@ -50,11 +50,13 @@ def _per_member_err(grad_gpu, grad_ref):
 
 
 # FP32 ensembles of padded width <= 256 take the fused sweep kernel (six
-# hidden layers fill every register stash slot); the width-300 case takes
-# the sweeps as separate GEMMs.
+# hidden layers fill every register stash slot); the width-300 case and the
+# 256-CV case (its input tile does not fit the fused kernel's LDS) take the
+# sweeps as separate GEMMs.
 @pytest.mark.parametrize("n,widths,K,B", [(3, [5, 4], 2, 4), (38, [256] * 4, 4, 4096),
                                           (7, [100, 33, 70], 3, 257), (2, [100] * 3, 4, 1000),
-                                          (4, [32] * 6, 2, 50), (5, [300, 40], 2, 100)])
+                                          (4, [32] * 6, 2, 50), (5, [300, 40], 2, 100),
+                                          (256, [64, 64], 2, 20)])
 def test_loss_grad_parity(torch, rid, n, widths, K, B):
     params = ridgen.xavier_ensemble(2 * n, widths, K, 1000, bias_std=0.1)
     s, F, _ = ridgen.mf_training_set(B, n)
