@@ -701,64 +701,99 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   // the LDS); the parts' partial sums go to LDS (u0 part q at
   // u0 + q * R * US) and are added in part order when u0 is read.
   // v_1 sits in buffer 1 (2L-1 buffer flips), so u0 may alias buffer 0.
-  // PARTS is U0_SPLIT (the common case, compile-time loops) or 1
-  auto u0_stage = [&](auto parts_c) {
-    constexpr int PARTS = decltype(parts_c)::value;
-    const T* in = act + cur * BUF;
-    const int JT0 = XP / 16;
-    constexpr int KQ = NK / PARTS;            // k-steps per part
-    for (int it = wave; it < JT0 * PARTS; it += NW) {
-      const int t = it / PARTS, q = it - t * PARTS;
-      f4 a1[RT][1];
+  if constexpr (U0_SPLIT == 1) {
+    // one part (16-bit tiles): the plain form
+    {
+      const T* in = act + cur * BUF;
+      const int JT0 = XP / 16;
+      for (int t = wave; t < JT0; t += NW) {
+        f4 a1[RT][1];
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) a1[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
-      gemm_tiles<P, RT, 1, 7>(
-          a1, in + q * KQ * KF, AS,
-          WSrc{rsrc, (int)p.bwd_off[0] + t * kFragBytes + q * KQ * JT0 * kFragBytes,
-               JT0 * kFragBytes},
-          KQ, lane);
-      float* uq0 = u0 + q * R * US;
+        for (int rt = 0; rt < RT; ++rt) a1[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
+        gemm_tiles<P, RT, 1, 7>(
+            a1, in, AS, WSrc{rsrc, (int)p.bwd_off[0] + t * kFragBytes, JT0 * kFragBytes}, NK,
+            lane);
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-        *reinterpret_cast<f4*>(uq0 + (rt * 16 + wl) * US + t * 16 + uq) = a1[rt][0];
+        for (int rt = 0; rt < RT; ++rt)
+          *reinterpret_cast<f4*>(u0 + (rt * 16 + wl) * US + t * 16 + uq) = a1[rt][0];
+      }
     }
-  };
-  const bool full = U0_SPLIT == 1 || p.u0p == U0_SPLIT;
-  if (full)
-    u0_stage(std::integral_constant<int, U0_SPLIT>{});
-  else
-    u0_stage(std::integral_constant<int, 1>{});
-  __syncthreads();
-  // A = sum of the waves' partial dot products + b_o
-  for (int i = threadIdx.x; i < R; i += NW * 64) {
-    float a = p.bo[k];
-    for (int w = 0; w < NW; ++w) a += red[w * R + i];
-    if (row0 + i < p.B) p.A_out[(size_t)k * p.B + row0 + i] = a;
-  }
-  // chain to the angles: g_i = -sin s_i u0[i] + cos s_i u0[n+i]
-  auto chain = [&](auto parts_c) {
-    constexpr int PARTS = decltype(parts_c)::value;
-    auto u0_at = [&](int i, int c) {
-      float v = u0[i * US + c];
-#pragma unroll
-      for (int q = 1; q < PARTS; ++q) v += u0[q * R * US + i * US + c];
-      return v;
-    };
+    __syncthreads();
+    for (int i = threadIdx.x; i < R; i += NW * 64) {
+      float a = p.bo[k];
+      for (int w = 0; w < NW; ++w) a += red[w * R + i];
+      if (row0 + i < p.B) p.A_out[(size_t)k * p.B + row0 + i] = a;
+    }
     for (int e = threadIdx.x; e < R * n; e += NW * 64) {
       const int i = e / n, c = e - i * n;
       const int row = row0 + i;
       if (row < p.B) {
         const float cs = xs[i * X2 + c];
         const float sn = xs[i * X2 + n + c];
-        const float gv = -sn * u0_at(i, c) + cs * u0_at(i, n + c);
+        const float gv = -sn * u0[i * US + c] + cs * u0[i * US + n + c];
         p.g_out[((size_t)k * p.B + row) * n + c] = gv;
       }
     }
-  };
-  if (full)
-    chain(std::integral_constant<int, U0_SPLIT>{});
-  else
-    chain(std::integral_constant<int, 1>{});
+  } else {
+    // PARTS is U0_SPLIT (the common case, compile-time loops) or 1
+    auto u0_stage = [&](auto parts_c) {
+      constexpr int PARTS = decltype(parts_c)::value;
+      const T* in = act + cur * BUF;
+      const int JT0 = XP / 16;
+      constexpr int KQ = NK / PARTS;            // k-steps per part
+      for (int it = wave; it < JT0 * PARTS; it += NW) {
+        const int t = it / PARTS, q = it - t * PARTS;
+        f4 a1[RT][1];
+  #pragma unroll
+        for (int rt = 0; rt < RT; ++rt) a1[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
+        gemm_tiles<P, RT, 1, 7>(
+            a1, in + q * KQ * KF, AS,
+            WSrc{rsrc, (int)p.bwd_off[0] + t * kFragBytes + q * KQ * JT0 * kFragBytes,
+                 JT0 * kFragBytes},
+            KQ, lane);
+        float* uq0 = u0 + q * R * US;
+  #pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+          *reinterpret_cast<f4*>(uq0 + (rt * 16 + wl) * US + t * 16 + uq) = a1[rt][0];
+      }
+    };
+    const bool full = U0_SPLIT == 1 || p.u0p == U0_SPLIT;
+    if (full)
+      u0_stage(std::integral_constant<int, U0_SPLIT>{});
+    else
+      u0_stage(std::integral_constant<int, 1>{});
+    __syncthreads();
+    // A = sum of the waves' partial dot products + b_o
+    for (int i = threadIdx.x; i < R; i += NW * 64) {
+      float a = p.bo[k];
+      for (int w = 0; w < NW; ++w) a += red[w * R + i];
+      if (row0 + i < p.B) p.A_out[(size_t)k * p.B + row0 + i] = a;
+    }
+    // chain to the angles: g_i = -sin s_i u0[i] + cos s_i u0[n+i]
+    auto chain = [&](auto parts_c) {
+      constexpr int PARTS = decltype(parts_c)::value;
+      auto u0_at = [&](int i, int c) {
+        float v = u0[i * US + c];
+  #pragma unroll
+        for (int q = 1; q < PARTS; ++q) v += u0[q * R * US + i * US + c];
+        return v;
+      };
+      for (int e = threadIdx.x; e < R * n; e += NW * 64) {
+        const int i = e / n, c = e - i * n;
+        const int row = row0 + i;
+        if (row < p.B) {
+          const float cs = xs[i * X2 + c];
+          const float sn = xs[i * X2 + n + c];
+          const float gv = -sn * u0_at(i, c) + cs * u0_at(i, n + c);
+          p.g_out[((size_t)k * p.B + row) * n + c] = gv;
+        }
+      }
+    };
+    if (full)
+      chain(std::integral_constant<int, U0_SPLIT>{});
+    else
+      chain(std::integral_constant<int, 1>{});
+  }
 }
 
 // ---------------------------------------------------------------------------
