@@ -4,6 +4,8 @@ differentiated too) against the FP64 oracle, through the C ABI."""
 import numpy as np
 import pytest
 
+import ridgen
+
 from oracle import rid_oracle as O
 from tests.gpu_common import FP32_TOL, HALF_TOL, assert_forces, oracle_models, workload
 
@@ -147,3 +149,19 @@ def test_conservative_16bit_ensemble(torch, rid):
     assert_forces(out["F"], ref["F"], HALF_TOL["bf16"], "bf16 conservative")
     frozen = O.bias_force(pos.astype(np.float64), sys_.quads, models, e0, e1)["F"]
     assert O.max_rel_err(frozen, ref["F"]) > 4 * HALF_TOL["bf16"][0]
+
+
+def test_conservative_at_256_cvs(torch, rid):
+    # the widest input: the fused Hessian-vector kernel's tile does not fit
+    # the LDS, so the switch gradient comes from the input-mode sweeps
+    sys_ = ridgen.chain_system(129, 5)
+    widths, K = [64, 64], 4
+    pos = ridgen.f32(ridgen.chain_coords(sys_, 5, 31))
+    params = ridgen.xavier_ensemble(2 * sys_.n_cv, widths, K, 1000, 0.1)
+    models = oracle_models(params, sys_.n_cv, widths, K)
+    ref1 = O.bias_force(pos.astype(np.float64), sys_.quads, models, 1e30, 2e30)
+    e0, e1 = 0.5 * ref1["eps"].min(), 2.0 * ref1["eps"].max()
+    ref = O.bias_force_conservative(pos.astype(np.float64), sys_.quads, models, e0, e1)
+    out = _run(torch, rid, sys_, pos, params, widths, K, e0, e1, True)
+    bound = walker_bounds(out["eps"].astype(np.float64), ref["eps"], e0, e1)
+    assert_walkers(out["F"], ref["F"], bound, "conservative, 256 CVs")

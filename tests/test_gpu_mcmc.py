@@ -133,3 +133,20 @@ def test_bf16_ensemble_and_argument_errors(torch, rid):
         rid.mcmc_run(E, s, 1, KT_300K, 4.0, 3)
     with pytest.raises(rid.RidError):
         rid.mcmc_run(E, s, 1, KT_300K, 0.3, 3, proj=(0, 38))
+
+
+def test_mcmc_at_256_cvs(torch, rid):
+    # the widest input (the energy-only MLP then sums its input-gradient
+    # region in one part): the infinite-temperature walk is the generator's
+    W, T, step, seed, n = 40, 6, 0.5, 99, 256
+    E, models = _ensemble(rid, n=n, widths=(64, 64), K=3)
+    s0 = ridgen.f32(ridgen.torus_samples(W, n, 6))
+    ref = O.mcmc_run(models, s0.astype(np.float64), T, 1e30, step, seed, nbins=17)
+    s = torch.from_numpy(s0.copy()).cuda()
+    out = rid.mcmc_run(E, s, T, 1e30, step, seed, nbins=17)
+    torch.cuda.synchronize()
+    assert int(out["accepted"].item()) == W * T
+    assert np.max(_wrapped(s.cpu().numpy().astype(np.float64), ref["s"])) < 2e-5
+    h1 = out["hist1"].cpu().numpy().astype(np.int64)
+    assert h1.sum() == W * T * n
+    assert np.abs(h1 - ref["hist1"]).sum() <= 4   # bin-boundary rounding only
