@@ -48,6 +48,11 @@ Functions and what pins them (tests/test_oracle_*.py):
   train_loss_grad     gradient of the mean-force loss in the weights
                       pinned: central FD on every parameter; exact least-
                       squares solution of the linear model has zero gradient
+  dropout_scales      training-time dropout of the hidden activations
+                      (counter-based masks); pinned: finite differences of
+                      the loss with the masks fixed, rate 0 reproduces the
+                      plain gradient bit for bit, kept fraction within a
+                      binomial bound, masks distinct per step and member
   adam_step / lr_at   optimiser and exponential LR decay ("Training phase")
                       pinned: one-step closed form; convergence on the linear
                       model to the analytic optimum
@@ -179,21 +184,29 @@ def embed(s):
     return np.concatenate([np.cos(s), np.sin(s)], axis=-1)
 
 
-def mlp_value_and_grad(model, x):
+def mlp_value_and_grad(model, x, scales=None):
     """One free-energy model: A(x) and dA/dx.
 
     model = (Ws, bs, wo, bo): h_0 = x, h_l = tanh(W_l h_{l-1} + b_l),
     A = wo . h_L + bo.  Reverse sweep: u_L = wo, v_l = u_l * (1 - h_l^2),
     u_{l-1} = W_l^T v_l; dA/dx = u_0.  x: [B][D] -> (A [B], u0 [B][D]).
+    scales (training with dropout): per hidden layer [B][w_l] factors that
+    multiply h_l = tanh(z_l), and so its derivative (see dropout_scales).
     """
     Ws, bs, wo, bo = model
     hs = [np.asarray(x, dtype=np.float64)]
-    for W, b in zip(Ws, bs):
-        hs.append(np.tanh(hs[-1] @ W.T + b))
+    ts = [None]
+    for l, (W, b) in enumerate(zip(Ws, bs)):
+        t = np.tanh(hs[-1] @ W.T + b)
+        ts.append(t)
+        hs.append(t if scales is None else t * scales[l])
     A = hs[-1] @ wo + bo
     u = np.broadcast_to(wo, hs[-1].shape)
     for l in range(len(Ws), 0, -1):
-        v = u * (1.0 - hs[l] ** 2)
+        d = 1.0 - ts[l] ** 2
+        if scales is not None:
+            d = d * scales[l - 1]
+        v = u * d
         u = v @ Ws[l - 1]
     return A, u
 
@@ -372,7 +385,7 @@ def bias_energy(pos, quads, models, eps0, eps1):
 # --------------------------------------------------------------------------
 # a7: mean-force fitting, double backward, Adam
 # --------------------------------------------------------------------------
-def train_loss_grad(model, s, F):
+def train_loss_grad(model, s, F, scales=None):
     """Loss L = (1/B) sum_b |g(s_b) - F_b|^2 of one model and its gradient.
 
     The models are trained to predict mean forces ("Training phase"), i.e.
@@ -393,33 +406,41 @@ def train_loss_grad(model, s, F):
     s = np.asarray(s, dtype=np.float64)
     F = np.asarray(F, dtype=np.float64)
     B, n = s.shape
-    A, u0 = mlp_value_and_grad(model, embed(s))
+    A, u0 = mlp_value_and_grad(model, embed(s), scales)
     g = mean_force_from_input_grad(s, u0)
     r = g - F
     loss = float(np.sum(r * r) / B)
-    return loss, mean_force_vjp(model, s, 2.0 * r / B)
+    return loss, mean_force_vjp(model, s, 2.0 * r / B, scales)
 
 
-def mean_force_vjp(model, s, rho):
+def mean_force_vjp(model, s, rho, scales=None):
     """Gradient in the parameters of J = sum_b rho_b . g(s_b) for a given
     rho [B][n] (the tangent + adjoint sweep described in train_loss_grad).
+    With dropout scales S_l the hidden output is S_l tanh(z_l): its
+    derivative S_l (1 - tanh^2) replaces (1 - h_l^2) throughout, and the
+    second-order term -2 tanh(z_l) zd_l keeps the unscaled tanh.
     Returns (dWs, dbs, dwo, dbo)."""
     Ws, bs, wo, bo = model
     s = np.asarray(s, dtype=np.float64)
     rho = np.asarray(rho, dtype=np.float64)
     x = embed(s)
     rho_x = np.concatenate([-np.sin(s) * rho, np.cos(s) * rho], axis=-1)
-    # primal activations
+    # primal activations (ts: tanh before the dropout scale)
     hs = [x]
-    for W, b in zip(Ws, bs):
-        hs.append(np.tanh(hs[-1] @ W.T + b))
+    ts = [None]
+    for l, (W, b) in enumerate(zip(Ws, bs)):
+        t = np.tanh(hs[-1] @ W.T + b)
+        ts.append(t)
+        hs.append(t if scales is None else t * scales[l])
+    ds = [None] + [(1.0 - ts[l] ** 2) * (1.0 if scales is None else scales[l - 1])
+                   for l in range(1, len(Ws) + 1)]
     # tangent forward
     hds = [rho_x]
     zds = [None]
     for l, W in enumerate(Ws, start=1):
         zd = hds[-1] @ W.T
         zds.append(zd)
-        hds.append((1.0 - hs[l] ** 2) * zd)
+        hds.append(ds[l] * zd)
     L = len(Ws)
     dWs = [None] * L
     dbs = [None] * L
@@ -427,9 +448,9 @@ def mean_force_vjp(model, s, rho):
     lam_hd = np.broadcast_to(wo, hds[L].shape)
     lam_h = np.zeros_like(hs[L])
     for l in range(L, 0, -1):
-        dl = 1.0 - hs[l] ** 2
+        dl = ds[l]
         lam_zd = dl * lam_hd
-        lam_h = lam_h - 2.0 * hs[l] * zds[l] * lam_hd
+        lam_h = lam_h - 2.0 * ts[l] * zds[l] * lam_hd
         lam_z = dl * lam_h
         dWs[l - 1] = lam_z.T @ hs[l - 1] + lam_zd.T @ hds[l - 1]
         dbs[l - 1] = np.sum(lam_z, axis=0)
@@ -438,10 +459,11 @@ def mean_force_vjp(model, s, rho):
     return (dWs, dbs, dwo, 0.0)
 
 
-def train_loss(model, s, F):
+def train_loss(model, s, F, scales=None):
     """Loss only (finite-difference target)."""
-    A, g = ensemble_mean_force([model], s)
-    r = g[:, 0, :] - np.asarray(F, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    _, u0 = mlp_value_and_grad(model, embed(s), scales)
+    r = mean_force_from_input_grad(s, u0) - np.asarray(F, dtype=np.float64)
     return float(np.sum(r * r) / r.shape[0])
 
 
@@ -560,6 +582,33 @@ def mcmc_uniforms(walkers, t, count, seed):
     x = philox4x32(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
     x = x.reshape(len(w), nblk * 4)[:, :count].astype(np.float64)
     return (2.0 * np.floor(x / 512.0) + 1.0) * 2.0 ** -24
+
+
+def dropout_scales(B, widths, rate, seed, step, member):
+    """Inverted-dropout factors of one model for one training step (the
+    paper names a dropout rate among the training settings; reading: every
+    hidden activation tanh(z_l) of a sample is kept with probability
+    1 - rate and scaled by 1/(1 - rate), dropped otherwise).  Unit j of
+    hidden layer l (1-based) of sample b takes word j mod 4 of the
+    Philox4x32-10 block with counter (b, step mod 2^32, 16 member + l,
+    j div 4) and key (seed mod 2^32, seed div 2^32); the word x gives
+    u = (2 (x >> 9) + 1) 2^-24 and the unit is kept when u >= rate, compared
+    in FP32.  Returns [len(widths)] arrays [B][w_l] of 0 or 1/(1 - rate)."""
+    key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    p32 = np.float32(rate)
+    inv = float(np.float32(1.0) / (np.float32(1.0) - p32))
+    out = []
+    for l, w in enumerate(widths, start=1):
+        nblk = (w + 3) // 4
+        ctr = np.zeros((B, nblk, 4), dtype=np.uint64)
+        ctr[:, :, 0] = np.arange(B, dtype=np.uint64)[:, None]
+        ctr[:, :, 1] = int(step) & 0xFFFFFFFF
+        ctr[:, :, 2] = 16 * int(member) + l
+        ctr[:, :, 3] = np.arange(nblk, dtype=np.uint64)[None, :]
+        x = philox4x32(ctr, key).reshape(B, nblk * 4)[:, :w].astype(np.float64)
+        u = ((2.0 * np.floor(x / 512.0) + 1.0) * 2.0 ** -24).astype(np.float32)
+        out.append(np.where(u >= p32, inv, 0.0))
+    return out
 
 
 def wrap_torus(s):

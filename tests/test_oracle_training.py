@@ -102,3 +102,52 @@ def test_learning_rate_schedule_from_paper():
     assert abs(O.lr_at(T) - lr0 * gam) < 1e-18
     assert abs(O.lr_at(10 * T) - lr0 * gam ** 10) < 1e-18
     assert abs(O.lr_at(T // 2) - lr0 * math.sqrt(gam)) < 1e-18
+
+
+def test_dropout_gradient_finite_differences():
+    n, widths = 3, [6, 5]
+    model = _model(2 * n, widths, 17)
+    rng = np.random.default_rng(18)
+    s = rng.uniform(-3, 3, size=(5, n))
+    F = rng.normal(size=(5, n))
+    sc = O.dropout_scales(5, widths, 0.3, seed=123, step=2, member=1)
+    assert any(np.any(x == 0.0) for x in sc) and any(np.any(x > 1.0) for x in sc)
+    loss, grads = O.train_loss_grad(model, s, F, sc)
+    assert abs(loss - O.train_loss(model, s, F, sc)) < 1e-13
+    assert abs(loss - O.train_loss(model, s, F)) > 1e-6      # the masks matter
+    theta = O.flat_model(model)
+    g = O.flat_grad(grads)
+    h = 1e-6
+    fd = np.zeros_like(theta)
+    for j in range(theta.size):
+        t1 = theta.copy(); t1[j] += h
+        t2 = theta.copy(); t2[j] -= h
+        fd[j] = (O.train_loss(O.unflat_model(t1, 2 * n, widths), s, F, sc)
+                 - O.train_loss(O.unflat_model(t2, 2 * n, widths), s, F, sc)) / (2 * h)
+    assert np.max(np.abs(fd - g)) < 1e-6 * np.max(np.abs(g))
+
+
+def test_dropout_rate_zero_is_the_plain_gradient():
+    n, widths = 4, [8, 8]
+    model = _model(2 * n, widths, 19)
+    rng = np.random.default_rng(20)
+    s = rng.uniform(-3, 3, size=(6, n))
+    F = rng.normal(size=(6, n))
+    sc = O.dropout_scales(6, widths, 0.0, seed=5, step=0, member=0)
+    assert all(np.all(x == 1.0) for x in sc)
+    l0, g0 = O.train_loss_grad(model, s, F)
+    l1, g1 = O.train_loss_grad(model, s, F, sc)
+    assert l0 == l1 and np.array_equal(O.flat_grad(g0), O.flat_grad(g1))
+
+
+def test_dropout_masks_statistics():
+    B, widths, p = 2000, [64, 64], 0.3
+    sc = O.dropout_scales(B, widths, p, seed=77, step=4, member=2)
+    keep = np.concatenate([(x > 0).ravel() for x in sc])
+    N = keep.size
+    assert abs(keep.mean() - (1 - p)) < 4 * math.sqrt(p * (1 - p) / N)
+    assert set(np.unique(np.concatenate([x.ravel() for x in sc]))) == {0.0, float(np.float32(1) / np.float32(0.7))}
+    other = O.dropout_scales(B, widths, p, seed=77, step=5, member=2)
+    member = O.dropout_scales(B, widths, p, seed=77, step=4, member=3)
+    assert not np.array_equal(sc[0], other[0]) and not np.array_equal(sc[0], member[0])
+    assert not np.array_equal(sc[0], sc[1][:, :64])
