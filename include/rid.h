@@ -107,6 +107,19 @@ rid_status rid_ensemble_get_params(rid_ensemble ens, float* host_params);
 rid_status rid_ensemble_set_params(rid_ensemble ens, const float* host_params);
 /* Number of Adam updates taken so far. */
 int64_t rid_ensemble_step(rid_ensemble ens);
+/* Training-time dropout of the hidden activations ("Training phase" lists a
+ * dropout rate among the training settings).  With rate p > 0 every training
+ * call (rid_mf_train_step, rid_mf_loss_grad, rid_mf_grad) keeps hidden unit j
+ * of layer l (1-based) of sample b of member k with probability 1 - p and
+ * scales it by 1/(1 - p): the unit is kept when the uniform
+ * (2 (x >> 9) + 1) 2^-24 of word j mod 4 of the Philox4x32-10 block with
+ * counter (b, step mod 2^32, 16 k + l, j div 4) and key (seed mod 2^32,
+ * seed div 2^32) is >= p (FP32), step being rid_ensemble_step at the call.
+ * The bias path, MCMC and selection evaluate the full network.  Dropout
+ * needs the fused training kernel (FP32 ensembles of padded width <= 256
+ * whose input tile fits it): training calls on other ensembles return
+ * RID_EUNSUPPORTED while p > 0.  Errors: RID_EINVAL (NULL, p outside [0, 1)). */
+rid_status rid_ensemble_set_dropout(rid_ensemble ens, float rate, uint64_t seed);
 void rid_ensemble_destroy(rid_ensemble ens);
 
 /* ------------------------------------------------------------------------

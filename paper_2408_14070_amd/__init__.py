@@ -28,7 +28,8 @@ _STATUS = {0: "RID_OK", -1: "RID_EINVAL", -2: "RID_ENOMEM", -3: "RID_EDEVICE",
 EXPORTS = (
     "rid_last_error", "rid_version", "rid_system_create", "rid_system_destroy",
     "rid_packed_param_count", "rid_ensemble_create", "rid_ensemble_get_params",
-    "rid_ensemble_set_params", "rid_ensemble_step", "rid_ensemble_destroy",
+    "rid_ensemble_set_params", "rid_ensemble_step", "rid_ensemble_set_dropout",
+    "rid_ensemble_destroy",
     "rid_cv_eval", "rid_model_dev", "rid_cluster_frames", "rid_select", "rid_bias_force",
     "rid_bias_force_conservative", "rid_mcmc_run",
     "rid_cv_apply_force",
@@ -81,6 +82,7 @@ def lib():
         "rid_ensemble_get_params": (i, [vp, vp]),
         "rid_ensemble_set_params": (i, [vp, vp]),
         "rid_ensemble_step": (i64, [vp]),
+        "rid_ensemble_set_dropout": (i, [vp, f, ctypes.c_uint64]),
         "rid_ensemble_destroy": (None, [vp]),
         "rid_cv_eval": (i, [vp, vp, i, vp, vp, vp]),
         "rid_model_dev": (i, [vp, vp, i, vp, vp, vp, vp, vp]),
@@ -210,6 +212,10 @@ class Ensemble:
     @property
     def step(self) -> int:
         return int(lib().rid_ensemble_step(self.handle))
+
+    def set_dropout(self, rate: float, seed: int = 0):
+        """rid_ensemble_set_dropout: training-time dropout rate and mask seed."""
+        _check(lib().rid_ensemble_set_dropout(self.handle, float(rate), int(seed)))
 
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:

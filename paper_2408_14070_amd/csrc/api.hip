@@ -325,6 +325,14 @@ rid_status rid_ensemble_set_params(rid_ensemble ens, const float* host_params) {
 
 int64_t rid_ensemble_step(rid_ensemble ens) { return ens ? ens->impl.step : -1; }
 
+rid_status rid_ensemble_set_dropout(rid_ensemble ens, float rate, uint64_t seed) {
+  if (!ens) return fail(RID_EINVAL, "NULL argument");
+  if (!(rate >= 0.f && rate < 1.f)) return fail(RID_EINVAL, "dropout rate must be in [0, 1)");
+  ens->impl.drop_p = rate;
+  ens->impl.drop_seed = seed;
+  return RID_OK;
+}
+
 void rid_ensemble_destroy(rid_ensemble ens) {
   if (!ens) return;
   (void)hipDeviceSynchronize();

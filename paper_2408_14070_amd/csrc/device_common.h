@@ -390,5 +390,28 @@ __device__ inline double scatter_stats_reg(const WalkerRegs& r, int K, int n, fl
   return sqrt(ss / K);
 }
 
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of two
+// 32x32 -> 64-bit multiplications, the key bumped by the Weyl constants
+// between rounds; counter c in/out, key (k0, k1).
+__device__ inline void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// A 32-bit word to a uniform in (0, 1): (2 (x >> 9) + 1) 2^-24, exact in FP32.
+__device__ inline float philox_uniform(uint32_t x) {
+  return (float)(2u * (x >> 9) + 1u) * 5.9604644775390625e-8f;
+}
+
 }  // namespace dev
 }  // namespace rid

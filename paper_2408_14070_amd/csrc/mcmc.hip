@@ -28,28 +28,13 @@ constexpr float kPi = 3.14159265358979f;
 constexpr float kTwoPi = 6.28318530717959f;
 constexpr int kMcmcWaves = 4;
 
-__device__ inline void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
-    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-}
-
 // Uniform number `word` of walker w at step t.
 __device__ inline float mcmc_uniform(int w, long long t, int word, unsigned long long seed) {
   uint32_t c[4] = {(uint32_t)w, (uint32_t)((unsigned long long)t & 0xFFFFFFFFull),
                    (uint32_t)((unsigned long long)t >> 32), (uint32_t)(word >> 2)};
   philox4x32_10(c, (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32));
   const uint32_t x = c[word & 3];
-  return (float)(2u * (x >> 9) + 1u) * 5.9604644775390625e-8f;   // 2^-24
+  return philox_uniform(x);
 }
 
 __device__ inline float wrap_pi(float s) {

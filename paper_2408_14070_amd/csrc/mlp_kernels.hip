@@ -1060,6 +1060,12 @@ __global__ __launch_bounds__(NW * 64) void hvp_kernel(HvpArgs p) {
 // every layer input (x ; rho_x first) and [lam_z ; lam_zd] of every layer,
 // each as [K][2B][width], plus the samples' squared residuals.  h and zd
 // of this lane's units stay in VGPRs between the sweeps.
+// Dropout (training only): hidden unit j of layer l of sample b is kept with
+// probability 1 - p and then scaled by 1/(1 - p): word j mod 4 of the
+// Philox4x32-10 block with counter (b, step, 16 member + l, j div 4), kept
+// when its uniform is >= p.  The scaled output S tanh(z) has derivative
+// S (1 - tanh^2) in every sweep; the second-order term keeps the unscaled
+// tanh.  Without dropout S = 1.
 // ---------------------------------------------------------------------------
 struct TrainArgs {
   const float* s;      // [B][n]
@@ -1077,6 +1083,9 @@ struct TrainArgs {
   const float* bias;   // [K][L][NP], pre-scaled
   const float* wo;     // [K][NP]
   unsigned off_u0, off_xs, off_wo;
+  float drop_p, drop_inv;       // rate and 1/(1 - rate); 0 and 1 without dropout
+  unsigned long long drop_seed;
+  uint32_t step;
 };
 
 template <int NP, int NW, int LM>
@@ -1126,6 +1135,24 @@ __global__ __launch_bounds__(NW * 64) void train_kernel(TrainArgs p) {
   ring_preload<PD, 1>(wr, wsrc(p.fwd_off[0]), XP / KF, lane);
   f4 bnext = *reinterpret_cast<const f4*>(bias + u);
   for (int i = threadIdx.x; i < NP; i += NW * 64) wos[i] = wo[i];
+  // dropout keep bits of this lane's 4 units, 4 bits per hidden layer
+  unsigned mbits = 0xFFFFFFFFu;
+  if (p.drop_p > 0.f) {
+    mbits = 0u;
+    for (int j = 0; j < L; ++j) {
+      uint32_t c[4] = {(uint32_t)brow, p.step, (uint32_t)(16 * k + j + 1), (uint32_t)(u >> 2)};
+      philox4x32_10(c, (uint32_t)(p.drop_seed & 0xFFFFFFFFull), (uint32_t)(p.drop_seed >> 32));
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (philox_uniform(c[q]) >= p.drop_p) mbits |= 1u << (4 * j + q);
+    }
+  }
+  auto dsc = [&](int j) {       // the dropout factors of hidden layer j (0-based)
+    f4 r;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = ((mbits >> (4 * j + q)) & 1u) ? p.drop_inv : 0.f;
+    return r;
+  };
 
   // 4 units of row r (0 .. 2B-1) of a [K][2B][w] array; units past w are
   // padding and stay unwritten
@@ -1178,11 +1205,13 @@ __global__ __launch_bounds__(NW * 64) void train_kernel(TrainArgs p) {
       d[q] = dq;
     }
     hj = h;
+    const f4 sc = dsc(j);
     if (j < L - 1) {
-      lds4(out, wl, h);
-      if (in_b) put4(p.hh[j + 1], p.wd[j + 1], brow, h);
+      const f4 hsc = h * sc;
+      lds4(out, wl, hsc);
+      if (in_b) put4(p.hh[j + 1], p.wd[j + 1], brow, hsc);
     } else {
-      lds4(out, wl, *reinterpret_cast<const f4*>(wos + u) * d);
+      lds4(out, wl, *reinterpret_cast<const f4*>(wos + u) * d * sc);
     }
   };
 
@@ -1226,7 +1255,7 @@ __global__ __launch_bounds__(NW * 64) void train_kernel(TrainArgs p) {
       gemm_hidden<P, 1, 1, 1, PDH, NK>(acc, wh, in, AS, wsrc(p.bwd_off[j]), j >= 2,
                                        wsrc(p.bwd_off[j >= 2 ? j - 1 : j]), lane);
       const f4 h = hs[j - 1];
-      lds4(out, wl, acc[0][0] * (1.f - h * h));
+      lds4(out, wl, acc[0][0] * ((1.f - h * h) * dsc(j - 1)));
       cur ^= 1;
       __syncthreads();
     }
@@ -1301,7 +1330,7 @@ __global__ __launch_bounds__(NW * 64) void train_kernel(TrainArgs p) {
   // lam_zd = tanh'_L w_o, lam_z = tanh'_L (-2 h_L zd_L w_o)
   auto tan_epi = [&](int j, const f4& h, f4& zj, const f4& y, float* out) {
     const f4 zd = y * kTanhUnscale;
-    const f4 d = 1.f - h * h;
+    const f4 d = (1.f - h * h) * dsc(j);
     const f4 hd = d * zd;
     if (in_b) put4(p.hh[j + 1], p.wd[j + 1], B + brow, hd);
     if (j < L - 1) {
@@ -1358,7 +1387,7 @@ __global__ __launch_bounds__(NW * 64) void train_kernel(TrainArgs p) {
       gemm_hidden<P, 2, 1, 1, PDH, NK>(acc, wh, in, AS, wsrc(p.bwd_off[j]), j >= 2,
                                        wsrc(p.bwd_off[j >= 2 ? j - 1 : j]), lane);
       const f4 h = hs[j - 1], zd = zs[j - 1];
-      const f4 d = 1.f - h * h;
+      const f4 d = (1.f - h * h) * dsc(j - 1);
       const f4 lhd = acc[1][0];
       const f4 lzd = d * lhd;
       const f4 lz = d * (acc[0][0] - 2.f * h * zd * lhd);
@@ -1719,6 +1748,10 @@ rid_status run_train(const rid_ensemble_impl& e, const TrainIo& io, int B, hipSt
     a.bwd_off[l] = (unsigned)e.layers[l].bwd_off;
   }
   a.bias = e.d_bias; a.wo = e.d_wo;
+  a.drop_p = io.drop_p;
+  a.drop_inv = io.drop_p > 0.f ? 1.f / (1.f - io.drop_p) : 1.f;
+  a.drop_seed = io.drop_seed;
+  a.step = io.step;
   const int grid = a.xcd_grp > 0 ? 8 * ((a.n_tiles + a.xcd_grp - 1) / a.xcd_grp)
                                   : a.n_tiles * e.K;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), (uint32_t)lds, st, a);

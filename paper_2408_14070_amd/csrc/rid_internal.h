@@ -137,6 +137,8 @@ struct rid_ensemble_impl {
   float* d_m = nullptr;
   float* d_v = nullptr;
   int64_t step = 0;
+  float drop_p = 0.f;                  // training-time dropout rate of the hidden activations
+  unsigned long long drop_seed = 0;
   // kernel-layout parameters
   std::vector<LayerDev> layers;
   size_t frag_bytes_per_model = 0;
@@ -187,6 +189,9 @@ struct TrainIo {
   float* hh[kMaxHidden + 1];
   float* sl[kMaxHidden];
   float* loss_rows;
+  float drop_p;                     // dropout rate (0: none)
+  unsigned long long drop_seed;
+  uint32_t step;                    // training step (mask counter)
 };
 // Threshold clustering of CV frames (selection); synchronises the stream.
 // Copies the first min(leaders, leaders_out) leaders' frame indices.

@@ -518,6 +518,9 @@ rid_status mf_grad_fused(rid_ensemble_impl& e, const float* s, const float* F,
   io.F = rho ? nullptr : F;
   io.rho = rho;
   io.loss_rows = rho ? nullptr : W + lrows;
+  io.drop_p = e.drop_p;
+  io.drop_seed = e.drop_seed;
+  io.step = (uint32_t)((unsigned long long)e.step & 0xFFFFFFFFull);
   for (int l = 0; l <= L; ++l) io.hh[l] = W + hh[l];
   for (int l = 0; l < L; ++l) io.sl[l] = W + sl[l];
   if ((rs = launch_train_sweeps(e, io, B, st)) != RID_OK) return rs;
@@ -596,6 +599,9 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   if (!input_mode && train_fused_supported(e))
     return mf_grad_fused(e, s, F, rho, B, loss, grad_out, grad_used, st, w, w_off, b_off,
                          wo_off, ks, kchunk);
+  if (!input_mode && e.drop_p > 0.f)
+    return fail(RID_EUNSUPPORTED,
+                "dropout needs the fused training kernel (FP32, padded width <= 256)");
 
   // workspace (floats)
   std::vector<long long> hh(L + 1), zd(L + 1);

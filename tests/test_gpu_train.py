@@ -153,3 +153,67 @@ def test_training_is_deterministic(torch, rid):
             rid.mf_train_step(E, S_, F_, 1e-3)
         out.append(E.get_params())
     assert np.array_equal(out[0], out[1])
+
+
+DROP_SEED = 0xABCDEF0123
+
+
+def _grad_ref_dropout(params, n, widths, K, s, F, rate, step):
+    models = ridgen.unpack_params(params, 2 * n, widths, K)
+    losses, grads = [], []
+    for k, m in enumerate(models):
+        sc = O.dropout_scales(len(s), widths, rate, DROP_SEED, step, k)
+        loss, g = O.train_loss_grad(m, s.astype(np.float64), F.astype(np.float64), sc)
+        losses.append(loss)
+        grads.append(O.flat_grad(g))
+    return np.array(losses), np.stack(grads)
+
+
+@pytest.mark.parametrize("n,widths,K,B", [(38, [256] * 4, 4, 4096), (7, [100, 33, 70], 3, 257)])
+def test_loss_grad_parity_with_dropout(torch, rid, n, widths, K, B):
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 1000, bias_std=0.1)
+    s, F, _ = ridgen.mf_training_set(B, n)
+    E = rid.Ensemble(n, widths, K, params)
+    E.set_dropout(0.2, DROP_SEED)
+    loss, grad = rid.mf_loss_grad(E, _dev(torch, s), _dev(torch, F))
+    torch.cuda.synchronize()
+    loss_ref, grad_ref = _grad_ref_dropout(params, n, widths, K, s, F, 0.2, 0)
+    lerr = np.max(np.abs(loss.cpu().numpy() - loss_ref) / loss_ref)
+    gerr = _per_member_err(grad.cpu().numpy(), grad_ref)
+    print(f"dropout 0.2 n={n} widths={widths}: loss rel err {lerr:.2e}, grad err {gerr:.2e}")
+    assert lerr <= 1e-5 and gerr <= GRAD_TOL
+    # the masks matter: the plain gradient is far outside the tolerance
+    _, plain = _grad_ref(params, n, widths, K, s, F)
+    assert _per_member_err(plain, grad_ref) > 100 * GRAD_TOL
+
+
+def test_dropout_masks_follow_the_step_counter(torch, rid):
+    n, widths, K, B = 6, [64, 48], 3, 300
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 31, bias_std=0.1)
+    s, F, _ = ridgen.mf_training_set(B, n)
+    E = rid.Ensemble(n, widths, K, params)
+    E.set_dropout(0.3, DROP_SEED)
+    rid.mf_train_step(E, _dev(torch, s), _dev(torch, F), 1e-3)
+    torch.cuda.synchronize()
+    assert E.step == 1
+    p1 = E.get_params()
+    loss, grad = rid.mf_loss_grad(E, _dev(torch, s), _dev(torch, F))
+    torch.cuda.synchronize()
+    loss_ref, grad_ref = _grad_ref_dropout(p1, n, widths, K, s, F, 0.3, 1)
+    assert np.max(np.abs(loss.cpu().numpy() - loss_ref) / loss_ref) <= 1e-5
+    assert _per_member_err(grad.cpu().numpy(), grad_ref) <= GRAD_TOL
+
+
+def test_dropout_needs_the_fused_kernel(torch, rid):
+    n, widths, K, B = 5, [300, 40], 2, 50
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 33, bias_std=0.1)
+    s, F, _ = ridgen.mf_training_set(B, n)
+    E = rid.Ensemble(n, widths, K, params)
+    E.set_dropout(0.1, 1)
+    with pytest.raises(rid.RidError):
+        rid.mf_loss_grad(E, _dev(torch, s), _dev(torch, F))
+    E.set_dropout(0.0, 1)
+    rid.mf_loss_grad(E, _dev(torch, s), _dev(torch, F))
+    torch.cuda.synchronize()
+    with pytest.raises(rid.RidError):
+        E.set_dropout(1.0, 1)
