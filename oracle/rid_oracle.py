@@ -22,9 +22,14 @@ Functions and what pins them (tests/test_oracle_*.py):
   embed               [cos s | sin s] periodic input encoding
                       pinned: 2pi periodicity of every downstream output
   mlp_value_and_grad  free-energy MLP A(x) and dA/dx ("Training phase":
-                      MLP of `neurons` widths, tanh)
+                      MLP of `neurons` widths, tanh; optional residual
+                      connections, the `resnet` setting)
                       pinned: closed forms for zero and one hidden layer,
-                      finite differences of A in x
+                      finite differences of A in x; residual form: the
+                      small-weight linear limit wo . prod(I + W_l) W_1 x,
+                      reduction to one layer when the later layers are
+                      zero, finite differences, one layer equals the plain
+                      MLP
   ensemble_mean_force per-model mean force dA_k/ds (Box 2: F = grad_s A)
                       pinned: closed form for a linear model, FD in s
   model_deviation     ensemble standard deviation of the mean forces
@@ -184,6 +189,19 @@ def embed(s):
     return np.concatenate([np.cos(s), np.sin(s)], axis=-1)
 
 
+def is_resnet(model):
+    """True for a model with residual connections: (Ws, bs, wo, bo, True)."""
+    return len(model) > 4 and bool(model[4])
+
+
+def _plain_model(model, what):
+    """The four parameter lists of a model without residual connections;
+    a residual model is refused (``what`` is not built for it)."""
+    if is_resnet(model):
+        raise ValueError(what + " is defined here for plain MLPs only")
+    return model[:4]
+
+
 def mlp_value_and_grad(model, x, scales=None):
     """One free-energy model: A(x) and dA/dx.
 
@@ -192,14 +210,28 @@ def mlp_value_and_grad(model, x, scales=None):
     u_{l-1} = W_l^T v_l; dA/dx = u_0.  x: [B][D] -> (A [B], u0 [B][D]).
     scales (training with dropout): per hidden layer [B][w_l] factors that
     multiply h_l = tanh(z_l), and so its derivative (see dropout_scales).
+
+    model = (Ws, bs, wo, bo, True): the `resnet` option of the training
+    settings ("Training phase": residual connections, hidden layers of
+    equal width).  Reading: every hidden layer after the first adds its
+    input, h_l = h_{l-1} + tanh(W_l h_{l-1} + b_l) for l >= 2 (the first
+    layer maps the CV encoding, of another width); the reverse sweep then
+    carries the skip, u_{l-1} = W_l^T v_l + u_l for l >= 2, with
+    v_l = u_l * (1 - tanh^2).
     """
-    Ws, bs, wo, bo = model
+    Ws, bs, wo, bo = model[:4]
+    res = is_resnet(model)
+    if res and scales is not None:
+        raise ValueError("dropout is defined here for plain MLPs only")
+    if res and any(np.shape(W)[0] != np.shape(Ws[0])[0] for W in Ws):
+        raise ValueError("residual connections need hidden layers of equal width")
     hs = [np.asarray(x, dtype=np.float64)]
     ts = [None]
     for l, (W, b) in enumerate(zip(Ws, bs)):
         t = np.tanh(hs[-1] @ W.T + b)
         ts.append(t)
-        hs.append(t if scales is None else t * scales[l])
+        h = t if scales is None else t * scales[l]
+        hs.append(h + hs[-1] if (res and l >= 1) else h)
     A = hs[-1] @ wo + bo
     u = np.broadcast_to(wo, hs[-1].shape)
     for l in range(len(Ws), 0, -1):
@@ -207,7 +239,7 @@ def mlp_value_and_grad(model, x, scales=None):
         if scales is not None:
             d = d * scales[l - 1]
         v = u * d
-        u = v @ Ws[l - 1]
+        u = v @ Ws[l - 1] + (u if (res and l >= 2) else 0.0)
     return A, u
 
 
@@ -313,7 +345,7 @@ def mlp_input_hvp(model, x, rho):
     hd_l = (1 - h_l^2) W_l hd_{l-1} (hd_0 = rho).  Reverse: v_L = wo (1 -
     h_L^2), u_{l-1} = W_l^T v_l, v_l = u_l (1 - h_l^2); its tangent uses
     d(1 - h^2) = -2 h hd.  x, rho: [B][D] -> [B][D]."""
-    Ws, bs, wo, bo = model
+    Ws, bs, wo, bo = _plain_model(model, "the input Hessian-vector product")
     hs = [np.asarray(x, dtype=np.float64)]
     hds = [np.asarray(rho, dtype=np.float64)]
     for W, b in zip(Ws, bs):
@@ -420,7 +452,7 @@ def mean_force_vjp(model, s, rho, scales=None):
     derivative S_l (1 - tanh^2) replaces (1 - h_l^2) throughout, and the
     second-order term -2 tanh(z_l) zd_l keeps the unscaled tanh.
     Returns (dWs, dbs, dwo, dbo)."""
-    Ws, bs, wo, bo = model
+    Ws, bs, wo, bo = _plain_model(model, "mean-force training")
     s = np.asarray(s, dtype=np.float64)
     rho = np.asarray(rho, dtype=np.float64)
     x = embed(s)
@@ -497,7 +529,7 @@ def flat_grad(grads):
 
 
 def flat_model(model):
-    Ws, bs, wo, bo = model
+    Ws, bs, wo, bo = model[:4]
     parts = []
     for W, b in zip(Ws, bs):
         parts += [np.ravel(W), np.ravel(b)]
