@@ -120,6 +120,18 @@ int64_t rid_ensemble_step(rid_ensemble ens);
  * whose input tile fits it): training calls on other ensembles return
  * RID_EUNSUPPORTED while p > 0.  Errors: RID_EINVAL (NULL, p outside [0, 1)). */
 rid_status rid_ensemble_set_dropout(rid_ensemble ens, float rate, uint64_t seed);
+/* rid_ensemble_set_resnet - residual connections (the `resnet` training
+ * setting, "Training phase": hidden layers of equal width joined by residual
+ * connections).  With enable != 0 every hidden layer after the first adds
+ * its input, h_l = h_{l-1} + tanh(W_l h_{l-1} + b_l) for l >= 2 (the first
+ * layer maps the CV encoding and has no skip); enable = 0 restores the plain
+ * MLP.  The packed parameters are the same in both forms.  Takes effect on
+ * the next call: rid_bias_force, rid_model_dev, rid_select, rid_mcmc_run
+ * and the server evaluate the residual form; rid_bias_force_conservative,
+ * rid_mf_train_step, rid_mf_loss_grad and rid_mf_grad return
+ * RID_EUNSUPPORTED while it is on.  Errors: RID_EINVAL (NULL, hidden widths
+ * not all equal), RID_EUNSUPPORTED (BF16/FP16 ensemble). */
+rid_status rid_ensemble_set_resnet(rid_ensemble ens, int enable);
 void rid_ensemble_destroy(rid_ensemble ens);
 
 /* ------------------------------------------------------------------------

@@ -29,6 +29,7 @@ EXPORTS = (
     "rid_last_error", "rid_version", "rid_system_create", "rid_system_destroy",
     "rid_packed_param_count", "rid_ensemble_create", "rid_ensemble_get_params",
     "rid_ensemble_set_params", "rid_ensemble_step", "rid_ensemble_set_dropout",
+    "rid_ensemble_set_resnet",
     "rid_ensemble_destroy",
     "rid_cv_eval", "rid_model_dev", "rid_cluster_frames", "rid_select", "rid_bias_force",
     "rid_bias_force_conservative", "rid_mcmc_run",
@@ -83,6 +84,7 @@ def lib():
         "rid_ensemble_set_params": (i, [vp, vp]),
         "rid_ensemble_step": (i64, [vp]),
         "rid_ensemble_set_dropout": (i, [vp, f, ctypes.c_uint64]),
+        "rid_ensemble_set_resnet": (i, [vp, i]),
         "rid_ensemble_destroy": (None, [vp]),
         "rid_cv_eval": (i, [vp, vp, i, vp, vp, vp]),
         "rid_model_dev": (i, [vp, vp, i, vp, vp, vp, vp, vp]),
@@ -216,6 +218,11 @@ class Ensemble:
     def set_dropout(self, rate: float, seed: int = 0):
         """rid_ensemble_set_dropout: training-time dropout rate and mask seed."""
         _check(lib().rid_ensemble_set_dropout(self.handle, float(rate), int(seed)))
+
+    def set_resnet(self, enable: bool = True):
+        """rid_ensemble_set_resnet: residual connections between the hidden
+        layers after the first (hidden widths must be equal; FP32 only)."""
+        _check(lib().rid_ensemble_set_resnet(self.handle, 1 if enable else 0))
 
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:

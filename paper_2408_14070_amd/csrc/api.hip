@@ -252,7 +252,9 @@ rid_status rid_ensemble_create(int n_cv, int n_models, int n_hidden,
   e.widths.assign(widths, widths + n_hidden);
   e.prec = prec;
   e.KF = kf_of(prec);
-  e.NP = round_up(wmax, 64);
+  // the MLP kernels exist for padded widths 64, 128, 256 and 512 (zero
+  // units pad the rest: their weights, biases and outputs stay 0)
+  e.NP = wmax <= 64 ? 64 : wmax <= 128 ? 128 : wmax <= 256 ? 256 : 512;
   e.XP = round_up(2 * n_cv, e.KF);
   e.per_model = per_model_count(n_cv, n_hidden, widths);
   e.n_params = e.per_model * n_models;
@@ -330,6 +332,20 @@ rid_status rid_ensemble_set_dropout(rid_ensemble ens, float rate, uint64_t seed)
   if (!(rate >= 0.f && rate < 1.f)) return fail(RID_EINVAL, "dropout rate must be in [0, 1)");
   ens->impl.drop_p = rate;
   ens->impl.drop_seed = seed;
+  return RID_OK;
+}
+
+rid_status rid_ensemble_set_resnet(rid_ensemble ens, int enable) {
+  if (!ens) return fail(RID_EINVAL, "NULL argument");
+  const rid_ensemble_impl& e = ens->impl;
+  if (enable) {
+    for (int w : e.widths)
+      if (w != e.widths[0])
+        return fail(RID_EINVAL, "residual connections need hidden layers of equal width");
+    if (e.prec != RID_FP32)
+      return fail(RID_EUNSUPPORTED, "residual connections need an FP32 ensemble");
+  }
+  ens->impl.resnet = enable != 0;
   return RID_OK;
 }
 

@@ -106,6 +106,8 @@ rid_status launch_bias_conservative(const rid_system_impl& s, rid_ensemble_impl&
                                     const float* pos, int B, float eps0, float eps1,
                                     float* force, float* energy, float* eps, float* sigma,
                                     uint8_t* flags, hipStream_t st) {
+  if (e.resnet)
+    return fail(RID_EUNSUPPORTED, "conservative switching is built for plain MLPs");
   const int K = e.K, n = e.n_cv;
   rid_status r;
   // workspace: s [B][n], gbar [B][n], fcv [B][n], rho [B][K][n], coef [B],

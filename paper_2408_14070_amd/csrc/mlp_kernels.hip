@@ -381,10 +381,11 @@ __host__ __device__ constexpr int u0_split() {
 
 // GRAD = false: the free energies only (the forward sweep, no tanh' stash,
 // no reverse sweep, no g output).
-template <class P, int NP, int RT, int NW, int LM, bool FROM_POS, bool GRAD>
+template <class P, int NP, int RT, int NW, int LM, bool FROM_POS, bool GRAD, bool RES>
 __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   using T = typename P::T;
   using SP = Pack4<T>;
+  static_assert(!RES || sizeof(T) == 4, "residual form: FP32 tiles");
   constexpr int KF = P::KF;
   constexpr int CT = NP / (16 * NW);
   constexpr int R = 16 * RT;
@@ -543,11 +544,18 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   // ---------------- forward: h_l = tanh(W_l h_{l-1} + b_l) ----------------
   // tile epilogues: tanh and its derivative; a layer before the last stores
   // h_l into the other buffer and stashes tanh'; the last layer stores
-  // v_L = w_o * tanh' and accumulates the lane's part of A = w_o . h_L
+  // v_L = w_o * tanh' and accumulates the lane's part of A = w_o . h_L.
+  // Residual form (RES): hidden layers after the first add their input,
+  // h_l = h_{l-1} + tanh(z_l), read from the layer's input buffer at the
+  // lane's own four units (all hidden layers share the padded width).
   float apart[RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) apart[rt] = 0.f;
-  auto mid_tile = [&](int l, int rt, int c, const f4& z, T* out) {
+  f4 ares[RT][CT];                   // RES: dA/dh of the layer being reversed
+  auto skip_in = [&](const T* in, int rt, int c) {
+    return *reinterpret_cast<const f4*>(in + (rt * 16 + wl) * AS + (jt0 + c) * 16 + uq);
+  };
+  auto mid_tile = [&](int l, int rt, int c, const f4& z, const T* in, T* out) {
     f4 h, d;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -555,12 +563,15 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       h[q] = tanh_and_grad(z[q], dq);
       d[q] = dq;
     }
+    if constexpr (RES) {
+      if (l >= 1) h += skip_in(in, rt, c);
+    }
     SP o;
     o.set(h);
     o.store(out + (rt * 16 + wl) * AS + (jt0 + c) * 16 + uq);
     if constexpr (GRAD) st[l][rt][c].set(d);
   };
-  auto last_tile = [&](int rt, int c, const f4& z, T* out) {
+  auto last_tile = [&](int rt, int c, const f4& z, const T* in, bool skip, T* out) {
     const int u = (jt0 + c) * 16 + uq;
     const f4 w4 = *reinterpret_cast<const f4*>(wos + u);
     f4 h, d;
@@ -569,6 +580,10 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       float dq;
       h[q] = tanh_and_grad(z[q], dq);
       d[q] = dq;
+    }
+    if constexpr (RES) {
+      if (skip) h += skip_in(in, rt, c);
+      ares[rt][c] = w4;              // dA/dh_L = w_o
     }
     apart[rt] += w4[0] * h[0] + w4[1] * h[1] + w4[2] * h[2] + w4[3] * h[3];
     if constexpr (GRAD) {
@@ -601,12 +616,12 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
 #pragma unroll
       for (int c = 0; c < CT; ++c)
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) mid_tile(0, rt, c, acc[rt][c], out);
+        for (int rt = 0; rt < RT; ++rt) mid_tile(0, rt, c, acc[rt][c], act, out);
     } else {
 #pragma unroll
       for (int c = 0; c < CT; ++c)
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) last_tile(rt, c, acc[rt][c], out);
+        for (int rt = 0; rt < RT; ++rt) last_tile(rt, c, acc[rt][c], act, false, out);
     }
     cur = 1;
     __syncthreads();
@@ -628,7 +643,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
 #pragma unroll
       for (int c = 0; c < CT; ++c)
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) mid_tile(l, rt, c, acc[rt][c], out);
+        for (int rt = 0; rt < RT; ++rt) mid_tile(l, rt, c, acc[rt][c], in, out);
       cur ^= 1;
       __syncthreads();
     }
@@ -646,7 +661,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
 #pragma unroll
     for (int c = 0; c < CT; ++c)
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) last_tile(rt, c, acc[rt][c], out);
+      for (int rt = 0; rt < RT; ++rt) last_tile(rt, c, acc[rt][c], in, true, out);
     cur ^= 1;
     __syncthreads();
   }
@@ -670,9 +685,17 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   }
 
   // ------------- reverse sweep: v_{l-1} = (W_l^T v_l) * tanh'_{l-1} -------------
+  // Residual form: the skip of layer l carries dA/dh_l on, so
+  // dA/dh_{l-1} = W_l^T v_l + dA/dh_l (kept per lane in ares) and
+  // v_{l-1} = dA/dh_{l-1} * tanh'_{l-1}.
   auto bwd_tile = [&](int l, int rt, int c, const f4& y, T* out) {
     SP o;
-    o.set(y * st[l - 1][rt][c].get());
+    if constexpr (RES) {
+      ares[rt][c] += y;
+      o.set(ares[rt][c] * st[l - 1][rt][c].get());
+    } else {
+      o.set(y * st[l - 1][rt][c].get());
+    }
     o.store(out + (rt * 16 + wl) * AS + (jt0 + c) * 16 + uq);
   };
 #pragma unroll
@@ -1528,7 +1551,7 @@ size_t lds_bytes(const rid_ensemble_impl& e, const TorsionInput* tin) {
                     tin ? tin->sys->n_uniq : 0, tin != nullptr, NP, u0_split<P, NP>(), a);
 }
 
-template <class P, int NP, int RT, int NW, int LM>
+template <class P, int NP, int RT, int NW, int LM, bool RES = false>
 rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
                    float* A_out, float* g_out, const TorsionInput* tin,
                    hipStream_t st) {
@@ -1556,9 +1579,9 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
   // without g_out only the free energies are computed (plain input only)
   const bool grad = g_out != nullptr;
   if (!grad && from_pos) return fail(RID_EUNSUPPORTED, "energy-only path takes the encoding");
-  auto kern = !grad    ? mlp_kernel<P, NP, RT, NW, LM, false, false>
-              : from_pos ? mlp_kernel<P, NP, RT, NW, LM, true, true>
-                         : mlp_kernel<P, NP, RT, NW, LM, false, true>;
+  auto kern = !grad    ? mlp_kernel<P, NP, RT, NW, LM, false, false, RES>
+              : from_pos ? mlp_kernel<P, NP, RT, NW, LM, true, true, RES>
+                         : mlp_kernel<P, NP, RT, NW, LM, false, true, RES>;
   const int ki = grad ? (from_pos ? 1 : 0) : 2;
   if (lds > 64 * 1024 && lds > attr_bytes[ki]) {
     RID_HIP(hipFuncSetAttribute((const void*)kern,
@@ -1633,6 +1656,18 @@ rid_status launch_16bit(const rid_ensemble_impl& e, const float* x, int B,
 
 rid_status dispatch(const rid_ensemble_impl& e, const float* x, int B, float* A_out,
                     float* g_out, const TorsionInput* t, hipStream_t st) {
+  if (e.resnet) {
+    // residual connections: FP32, 16-walker tiles
+    if (e.prec != RID_FP32)
+      return fail(RID_EUNSUPPORTED, "residual connections need an FP32 ensemble");
+    switch (e.NP) {
+      case 64:  return run_mlp<F32, 64, 1, 1, 6, true>(e, x, B, A_out, g_out, t, st);
+      case 128: return run_mlp<F32, 128, 1, 2, 6, true>(e, x, B, A_out, g_out, t, st);
+      case 256: return run_mlp<F32, 256, 1, RID_F32_NW256, 6, true>(e, x, B, A_out, g_out, t, st);
+      case 512: return run_mlp<F32, 512, 1, 8, 6, true>(e, x, B, A_out, g_out, t, st);
+    }
+    return fail(RID_EUNSUPPORTED, "no kernel for this padded width");
+  }
   if (e.prec == RID_FP32) {
     switch (e.NP) {
       case 64:  return run_mlp<F32, 64, 1, 1, 6>(e, x, B, A_out, g_out, t, st);

@@ -139,6 +139,7 @@ struct rid_ensemble_impl {
   int64_t step = 0;
   float drop_p = 0.f;                  // training-time dropout rate of the hidden activations
   unsigned long long drop_seed = 0;
+  bool resnet = false;                 // residual connections between hidden layers 2..L
   // kernel-layout parameters
   std::vector<LayerDev> layers;
   size_t frag_bytes_per_model = 0;

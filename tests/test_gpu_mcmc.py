@@ -28,11 +28,15 @@ def rid():
     return r
 
 
-def _ensemble(rid, n=38, widths=(64, 64), K=4, prec=0, bias_std=0.1, seed=1000):
+def _ensemble(rid, n=38, widths=(64, 64), K=4, prec=0, bias_std=0.1, seed=1000, resnet=False):
     widths = list(widths)
     params = ridgen.xavier_ensemble(2 * n, widths, K, seed, bias_std)
-    return (rid.Ensemble(n, widths, K, params, prec),
-            ridgen.unpack_params(params, 2 * n, widths, K))
+    E = rid.Ensemble(n, widths, K, params, prec)
+    models = ridgen.unpack_params(params, 2 * n, widths, K)
+    if resnet:
+        E.set_resnet(True)
+        models = [m + (True,) for m in models]
+    return E, models
 
 
 def _wrapped(a, b):
@@ -61,13 +65,15 @@ def test_infinite_temperature_walk_matches_the_generator(torch, rid):
 # ensemble; kT = 0.01 kJ/mol rejects about half of them
 # The second case is the headline ensemble at 2048 walkers, where the free
 # energies come from 32-walker tiles (the energy-only kernel's large-batch form).
-@pytest.mark.parametrize("kT,widths,W,T", [(KT_300K, (128, 128), 256, 25),
-                                           (0.01, (128, 128), 256, 25),
-                                           (0.01, (256, 256, 256, 256), 2048, 8)])
-def test_metropolis_decisions_step_by_step(torch, rid, kT, widths, W, T):
+# The last case runs the residual network form (energy-only residual kernel).
+@pytest.mark.parametrize("kT,widths,W,T,resnet", [(KT_300K, (128, 128), 256, 25, False),
+                                                  (0.01, (128, 128), 256, 25, False),
+                                                  (0.01, (256, 256, 256, 256), 2048, 8, False),
+                                                  (0.01, (128, 128, 128), 256, 25, True)])
+def test_metropolis_decisions_step_by_step(torch, rid, kT, widths, W, T, resnet):
     # one call per step; a walker may only leave the oracle's chain at a step
     # whose acceptance margin |ln u_n + dAbar/kT| is at rounding level
-    E, models = _ensemble(rid, widths=widths, K=4)
+    E, models = _ensemble(rid, widths=widths, K=4, resnet=resnet)
     step, seed, n = 0.35, 77, 38
     s0 = ridgen.f32(ridgen.torus_samples(W, n, 5))
     ref = O.mcmc_run(models, s0.astype(np.float64), T, kT, step, seed, nbins=31,
