@@ -19,8 +19,16 @@ Functions and what pins them (tests/test_oracle_*.py):
   dihedral_jacobian   ds/dr (chain rule the bias uses to reach atoms)
                       pinned: central finite differences, zero net force and
                       torque per dihedral
-  embed               [cos s | sin s] periodic input encoding
-                      pinned: 2pi periodicity of every downstream output
+  embed               [cos s | sin s] periodic input encoding; with an
+                      angular mask, non-angular CVs as (s, 0)
+                      pinned: 2pi periodicity of every downstream output;
+                      mixed: linear-model closed form, FD in s
+  distance_cv, cv_values, distance_jacobian
+                      distance CVs and mixed CV tables ("CV selection",
+                      `distance` type, `angular_mask`)
+                      pinned: closed-form geometry, FD of the Jacobian,
+                      zero net force and torque of a pair force, FD of the
+                      whole mixed bias path
   mlp_value_and_grad  free-energy MLP A(x) and dA/dx ("Training phase":
                       MLP of `neurons` widths, tanh; optional residual
                       connections, the `resnet` setting)
@@ -126,6 +134,62 @@ def dihedral(pos, quads):
     return np.arctan2(Y, X)
 
 
+def distance_cv(pos, pairs):
+    """Distance CV s = |r_b - r_a| of each atom pair (a, b), per walker (the
+    `distance` CV type of "CV selection").  pairs: [n][2] -> s [B][n]."""
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.asarray(pairs, dtype=np.int64)
+    return np.linalg.norm(pos[:, q[:, 1]] - pos[:, q[:, 0]], axis=-1)
+
+
+def distance_jacobian(pos, pairs):
+    """ds/dr of each distance CV: slot a gets (r_a - r_b)/s, slot b its
+    negative; a pair closer than sqrt(DEGENERATE_TOL) gets zeros.
+    Returns [B][n][2][3]."""
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.asarray(pairs, dtype=np.int64)
+    d = pos[:, q[:, 0]] - pos[:, q[:, 1]]
+    r2 = np.sum(d * d, axis=-1, keepdims=True)
+    u = d / np.sqrt(np.where(r2 < DEGENERATE_TOL, 1.0, r2))
+    u = np.where(r2 < DEGENERATE_TOL, 0.0, u)
+    return np.stack([u, -u], axis=2)
+
+
+def _split_cvs(cvs, mask):
+    """Rows of a mixed CV table: torsion quads where mask is 1, atom pairs
+    (a, b, -1, -1) where it is 0.  Returns (mask bool [n], quads of the
+    angular rows, pairs of the others)."""
+    q = np.asarray(cvs, dtype=np.int64)
+    m = np.ones(q.shape[0], bool) if mask is None else np.asarray(mask).astype(bool)
+    return m, q[m], q[~m][:, :2]
+
+
+def cv_values(pos, cvs, mask=None):
+    """CV values of a mixed table (torsions where mask is 1, distances where
+    it is 0), in table order.  [B][n]."""
+    m, quads, pairs = _split_cvs(cvs, mask)
+    pos = np.asarray(pos, dtype=np.float64)
+    s = np.zeros((pos.shape[0], m.size))
+    if quads.size:
+        s[:, m] = dihedral(pos, quads)
+    if pairs.size:
+        s[:, ~m] = distance_cv(pos, pairs)
+    return s
+
+
+def cv_degenerate(pos, cvs, mask=None):
+    """[B][n] bool: torsions as ``degenerate``; pairs closer than
+    sqrt(DEGENERATE_TOL)."""
+    m, quads, pairs = _split_cvs(cvs, mask)
+    pos = np.asarray(pos, dtype=np.float64)
+    out = np.zeros((pos.shape[0], m.size), bool)
+    if quads.size:
+        out[:, m] = degenerate(pos, quads)
+    if pairs.size:
+        out[:, ~m] = distance_cv(pos, pairs) ** 2 < DEGENERATE_TOL
+    return out
+
+
 def degenerate(pos, quads, tol=DEGENERATE_TOL):
     """[B][n] bool: dihedral whose |n1|^2 or |n2|^2 is below ``tol``."""
     ra, rb, rc, rd = _gather(pos, quads)
@@ -166,27 +230,46 @@ def dihedral_jacobian(pos, quads):
     return np.where(bad[..., None], 0.0, J)
 
 
-def apply_cv_force(pos, quads, fcv, n_atoms=None):
-    """Atomic forces F_a = sum_i f_i ds_i/dr_a.  fcv: [B][n] -> [B][N][3]."""
+def apply_cv_force(pos, quads, fcv, n_atoms=None, mask=None):
+    """Atomic forces F_a = sum_i f_i ds_i/dr_a.  fcv: [B][n] -> [B][N][3].
+    With a mask, rows where it is 0 are distance pairs (a, b, -1, -1)."""
     pos = np.asarray(pos, dtype=np.float64)
     B, N, _ = pos.shape
-    J = dihedral_jacobian(pos, quads)
+    m, quads_a, pairs = _split_cvs(quads, mask)
+    Ja = dihedral_jacobian(pos, quads_a) if quads_a.size else None
+    Jd = distance_jacobian(pos, pairs) if pairs.size else None
+    ia = np.cumsum(m) - 1             # row -> index among torsions / pairs
+    idd = np.cumsum(~m) - 1
     F = np.zeros((B, N if n_atoms is None else n_atoms, 3))
     q = np.asarray(quads, dtype=np.int64)
     f = np.asarray(fcv, dtype=np.float64)
     for i in range(q.shape[0]):          # plain accumulation, CV by CV
-        for slot in range(4):
-            F[:, q[i, slot]] += f[:, i, None] * J[:, i, slot]
+        if m[i]:
+            for slot in range(4):
+                F[:, q[i, slot]] += f[:, i, None] * Ja[:, ia[i], slot]
+        else:
+            for slot in range(2):
+                F[:, q[i, slot]] += f[:, i, None] * Jd[:, idd[i], slot]
     return F
 
 
 # --------------------------------------------------------------------------
 # a2/a3: ensemble of MLP free-energy models
 # --------------------------------------------------------------------------
-def embed(s):
-    """Periodic input encoding x = [cos s_1..cos s_n | sin s_1..sin s_n]."""
+def embed(s, mask=None):
+    """Periodic input encoding x = [cos s_1..cos s_n | sin s_1..sin s_n].
+
+    With an angular mask (the `angular_mask` setting of "CV selection"), a
+    CV whose entry is 0 is not periodic and enters raw.  Reading: it fills
+    its own two slots as (s_i, 0), so x = [c | t] with (c_i, t_i) =
+    (cos s_i, sin s_i) for angular CVs and (s_i, 0) for the others."""
     s = np.asarray(s, dtype=np.float64)
-    return np.concatenate([np.cos(s), np.sin(s)], axis=-1)
+    if mask is None:
+        return np.concatenate([np.cos(s), np.sin(s)], axis=-1)
+    m = np.asarray(mask).astype(bool)
+    c = np.where(m, np.cos(s), s)
+    t = np.where(m, np.sin(s), 0.0)
+    return np.concatenate([c, t], axis=-1)
 
 
 def is_resnet(model):
@@ -243,23 +326,27 @@ def mlp_value_and_grad(model, x, scales=None):
     return A, u
 
 
-def mean_force_from_input_grad(s, u0):
-    """Chain dA/dx to the angles: g_i = -sin s_i u0[i] + cos s_i u0[n+i]."""
+def mean_force_from_input_grad(s, u0, mask=None):
+    """Chain dA/dx to the angles: g_i = -sin s_i u0[i] + cos s_i u0[n+i];
+    a non-angular CV (mask 0, encoded (s_i, 0)) gets g_i = u0[i]."""
     s = np.asarray(s, dtype=np.float64)
     n = s.shape[-1]
-    return -np.sin(s) * u0[..., :n] + np.cos(s) * u0[..., n:]
+    g = -np.sin(s) * u0[..., :n] + np.cos(s) * u0[..., n:]
+    if mask is None:
+        return g
+    return np.where(np.asarray(mask).astype(bool), g, u0[..., :n])
 
 
-def ensemble_mean_force(models, s):
+def ensemble_mean_force(models, s, mask=None):
     """Per-model free energy and mean force (Box 2: F(s) = grad_s A(s)).
 
-    s: [B][n] -> (A [B][K], g [B][K][n])."""
-    x = embed(s)
+    s: [B][n] -> (A [B][K], g [B][K][n]).  mask: angular mask (see embed)."""
+    x = embed(s, mask)
     As, gs = [], []
     for m in models:
         A, u0 = mlp_value_and_grad(m, x)
         As.append(A)
-        gs.append(mean_force_from_input_grad(s, u0))
+        gs.append(mean_force_from_input_grad(s, u0, mask))
     return np.stack(As, axis=1), np.stack(gs, axis=1)
 
 
@@ -298,7 +385,7 @@ def switch(eps, eps0, eps1):
     return sigma, regime
 
 
-def bias_force(pos, quads, models, eps0, eps1, n_atoms=None):
+def bias_force(pos, quads, models, eps0, eps1, n_atoms=None, mask=None):
     """Whole bias path for a batch of walkers.
 
     Bias energy E = -sigma(eps) * Abar (the inverted predicted PMF, only where
@@ -306,23 +393,25 @@ def bias_force(pos, quads, models, eps0, eps1, n_atoms=None):
     step); atomic force F_a = sum_i f_i ds_i/dr_a.
 
     Returns dict(F [B][N][3], E [B], eps [B], sigma [B], regime [B], s [B][n],
-    A [B][K], g [B][K][n], gbar [B][n], flags [B])."""
-    s = dihedral(pos, quads)
-    A, g = ensemble_mean_force(models, s)
+    A [B][K], g [B][K][n], gbar [B][n], flags [B]).
+    With a mask, rows of ``quads`` where it is 0 are distance CVs (atom
+    pairs (a, b, -1, -1)) that enter the networks raw (see embed)."""
+    s = cv_values(pos, quads, mask)
+    A, g = ensemble_mean_force(models, s, mask)
     gbar, eps = model_deviation(g)
     sigma, regime = switch(eps, eps0, eps1)
     E = -sigma * np.mean(A, axis=1)
     fcv = sigma[:, None] * gbar
-    F = apply_cv_force(pos, quads, fcv, n_atoms)
-    flags = np.any(degenerate(pos, quads), axis=1).astype(np.uint8)
+    F = apply_cv_force(pos, quads, fcv, n_atoms, mask)
+    flags = np.any(cv_degenerate(pos, quads, mask), axis=1).astype(np.uint8)
     return dict(F=F, E=E, eps=eps, sigma=sigma, regime=regime, s=s, A=A, g=g,
                 gbar=gbar, flags=flags)
 
 
-def bias_energy_frozen(pos, quads, models, sigma):
+def bias_energy_frozen(pos, quads, models, sigma, mask=None):
     """E(r) = -sigma Abar(s(r)) with sigma given (finite-difference target)."""
-    s = dihedral(pos, quads)
-    A, _ = ensemble_mean_force(models, s)
+    s = cv_values(pos, quads, mask)
+    A, _ = ensemble_mean_force(models, s, mask)
     return -np.asarray(sigma) * np.mean(A, axis=1)
 
 

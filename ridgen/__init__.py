@@ -89,6 +89,27 @@ def chain_system(n_res: int, apr: int, n_extra: int = 0) -> ChainSystem:
     return ChainSystem(n_res, apr, n_extra, q, np.ones(len(q), np.uint8))
 
 
+def with_distances(sys_: ChainSystem, n_dist: int, stride: int = 3,
+                   every: int = 4) -> ChainSystem:
+    """The chain's torsion table with n_dist distance CVs CA_r - CA_{r+stride}
+    (r = 0, 1, ...) interleaved: one distance row after every ``every``
+    torsion rows, the rest at the end.  Distance rows are (a, b, -1, -1)
+    with angular mask 0."""
+    ca = [r * sys_.apr + 2 for r in range(sys_.n_res)]
+    pairs = [(ca[r], ca[r + stride]) for r in range(sys_.n_res - stride)][:n_dist]
+    if len(pairs) < n_dist:
+        raise ValueError("chain too short for that many distances")
+    rows, mask, d = [], [], 0
+    for i, q in enumerate(sys_.quads):
+        rows.append(tuple(int(v) for v in q)); mask.append(1)
+        if (i + 1) % every == 0 and d < n_dist:
+            rows.append((pairs[d][0], pairs[d][1], -1, -1)); mask.append(0); d += 1
+    for a, b in pairs[d:]:
+        rows.append((a, b, -1, -1)); mask.append(0)
+    return ChainSystem(sys_.n_res, sys_.apr, sys_.n_extra, np.asarray(rows, np.int32),
+                       np.asarray(mask, np.uint8))
+
+
 # Shapes of the workloads (atoms per residue chosen so the totals match).
 def system_dipeptide() -> ChainSystem:      # 2 torsions, 22 atoms
     return chain_system(2, 11)
