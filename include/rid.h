@@ -72,10 +72,14 @@ const char* rid_version(void);
  *               each torsion; the torsion is
  *               s = atan2(|b2| b1.(b2 x b3), (b1 x b2).(b2 x b3)) with
  *               b1 = r_b - r_a, b2 = r_c - r_b, b3 = r_d - r_c, in (-pi, pi].
- * angular_mask  host uint8 [n_cv] or NULL (= all 1).  The torsion path
- *               needs every entry 1 (RID_EUNSUPPORTED otherwise).
+ * angular_mask  host uint8 [n_cv] or NULL (= all 1).  A row whose entry is
+ *               0 is a distance CV (the `distance` type of "CV selection"):
+ *               quads[i] = (a, b, -1, -1), s = |r_b - r_a| (nm), not
+ *               periodic; a pair closer than 1e-6 nm is degenerate (s = 0,
+ *               no force, the walker's flag set).
  * Errors        RID_EINVAL for n_atoms < 1, n_cv < 1, an index outside
- *               [0, n_atoms) or a quad that repeats an atom.
+ *               [0, n_atoms), a row that repeats an atom, a distance row
+ *               not ending in -1, -1, or a mask entry other than 0 or 1.
  * ------------------------------------------------------------------------ */
 rid_status rid_system_create(int n_atoms, int n_cv, const int32_t* quads,
                              const uint8_t* angular_mask, rid_system* out);
@@ -132,10 +136,23 @@ rid_status rid_ensemble_set_dropout(rid_ensemble ens, float rate, uint64_t seed)
  * RID_EUNSUPPORTED while it is on.  Errors: RID_EINVAL (NULL, hidden widths
  * not all equal), RID_EUNSUPPORTED (BF16/FP16 ensemble). */
 rid_status rid_ensemble_set_resnet(rid_ensemble ens, int enable);
+/* rid_ensemble_set_angular_mask - which network inputs are periodic (the
+ * `angular_mask` setting of "CV selection").  angular_mask: host uint8
+ * [n_cv] or NULL (= all 1).  An angular CV enters as (cos s, sin s) in
+ * input slots (i, n_cv + i); a CV whose entry is 0 enters raw, as (s, 0) in
+ * the same two slots (input width and packed parameters unchanged), and its
+ * mean force is dA/dx_i.  rid_model_dev encodes its CVs with the mask;
+ * rid_bias_force and the server need the system's distance rows to be the
+ * ensemble's raw CVs (RID_EINVAL otherwise).  While any entry is 0,
+ * rid_mcmc_run, rid_select, rid_bias_force_conservative and the training
+ * calls return RID_EUNSUPPORTED.  Synchronizes the device.  Errors:
+ * RID_EINVAL (NULL ensemble, an entry other than 0 or 1), RID_ENOMEM. */
+rid_status rid_ensemble_set_angular_mask(rid_ensemble ens, const uint8_t* angular_mask);
 void rid_ensemble_destroy(rid_ensemble ens);
 
 /* ------------------------------------------------------------------------
- * rid_cv_eval - torsion CVs of B walkers ("CV selection").
+ * rid_cv_eval - CVs of B walkers ("CV selection"): torsions, and distances
+ * for the system's distance rows (x = (s, 0) for those).
  *   d_pos  [B][n_atoms][3]   atom positions (whole molecules, no PBC)
  *   d_s    [B][n_cv]         torsions in (-pi, pi]
  *   d_x    [B][2 n_cv] or NULL: [cos s | sin s], computed from the geometry

@@ -29,7 +29,7 @@ EXPORTS = (
     "rid_last_error", "rid_version", "rid_system_create", "rid_system_destroy",
     "rid_packed_param_count", "rid_ensemble_create", "rid_ensemble_get_params",
     "rid_ensemble_set_params", "rid_ensemble_step", "rid_ensemble_set_dropout",
-    "rid_ensemble_set_resnet",
+    "rid_ensemble_set_resnet", "rid_ensemble_set_angular_mask",
     "rid_ensemble_destroy",
     "rid_cv_eval", "rid_model_dev", "rid_cluster_frames", "rid_select", "rid_bias_force",
     "rid_bias_force_conservative", "rid_mcmc_run",
@@ -85,6 +85,7 @@ def lib():
         "rid_ensemble_step": (i64, [vp]),
         "rid_ensemble_set_dropout": (i, [vp, f, ctypes.c_uint64]),
         "rid_ensemble_set_resnet": (i, [vp, i]),
+        "rid_ensemble_set_angular_mask": (i, [vp, vp]),
         "rid_ensemble_destroy": (None, [vp]),
         "rid_cv_eval": (i, [vp, vp, i, vp, vp, vp]),
         "rid_model_dev": (i, [vp, vp, i, vp, vp, vp, vp, vp]),
@@ -155,7 +156,8 @@ def _f32(t, shape, name):
 
 
 class System:
-    """Atoms and torsion CVs (rid_system_create)."""
+    """Atoms and CVs (rid_system_create): torsion rows (a, b, c, d) and,
+    where angular_mask is 0, distance rows (a, b, -1, -1)."""
 
     def __init__(self, n_atoms: int, quads, angular_mask=None):
         q = np.ascontiguousarray(np.asarray(quads, dtype=np.int32))
@@ -223,6 +225,17 @@ class Ensemble:
         """rid_ensemble_set_resnet: residual connections between the hidden
         layers after the first (hidden widths must be equal; FP32 only)."""
         _check(lib().rid_ensemble_set_resnet(self.handle, 1 if enable else 0))
+
+    def set_angular_mask(self, angular_mask=None):
+        """rid_ensemble_set_angular_mask: CVs whose entry is 0 enter the
+        networks raw, as (s, 0); None makes every CV angular again."""
+        if angular_mask is None:
+            _check(lib().rid_ensemble_set_angular_mask(self.handle, None))
+            return
+        m = np.ascontiguousarray(np.asarray(angular_mask, dtype=np.uint8))
+        if m.shape != (self.n_cv,):
+            raise ValueError("angular_mask must be [n_cv]")
+        _check(lib().rid_ensemble_set_angular_mask(self.handle, m.ctypes.data_as(ctypes.c_void_p)))
 
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:

@@ -124,6 +124,7 @@ static void free_ensemble(rid_ensemble_impl& e) {
   dev_free(e.d_bias);
   dev_free(e.d_wo);
   dev_free(e.d_bo);
+  dev_free(e.d_raw);
   e.ws_x.release();
   e.ws_A.release();
   e.ws_g.release();
@@ -147,18 +148,25 @@ rid_status rid_system_create(int n_atoms, int n_cv, const int32_t* quads,
   *out = nullptr;
   if (n_atoms < 1 || n_cv < 1 || !quads)
     return fail(RID_EINVAL, "need n_atoms >= 1, n_cv >= 1 and a quad table");
-  if (n_cv > 256) return fail(RID_EUNSUPPORTED, "at most 256 torsion CVs");
+  if (n_cv > 256) return fail(RID_EUNSUPPORTED, "at most 256 CVs");
   for (int i = 0; i < n_cv; ++i) {
+    if (angular_mask && angular_mask[i] > 1)
+      return fail(RID_EINVAL, "angular_mask entries must be 0 or 1");
+    // a torsion row names 4 atoms; a distance row (mask 0) names 2, then -1, -1
+    const int na = (angular_mask && angular_mask[i] == 0) ? 2 : 4;
     for (int j = 0; j < 4; ++j) {
       const int a = quads[4 * i + j];
+      if (j >= na) {
+        if (a != -1)
+          return fail(RID_EINVAL, "distance row " + std::to_string(i) + " must end in -1, -1");
+        continue;
+      }
       if (a < 0 || a >= n_atoms)
         return fail(RID_EINVAL, "quad " + std::to_string(i) + " has an atom index out of range");
       for (int j2 = 0; j2 < j; ++j2)
         if (quads[4 * i + j2] == a)
           return fail(RID_EINVAL, "quad " + std::to_string(i) + " repeats an atom");
     }
-    if (angular_mask && angular_mask[i] != 1)
-      return fail(RID_EUNSUPPORTED, "torsion CVs must be periodic (angular_mask 1)");
   }
   rid_system_s* h = new (std::nothrow) rid_system_s();
   if (!h) return fail(RID_ENOMEM, "host allocation failed");
@@ -166,23 +174,38 @@ rid_status rid_system_create(int n_atoms, int n_cv, const int32_t* quads,
   s.n_atoms = n_atoms;
   s.n_cv = n_cv;
   s.quads.assign(quads, quads + 4 * (size_t)n_cv);
-  s.uniq = s.quads;
+  s.mask.assign(n_cv, 1);
+  for (int i = 0; i < n_cv; ++i)
+    if (angular_mask && angular_mask[i] == 0) {
+      s.mask[i] = 0;
+      s.has_dist = true;
+    }
+  s.uniq.clear();
+  for (int32_t a : s.quads)
+    if (a >= 0) s.uniq.push_back(a);
   std::sort(s.uniq.begin(), s.uniq.end());
   s.uniq.erase(std::unique(s.uniq.begin(), s.uniq.end()), s.uniq.end());
   s.n_uniq = (int)s.uniq.size();
   std::vector<int32_t> atom_local(n_atoms, -1);
   for (int u = 0; u < s.n_uniq; ++u) atom_local[s.uniq[u]] = u;
+  // local indices; the -1 slots of distance rows stay -1 (the kernels'
+  // marker of a distance CV)
   std::vector<int32_t> lq(4 * (size_t)n_cv);
-  for (size_t e = 0; e < lq.size(); ++e) lq[e] = atom_local[s.quads[e]];
-  // CSR inverse map in (cv, slot) order
-  std::vector<int32_t> ptr(s.n_uniq + 1, 0), ent(4 * (size_t)n_cv);
-  for (size_t e = 0; e < lq.size(); ++e) ptr[lq[e] + 1]++;
+  for (size_t e = 0; e < lq.size(); ++e) lq[e] = s.quads[e] >= 0 ? atom_local[s.quads[e]] : -1;
+  // CSR inverse map in (cv, slot) order over the rows' atoms.  The entry
+  // array keeps 4 n_cv slots whatever the rows (the kernels copy the tables
+  // with that layout); a distance row leaves two of them unused at the end,
+  // past csr_ptr[n_uniq].
+  std::vector<int32_t> ptr(s.n_uniq + 1, 0), ent(4 * (size_t)n_cv, 0);
+  for (size_t e = 0; e < lq.size(); ++e)
+    if (lq[e] >= 0) ptr[lq[e] + 1]++;
   for (int u = 0; u < s.n_uniq; ++u) {
     s.max_deg = std::max(s.max_deg, ptr[u + 1]);
     ptr[u + 1] += ptr[u];
   }
   std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
-  for (size_t e = 0; e < lq.size(); ++e) ent[fill[lq[e]]++] = (int32_t)e;
+  for (size_t e = 0; e < lq.size(); ++e)
+    if (lq[e] >= 0) ent[fill[lq[e]]++] = (int32_t)e;
   // one allocation: uniq | lquads | csr_ptr | csr_ent | atom_local
   std::vector<int32_t> tab;
   tab.reserve(s.uniq.size() + lq.size() + ptr.size() + ent.size() + atom_local.size());
@@ -335,6 +358,30 @@ rid_status rid_ensemble_set_dropout(rid_ensemble ens, float rate, uint64_t seed)
   return RID_OK;
 }
 
+rid_status rid_ensemble_set_angular_mask(rid_ensemble ens, const uint8_t* angular_mask) {
+  if (!ens) return fail(RID_EINVAL, "NULL argument");
+  rid_ensemble_impl& e = ens->impl;
+  std::vector<uint8_t> raw;
+  bool any = false;
+  if (angular_mask) {
+    raw.resize(e.n_cv);
+    for (int i = 0; i < e.n_cv; ++i) {
+      if (angular_mask[i] > 1) return fail(RID_EINVAL, "angular_mask entries must be 0 or 1");
+      raw[i] = angular_mask[i] == 0;
+      any = any || raw[i];
+    }
+  }
+  RID_HIP(hipDeviceSynchronize());   // calls in flight may still read the old mask
+  dev_free(e.d_raw);
+  e.raw.clear();
+  if (!any) return RID_OK;
+  rid_status st = dev_alloc(&e.d_raw, (size_t)e.n_cv);
+  if (st != RID_OK) return st;
+  RID_HIP(hipMemcpy(e.d_raw, raw.data(), (size_t)e.n_cv, hipMemcpyHostToDevice));
+  e.raw = raw;
+  return RID_OK;
+}
+
 rid_status rid_ensemble_set_resnet(rid_ensemble ens, int enable) {
   if (!ens) return fail(RID_EINVAL, "NULL argument");
   const rid_ensemble_impl& e = ens->impl;
@@ -374,7 +421,7 @@ rid_status rid_model_dev(rid_ensemble ens, const float* d_s, int B, float* d_eps
   if ((r = e.ws_x.ensure(sizeof(float) * 2 * e.n_cv * (size_t)B)) != RID_OK) return r;
   if ((r = e.ws_A.ensure(sizeof(float) * e.K * (size_t)B)) != RID_OK) return r;
   if ((r = e.ws_g.ensure(sizeof(float) * e.K * (size_t)B * e.n_cv)) != RID_OK) return r;
-  if ((r = launch_embed(d_s, B, e.n_cv, e.ws_x.as<float>(), st)) != RID_OK) return r;
+  if ((r = launch_embed(d_s, B, e.n_cv, e.d_raw, e.ws_x.as<float>(), st)) != RID_OK) return r;
   if (e.frag_dirty) {
     if ((r = pack_ensemble_weights(e, st)) != RID_OK) return r;
     e.frag_dirty = false;
@@ -412,6 +459,8 @@ rid_status rid_select(rid_ensemble ens, const float* d_s, int B, float eps0, flo
     return fail(RID_EINVAL, "threshold must be positive and finite");
   if (lower < 1 || upper < lower) return fail(RID_EINVAL, "need 1 <= lower <= upper");
   if (max_selection < 1) return fail(RID_EINVAL, "max_selection must be >= 1");
+  if (!ens->impl.raw.empty())
+    return fail(RID_EUNSUPPORTED, "selection clusters periodic CVs only (angular mask all 1)");
   rid_status r = rid_model_dev(ens, d_s, B, d_eps, nullptr, nullptr, nullptr, stream);
   if (r != RID_OK) return r;
   const int cap = std::max(upper, max_selection) + 1;
@@ -439,6 +488,8 @@ rid_status rid_bias_force(rid_system sys, rid_ensemble ens, const float* d_pos,
   rid_system_impl& s = sys->impl;
   rid_ensemble_impl& e = ens->impl;
   if (s.n_cv != e.n_cv) return fail(RID_EINVAL, "system and ensemble disagree on n_cv");
+  if (!cv_kinds_match(s, e))
+    return fail(RID_EINVAL, "the ensemble's angular mask does not match the system's CV kinds");
   const hipStream_t st = (hipStream_t)stream;
   rid_status r;
   if ((r = e.ws_A.ensure(sizeof(float) * e.K * (size_t)B)) != RID_OK) return r;
@@ -475,6 +526,8 @@ rid_status rid_bias_force_conservative(rid_system sys, rid_ensemble ens,
     return fail(RID_EINVAL, "trust levels need 0 <= eps0 < eps1");
   if (sys->impl.n_cv != ens->impl.n_cv)
     return fail(RID_EINVAL, "system and ensemble disagree on n_cv");
+  if (sys->impl.has_dist || !ens->impl.raw.empty())
+    return fail(RID_EUNSUPPORTED, "conservative switching is built for torsion CVs");
   return launch_bias_conservative(sys->impl, ens->impl, d_pos, B, eps0, eps1, d_force,
                                   d_energy, d_eps, d_sigma, d_flags, (hipStream_t)stream);
 }
@@ -489,6 +542,8 @@ rid_status rid_mcmc_run(rid_ensemble ens, float* d_s, int W, int64_t n_steps,
   if (!(step_size > 0.f) || step_size > 3.14159265358979f)
     return fail(RID_EINVAL, "step_size must be in (0, pi]");
   const int n = ens->impl.n_cv;
+  if (!ens->impl.raw.empty())
+    return fail(RID_EUNSUPPORTED, "the MCMC walks on the torus (angular mask all 1)");
   if (nbins < 1 || proj0 < 0 || proj0 >= n || proj1 < 0 || proj1 >= n)
     return fail(RID_EINVAL, "need nbins >= 1 and projected indices in [0, n_cv)");
   return launch_mcmc(ens->impl, d_s, W, n_steps, step0, kT, step_size, seed, proj0, proj1,

@@ -1,8 +1,9 @@
 // Stand-alone kernels of the CV side of the path:
 //
 //  cv_eval_kernel       torsions of each walker ("CV selection": backbone
-//                       phi/psi) and the periodic encoding [cos s | sin s]
-//  embed_kernel         [cos s | sin s] from given CVs
+//                       phi/psi) and the periodic encoding [cos s | sin s];
+//                       distance rows (atom pairs) encoded raw as (s, 0)
+//  embed_kernel         [cos s | sin s] from given CVs (raw ones as (s, 0))
 //  reduce_kernel        ensemble mean force and model deviation (FP64)
 //  scatter_kernel       F_a = sum_i f_i ds_i/dr_a for a given CV force, or the
 //                       full deviation + switch + chain rule tail of the bias
@@ -42,10 +43,18 @@ __global__ __launch_bounds__(kCvWaves * kWave) void cv_eval_kernel(
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   for (int i = lane; i < n; i += kWave) {
-    const Torsion t = torsion(sp, t_lq + 4 * i);
-    float cs, sn;
-    torsion_cos_sin(t, cs, sn);
-    const float sv = t.deg ? 0.f : atan2f(t.Y, t.X);
+    float cs, sn, sv;
+    if (t_lq[4 * i + 2] < 0) {
+      // distance row: s = |r_b - r_a|, encoded raw as (s, 0)
+      const Pair d = pair(sp, t_lq + 4 * i);
+      sv = d.deg ? 0.f : d.r;
+      cs = sv;
+      sn = 0.f;
+    } else {
+      const Torsion t = torsion(sp, t_lq + 4 * i);
+      torsion_cos_sin(t, cs, sn);
+      sv = t.deg ? 0.f : atan2f(t.Y, t.X);
+    }
     if (s) s[(size_t)w * n + i] = sv;
     if (x) {
       x[(size_t)w * 2 * n + i] = cs;
@@ -54,13 +63,18 @@ __global__ __launch_bounds__(kCvWaves * kWave) void cv_eval_kernel(
   }
 }
 
-__global__ void embed_kernel(const float* s, int B, int n, float* x) {
+__global__ void embed_kernel(const float* s, int B, int n, const uint8_t* raw, float* x) {
   const size_t total = (size_t)B * n;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
     const size_t w = e / n, i = e - w * n;
     float sn, cs;
-    sincosf(s[e], &sn, &cs);
+    if (raw && raw[i]) {
+      cs = s[e];
+      sn = 0.f;
+    } else {
+      sincosf(s[e], &sn, &cs);
+    }
     x[w * 2 * n + i] = cs;
     x[w * 2 * n + n + i] = sn;
   }
@@ -212,10 +226,11 @@ rid_status launch_cv_eval(const rid_system_impl& s, const float* pos, int B,
   return RID_OK;
 }
 
-rid_status launch_embed(const float* s, int B, int n, float* x, hipStream_t st) {
+rid_status launch_embed(const float* s, int B, int n, const uint8_t* raw, float* x,
+                        hipStream_t st) {
   const size_t total = (size_t)B * n;
   const int grid = (int)std::min<size_t>((total + 255) / 256, 8192);
-  launch_timed(kProfEmbed, embed_kernel, dim3(grid), dim3(256), 0, st, s, B, n, x);
+  launch_timed(kProfEmbed, embed_kernel, dim3(grid), dim3(256), 0, st, s, B, n, raw, x);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }

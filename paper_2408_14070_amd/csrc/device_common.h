@@ -90,6 +90,23 @@ __device__ inline Torsion torsion(const float* sp, const int* q) {
   return t;
 }
 
+// Distance CV of pair row q (q[0], q[1]; q[2] = q[3] = -1 mark the row):
+// s = |r_b - r_a|; degenerate (direction undefined) below sqrt(kDegTol).
+struct Pair {
+  V3 d;        // r_a - r_b
+  float r;
+  bool deg;
+};
+
+__device__ inline Pair pair(const float* sp, const int* q) {
+  Pair p;
+  p.d = sub(ld3(sp, q[0]), ld3(sp, q[1]));
+  const float r2 = dot(p.d, p.d);
+  p.deg = !(r2 >= kDegTol);
+  p.r = sqrtf(r2);
+  return p;
+}
+
 // cos s, sin s straight from the geometry (degenerate: s = 0).
 __device__ inline void torsion_cos_sin(const Torsion& t, float& cs, float& sn) {
   if (t.deg) {
@@ -192,8 +209,22 @@ __device__ inline void scatter_forces(const SysView& sv, const float* sp, const 
   const int U = sv.U, n = sv.n;
   bool deg_any = false;
   for (int i = lane; i < n; i += kWave) {
-    const Torsion t = torsion(sp, sv.lq + 4 * i);
     float* c = ct + 12 * i;
+    if (sv.lq[4 * i + 2] < 0) {
+      // distance row: ds/dr_a = (r_a - r_b)/s, ds/dr_b the negative (its
+      // CSR entries name slots 0 and 1 only)
+      const Pair d = pair(sp, sv.lq + 4 * i);
+      if (d.deg) {
+        deg_any = true;
+        for (int j = 0; j < 6; ++j) c[j] = 0.f;
+        continue;
+      }
+      const float f = sig * fc[i] / d.r;
+      c[0] = f * d.d.x; c[1] = f * d.d.y; c[2] = f * d.d.z;
+      c[3] = -c[0]; c[4] = -c[1]; c[5] = -c[2];
+      continue;
+    }
+    const Torsion t = torsion(sp, sv.lq + 4 * i);
     if (t.deg) {
       deg_any = true;
       for (int j = 0; j < 12; ++j) c[j] = 0.f;

@@ -164,6 +164,9 @@ struct MlpArgs {
   // torsion input (bias path)
   SysView sv;
   const float* pos;    // [B][n_atoms][3]
+  // encoding input: CVs with raw[i] = 1 are non-angular, encoded (s_i, 0),
+  // so dA/ds_i = dA/dx_i (null: every CV angular)
+  const uint8_t* raw;
 };
 
 __device__ inline void map_block(int b, int K, int grp, int& k, int& tile) {
@@ -753,7 +756,10 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       if (row < p.B) {
         const float cs = xs[i * X2 + c];
         const float sn = xs[i * X2 + n + c];
-        const float gv = -sn * u0[i * US + c] + cs * u0[i * US + n + c];
+        float gv = -sn * u0[i * US + c] + cs * u0[i * US + n + c];
+        if constexpr (!FROM_POS) {
+          if (p.raw && p.raw[c]) gv = u0[i * US + c];
+        }
         p.g_out[((size_t)k * p.B + row) * n + c] = gv;
       }
     }
@@ -807,7 +813,10 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
         if (row < p.B) {
           const float cs = xs[i * X2 + c];
           const float sn = xs[i * X2 + n + c];
-          const float gv = -sn * u0_at(i, c) + cs * u0_at(i, n + c);
+          float gv = -sn * u0_at(i, c) + cs * u0_at(i, n + c);
+          if constexpr (!FROM_POS) {
+            if (p.raw && p.raw[c]) gv = u0_at(i, c);
+          }
           p.g_out[((size_t)k * p.B + row) * n + c] = gv;
         }
       }
@@ -1598,6 +1607,7 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
   }
   a.bias = e.d_bias; a.wo = e.d_wo; a.bo = e.d_bo;
   a.A_out = A_out; a.g_out = g_out;
+  a.raw = e.d_raw;
   if (from_pos) {
     const rid_system_impl& s = *tin->sys;
     a.sv = SysView{s.n_atoms, s.n_uniq, s.n_cv, s.d_uniq, s.d_lquads, s.d_csr_ptr,
@@ -1844,6 +1854,9 @@ rid_status launch_train_sweeps(const rid_ensemble_impl& e, const TrainIo& io, in
 
 rid_status launch_mlp_from_pos(const rid_ensemble_impl& e, const TorsionInput& tin,
                                int B, float* A_out, float* g_out, hipStream_t st) {
+  // the in-kernel gather computes torsions only: systems with distance CVs
+  // take the encoding from cv_eval_kernel
+  if (tin.sys->has_dist) return RID_EUNSUPPORTED;
   return dispatch(e, nullptr, B, A_out, g_out, &tin, st);
 }
 

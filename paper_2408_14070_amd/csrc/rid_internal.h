@@ -121,6 +121,8 @@ struct rid_system_impl {
   int32_t* d_csr_ent = nullptr;      // [4 n_cv] entry = cv * 4 + slot
   int32_t* d_atom_local = nullptr;   // [n_atoms] local index or -1
   int max_deg = 0;
+  std::vector<uint8_t> mask;         // [n_cv] 1 = torsion (angular), 0 = distance pair
+  bool has_dist = false;             // any distance row (lquads slots 2, 3 are -1)
 };
 
 struct rid_ensemble_impl {
@@ -140,6 +142,9 @@ struct rid_ensemble_impl {
   float drop_p = 0.f;                  // training-time dropout rate of the hidden activations
   unsigned long long drop_seed = 0;
   bool resnet = false;                 // residual connections between hidden layers 2..L
+  // angular mask of the inputs: CVs with raw[i] = 1 enter as (s_i, 0)
+  std::vector<uint8_t> raw;            // [n_cv] (empty: every CV angular)
+  uint8_t* d_raw = nullptr;            // device copy, or null when no CV is raw
   // kernel-layout parameters
   std::vector<LayerDev> layers;
   size_t frag_bytes_per_model = 0;
@@ -157,7 +162,19 @@ struct rid_ensemble_impl {
 // ---------------------------------------------------------------------------
 rid_status launch_cv_eval(const rid_system_impl& s, const float* pos, int B,
                           float* d_s, float* d_x, hipStream_t st);
-rid_status launch_embed(const float* s, int B, int n, float* x, hipStream_t st);
+// x = [cos s | sin s]; CVs with raw[i] = 1 (raw may be null) as (s_i, 0)
+rid_status launch_embed(const float* s, int B, int n, const uint8_t* raw, float* x,
+                        hipStream_t st);
+// The system's CV kinds must match the ensemble's angular mask (distance rows
+// raw, torsion rows angular).
+inline bool cv_kinds_match(const rid_system_impl& s, const rid_ensemble_impl& e) {
+  for (int i = 0; i < s.n_cv; ++i) {
+    const bool dist = s.has_dist && s.mask[i] == 0;
+    const bool raw = !e.raw.empty() && e.raw[i] != 0;
+    if (dist != raw) return false;
+  }
+  return true;
+}
 // Ensemble MLP fed straight from atom positions (torsions computed in-kernel).
 struct TorsionInput {
   const rid_system_impl* sys;

@@ -332,6 +332,8 @@ rid_status rid_server_register(rid_server srv, rid_system sys, rid_ensemble ens,
   if (!srv || !sys || !ens || !model_id) return fail(RID_EINVAL, "NULL argument");
   if (!(eps0 >= 0.f) || !(eps0 < eps1)) return fail(RID_EINVAL, "trust levels need 0 <= eps0 < eps1");
   if (sys->impl.n_cv != ens->impl.n_cv) return fail(RID_EINVAL, "system and ensemble disagree on n_cv");
+  if (!cv_kinds_match(sys->impl, ens->impl))
+    return fail(RID_EINVAL, "the ensemble's angular mask does not match the system's CV kinds");
   Server& s = srv->s;
   rid_ensemble_impl& e = ens->impl;
   if (e.frag_dirty) {

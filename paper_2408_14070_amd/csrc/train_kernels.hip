@@ -571,6 +571,8 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   const bool input_mode = hvp != nullptr;
   if (input_mode && !rho) return fail(RID_EINVAL, "input mode needs an upstream gradient");
   if (e.resnet) return fail(RID_EUNSUPPORTED, "mean-force training is built for plain MLPs");
+  if (!e.raw.empty())
+    return fail(RID_EUNSUPPORTED, "mean-force training is built for torsion CVs");
   const int K = e.K, L = e.L, n = e.n_cv, X = 2 * n;
   std::vector<int> w(L + 1);
   w[0] = X;

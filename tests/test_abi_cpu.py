@@ -62,9 +62,17 @@ def test_system_create_rejects_bad_quads_on_host():
     assert L.rid_system_create(22, 1, q.ctypes.data_as(ctypes.c_void_p), None,
                                ctypes.byref(h)) == rid.RID_EINVAL
     q = np.array([[0, 1, 2, 3]], np.int32)
-    m = np.array([0], np.uint8)                # non-periodic CV on the torsion path
+    m = np.array([0], np.uint8)                # distance row must be (a, b, -1, -1)
     assert L.rid_system_create(22, 1, q.ctypes.data_as(ctypes.c_void_p),
-                               m.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) == rid.RID_EUNSUPPORTED
+                               m.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) == rid.RID_EINVAL
+    assert b"-1, -1" in L.rid_last_error()
+    q = np.array([[4, 4, -1, -1]], np.int32)   # a pair of one atom
+    assert L.rid_system_create(22, 1, q.ctypes.data_as(ctypes.c_void_p),
+                               m.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) == rid.RID_EINVAL
+    q = np.array([[0, 1, 2, 3]], np.int32)
+    m = np.array([2], np.uint8)                # mask entries are 0 or 1
+    assert L.rid_system_create(22, 1, q.ctypes.data_as(ctypes.c_void_p),
+                               m.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)) == rid.RID_EINVAL
     assert L.rid_system_create(0, 1, q.ctypes.data_as(ctypes.c_void_p), None,
                                ctypes.byref(h)) == rid.RID_EINVAL
 
