@@ -85,7 +85,7 @@ def train_flops_per_sample(n_cv, widths, K):
 def build_case(rid, torch, sys_, B, K, widths, prec, seed=1):
     pos = ridgen.f32(ridgen.chain_coords(sys_, B, seed))
     params = ridgen.xavier_ensemble(2 * sys_.n_cv, widths, K, 1000)
-    S = rid.System(sys_.n_atoms, sys_.quads)
+    S = rid.System(sys_.n_atoms, sys_.quads, sys_.mask)
     E = rid.Ensemble(sys_.n_cv, widths, K, params, prec)
     P = torch.from_numpy(pos).cuda()
     out = dict(
@@ -293,6 +293,44 @@ def bench_precision(rid, torch, sys20, prec, name, steps, warmup):
                      "avg_launch_us": kern["mlp"] * 1e3, "flop_per_launch": fl},
         "kernels_us": {k: v * 1e3 for k, v in kern.items()},
     }
+
+
+def bench_variants(rid, torch, sys20, steps, warmup):
+    """The network and CV variants on the headline shape (1024 walkers,
+    4 x [256 x 4] FP32): residual connections, and a mixed table with 6
+    distance CVs beside the 38 torsions (encoded once by cv_eval)."""
+    B, K, widths = 1024, 4, [256] * 4
+    res = {}
+    c = build_case(rid, torch, sys20, B, K, widths, rid.RID_FP32)
+    c["E"].set_resnet(True)
+    el, kern = time_bias(rid, torch, c, steps, warmup)
+    fl = mlp_flops_per_walker(sys20.n_cv, widths, K) * B
+    ach = fl / (kern["mlp"] * 1e-3) / 1e12
+    res["resnet"] = {
+        "workload": "headline chain and ensemble with residual connections between the "
+                    "hidden layers (h_l = h_{l-1} + tanh(W_l h_{l-1} + b_l), l >= 2)",
+        "value": B * steps / el, "unit": "walker-steps/s", "ms_per_step": 1e3 * el / steps,
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
+                     "avg_launch_us": kern["mlp"] * 1e3, "flop_per_launch": fl},
+        "kernels_us": {k: v * 1e3 for k, v in kern.items()},
+    }
+    mixed = ridgen.with_distances(sys20, 6)
+    c = build_case(rid, torch, mixed, B, K, widths, rid.RID_FP32)
+    c["E"].set_angular_mask(mixed.mask)
+    el, kern = time_bias(rid, torch, c, steps, warmup)
+    fl = mlp_flops_per_walker(mixed.n_cv, widths, K) * B
+    ach = fl / (kern["mlp"] * 1e-3) / 1e12
+    res["distance_cvs"] = {
+        "workload": "headline chain with 6 CA-CA distance CVs among its 38 torsions (44 CVs, "
+                    "angular mask 0 for the distances), headline ensemble shape",
+        "value": B * steps / el, "unit": "walker-steps/s", "ms_per_step": 1e3 * el / steps,
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
+                     "avg_launch_us": kern["mlp"] * 1e3, "flop_per_launch": fl},
+        "kernels_us": {k: v * 1e3 for k, v in kern.items()},
+    }
+    return res
 
 
 def bench_training(rid, torch, steps=20, warmup=3):
@@ -624,6 +662,8 @@ def main():
                                                 steps_b, wb)
         rec["precision_form_fp16"] = bench_precision(rid, torch, sys20, rid.RID_FP16, "FP16",
                                                      steps_b, wb)
+        log("network and CV variants")
+        rec["variants"] = bench_variants(rid, torch, sys20, steps_b, wb)
         log("conservative switching")
         rec["conservative"] = bench_conservative(rid, torch, case)
         log("mcmc")
