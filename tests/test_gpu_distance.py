@@ -8,7 +8,7 @@ import pytest
 
 import ridgen
 from oracle import rid_oracle as O
-from tests.gpu_common import FP32_TOL, assert_forces
+from tests.gpu_common import FP32_TOL, HALF_TOL, assert_forces
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +85,24 @@ def test_mixed_bias_force_parity(torch, rid, widths, K, B, resnet):
     E_ref = ref["E"]
     assert np.max(np.abs(out["E"].cpu().numpy() - E_ref)) <= FP32_TOL * max(1.0, np.abs(E_ref).max())
     assert not out["flags"].cpu().numpy().any()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_mixed_bias_force_16bit(torch, rid, prec):
+    # the 16-bit encoding instances share the raw-CV chain; tolerance of the
+    # 16-bit forms (operand rounding in every GEMM stage)
+    sys_ = _mixed()
+    B, K, widths = 300, 4, [256] * 4
+    pos = ridgen.f32(ridgen.chain_coords(sys_, B, seed=11))
+    params = ridgen.xavier_ensemble(2 * sys_.n_cv, widths, K, 1011, 0.1)
+    S = rid.System(sys_.n_atoms, sys_.quads, sys_.mask)
+    E = rid.Ensemble(sys_.n_cv, widths, K, params, rid.RID_BF16 if prec == "bf16" else rid.RID_FP16)
+    E.set_angular_mask(sys_.mask)
+    models = ridgen.unpack_params(params, 2 * sys_.n_cv, widths, K)
+    ref = O.bias_force(pos.astype(np.float64), sys_.quads, models, 1e9, 2e9, mask=sys_.mask)
+    out = rid.bias_force(S, E, _dev(torch, pos), 1e9, 2e9)
+    torch.cuda.synchronize()
+    assert_forces(out["F"].cpu().numpy(), ref["F"], HALF_TOL[prec], f"mixed {prec} F")
 
 
 def test_mixed_cv_apply_force_parity(torch, rid):
