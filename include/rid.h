@@ -65,8 +65,9 @@ const char* rid_last_error(void);
 const char* rid_version(void);
 
 /* ------------------------------------------------------------------------
- * Systems: atoms and torsion CVs ("CV selection": backbone phi/psi of the
- * selected residues, 2n-2 torsions for n residues, periodic over 2 pi).
+ * Systems: atoms and CVs ("CV selection": backbone phi/psi torsions of the
+ * selected residues, 2n-2 torsions for n residues, periodic over 2 pi; and
+ * interatomic distances, the `distance` type, where angular_mask is 0).
  *
  * quads         host int32 [n_cv][4], 0-based atom indices (a, b, c, d) of
  *               each torsion; the torsion is
@@ -154,9 +155,10 @@ void rid_ensemble_destroy(rid_ensemble ens);
  * rid_cv_eval - CVs of B walkers ("CV selection"): torsions, and distances
  * for the system's distance rows (x = (s, 0) for those).
  *   d_pos  [B][n_atoms][3]   atom positions (whole molecules, no PBC)
- *   d_s    [B][n_cv]         torsions in (-pi, pi]
+ *   d_s    [B][n_cv]         torsions in (-pi, pi]; distances in nm
  *   d_x    [B][2 n_cv] or NULL: [cos s | sin s], computed from the geometry
- *          (cos s = X/sqrt(X^2+Y^2), sin s = Y/sqrt(X^2+Y^2)).
+ *          (cos s = X/sqrt(X^2+Y^2), sin s = Y/sqrt(X^2+Y^2)); a distance
+ *          row's slots hold (s, 0).
  * A degenerate torsion (|b1 x b2|^2 or |b2 x b3|^2 < 1e-12 nm^4) gives
  * s = 0, x = (1, 0).
  * ------------------------------------------------------------------------ */
@@ -170,7 +172,8 @@ rid_status rid_cv_eval(rid_system sys, const float* d_pos, int B, float* d_s,
  * ("Development of the protocol", "Training phase"), taken here as
  *   eps = sqrt( (1/K) sum_k |g_k - gbar|^2 ),  g_k = grad_s A_k(s),
  * accumulated in FP64 (shifted by member 0, so identical members give 0).
- *   d_s     [B][n_cv]  CVs (any real values; periodic)
+ *   d_s     [B][n_cv]  CVs (any real values; periodic unless the ensemble's
+ *                      angular mask marks them raw)
  *   d_eps   [B]        model deviation (required)
  *   d_gbar  [B][n_cv]  ensemble-mean mean force, or NULL
  *   d_A     [B][K]     per-model free energies, or NULL
