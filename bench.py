@@ -602,8 +602,8 @@ def main():
         pmc_summary(*args.pmc_summary)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(walkers shard with no exchange; see the design notes). Use --gpus 1.",
+        print("bench.py measures one GPU: the library has no multi-GPU path (walkers "
+              "would shard across GPUs with no exchange between them). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
