@@ -878,19 +878,20 @@ def rms_rel_err(test, ref):
 # next-3: selection ("Selection" phase; "SelectorConfig": cluster_threshold,
 # numb_cluster_lower/upper, max_selection)
 # --------------------------------------------------------------------------
-def frame_deviation(models, s):
+def frame_deviation(models, s, mask=None):
     """Model deviation eps of CV frames s [B][n] (the uncertainty the
     selection filters on): model_deviation of the ensemble's mean forces."""
-    _, g = ensemble_mean_force(models, s)
+    _, g = ensemble_mean_force(models, s, mask)
     return model_deviation(g)[1]
 
 
-def cv_distance_sq_f32(a, b):
+def cv_distance_sq_f32(a, b, mask=None):
     """Squared periodic distance between CV vectors a, b [..., n] (angles in
     [-pi, pi]) in the FP32 arithmetic the clustering decides in: per CV the
     FP32 difference wrapped to (-pi, pi] with FP32 constants, then the
     squares summed in CV order, every product and sum rounded to FP32 (no
-    fused multiply-add)."""
+    fused multiply-add).  CVs whose angular-mask entry is 0 (distances) are
+    not periodic: their difference is not wrapped."""
     a = np.asarray(a, dtype=np.float32)
     b = np.asarray(b, dtype=np.float32)
     pi = np.float32(math.pi)
@@ -898,13 +899,14 @@ def cv_distance_sq_f32(a, b):
     acc = np.zeros(np.broadcast(a[..., 0], b[..., 0]).shape, dtype=np.float32)
     for i in range(a.shape[-1]):
         d = (a[..., i] - b[..., i]).astype(np.float32)
-        d = np.where(d > pi, (d - two_pi).astype(np.float32), d)
-        d = np.where(d <= -pi, (d + two_pi).astype(np.float32), d)
+        if mask is None or mask[i]:
+            d = np.where(d > pi, (d - two_pi).astype(np.float32), d)
+            d = np.where(d <= -pi, (d + two_pi).astype(np.float32), d)
         acc = (acc + (d * d).astype(np.float32)).astype(np.float32)
     return acc
 
 
-def leader_cluster(s, threshold, keep=None, max_clusters=None):
+def leader_cluster(s, threshold, keep=None, max_clusters=None, mask=None):
     """Threshold clustering of CV frames.  Reading (the paper names a cluster
     threshold and a window for the cluster count, not the algorithm): frames
     are taken in order; a kept frame joins the first cluster, in founding
@@ -926,7 +928,7 @@ def leader_cluster(s, threshold, keep=None, max_clusters=None):
         if keep is not None and not keep[f]:
             continue
         if leaders:
-            hit = np.nonzero(cv_distance_sq_f32(s[leaders], s[f][None, :]) <= t2)[0]
+            hit = np.nonzero(cv_distance_sq_f32(s[leaders], s[f][None, :], mask) <= t2)[0]
             if hit.size:
                 labels[f] = hit[0]
                 continue
@@ -942,14 +944,15 @@ def leader_cluster(s, threshold, keep=None, max_clusters=None):
 THRESHOLD_FACTOR = np.float32(1.1)
 
 
-def adapt_threshold(s, threshold, lower, upper, keep=None, max_clusters=None, max_iter=100):
+def adapt_threshold(s, threshold, lower, upper, keep=None, max_clusters=None, max_iter=100,
+                    mask=None):
     """Reading of the threshold adjustment (first iteration only; the rule is
     not printed): while the cluster count is above `upper` the threshold is
     multiplied by 1.1, while below `lower` divided by 1.1 (FP32), at most
     max_iter adjustments.  Returns (threshold, leader_cluster result)."""
     t = np.float32(threshold)
     for it in range(max_iter + 1):
-        res = leader_cluster(s, t, keep, max_clusters)
+        res = leader_cluster(s, t, keep, max_clusters, mask)
         n = res[2]
         if lower <= n <= upper or it == max_iter:
             return t, res
@@ -958,20 +961,21 @@ def adapt_threshold(s, threshold, lower, upper, keep=None, max_clusters=None, ma
 
 
 def select_frames(models, s, eps0, threshold, lower, upper, max_selection, adapt=True,
-                  max_iter=100):
+                  max_iter=100, mask=None):
     """Selection: the frames whose model deviation reaches the lower trust
     level (eps >= eps0, reading: "high model deviation" relative to the
     trust level) are clustered, the threshold adapted into [lower, upper]
     when `adapt`, and the leaders of the first max_selection clusters are
     the selected frames.  Returns dict(eps, keep, threshold, labels,
     leaders, n_clusters, selected)."""
-    eps = frame_deviation(models, s)
+    eps = frame_deviation(models, s, mask)
     keep = eps >= eps0
     cap = max(upper, max_selection) + 1
     if adapt:
-        t, (labels, leaders, n) = adapt_threshold(s, threshold, lower, upper, keep, cap, max_iter)
+        t, (labels, leaders, n) = adapt_threshold(s, threshold, lower, upper, keep, cap, max_iter,
+                                                  mask)
     else:
         t = np.float32(threshold)
-        labels, leaders, n = leader_cluster(s, t, keep, cap)
+        labels, leaders, n = leader_cluster(s, t, keep, cap, mask)
     return dict(eps=eps, keep=keep, threshold=t, labels=labels, leaders=leaders,
                 n_clusters=n, selected=list(leaders[:max_selection]))

@@ -125,3 +125,35 @@ def test_coincident_pair_is_degenerate():
     assert not deg[0].any() and deg[1, 1]
     J = O.distance_jacobian(pos, cvs[1:, :2])
     assert np.all(J[1] == 0.0)
+
+
+def test_masked_clustering_does_not_wrap_raw_cvs():
+    # 3.0 and -3.1 are 0.18 apart through the periodic wrap, 6.1 apart on the
+    # line: at threshold 0.2 they share a cluster only as an angle
+    s = np.array([[3.0], [-3.1]], np.float32)
+    lab_a, _, n_a = O.leader_cluster(s, 0.2)
+    lab_d, _, n_d = O.leader_cluster(s, 0.2, mask=np.array([0], np.uint8))
+    assert n_a == 1 and list(lab_a) == [0, 0]
+    assert n_d == 2 and list(lab_d) == [0, 1]
+
+
+def test_masked_distance_against_fp64_and_labels_by_brute_force():
+    rng = np.random.default_rng(12)
+    n = 7
+    mask = np.array([1, 0, 1, 1, 0, 1, 0], np.uint8)
+    m = mask.astype(bool)
+    s = np.where(m, rng.uniform(-np.pi, np.pi, (300, n)), rng.uniform(0.2, 1.6, (300, n)))
+    s = s.astype(np.float32)
+    a, b = s[:150].astype(np.float64), s[150:].astype(np.float64)
+    d = a - b
+    d = np.where(m, (d + np.pi) % (2 * np.pi) - np.pi, d)
+    exact = np.sum(d * d, axis=-1)
+    got = O.cv_distance_sq_f32(s[:150], s[150:], mask).astype(np.float64)
+    assert np.max(np.abs(got - exact) / np.maximum(exact, 1e-6)) < 1e-5
+    t = np.float32(1.4)
+    labels, leaders, nc = O.leader_cluster(s, t, mask=mask)
+    L = s[leaders]
+    for f in range(len(s)):
+        d2 = O.cv_distance_sq_f32(L, s[f][None, :], mask)
+        first = int(np.nonzero(d2 <= t * t)[0][0])
+        assert labels[f] == first
