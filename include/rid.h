@@ -144,9 +144,10 @@ rid_status rid_ensemble_set_resnet(rid_ensemble ens, int enable);
  * the same two slots (input width and packed parameters unchanged), and its
  * mean force is dA/dx_i.  rid_model_dev encodes its CVs with the mask;
  * rid_bias_force and the server need the system's distance rows to be the
- * ensemble's raw CVs (RID_EINVAL otherwise).  While any entry is 0,
- * rid_mcmc_run, rid_select, rid_bias_force_conservative and the training
- * calls return RID_EUNSUPPORTED.  Synchronizes the device.  Errors:
+ * ensemble's raw CVs (RID_EINVAL otherwise); rid_select leaves raw CVs
+ * unwrapped in its clustering distance.  While any entry is 0,
+ * rid_mcmc_run, rid_bias_force_conservative and the training calls return
+ * RID_EUNSUPPORTED.  Synchronizes the device.  Errors:
  * RID_EINVAL (NULL ensemble, an entry other than 0 or 1), RID_ENOMEM. */
 rid_status rid_ensemble_set_angular_mask(rid_ensemble ens, const uint8_t* angular_mask);
 void rid_ensemble_destroy(rid_ensemble ens);

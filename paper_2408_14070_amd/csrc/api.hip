@@ -443,7 +443,8 @@ rid_status rid_cluster_frames(const float* d_s, int B, int n_cv, const float* d_
     return fail(RID_EINVAL, "threshold must be positive and finite");
   if (max_clusters < 1) return fail(RID_EINVAL, "max_clusters must be >= 1");
   if (adapt && (lower < 1 || upper < lower)) return fail(RID_EINVAL, "need 1 <= lower <= upper");
-  return launch_cluster(d_s, B, n_cv, d_eps, eps0, threshold, lower, upper, adapt, max_clusters,
+  return launch_cluster(d_s, B, n_cv, nullptr, d_eps, eps0, threshold, lower, upper, adapt,
+                        max_clusters,
                         d_labels, d_leaders, max_clusters, nullptr, n_clusters, threshold_used,
                         (hipStream_t)stream);
 }
@@ -459,12 +460,11 @@ rid_status rid_select(rid_ensemble ens, const float* d_s, int B, float eps0, flo
     return fail(RID_EINVAL, "threshold must be positive and finite");
   if (lower < 1 || upper < lower) return fail(RID_EINVAL, "need 1 <= lower <= upper");
   if (max_selection < 1) return fail(RID_EINVAL, "max_selection must be >= 1");
-  if (!ens->impl.raw.empty())
-    return fail(RID_EUNSUPPORTED, "selection clusters periodic CVs only (angular mask all 1)");
   rid_status r = rid_model_dev(ens, d_s, B, d_eps, nullptr, nullptr, nullptr, stream);
   if (r != RID_OK) return r;
   const int cap = std::max(upper, max_selection) + 1;
-  return launch_cluster(d_s, B, ens->impl.n_cv, d_eps, eps0, threshold, lower, upper, adapt, cap,
+  return launch_cluster(d_s, B, ens->impl.n_cv, ens->impl.d_raw, d_eps, eps0, threshold, lower,
+                        upper, adapt, cap,
                         d_labels, d_selected, max_selection, n_selected, n_clusters,
                         threshold_used, (hipStream_t)stream);
 }

@@ -213,8 +213,8 @@ struct TrainIo {
 };
 // Threshold clustering of CV frames (selection); synchronises the stream.
 // Copies the first min(leaders, leaders_out) leaders' frame indices.
-rid_status launch_cluster(const float* s, int B, int n, const float* eps, float eps0,
-                          float threshold, int lower, int upper, int adapt, int cap,
+rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw, const float* eps,
+                          float eps0, float threshold, int lower, int upper, int adapt, int cap,
                           int* labels, int* leaders, int leaders_out, int* n_leaders,
                           int* n_clusters, float* t_used, hipStream_t st);
 bool train_fused_supported(const rid_ensemble_impl& e);

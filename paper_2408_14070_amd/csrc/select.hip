@@ -46,12 +46,34 @@ struct ClusterArgs {
   int* state;            // [0] leaders so far, [1] next frame, [2] over the cap
   int* labels;           // [B]
   unsigned long long* pend;   // [ceil(B/64)] bit f%64 of word f/64: frame f unmatched
+  const uint8_t* raw;    // [n] or null: CVs with raw[i] = 1 are not periodic
 };
+
+// Squared distance leader - frame with non-periodic CVs (raw[i] = 1: the
+// difference is not wrapped); otherwise as leader_d2.
+__device__ inline float leader_d2_masked(const float* lead, long long ls, const float* x, int n,
+                                         const uint8_t* raw) {
+#pragma clang fp contract(off)
+  constexpr float kPi = 3.14159265358979f;
+  constexpr float kTwoPi = 6.28318530717959f;
+  float acc = 0.f;
+  for (int i = 0; i < n; ++i) {
+    float d = lead[i * ls] - x[i];
+    if (!raw[i]) {
+      if (d > kPi) d = d - kTwoPi;
+      if (d <= -kPi) d = d + kTwoPi;
+    }
+    acc = acc + d * d;
+  }
+  return acc;
+}
 
 // Squared periodic distance leader - frame, the leader's CV i at lead[i * ls],
 // the frame's at x[i]; FP32, CV order, no fused multiply-add.
-__device__ inline float leader_d2(const float* lead, long long ls, const float* x, int n) {
+__device__ inline float leader_d2(const float* lead, long long ls, const float* x, int n,
+                                  const uint8_t* raw) {
 #pragma clang fp contract(off)
+  if (raw) return leader_d2_masked(lead, ls, x, n, raw);
   constexpr float kPi = 3.14159265358979f;
   constexpr float kTwoPi = 6.28318530717959f;
   float acc = 0.f;
@@ -91,7 +113,7 @@ __global__ __launch_bounds__(kMatchWaves * kWave) void sel_match_kernel(ClusterA
   int lab = kPending;
   for (int j0 = 0; j0 < nl; j0 += kWave) {
     const int j = j0 + lane;
-    const bool hit = j < nl && leader_d2(a.LT + j, a.cap, xs[wave], n) <= a.t2;
+    const bool hit = j < nl && leader_d2(a.LT + j, a.cap, xs[wave], n, a.raw) <= a.t2;
     const unsigned long long m = __ballot(hit);
     if (m) {
       lab = j0 + __ffsll((long long)m) - 1;
@@ -178,7 +200,7 @@ __global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(Clus
       int hitj = -1;
       for (int j0 = 0; j0 < n_new0 && hitj < 0; j0 += kWave) {
         const int j = j0 + lane;
-        const bool hit = j < n_new0 && leader_d2(NL + (size_t)j * n, 1, XB + (size_t)q * n, n) <= a.t2;
+        const bool hit = j < n_new0 && leader_d2(NL + (size_t)j * n, 1, XB + (size_t)q * n, n, a.raw) <= a.t2;
         const unsigned long long m = __ballot(hit);
         if (m) hitj = j0 + __ffsll((long long)m) - 1;
       }
@@ -230,7 +252,7 @@ __global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(Clus
       if (sh[1] != f_end || start >= g) break;
       const int jn = sh[0] - 1;                  // the leader just founded
       for (int q = start + tid; q < g; q += kResolveWaves * kWave)
-        if (gm[q] < 0 && leader_d2(NL + (size_t)jn * n, 1, XB + (size_t)q * n, n) <= a.t2)
+        if (gm[q] < 0 && leader_d2(NL + (size_t)jn * n, 1, XB + (size_t)q * n, n, a.raw) <= a.t2)
           gm[q] = jn;
       __syncthreads();
     }
@@ -307,8 +329,8 @@ rid_status cluster_once(ClusterArgs a, float t, int nlmax, int gmax, hipStream_t
 
 }  // namespace
 
-rid_status launch_cluster(const float* s, int B, int n, const float* eps, float eps0,
-                          float threshold, int lower, int upper, int adapt, int cap,
+rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw, const float* eps,
+                          float eps0, float threshold, int lower, int upper, int adapt, int cap,
                           int* labels, int* leaders, int leaders_out, int* n_leaders,
                           int* n_clusters, float* t_used, hipStream_t st) {
   ClusterWs ws;
@@ -318,6 +340,7 @@ rid_status launch_cluster(const float* s, int B, int n, const float* eps, float 
   RID_HIP(hipMalloc(&ws.pend, sizeof(unsigned long long) * (size_t)((B + 63) / 64)));
   ClusterArgs a{};
   a.s = s;
+  a.raw = raw;
   a.eps = eps;
   a.eps0 = eps0;
   a.B = B;

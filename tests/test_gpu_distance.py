@@ -178,6 +178,44 @@ def test_mixed_server_matches_direct_call(torch, rid):
     srv.close()
 
 
+def test_masked_select_matches_oracle(torch, rid):
+    # exploration frames with every fourth CV turned into a raw, distance-like
+    # value (not periodic): the deviation uses the raw encoding and the
+    # clustering distance leaves those CVs unwrapped
+    n, widths, K = 38, [64, 64], 4
+    mask = np.ones(n, np.uint8)
+    mask[::4] = 0
+    raw = ~mask.astype(bool)
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 22, bias_std=0.1)
+    models = ridgen.unpack_params(params, 2 * n, widths, K)
+    s = ridgen.exploration_frames(16, 125, n, 30, 0.3, seed=15)
+    s[:, raw] = (1.0 + 1.5 * s[:, raw]).astype(np.float32)
+    eps_ref = O.frame_deviation(models, s.astype(np.float64), mask)
+    e = np.sort(eps_ref)
+    mid = len(e) // 2
+    k = mid - 200 + int(np.argmax(np.diff(e[mid - 200:mid + 200])))
+    eps0 = 0.5 * (e[k] + e[k + 1])
+    gap = e[k + 1] - e[k]
+    assert gap > 1e-4 * e[k]
+    ref = O.select_frames(models, s, eps0, 0.5, 30, 45, 50, adapt=True, mask=mask)
+    E = rid.Ensemble(n, widths, K, params)
+    E.set_angular_mask(mask)
+    out = rid.select(E, torch.from_numpy(s).cuda(), eps0, 0.5, 30, 45, 50, adapt=True)
+    torch.cuda.synchronize()
+    eps = out["eps"].cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(eps - eps_ref) / eps_ref) < 1e-4
+    assert np.min(np.abs(eps - eps0)) > 0.25 * gap
+    print(f"masked selection: {len(ref['selected'])} of {ref['n_clusters']} clusters, "
+          f"threshold {ref['threshold']}", flush=True)
+    assert np.float32(out["threshold"]) == ref["threshold"]
+    assert out["n_clusters"] == ref["n_clusters"]
+    assert out["selected"].cpu().numpy().tolist() == ref["selected"]
+    assert np.array_equal(out["labels"].cpu().numpy().astype(np.int64), ref["labels"])
+    # the periodic clustering of the same frames differs (the mask matters)
+    plain = O.leader_cluster(s, ref["threshold"], ref["keep"], 51)
+    assert not np.array_equal(plain[0], ref["labels"])
+
+
 def test_mixed_refusals(torch, rid):
     sys_ = _mixed()
     S = rid.System(sys_.n_atoms, sys_.quads, sys_.mask)
@@ -190,8 +228,6 @@ def test_mixed_refusals(torch, rid):
         rid.mf_train_step(E, s, torch.zeros_like(s), 1e-3)
     with pytest.raises(rid.RidError, match="EUNSUPPORTED"):
         rid.mcmc_run(E, s.clone(), 1, 1.0, 0.3, 1)
-    with pytest.raises(rid.RidError, match="EUNSUPPORTED"):
-        rid.select(E, s, 0.0, 1.0, 1, 4, 4)
     # the ensemble's mask must match the system's CV kinds
     E2, _ = _ens(rid, sys_, [64, 64], 2, 1010)
     E2.set_angular_mask(None)
