@@ -132,3 +132,18 @@ def test_resnet_refusals(torch, rid):
     E3 = rid.Ensemble(sys_.n_cv, widths, K, params, rid.RID_BF16)
     with pytest.raises(rid.RidError, match="EUNSUPPORTED"):
         E3.set_resnet(True)
+
+
+def test_resnet_server_matches_direct_call(torch, rid):
+    sys_, pos, params, widths, K = workload("peptide20", 37, seed=25, bias_std=0.1)
+    S = rid.System(sys_.n_atoms, sys_.quads)
+    E = rid.Ensemble(sys_.n_cv, widths, K, params)
+    E.set_resnet(True)
+    srv = rid.Server(1 << 30, n_streams=2)
+    mid = srv.register(S, E, 2.0, 3.0)
+    got = srv.wait(srv.submit(mid, pos))
+    ref = rid.bias_force(S, E, _dev(torch, pos), 2.0, 3.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(got["F"], ref["F"].cpu().numpy())
+    assert np.array_equal(got["eps"], ref["eps"].cpu().numpy())
+    srv.close()
