@@ -95,8 +95,9 @@ struct Server {
   std::vector<Batch> inflight;
   int64_t next_ticket = 1;
   int launching = 0;               // batches being launched outside the lock
+  int waiters = 0;                 // threads inside rid_server_wait
   bool stop = false;
-  rid_status fatal = RID_OK;
+  int fatal = RID_OK;              // first device error; then nothing more is launched
   std::thread sched, poller;
 
   // statistics
@@ -108,6 +109,13 @@ struct Server {
 
   void run_scheduler();
   void run_poller();
+  // finish request t with status st (under the lock)
+  void mark(int64_t t, int st) {
+    Req& r = reqs[t];
+    r.status = (rid_status)st;
+    r.done = true;
+    r.done_at = clk::now();
+  }
   rid_status launch(const Batch& b, const ServeModel& m);
 };
 
@@ -159,6 +167,12 @@ void Server::run_scheduler() {
   (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
   while (!stop) {
+    if (fatal != RID_OK && !waiting.empty()) {
+      // a device error stopped the server: fail what is still queued
+      serve::drain_waiting(waiting, fatal, [&](int64_t t, int st) { mark(t, st); });
+      cv_done.notify_all();
+      continue;
+    }
     int slot = -1;
     for (int s = 0; s < n_slots; ++s)
       if (!slot_busy[s]) {
@@ -207,14 +221,9 @@ void Server::run_scheduler() {
     lk.lock();
     --launching;
     if (rs != RID_OK) {
-      fatal = rs;
-      for (int64_t t : b.tickets) {
-        reqs[t].status = rs;
-        reqs[t].done = true;
-        reqs[t].done_at = clk::now();
-      }
-      dev.release(off);
-      slot_busy[slot] = false;
+      // the launch itself failed: this batch's requests carry its status
+      serve::retire(serve::Poll::failed, b.tickets, off, slot, dev, slot_busy, RID_OK, rs,
+                    &fatal, [&](int64_t t, int st) { mark(t, st); });
       cv_done.notify_all();
       continue;
     }
@@ -233,20 +242,20 @@ void Server::run_poller() {
     bool any = false;
     for (size_t i = 0; i < inflight.size();) {
       Batch& b = inflight[i];
-      if (hipEventQuery(events[b.slot]) == hipSuccess) {
-        const auto now = clk::now();
-        for (int64_t t : b.tickets) {
-          Req& r = reqs[t];
-          r.done = true;
-          r.done_at = now;
-        }
-        dev.release(b.dev_off);
-        slot_busy[b.slot] = false;
-        inflight.erase(inflight.begin() + i);
-        any = true;
-      } else {
+      const serve::Poll pr =
+          serve::poll_outcome((int)hipEventQuery(events[b.slot]), (int)hipSuccess,
+                              (int)hipErrorNotReady);
+      if (pr == serve::Poll::pending) {
         ++i;
+        continue;
       }
+      // finished, or a device error (its event may never signal): either
+      // way the batch leaves the in-flight list and its waiters wake
+      if (pr == serve::Poll::failed) (void)hipGetLastError();
+      serve::retire(pr, b.tickets, b.dev_off, b.slot, dev, slot_busy, RID_OK, RID_EDEVICE,
+                    &fatal, [&](int64_t t, int st) { mark(t, st); });
+      inflight.erase(inflight.begin() + i);
+      any = true;
     }
     if (any) {
       cv_done.notify_all();
@@ -359,7 +368,8 @@ rid_status rid_server_submit(rid_server srv, int model_id, const float* host_pos
   std::unique_lock<std::mutex> lk(s.mu);
   if (model_id < 0 || model_id >= (int)s.models.size()) return fail(RID_EINVAL, "unknown model id");
   if (n_walkers < 1) return fail(RID_EINVAL, "n_walkers must be >= 1");
-  if (s.fatal != RID_OK) return fail(s.fatal, "server stopped after a device error");
+  if (s.fatal != RID_OK) return fail((rid_status)s.fatal, "server stopped after a device error");
+  if (s.stop) return fail(RID_EINVAL, "server is being destroyed");
   const ServeModel& m = s.models[model_id];
   if (m.shape.batch_bytes(n_walkers) > s.dev.capacity())
     return fail(RID_ENOMEM, "request larger than the HBM budget");
@@ -409,6 +419,9 @@ rid_status rid_server_wait(rid_server srv, int64_t ticket, float* host_force,
   Server& s = srv->s;
   std::unique_lock<std::mutex> lk(s.mu);
   if (s.reqs.find(ticket) == s.reqs.end()) return fail(RID_EINVAL, "unknown ticket");
+  // counted from here to the last touch of the server below: destroy waits
+  // until no waiter is left before it frees anything
+  ++s.waiters;
   // look the request up again after every wake-up: other threads' submits
   // may rehash the table (references stay valid, iterators do not)
   Req& r = s.reqs.find(ticket)->second;
@@ -441,7 +454,10 @@ rid_status rid_server_wait(rid_server srv, int64_t ticket, float* host_force,
   }
   if (!done.own_pin) s.pin.release(done.pin_off);
   s.reqs.erase(ticket);
-  if (st != RID_OK) return fail(st, "request failed");
+  --s.waiters;
+  if (s.stop) s.cv_done.notify_all();   // wake destroy, which waits for the last waiter
+  lk.unlock();
+  if (st != RID_OK) return fail(st, "request failed (device error, or the server was destroyed)");
   return RID_OK;
 }
 
@@ -490,10 +506,17 @@ void rid_server_destroy(rid_server srv) {
     s.stop = true;
   }
   s.cv_sched.notify_all();
-  s.cv_done.notify_all();
   s.cv_poll.notify_all();
   if (s.sched.joinable()) s.sched.join();
-  if (s.poller.joinable()) s.poller.join();
+  if (s.poller.joinable()) s.poller.join();   // returns once nothing is in flight
+  {
+    // requests never launched are failed, and their waiters (if any) must
+    // leave rid_server_wait before the server's memory goes away
+    std::unique_lock<std::mutex> lk(s.mu);
+    serve::drain_waiting(s.waiting, RID_EINVAL, [&](int64_t t, int st) { s.mark(t, st); });
+    s.cv_done.notify_all();
+    s.cv_done.wait(lk, [&] { return s.waiters == 0; });
+  }
   for (auto st : s.streams) (void)hipStreamSynchronize(st);
   for (auto st : s.streams) (void)hipStreamDestroy(st);
   for (auto ev : s.events) (void)hipEventDestroy(ev);

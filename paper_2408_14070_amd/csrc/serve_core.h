@@ -128,6 +128,42 @@ inline bool admit(const std::deque<Waiting>& q, std::vector<size_t>& pick,
   return false;
 }
 
+// Outcome of polling an in-flight batch's completion event.  Only the
+// runtime's "not ready" status means the batch is still running; success
+// means it finished; any other status is a device error (a failed kernel
+// or copy), and the batch must not be polled again: its event may never
+// signal.
+enum class Poll { pending, done, failed };
+inline Poll poll_outcome(int query_status, int success, int not_ready) {
+  if (query_status == not_ready) return Poll::pending;
+  return query_status == success ? Poll::done : Poll::failed;
+}
+
+// Retire an in-flight batch whose poll was not pending: each of its requests
+// is finished with ok_status, or after a device error with err_status (and
+// *fatal is set, so later submissions are refused and waiting requests are
+// failed instead of launched); its arena block and stream slot are freed.
+// mark(ticket, status) finishes one request.  Returns the status given.
+template <class Mark>
+inline int retire(Poll p, const std::vector<int64_t>& tickets, size_t dev_off, int slot,
+                  Arena& dev, std::vector<bool>& slot_busy, int ok_status, int err_status,
+                  int* fatal, Mark&& mark) {
+  const int st = p == Poll::done ? ok_status : err_status;
+  if (p == Poll::failed && *fatal == ok_status) *fatal = err_status;
+  for (int64_t t : tickets) mark(t, st);
+  dev.release(dev_off);
+  slot_busy[slot] = false;
+  return st;
+}
+
+// Finish every waiting request with `status` (server stopping, or fatal
+// after a device error) and empty the queue.
+template <class Mark>
+inline void drain_waiting(std::deque<Waiting>& q, int status, Mark&& mark) {
+  for (const Waiting& w : q) mark(w.ticket, status);
+  q.clear();
+}
+
 // Choose the next batch from the waiting queue (indices into `q`).  Returns
 // an empty vector if the queue is empty.
 inline std::vector<size_t> form_batch(const std::deque<Waiting>& q, int max_batch_walkers,

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <deque>
+#include <map>
 #include <random>
 #include <set>
 #include <vector>
@@ -42,9 +43,17 @@ struct Running {
   size_t off;
   double end;
   int model;
+  int slot;
 };
 
-static int sim(bool fifo, int slots, int max_batch, size_t budget, unsigned seed) {
+// fail_at > 0: the completion poll of the fail_at-th finishing batch reports
+// a device error (a status other than success and not-ready), which must
+// fail that batch's requests, every queued one, and refuse later arrivals.
+constexpr int kSuccess = 0, kNotReady = 600, kDeviceError = 719;
+constexpr int kOk = 0, kErr = -3;
+
+static int sim(bool fifo, int slots, int max_batch, size_t budget, unsigned seed,
+               int fail_at = 0) {
   std::mt19937 rng(seed);
   std::vector<ModelShape> models = {{22, 2, 4}, {200, 38, 4}, {1000, 120, 8}};
   Arena arena(budget);
@@ -53,6 +62,13 @@ static int sim(bool fifo, int slots, int max_batch, size_t budget, unsigned seed
   std::set<int64_t> done;
   std::vector<std::vector<int64_t>> order(models.size());   // submission order per model
   std::vector<int64_t> last_started(models.size(), 0);
+  std::vector<bool> slot_busy(slots, false);
+  std::map<int64_t, int> status;   // finished tickets -> status
+  int fatal = kOk, finished_batches = 0;
+  auto mark = [&](int64_t t, int st) {
+    status[t] = st;
+    done.insert(t);
+  };
   const int n_req = 400;
   double t = 0.0, next_arrival = 0.0;
   int submitted = 0;
@@ -62,9 +78,10 @@ static int sim(bool fifo, int slots, int max_batch, size_t budget, unsigned seed
     while (submitted < n_req && next_arrival <= t) {
       const int m = rng() % models.size();
       const int w = 1 + rng() % 256;
-      if (models[m].batch_bytes(w) > budget) {   // rejected at submission
+      if (models[m].batch_bytes(w) > budget || fatal != kOk) {   // refused at submission
         ++submitted;
         done.insert(-(int64_t)submitted);
+        next_arrival += std::exponential_distribution<double>(1.0)(rng);
         continue;
       }
       q.push_back({ticket, m, w});
@@ -72,6 +89,9 @@ static int sim(bool fifo, int slots, int max_batch, size_t budget, unsigned seed
       ++ticket;
       ++submitted;
       next_arrival += std::exponential_distribution<double>(1.0)(rng);
+    }
+    if (fatal != kOk) {
+      drain_waiting(q, fatal, mark);                 // nothing more is launched
     }
     // schedule while slots are free and memory admits
     while ((int)run.size() < slots && !q.empty()) {
@@ -91,7 +111,11 @@ static int sim(bool fifo, int slots, int max_batch, size_t budget, unsigned seed
       }
       CHECK(!pick.empty() && pick[0] == 0);          // shrinking keeps the oldest
       CHECK(arena.in_use() <= budget);
-      Running r{{}, off, t + 1e-3 * walkers, model};
+      int slot = 0;
+      while (slot_busy[slot]) ++slot;
+      CHECK(slot < slots);
+      slot_busy[slot] = true;
+      Running r{{}, off, t + 1e-3 * walkers, model, slot};
       for (size_t i : pick) {
         // FIFO within a model: tickets start in submission order
         CHECK(q[i].ticket > last_started[model]);
@@ -106,28 +130,60 @@ static int sim(bool fifo, int slots, int max_batch, size_t budget, unsigned seed
     for (auto& r : run) t_next = r.end < t_next ? r.end : t_next;
     t = t_next;
     for (size_t i = 0; i < run.size();) {
-      if (run[i].end <= t) {
-        for (int64_t tk : run[i].tickets) {
-          CHECK(done.insert(tk).second);             // completes exactly once
-        }
-        CHECK(arena.release(run[i].off));
-        run.erase(run.begin() + i);
-      } else {
+      const int query = run[i].end <= t
+                            ? (++finished_batches == fail_at ? kDeviceError : kSuccess)
+                            : kNotReady;
+      const Poll pr = poll_outcome(query, kSuccess, kNotReady);
+      if (pr == Poll::pending) {
         ++i;
+        continue;
       }
+      for (int64_t tk : run[i].tickets) CHECK(!done.count(tk));   // completes exactly once
+      const size_t before = arena.in_use();
+      const int st = retire(pr, run[i].tickets, run[i].off, run[i].slot, arena, slot_busy, kOk,
+                            kErr, &fatal, mark);
+      CHECK(arena.in_use() < before);                 // its block went back
+      CHECK(!slot_busy[run[i].slot]);
+      CHECK(st == (pr == Poll::done ? kOk : kErr));
+      for (int64_t tk : run[i].tickets) CHECK(status.at(tk) == st);
+      run.erase(run.begin() + i);
     }
   }
   CHECK(arena.in_use() == 0);
+  CHECK(q.empty());
+  if (fail_at > 0) {
+    CHECK(fatal == kErr);
+    // every request that finished after the failure carries the error
+    int n_err = 0;
+    for (auto& kv : status) n_err += kv.second == kErr;
+    CHECK(n_err >= 1);
+  } else {
+    CHECK(fatal == kOk);
+    for (auto& kv : status) CHECK(kv.second == kOk);
+  }
+  return 0;
+}
+
+static int poll_test() {
+  CHECK(poll_outcome(kNotReady, kSuccess, kNotReady) == Poll::pending);
+  CHECK(poll_outcome(kSuccess, kSuccess, kNotReady) == Poll::done);
+  // any other status (an asynchronous kernel or copy error) is final
+  CHECK(poll_outcome(kDeviceError, kSuccess, kNotReady) == Poll::failed);
+  CHECK(poll_outcome(1, kSuccess, kNotReady) == Poll::failed);
   return 0;
 }
 
 int main() {
   if (arena_test()) return 1;
+  if (poll_test()) return 1;
   const size_t MB = 1 << 20;
   if (sim(false, 4, 4096, 512 * MB, 1)) return 1;      // roomy budget
   if (sim(false, 4, 512, 16 * MB, 2)) return 1;       // tight budget: admission waits
   if (sim(true, 1, 4096, 64 * MB, 3)) return 1;       // FIFO baseline
   if (sim(false, 8, 64, 8 * MB, 4)) return 1;         // small batches, many slots
+  if (sim(false, 4, 4096, 512 * MB, 5, 7)) return 1;  // device error in the 7th batch
+  if (sim(false, 4, 512, 16 * MB, 6, 30)) return 1;   // ... under admission pressure
+  if (sim(true, 1, 4096, 64 * MB, 7, 1)) return 1;    // ... in the first FIFO batch
   std::printf("serve core ok\n");
   return 0;
 }
