@@ -46,12 +46,25 @@ typedef enum {
 } rid_status;
 
 typedef enum {
-  RID_FP32 = 0,  /* every GEMM on FP32 MFMA, FP32 activations               */
-  RID_BF16 = 1,  /* hidden GEMMs on BF16 MFMA with FP32 accumulation; BF16
-                    weights and activations; CV geometry, tanh derivatives
-                    and the switch in FP32; ensemble variance in FP64        */
-  RID_FP16 = 2   /* as RID_BF16 with FP16 operands (same MFMA rate, 3 more
-                    mantissa bits); needs |weights|, |activations| < 65504   */
+  RID_FP32 = 0,     /* every GEMM on FP32 MFMA, FP32 activations            */
+  RID_BF16 = 1,     /* the precision form: the hidden-layer forward GEMMs on
+                       BF16 MFMA with FP32 accumulation (BF16 weights and
+                       activations); the first layer (CV encoding -> first
+                       hidden layer) and the reverse sweep that gives the
+                       mean force on FP16 MFMA (same rate) with FP32
+                       accumulation; tanh derivatives computed in FP32 and
+                       stored in FP16 between the sweeps; CV geometry and the
+                       switch in FP32; ensemble variance in FP64.  The reverse
+                       vectors carry a per-member power-of-two scale (exact)
+                       that keeps them inside FP16's range.  Measured max
+                       normwise force error vs the FP64 oracle ~3e-3        */
+  RID_FP16 = 2,     /* every GEMM on FP16 MFMA with FP32 accumulation (same
+                       rate, 3 more mantissa bits than BF16); needs
+                       |weights|, |hidden activations| < 65504              */
+  RID_BF16_ALL = 3  /* every GEMM operand BF16, tanh' stored in BF16: the
+                       plain BF16 form, kept for comparison (max normwise
+                       force error ~2e-2: each reverse-sweep rounding enters
+                       the mean force linearly)                             */
 } rid_precision;
 
 typedef struct rid_system_s* rid_system;
@@ -110,6 +123,14 @@ rid_status rid_ensemble_create(int n_cv, int n_models, int n_hidden,
  * set_params also resets the Adam moments and step counter. */
 rid_status rid_ensemble_get_params(rid_ensemble ens, float* host_params);
 rid_status rid_ensemble_set_params(rid_ensemble ens, const float* host_params);
+/* Load the packed FP32 parameters from device memory (d_params, caller
+ * owned, n_params floats in the packed layout) into the masters and rebuild
+ * the MFMA fragments, ordered on `stream` with the calls around it (no host
+ * synchronisation).  The Adam moments and step counter are kept.  Used by
+ * the autograd binding, whose parameter tensor is the source of truth for
+ * every forward evaluation.  Errors: RID_EINVAL for NULL arguments. */
+rid_status rid_ensemble_load_params(rid_ensemble ens, const float* d_params,
+                                    rid_stream stream);
 /* Number of Adam updates taken so far. */
 int64_t rid_ensemble_step(rid_ensemble ens);
 /* Training-time dropout of the hidden activations ("Training phase" lists a
@@ -398,18 +419,30 @@ rid_status rid_mf_label(const float* d_traj, const float* d_s0,
  *                      must outlive the server and must not be trained while
  *                      registered.  Returns a model id.
  * rid_server_submit    copies host_pos [n_walkers][n_atoms][3] into pinned
- *                      staging (blocks while staging memory is full) and
- *                      queues the request; RID_ENOMEM if it can never fit the
- *                      budget.  Thread-safe.
+ *                      staging and queues the request; never blocks on
+ *                      memory: when the 1 GiB staging arena is full the
+ *                      request gets a pinned block of its own (RID_ENOMEM if
+ *                      that allocation fails).  RID_ENOMEM if the request can
+ *                      never fit the HBM budget; RID_EDEVICE once a device
+ *                      error has stopped the server; RID_EINVAL while it is
+ *                      being destroyed.  Thread-safe.
  * rid_server_wait      blocks until the request is done and copies its
  *                      results to the host arrays (any may be NULL):
  *                      force [n_walkers][n_atoms][3], energy/eps/sigma
  *                      [n_walkers]; latency_us = arrival (submit) to results
  *                      visible in host memory.  Each ticket is waited once.
+ *                      A request whose batch hit a device error (a kernel or
+ *                      copy failing asynchronously) returns RID_EDEVICE, and
+ *                      so does every request queued after it: the server
+ *                      launches nothing more.  A request still queued when
+ *                      the server is destroyed returns RID_EINVAL.
  * rid_server_stats     latency percentiles and throughput of the requests
  *                      waited since creation or the last reset.
- * rid_server_destroy   stops the threads after in-flight batches finish; call
- *                      after every submitted request has been waited.
+ * rid_server_destroy   stops accepting requests, lets in-flight batches
+ *                      finish, fails the queued ones (RID_EINVAL) and waits
+ *                      until every thread blocked in rid_server_wait has
+ *                      returned before it frees the server.  No call on the
+ *                      handle may start once destroy has been called.
  * ------------------------------------------------------------------------ */
 typedef struct rid_server_s* rid_server;
 #define RID_SERVE_FIFO 1

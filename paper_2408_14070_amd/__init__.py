@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librid.so")
 
 RID_OK, RID_EINVAL, RID_ENOMEM, RID_EDEVICE, RID_EDEGENERATE, RID_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-RID_FP32, RID_BF16, RID_FP16 = 0, 1, 2
+RID_FP32, RID_BF16, RID_FP16, RID_BF16_ALL = 0, 1, 2, 3
 _STATUS = {0: "RID_OK", -1: "RID_EINVAL", -2: "RID_ENOMEM", -3: "RID_EDEVICE",
            -4: "RID_EDEGENERATE", -5: "RID_EUNSUPPORTED"}
 
@@ -28,7 +28,7 @@ _STATUS = {0: "RID_OK", -1: "RID_EINVAL", -2: "RID_ENOMEM", -3: "RID_EDEVICE",
 EXPORTS = (
     "rid_last_error", "rid_version", "rid_system_create", "rid_system_destroy",
     "rid_packed_param_count", "rid_ensemble_create", "rid_ensemble_get_params",
-    "rid_ensemble_set_params", "rid_ensemble_step", "rid_ensemble_set_dropout",
+    "rid_ensemble_set_params", "rid_ensemble_load_params", "rid_ensemble_step", "rid_ensemble_set_dropout",
     "rid_ensemble_set_resnet", "rid_ensemble_set_angular_mask",
     "rid_ensemble_destroy",
     "rid_cv_eval", "rid_model_dev", "rid_cluster_frames", "rid_select", "rid_bias_force",
@@ -82,6 +82,7 @@ def lib():
         "rid_ensemble_create": (i, [i, i, i, vp, i, vp, P(vp)]),
         "rid_ensemble_get_params": (i, [vp, vp]),
         "rid_ensemble_set_params": (i, [vp, vp]),
+        "rid_ensemble_load_params": (i, [vp, vp, vp]),
         "rid_ensemble_step": (i64, [vp]),
         "rid_ensemble_set_dropout": (i, [vp, f, ctypes.c_uint64]),
         "rid_ensemble_set_resnet": (i, [vp, i]),
@@ -201,6 +202,7 @@ class Ensemble:
         self.n_cv, self.K, self.widths = int(n_cv), int(n_models), [int(v) for v in w]
         self.precision = int(precision)
         self.n_params = int(need)
+        self.dropout_rate = 0.0
 
     def get_params(self) -> np.ndarray:
         out = np.empty(self.n_params, dtype=np.float32)
@@ -220,6 +222,7 @@ class Ensemble:
     def set_dropout(self, rate: float, seed: int = 0):
         """rid_ensemble_set_dropout: training-time dropout rate and mask seed."""
         _check(lib().rid_ensemble_set_dropout(self.handle, float(rate), int(seed)))
+        self.dropout_rate = float(rate)
 
     def set_resnet(self, enable: bool = True):
         """rid_ensemble_set_resnet: residual connections between the hidden
@@ -414,13 +417,23 @@ def _make_mean_force_fn():
 
     class MeanForce(torch.autograd.Function):
         """g = grad_s A_k(s) of every member as a differentiable function of
-        the ensemble's packed parameters.  forward calls rid_model_dev;
-        backward calls the double-backward kernels (rid_mf_grad).  The
-        ``params`` tensor stands for the ensemble's FP32 masters (it carries
-        the gradient); keep it in sync with Ensemble.set_params."""
+        the ensemble's packed parameters.  forward loads ``params`` (FP32,
+        packed layout, on the device) into the ensemble
+        (rid_ensemble_load_params, stream-ordered) and calls rid_model_dev;
+        backward calls the double-backward kernels (rid_mf_grad) at those
+        parameters.  ``params`` is therefore the source of truth: the
+        ensemble's masters follow it at every forward call.  Ensembles with a
+        dropout rate are refused: rid_model_dev evaluates the full network
+        while the training sweeps apply the masks, so the backward would
+        belong to another function."""
 
         @staticmethod
         def forward(ctx, s, params, ens):
+            if ens.dropout_rate > 0.0:
+                raise ValueError("mean_force: the ensemble has a dropout rate; the "
+                                 "autograd form is defined for the full network only")
+            _f32(params, (ens.n_params,), "params")
+            _check(lib().rid_ensemble_load_params(ens.handle, _ptr(params), _stream(None)))
             ctx.ens = ens
             ctx.save_for_backward(s)
             _, _, _, g = model_dev(ens, s.contiguous())

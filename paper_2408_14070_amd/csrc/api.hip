@@ -124,6 +124,7 @@ static void free_ensemble(rid_ensemble_impl& e) {
   dev_free(e.d_bias);
   dev_free(e.d_wo);
   dev_free(e.d_bo);
+  dev_free(e.d_vscale);
   dev_free(e.d_raw);
   e.ws_x.release();
   e.ws_A.release();
@@ -254,7 +255,7 @@ rid_status rid_ensemble_create(int n_cv, int n_models, int n_hidden,
   if (!out) return fail(RID_EINVAL, "out is NULL");
   *out = nullptr;
   if (!params || !widths) return fail(RID_EINVAL, "params and widths are required");
-  if (prec != RID_FP32 && prec != RID_BF16 && prec != RID_FP16)
+  if (prec != RID_FP32 && prec != RID_BF16 && prec != RID_FP16 && prec != RID_BF16_ALL)
     return fail(RID_EINVAL, "unknown precision");
   if (n_cv < 1 || n_cv > 256) return fail(RID_EUNSUPPORTED, "n_cv must be in [1, 256]");
   if (n_models < 1 || n_models > 64) return fail(RID_EUNSUPPORTED, "n_models must be in [1, 64]");
@@ -299,7 +300,8 @@ rid_status rid_ensemble_create(int n_cv, int n_models, int n_hidden,
       (st = dev_alloc(&e.d_frag, e.frag_bytes_per_model * n_models)) != RID_OK ||
       (st = dev_alloc(&e.d_bias, (size_t)n_models * n_hidden * e.NP)) != RID_OK ||
       (st = dev_alloc(&e.d_wo, (size_t)n_models * e.NP)) != RID_OK ||
-      (st = dev_alloc(&e.d_bo, (size_t)n_models)) != RID_OK) {
+      (st = dev_alloc(&e.d_bo, (size_t)n_models)) != RID_OK ||
+      (st = dev_alloc(&e.d_vscale, (size_t)2 * n_models)) != RID_OK) {
     free_ensemble(e);
     delete h;
     return st;
@@ -345,6 +347,19 @@ rid_status rid_ensemble_set_params(rid_ensemble ens, const float* host_params) {
   rid_status st = pack_ensemble_weights(e, nullptr);
   if (st != RID_OK) return st;
   RID_HIP(hipStreamSynchronize(nullptr));
+  return RID_OK;
+}
+
+rid_status rid_ensemble_load_params(rid_ensemble ens, const float* d_params,
+                                    rid_stream stream) {
+  if (!ens || !d_params) return fail(RID_EINVAL, "NULL argument");
+  rid_ensemble_impl& e = ens->impl;
+  hipStream_t st = (hipStream_t)stream;
+  if (d_params != e.d_master)
+    RID_HIP(hipMemcpyAsync(e.d_master, d_params, e.n_params * 4, hipMemcpyDeviceToDevice, st));
+  rid_status r = pack_ensemble_weights(e, st);
+  if (r != RID_OK) return r;
+  e.frag_dirty = false;
   return RID_OK;
 }
 

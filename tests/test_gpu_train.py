@@ -95,6 +95,42 @@ def test_vjp_parity_and_autograd(torch, rid):
     assert O.max_rel_err(g.detach().cpu().numpy(), g_ref) <= 1e-5
 
 
+def test_autograd_follows_params_tensor(torch, rid):
+    """The autograd form evaluates the network its params tensor describes
+    (the ensemble was created with other weights and never told), its
+    gradient is the oracle's VJP there and agrees with a directional finite
+    difference of the loss; an ensemble with a dropout rate is refused."""
+    n, widths, K, B = 6, [64, 48], 3, 77
+    p1 = ridgen.xavier_ensemble(2 * n, widths, K, 7, bias_std=0.1)
+    p2 = ridgen.xavier_ensemble(2 * n, widths, K, 8, bias_std=0.1)
+    s = ridgen.f32(ridgen.torus_samples(B, n, 4))
+    rho = ridgen.f32(np.random.default_rng(5).normal(size=(B, K, n)))
+    E = rid.Ensemble(n, widths, K, p1)
+    sd, rd = _dev(torch, s), _dev(torch, rho)
+    P = _dev(torch, p2).requires_grad_(True)
+    g = rid.mean_force(sd, P, E)
+    (g * rd).sum().backward()
+    torch.cuda.synchronize()
+    models2 = ridgen.unpack_params(p2, 2 * n, widths, K)
+    ref = np.stack([O.flat_grad(O.mean_force_vjp(m, s.astype(np.float64), rho[:, k, :]))
+                    for k, m in enumerate(models2)])
+    _, g_ref = O.ensemble_mean_force(models2, s.astype(np.float64))
+    assert O.max_rel_err(g.detach().cpu().numpy(), g_ref) <= 1e-5
+    assert _per_member_err(P.grad.cpu().numpy(), ref) <= GRAD_TOL
+    # central difference of L(P) = sum rho . g(P) along the unit gradient
+    d = P.grad / P.grad.norm()
+    h = 1e-2
+    with torch.no_grad():
+        lp = (rid.mean_force(sd, P + h * d, E) * rd).sum().item()
+        lm = (rid.mean_force(sd, P - h * d, E) * rd).sum().item()
+    fd, exact = (lp - lm) / (2 * h), (P.grad * d).sum().item()
+    print(f"directional derivative: FD {fd:.6e} autograd {exact:.6e}")
+    assert abs(fd - exact) <= 1e-3 * abs(exact)
+    E.set_dropout(0.1, 1)
+    with pytest.raises(ValueError):
+        rid.mean_force(sd, P, E)
+
+
 def test_train_steps_follow_oracle(torch, rid):
     n, widths, K, B = 38, [256] * 4, 4, 4096
     params = ridgen.xavier_ensemble(2 * n, widths, K, 1000)
