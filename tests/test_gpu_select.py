@@ -110,6 +110,36 @@ def test_select_matches_oracle(torch, rid):
     assert np.array_equal(out["labels"].cpu().numpy().astype(np.int64), ref["labels"])
 
 
+def test_select_benchmarked_workload_matches_oracle(torch, rid):
+    """The selection the benchmark times: 20 000 frames, threshold 2.6
+    adapted into [30, 45] (15 adjustments, chunks up to 8192 frames and
+    full rounds), max_selection 50.  The oracle's result is stored by
+    tests/golden/make_selection_golden.py (about a minute of CPU)."""
+    import hashlib
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "selection_20k.json")))
+    n, widths, K = 38, g["ensemble"]["widths"], g["ensemble"]["K"]
+    params = ridgen.xavier_ensemble(2 * n, widths, K, g["ensemble"]["seed"])
+    s = ridgen.exploration_frames(*g["frames"])
+    E = rid.Ensemble(n, widths, K, params)
+    out = rid.select(E, torch.from_numpy(s).cuda(), g["eps0"], g["threshold0"], *g["window"],
+                     g["max_selection"], adapt=True)
+    torch.cuda.synchronize()
+    eps = out["eps"].cpu().numpy().astype(np.float64)
+    # the FP32 deviations stay on the oracle's side of eps0
+    assert np.min(np.abs(eps - g["eps0"])) > 0.25 * g["eps_gap"]
+    assert int(np.sum(eps >= g["eps0"])) == g["n_kept"]
+    labels = out["labels"].cpu().numpy().astype("<i8")
+    print(f"threshold {out['threshold']}, {out['n_clusters']} clusters", flush=True)
+    assert np.float32(out["threshold"]) == np.float32(g["threshold"])
+    assert out["n_clusters"] == g["n_clusters"]
+    # 30 clusters, under max_selection: the selected frames are every leader
+    assert g["selected"] == g["leaders"][:g["max_selection"]]
+    assert out["selected"].cpu().numpy().tolist() == g["selected"]
+    assert hashlib.sha256(np.ascontiguousarray(labels).tobytes()).hexdigest() == g["labels_sha256"]
+
+
 def test_cluster_rejects_bad_arguments(torch, rid):
     s = torch.zeros((10, 300), dtype=torch.float32, device="cuda")
     with pytest.raises(rid.RidError):

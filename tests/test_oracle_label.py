@@ -54,3 +54,24 @@ def test_compensated_sum_matches_exact_sum():
     got = O._neumaier_sum(x, axis=1)
     exact = np.array([math.fsum(r) for r in x])
     assert np.all(np.abs(got - exact) <= 2 * np.spacing(np.abs(exact)))
+
+
+def test_block_standard_error_closed_form():
+    """Blocks whose frames all carry one spring force: block j of 10 frames
+    at force j (j = 0..9), then 5 tail frames at force 100.  The block means
+    are 0..9, so SE = sqrt(sum (j - 4.5)^2 / 9 / 10) = sqrt(82.5 / 90) (a
+    denominator of 10 instead of 9 would give sqrt(82.5 / 100)); the tail
+    frames enter the mean force but no block.  kappa = 100 keeps every frame
+    inside (-pi, pi], so the periodic and the raw CV agree."""
+    kappa = 100.0
+    forces = np.concatenate([np.repeat(np.arange(10.0), 10), np.full(5, 100.0)])
+    traj = (-forces / kappa).reshape(1, 105, 1)      # spring = kappa (0 - s) = force
+    for mask in (1, 0):
+        F, SE, keep = O.mf_label(traj, np.zeros((1, 1)), np.array([kappa]), np.array([mask]),
+                                 0.96)
+        assert abs(F[0, 0] - (10 * 45.0 + 500.0) / 105) < 1e-12
+        assert abs(SE[0, 0] - math.sqrt(82.5 / 90)) < 1e-12
+        assert abs(SE[0, 0] - math.sqrt(82.5 / 100)) > 0.04
+        assert keep[0] == 1                            # 0.957 <= 0.96
+    _, _, keep = O.mf_label(traj, np.zeros((1, 1)), np.array([kappa]), np.array([1]), 0.95)
+    assert keep[0] == 0
