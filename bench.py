@@ -252,43 +252,112 @@ def pmc_summary(fetch_dir, write_dir, out_path):
     print(json.dumps(res, indent=1))
 
 
-def cpu_baseline(case, budget_s=12.0):
-    """The FP64 oracle on the same batch, repeated for about budget_s."""
-    from oracle import rid_oracle as O
+def sample_outputs(case, n_sample, seed=0):
+    """Host copies of the last bias-force call's outputs for a seeded sample
+    of walkers (for the accuracy check of the CPU-baseline leg)."""
+    B = case["B"]
+    rows = np.sort(np.random.default_rng(seed).choice(B, min(n_sample, B), replace=False))
+    o = case["out"]
+    return {"rows": rows, "pos": case["pos"][rows], "sys": case["sys"],
+            "params": case["params"], "widths": case["widths"], "K": case["K"],
+            "F": o["F"].cpu().numpy()[rows], "eps": o["eps"].cpu().numpy()[rows],
+            "sigma": o["sigma"].cpu().numpy()[rows]}
+
+
+def _cpu_info():
+    info = {"nproc": os.cpu_count()}
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
-    sys_ = case["sys"]
-    models = ridgen.unpack_params(case["params"], 2 * sys_.n_cv, case["widths"], case["K"])
-    sub = case["pos"][:256].astype(np.float64)
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return info
+
+
+def _time_oracle(O, sys_, models, sub, budget_s):
     reps, walkers = 0, 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
         O.bias_force(sub, sys_.quads, models, 2.0, 3.0)
         reps += 1
         walkers += len(sub)
-    dt = time.perf_counter() - t0
-    return {"value": walkers / dt, "unit": "walker-steps/s", "cores": int(cores),
+    return walkers / (time.perf_counter() - t0), reps
+
+
+def cpu_baseline(case, samples, budget_s=10.0):
+    """CPU-baseline leg: the FP64 oracle timed on the host on a bounded
+    sample of the headline workload, with numpy's BLAS threads (the matrix
+    products) and with one thread; then, on seeded samples of walkers of
+    each benchmarked bias line, the oracle's forces beside the GPU's (max
+    normwise per-walker and rms relative force error, eps error).  The
+    oracle is test infrastructure: this leg is the only part of the
+    benchmark that runs it."""
+    from oracle import rid_oracle as O
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threadpool_limits, blas = None, 1
+    sys_ = case["sys"]
+    models = ridgen.unpack_params(case["params"], 2 * sys_.n_cv, case["widths"], case["K"])
+    sub = case["pos"][:256].astype(np.float64)
+    v_all, reps = _time_oracle(O, sys_, models, sub, budget_s)
+    single = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            v1, reps1 = _time_oracle(O, sys_, models, sub, budget_s / 2)
+        single = {"value": v1, "unit": "walker-steps/s", "threads": 1,
+                  "sample": f"{reps1} x 256 walkers"}
+    acc = {}
+    for name, smp in samples.items():
+        sm = smp["sys"]
+        mods = ridgen.unpack_params(smp["params"], 2 * sm.n_cv, smp["widths"], smp["K"])
+        ref = O.bias_force(smp["pos"].astype(np.float64), sm.quads, mods, 2.0, 3.0)
+        acc[name] = {"walkers_sampled": int(len(smp["rows"])),
+                     "max_rel_force_err": O.max_rel_err(smp["F"], ref["F"]),
+                     "rms_rel_force_err": O.rms_rel_err(smp["F"], ref["F"]),
+                     "max_rel_eps_err": float(np.max(np.abs(smp["eps"] - ref["eps"]) / ref["eps"])),
+                     "regime_agreement_at_2_3": float(np.mean(
+                         O.switch(smp["eps"].astype(np.float64), 2.0, 3.0)[1] == ref["regime"]))}
+    return {"value": v_all, "unit": "walker-steps/s", "cores": int(blas),
             "kind": "oracle",
-            "sample": f"{reps} x 256 walkers of the same workload (FP64 numpy oracle, "
-                      f"{dt:.1f} s)"}
+            "sample": f"{reps} x 256 walkers of the headline workload (FP64 numpy oracle; "
+                      f"its matrix products use {blas} BLAS threads, the per-CV loops one)",
+            "single_thread": single, "host": _cpu_info(),
+            "accuracy_vs_oracle": acc}
 
 
-def bench_precision(rid, torch, sys20, prec, name, steps, warmup):
+PRECISION_ARITH = {
+    "BF16": "hidden-layer forward GEMMs on BF16 MFMA, first layer and reverse sweep on "
+            "FP16 MFMA, FP32 accumulate, FP32 tanh' arithmetic (stored FP16), FP32 switch, "
+            "FP64 variance",
+    "FP16": "every GEMM on FP16 MFMA, FP32 accumulate, FP32 tanh' arithmetic (stored FP16), "
+            "FP32 switch, FP64 variance",
+    "BF16_ALL": "every GEMM operand BF16 (the plain BF16 form, for comparison), FP32 "
+                "accumulate, tanh' stored BF16, FP32 switch, FP64 variance",
+    "FP32": "every GEMM on FP32 MFMA (the FP32 path at the precision form's shape)",
+}
+
+
+def bench_precision(rid, torch, sys20, prec, name, steps, warmup, samples):
+    """The precision form's shape (8 x [512 x 4], 16384 walkers) in one
+    arithmetic; its sampled outputs go to the CPU-baseline leg's accuracy
+    check."""
     Bb, Kb, wb = 16384, 8, [512] * 4
     cb = build_case(rid, torch, sys20, Bb, Kb, wb, prec)
     el, kern = time_bias(rid, torch, cb, steps, warmup)
+    samples[name.lower()] = sample_outputs(cb, 128)
     fl = mlp_flops_per_walker(sys20.n_cv, wb, Kb) * Bb
     ach = fl / (kern["mlp"] * 1e-3) / 1e12
+    peak = FP32_PEAK_TFLOPS if name == "FP32" else BF16_PEAK_TFLOPS
     return {
-        "workload": f"same chain; ensemble 8 x [512 x 4], {name} MFMA / FP32 accumulate / "
-                    "FP32 tanh' and switch / FP64 variance; 16384 walkers (CVs encoded "
-                    "once by cv_eval, then mlp_kernel)",
+        "workload": f"same chain; ensemble 8 x [512 x 4], {PRECISION_ARITH[name]}; 16384 "
+                    "walkers (CVs encoded once by cv_eval, then mlp_kernel)",
         "value": Bb * steps / el, "unit": "walker-steps/s", "ms_per_step": 1e3 * el / steps,
-        "roofline": {"bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS,
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": peak,
+                     "unit": "TFLOP/s", "frac": ach / peak,
                      "traffic": traffic_for(f"mlp_{name.lower()}_8x512_b16384"),
                      "avg_launch_us": kern["mlp"] * 1e3, "flop_per_launch": fl},
         "kernels_us": {k: v * 1e3 for k, v in kern.items()},
@@ -654,14 +723,22 @@ def main():
         "kernel_events": f"1 call in {EVENT_EVERY} of the timed region",
         "latency_us_per_call": ms_step * 1e3,
     }
+    samples = {"fp32_headline": sample_outputs(case, 128)}
     if not args.no_extra:
         steps_b = max(10, args.steps // 10)
         wb = max(3, args.warmup // 4)
         log("precision forms")
         rec["precision_form"] = bench_precision(rid, torch, sys20, rid.RID_BF16, "BF16",
-                                                steps_b, wb)
+                                                steps_b, wb, samples)
         rec["precision_form_fp16"] = bench_precision(rid, torch, sys20, rid.RID_FP16, "FP16",
-                                                     steps_b, wb)
+                                                     steps_b, wb, samples)
+        rec["precision_form_bf16_all"] = bench_precision(rid, torch, sys20, rid.RID_BF16_ALL,
+                                                         "BF16_ALL", steps_b, wb, samples)
+        rec["precision_form_fp32"] = bench_precision(rid, torch, sys20, rid.RID_FP32, "FP32",
+                                                     max(4, steps_b // 8), max(2, wb // 8),
+                                                     samples)
+        rec["precision_form"]["speedup_vs_fp32_same_shape"] = (
+            rec["precision_form"]["value"] / rec["precision_form_fp32"]["value"])
         log("network and CV variants")
         rec["variants"] = bench_variants(rid, torch, sys20, steps_b, wb)
         log("conservative switching")
@@ -678,8 +755,16 @@ def main():
             log("serving")
             rec["serving"] = bench_serving(rid)
     if not args.no_cpu_baseline:
-        log("cpu baseline")
-        rec["cpu_baseline"] = cpu_baseline(case)
+        log("cpu baseline and sampled accuracy")
+        rec["cpu_baseline"] = cpu_baseline(case, samples)
+        # each line's force error against the FP64 oracle, from that leg
+        acc = rec["cpu_baseline"]["accuracy_vs_oracle"]
+        rec["accuracy"] = acc.get("fp32_headline")
+        for key, name in (("precision_form", "bf16"), ("precision_form_fp16", "fp16"),
+                          ("precision_form_bf16_all", "bf16_all"),
+                          ("precision_form_fp32", "fp32")):
+            if key in rec and name in acc:
+                rec[key]["accuracy"] = acc[name]
     print(json.dumps(rec), flush=True)
 
 

@@ -20,9 +20,19 @@
 //  * The activation tile (shared by all waves) lives in LDS, ping-ponged
 //    between two buffers so each layer needs one barrier; it holds x, then
 //    h_1 .. h_L, then the reverse-sweep vectors v_l.
-//  * tanh'(z_l) = 1 - h_l^2 is kept in VGPRs for the reverse sweep (FP32 for
-//    the FP32 path; the operand format for the 16-bit paths, whose 64-walker
-//    tiles would not fit an FP32 copy): nothing goes to HBM between layers.
+//  * tanh'(z_l) = 1 - h_l^2 is computed in FP32 and kept in VGPRs for the
+//    reverse sweep (FP32 for the FP32 path; FP16 for the 16-bit plans except
+//    the all-BF16 one, whose 64-walker tiles would not fit an FP32 copy):
+//    nothing goes to HBM between layers.
+//  * 16-bit arithmetic plans (Plan below) choose the operand format of the
+//    first layer, of the hidden-layer forward GEMMs and of the reverse sweep
+//    separately.  The precision form runs the hidden-layer forward GEMMs in
+//    BF16 and the first layer and the reverse sweep in FP16 (same MFMA rate):
+//    the mean force is linear in the reverse sweep's roundings but sees the
+//    forward sweep's only through tanh', so the reverse sweep's operand
+//    format sets most of the force error.  The reverse vectors carry a
+//    per-member power-of-two scale (exact) that keeps them inside FP16's
+//    range.
 //  * Forward weights and biases are stored pre-multiplied by 2/ln 2, so the
 //    epilogue evaluates tanh from exp2 of the GEMM output and one reciprocal.
 //  * Blocks are mapped XCD-aware: when K divides 8, member k runs on XCDs
@@ -83,6 +93,23 @@ struct F16 {
   }
   __device__ static inline T from_float(float v) { return (_Float16)v; }
 };
+
+// Arithmetic plan of the MLP kernel: MFMA operand format of the first layer
+// (P1), of the hidden-layer forward GEMMs (PH) and of the reverse sweep (PB),
+// and the storage type of tanh' between the sweeps (S).  The formats of one
+// plan share an element size, so the activation tile's layout is the same
+// for every layer.
+template <class P1_, class PH_, class PB_, class S_>
+struct Plan {
+  using P1 = P1_;
+  using PH = PH_;
+  using PB = PB_;
+  using S = S_;
+};
+using PlanF32 = Plan<F32, F32, F32, float>;
+using PlanBF16 = Plan<F16, BF16, F16, _Float16>;      // the BF16 precision form
+using PlanF16 = Plan<F16, F16, F16, _Float16>;
+using PlanBF16All = Plan<BF16, BF16, BF16, __bf16>;   // every operand BF16
 
 // Four consecutive elements of type T as one register group.
 template <class T> struct Pack4;
@@ -155,6 +182,7 @@ struct MlpArgs {
   const float* bias;   // [K][L][NP]
   const float* wo;     // [K][NP]
   const float* bo;     // [K]
+  const float* vscale; // [K][2] power-of-two scale folded into wo and its inverse
   float* A_out;        // [K][B]
   float* g_out;        // [K][B][n]
   // LDS layout (byte offsets; activation buffer 0 starts at 0)
@@ -384,10 +412,19 @@ __host__ __device__ constexpr int u0_split() {
 
 // GRAD = false: the free energies only (the forward sweep, no tanh' stash,
 // no reverse sweep, no g output).
-template <class P, int NP, int RT, int NW, int LM, bool FROM_POS, bool GRAD, bool RES>
+template <class PL, int NP, int RT, int NW, int LM, bool FROM_POS, bool GRAD, bool RES>
 __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
+  using P = typename PL::PH;         // hidden-layer forward GEMMs
+  using P1 = typename PL::P1;        // first layer
+  using PB = typename PL::PB;        // reverse sweep
   using T = typename P::T;
-  using SP = Pack4<T>;
+  using T1 = typename P1::T;
+  using TB = typename PB::T;
+  static_assert(sizeof(T1) == sizeof(T) && sizeof(TB) == sizeof(T) && P1::KF == P::KF &&
+                    PB::KF == P::KF, "one element size per plan");
+  using SP = Pack4<T>;               // hidden activations
+  using SB = Pack4<TB>;              // reverse vectors
+  using SS = Pack4<typename PL::S>;  // tanh' between the sweeps
   static_assert(!RES || sizeof(T) == 4, "residual form: FP32 tiles");
   constexpr int KF = P::KF;
   constexpr int CT = NP / (16 * NW);
@@ -407,6 +444,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   const int AS = AW + RID_ACT_PAD_BYTES / (int)sizeof(T);    // row stride (+16 bytes)
   const int BUF = R * AS;                     // elements per ping-pong buffer
   T* act = reinterpret_cast<T*>(smem);
+  T1* act1 = reinterpret_cast<T1*>(smem);      // the input tile (first layer's format)
   float* u0 = reinterpret_cast<float*>(smem + p.off_u0);
   const int US = XP + 4;
   float* red = reinterpret_cast<float*>(smem + p.off_red);   // [NW][R]
@@ -503,14 +541,14 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
           }
           xs[i * X2 + c] = cs;
           xs[i * X2 + n + c] = sn;
-          act[i * AS + c] = P::from_float(cs);
-          act[i * AS + n + c] = P::from_float(sn);
+          act1[i * AS + c] = P1::from_float(cs);
+          act1[i * AS + n + c] = P1::from_float(sn);
         }
       }
       __syncthreads();
     }
     for (int i = wave; i < R; i += NW)
-      for (int c = X2 + lane; c < XP; c += 64) act[i * AS + c] = P::from_float(0.f);
+      for (int c = X2 + lane; c < XP; c += 64) act1[i * AS + c] = P1::from_float(0.f);
   } else {
     // rows of the tile go to the waves in turn; a wave's lanes cover the row
     // in float2 columns (X2 is even), padding columns [X2, XP) get zeros.
@@ -532,7 +570,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
 #pragma unroll
         for (int j = 0; j < RW; ++j) {
           const int i = wave * RW + j;
-          Pack2<T>::store(act + i * AS + 2 * col, v[j].x, v[j].y);
+          Pack2<T1>::store(act1 + i * AS + 2 * col, v[j].x, v[j].y);
           if (col < h2) *reinterpret_cast<float2*>(xs + i * X2 + 2 * col) = v[j];
         }
       }
@@ -541,7 +579,22 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   __syncthreads();
 
   const int wl = lane & 15;          // walker within a 16-walker tile
-  SP st[LM - 1][RT][CT];             // tanh' of hidden layers 1..L-1
+  SS st[LM - 1][RT][CT];             // tanh' of hidden layers 1..L-1
+  // 16-bit plans: the packed w_o carries a per-member power-of-two scale
+  // (exact), so the reverse vectors start scaled; the scale is undone where
+  // A and g are written (uniform loads of its inverse there)
+  constexpr bool SCALED = sizeof(T) == 2;
+  auto a_total = [&](int i) {
+    if constexpr (SCALED) {
+      float a = 0.f;
+      for (int w = 0; w < NW; ++w) a += red[w * R + i];
+      return __builtin_fmaf(a, p.vscale[2 * k + 1], p.bo[k]);
+    } else {
+      float a = p.bo[k];
+      for (int w = 0; w < NW; ++w) a += red[w * R + i];
+      return a;
+    }
+  };
   int cur = 0;
 
   // ---------------- forward: h_l = tanh(W_l h_{l-1} + b_l) ----------------
@@ -590,9 +643,9 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
     }
     apart[rt] += w4[0] * h[0] + w4[1] * h[1] + w4[2] * h[2] + w4[3] * h[3];
     if constexpr (GRAD) {
-      SP o;
+      SB o;
       o.set(w4 * d);
-      o.store(out + (rt * 16 + wl) * AS + u);
+      o.store(reinterpret_cast<TB*>(out) + (rt * 16 + wl) * AS + u);
     }
   };
   // the GEMM after forward layer l: forward layer l+1, or the first backward
@@ -612,7 +665,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
     for (int c = 0; c < CT; ++c)
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) acc[rt][c] = bnext[c];
-    gemm_run<P, RT, CT, PD>(acc, wr, act, AS, wsrc(p.fwd_off[0]), XP / KF, lane);
+    gemm_run<P1, RT, CT, PD>(acc, wr, act1, AS, wsrc(p.fwd_off[0]), XP / KF, lane);
     if (L > 1) {
       ring_preload<PDH, CH>(wh, next_after_fwd(0), NK, lane);
       load_bias(1);
@@ -680,8 +733,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   if constexpr (!GRAD) {
     __syncthreads();
     for (int i = threadIdx.x; i < R; i += NW * 64) {
-      float a = p.bo[k];
-      for (int w = 0; w < NW; ++w) a += red[w * R + i];
+      const float a = a_total(i);
       if (row0 + i < p.B) p.A_out[(size_t)k * p.B + row0 + i] = a;
     }
     return;
@@ -692,14 +744,14 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   // dA/dh_{l-1} = W_l^T v_l + dA/dh_l (kept per lane in ares) and
   // v_{l-1} = dA/dh_{l-1} * tanh'_{l-1}.
   auto bwd_tile = [&](int l, int rt, int c, const f4& y, T* out) {
-    SP o;
+    SB o;
     if constexpr (RES) {
       ares[rt][c] += y;
       o.set(ares[rt][c] * st[l - 1][rt][c].get());
     } else {
       o.set(y * st[l - 1][rt][c].get());
     }
-    o.store(out + (rt * 16 + wl) * AS + (jt0 + c) * 16 + uq);
+    o.store(reinterpret_cast<TB*>(out) + (rt * 16 + wl) * AS + (jt0 + c) * 16 + uq);
   };
 #pragma unroll
   for (int l = LM - 1; l >= 1; --l) {
@@ -711,8 +763,9 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[rt][c] = f4{0.f, 0.f, 0.f, 0.f};
-      gemm_hidden<P, RT, CT, NPASS, PDH, NK>(acc, wh, in, AS, wsrc(p.bwd_off[l]), l >= 2,
-                                             wsrc(p.bwd_off[l >= 2 ? l - 1 : l]), lane);
+      gemm_hidden<PB, RT, CT, NPASS, PDH, NK>(acc, wh, reinterpret_cast<const TB*>(in), AS,
+                                              wsrc(p.bwd_off[l]), l >= 2,
+                                              wsrc(p.bwd_off[l >= 2 ? l - 1 : l]), lane);
 #pragma unroll
       for (int c = 0; c < CT; ++c)
 #pragma unroll
@@ -736,9 +789,9 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
         f4 a1[RT][1];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) a1[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
-        gemm_tiles<P, RT, 1, 7>(
-            a1, in, AS, WSrc{rsrc, (int)p.bwd_off[0] + t * kFragBytes, JT0 * kFragBytes}, NK,
-            lane);
+        gemm_tiles<PB, RT, 1, 7>(
+            a1, reinterpret_cast<const TB*>(in), AS,
+            WSrc{rsrc, (int)p.bwd_off[0] + t * kFragBytes, JT0 * kFragBytes}, NK, lane);
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
           *reinterpret_cast<f4*>(u0 + (rt * 16 + wl) * US + t * 16 + uq) = a1[rt][0];
@@ -746,10 +799,10 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
     }
     __syncthreads();
     for (int i = threadIdx.x; i < R; i += NW * 64) {
-      float a = p.bo[k];
-      for (int w = 0; w < NW; ++w) a += red[w * R + i];
+      const float a = a_total(i);
       if (row0 + i < p.B) p.A_out[(size_t)k * p.B + row0 + i] = a;
     }
+    const float ivs = SCALED ? p.vscale[2 * k + 1] : 1.f;
     for (int e = threadIdx.x; e < R * n; e += NW * 64) {
       const int i = e / n, c = e - i * n;
       const int row = row0 + i;
@@ -760,7 +813,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
         if constexpr (!FROM_POS) {
           if (p.raw && p.raw[c]) gv = u0[i * US + c];
         }
-        p.g_out[((size_t)k * p.B + row) * n + c] = gv;
+        p.g_out[((size_t)k * p.B + row) * n + c] = SCALED ? gv * ivs : gv;
       }
     }
   } else {
@@ -775,8 +828,8 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
         f4 a1[RT][1];
   #pragma unroll
         for (int rt = 0; rt < RT; ++rt) a1[rt][0] = f4{0.f, 0.f, 0.f, 0.f};
-        gemm_tiles<P, RT, 1, 7>(
-            a1, in + q * KQ * KF, AS,
+        gemm_tiles<PB, RT, 1, 7>(
+            a1, reinterpret_cast<const TB*>(in) + q * KQ * KF, AS,
             WSrc{rsrc, (int)p.bwd_off[0] + t * kFragBytes + q * KQ * JT0 * kFragBytes,
                  JT0 * kFragBytes},
             KQ, lane);
@@ -794,8 +847,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
     __syncthreads();
     // A = sum of the waves' partial dot products + b_o
     for (int i = threadIdx.x; i < R; i += NW * 64) {
-      float a = p.bo[k];
-      for (int w = 0; w < NW; ++w) a += red[w * R + i];
+      const float a = a_total(i);
       if (row0 + i < p.B) p.A_out[(size_t)k * p.B + row0 + i] = a;
     }
     // chain to the angles: g_i = -sin s_i u0[i] + cos s_i u0[n+i]
@@ -807,6 +859,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
         for (int q = 1; q < PARTS; ++q) v += u0[q * R * US + i * US + c];
         return v;
       };
+      const float ivs = SCALED ? p.vscale[2 * k + 1] : 1.f;
       for (int e = threadIdx.x; e < R * n; e += NW * 64) {
         const int i = e / n, c = e - i * n;
         const int row = row0 + i;
@@ -817,7 +870,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
           if constexpr (!FROM_POS) {
             if (p.raw && p.raw[c]) gv = u0_at(i, c);
           }
-          p.g_out[((size_t)k * p.B + row) * n + c] = gv;
+          p.g_out[((size_t)k * p.B + row) * n + c] = SCALED ? gv * ivs : gv;
         }
       }
     };
@@ -1445,13 +1498,18 @@ struct PackLayer {
   int in, out;            // real widths
   int kin_pad;            // padded input width
   unsigned fwd_off, bwd_off;  // byte offsets inside one model's fragments
+  int fmt_fwd, fmt_bwd;   // fragment formats (FragFmt)
 };
+
+// element format of a set of MFMA fragments
+enum FragFmt { kFmtF32 = 0, kFmtBF16 = 1, kFmtF16 = 2 };
 
 struct VecArgs {
   unsigned b_off[kMaxHidden];
   int out[kMaxHidden];
   unsigned wo_off;
   int last_w;
+  int vscale_on;          // reverse vectors in a 16-bit format: scale them
 };
 
 struct PackAll {
@@ -1462,17 +1520,19 @@ struct PackAll {
 
 // One launch packs a whole ensemble: block row y < 2L packs layer y/2 in
 // direction y%2 (0: forward fragments, contraction = the layer input,
-// pre-scaled by 2/ln 2; 1: backward, contraction = the layer output); row
-// 2L packs the biases (pre-scaled), w_o and b_o, zero-padded to NP.
-template <class P>
+// pre-scaled by 2/ln 2; 1: backward, contraction = the layer output), each
+// in its plan's format; row 2L packs the biases (pre-scaled), w_o and b_o,
+// zero-padded to NP.  When the reverse sweep runs in FP16, w_o is stored
+// times a per-member power of two that puts max |w_o| in [128, 256), so
+// v_L = w_o tanh'_L and the vectors after it stay far inside FP16's range
+// (and clear of its subnormals) through the sweep; the kernel undoes the
+// scale, exactly, in A and g.  vscale[k] = (scale, 1 / scale).
 __global__ void pack_kernel(const float* master, size_t per_model, PackAll pa,
                             unsigned char* frag, size_t frag_model_bytes, float* bias,
-                            float* wo, float* bo) {
-  using T = typename P::T;
-  constexpr int KF = P::KF;
-  constexpr int E = 16 / sizeof(T);
+                            float* wo, float* bo, float* vscale) {
   const int NP = pa.NP;
   if ((int)blockIdx.y == 2 * pa.L) {
+    __shared__ float red[256];
     const VecArgs& va = pa.va;
     for (int k = blockIdx.x; k < pa.K; k += gridDim.x) {
       const float* m = master + (size_t)k * per_model;
@@ -1480,14 +1540,36 @@ __global__ void pack_kernel(const float* master, size_t per_model, PackAll pa,
         for (int j = threadIdx.x; j < NP; j += blockDim.x)
           bias[((size_t)k * pa.L + l) * NP + j] =
               j < va.out[l] ? kTanhPrescale * m[va.b_off[l] + j] : 0.f;
+      float mx = 0.f;
+      for (int j = threadIdx.x; j < va.last_w; j += blockDim.x) mx = fmaxf(mx, fabsf(m[va.wo_off + j]));
+      red[threadIdx.x] = mx;
+      __syncthreads();
+      for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+      }
+      float sc = 1.f;
+      if (va.vscale_on && red[0] > 0.f && red[0] < 3.0e38f) {
+        int ex;
+        (void)frexpf(red[0], &ex);            // red[0] = f 2^ex, f in [0.5, 1)
+        sc = ldexpf(1.f, 8 - ex);             // red[0] sc in [128, 256)
+      }
       for (int j = threadIdx.x; j < NP; j += blockDim.x)
-        wo[(size_t)k * NP + j] = j < va.last_w ? m[va.wo_off + j] : 0.f;
-      if (threadIdx.x == 0) bo[k] = m[va.wo_off + va.last_w];
+        wo[(size_t)k * NP + j] = j < va.last_w ? m[va.wo_off + j] * sc : 0.f;
+      if (threadIdx.x == 0) {
+        bo[k] = m[va.wo_off + va.last_w];
+        vscale[2 * k] = sc;
+        vscale[2 * k + 1] = 1.f / sc;         // exact: sc is a power of two
+      }
+      __syncthreads();
     }
     return;
   }
   const PackLayer& pl = pa.layer[blockIdx.y >> 1];
   const int dir = blockIdx.y & 1;
+  const int fmt = dir == 0 ? pl.fmt_fwd : pl.fmt_bwd;
+  const int KF = fmt == kFmtF32 ? 16 : 32;
+  const int E = fmt == kFmtF32 ? 4 : 8;       // elements per lane (16 bytes)
   const int kc = dir == 0 ? pl.kin_pad : NP;
   const int nc = dir == 0 ? NP : pl.kin_pad;
   const int JT = nc / 16, KT = kc / KF;
@@ -1501,22 +1583,32 @@ __global__ void pack_kernel(const float* master, size_t per_model, PackAll pa,
     const int k = (int)(f / KT);
     const float* W = master + (size_t)k * per_model + pl.w_off;
     const int col = jt * 16 + (lane & 15);
-    T out[E];
-#pragma unroll
+    float v[8];
     for (int e = 0; e < E; ++e) {
       const int kk = kt * KF + (KF / 4) * (lane >> 4) + e;
       // W is [out][in]; forward: (unit col = out, contraction kk = in);
       // backward: (unit col = in, contraction kk = out)
       const int o = dir == 0 ? col : kk;
       const int i = dir == 0 ? kk : col;
-      float v = (o < pl.out && i < pl.in) ? W[(size_t)o * pl.in + i] : 0.f;
-      if (dir == 0) v *= kTanhPrescale;
-      out[e] = P::from_float(v);
+      v[e] = (o < pl.out && i < pl.in) ? W[(size_t)o * pl.in + i] : 0.f;
+      if (dir == 0) v[e] *= kTanhPrescale;
+    }
+    uint4 out;
+    if (fmt == kFmtF32) {
+      out = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                       __float_as_uint(v[3]));
+    } else {
+      unsigned short hv[8];
+      for (int e = 0; e < 8; ++e)
+        hv[e] = fmt == kFmtBF16 ? __builtin_bit_cast(unsigned short, (__bf16)v[e])
+                                : __builtin_bit_cast(unsigned short, (_Float16)v[e]);
+      out = make_uint4(hv[0] | (unsigned)hv[1] << 16, hv[2] | (unsigned)hv[3] << 16,
+                       hv[4] | (unsigned)hv[5] << 16, hv[6] | (unsigned)hv[7] << 16);
     }
     unsigned char* dst = frag + (size_t)k * frag_model_bytes +
                          (dir == 0 ? pl.fwd_off : pl.bwd_off) +
                          (((size_t)kt * JT + jt) * 64 + lane) * 16;
-    *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(out);
+    *reinterpret_cast<uint4*>(dst) = out;
   }
 }
 
@@ -1550,8 +1642,9 @@ size_t mlp_layout(int R, int NW, int AS, size_t tsize, int XP, int n, int U,
   return off;
 }
 
-template <class P, int NP, int RT, int NW, int LM>
+template <class PL, int NP, int RT, int NW, int LM>
 size_t lds_bytes(const rid_ensemble_impl& e, const TorsionInput* tin) {
+  using P = typename PL::PH;
   using T = typename P::T;
   MlpArgs a{};
   const int AW = NP > e.XP ? NP : e.XP;
@@ -1560,12 +1653,13 @@ size_t lds_bytes(const rid_ensemble_impl& e, const TorsionInput* tin) {
                     tin ? tin->sys->n_uniq : 0, tin != nullptr, NP, u0_split<P, NP>(), a);
 }
 
-template <class P, int NP, int RT, int NW, int LM, bool RES = false>
+template <class PL, int NP, int RT, int NW, int LM, bool RES = false>
 rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
                    float* A_out, float* g_out, const TorsionInput* tin,
                    hipStream_t st) {
   static size_t attr_bytes[3] = {0, 0, 0};   // dynamic-LDS limit set per kernel
   constexpr int R = 16 * RT;
+  using P = typename PL::PH;
   using T = typename P::T;
   const bool from_pos = tin != nullptr;
   const int AW = NP > e.XP ? NP : e.XP;
@@ -1588,9 +1682,9 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
   // without g_out only the free energies are computed (plain input only)
   const bool grad = g_out != nullptr;
   if (!grad && from_pos) return fail(RID_EUNSUPPORTED, "energy-only path takes the encoding");
-  auto kern = !grad    ? mlp_kernel<P, NP, RT, NW, LM, false, false, RES>
-              : from_pos ? mlp_kernel<P, NP, RT, NW, LM, true, true, RES>
-                         : mlp_kernel<P, NP, RT, NW, LM, false, true, RES>;
+  auto kern = !grad    ? mlp_kernel<PL, NP, RT, NW, LM, false, false, RES>
+              : from_pos ? mlp_kernel<PL, NP, RT, NW, LM, true, true, RES>
+                         : mlp_kernel<PL, NP, RT, NW, LM, false, true, RES>;
   const int ki = grad ? (from_pos ? 1 : 0) : 2;
   if (lds > 64 * 1024 && lds > attr_bytes[ki]) {
     RID_HIP(hipFuncSetAttribute((const void*)kern,
@@ -1605,7 +1699,7 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
     a.fwd_off[l] = (unsigned)e.layers[l].fwd_off;
     a.bwd_off[l] = (unsigned)e.layers[l].bwd_off;
   }
-  a.bias = e.d_bias; a.wo = e.d_wo; a.bo = e.d_bo;
+  a.bias = e.d_bias; a.wo = e.d_wo; a.bo = e.d_bo; a.vscale = e.d_vscale;
   a.A_out = A_out; a.g_out = g_out;
   a.raw = e.d_raw;
   if (from_pos) {
@@ -1630,6 +1724,7 @@ rid_status run_mlp(const rid_ensemble_impl& e, const float* x, int B,
 template <class P, int NP, int NW>
 rid_status run_16bit(const rid_ensemble_impl& e, const float* x, int B, float* A_out,
                      float* g_out, const TorsionInput* t, hipStream_t st) {
+  // P: the arithmetic plan
   if (e.L <= 4) {
     if (lds_bytes<P, NP, 4, NW, 4>(e, t) <= 160 * 1024)
       return run_mlp<P, NP, 4, NW, 4>(e, x, B, A_out, g_out, t, st);
@@ -1671,29 +1766,34 @@ rid_status dispatch(const rid_ensemble_impl& e, const float* x, int B, float* A_
     if (e.prec != RID_FP32)
       return fail(RID_EUNSUPPORTED, "residual connections need an FP32 ensemble");
     switch (e.NP) {
-      case 64:  return run_mlp<F32, 64, 1, 1, 6, true>(e, x, B, A_out, g_out, t, st);
-      case 128: return run_mlp<F32, 128, 1, 2, 6, true>(e, x, B, A_out, g_out, t, st);
-      case 256: return run_mlp<F32, 256, 1, RID_F32_NW256, 6, true>(e, x, B, A_out, g_out, t, st);
-      case 512: return run_mlp<F32, 512, 1, 8, 6, true>(e, x, B, A_out, g_out, t, st);
+      case 64:  return run_mlp<PlanF32, 64, 1, 1, 6, true>(e, x, B, A_out, g_out, t, st);
+      case 128: return run_mlp<PlanF32, 128, 1, 2, 6, true>(e, x, B, A_out, g_out, t, st);
+      case 256: return run_mlp<PlanF32, 256, 1, RID_F32_NW256, 6, true>(e, x, B, A_out, g_out, t, st);
+      case 512: return run_mlp<PlanF32, 512, 1, 8, 6, true>(e, x, B, A_out, g_out, t, st);
     }
     return fail(RID_EUNSUPPORTED, "no kernel for this padded width");
   }
   if (e.prec == RID_FP32) {
     switch (e.NP) {
-      case 64:  return run_mlp<F32, 64, 1, 1, 6>(e, x, B, A_out, g_out, t, st);
-      case 128: return run_mlp<F32, 128, 1, 2, 6>(e, x, B, A_out, g_out, t, st);
+      case 64:  return run_mlp<PlanF32, 64, 1, 1, 6>(e, x, B, A_out, g_out, t, st);
+      case 128: return run_mlp<PlanF32, 128, 1, 2, 6>(e, x, B, A_out, g_out, t, st);
       case 256:
         // free energies only (MCMC): 32-walker tiles feed two MFMA tiles from
         // each weight fragment, taken while they still keep 3/4 of the CUs busy
         if (!g_out && !t && (long long)((B + 31) / 32) * e.K >= 192)
-          return run_mlp<F32, 256, 2, RID_F32_NW256, 6>(e, x, B, A_out, g_out, t, st);
-        return run_mlp<F32, 256, 1, RID_F32_NW256, 6>(e, x, B, A_out, g_out, t, st);
-      case 512: return run_mlp<F32, 512, 1, 8, 6>(e, x, B, A_out, g_out, t, st);
+          return run_mlp<PlanF32, 256, 2, RID_F32_NW256, 6>(e, x, B, A_out, g_out, t, st);
+        return run_mlp<PlanF32, 256, 1, RID_F32_NW256, 6>(e, x, B, A_out, g_out, t, st);
+      case 512: return run_mlp<PlanF32, 512, 1, 8, 6>(e, x, B, A_out, g_out, t, st);
     }
     return fail(RID_EUNSUPPORTED, "no kernel for this padded width");
   }
-  if (e.prec == RID_BF16) return launch_16bit<BF16>(e, x, B, A_out, g_out, t, st);
-  return launch_16bit<F16>(e, x, B, A_out, g_out, t, st);
+  switch (e.prec) {
+    case RID_BF16:     return launch_16bit<PlanBF16>(e, x, B, A_out, g_out, t, st);
+    case RID_FP16:     return launch_16bit<PlanF16>(e, x, B, A_out, g_out, t, st);
+    case RID_BF16_ALL: return launch_16bit<PlanBF16All>(e, x, B, A_out, g_out, t, st);
+    default: break;
+  }
+  return fail(RID_EUNSUPPORTED, "unknown precision");
 }
 
 size_t hvp_layout(int NP, int XP, int n, HvpArgs& a) {
@@ -1881,20 +1981,30 @@ rid_status pack_ensemble_weights(rid_ensemble_impl& e, hipStream_t st) {
     pl.kin_pad = e.layers[l].kin_pad;
     pl.fwd_off = (unsigned)e.layers[l].fwd_off;
     pl.bwd_off = (unsigned)e.layers[l].bwd_off;
+    // the plan's formats: first layer, hidden-layer forward, reverse sweep
+    switch (e.prec) {
+      case RID_BF16:
+        pl.fmt_fwd = l == 0 ? kFmtF16 : kFmtBF16;
+        pl.fmt_bwd = kFmtF16;
+        break;
+      case RID_FP16:
+        pl.fmt_fwd = pl.fmt_bwd = kFmtF16;
+        break;
+      case RID_BF16_ALL:
+        pl.fmt_fwd = pl.fmt_bwd = kFmtBF16;
+        break;
+      default:
+        pl.fmt_fwd = pl.fmt_bwd = kFmtF32;
+        break;
+    }
     prev = pl.out;
   }
   pa.va.wo_off = off;
   pa.va.last_w = prev;
+  pa.va.vscale_on = e.prec == RID_BF16 || e.prec == RID_FP16;
   const dim3 grid(256, 2 * L + 1), block(256);
-  if (e.prec == RID_FP32)
-    hipLaunchKernelGGL(pack_kernel<F32>, grid, block, 0, st, e.d_master, e.per_model, pa,
-                       e.d_frag, e.frag_bytes_per_model, e.d_bias, e.d_wo, e.d_bo);
-  else if (e.prec == RID_BF16)
-    hipLaunchKernelGGL(pack_kernel<BF16>, grid, block, 0, st, e.d_master, e.per_model, pa,
-                       e.d_frag, e.frag_bytes_per_model, e.d_bias, e.d_wo, e.d_bo);
-  else
-    hipLaunchKernelGGL(pack_kernel<F16>, grid, block, 0, st, e.d_master, e.per_model, pa,
-                       e.d_frag, e.frag_bytes_per_model, e.d_bias, e.d_wo, e.d_bo);
+  hipLaunchKernelGGL(pack_kernel, grid, block, 0, st, e.d_master, e.per_model, pa, e.d_frag,
+                     e.frag_bytes_per_model, e.d_bias, e.d_wo, e.d_bo, e.d_vscale);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }

@@ -85,7 +85,7 @@ struct ProfScope {
 // stored as 64 lanes x 16 bytes: lane l holds column (l % 16) and the KF/4
 // consecutive contraction indices starting at (KF/4) * (l / 16).
 //   FP32 (v_mfma_f32_16x16x4_f32 issued four times): KF = 16, 4 floats/lane
-//   BF16 (v_mfma_f32_16x16x32_bf16):                KF = 32, 8 bf16/lane
+//   BF16 / FP16 (v_mfma_f32_16x16x32_{bf16,f16}):    KF = 32, 8 values/lane
 // ---------------------------------------------------------------------------
 constexpr int kFragBytes = 1024;
 inline int kf_of(rid_precision p) { return p == RID_FP32 ? 16 : 32; }
@@ -152,6 +152,7 @@ struct rid_ensemble_impl {
   float* d_bias = nullptr;           // [K][L][NP] zero padded
   float* d_wo = nullptr;             // [K][NP]
   float* d_bo = nullptr;             // [K]
+  float* d_vscale = nullptr;         // [K][2] reverse-vector scale (a power of two), inverse
   // scratch
   bool frag_dirty = false;           // masters changed since the last pack
   DevBuf ws_x, ws_A, ws_g, ws_train, ws_cons;

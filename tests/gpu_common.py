@@ -6,14 +6,25 @@ Errors are measured against the FP64 oracle on the same FP32-rounded inputs;
 the batch.
 
 FP32 path: max <= 1e-5.
-16-bit forms (tolerance derived from the arithmetic): every one of the 8
-GEMM stages of a 4-layer forward + reverse sweep rounds both MFMA operands
-to the 16-bit format, a relative perturbation of about sqrt(2) u per stage
-(u = 2^-9 for BF16, 2^-12 for FP16), independent across stages, so the
-mean force carries about sqrt(8 stages x 2 operands) u = 4u rms relative error:
-7.8e-3 for BF16 and 1e-3 for FP16.  The per-walker max over thousands of
-walkers runs to about 3x the rms.  Bounds: BF16 max 2.5e-2, rms 1e-2;
-FP16 max 1e-2, rms 2e-3."""
+16-bit forms (tolerances derived from the arithmetic).  Rounding a value to
+a format with p significant bits perturbs it by a relative amount of rms
+about 2^-p / sqrt(3) x 0.7 (over a binade): 1.6e-3 for BF16 (p = 8), 2e-4
+for FP16 (p = 11).  A 4-layer network has 19 rounding sites: the encoding,
+each layer's forward weights, the 3 stored hidden activations, the 3 stored
+tanh', the 4 reverse vectors and the 4 layers' reverse weights.  Each
+reverse-sweep site perturbs the mean force linearly by about that rms
+relative amount; the forward sites enter only through tanh' and are damped
+(their relative effect is about a third as large).  Summed in quadrature
+over independent sites, and with the normwise per-walker maximum about 3x
+the rms over a few hundred walkers:
+  * all-BF16 form: 12 reverse sites x 1.6e-3 -> rms ~5.5e-3, max ~1.8e-2;
+    bounds max 2.5e-2, rms 1e-2;
+  * BF16 precision form (BF16 hidden-layer forward GEMMs, FP16 first layer
+    and reverse sweep, FP16 tanh'): 6 damped BF16 forward sites -> rms
+    ~1e-3, max ~3e-3; bounds max 1e-2 (the precision form's target), rms 3e-3;
+  * FP16 form: rms ~7e-4, max ~2e-3; bounds max 1e-2, rms 2e-3.
+A rounding-site emulation of these plans in numpy reproduces the GPU's
+measured all-BF16 error (max 1.77e-2, rms 5.57e-3 at 300 walkers)."""
 from __future__ import annotations
 
 import numpy as np
@@ -22,7 +33,7 @@ import ridgen
 from oracle import rid_oracle as O
 
 FP32_TOL = 1e-5
-HALF_TOL = {"bf16": (2.5e-2, 1e-2), "fp16": (1e-2, 2e-3)}   # (max, rms)
+HALF_TOL = {"bf16": (1e-2, 3e-3), "fp16": (1e-2, 2e-3), "bf16_all": (2.5e-2, 1e-2)}  # (max, rms)
 
 
 def workload(kind: str, B: int, seed: int = 1, K=None, widths=None, bias_std=0.0,
