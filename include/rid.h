@@ -276,6 +276,29 @@ rid_status rid_bias_force(rid_system sys, rid_ensemble ens, const float* d_pos,
                           uint8_t* d_flags, rid_stream stream);
 
 /* ------------------------------------------------------------------------
+ * rid_bias_force_noalloc - rid_bias_force for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * rid_bias_force (bit for bit: the same kernels run), but the per-call
+ * scratch (A [K][B], g [K][B][n_cv], the CV encoding [B][2 n_cv]) lives in a
+ * fixed 32 MiB device array of the library that each GPU holds until the
+ * process ends, so the call performs no device allocation.  Limit:
+ * K*B + K*B*n_cv + 2*B*n_cv floats (each part rounded up to 64 floats) must
+ * not exceed rid_noalloc_scratch_floats() = 8388608, else RID_EINVAL before
+ * any device work (e.g. 8 members, 38 CVs: B <= 21845).  All calls on one
+ * GPU share that array: calls that may overlap on one GPU (other streams,
+ * other threads) race and must be ordered by the caller.  The ensemble's
+ * weights must already be packed (they are after create, set/load_params
+ * and every training call's next use) -- repacking after training runs
+ * in place and allocates nothing either.
+ * ------------------------------------------------------------------------ */
+rid_status rid_bias_force_noalloc(rid_system sys, rid_ensemble ens, const float* d_pos,
+                                  int B, float eps0, float eps1, float* d_force,
+                                  float* d_energy, float* d_eps, float* d_sigma,
+                                  uint8_t* d_flags, rid_stream stream);
+size_t rid_noalloc_scratch_floats(void);
+
+/* ------------------------------------------------------------------------
  * rid_bias_force_conservative - the same bias with the switch differentiated
  * too, so the force is exactly -grad E of E = -sigma(eps) Abar everywhere,
  * including the switching band ("Overall workflow setting": trust levels;

@@ -32,7 +32,8 @@ EXPORTS = (
     "rid_ensemble_set_resnet", "rid_ensemble_set_angular_mask",
     "rid_ensemble_destroy",
     "rid_cv_eval", "rid_model_dev", "rid_cluster_frames", "rid_select", "rid_bias_force",
-    "rid_bias_force_conservative", "rid_mcmc_run",
+    "rid_bias_force_conservative", "rid_bias_force_noalloc", "rid_noalloc_scratch_floats",
+    "rid_mcmc_run",
     "rid_cv_apply_force",
     "rid_mf_train_step", "rid_lr_exponential", "rid_mf_label",
     "rid_profile_enable", "rid_profile_read", "rid_mf_loss_grad", "rid_mf_grad",
@@ -94,6 +95,8 @@ def lib():
         "rid_select": (i, [vp, vp, i, f, f, i, i, i, i, vp, vp, vp, P(i), P(i), P(f), vp]),
         "rid_bias_force": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
         "rid_bias_force_conservative": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
+        "rid_bias_force_noalloc": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
+        "rid_noalloc_scratch_floats": (sz, []),
         "rid_mcmc_run": (i, [vp, vp, i, i64, i64, ctypes.c_double, f, ctypes.c_uint64, i, i, i,
                              vp, vp, vp, vp]),
         "rid_cv_apply_force": (i, [vp, vp, vp, i, vp, vp]),
@@ -317,8 +320,9 @@ def select(ens: Ensemble, s, eps0: float, threshold: float, lower: int, upper: i
 
 
 def bias_force(system: System, ens: Ensemble, pos, eps0: float, eps1: float,
-               stream=None, out=None, conservative=False):
-    """rid_bias_force (or rid_bias_force_conservative when ``conservative``):
+               stream=None, out=None, conservative=False, noalloc=False):
+    """rid_bias_force (rid_bias_force_conservative when ``conservative``,
+    rid_bias_force_noalloc when ``noalloc``):
     pos [B][n_atoms][3] -> dict(F, E, eps, sigma, flags)."""
     torch = _torch()
     B = pos.shape[0]
@@ -332,7 +336,10 @@ def bias_force(system: System, ens: Ensemble, pos, eps0: float, eps1: float,
             sigma=torch.empty(B, dtype=torch.float32, device=dev),
             flags=torch.empty(B, dtype=torch.uint8, device=dev),
         )
-    fn = lib().rid_bias_force_conservative if conservative else lib().rid_bias_force
+    if conservative and noalloc:
+        raise ValueError("the no-allocation entry point is the frozen-switch bias force")
+    fn = (lib().rid_bias_force_conservative if conservative else
+          lib().rid_bias_force_noalloc if noalloc else lib().rid_bias_force)
     _check(fn(system.handle, ens.handle, _ptr(pos), B, float(eps0), float(eps1),
               _ptr(out["F"]), _ptr(out.get("E")), _ptr(out.get("eps")),
               _ptr(out.get("sigma")), _ptr(out.get("flags")), _stream(stream)))

@@ -137,6 +137,58 @@ static void free_ensemble(rid_ensemble_impl& e) {
 
 using namespace rid;
 
+// Batches up to this many walkers gather torsion atoms inside the MLP kernel
+// (one launch less); larger ones encode the CVs once into HBM first, so the
+// K members' workgroups read a compact [B][2n] encoding instead of each
+// re-reading the positions.
+#ifndef RID_FROM_POS_MAX_B
+#define RID_FROM_POS_MAX_B 4096
+#endif
+
+namespace rid {
+
+rid_status bias_force_check(const rid_system_s* sys, const rid_ensemble_s* ens,
+                            const float* d_pos, int B, float eps0, float eps1,
+                            const float* d_force) {
+  if (!sys || !ens || !d_pos || !d_force) return fail(RID_EINVAL, "NULL argument");
+  if (B < 1) return fail(RID_EINVAL, "B must be >= 1");
+  if (!(eps0 >= 0.f) || !(eps0 < eps1))
+    return fail(RID_EINVAL, "trust levels need 0 <= eps0 < eps1");
+  if (sys->impl.n_cv != ens->impl.n_cv)
+    return fail(RID_EINVAL, "system and ensemble disagree on n_cv");
+  if (!cv_kinds_match(sys->impl, ens->impl))
+    return fail(RID_EINVAL, "the ensemble's angular mask does not match the system's CV kinds");
+  return RID_OK;
+}
+
+rid_status bias_force_core(rid_system_impl& s, rid_ensemble_impl& e, const float* d_pos,
+                           int B, float eps0, float eps1, float* A, float* g, float* x,
+                           float* d_force, float* d_energy, float* d_eps, float* d_sigma,
+                           uint8_t* d_flags, hipStream_t st) {
+  rid_status r;
+  if (e.frag_dirty) {
+    if ((r = pack_ensemble_weights(e, st)) != RID_OK) return r;
+    e.frag_dirty = false;
+  }
+  const TorsionInput tin{&s, d_pos};
+  r = B <= RID_FROM_POS_MAX_B ? launch_mlp_from_pos(e, tin, B, A, g, st) : RID_EUNSUPPORTED;
+  if (r == RID_EUNSUPPORTED) {
+    // large batch, or too many torsion atoms for the in-kernel gather:
+    // encode in HBM first
+    if (!x) {
+      if ((r = e.ws_x.ensure(sizeof(float) * 2 * e.n_cv * (size_t)B)) != RID_OK) return r;
+      x = e.ws_x.as<float>();
+    }
+    if ((r = launch_cv_eval(s, d_pos, B, nullptr, x, st)) != RID_OK) return r;
+    r = launch_mlp(e, x, B, A, g, st);
+  }
+  if (r != RID_OK) return r;
+  return launch_bias_scatter(s, e.K, d_pos, B, A, g, nullptr, eps0, eps1, d_force, d_energy,
+                             d_eps, d_sigma, d_flags, st);
+}
+
+}  // namespace rid
+
 extern "C" {
 
 const char* rid_last_error(void) { return g_err.c_str(); }
@@ -484,50 +536,20 @@ rid_status rid_select(rid_ensemble ens, const float* d_s, int B, float eps0, flo
                         threshold_used, (hipStream_t)stream);
 }
 
-// Batches up to this many walkers gather torsion atoms inside the MLP kernel
-// (one launch less); larger ones encode the CVs once into HBM first, so the
-// K members' workgroups read a compact [B][2n] encoding instead of each
-// re-reading the positions.
-#ifndef RID_FROM_POS_MAX_B
-#define RID_FROM_POS_MAX_B 4096
-#endif
+
 
 rid_status rid_bias_force(rid_system sys, rid_ensemble ens, const float* d_pos,
                           int B, float eps0, float eps1, float* d_force,
                           float* d_energy, float* d_eps, float* d_sigma,
                           uint8_t* d_flags, rid_stream stream) {
-  if (!sys || !ens || !d_pos || !d_force) return fail(RID_EINVAL, "NULL argument");
-  if (B < 1) return fail(RID_EINVAL, "B must be >= 1");
-  if (!(eps0 >= 0.f) || !(eps0 < eps1))
-    return fail(RID_EINVAL, "trust levels need 0 <= eps0 < eps1");
-  rid_system_impl& s = sys->impl;
+  rid_status r = bias_force_check(sys, ens, d_pos, B, eps0, eps1, d_force);
+  if (r != RID_OK) return r;
   rid_ensemble_impl& e = ens->impl;
-  if (s.n_cv != e.n_cv) return fail(RID_EINVAL, "system and ensemble disagree on n_cv");
-  if (!cv_kinds_match(s, e))
-    return fail(RID_EINVAL, "the ensemble's angular mask does not match the system's CV kinds");
-  const hipStream_t st = (hipStream_t)stream;
-  rid_status r;
   if ((r = e.ws_A.ensure(sizeof(float) * e.K * (size_t)B)) != RID_OK) return r;
   if ((r = e.ws_g.ensure(sizeof(float) * e.K * (size_t)B * e.n_cv)) != RID_OK) return r;
-  if (e.frag_dirty) {
-    if ((r = pack_ensemble_weights(e, st)) != RID_OK) return r;
-    e.frag_dirty = false;
-  }
-  const TorsionInput tin{&s, d_pos};
-  r = B <= RID_FROM_POS_MAX_B
-          ? launch_mlp_from_pos(e, tin, B, e.ws_A.as<float>(), e.ws_g.as<float>(), st)
-          : RID_EUNSUPPORTED;
-  if (r == RID_EUNSUPPORTED) {
-    // large batch, or too many torsion atoms for the in-kernel gather:
-    // encode in HBM first
-    if ((r = e.ws_x.ensure(sizeof(float) * 2 * e.n_cv * (size_t)B)) != RID_OK) return r;
-    if ((r = launch_cv_eval(s, d_pos, B, nullptr, e.ws_x.as<float>(), st)) != RID_OK) return r;
-    r = launch_mlp(e, e.ws_x.as<float>(), B, e.ws_A.as<float>(), e.ws_g.as<float>(), st);
-  }
-  if (r != RID_OK) return r;
-  return launch_bias_scatter(s, e.K, d_pos, B, e.ws_A.as<float>(), e.ws_g.as<float>(),
-                             nullptr, eps0, eps1, d_force, d_energy, d_eps, d_sigma,
-                             d_flags, st);
+  return bias_force_core(sys->impl, e, d_pos, B, eps0, eps1, e.ws_A.as<float>(),
+                         e.ws_g.as<float>(), nullptr, d_force, d_energy, d_eps, d_sigma,
+                         d_flags, (hipStream_t)stream);
 }
 
 rid_status rid_bias_force_conservative(rid_system sys, rid_ensemble ens,

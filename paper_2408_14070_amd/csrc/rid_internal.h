@@ -257,6 +257,13 @@ rid_status launch_bias_conservative(const rid_system_impl& s, rid_ensemble_impl&
 rid_status launch_train_step(rid_ensemble_impl& e, const float* s,
                              const float* F, int B, float lr, float* loss,
                              hipStream_t st);
+// The bias path (rid_bias_force) with its scratch given: A [K][B], g
+// [K][B][n], and x [B][2n] for the encoding when it goes through memory
+// (null: taken from the ensemble's workspace, grown on demand).
+rid_status bias_force_core(rid_system_impl& s, rid_ensemble_impl& e, const float* d_pos,
+                           int B, float eps0, float eps1, float* A, float* g, float* x,
+                           float* d_force, float* d_energy, float* d_eps, float* d_sigma,
+                           uint8_t* d_flags, hipStream_t st);
 rid_status launch_mf_label_impl(const float* traj, const float* s0,
                                 const float* kappa, const uint8_t* mask, int M,
                                 int T, int n, float thr, double* F, double* se,
@@ -271,3 +278,10 @@ struct rid_system_s {
 struct rid_ensemble_s {
   rid::rid_ensemble_impl impl;
 };
+
+namespace rid {
+// Argument checks of rid_bias_force (and its no-allocation variant).
+rid_status bias_force_check(const rid_system_s* sys, const rid_ensemble_s* ens,
+                            const float* d_pos, int B, float eps0, float eps1,
+                            const float* d_force);
+}  // namespace rid
