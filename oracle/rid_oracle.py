@@ -50,17 +50,23 @@ Functions and what pins them (tests/test_oracle_*.py):
                       pinned: force = -grad E by FD (sigma frozen), zero
                       total force and torque per walker
   mlp_input_hvp       Hessian-vector product of a model in its input
+                      (plain and residual)
                       pinned: central FD of dA/dx along the vector
-  deviation_gradient  d eps / d s (conservative switching)
-                      pinned: central FD of eps in s
+  deviation_gradient  d eps / d s (conservative switching), also on mixed
+                      tables
+                      pinned: central FD of eps in s (plain and masked)
   bias_force_conservative
                       -grad of E = -sigma(eps) Abar with the switch
                       differentiated too
                       pinned: force = -grad E by FD inside the switching
-                      band; equals bias_force where sigma is 0 or 1
+                      band (plain, residual and mixed tables); equals
+                      bias_force where sigma is 0 or 1
   train_loss_grad     gradient of the mean-force loss in the weights
-                      pinned: central FD on every parameter; exact least-
-                      squares solution of the linear model has zero gradient
+  mean_force_vjp      (plain, residual with or without dropout, mixed tables)
+                      pinned: central FD on every parameter in each form;
+                      exact least-squares solution of the linear model has
+                      zero gradient; a residual network whose later layers
+                      are zero has the one-layer network's gradient
   dropout_scales      training-time dropout of the hidden activations
                       (counter-based masks); pinned: finite differences of
                       the loss with the masks fixed, rate 0 reproduces the
@@ -300,12 +306,12 @@ def mlp_value_and_grad(model, x, scales=None):
     input, h_l = h_{l-1} + tanh(W_l h_{l-1} + b_l) for l >= 2 (the first
     layer maps the CV encoding, of another width); the reverse sweep then
     carries the skip, u_{l-1} = W_l^T v_l + u_l for l >= 2, with
-    v_l = u_l * (1 - tanh^2).
+    v_l = u_l * (1 - tanh^2).  With dropout in a residual network the mask
+    scales the layer's tanh branch, not the skip:
+    h_l = h_{l-1} + S_l tanh(z_l).
     """
     Ws, bs, wo, bo = model[:4]
     res = is_resnet(model)
-    if res and scales is not None:
-        raise ValueError("dropout is defined here for plain MLPs only")
     if res and any(np.shape(W)[0] != np.shape(Ws[0])[0] for W in Ws):
         raise ValueError("residual connections need hidden layers of equal width")
     hs = [np.asarray(x, dtype=np.float64)]
@@ -433,71 +439,85 @@ def mlp_input_hvp(model, x, rho):
     of ``mlp_value_and_grad`` along rho.  Forward: h_l and its tangent
     hd_l = (1 - h_l^2) W_l hd_{l-1} (hd_0 = rho).  Reverse: v_L = wo (1 -
     h_L^2), u_{l-1} = W_l^T v_l, v_l = u_l (1 - h_l^2); its tangent uses
-    d(1 - h^2) = -2 h hd.  x, rho: [B][D] -> [B][D]."""
-    Ws, bs, wo, bo = _plain_model(model, "the input Hessian-vector product")
+    d(1 - h^2) = -2 h hd.  x, rho: [B][D] -> [B][D].
+    Residual networks: the tanh branch t_l and its tangent td_l = (1 - t_l^2)
+    W_l hd_{l-1} enter the reverse sweep's derivative; h_l = h_{l-1} + t_l
+    and hd_l = hd_{l-1} + td_l for l >= 2, and both u and its tangent ud
+    carry the skip, u_{l-1} = W_l^T v_l + u_l."""
+    Ws, bs, wo, bo = model[:4]
+    res = is_resnet(model)
     hs = [np.asarray(x, dtype=np.float64)]
     hds = [np.asarray(rho, dtype=np.float64)]
-    for W, b in zip(Ws, bs):
-        h = np.tanh(hs[-1] @ W.T + b)
-        hds.append((1.0 - h ** 2) * (hds[-1] @ W.T))
-        hs.append(h)
+    ts, tds = [None], [None]
+    for l, (W, b) in enumerate(zip(Ws, bs), start=1):
+        t = np.tanh(hs[-1] @ W.T + b)
+        td = (1.0 - t ** 2) * (hds[-1] @ W.T)
+        ts.append(t)
+        tds.append(td)
+        skip = res and l >= 2
+        hs.append(t + hs[-1] if skip else t)
+        hds.append(td + hds[-1] if skip else td)
     u = np.broadcast_to(wo, hs[-1].shape)
     ud = np.zeros_like(hs[-1])
     for l in range(len(Ws), 0, -1):
-        v = u * (1.0 - hs[l] ** 2)
-        vd = ud * (1.0 - hs[l] ** 2) - 2.0 * u * hs[l] * hds[l]
-        u = v @ Ws[l - 1]
-        ud = vd @ Ws[l - 1]
+        v = u * (1.0 - ts[l] ** 2)
+        vd = ud * (1.0 - ts[l] ** 2) - 2.0 * u * ts[l] * tds[l]
+        skip = res and l >= 2
+        u, ud = (v @ Ws[l - 1] + (u if skip else 0.0),
+                 vd @ Ws[l - 1] + (ud if skip else 0.0))
     return ud
 
 
-def deviation_gradient(models, s):
+def deviation_gradient(models, s, mask=None):
     """d eps / d s of the model deviation (the reading of model_deviation).
 
     With w_k = (g_k - gbar) / (K eps), d eps/ds = sum_k H_k w_k, where H_k is
     the Hessian of A_k in s.  In the input x = [cos s | sin s], with
     J = dx/ds and rho = J w: H_k w = J^T H_x rho + (d rho/ds)^T dA/dx, the
-    second term being -cos s_i w_i u0[i] - sin s_i w_i u0[n+i].  eps = 0
-    gives 0.  s: [B][n] -> (eps [B], deps_ds [B][n])."""
+    second term being -cos s_i w_i u0[i] - sin s_i w_i u0[n+i].  A raw CV
+    (angular mask 0, encoded (s_i, 0)) has a linear encoding: its J^T slot
+    is the identity on x_i and its second term vanishes.  eps = 0 gives 0.
+    s: [B][n] -> (eps [B], deps_ds [B][n])."""
     s = np.asarray(s, dtype=np.float64)
     n = s.shape[-1]
-    x = embed(s)
-    _, g = ensemble_mean_force(models, s)
+    x = embed(s, mask)
+    _, g = ensemble_mean_force(models, s, mask)
     gbar, eps = model_deviation(g)
     K = len(models)
+    ang = np.ones(n, bool) if mask is None else np.asarray(mask).astype(bool)
     out = np.zeros_like(s)
     safe = np.where(eps > 0, eps, 1.0)
     for k, m in enumerate(models):
         w = (g[:, k, :] - gbar) / (K * safe[:, None])
-        rho = np.concatenate([-np.sin(s) * w, np.cos(s) * w], axis=-1)
+        rho = rho_to_input(s, w, mask)
         _, u0 = mlp_value_and_grad(m, x)
         hx = mlp_input_hvp(m, x, rho)
-        out += (-np.sin(s) * hx[:, :n] + np.cos(s) * hx[:, n:]
-                - w * (np.cos(s) * u0[:, :n] + np.sin(s) * u0[:, n:]))
+        curv = -w * (np.cos(s) * u0[:, :n] + np.sin(s) * u0[:, n:])
+        out += mean_force_from_input_grad(s, hx, mask) + np.where(ang, curv, 0.0)
     out[eps == 0] = 0.0
     return eps, out
 
 
-def bias_force_conservative(pos, quads, models, eps0, eps1, n_atoms=None):
+def bias_force_conservative(pos, quads, models, eps0, eps1, n_atoms=None, mask=None):
     """Bias force that is exactly -grad E with E = -sigma(eps) Abar,
     including the switching band: f = sigma gbar + Abar sigma'(eps) deps/ds.
     Outside the band it equals bias_force.  Same outputs as bias_force."""
-    out = bias_force(pos, quads, models, eps0, eps1, n_atoms)
+    out = bias_force(pos, quads, models, eps0, eps1, n_atoms, mask)
     s = out["s"]
-    _, deps = deviation_gradient(models, s)
+    _, deps = deviation_gradient(models, s, mask)
     Abar = np.mean(out["A"], axis=1)
     fcv = out["sigma"][:, None] * out["gbar"] + \
         (Abar * switch_slope(out["eps"], eps0, eps1))[:, None] * deps
     out["fcv"] = fcv
-    out["F"] = apply_cv_force(pos, quads, fcv, n_atoms)
+    out["F"] = apply_cv_force(pos, quads, fcv, n_atoms, mask)
     return out
 
 
-def bias_energy(pos, quads, models, eps0, eps1):
+def bias_energy(pos, quads, models, eps0, eps1, mask=None):
     """E(r) = -sigma(eps(s(r))) Abar(s(r)), the switch evaluated at r
     (finite-difference target of the conservative force)."""
-    s = dihedral(pos, quads)
-    A, g = ensemble_mean_force(models, s)
+    s = cv_values(pos, quads, mask)
+    A, g = ensemble_mean_force(models, s, mask)
     _, eps = model_deviation(g)
     sigma, _ = switch(eps, eps0, eps1)
     return -sigma * np.mean(A, axis=1)
@@ -506,7 +526,7 @@ def bias_energy(pos, quads, models, eps0, eps1):
 # --------------------------------------------------------------------------
 # a7: mean-force fitting, double backward, Adam
 # --------------------------------------------------------------------------
-def train_loss_grad(model, s, F, scales=None):
+def train_loss_grad(model, s, F, scales=None, mask=None):
     """Loss L = (1/B) sum_b |g(s_b) - F_b|^2 of one model and its gradient.
 
     The models are trained to predict mean forces ("Training phase"), i.e.
@@ -522,37 +542,59 @@ def train_loss_grad(model, s, F, scales=None):
                 dW_l = lam_z h_{l-1}^T + lam_zd hd_{l-1}^T;  db_l = lam_z
                 lam_hd_{l-1} = W_l^T lam_zd;  lam_h_{l-1} = W_l^T lam_z
       dwo = hd_L;  dbo = 0 (the constant never reaches grad_s A).
+    Residual networks, dropout and angular masks as in mean_force_vjp.
     Returns (loss, (dWs, dbs, dwo, dbo)), all summed over the batch.
     """
     s = np.asarray(s, dtype=np.float64)
     F = np.asarray(F, dtype=np.float64)
     B, n = s.shape
-    A, u0 = mlp_value_and_grad(model, embed(s), scales)
-    g = mean_force_from_input_grad(s, u0)
+    A, u0 = mlp_value_and_grad(model, embed(s, mask), scales)
+    g = mean_force_from_input_grad(s, u0, mask)
     r = g - F
     loss = float(np.sum(r * r) / B)
-    return loss, mean_force_vjp(model, s, 2.0 * r / B, scales)
+    return loss, mean_force_vjp(model, s, 2.0 * r / B, scales, mask)
 
 
-def mean_force_vjp(model, s, rho, scales=None):
+def rho_to_input(s, rho, mask=None):
+    """A CV-space vector mapped to the network input by the encoding's
+    Jacobian dx/ds: (rho_x[i], rho_x[n+i]) = (-sin s_i, cos s_i) rho_i for
+    an angular CV, (rho_i, 0) for a raw one (encoded (s_i, 0))."""
+    s = np.asarray(s, dtype=np.float64)
+    rho = np.asarray(rho, dtype=np.float64)
+    a = np.concatenate([-np.sin(s) * rho, np.cos(s) * rho], axis=-1)
+    if mask is None:
+        return a
+    m = np.asarray(mask).astype(bool)
+    return np.concatenate([np.where(m, a[..., :s.shape[-1]], rho),
+                           np.where(m, a[..., s.shape[-1]:], 0.0)], axis=-1)
+
+
+def mean_force_vjp(model, s, rho, scales=None, mask=None):
     """Gradient in the parameters of J = sum_b rho_b . g(s_b) for a given
     rho [B][n] (the tangent + adjoint sweep described in train_loss_grad).
     With dropout scales S_l the hidden output is S_l tanh(z_l): its
-    derivative S_l (1 - tanh^2) replaces (1 - h_l^2) throughout, and the
-    second-order term -2 tanh(z_l) zd_l keeps the unscaled tanh.
+    derivative d_l = S_l (1 - t_l^2) (t_l = tanh(z_l)) replaces
+    (1 - h_l^2) throughout, and the second-order term -2 t_l zd_l keeps the
+    unscaled tanh.  Residual networks (h_l = h_{l-1} + S_l t_l for l >= 2):
+    the tangent carries the skip too, hd_l = hd_{l-1} + d_l zd_l, and in the
+    adjoint both lam_h_l and lam_hd_l flow unchanged into layer l-1 beside
+    W_l^T [lam_z ; lam_zd]; everything else is the plain recipe.  With an
+    angular mask, rho reaches the input through rho_to_input.
     Returns (dWs, dbs, dwo, dbo)."""
-    Ws, bs, wo, bo = _plain_model(model, "mean-force training")
+    Ws, bs, wo, bo = model[:4]
+    res = is_resnet(model)
     s = np.asarray(s, dtype=np.float64)
     rho = np.asarray(rho, dtype=np.float64)
-    x = embed(s)
-    rho_x = np.concatenate([-np.sin(s) * rho, np.cos(s) * rho], axis=-1)
+    x = embed(s, mask)
+    rho_x = rho_to_input(s, rho, mask)
     # primal activations (ts: tanh before the dropout scale)
     hs = [x]
     ts = [None]
     for l, (W, b) in enumerate(zip(Ws, bs)):
         t = np.tanh(hs[-1] @ W.T + b)
         ts.append(t)
-        hs.append(t if scales is None else t * scales[l])
+        h = t if scales is None else t * scales[l]
+        hs.append(h + hs[-1] if (res and l >= 1) else h)
     ds = [None] + [(1.0 - ts[l] ** 2) * (1.0 if scales is None else scales[l - 1])
                    for l in range(1, len(Ws) + 1)]
     # tangent forward
@@ -561,7 +603,8 @@ def mean_force_vjp(model, s, rho, scales=None):
     for l, W in enumerate(Ws, start=1):
         zd = hds[-1] @ W.T
         zds.append(zd)
-        hds.append(ds[l] * zd)
+        hd = ds[l] * zd
+        hds.append(hd + hds[-1] if (res and l >= 2) else hd)
     L = len(Ws)
     dWs = [None] * L
     dbs = [None] * L
@@ -571,20 +614,20 @@ def mean_force_vjp(model, s, rho, scales=None):
     for l in range(L, 0, -1):
         dl = ds[l]
         lam_zd = dl * lam_hd
-        lam_h = lam_h - 2.0 * ts[l] * zds[l] * lam_hd
-        lam_z = dl * lam_h
+        lam_z = dl * (lam_h - 2.0 * ts[l] * zds[l] * lam_hd)
         dWs[l - 1] = lam_z.T @ hs[l - 1] + lam_zd.T @ hds[l - 1]
         dbs[l - 1] = np.sum(lam_z, axis=0)
-        lam_hd = lam_zd @ Ws[l - 1]
-        lam_h = lam_z @ Ws[l - 1]
+        skip = res and l >= 2
+        lam_hd, lam_h = (lam_zd @ Ws[l - 1] + (lam_hd if skip else 0.0),
+                         lam_z @ Ws[l - 1] + (lam_h if skip else 0.0))
     return (dWs, dbs, dwo, 0.0)
 
 
-def train_loss(model, s, F, scales=None):
+def train_loss(model, s, F, scales=None, mask=None):
     """Loss only (finite-difference target)."""
     s = np.asarray(s, dtype=np.float64)
-    _, u0 = mlp_value_and_grad(model, embed(s), scales)
-    r = mean_force_from_input_grad(s, u0) - np.asarray(F, dtype=np.float64)
+    _, u0 = mlp_value_and_grad(model, embed(s, mask), scales)
+    r = mean_force_from_input_grad(s, u0, mask) - np.asarray(F, dtype=np.float64)
     return float(np.sum(r * r) / r.shape[0])
 
 
@@ -626,7 +669,7 @@ def flat_model(model):
     return np.concatenate(parts).astype(np.float64)
 
 
-def unflat_model(flat, n_in, widths):
+def unflat_model(flat, n_in, widths, resnet=False):
     p = np.asarray(flat, dtype=np.float64)
     Ws, bs = [], []
     off, prev = 0, n_in
@@ -636,21 +679,26 @@ def unflat_model(flat, n_in, widths):
         prev = w
     wo = p[off:off + prev]; off += prev
     bo = float(p[off])
-    return (Ws, bs, wo, bo)
+    return (Ws, bs, wo, bo, True) if resnet else (Ws, bs, wo, bo)
 
 
-def train_step(models, s, F, states, lr):
+def train_step(models, s, F, states, lr, dropout=None, mask=None):
     """One mean-force fitting step for every member (same minibatch, models
     independent).  states: list of (m, v, t) per model (t = updates done).
+    dropout: (rate, seed) or None; member k's masks are those of step t
+    (dropout_scales).  mask: angular mask of the CVs.
     Returns (new_models, new_states, losses [K])."""
     new_models, new_states, losses = [], [], []
     widths = [W.shape[0] for W in models[0][0]]
     n_in = models[0][0][0].shape[1] if models[0][0] else models[0][2].size
-    for model, (m, v, t) in zip(models, states):
-        loss, grads = train_loss_grad(model, s, F)
+    for k, (model, (m, v, t)) in enumerate(zip(models, states)):
+        sc = None
+        if dropout is not None and dropout[0] > 0.0:
+            sc = dropout_scales(len(s), widths, dropout[0], dropout[1], t, k)
+        loss, grads = train_loss_grad(model, s, F, sc, mask)
         theta, m2, v2 = adam_step(flat_model(model), flat_grad(grads), m, v,
                                   t + 1, lr)
-        new_models.append(unflat_model(theta, n_in, widths))
+        new_models.append(unflat_model(theta, n_in, widths, is_resnet(model)))
         new_states.append((m2, v2, t + 1))
         losses.append(loss)
     return new_models, new_states, np.asarray(losses)

@@ -113,3 +113,23 @@ def test_conservative_force_equals_frozen_outside_the_band(band):
     a = O.bias_force_conservative(pos, sys_.quads, models, e0, e1)
     b = O.bias_force(pos, sys_.quads, models, e0, e1)
     assert np.array_equal(a["F"], b["F"])
+
+
+def test_resnet_conservative_force_is_minus_grad_energy_in_the_band():
+    sys_ = ridgen.system_dipeptide()
+    pos = ridgen.chain_coords(sys_, 3, seed=12)
+    models = [tuple(m[:4]) + (True,) for m in _models(2 * sys_.n_cv, [6, 6, 6], 3, seed=21)]
+    eps = O.bias_force(pos, sys_.quads, models, 1e9, 2e9)["eps"]
+    e0, e1 = 0.5 * eps.min(), 2.0 * eps.max()
+    out = O.bias_force_conservative(pos, sys_.quads, models, e0, e1)
+    assert np.all((out["sigma"] > 0) & (out["sigma"] < 1))
+    F = out["F"]
+    h = 1e-6
+    fd = np.zeros_like(F)
+    for a in range(sys_.n_atoms):
+        for k in range(3):
+            p1 = pos.copy(); p1[:, a, k] += h
+            p2 = pos.copy(); p2[:, a, k] -= h
+            fd[:, a, k] = -(O.bias_energy(p1, sys_.quads, models, e0, e1)
+                            - O.bias_energy(p2, sys_.quads, models, e0, e1)) / (2 * h)
+    assert np.max(np.abs(fd - F)) <= 1e-6 * np.max(np.abs(F))

@@ -157,3 +157,61 @@ def test_masked_distance_against_fp64_and_labels_by_brute_force():
         d2 = O.cv_distance_sq_f32(L, s[f][None, :], mask)
         first = int(np.nonzero(d2 <= t * t)[0][0])
         assert labels[f] == first
+
+
+def test_masked_training_gradient_finite_differences():
+    """Training on a mixed table: raw CVs enter as (s, 0), their mean force
+    is dA/dx_i and the label residual reaches the input as (rho_i, 0)."""
+    n, widths = 4, [6, 5]
+    mask = np.array([1, 0, 1, 0], np.uint8)
+    (m,) = _models(2 * n, widths, 1, seed=31, bias_std=0.2)
+    rng = np.random.default_rng(32)
+    s = np.where(mask.astype(bool), rng.uniform(-3, 3, size=(5, n)), rng.uniform(0.3, 1.5, size=(5, n)))
+    F = rng.normal(size=(5, n))
+    loss, grads = O.train_loss_grad(m, s, F, mask=mask)
+    assert abs(loss - O.train_loss(m, s, F, mask=mask)) < 1e-13
+    assert abs(loss - O.train_loss(m, s, F)) > 1e-6          # the mask matters
+    g = O.flat_grad(grads)
+    theta = O.flat_model(m)
+    h = 1e-6
+    fd = np.array([(O.train_loss(O.unflat_model(theta + h * e, 2 * n, widths), s, F, mask=mask)
+                    - O.train_loss(O.unflat_model(theta - h * e, 2 * n, widths), s, F, mask=mask))
+                   / (2 * h) for e in np.eye(theta.size)])
+    assert np.max(np.abs(fd - g)) < 1e-6 * np.max(np.abs(g))
+
+
+def test_masked_deviation_gradient_finite_differences():
+    n = 4
+    mask = np.array([0, 1, 1, 0], np.uint8)
+    models = _models(2 * n, [6, 5], 3, seed=33, bias_std=0.2)
+    rng = np.random.default_rng(34)
+    s = np.where(mask.astype(bool), rng.uniform(-3, 3, size=(4, n)), rng.uniform(0.3, 1.5, size=(4, n)))
+    eps, de = O.deviation_gradient(models, s, mask)
+    h = 1e-6
+    fd = np.zeros_like(s)
+    for i in range(n):
+        e = np.zeros(n); e[i] = h
+        ep = O.model_deviation(O.ensemble_mean_force(models, s + e, mask)[1])[1]
+        em = O.model_deviation(O.ensemble_mean_force(models, s - e, mask)[1])[1]
+        fd[:, i] = (ep - em) / (2 * h)
+    assert np.max(np.abs(de - fd)) <= 1e-7 * np.max(np.abs(fd))
+
+
+def test_masked_conservative_force_is_minus_grad_energy_in_the_band():
+    sys_ = ridgen.with_distances(ridgen.chain_system(4, 6), 2, stride=2, every=3)
+    models = _models(2 * sys_.n_cv, [10, 10], 3, seed=35, bias_std=0.2)
+    pos = ridgen.chain_coords(sys_, 2, seed=36)
+    eps = O.bias_force(pos, sys_.quads, models, 1e9, 2e9, mask=sys_.mask)["eps"]
+    e0, e1 = 0.5 * eps.min(), 2.0 * eps.max()
+    out = O.bias_force_conservative(pos, sys_.quads, models, e0, e1, mask=sys_.mask)
+    assert np.all((out["sigma"] > 0) & (out["sigma"] < 1))
+    F = out["F"]
+    h = 1e-6
+    fd = np.zeros_like(F)
+    for a in range(sys_.n_atoms):
+        for k in range(3):
+            p1 = pos.copy(); p1[:, a, k] += h
+            p2 = pos.copy(); p2[:, a, k] -= h
+            fd[:, a, k] = -(O.bias_energy(p1, sys_.quads, models, e0, e1, sys_.mask)
+                            - O.bias_energy(p2, sys_.quads, models, e0, e1, sys_.mask)) / (2 * h)
+    assert np.max(np.abs(fd - F)) <= 1e-6 * np.max(np.abs(F))

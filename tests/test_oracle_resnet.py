@@ -119,12 +119,100 @@ def test_resnet_one_layer_is_plain():
     assert np.array_equal(A0, A1) and np.array_equal(u0, u1)
 
 
-def test_resnet_rejected_where_not_defined():
-    m = _res(_models(6, [7, 7], 1, seed=17)[0])
+def test_resnet_refuses_unequal_widths():
     s = np.zeros((2, 3))
     with pytest.raises(ValueError):
-        O.mlp_input_hvp(m, O.embed(s), np.ones((2, 6)))
-    with pytest.raises(ValueError):
-        O.mean_force_vjp(m, s, np.ones((2, 3)))
-    with pytest.raises(ValueError):
         O.mlp_value_and_grad(_res(_models(6, [7, 5], 1, seed=18)[0]), O.embed(s))
+
+
+def _flat_fd(loss_of, theta, h=1e-6):
+    fd = np.zeros_like(theta)
+    for j in range(theta.size):
+        t1 = theta.copy(); t1[j] += h
+        t2 = theta.copy(); t2[j] -= h
+        fd[j] = (loss_of(t1) - loss_of(t2)) / (2 * h)
+    return fd
+
+
+@pytest.mark.parametrize("dropout", [False, True])
+def test_resnet_training_gradient_finite_differences(dropout):
+    """Loss gradient of a residual network on every parameter (three hidden
+    layers: two skips), with the dropout masks held fixed when on."""
+    n, widths = 3, [5, 5, 5]
+    m = _res(_models(2 * n, widths, 1, seed=21, bias_std=0.2)[0])
+    rng = np.random.default_rng(22)
+    s = rng.uniform(-3, 3, size=(4, n))
+    F = rng.normal(size=(4, n))
+    sc = O.dropout_scales(4, widths, 0.3, seed=9, step=1, member=0) if dropout else None
+    if dropout:
+        assert any(np.any(x == 0.0) for x in sc)
+    loss, grads = O.train_loss_grad(m, s, F, sc)
+    assert abs(loss - O.train_loss(m, s, F, sc)) < 1e-13
+    g = O.flat_grad(grads)
+    fd = _flat_fd(lambda th: O.train_loss(O.unflat_model(th, 2 * n, widths, True), s, F, sc),
+                  O.flat_model(m))
+    assert np.max(np.abs(fd - g)) < 1e-6 * np.max(np.abs(g))
+    # the skips matter: the plain network's gradient differs
+    _, gp = O.train_loss_grad(tuple(m[:4]), s, F, sc)
+    assert np.max(np.abs(O.flat_grad(gp) - g)) > 1e-3 * np.max(np.abs(g))
+
+
+def test_resnet_vjp_finite_differences():
+    n, widths = 4, [6, 6]
+    m = _res(_models(2 * n, widths, 1, seed=23, bias_std=0.2)[0])
+    rng = np.random.default_rng(24)
+    s = rng.uniform(-3, 3, size=(5, n))
+    rho = rng.normal(size=(5, n))
+    g = O.flat_grad(O.mean_force_vjp(m, s, rho))
+
+    def J(th):
+        _, gg = O.ensemble_mean_force([O.unflat_model(th, 2 * n, widths, True)], s)
+        return float(np.sum(rho * gg[:, 0, :]))
+
+    fd = _flat_fd(J, O.flat_model(m))
+    assert np.max(np.abs(fd - g)) < 1e-6 * np.max(np.abs(g))
+
+
+def test_resnet_training_reduces_to_one_layer():
+    """Later layers with zero weights and biases pass h_1 through unchanged
+    (tanh(0) = 0): the residual network is the one-layer network, and so is
+    the gradient of its first layer and output weights."""
+    n, w = 3, 6
+    (m1,) = _models(2 * n, [w], 1, seed=25, bias_std=0.2)
+    Ws, bs, wo, bo = m1
+    z = np.zeros((w, w))
+    mres = ([Ws[0], z, z], [bs[0], np.zeros(w), np.zeros(w)], wo, bo, True)
+    rng = np.random.default_rng(26)
+    s = rng.uniform(-3, 3, size=(6, n))
+    F = rng.normal(size=(6, n))
+    l1, g1 = O.train_loss_grad(m1, s, F)
+    lr, gr = O.train_loss_grad(mres, s, F)
+    assert abs(l1 - lr) < 1e-13
+    assert np.allclose(gr[0][0], g1[0][0], rtol=0, atol=1e-13)
+    assert np.allclose(gr[1][0], g1[1][0], rtol=0, atol=1e-13)
+    assert np.allclose(gr[2], g1[2], rtol=0, atol=1e-13)
+
+
+def test_resnet_input_hvp_finite_differences():
+    rng = np.random.default_rng(27)
+    m = _res(_models(6, [7, 7, 7], 1, seed=28, bias_std=0.2)[0])
+    x = rng.normal(size=(4, 6))
+    rho = rng.normal(size=(4, 6))
+    hv = O.mlp_input_hvp(m, x, rho)
+    h = 1e-5
+    fd = (O.mlp_value_and_grad(m, x + h * rho)[1] - O.mlp_value_and_grad(m, x - h * rho)[1]) / (2 * h)
+    assert np.max(np.abs(hv - fd)) <= 1e-8 * np.max(np.abs(fd))
+
+
+def test_resnet_dropout_value_and_grad_finite_differences():
+    rng = np.random.default_rng(29)
+    widths = [6, 6, 6]
+    m = _res(_models(5, widths, 1, seed=30, bias_std=0.2)[0])
+    x = rng.normal(size=(3, 5))
+    sc = O.dropout_scales(3, widths, 0.4, seed=3, step=0, member=0)
+    A, u0 = O.mlp_value_and_grad(m, x, sc)
+    h = 1e-6
+    for j in range(5):
+        e = np.zeros(5); e[j] = h
+        fd = (O.mlp_value_and_grad(m, x + e, sc)[0] - O.mlp_value_and_grad(m, x - e, sc)[0]) / (2 * h)
+        assert np.max(np.abs(fd - u0[:, j])) < 1e-8
