@@ -563,8 +563,8 @@ rid_status rid_bias_force_conservative(rid_system sys, rid_ensemble ens,
     return fail(RID_EINVAL, "trust levels need 0 <= eps0 < eps1");
   if (sys->impl.n_cv != ens->impl.n_cv)
     return fail(RID_EINVAL, "system and ensemble disagree on n_cv");
-  if (sys->impl.has_dist || !ens->impl.raw.empty())
-    return fail(RID_EUNSUPPORTED, "conservative switching is built for torsion CVs");
+  if (!cv_kinds_match(sys->impl, ens->impl))
+    return fail(RID_EINVAL, "the ensemble's angular mask does not match the system's CV kinds");
   return launch_bias_conservative(sys->impl, ens->impl, d_pos, B, eps0, eps1, d_force,
                                   d_energy, d_eps, d_sigma, d_flags, (hipStream_t)stream);
 }

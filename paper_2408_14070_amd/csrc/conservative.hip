@@ -6,9 +6,10 @@
 // with H_k the Hessian of member k's free energy in s.  FP32 ensembles of
 // padded width <= 256 get H_k w_k from one fused forward-over-reverse
 // kernel (hvp_kernel: primal and tangent rows share every weight fragment).
-// Other ensembles use the mean-force sweeps of the training path in input
-// mode: with rho_x = (dx/ds) w_k held fixed, the tangent and adjoint sweeps
-// give d(rho_x . dA_k/dx)/dx; the angle chain adds (d rho_x/ds)^T dA_k/dx.
+// Other ensembles (wider, 16-bit, residual, raw CVs) use the mean-force
+// sweeps of the training path in input mode: with rho_x = (dx/ds) w_k held
+// fixed, the tangent and adjoint sweeps give d(rho_x . dA_k/dx)/dx; the
+// angle chain adds (d rho_x/ds)^T dA_k/dx (zero for a raw CV).
 // The frozen-switch path (rid_bias_force) is the same where sigma' = 0.
 #include "device_common.h"
 
@@ -58,25 +59,26 @@ __global__ __launch_bounds__(kPrepWaves * kWave) void cons_prep_kernel(
 // CV force per (walker, CV): sigma gbar + Abar sigma' sum_k H_k w_k, where
 // member k's term in s is  -sin s_i lx[i] + cos s_i lx[n+i]
 //                          - w_ki (cos s_i u0[i] + sin s_i u0[n+i])
-// (lx = d J_k/dx from the input-mode sweep, u0 = dA_k/dx); members summed
-// in order.
+// (lx = d J_k/dx from the input-mode sweep, u0 = dA_k/dx); for a raw CV
+// (encoded (s_i, 0): linear) it is lx[i].  Members summed in order.
 __global__ void cons_combine_kernel(const float* s, const float* rho, const float* lam_x,
                                     long long slab_lam, const float* u0, const float* gbar,
                                     const float* coef, const float* sig_w, int K, int B,
-                                    int n, float* fcv) {
+                                    int n, const uint8_t* raw, float* fcv) {
   const long long total = (long long)B * n;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const int b = (int)(e / n), i = (int)(e - (long long)b * n);
     float sn, cs;
     sincosf(s[e], &sn, &cs);
+    const bool r = raw && raw[i];
     float de = 0.f;
     if (coef[b] != 0.f) {
       for (int k = 0; k < K; ++k) {
         const float* lx = lam_x + k * slab_lam + (long long)b * 2 * n;
         const float* u = u0 + ((long long)k * B + b) * 2 * n;
         const float wk = rho[((long long)b * K + k) * n + i];
-        de += -sn * lx[i] + cs * lx[n + i] - wk * (cs * u[i] + sn * u[n + i]);
+        de += r ? lx[i] : -sn * lx[i] + cs * lx[n + i] - wk * (cs * u[i] + sn * u[n + i]);
       }
     }
     fcv[e] = sig_w[b] * gbar[e] + coef[b] * de;
@@ -106,8 +108,6 @@ rid_status launch_bias_conservative(const rid_system_impl& s, rid_ensemble_impl&
                                     const float* pos, int B, float eps0, float eps1,
                                     float* force, float* energy, float* eps, float* sigma,
                                     uint8_t* flags, hipStream_t st) {
-  if (e.resnet)
-    return fail(RID_EUNSUPPORTED, "conservative switching is built for plain MLPs");
   const int K = e.K, n = e.n_cv;
   rid_status r;
   // workspace: s [B][n], gbar [B][n], fcv [B][n], rho [B][K][n], coef [B],
@@ -153,7 +153,8 @@ rid_status launch_bias_conservative(const rid_system_impl& s, rid_ensemble_impl&
       RID_OK)
     return r;
   hipLaunchKernelGGL(cons_combine_kernel, dim3(grid), dim3(256), 0, st, d_s, d_rho, hvp.lam_x,
-                     hvp.slab_lam, hvp.u0, d_gbar, d_coef, d_sig, K, B, n, d_fcv);
+                     hvp.slab_lam, hvp.u0, d_gbar, d_coef, d_sig, K, B, n,
+                     e.raw.empty() ? nullptr : e.d_raw, d_fcv);
   RID_HIP(hipGetLastError());
   return launch_bias_scatter(s, 0, pos, B, nullptr, nullptr, d_fcv, 0.0f, 1.0f, force,
                              nullptr, nullptr, nullptr, flags, st);

@@ -1917,7 +1917,10 @@ rid_status launch_mlp(const rid_ensemble_impl& e, const float* x, int B,
 }
 
 bool hvp_fused_supported(const rid_ensemble_impl& e) {
-  if (e.prec != RID_FP32 || e.NP > 256 || e.L > kMaxHidden) return false;
+  // plain MLPs on periodic inputs (residual and raw-CV ensembles take the
+  // training sweeps in input mode)
+  if (e.prec != RID_FP32 || e.NP > 256 || e.L > kMaxHidden || e.resnet || !e.raw.empty())
+    return false;
   HvpArgs a{};
   return hvp_layout(e.NP, e.XP, e.n_cv, a) <= 160 * 1024;
 }
@@ -1935,7 +1938,10 @@ rid_status launch_hvp(const rid_ensemble_impl& e, const float* x, const float* r
 }
 
 bool train_fused_supported(const rid_ensemble_impl& e) {
-  if (e.prec != RID_FP32 || e.NP > 256 || e.L > kMaxHidden) return false;
+  // plain MLPs on periodic inputs (residual and raw-CV ensembles take the
+  // sweeps as separate GEMMs)
+  if (e.prec != RID_FP32 || e.NP > 256 || e.L > kMaxHidden || e.resnet || !e.raw.empty())
+    return false;
   TrainArgs a{};
   return train_layout(e.NP, e.XP, e.n_cv, a) <= 160 * 1024;
 }

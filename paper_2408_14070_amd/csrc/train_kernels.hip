@@ -16,6 +16,18 @@
 //   dw_o = sum hd_L, db_o = 0.
 // Then one Adam step on the FP32 masters.
 //
+// General form (the sweeps as separate GEMMs: wide and 16-bit ensembles,
+// residual networks, dropout on them, mixed angular masks).  With t_l =
+// tanh(z_l), dropout factors S_l (1 without dropout) and d_l = S_l (1 - t_l^2):
+//   primal   h_l = S_l t_l (+ h_{l-1} for a residual layer l >= 2)
+//   backward u_L = w_o, v_l = u_l d_l, u_{l-1} = W_l^T v_l (+ u_l, residual)
+//   tangent  hd_l = d_l zd_l (+ hd_{l-1}, residual)
+//   adjoint  lam_zd = d_l lam_hd, lam_z = d_l (lam_h - 2 t_l zd_l lam_hd),
+//            [lam_h ; lam_hd]_{l-1} = [lam_z ; lam_zd] W_l (+ [lam_h ; lam_hd]_l,
+//            residual)
+// Raw CVs (angular mask 0) enter as (s, 0): their mean force is dA/dx_i and
+// rho reaches the input as (rho_i, 0).
+//
 // Layout: batched over the K members; "stacked" tensors hold the primal
 // quantity in rows [0, B) and the tangent one in rows [B, 2B) of each
 // member's slab, so one GEMM moves both halves, and the weight gradient is a
@@ -23,7 +35,7 @@
 // kernel (64x64 tiles, LDS double buffering, arbitrary strides, fused
 // epilogues); the weight-gradient GEMM is split along the batch with a
 // fixed-order reduction, so the whole step is deterministic.
-#include "rid_internal.h"
+#include "device_common.h"
 
 namespace rid {
 namespace {
@@ -36,8 +48,7 @@ constexpr int kThreads = 256;
 enum Epi {
   EPI_STORE = 0,      // C = acc
   EPI_BIAS_TANH = 1,  // C = tanh(acc + bias[n])
-  EPI_MUL_DTANH = 2,  // C = acc * (1 - aux^2)
-  EPI_TANGENT = 3     // C = acc, C2 = acc * (1 - aux^2)
+  EPI_GEN = 2         // r = acc + add; C = r (if C); C2 = r * mul + add2 (if C2)
 };
 
 struct GemmArgs {
@@ -47,12 +58,17 @@ struct GemmArgs {
   long long sBb, sBk, sBn;
   float* C;
   long long sCb, sCm, sCn, sCs;   // sCs: split-K slab stride
-  float* C2;                      // second output (EPI_TANGENT): C's row and
+  float* C2;                      // second output (EPI_GEN): C's row and
   long long sC2b;                 // column strides, own batch stride
   const float* bias;
   long long sBiasb;
-  const float* aux;               // same strides as C (sXb, sXm, sXn)
-  long long sXb, sXm, sXn;
+  // EPI_GEN operands (each null or indexed like C, with its own batch stride)
+  const float* add;
+  long long sAddb;
+  const float* mul;
+  long long sMulb;
+  const float* add2;
+  long long sAdd2b;
   int M, N, Kc, batch, ksplit, kchunk, mode;
   int modeA, modeB;               // operand load modes (TileLoad), set by gemm()
 };
@@ -188,7 +204,7 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
     }
   }
 
-  float* C = g.C + b * g.sCb + s * g.sCs;
+  float* C = g.C ? g.C + b * g.sCb + s * g.sCs : nullptr;
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -207,13 +223,12 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
         } else if (g.mode == EPI_BIAS_TANH) {
           C[ci] = tanh_fast(v + bias);
         } else {
-          const float h = g.aux[b * g.sXb + m * g.sXm + n * g.sXn];
-          const float d = 1.f - h * h;
-          if (g.mode == EPI_MUL_DTANH) {
-            C[ci] = v * d;
-          } else {
-            C[ci] = v;
-            g.C2[b * g.sC2b + ci] = v * d;
+          const float rr = g.add ? v + g.add[b * g.sAddb + ci] : v;
+          if (C) C[ci] = rr;
+          if (g.C2) {
+            float o = rr * g.mul[b * g.sMulb + ci];
+            if (g.add2) o += g.add2[b * g.sAdd2b + ci];
+            g.C2[b * g.sC2b + ci] = o;
           }
         }
       }
@@ -221,7 +236,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
 }
 
 // x = [cos s | sin s] into the primal half of every member's stacked slab
-__global__ void train_embed_kernel(const float* s, int B, int n, int K,
+// (raw CVs, raw[i] = 1: (s_i, 0))
+__global__ void train_embed_kernel(const float* s, int B, int n, int K, const uint8_t* raw,
                                    float* HH0, long long slab) {
   const long long total = (long long)K * B * n;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
@@ -229,26 +245,77 @@ __global__ void train_embed_kernel(const float* s, int B, int n, int K,
     const int k = (int)(e / ((long long)B * n));
     const long long r = e - (long long)k * B * n;
     const int b = (int)(r / n), i = (int)(r - (long long)b * n);
+    const float si = s[(long long)b * n + i];
     float sn, cs;
-    sincosf(s[(long long)b * n + i], &sn, &cs);
+    sincosf(si, &sn, &cs);
+    const bool is_raw = raw && raw[i];
     float* row = HH0 + k * slab + (long long)b * 2 * n;
-    row[i] = cs;
-    row[n + i] = sn;
+    row[i] = is_raw ? si : cs;
+    row[n + i] = is_raw ? 0.f : sn;
   }
 }
 
-// v_L = w_o (1 - h_L^2)
-__global__ void vlast_kernel(const float* HHL, long long slab, const float* master,
-                             long long per_model, int wo_off, int w, int B, int K,
-                             float* V) {
+// Activation stage of hidden layer l (1-based) from its tanh branch
+// T = tanh(z_l) [K][B][w]: h_l = S t (+ h_{l-1} when residual) into the
+// primal half of the stacked slab, and d_l = S (1 - t^2) into D.  S is the
+// dropout factor: unit j of sample b of member k is kept when the uniform of
+// word j mod 4 of the Philox4x32-10 block with counter (b, step, 16 k + l,
+// j div 4) and key (seed) is >= p, scaled by 1/(1 - p); 1 without dropout.
+// A thread handles the 4 units of one block.
+__global__ void act_kernel(const float* T, int l, int w, int B, int K, float drop_p,
+                           float drop_inv, unsigned long long seed, uint32_t step,
+                           const float* Hprev, long long slab_prev, float* H, long long slab,
+                           float* D) {
+  const int nq = (w + 3) / 4;
+  const long long total = (long long)K * B * nq;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(e / ((long long)B * nq));
+    const long long rq = e - (long long)k * B * nq;
+    const int b = (int)(rq / nq), q = (int)(rq - (long long)b * nq);
+    uint32_t c[4] = {(uint32_t)b, step, (uint32_t)(16 * k + l), (uint32_t)q};
+    if (drop_p > 0.f)
+      dev::philox4x32_10(c, (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32));
+    for (int u = 0; u < 4; ++u) {
+      const int j = 4 * q + u;
+      if (j >= w) break;
+      const float sc = drop_p > 0.f ? (dev::philox_uniform(c[u]) >= drop_p ? drop_inv : 0.f)
+                                    : 1.f;
+      const long long o = ((long long)k * B + b) * w + j;          // [K][B][w]
+      const long long oh = (long long)k * slab + (long long)b * w + j;
+      const float t = T[o];
+      float h = sc * t;
+      if (Hprev) h += Hprev[(long long)k * slab_prev + (long long)b * w + j];
+      H[oh] = h;
+      D[o] = sc * (1.f - t * t);
+    }
+  }
+}
+
+// out[k][b][j] = w_o[k][j] (the top of the reverse sweeps: u_L, lam_hd_L),
+// into rows [r0, r0 + B) of a [K][rows][w] slab (the other rows, if any, 0)
+__global__ void top_kernel(const float* master, long long per_model, int wo_off, int w, int B,
+                           int K, int rows, int r0, float* out) {
+  const long long total = (long long)K * rows * w;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(e / ((long long)rows * w));
+    const long long r = e - (long long)k * rows * w;
+    const int row = (int)(r / w), j = (int)(r - (long long)row * w);
+    out[e] = (row >= r0 && row < r0 + B) ? master[k * per_model + wo_off + j] : 0.f;
+  }
+}
+
+// v_L = w_o d_L
+__global__ void vlast_kernel(const float* DL, const float* master, long long per_model,
+                             int wo_off, int w, int B, int K, float* V) {
   const long long total = (long long)K * B * w;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const int k = (int)(e / ((long long)B * w));
     const long long r = e - (long long)k * B * w;
     const int j = (int)(r % w);
-    const float h = HHL[k * slab + r];
-    V[e] = master[k * per_model + wo_off + j] * (1.f - h * h);
+    V[e] = master[k * per_model + wo_off + j] * DL[e];
   }
 }
 
@@ -260,7 +327,7 @@ __global__ void vlast_kernel(const float* HHL, long long slab, const float* mast
 constexpr int kResWaves = 4;
 __global__ __launch_bounds__(kResWaves * 64) void residual_kernel(
     const float* s, const float* F, const float* rho_in, const float* U0, int B, int n,
-    int K, float* HH0, long long slab, float* loss_rows) {
+    int K, const uint8_t* raw, float* HH0, long long slab, float* loss_rows) {
   const long long e = (long long)blockIdx.x * kResWaves + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (e >= (long long)K * B) return;
@@ -271,6 +338,11 @@ __global__ __launch_bounds__(kResWaves * 64) void residual_kernel(
   for (int i = lane; i < n; i += 64) {
     float sn, cs;
     sincosf(s[(long long)b * n + i], &sn, &cs);
+    const bool r = raw && raw[i];     // raw CV: x_i = s_i, dx/ds = (1, 0)
+    if (r) {
+      sn = -1.f;
+      cs = 0.f;
+    }
     float rho;
     if (rho_in) {
       rho = rho_in[((long long)b * K + k) * n + i];
@@ -290,34 +362,21 @@ __global__ __launch_bounds__(kResWaves * 64) void residual_kernel(
   }
 }
 
-// Adjoint stage of layer l: given h_l, zd_l and (lam_h, lam_hd) produce the
-// stacked (lam_z ; lam_zd).  For the top layer lam_hd = w_o, lam_h = 0.
-__global__ void adjoint_kernel(const float* HHl, long long slab_h, const float* Zd,
-                               const float* LAM, long long slab_lam,
-                               const float* master, long long per_model, int wo_off,
-                               int top, int w, int B, int K, float* S,
-                               long long slab_s) {
+// Adjoint stage of layer l: given t_l, d_l, zd_l (each [K][B][w]) and the
+// stacked (lam_h ; lam_hd) of layer l, produce the stacked (lam_z ; lam_zd).
+__global__ void adjoint_kernel(const float* Tl, const float* Dl, const float* Zd,
+                               const float* LAM, long long slab_lam, int w, int B, int K,
+                               float* S, long long slab_s) {
   const long long total = (long long)K * B * w;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const int k = (int)(e / ((long long)B * w));
     const long long r = e - (long long)k * B * w;   // row-major offset inside the primal half
-    const int j = (int)(r % w);
-    const float h = HHl[k * slab_h + r];
-    const float zd = Zd[e];
-    float lh, lhd;
-    if (top) {
-      lh = 0.f;
-      lhd = master[k * per_model + wo_off + j];
-    } else {
-      lh = LAM[k * slab_lam + r];
-      lhd = LAM[k * slab_lam + (long long)B * w + r];
-    }
-    const float d = 1.f - h * h;
-    const float lzd = d * lhd;
-    lh -= 2.f * h * zd * lhd;
-    S[k * slab_s + r] = d * lh;                       // lam_z
-    S[k * slab_s + (long long)B * w + r] = lzd;       // lam_zd
+    const float t = Tl[e], d = Dl[e], zd = Zd[e];
+    const float lh = LAM[k * slab_lam + r];
+    const float lhd = LAM[k * slab_lam + (long long)B * w + r];
+    S[k * slab_s + r] = d * (lh - 2.f * t * zd * lhd);   // lam_z
+    S[k * slab_s + (long long)B * w + r] = d * lhd;       // lam_zd
   }
 }
 
@@ -570,9 +629,6 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   // forming weight gradients
   const bool input_mode = hvp != nullptr;
   if (input_mode && !rho) return fail(RID_EINVAL, "input mode needs an upstream gradient");
-  if (e.resnet) return fail(RID_EUNSUPPORTED, "mean-force training is built for plain MLPs");
-  if (!e.raw.empty())
-    return fail(RID_EUNSUPPORTED, "mean-force training is built for torsion CVs");
   const int K = e.K, L = e.L, n = e.n_cv, X = 2 * n;
   std::vector<int> w(L + 1);
   w[0] = X;
@@ -602,23 +658,30 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   if (!input_mode && train_fused_supported(e))
     return mf_grad_fused(e, s, F, rho, B, loss, grad_out, grad_used, st, w, w_off, b_off,
                          wo_off, ks, kchunk);
-  if (!input_mode && e.drop_p > 0.f)
-    return fail(RID_EUNSUPPORTED,
-                "dropout needs the fused training kernel (FP32, padded width <= 256)");
+
+  // the general form: residual layers, dropout (training only), raw CVs
+  const bool res = e.resnet;
+  const float drop_p = input_mode ? 0.f : e.drop_p;
+  const float drop_inv = drop_p > 0.f ? 1.f / (1.f - drop_p) : 1.f;
+  const uint8_t* raw = e.raw.empty() ? nullptr : e.d_raw;
+  auto skip = [&](int l) { return res && l >= 2; };   // layer l (1-based) adds its input
 
   // workspace (floats)
-  std::vector<long long> hh(L + 1), zd(L + 1);
+  std::vector<long long> hh(L + 1), zd(L + 1), tt(L + 1), dd(L + 1);
   long long tot = 0;
   for (int l = 0; l <= L; ++l) {
     hh[l] = tot;
     tot += (long long)K * 2 * B * w[l];
   }
   for (int l = 1; l <= L; ++l) {
-    zd[l] = tot;
-    tot += (long long)K * B * w[l];
+    zd[l] = tot; tot += (long long)K * B * w[l];
+    tt[l] = tot; tot += (long long)K * B * w[l];
+    dd[l] = tot; tot += (long long)K * B * w[l];
   }
   const long long vA = tot; tot += (long long)K * B * wmax;
   const long long vB = tot; tot += (long long)K * B * wmax;
+  const long long uA = tot; tot += res ? (long long)K * B * wmax : 0;
+  const long long uB = tot; tot += res ? (long long)K * B * wmax : 0;
   const long long lamA = tot; tot += (long long)K * 2 * B * wmax;
   const long long lamB = tot; tot += (long long)K * 2 * B * wmax;
   const long long sbuf = tot; tot += (long long)K * 2 * B * wmax;
@@ -635,69 +698,95 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   float* G = grad_out ? grad_out : W + grad;
   if (grad_used) *grad_used = G;
   ProfScope ps(kProfTrain, st);
+  const uint32_t step32 = (uint32_t)((unsigned long long)e.step & 0xFFFFFFFFull);
 
   auto slab = [&](int l) { return 2LL * B * w[l]; };
-  // ---- primal forward ----
+  // ---- primal forward: t_l = tanh(W_l h_{l-1} + b_l), then h_l and d_l ----
   hipLaunchKernelGGL(train_embed_kernel, dim3(grid1d((long long)K * B * n)), dim3(256), 0, st,
-                     s, B, n, K, W + hh[0], slab(0));
+                     s, B, n, K, raw, W + hh[0], slab(0));
   RID_HIP(hipGetLastError());
   for (int l = 1; l <= L; ++l) {
     GemmArgs g{};
     g.A = W + hh[l - 1]; g.sAb = slab(l - 1); g.sAm = w[l - 1]; g.sAk = 1;
     g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = 1; g.sBn = w[l - 1];
-    g.C = W + hh[l]; g.sCb = slab(l); g.sCm = w[l]; g.sCn = 1;
+    g.C = W + tt[l]; g.sCb = (long long)B * w[l]; g.sCm = w[l]; g.sCn = 1;
     g.bias = P + b_off[l - 1]; g.sBiasb = pm;
     g.M = B; g.N = w[l]; g.Kc = w[l - 1]; g.batch = K; g.mode = EPI_BIAS_TANH;
     if ((rs = gemm(g, st)) != RID_OK) return rs;
+    hipLaunchKernelGGL(act_kernel, dim3(grid1d((long long)K * B * ((w[l] + 3) / 4))), dim3(256),
+                       0, st, W + tt[l], l, w[l], B, K, drop_p, drop_inv, e.drop_seed, step32,
+                       skip(l) ? W + hh[l - 1] : nullptr, slab(l - 1), W + hh[l], slab(l),
+                       W + dd[l]);
+    RID_HIP(hipGetLastError());
   }
-  // ---- primal backward to u0 ----
+  // ---- primal backward to u0: v_l = u_l d_l, u_{l-1} = W_l^T v_l (+ u_l) ----
   hipLaunchKernelGGL(vlast_kernel, dim3(grid1d((long long)K * B * w[L])), dim3(256), 0, st,
-                     W + hh[L], slab(L), P, pm, (int)wo_off, w[L], B, K, W + vA);
+                     W + dd[L], P, pm, (int)wo_off, w[L], B, K, W + vA);
   RID_HIP(hipGetLastError());
+  long long uin = uA, uout = uB;
+  if (res) {   // u_L = w_o
+    hipLaunchKernelGGL(top_kernel, dim3(grid1d((long long)K * B * w[L])), dim3(256), 0, st, P,
+                       pm, (int)wo_off, w[L], B, K, B, 0, W + uin);
+    RID_HIP(hipGetLastError());
+  }
   long long vin = vA, vout = vB;
   for (int l = L; l >= 1; --l) {
     GemmArgs g{};
     g.A = W + vin; g.sAb = (long long)B * w[l]; g.sAm = w[l]; g.sAk = 1;
     g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = w[l - 1]; g.sBn = 1;
-    g.C = W + vout; g.sCb = (long long)B * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
+    g.sCb = (long long)B * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
     g.M = B; g.N = w[l - 1]; g.Kc = w[l]; g.batch = K;
     if (l > 1) {
-      g.mode = EPI_MUL_DTANH;
-      g.aux = W + hh[l - 1]; g.sXb = slab(l - 1); g.sXm = w[l - 1]; g.sXn = 1;
+      // v_{l-1} = (W_l^T v_l (+ u_l)) d_{l-1}; with a skip u_{l-1} is kept
+      g.mode = EPI_GEN;
+      g.C = skip(l) ? W + uout : nullptr;
+      g.add = skip(l) ? W + uin : nullptr; g.sAddb = (long long)B * w[l];
+      g.C2 = W + vout; g.sC2b = (long long)B * w[l - 1];
+      g.mul = W + dd[l - 1]; g.sMulb = (long long)B * w[l - 1];
     } else {
       g.mode = EPI_STORE;
+      g.C = W + vout;
     }
     if ((rs = gemm(g, st)) != RID_OK) return rs;
     std::swap(vin, vout);
+    if (skip(l)) std::swap(uin, uout);
   }
   // vin now holds u0 [K][B][2n]
   hipLaunchKernelGGL(residual_kernel,
                      dim3((unsigned)(((long long)K * B + kResWaves - 1) / kResWaves)),
                      dim3(kResWaves * 64), 0, st,
-                     s, F, rho, W + vin, B, n, K, W + hh[0], slab(0),
+                     s, F, rho, W + vin, B, n, K, raw, W + hh[0], slab(0),
                      rho ? nullptr : W + lrows);
   RID_HIP(hipGetLastError());
   if (!rho) {
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(K), dim3(256), 0, st, W + lrows, B, loss);
     RID_HIP(hipGetLastError());
   }
-  // ---- tangent forward: zd_l = W_l hd_{l-1}, hd_l = (1-h_l^2) zd_l ----
+  // ---- tangent forward: zd_l = W_l hd_{l-1}, hd_l = d_l zd_l (+ hd_{l-1}) ----
   for (int l = 1; l <= L; ++l) {
     GemmArgs g{};
     g.A = W + hh[l - 1] + (long long)B * w[l - 1]; g.sAb = slab(l - 1); g.sAm = w[l - 1]; g.sAk = 1;
     g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = 1; g.sBn = w[l - 1];
     g.C = W + zd[l]; g.sCb = (long long)B * w[l]; g.sCm = w[l]; g.sCn = 1;
     g.C2 = W + hh[l] + (long long)B * w[l]; g.sC2b = slab(l);
-    g.aux = W + hh[l]; g.sXb = slab(l); g.sXm = w[l]; g.sXn = 1;
-    g.M = B; g.N = w[l]; g.Kc = w[l - 1]; g.batch = K; g.mode = EPI_TANGENT;
+    g.mul = W + dd[l]; g.sMulb = (long long)B * w[l];
+    if (skip(l)) {
+      g.add2 = W + hh[l - 1] + (long long)B * w[l - 1];
+      g.sAdd2b = slab(l - 1);
+    }
+    g.M = B; g.N = w[l]; g.Kc = w[l - 1]; g.batch = K; g.mode = EPI_GEN;
     if ((rs = gemm(g, st)) != RID_OK) return rs;
   }
   // ---- adjoint sweep with weight gradients (or down to the input) ----
   long long lin = lamA, lout = lamB;
+  // top: lam_h_L = 0, lam_hd_L = w_o (stacked rows [0, B) and [B, 2B))
+  hipLaunchKernelGGL(top_kernel, dim3(grid1d((long long)K * 2 * B * w[L])), dim3(256), 0, st, P,
+                     pm, (int)wo_off, w[L], B, K, 2 * B, B, W + lin);
+  RID_HIP(hipGetLastError());
   for (int l = L; l >= 1; --l) {
     hipLaunchKernelGGL(adjoint_kernel, dim3(grid1d((long long)K * B * w[l])), dim3(256), 0, st,
-                       W + hh[l], slab(l), W + zd[l], W + lin, 2LL * B * w[l], P, pm,
-                       (int)wo_off, l == L ? 1 : 0, w[l], B, K, W + sbuf, 2LL * B * w[l]);
+                       W + tt[l], W + dd[l], W + zd[l], W + lin, 2LL * B * w[l], w[l], B, K,
+                       W + sbuf, 2LL * B * w[l]);
     RID_HIP(hipGetLastError());
     // dW_l = S^T [h_{l-1}; hd_{l-1}]  (contraction over 2B rows, split)
     if (!input_mode) {
@@ -721,12 +810,18 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
                      (int)b_off[l - 1], st)) != RID_OK)
       return rs;
     if (l > 1 || input_mode) {
-      // [lam_h ; lam_hd]_{l-1} = [lam_z ; lam_zd] W_l
+      // [lam_h ; lam_hd]_{l-1} = [lam_z ; lam_zd] W_l (+ [lam_h ; lam_hd]_l)
       GemmArgs g{};
       g.A = W + sbuf; g.sAb = 2LL * B * w[l]; g.sAm = w[l]; g.sAk = 1;
       g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = w[l - 1]; g.sBn = 1;
       g.C = W + lout; g.sCb = 2LL * B * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
-      g.M = 2 * B; g.N = w[l - 1]; g.Kc = w[l]; g.batch = K; g.mode = EPI_STORE;
+      g.M = 2 * B; g.N = w[l - 1]; g.Kc = w[l]; g.batch = K;
+      if (skip(l)) {
+        g.mode = EPI_GEN;
+        g.add = W + lin; g.sAddb = 2LL * B * w[l];
+      } else {
+        g.mode = EPI_STORE;
+      }
       if ((rs = gemm(g, st)) != RID_OK) return rs;
       std::swap(lin, lout);
     }

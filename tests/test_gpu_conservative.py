@@ -165,3 +165,48 @@ def test_conservative_at_256_cvs(torch, rid):
     out = _run(torch, rid, sys_, pos, params, widths, K, e0, e1, True)
     bound = walker_bounds(out["eps"].astype(np.float64), ref["eps"], e0, e1)
     assert_walkers(out["F"], ref["F"], bound, "conservative, 256 CVs")
+
+
+def test_conservative_residual_ensemble(torch, rid):
+    # residual networks take the training sweeps in input mode
+    sys_, pos, params, widths, K = workload("peptide20", 40, seed=25, K=3, widths=[128] * 3,
+                                            bias_std=0.1)
+    models = [tuple(m[:4]) + (True,) for m in oracle_models(params, sys_.n_cv, widths, K)]
+    ref1 = O.bias_force(pos.astype(np.float64), sys_.quads, models, 1e30, 2e30)
+    e0, e1 = 0.5 * ref1["eps"].min(), 2.0 * ref1["eps"].max()
+    ref = O.bias_force_conservative(pos.astype(np.float64), sys_.quads, models, e0, e1)
+    S = rid.System(sys_.n_atoms, sys_.quads)
+    E = rid.Ensemble(sys_.n_cv, widths, K, params)
+    E.set_resnet(True)
+    out = rid.bias_force(S, E, torch.from_numpy(pos).cuda(), float(e0), float(e1),
+                         conservative=True)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    bound = walker_bounds(out["eps"].astype(np.float64), ref["eps"], e0, e1)
+    assert_walkers(out["F"], ref["F"], bound, "conservative, residual")
+    frozen = O.bias_force(pos.astype(np.float64), sys_.quads, models, e0, e1)["F"]
+    assert O.max_rel_err(frozen, ref["F"]) > 1e-2
+
+
+def test_conservative_mixed_cv_table(torch, rid):
+    # 38 torsions and 6 distances: the raw CVs' chain is linear
+    sys_ = ridgen.with_distances(ridgen.system_peptide20(), 6)
+    widths, K = [64, 64], 4
+    pos = ridgen.f32(ridgen.chain_coords(sys_, 40, 27))
+    params = ridgen.xavier_ensemble(2 * sys_.n_cv, widths, K, 1000, 0.1)
+    models = oracle_models(params, sys_.n_cv, widths, K)
+    p64 = pos.astype(np.float64)
+    ref1 = O.bias_force(p64, sys_.quads, models, 1e30, 2e30, mask=sys_.mask)
+    e0, e1 = 0.5 * ref1["eps"].min(), 2.0 * ref1["eps"].max()
+    ref = O.bias_force_conservative(p64, sys_.quads, models, e0, e1, mask=sys_.mask)
+    S = rid.System(sys_.n_atoms, sys_.quads, sys_.mask)
+    E = rid.Ensemble(sys_.n_cv, widths, K, params)
+    E.set_angular_mask(sys_.mask)
+    out = rid.bias_force(S, E, torch.from_numpy(pos).cuda(), float(e0), float(e1),
+                         conservative=True)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    bound = walker_bounds(out["eps"].astype(np.float64), ref["eps"], e0, e1)
+    assert_walkers(out["F"], ref["F"], bound, "conservative, mixed table")
+    frozen = O.bias_force(p64, sys_.quads, models, e0, e1, mask=sys_.mask)["F"]
+    assert O.max_rel_err(frozen, ref["F"]) > 1e-2

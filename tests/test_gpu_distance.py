@@ -222,10 +222,8 @@ def test_mixed_refusals(torch, rid):
     E, _ = _ens(rid, sys_, [64, 64], 2, 1009)
     pos = _dev(torch, ridgen.f32(ridgen.chain_coords(sys_, 8, 1)))
     s = _dev(torch, ridgen.f32(ridgen.torus_samples(8, sys_.n_cv, 2)))
-    with pytest.raises(rid.RidError, match="EUNSUPPORTED"):
-        rid.bias_force(S, E, pos, 2.0, 3.0, conservative=True)
-    with pytest.raises(rid.RidError, match="EUNSUPPORTED"):
-        rid.mf_train_step(E, s, torch.zeros_like(s), 1e-3)
+    # (training and conservative switching take mixed tables: their parity
+    # is in tests/test_gpu_train.py and tests/test_gpu_conservative.py)
     with pytest.raises(rid.RidError, match="EUNSUPPORTED"):
         rid.mcmc_run(E, s.clone(), 1, 1.0, 0.3, 1)
     # the ensemble's mask must match the system's CV kinds
@@ -233,6 +231,8 @@ def test_mixed_refusals(torch, rid):
     E2.set_angular_mask(None)
     with pytest.raises(rid.RidError, match="EINVAL"):
         rid.bias_force(S, E2, pos, 2.0, 3.0)
+    with pytest.raises(rid.RidError, match="EINVAL"):
+        rid.bias_force(S, E2, pos, 2.0, 3.0, conservative=True)
     # malformed tables
     bad = sys_.quads.copy()
     drow = int(np.nonzero(sys_.mask == 0)[0][0])

@@ -118,12 +118,8 @@ def test_resnet_refusals(torch, rid):
     S = rid.System(sys_.n_atoms, sys_.quads)
     E = rid.Ensemble(sys_.n_cv, widths, K, params)
     E.set_resnet(True)
-    s = _dev(torch, ridgen.f32(ridgen.torus_samples(16, sys_.n_cv, seed=9)))
-    F = torch.zeros_like(s)
-    with pytest.raises(rid.RidError, match="EUNSUPPORTED"):
-        rid.bias_force(S, E, _dev(torch, pos), 2.0, 3.0, conservative=True)
-    with pytest.raises(rid.RidError, match="EUNSUPPORTED"):
-        rid.mf_train_step(E, s, F, 1e-3)
+    # (training and conservative switching take residual ensembles: their
+    # parity is in tests/test_gpu_train.py and tests/test_gpu_conservative.py)
     # unequal hidden widths, and 16-bit ensembles, are refused
     p2 = ridgen.xavier_ensemble(2 * sys_.n_cv, [64, 32], 2, 5, 0.0)
     E2 = rid.Ensemble(sys_.n_cv, [64, 32], 2, p2)

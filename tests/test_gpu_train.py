@@ -240,16 +240,117 @@ def test_dropout_masks_follow_the_step_counter(torch, rid):
     assert _per_member_err(grad.cpu().numpy(), grad_ref) <= GRAD_TOL
 
 
-def test_dropout_needs_the_fused_kernel(torch, rid):
-    n, widths, K, B = 5, [300, 40], 2, 50
+def _grad_ref_general(params, n, widths, K, s, F, rate=0.0, step=0, resnet=False, mask=None):
+    """Oracle loss and gradient per member, with the training-time dropout
+    masks of `step` (rate > 0), residual connections and an angular mask."""
+    models = ridgen.unpack_params(params, 2 * n, widths, K)
+    losses, grads = [], []
+    for k, m in enumerate(models):
+        if resnet:
+            m = tuple(m[:4]) + (True,)
+        sc = O.dropout_scales(len(s), widths, rate, DROP_SEED, step, k) if rate > 0 else None
+        loss, g = O.train_loss_grad(m, s.astype(np.float64), F.astype(np.float64), sc, mask)
+        losses.append(loss)
+        grads.append(O.flat_grad(g))
+    return np.array(losses), np.stack(grads)
+
+
+# The general sweeps (separate GEMMs): width 300 pads to 512, beyond the fused
+# kernel; residual ensembles of any width; dropout on both.
+@pytest.mark.parametrize("n,widths,K,B,rate,resnet", [(5, [300, 40], 2, 100, 0.1, False),
+                                                      (6, [256] * 3, 2, 200, 0.0, True),
+                                                      (4, [96] * 4, 3, 77, 0.25, True)])
+def test_general_sweeps_dropout_and_residual(torch, rid, n, widths, K, B, rate, resnet):
     params = ridgen.xavier_ensemble(2 * n, widths, K, 33, bias_std=0.1)
     s, F, _ = ridgen.mf_training_set(B, n)
     E = rid.Ensemble(n, widths, K, params)
-    E.set_dropout(0.1, 1)
-    with pytest.raises(rid.RidError):
-        rid.mf_loss_grad(E, _dev(torch, s), _dev(torch, F))
-    E.set_dropout(0.0, 1)
-    rid.mf_loss_grad(E, _dev(torch, s), _dev(torch, F))
+    if resnet:
+        E.set_resnet(True)
+    E.set_dropout(rate, DROP_SEED)
+    loss, grad = rid.mf_loss_grad(E, _dev(torch, s), _dev(torch, F))
     torch.cuda.synchronize()
+    loss_ref, grad_ref = _grad_ref_general(params, n, widths, K, s, F, rate, 0, resnet)
+    lerr = np.max(np.abs(loss.cpu().numpy() - loss_ref) / loss_ref)
+    gerr = _per_member_err(grad.cpu().numpy(), grad_ref)
+    print(f"rate {rate} resnet {resnet} widths={widths}: loss rel err {lerr:.2e}, "
+          f"grad err {gerr:.2e}", flush=True)
+    assert lerr <= 1e-5 and gerr <= GRAD_TOL
+    # the masks and the skips matter: the plain gradient is far off
+    _, plain = _grad_ref(params, n, widths, K, s, F)
+    assert _per_member_err(plain, grad_ref) > 100 * GRAD_TOL
     with pytest.raises(rid.RidError):
         E.set_dropout(1.0, 1)
+
+
+def test_paper_training_config(torch, rid):
+    """The paper's Train example for chignolin: 4 members of 4 hidden layers
+    of 300 units (padded to 512), residual connections, dropout 0.1, batch
+    128, init_lr / decay as printed, on the example's 18 torsion CVs: the
+    gradient against the oracle, then three Adam steps (each with its own
+    dropout masks) against the oracle's."""
+    import json
+    import os
+    cfg = {k: v["value"] for k, v in json.load(open(os.path.join(
+        os.path.dirname(__file__), "golden", "paper_config.json"))).items() if k != "_about"}
+    n, widths, K = cfg["chignolin_angular_mask_len"], cfg["neurons"], cfg["numb_models"]
+    B, rate = cfg["batch_size"], cfg["drop_out_rate"]
+    assert cfg["resnet"] is True and (n, widths, K, B, rate) == (18, [300] * 4, 4, 128, 0.1)
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 1000, bias_std=0.1)
+    s_all, F_all, _ = ridgen.mf_training_set(3 * B, n)
+    E = rid.Ensemble(n, widths, K, params)
+    E.set_resnet(True)
+    E.set_dropout(rate, DROP_SEED)
+    loss, grad = rid.mf_loss_grad(E, _dev(torch, s_all[:B]), _dev(torch, F_all[:B]))
+    torch.cuda.synchronize()
+    loss_ref, grad_ref = _grad_ref_general(params, n, widths, K, s_all[:B], F_all[:B], rate, 0,
+                                           True)
+    gerr = _per_member_err(grad.cpu().numpy(), grad_ref)
+    print(f"paper config: loss {loss.cpu().numpy()}, grad err {gerr:.2e}", flush=True)
+    assert np.max(np.abs(loss.cpu().numpy() - loss_ref) / loss_ref) <= 1e-5
+    assert gerr <= GRAD_TOL
+    models = [tuple(m[:4]) + (True,) for m in ridgen.unpack_params(params, 2 * n, widths, K)]
+    states = [(np.zeros(O.flat_model(m).size), np.zeros(O.flat_model(m).size), 0) for m in models]
+    for step in range(3):
+        sl = slice(step * B, (step + 1) * B)
+        lr = O.lr_at(step, cfg["init_lr"], cfg["decay_steps"], cfg["decay_rate"])
+        loss = rid.mf_train_step(E, _dev(torch, s_all[sl]), _dev(torch, F_all[sl]), lr)
+        models, states, loss_ref = O.train_step(models, s_all[sl], F_all[sl], states, lr,
+                                                dropout=(rate, DROP_SEED))
+        torch.cuda.synchronize()
+        lerr = np.max(np.abs(loss.cpu().numpy() - loss_ref) / loss_ref)
+        print(f"step {step}: loss rel err {lerr:.2e}", flush=True)
+        assert lerr <= 1e-4
+    assert E.step == 3
+    got = E.get_params().astype(np.float64).reshape(K, -1)
+    ref = np.stack([O.flat_model(m) for m in models])
+    step_scale = 3 * O.INIT_LR
+    d = np.abs(got - ref)
+    assert np.quantile(d, 0.99) <= 0.05 * step_scale
+    assert d.max() <= 2.5 * step_scale
+
+
+def test_masked_training_parity(torch, rid):
+    """Training on the mixed table (38 torsions, 6 distances): raw CVs enter
+    as (s, 0) and their mean force is dA/dx_i; residual and plain."""
+    base = ridgen.with_distances(ridgen.system_peptide20(), 6)
+    n, widths, K, B = base.n_cv, [64, 64], 3, 300
+    m = base.mask.astype(bool)
+    rng = np.random.default_rng(41)
+    s = ridgen.f32(np.where(m, rng.uniform(-np.pi, np.pi, (B, n)), rng.uniform(0.3, 1.5, (B, n))))
+    F = ridgen.f32(rng.normal(0.0, 2.0, (B, n)))
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 43, bias_std=0.1)
+    for resnet in (False, True):
+        E = rid.Ensemble(n, widths, K, params)
+        E.set_angular_mask(base.mask)
+        if resnet:
+            E.set_resnet(True)
+        loss, grad = rid.mf_loss_grad(E, _dev(torch, s), _dev(torch, F))
+        torch.cuda.synchronize()
+        loss_ref, grad_ref = _grad_ref_general(params, n, widths, K, s, F, resnet=resnet,
+                                               mask=base.mask)
+        gerr = _per_member_err(grad.cpu().numpy(), grad_ref)
+        print(f"masked resnet={resnet}: grad err {gerr:.2e}", flush=True)
+        assert np.max(np.abs(loss.cpu().numpy() - loss_ref) / loss_ref) <= 1e-5
+        assert gerr <= GRAD_TOL
+    _, unmasked = _grad_ref_general(params, n, widths, K, s, F)
+    assert _per_member_err(unmasked, grad_ref) > 100 * GRAD_TOL
