@@ -141,10 +141,9 @@ int64_t rid_ensemble_step(rid_ensemble ens);
  * (2 (x >> 9) + 1) 2^-24 of word j mod 4 of the Philox4x32-10 block with
  * counter (b, step mod 2^32, 16 k + l, j div 4) and key (seed mod 2^32,
  * seed div 2^32) is >= p (FP32), step being rid_ensemble_step at the call.
- * The bias path, MCMC and selection evaluate the full network.  Dropout
- * needs the fused training kernel (FP32 ensembles of padded width <= 256
- * whose input tile fits it): training calls on other ensembles return
- * RID_EUNSUPPORTED while p > 0.  Errors: RID_EINVAL (NULL, p outside [0, 1)). */
+ * The bias path, MCMC and selection evaluate the full network.  With
+ * residual connections the mask scales each layer's tanh branch, not the
+ * skip.  Errors: RID_EINVAL (NULL, p outside [0, 1)). */
 rid_status rid_ensemble_set_dropout(rid_ensemble ens, float rate, uint64_t seed);
 /* rid_ensemble_set_resnet - residual connections (the `resnet` training
  * setting, "Training phase": hidden layers of equal width joined by residual
@@ -152,11 +151,12 @@ rid_status rid_ensemble_set_dropout(rid_ensemble ens, float rate, uint64_t seed)
  * its input, h_l = h_{l-1} + tanh(W_l h_{l-1} + b_l) for l >= 2 (the first
  * layer maps the CV encoding and has no skip); enable = 0 restores the plain
  * MLP.  The packed parameters are the same in both forms.  Takes effect on
- * the next call: rid_bias_force, rid_model_dev, rid_select, rid_mcmc_run
- * and the server evaluate the residual form; rid_bias_force_conservative,
- * rid_mf_train_step, rid_mf_loss_grad and rid_mf_grad return
- * RID_EUNSUPPORTED while it is on.  Errors: RID_EINVAL (NULL, hidden widths
- * not all equal), RID_EUNSUPPORTED (BF16/FP16 ensemble). */
+ * the next call: every evaluation (rid_bias_force, rid_model_dev,
+ * rid_select, rid_mcmc_run, the server), conservative switching and the
+ * training calls use the residual form (training and conservative
+ * switching through the general sweeps: the tangent and both adjoints carry
+ * the skip too).  Errors: RID_EINVAL (NULL, hidden widths not all equal),
+ * RID_EUNSUPPORTED (16-bit ensemble: the 16-bit kernels have no skip). */
 rid_status rid_ensemble_set_resnet(rid_ensemble ens, int enable);
 /* rid_ensemble_set_angular_mask - which network inputs are periodic (the
  * `angular_mask` setting of "CV selection").  angular_mask: host uint8
@@ -166,11 +166,23 @@ rid_status rid_ensemble_set_resnet(rid_ensemble ens, int enable);
  * mean force is dA/dx_i.  rid_model_dev encodes its CVs with the mask;
  * rid_bias_force and the server need the system's distance rows to be the
  * ensemble's raw CVs (RID_EINVAL otherwise); rid_select leaves raw CVs
- * unwrapped in its clustering distance.  While any entry is 0,
- * rid_mcmc_run, rid_bias_force_conservative and the training calls return
- * RID_EUNSUPPORTED.  Synchronizes the device.  Errors:
+ * unwrapped in its clustering distance; the training calls fit dA/dx_i to
+ * a raw CV's label and rid_bias_force_conservative uses its linear chain;
+ * rid_mcmc_run walks raw CVs in their box (rid_ensemble_set_cv_bounds,
+ * RID_EINVAL until it is set).  Synchronizes the device.  Errors:
  * RID_EINVAL (NULL ensemble, an entry other than 0 or 1), RID_ENOMEM. */
 rid_status rid_ensemble_set_angular_mask(rid_ensemble ens, const uint8_t* angular_mask);
+/* rid_ensemble_set_cv_bounds - sampling box of the raw CVs for rid_mcmc_run
+ * (the dimension-reduction settings' `cv_lower_bound` / `cv_upper_bound`,
+ * which the paper introduces for distance CVs).  lower, upper: host float
+ * [n_cv] (entries of angular CVs are checked but unused), or both NULL to
+ * clear.  A raw CV then moves by step (upper - lower) / 2pi (2u - 1), is
+ * not wrapped, a proposal that takes any raw CV outside [lower, upper] is
+ * rejected, and its histogram bins cover [lower, upper).  Synchronizes the
+ * device.  Errors: RID_EINVAL (NULL ensemble, one bound NULL, a non-finite
+ * bound or lower >= upper), RID_ENOMEM. */
+rid_status rid_ensemble_set_cv_bounds(rid_ensemble ens, const float* lower,
+                                      const float* upper);
 void rid_ensemble_destroy(rid_ensemble ens);
 
 /* ------------------------------------------------------------------------
@@ -326,7 +338,7 @@ rid_status rid_bias_force_conservative(rid_system sys, rid_ensemble ens,
  * rid_mcmc_run - Metropolis MCMC in CV space on the ensemble's free energy
  * ("Dimension reduction phase": numb_walkers walkers, numb_steps steps, a
  * temperature, histograms of every CV and of the projected pair
- * proj_cv_index; the projected PMF is -kT ln p).  Torsion CVs only.
+ * proj_cv_index; the projected PMF is -kT ln p).
  * Per step t and walker w: s' = wrap(s + step_size (2u - 1)) on every CV,
  * accepted when u_n < exp(-(Abar(s') - Abar(s))/kT), Abar the ensemble
  * mean free energy (kJ/mol) from the ensemble's kernels at its precision,
@@ -334,8 +346,13 @@ rid_status rid_bias_force_conservative(rid_system sys, rid_ensemble ens,
  * Philox4x32-10, counter (w, t mod 2^32, t div 2^32, j), key (seed mod 2^32,
  * seed div 2^32), word 4j+i -> u = (2 (x >> 9) + 1) 2^-24; words 0..n-1 drive
  * the proposal, word n the acceptance.  Steps step0 .. step0+n_steps-1, so
- * consecutive calls with consecutive step0 continue one chain.
- *   d_s        [W][n_cv] angles, in/out (wrapped to [-pi, pi) on entry)
+ * consecutive calls with consecutive step0 continue one chain.  Raw CVs
+ * (an ensemble angular mask with zeros: distances) walk in the box of
+ * rid_ensemble_set_cv_bounds: s'_i = s_i + step_size (hi_i - lo_i)/2pi
+ * (2u - 1), unwrapped; a proposal with any raw CV outside its box is
+ * rejected; their bins cover [lo_i, hi_i).
+ *   d_s        [W][n_cv] angles (wrapped to [-pi, pi) on entry) and raw
+ *              CVs (as given), in/out
  *   kT         k_B T in kJ/mol (> 0); step_size in (0, pi]
  *   nbins      bins over [-pi, pi) per CV (>= 1)
  *   d_hist1    [n_cv][nbins] uint32 counts, ACCUMULATED (caller zeroes)
@@ -345,7 +362,7 @@ rid_status rid_bias_force_conservative(rid_system sys, rid_ensemble ens,
  * Uses the ensemble's scratch: not concurrent with other calls on it.
  * Errors: RID_EINVAL for NULL ens/d_s/d_hist1, W < 1, n_steps < 0,
  *         step0 < 0, kT <= 0, step_size outside (0, pi], nbins < 1, proj
- *         index outside [0, n_cv).
+ *         index outside [0, n_cv), raw CVs without a box.
  * ------------------------------------------------------------------------ */
 rid_status rid_mcmc_run(rid_ensemble ens, float* d_s, int W, int64_t n_steps,
                         int64_t step0, double kT, float step_size, uint64_t seed,

@@ -793,14 +793,21 @@ def cv_bins(s, nbins):
     return np.clip(b, 0, nbins - 1).astype(np.int64)
 
 
-def ensemble_energy(models, s):
+def ensemble_energy(models, s, mask=None):
     """Abar(s): the ensemble mean of the members' free energies."""
-    A, _ = ensemble_mean_force(models, s)
+    A, _ = ensemble_mean_force(models, s, mask)
     return np.mean(A, axis=1)
 
 
+def box_bins(s, lo, hi, nbins):
+    """Histogram bin of a raw CV in its box [lo, hi):
+    floor((s - lo) nbins / (hi - lo)), clamped to [0, nbins - 1]."""
+    b = np.floor((np.asarray(s, np.float64) - lo) * (nbins / (hi - lo)))
+    return np.clip(b, 0, nbins - 1).astype(np.int64)
+
+
 def mcmc_run(models, s0, n_steps, kT, step, seed, t0=0, proj=(0, 1), nbins=101,
-             keep_path=False):
+             keep_path=False, mask=None, lower=None, upper=None):
     """Metropolis MCMC in CV space on the ensemble's free energy, the
     dimension-reduction phase: many walkers, a temperature, histograms of
     every CV and of one projected pair, PMF = -kT ln p.  Readings (the paper
@@ -810,25 +817,57 @@ def mcmc_run(models, s0, n_steps, kT, step, seed, t0=0, proj=(0, 1), nbins=101,
     words 0..n-1); accept when u_n < exp(-(Abar(s') - Abar(s))/kT) (word n);
     after each step the walker's current state is counted in the 1D
     histograms of every CV and the 2D histogram of the pair ``proj``.
+
+    Raw CVs (angular mask 0, distances: the paper's `cv_type` "dis") walk in
+    the box [lower_i, upper_i] of the dimension-reduction settings
+    (`cv_lower_bound`, `cv_upper_bound`, which the paper introduces to bound
+    distance CVs).  Reading: the proposal moves a raw CV by
+    step (upper_i - lower_i) / 2pi (2u - 1) -- the same fraction of its
+    range as the angles' step of the circle -- without wrapping; a proposal
+    with a raw CV outside its box has zero target density and is rejected;
+    raw CVs are binned over their box (box_bins).  A walker may start outside
+    its box: it can then only move into it.
+
     s0: [W][n].  Returns dict(s, A, hist1 [n][nbins], hist2 [nbins][nbins],
     accepted, path [n_steps][W][n] when keep_path)."""
-    s = wrap_torus(s0)
-    W, n = s.shape
-    A = ensemble_energy(models, s)
+    s0 = np.asarray(s0, dtype=np.float64)
+    W, n = s0.shape
+    ang = np.ones(n, bool) if mask is None else np.asarray(mask).astype(bool)
+    if not np.all(ang):
+        lo = np.asarray(lower, dtype=np.float64)
+        hi = np.asarray(upper, dtype=np.float64)
+        if not np.all(hi[~ang] > lo[~ang]):
+            raise ValueError("raw CVs need lower < upper")
+        span = np.where(ang, 2.0 * math.pi, hi - lo)
+    s = np.where(ang, wrap_torus(s0), s0)
+    A = ensemble_energy(models, s, mask)
     hist1 = np.zeros((n, nbins), dtype=np.int64)
     hist2 = np.zeros((nbins, nbins), dtype=np.int64)
     accepted = 0
     path = []
     walkers = np.arange(W)
+
+    def bins(v):
+        b = cv_bins(v, nbins)
+        if np.all(ang):
+            return b
+        return np.where(ang, b, box_bins(v, lo, hi, nbins))
+
     for t in range(t0, t0 + n_steps):
         u = mcmc_uniforms(walkers, t, n + 1, seed)
-        sp = wrap_torus(s + step * (2.0 * u[:, :n] - 1.0))
-        Ap = ensemble_energy(models, sp)
-        acc = u[:, n] < np.exp(-(Ap - A) / kT)
+        if np.all(ang):
+            sp = wrap_torus(s + step * (2.0 * u[:, :n] - 1.0))
+            inbox = np.ones(W, bool)
+        else:
+            prop = s + step * span / (2.0 * math.pi) * (2.0 * u[:, :n] - 1.0)
+            sp = np.where(ang, wrap_torus(prop), prop)
+            inbox = np.all(ang | ((sp >= lo) & (sp <= hi)), axis=1)
+        Ap = ensemble_energy(models, sp, mask)
+        acc = inbox & (u[:, n] < np.exp(-(Ap - A) / kT))
         s = np.where(acc[:, None], sp, s)
         A = np.where(acc, Ap, A)
         accepted += int(np.sum(acc))
-        b = cv_bins(s, nbins)
+        b = bins(s)
         for i in range(n):
             hist1[i] += np.bincount(b[:, i], minlength=nbins)
         np.add.at(hist2, (b[:, proj[0]], b[:, proj[1]]), 1)

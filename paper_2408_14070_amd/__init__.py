@@ -29,7 +29,7 @@ EXPORTS = (
     "rid_last_error", "rid_version", "rid_system_create", "rid_system_destroy",
     "rid_packed_param_count", "rid_ensemble_create", "rid_ensemble_get_params",
     "rid_ensemble_set_params", "rid_ensemble_load_params", "rid_ensemble_step", "rid_ensemble_set_dropout",
-    "rid_ensemble_set_resnet", "rid_ensemble_set_angular_mask",
+    "rid_ensemble_set_resnet", "rid_ensemble_set_angular_mask", "rid_ensemble_set_cv_bounds",
     "rid_ensemble_destroy",
     "rid_cv_eval", "rid_model_dev", "rid_cluster_frames", "rid_select", "rid_bias_force",
     "rid_bias_force_conservative", "rid_bias_force_noalloc", "rid_noalloc_scratch_floats",
@@ -88,6 +88,7 @@ def lib():
         "rid_ensemble_set_dropout": (i, [vp, f, ctypes.c_uint64]),
         "rid_ensemble_set_resnet": (i, [vp, i]),
         "rid_ensemble_set_angular_mask": (i, [vp, vp]),
+        "rid_ensemble_set_cv_bounds": (i, [vp, vp, vp]),
         "rid_ensemble_destroy": (None, [vp]),
         "rid_cv_eval": (i, [vp, vp, i, vp, vp, vp]),
         "rid_model_dev": (i, [vp, vp, i, vp, vp, vp, vp, vp]),
@@ -242,6 +243,19 @@ class Ensemble:
         if m.shape != (self.n_cv,):
             raise ValueError("angular_mask must be [n_cv]")
         _check(lib().rid_ensemble_set_angular_mask(self.handle, m.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_cv_bounds(self, lower=None, upper=None):
+        """rid_ensemble_set_cv_bounds: the MCMC box of the raw CVs (host
+        arrays [n_cv]); None clears."""
+        if lower is None and upper is None:
+            _check(lib().rid_ensemble_set_cv_bounds(self.handle, None, None))
+            return
+        lo = np.ascontiguousarray(np.asarray(lower, dtype=np.float32))
+        hi = np.ascontiguousarray(np.asarray(upper, dtype=np.float32))
+        if lo.shape != (self.n_cv,) or hi.shape != (self.n_cv,):
+            raise ValueError("bounds must be [n_cv]")
+        _check(lib().rid_ensemble_set_cv_bounds(self.handle, lo.ctypes.data_as(ctypes.c_void_p),
+                                                hi.ctypes.data_as(ctypes.c_void_p)))
 
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:

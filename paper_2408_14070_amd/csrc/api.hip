@@ -126,6 +126,7 @@ static void free_ensemble(rid_ensemble_impl& e) {
   dev_free(e.d_bo);
   dev_free(e.d_vscale);
   dev_free(e.d_raw);
+  dev_free(e.d_bounds);
   e.ws_x.release();
   e.ws_A.release();
   e.ws_g.release();
@@ -425,6 +426,33 @@ rid_status rid_ensemble_set_dropout(rid_ensemble ens, float rate, uint64_t seed)
   return RID_OK;
 }
 
+rid_status rid_ensemble_set_cv_bounds(rid_ensemble ens, const float* lower,
+                                      const float* upper) {
+  if (!ens) return fail(RID_EINVAL, "NULL argument");
+  rid_ensemble_impl& e = ens->impl;
+  if ((lower == nullptr) != (upper == nullptr))
+    return fail(RID_EINVAL, "give both bounds or neither");
+  std::vector<float> b;
+  if (lower) {
+    b.resize(2 * (size_t)e.n_cv);
+    for (int i = 0; i < e.n_cv; ++i) {
+      if (!std::isfinite(lower[i]) || !std::isfinite(upper[i]) || !(lower[i] < upper[i]))
+        return fail(RID_EINVAL, "every CV needs finite bounds with lower < upper");
+      b[i] = lower[i];
+      b[e.n_cv + i] = upper[i];
+    }
+  }
+  RID_HIP(hipDeviceSynchronize());   // calls in flight may still read the old bounds
+  dev_free(e.d_bounds);
+  e.bounds.clear();
+  if (b.empty()) return RID_OK;
+  rid_status st = dev_alloc(&e.d_bounds, b.size());
+  if (st != RID_OK) return st;
+  RID_HIP(hipMemcpy(e.d_bounds, b.data(), b.size() * sizeof(float), hipMemcpyHostToDevice));
+  e.bounds = b;
+  return RID_OK;
+}
+
 rid_status rid_ensemble_set_angular_mask(rid_ensemble ens, const uint8_t* angular_mask) {
   if (!ens) return fail(RID_EINVAL, "NULL argument");
   rid_ensemble_impl& e = ens->impl;
@@ -579,8 +607,8 @@ rid_status rid_mcmc_run(rid_ensemble ens, float* d_s, int W, int64_t n_steps,
   if (!(step_size > 0.f) || step_size > 3.14159265358979f)
     return fail(RID_EINVAL, "step_size must be in (0, pi]");
   const int n = ens->impl.n_cv;
-  if (!ens->impl.raw.empty())
-    return fail(RID_EUNSUPPORTED, "the MCMC walks on the torus (angular mask all 1)");
+  if (!ens->impl.raw.empty() && ens->impl.bounds.empty())
+    return fail(RID_EINVAL, "raw CVs need their sampling box (rid_ensemble_set_cv_bounds)");
   if (nbins < 1 || proj0 < 0 || proj0 >= n || proj1 < 0 || proj1 >= n)
     return fail(RID_EINVAL, "need nbins >= 1 and projected indices in [0, n_cv)");
   return launch_mcmc(ens->impl, d_s, W, n_steps, step0, kT, step_size, seed, proj0, proj1,

@@ -12,6 +12,13 @@
 // Words 0..n-1 drive the proposal, word n the acceptance.  Histogram counts
 // are integer atomics, so the result does not depend on their order.
 //
+// Raw CVs (angular mask 0: distances) walk in their box [lo_i, hi_i] (the
+// dimension-reduction settings' lower and upper CV bounds): the proposal
+// moves them by step (hi_i - lo_i) / 2pi (2u - 1) without wrapping, a move
+// that takes any raw CV outside its box is rejected (flag computed with the
+// proposal), they enter the network as (s, 0), and they are binned over
+// their box.
+//
 // One wave per walker, lanes over CVs.  A step kernel issues every load it
 // needs (member energies, the current state and the proposal, the walker's
 // acceptance count) before it waits, keeps the updated state in registers
@@ -63,7 +70,47 @@ struct McmcArgs {
   unsigned* hist2;          // [nbins][nbins] or null
   unsigned long long* accepted;
   unsigned long long* acc_count;   // [W] acceptances of this call, per walker
+  const uint8_t* raw;       // [n] 1 = raw CV (null: every CV angular)
+  const float* lo;          // [n] box of the raw CVs
+  const float* hi;          // [n]
+  int* inbox;               // [W] the pending proposal keeps every raw CV in its box
 };
+
+// Bin of CV i's value v: the circle for angles, the box for raw CVs.
+__device__ inline int bin_of(const McmcArgs& a, int i, float v) {
+  if (a.raw && a.raw[i]) {
+    const float l = a.lo[i], h = a.hi[i];
+    const int b = (int)floorf((v - l) * ((float)a.nbins / (h - l)));
+    return min(max(b, 0), a.nbins - 1);
+  }
+  return cv_bin(v, a.nbins);
+}
+
+// CV i moved from v by the uniform u: wrapped on the circle, or scaled to its
+// box and unwrapped for a raw CV (in_box says whether it stays inside).
+__device__ inline float step_cv(const McmcArgs& a, int i, float v, float u, bool& in_box) {
+  if (a.raw && a.raw[i]) {
+    const float l = a.lo[i], h = a.hi[i];
+    const float vp = v + a.step * ((h - l) * (1.f / kTwoPi)) * (2.f * u - 1.f);
+    in_box = vp >= l && vp <= h;
+    return vp;
+  }
+  in_box = true;
+  return wrap_pi(v + a.step * (2.f * u - 1.f));
+}
+
+// (x_i, x_{n+i}): (cos v, sin v), or (v, 0) for a raw CV
+__device__ inline void encode_cv(const McmcArgs& a, int i, float v, float* x) {
+  if (a.raw && a.raw[i]) {
+    x[i] = v;
+    x[a.n + i] = 0.f;
+    return;
+  }
+  float sn, cs;
+  sincosf(v, &sn, &cs);
+  x[i] = cs;
+  x[a.n + i] = sn;
+}
 
 // Abar of walker w: lane k holds member k (K <= 64); the sum is in FP64, so
 // its order does not matter at FP32 inputs.  Every lane of the wave calls it.
@@ -72,17 +119,20 @@ __device__ inline double member_mean(const McmcArgs& a, int w, int lane) {
   return wave_sum((double)ak) / a.K;
 }
 
-// Proposal of step t for walker w (one wave, lanes over CVs) and its encoding.
+// Proposal of step t for walker w (one wave, lanes over CVs), its encoding
+// and its box flag.
 __device__ inline void propose(const McmcArgs& a, int w, long long t, int lane) {
+  bool ok = true;
   for (int i = lane; i < a.n; i += kWave) {
     const float u = mcmc_uniform(w, t, i, a.seed);
-    const float v = wrap_pi(a.s[(size_t)w * a.n + i] + a.step * (2.f * u - 1.f));
+    bool in_box;
+    const float v = step_cv(a, i, a.s[(size_t)w * a.n + i], u, in_box);
+    ok = ok && in_box;
     a.sp[(size_t)w * a.n + i] = v;
-    float sn, cs;
-    sincosf(v, &sn, &cs);
-    a.xp[(size_t)w * 2 * a.n + i] = cs;
-    a.xp[(size_t)w * 2 * a.n + a.n + i] = sn;
+    encode_cv(a, i, v, a.xp + (size_t)w * 2 * a.n);
   }
+  ok = __all(ok);
+  if (lane == 0) a.inbox[w] = ok ? 1 : 0;
 }
 
 // Encoding of the (wrapped) current state, to evaluate its energy.
@@ -91,13 +141,11 @@ __global__ __launch_bounds__(kMcmcWaves * kWave) void mcmc_encode_kernel(McmcArg
   if (w >= a.W) return;
   if (lane == 0) a.acc_count[w] = 0ull;
   for (int i = lane; i < a.n; i += kWave) {
-    const float s0 = a.s[(size_t)w * a.n + i];   // any real angle
-    const float v = wrap_pi(s0 - kTwoPi * floorf((s0 + kPi) / kTwoPi));
+    const float s0 = a.s[(size_t)w * a.n + i];   // any real angle (raw CVs as given)
+    const float v = (a.raw && a.raw[i]) ? s0
+                                         : wrap_pi(s0 - kTwoPi * floorf((s0 + kPi) / kTwoPi));
     a.s[(size_t)w * a.n + i] = v;
-    float sn, cs;
-    sincosf(v, &sn, &cs);
-    a.xp[(size_t)w * 2 * a.n + i] = cs;
-    a.xp[(size_t)w * 2 * a.n + a.n + i] = sn;
+    encode_cv(a, i, v, a.xp + (size_t)w * 2 * a.n);
   }
 }
 
@@ -123,14 +171,16 @@ __global__ __launch_bounds__(kMcmcWaves * kWave) void mcmc_step_kernel(McmcArgs 
   const float ak = lane < a.K ? a.A[(size_t)lane * a.W + w] : 0.f;
   const double acur = a.acur[w];
   const unsigned long long cnt = a.acc_count[w];
+  const bool inbox = a.raw ? a.inbox[w] != 0 : true;
   const int i0c = min(lane, n - 1);
   float sc = a.s[row + i0c], spc = a.sp[row + i0c];
   // the random numbers do not depend on the loads
   const float un = mcmc_uniform(w, t, n, a.seed);
   float unext = last ? 0.f : mcmc_uniform(w, t + 1, i0c, a.seed);
   const double ap = wave_sum((double)ak) / a.K;
-  const bool acc = (double)un < exp(-(ap - acur) / a.kT);
+  const bool acc = inbox && (double)un < exp(-(ap - acur) / a.kT);
   float p0 = 0.f, p1 = 0.f;
+  bool ok = true;                       // the next proposal stays in the box
   for (int i0 = 0; i0 < n; i0 += kWave) {
     const int i = i0 + lane;
     if (i0 > 0) {
@@ -146,24 +196,26 @@ __global__ __launch_bounds__(kMcmcWaves * kWave) void mcmc_step_kernel(McmcArgs 
     }
     if (i < n) {
       if (acc) a.s[row + i] = v;
-      atomicAdd(&a.hist1[(size_t)i * a.nbins + cv_bin(v, a.nbins)], 1u);
+      atomicAdd(&a.hist1[(size_t)i * a.nbins + bin_of(a, i, v)], 1u);
       if (!last) {
-        const float vp = wrap_pi(v + a.step * (2.f * unext - 1.f));
+        bool in_box;
+        const float vp = step_cv(a, i, v, unext, in_box);
+        ok = ok && in_box;
         a.sp[row + i] = vp;
-        float sn, cs;
-        sincosf(vp, &sn, &cs);
-        a.xp[2 * row + i] = cs;
-        a.xp[2 * row + n + i] = sn;
+        encode_cv(a, i, vp, a.xp + 2 * row);
       }
     }
   }
+  if (a.raw && !last) ok = __all(ok);
   if (lane == 0) {
     if (acc) {
       a.acur[w] = ap;
       a.acc_count[w] = cnt + 1ull;
     }
+    if (a.raw && !last) a.inbox[w] = ok ? 1 : 0;
     if (a.hist2)
-      atomicAdd(&a.hist2[(size_t)cv_bin(p0, a.nbins) * a.nbins + cv_bin(p1, a.nbins)], 1u);
+      atomicAdd(&a.hist2[(size_t)bin_of(a, a.proj0, p0) * a.nbins + bin_of(a, a.proj1, p1)],
+                1u);
   }
 }
 
@@ -193,9 +245,9 @@ rid_status launch_mcmc(rid_ensemble_impl& e, float* s, int W, long long n_steps,
   rid_status r;
   const size_t wn = (size_t)W * n;
   // workspace: Abar (FP64) [W], acceptance counts [W], proposal [W][n], its
-  // encoding [W][2n]
-  if ((r = e.ws_cons.ensure(2 * sizeof(double) * (size_t)W + sizeof(float) * 3 * wn + 256)) !=
-      RID_OK)
+  // encoding [W][2n], the proposals' box flags [W]
+  if ((r = e.ws_cons.ensure(2 * sizeof(double) * (size_t)W + sizeof(float) * 3 * wn +
+                            sizeof(int) * (size_t)W + 256)) != RID_OK)
     return r;
   if ((r = e.ws_A.ensure(sizeof(float) * K * (size_t)W)) != RID_OK) return r;
   if (e.frag_dirty) {
@@ -209,6 +261,12 @@ rid_status launch_mcmc(rid_ensemble_impl& e, float* s, int W, long long n_steps,
   a.acc_count = reinterpret_cast<unsigned long long*>(base + sizeof(double) * (size_t)W);
   a.sp = reinterpret_cast<float*>(base + 2 * sizeof(double) * (size_t)W);
   a.xp = a.sp + wn;
+  a.inbox = reinterpret_cast<int*>(a.xp + 2 * wn);
+  if (!e.raw.empty()) {
+    a.raw = e.d_raw;
+    a.lo = e.d_bounds;
+    a.hi = e.d_bounds + n;
+  }
   a.A = e.ws_A.as<float>();
   a.W = W;
   a.n = n;

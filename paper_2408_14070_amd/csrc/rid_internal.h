@@ -145,6 +145,9 @@ struct rid_ensemble_impl {
   // angular mask of the inputs: CVs with raw[i] = 1 enter as (s_i, 0)
   std::vector<uint8_t> raw;            // [n_cv] (empty: every CV angular)
   uint8_t* d_raw = nullptr;            // device copy, or null when no CV is raw
+  // MCMC box of the raw CVs: lower [n], then upper [n] (null until set)
+  std::vector<float> bounds;
+  float* d_bounds = nullptr;
   // kernel-layout parameters
   std::vector<LayerDev> layers;
   size_t frag_bytes_per_model = 0;

@@ -224,7 +224,8 @@ def test_mixed_refusals(torch, rid):
     s = _dev(torch, ridgen.f32(ridgen.torus_samples(8, sys_.n_cv, 2)))
     # (training and conservative switching take mixed tables: their parity
     # is in tests/test_gpu_train.py and tests/test_gpu_conservative.py)
-    with pytest.raises(rid.RidError, match="EUNSUPPORTED"):
+    # MCMC on raw CVs needs their sampling box first
+    with pytest.raises(rid.RidError, match="EINVAL"):
         rid.mcmc_run(E, s.clone(), 1, 1.0, 0.3, 1)
     # the ensemble's mask must match the system's CV kinds
     E2, _ = _ens(rid, sys_, [64, 64], 2, 1010)

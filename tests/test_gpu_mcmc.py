@@ -156,3 +156,73 @@ def test_mcmc_at_256_cvs(torch, rid):
     h1 = out["hist1"].cpu().numpy().astype(np.int64)
     assert h1.sum() == W * T * n
     assert np.abs(h1 - ref["hist1"]).sum() <= 4   # bin-boundary rounding only
+
+
+def test_mixed_table_box_walk_step_by_step(torch, rid):
+    """38 torsions and 6 distance CVs: the raw CVs walk in their box [0.2,
+    1.2] (proposals that leave it are rejected), the angles on the circle.
+    Step by step against the oracle: a walker may only leave the oracle's
+    chain where the acceptance margin or a raw CV's distance to its box wall
+    is at rounding level."""
+    base = ridgen.with_distances(ridgen.system_peptide20(), 6)
+    n, widths, K, W, T = base.n_cv, [64, 64], 4, 256, 20
+    mask = base.mask
+    raw = mask == 0
+    lo = np.where(raw, 0.2, -math.pi).astype(np.float32)
+    hi = np.where(raw, 1.2, math.pi).astype(np.float32)
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 1000, 0.1)
+    models = ridgen.unpack_params(params, 2 * n, widths, K)
+    E = rid.Ensemble(n, widths, K, params)
+    E.set_angular_mask(mask)
+    s_chk = torch.zeros((4, n), dtype=torch.float32, device="cuda")
+    with pytest.raises(rid.RidError):       # no box yet
+        rid.mcmc_run(E, s_chk, 1, 0.05, 0.3, 1)
+    E.set_cv_bounds(lo, hi)
+    rng = np.random.default_rng(8)
+    s0 = ridgen.f32(np.where(raw, rng.uniform(0.2, 1.2, (W, n)), ridgen.torus_samples(W, n, 8)))
+    kT, step, seed = 0.05, 0.5, 123
+    ref = O.mcmc_run(models, s0.astype(np.float64), T, kT, step, seed, nbins=21, proj=(0, 4),
+                     keep_path=True, mask=mask, lower=lo.astype(np.float64),
+                     upper=hi.astype(np.float64))
+    s = torch.from_numpy(s0.copy()).cuda()
+    h1 = torch.zeros((n, 21), dtype=torch.int32, device="cuda")
+    h2 = torch.zeros((21, 21), dtype=torch.int32, device="cuda")
+    acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    alive = np.ones(W, bool)
+    prev = s0.astype(np.float64)
+    lost = 0
+    span = (hi - lo).astype(np.float64)
+
+    def dist(a, b):
+        d = np.abs(a - b)
+        return np.where(raw, d, np.abs(np.mod(a - b + math.pi, 2 * math.pi) - math.pi))
+
+    for t in range(T):
+        rid.mcmc_run(E, s, 1, kT, step, seed, step0=t, nbins=21, proj=(0, 4), hist1=h1,
+                     hist2=h2, accepted=acc)
+        torch.cuda.synchronize()
+        cur = s.cpu().numpy().astype(np.float64)
+        assert np.all((cur[:, raw] >= 0.2 - 1e-6) & (cur[:, raw] <= 1.2 + 1e-6))
+        off = alive & (np.max(dist(cur, ref["path"][t]), axis=1) > 1e-4)
+        for w in np.nonzero(off)[0]:
+            u = O.mcmc_uniforms([w], t, n + 1, seed)[0]
+            prop = prev[w] + step * span / (2 * math.pi) * (2 * u[:n] - 1)
+            sp = np.where(raw, prop, O.wrap_torus(prop))
+            wall = np.min(np.minimum(np.abs(sp[raw] - 0.2), np.abs(sp[raw] - 1.2)))
+            dA = (O.ensemble_energy(models, sp[None], mask)[0]
+                  - O.ensemble_energy(models, prev[w][None], mask)[0])
+            margin = abs(math.log(u[n]) + dA / kT)
+            assert margin < 1e-3 or wall < 1e-5, \
+                f"walker {w} step {t}: differs with margin {margin:.2e}, wall {wall:.2e}"
+        lost += int(np.sum(~alive)) + int(np.sum(off))
+        alive &= ~off
+        prev = ref["path"][t]
+    print(f"walkers on the oracle's chain after {T} steps: {alive.sum()} of {W}; "
+          f"accepted {int(acc.item()) / (W * T):.3f}", flush=True)
+    assert alive.mean() >= 0.97
+    a = int(acc.item())
+    assert abs(a - ref["accepted"]) <= lost + 2
+    assert 0.05 * W * T < a < 0.95 * W * T
+    h1 = h1.cpu().numpy().astype(np.int64)
+    assert h1.sum() == W * T * n and int(h2.sum().item()) == W * T
+    assert np.abs(h1 - ref["hist1"]).sum() <= 2 * n * lost + 8

@@ -6,6 +6,7 @@ import math
 import numpy as np
 import pytest
 
+import ridgen
 from oracle import rid_oracle as O
 
 # Philox4x32-10 known-answer vectors (counter, key) -> output, as published
@@ -94,3 +95,54 @@ def test_acceptance_follows_the_metropolis_rule():
     assert 0.2 < acc.mean() < 0.95
     assert np.allclose(out["s"], np.where(acc[:, None], sp, s0), atol=1e-12)
     assert out["accepted"] == int(acc.sum())
+
+
+def _lin_raw_model(w):
+    # no hidden layer: A = w . x with x = (s, 0) for the raw CV
+    return ([], [], np.array([w, 0.0]), 0.0)
+
+
+def test_all_angular_mask_is_the_torus_chain():
+    models = [tuple(m) for m in ridgen.unpack_params(
+        ridgen.xavier_ensemble(6, [8], 2, 5, 0.1), 6, [8], 2)]
+    s0 = ridgen.torus_samples(16, 3, 3)
+    a = O.mcmc_run(models, s0, 12, 0.05, 0.4, 11, proj=(0, 2), nbins=9)
+    b = O.mcmc_run(models, s0, 12, 0.05, 0.4, 11, proj=(0, 2), nbins=9,
+                   mask=np.ones(3, np.uint8), lower=np.zeros(3), upper=np.ones(3))
+    assert np.array_equal(a["s"], b["s"]) and a["accepted"] == b["accepted"]
+    assert np.array_equal(a["hist1"], b["hist1"]) and np.array_equal(a["hist2"], b["hist2"])
+
+
+def test_raw_cv_infinite_temperature_is_uniform_on_its_box():
+    # a symmetric proposal with rejection outside the box has the uniform
+    # density on the box as its stationary distribution; walkers start inside
+    lo, hi, nb = 0.4, 1.6, 6
+    W, T = 400, 400
+    s0 = np.random.default_rng(1).uniform(lo, hi, (W, 1))
+    out = O.mcmc_run([_lin_raw_model(0.0)], s0, T, 1e30, 1.0, 3, proj=(0, 0), nbins=nb,
+                     mask=np.array([0], np.uint8), lower=[lo], upper=[hi])
+    assert np.all((out["s"] >= lo) & (out["s"] <= hi))
+    h = out["hist1"][0]
+    assert h.sum() == W * T
+    # every state stays in the box; counts per bin within 5 % of flat
+    # (W T / nb = 26 667 per bin; the chains are correlated over ~10 steps)
+    assert np.max(np.abs(h / (W * T / nb) - 1.0)) < 0.05
+    assert out["accepted"] < W * T                    # the walls reject
+
+
+def test_raw_cv_samples_the_boltzmann_density_of_a_linear_free_energy():
+    # A(s) = a s on [lo, hi]: density proportional to exp(-a s / kT)
+    lo, hi, a, kT, nb = 0.5, 2.5, 3.0, 1.0, 8
+    W, T = 500, 500
+    s0 = np.random.default_rng(2).uniform(lo, hi, (W, 1))
+    out = O.mcmc_run([_lin_raw_model(a)], s0, T, kT, 1.5, 5, t0=0, proj=(0, 0), nbins=nb,
+                     mask=np.array([0], np.uint8), lower=[lo], upper=[hi])
+    edges = np.linspace(lo, hi, nb + 1)
+    mass = np.exp(-a * edges[:-1] / kT) - np.exp(-a * edges[1:] / kT)
+    mass /= mass.sum()
+    h = out["hist1"][0] / (W * T)
+    # the first half of the bins (95 % of the mass) within 10 %
+    assert np.max(np.abs(h[:4] / mass[:4] - 1.0)) < 0.1
+    pmf = O.pmf_from_histogram(out["hist1"][0], kT)
+    centres = 0.5 * (edges[:-1] + edges[1:])
+    assert np.max(np.abs(pmf[:4] - a * (centres[:4] - centres[0]))) < 0.25
