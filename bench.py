@@ -149,30 +149,46 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel_key):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
-    was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def pmc_for(kernel_key):
+    """Counter figures of one kernel family from the committed rocprofv3
+    summary (profiles/pmc.json), if they were taken on the current kernel
+    source (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc.json")
     if not os.path.exists(path):
         return None
     try:
-        t = json.load(open(path))
-        rec = t.get(kernel_key)
+        rec = json.load(open(path)).get(kernel_key)
         if rec and rec.get("source_hash") == kernel_source_hash():
-            return rec.get("bytes_per_launch")
+            return rec
     except Exception:
         return None
     return None
 
 
+def traffic_for(kernel_key):
+    rec = pmc_for(kernel_key)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def mfma_busy_for(kernel_key):
+    rec = pmc_for(kernel_key)
+    return rec.get("mfma_busy") if rec else None
+
+
 PMC_COPY_BYTES = 256 << 20      # bytes read (and written) by the calibration copy
+PMC_CASES = (("mlp_fp32_4x256_b1024", "FP32", 1024, 4, [256] * 4),
+             ("mlp_bf16_8x512_b16384", "BF16", 16384, 8, [512] * 4),
+             ("mlp_fp16_8x512_b16384", "FP16", 16384, 8, [512] * 4),
+             ("mlp_bf16_all_8x512_b16384", "BF16_ALL", 16384, 8, [512] * 4),
+             ("mlp_fp32_8x512_b16384", "FP32", 16384, 8, [512] * 4))
 
 
 def pmc_workload(rid, torch, reps=3):
     """A short program for the rocprofv3 counter passes: a plain elementwise
     copy of known size (y = x * 1, reads and writes PMC_COPY_BYTES), then the
-    bias path on the 200-atom chain: 4 x [256 x 4] FP32 with 1024 walkers and
-    8 x [512 x 4] BF16 and FP16 with 16384 walkers, `reps` launches each."""
+    bias path on the 200-atom chain for each PMC_CASES entry (the headline
+    FP32 ensemble at 1024 walkers; the precision form's shape at 16384
+    walkers in each arithmetic), `reps` launches each."""
     x = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     for _ in range(reps):
@@ -180,10 +196,8 @@ def pmc_workload(rid, torch, reps=3):
     torch.cuda.synchronize()
     del x, y
     sys20 = ridgen.system_peptide20()
-    for prec, B, K, widths in ((rid.RID_FP32, 1024, 4, [256] * 4),
-                               (rid.RID_BF16, 16384, 8, [512] * 4),
-                               (rid.RID_FP16, 16384, 8, [512] * 4)):
-        c = build_case(rid, torch, sys20, B, K, widths, prec)
+    for _, prec, B, K, widths in PMC_CASES:
+        c = build_case(rid, torch, sys20, B, K, widths, getattr(rid, "RID_" + prec))
         for _ in range(reps):
             rid.bias_force(c["S"], c["E"], c["P"], 2.0, 3.0, out=c["out"])
         torch.cuda.synchronize()
@@ -191,62 +205,189 @@ def pmc_workload(rid, torch, reps=3):
     print("pmc workload done", flush=True)
 
 
-def _read_counters(d, counter):
-    """{kernel name: [value per dispatch]} from a rocprofv3 --pmc CSV."""
+def _demangle(names):
+    """Demangled kernel names (c++filt), the others unchanged."""
+    import subprocess
+    mangled = sorted({n for n in names if n.startswith("_Z")})
+    if not mangled:
+        return {}
+    try:
+        r = subprocess.run(["c++filt"], input="\n".join(mangled), capture_output=True, text=True,
+                           check=True)
+        return dict(zip(mangled, r.stdout.splitlines()))
+    except (OSError, subprocess.CalledProcessError):
+        return {}
+
+
+def _read_counters(d):
+    """{(kernel name, counter): [value per dispatch]} from one rocprofv3
+    --pmc pass: the CSV output, or the counters_collection view of its
+    rocpd database."""
     import csv
     import glob
-    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-    if not files:
-        raise SystemExit(f"no counter_collection.csv under {d}")
+    import sqlite3
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        rows += [(r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"]))
+                 for r in csv.DictReader(open(f))]
+    for f in glob.glob(os.path.join(d, "**", "*.db"), recursive=True):
+        con = sqlite3.connect(f)
+        rows += [(k, c, float(v)) for k, c, v in
+                 con.execute("select kernel_name, counter_name, value from counters_collection")]
+        con.close()
+    if not rows:
+        raise SystemExit(f"no counter output under {d}")
+    dm = _demangle([k for k, _, _ in rows])
     out = {}
-    for f in files:
-        for row in csv.DictReader(open(f)):
-            if row.get("Counter_Name") != counter:
-                continue
-            out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    for k, c, v in rows:
+        out.setdefault((dm.get(k, k), c), []).append(v)
     return out
 
 
-def pmc_summary(fetch_dir, write_dir, out_path):
-    """Turn the two counter passes over --pmc-workload into HBM bytes per
-    launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of each kernel,
-    scaled by what the same counter reads for the calibration copy."""
+def _mlp_signature(name):
+    """(formats, (NP, RT, NW, LM), (FROM_POS, GRAD, RES)) of an mlp_kernel
+    instance from its demangled or mangled name, or None.  Mangled names
+    (the host demangler may not know _Float16): the Plan's first three
+    template arguments are rid::(anonymous)::<format> names, written out
+    (NS0_<n><name>E) or as substitutions S<k>_; the names met in the argument
+    list enter the substitution table after rid, the anonymous namespace,
+    mlp_kernel and Plan (indices 0-3), so S<k>_ is the (k - 3)-th of them."""
     import re
-    fetch = _read_counters(fetch_dir, "FETCH_SIZE")
-    write = _read_counters(write_dir, "WRITE_SIZE")
+    m = re.search(r"mlp_kernel<[^<>]*Plan<([^<>]*)>\s*,\s*(\d+)\s*,\s*(\d+)\s*,\s*(\d+)\s*,"
+                  r"\s*(\d+)\s*,\s*(true|false)\s*,\s*(true|false)\s*,\s*(true|false)", name)
+    if m:
+        fmts = [re.sub(r".*::", "", f.strip()) for f in m.group(1).split(",")][:3]
+        ints = tuple(int(m.group(k)) for k in range(2, 6))
+        flags = tuple(m.group(k) == "true" for k in range(6, 9))
+        return fmts, ints, flags
+    tag = "mlp_kernelINS0_4PlanI"
+    i = name.find(tag)
+    if i < 0:
+        return None
+    pos, seen, fmts = i + len(tag), [], []
+    while len(fmts) < 3:
+        m = re.match(r"NS0_(\d+)", name[pos:])
+        if m:
+            n = int(m.group(1))
+            start = pos + m.end()
+            fmt = name[start:start + n]
+            pos = start + n + 1                  # past the closing E
+            seen.append(fmt)
+            fmts.append(fmt)
+            continue
+        m = re.match(r"S(\d*)_", name[pos:])
+        if not m:
+            return None
+        k = int(m.group(1)) + 1 if m.group(1) else 0
+        if not 4 <= k < 4 + len(seen):
+            return None
+        fmts.append(seen[k - 4])
+        pos += m.end()
+    m = re.search(r"ELi(\d+)ELi(\d+)ELi(\d+)ELi(\d+)ELb([01])ELb([01])ELb([01])E", name[pos:])
+    if not m:
+        return None
+    return (fmts, tuple(int(m.group(k)) for k in range(1, 5)),
+            tuple(m.group(k) == "1" for k in range(5, 8)))
+
+
+def mlp_display(name):
+    """A short readable name of an mlp_kernel instance (else None)."""
+    sig = _mlp_signature(name)
+    if sig is None:
+        return None
+    fmts, ints, flags = sig
+    return ("mlp_kernel<Plan<" + ", ".join(fmts) + ">, " + ", ".join(map(str, ints)) + ", "
+            + ", ".join("true" if f else "false" for f in flags) + ">")
+
+
+def pmc_kernel_key(name):
+    """The PMC_CASES key of an mlp_kernel launch from its name: the
+    arithmetic plan's three MFMA formats, the padded width and the instance
+    the benchmark's bias calls use (1024 walkers: torsions gathered in-kernel;
+    16384 walkers: the encoding from memory), with the input gradient and no
+    residual connections."""
+    sig = _mlp_signature(name)
+    if sig is None:
+        return None
+    fmts, (width, _, _, _), (from_pos, grad, res) = sig
+    if not grad or res:
+        return None
+    plan = {("F32", "F32", "F32"): "fp32", ("F16", "BF16", "F16"): "bf16",
+            ("F16", "F16", "F16"): "fp16", ("BF16", "BF16", "BF16"): "bf16_all"}.get(tuple(fmts))
+    key = {("fp32", 256, True): "mlp_fp32_4x256_b1024",
+           ("bf16", 512, False): "mlp_bf16_8x512_b16384",
+           ("fp16", 512, False): "mlp_fp16_8x512_b16384",
+           ("bf16_all", 512, False): "mlp_bf16_all_8x512_b16384",
+           ("fp32", 512, False): "mlp_fp32_8x512_b16384"}
+    return key.get((plan, width, from_pos))
+
+
+N_CU, N_SIMD, N_XCD = 256, 4, 8
+
+
+def pmc_summary(out_path, *dirs):
+    """Summarize rocprofv3 --pmc passes over --pmc-workload (each pass in
+    its own directory) into per-kernel figures:
+      bytes_per_launch  FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each
+                        scaled by what the counter reads for the calibration
+                        copy of known size;
+      mfma_busy         SQ_VALU_MFMA_BUSY_CYCLES / (4 SQ_BUSY_CU_CYCLES): the
+                        fraction of SIMD cycles, on CUs busy with the kernel,
+                        in which the matrix unit worked (the busy-cycle counter
+                        sums over all SIMDs: an FP32 16x16x4 MFMA of 2048 FLOP
+                        counts 32 cycles; SQ_BUSY_CU_CYCLES sums busy cycles
+                        over the 256 CUs);
+      mfma_busy_gpu     the same over every SIMD of the chip for the kernel's
+                        whole GPU-active time: SQ_VALU_MFMA_BUSY_CYCLES /
+                        (GRBM_GUI_ACTIVE / 8 XCDs x 1024 SIMDs) (the GRBM
+                        counter sums the 8 XCDs' active cycles);
+      mfma_flop         SQ_INSTS_VALU_MFMA_MOPS_* x 512 (the MOPS counters
+                        count math operations in units of 512);
+      l2_hit            TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)."""
+    table = {}
+    for d in dirs:
+        table.update(_read_counters(d))
+
+    def mean(name_pred, counter):
+        vals = [v for (k, c), vs in table.items() if c == counter and name_pred(k) for v in vs]
+        return sum(vals) / len(vals) if vals else None
 
     def is_copy(name):
         return "MulFunctor" in name or "mul_kernel" in name
 
-    def classify(name):
-        m = re.search(r"mlp_kernel<[^<>]*?\b(BF16|F16|F32)\b\s*,\s*(\d+)", name)
-        if not m:
-            return None
-        return {"F32": "mlp_fp32_4x256_b1024", "BF16": "mlp_bf16_8x512_b16384", "F16": "mlp_fp16_8x512_b16384"}[m.group(1)]
-
-    def mean_of(table, pick):
-        vals = [v for k, vs in table.items() if pick(k) for v in vs]
-        return sum(vals) / len(vals) if vals else None
-
-    cf, cw = mean_of(fetch, is_copy), mean_of(write, is_copy)
-    if not cf or not cw:
-        raise SystemExit("calibration copy not found in the counter output")
-    f_scale = PMC_COPY_BYTES / (cf * 1024.0)
-    w_scale = PMC_COPY_BYTES / (cw * 1024.0)
-    res = {"_calibration": {"copy_bytes": PMC_COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
-                            "fetch_scale": f_scale, "write_scale": w_scale},
-           "_source": "rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE over "
-                      "bench.py --pmc-workload"}
-    for key in ("mlp_fp32_4x256_b1024", "mlp_bf16_8x512_b16384", "mlp_fp16_8x512_b16384"):
-        fk = mean_of(fetch, lambda n, key=key: classify(n) == key)
-        wk = mean_of(write, lambda n, key=key: classify(n) == key)
-        if fk is None or wk is None:
+    res = {"_source": "rocprofv3 --pmc passes over bench.py --pmc-workload: " + ", ".join(dirs),
+           "_formulas": pmc_summary.__doc__}
+    cf, cw = mean(is_copy, "FETCH_SIZE"), mean(is_copy, "WRITE_SIZE")
+    if cf and cw:
+        res["_calibration"] = {"copy_bytes": PMC_COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
+                               "fetch_scale": PMC_COPY_BYTES / (cf * 1024.0),
+                               "write_scale": PMC_COPY_BYTES / (cw * 1024.0)}
+    for key, *_ in PMC_CASES:
+        pick = (lambda n, key=key: pmc_kernel_key(n) == key)
+        rec = {"source_hash": kernel_source_hash()}
+        counters = sorted({c for (k, c) in table if pmc_kernel_key(k) == key})
+        if not counters:
             continue
-        res[key] = {"fetch_kib": fk, "write_kib": wk,
-                    "fetch_bytes": fk * 1024.0 * f_scale,
-                    "write_bytes": wk * 1024.0 * w_scale,
-                    "bytes_per_launch": fk * 1024.0 * f_scale + wk * 1024.0 * w_scale,
-                    "source_hash": kernel_source_hash()}
+        for c in counters:
+            rec[c] = mean(pick, c)
+        if "_calibration" in res and "FETCH_SIZE" in rec and "WRITE_SIZE" in rec:
+            cal = res["_calibration"]
+            rec["fetch_bytes"] = rec["FETCH_SIZE"] * 1024.0 * cal["fetch_scale"]
+            rec["write_bytes"] = rec["WRITE_SIZE"] * 1024.0 * cal["write_scale"]
+            rec["bytes_per_launch"] = rec["fetch_bytes"] + rec["write_bytes"]
+        busy = rec.get("SQ_VALU_MFMA_BUSY_CYCLES")
+        if busy is not None and rec.get("SQ_BUSY_CU_CYCLES"):
+            rec["mfma_busy"] = busy / (N_SIMD * rec["SQ_BUSY_CU_CYCLES"])
+        if busy is not None and rec.get("GRBM_GUI_ACTIVE"):
+            rec["mfma_busy_gpu"] = busy / (rec["GRBM_GUI_ACTIVE"] / N_XCD * N_CU * N_SIMD)
+        mops = [rec.get(c) for c in ("SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F16",
+                                     "SQ_INSTS_VALU_MFMA_MOPS_F32")]
+        if any(v is not None for v in mops):
+            rec["mfma_flop"] = 512.0 * sum(v or 0.0 for v in mops)
+        if rec.get("TCC_HIT_sum") is not None and rec.get("TCC_MISS_sum") is not None:
+            tot = rec["TCC_HIT_sum"] + rec["TCC_MISS_sum"]
+            rec["l2_hit"] = rec["TCC_HIT_sum"] / tot if tot else None
+        res[key] = rec
     with open(out_path, "w") as fh:
         json.dump(res, fh, indent=1)
     print(json.dumps(res, indent=1))
@@ -359,6 +500,7 @@ def bench_precision(rid, torch, sys20, prec, name, steps, warmup, samples):
         "roofline": {"bound": "mfma", "achieved": ach, "peak": peak,
                      "unit": "TFLOP/s", "frac": ach / peak,
                      "traffic": traffic_for(f"mlp_{name.lower()}_8x512_b16384"),
+                     "mfma_busy": mfma_busy_for(f"mlp_{name.lower()}_8x512_b16384"),
                      "avg_launch_us": kern["mlp"] * 1e3, "flop_per_launch": fl},
         "kernels_us": {k: v * 1e3 for k, v in kern.items()},
     }
@@ -651,6 +793,32 @@ def bench_serving(rid, n_req=1500):
     }
 
 
+def trace_summary(db, out_path, command):
+    """Kernel statistics (calls, total, average, share of GPU time) of a
+    rocprofv3 --kernel-trace --stats run, from its rocpd database, as text;
+    the mlp_kernel families are named by their PMC_CASES key."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = list(con.execute("select name, total_calls, total_duration, average, percentage "
+                            "from top_kernels order by total_duration desc"))
+    con.close()
+    dm = _demangle([r[0] for r in rows])
+    lines = [f"rocprofv3 kernel statistics (durations in microseconds)", f"command: {command}", "",
+             f"{'calls':>7} {'total_us':>12} {'avg_us':>10} {'pct':>6}  kernel"]
+    for name, calls, tot, avg, pct in rows:
+        nm = mlp_display(name) or dm.get(name, name)
+        key = pmc_kernel_key(name)
+        short = nm.replace("rid::(anonymous namespace)::", "")
+        if len(short) > 150:
+            short = short[:150] + "..."
+        lines.append(f"{calls:>7} {tot:>12.1f} {avg:>10.3f} {pct:>6.2f}  {short}"
+                     + (f"   [{key}]" if key else ""))
+    txt = "\n".join(lines) + "\n"
+    with open(out_path, "w") as fh:
+        fh.write(txt)
+    print(txt)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -662,12 +830,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--trace-summary", nargs=3, metavar=("DB", "OUT", "COMMAND"),
+                    help="render a rocprofv3 --kernel-trace --stats database as text")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run the short program the counter passes profile")
-    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
-                    help="summarize two rocprofv3 --pmc passes into HBM bytes per launch")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="OUT DIR",
+                    help="summarize rocprofv3 --pmc passes (one directory each) into "
+                         "per-kernel counter figures, written to OUT")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(*args.trace_summary)
+        return
     if args.pmc_summary:
+        if len(args.pmc_summary) < 2:
+            ap.error("--pmc-summary OUT DIR [DIR ...]")
         pmc_summary(*args.pmc_summary)
         return
     if args.gpus != 1:
@@ -697,6 +873,7 @@ def main():
     roof = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
             "traffic": traffic_for("mlp_fp32_4x256_b1024"),
+            "mfma_busy": mfma_busy_for("mlp_fp32_4x256_b1024"),
             "kernel": "mlp_kernel<F32,256> (torsions gathered in-kernel + ensemble "
                       "forward + input-gradient sweep)",
             "avg_launch_us": kern["mlp"] * 1e3, "flop_per_launch": flop_launch}

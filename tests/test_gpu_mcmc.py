@@ -126,13 +126,57 @@ def test_chain_continues_across_calls(torch, rid):
     assert torch.equal(ra["hist1"], hb1)
 
 
-def test_bf16_ensemble_and_argument_errors(torch, rid):
-    E, _ = _ensemble(rid, widths=(512, 512), K=4, prec=rid.RID_BF16)
-    s = torch.from_numpy(ridgen.f32(ridgen.torus_samples(200, 38, 7))).cuda()
-    out = rid.mcmc_run(E, s, 10, KT_300K, 0.3, 3)
+def test_bf16_metropolis_decisions_step_by_step(torch, rid):
+    """The BF16 precision form's free energies (the forward sweep: FP16 first
+    layer, BF16 hidden layers) on the precision form's ensemble shape.  The
+    margin rule of the FP32 test, with the tolerance set by the measured
+    error of Abar: a walker may only leave the oracle's chain at a step whose
+    acceptance margin |ln u + dAbar/kT| is below 3 max|dAbar_err| / kT."""
+    n, widths, K, W, T = 38, (512, 512, 512, 512), 8, 256, 10
+    E, models = _ensemble(rid, n=n, widths=widths, K=K, prec=rid.RID_BF16, bias_std=0.1)
+    kT, step, seed = 0.05, 0.35, 91
+    # measured error of Abar on torus samples
+    probe = ridgen.f32(ridgen.torus_samples(1024, n, 17))
+    A = rid.model_dev(E, torch.from_numpy(probe).cuda())[2]
     torch.cuda.synchronize()
-    assert torch.isfinite(s).all() and (s.abs() <= math.pi).all()
-    assert 0 < int(out["accepted"].item()) < 2000
+    abar = A.cpu().numpy().astype(np.float64).mean(axis=1)
+    e_A = float(np.max(np.abs(abar - O.ensemble_energy(models, probe.astype(np.float64)))))
+    tol = 3.0 * e_A / kT
+    print(f"bf16 Abar error {e_A:.2e} kJ/mol -> margin tolerance {tol:.3f}", flush=True)
+    assert e_A < 1e-2
+    s0 = ridgen.f32(ridgen.torus_samples(W, n, 19))
+    ref = O.mcmc_run(models, s0.astype(np.float64), T, kT, step, seed, nbins=31, keep_path=True)
+    s = torch.from_numpy(s0.copy()).cuda()
+    h1 = torch.zeros((n, 31), dtype=torch.int32, device="cuda")
+    acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    alive = np.ones(W, bool)
+    prev = s0.astype(np.float64)
+    lost = 0
+    for t in range(T):
+        rid.mcmc_run(E, s, 1, kT, step, seed, step0=t, nbins=31, hist1=h1, accepted=acc)
+        torch.cuda.synchronize()
+        cur = s.cpu().numpy().astype(np.float64)
+        off = alive & (np.max(_wrapped(cur, ref["path"][t]), axis=1) > 1e-4)
+        for w in np.nonzero(off)[0]:
+            u = O.mcmc_uniforms([w], t, n + 1, seed)[0]
+            sp = O.wrap_torus(prev[w] + step * (2 * u[:n] - 1))
+            dA = O.ensemble_energy(models, sp[None])[0] - O.ensemble_energy(models, prev[w][None])[0]
+            margin = abs(math.log(u[n]) + dA / kT)
+            assert margin < tol, f"walker {w} step {t}: decision differs with margin {margin:.2e}"
+        lost += int(np.sum(~alive)) + int(np.sum(off))
+        alive &= ~off
+        prev = ref["path"][t]
+    a = int(acc.item())
+    print(f"bf16: walkers on the oracle's chain after {T} steps: {alive.sum()} of {W}; "
+          f"accepted {a / (W * T):.3f} (oracle {ref['accepted'] / (W * T):.3f})", flush=True)
+    assert alive.mean() >= 0.9
+    assert abs(a - ref["accepted"]) <= lost + 2
+    assert 0.2 * W * T < a < 0.98 * W * T
+
+
+def test_mcmc_argument_errors(torch, rid):
+    E, _ = _ensemble(rid, widths=(64, 64), K=2)
+    s = torch.from_numpy(ridgen.f32(ridgen.torus_samples(20, 38, 7))).cuda()
     with pytest.raises(rid.RidError):
         rid.mcmc_run(E, s, 1, -1.0, 0.3, 3)
     with pytest.raises(rid.RidError):
