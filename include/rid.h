@@ -444,8 +444,9 @@ rid_status rid_mf_label(const float* d_traj, const float* d_s0,
  * walkers of different systems, ensembles and precisions on one GPU (the
  * exploration phase runs many walkers at once, "Overall workflow setting":
  * numb_walkers).  Ensemble weights and system tables stay resident on the
- * device.  A scheduler thread takes the oldest waiting request plus every
- * later waiting request of the same model (up to max_batch_walkers), admits
+ * device, and so may the walkers' positions and forces (device requests).
+ * A scheduler thread takes the oldest waiting request plus every later
+ * waiting request of the same model (up to max_batch_walkers), admits
  * the batch only when its device memory fits the HBM budget, and runs it on
  * one of n_streams streams (copies in, bias kernels, copies out).  Requests
  * that arrive while others run are admitted as slots and memory free up.
@@ -466,8 +467,18 @@ rid_status rid_mf_label(const float* d_traj, const float* d_s0,
  *                      never fit the HBM budget; RID_EDEVICE once a device
  *                      error has stopped the server; RID_EINVAL while it is
  *                      being destroyed.  Thread-safe.
+ * rid_server_submit_device  the same with the walker state resident in
+ *                      device memory: d_pos [n_walkers][n_atoms][3] is read
+ *                      and d_force [n_walkers][n_atoms][3], d_energy /
+ *                      d_eps / d_sigma [n_walkers] (any may be NULL) are
+ *                      written by the request's batch on the device (no host
+ *                      staging, no PCIe copies).  The buffers are the
+ *                      caller's and must stay valid, and d_pos unchanged,
+ *                      until the request has been waited.  Same errors.
  * rid_server_wait      blocks until the request is done and copies its
- *                      results to the host arrays (any may be NULL):
+ *                      results to the host arrays (any may be NULL; ignored
+ *                      for a device request, whose results are then in its
+ *                      device buffers):
  *                      force [n_walkers][n_atoms][3], energy/eps/sigma
  *                      [n_walkers]; latency_us = arrival (submit) to results
  *                      visible in host memory.  Each ticket is waited once.
@@ -500,9 +511,39 @@ rid_status rid_server_register(rid_server srv, rid_system sys, rid_ensemble ens,
                                float eps0, float eps1, int* model_id);
 rid_status rid_server_submit(rid_server srv, int model_id, const float* host_pos,
                              int n_walkers, int64_t* ticket);
+rid_status rid_server_submit_device(rid_server srv, int model_id, const float* d_pos,
+                                    int n_walkers, float* d_force, float* d_energy,
+                                    float* d_eps, float* d_sigma, int64_t* ticket);
 rid_status rid_server_wait(rid_server srv, int64_t ticket, float* host_force,
                            float* host_energy, float* host_eps, float* host_sigma,
                            double* latency_us);
+
+/* rid_server_replay - an open-loop request trace driven from native threads,
+ * for measuring the server (capacity, latency under an offered load)
+ * without a client in the way.  One thread submits request i at
+ * arrival_s[i] seconds after the call starts (sleeping, then spinning to
+ * the instant; arrival times must not decrease), the calling thread waits
+ * on every ticket in order.  Per request: latency_us[i] (arrival at the
+ * server to results visible, as rid_server_wait; -1 if it failed),
+ * submit_lag_us[i] (how late the submission was against its arrival time);
+ * *wall_s = first arrival to last wait.  Any output may be NULL.  The
+ * requests enter the server's statistics like any others.  Errors:
+ * RID_EINVAL (NULL server or requests, n < 1, a request without positions,
+ * walkers < 1, arrival times out of order); otherwise the first failing
+ * request's status after every request has been waited. */
+typedef struct {
+  int model_id;
+  int n_walkers;
+  double arrival_s;          /* offset from the start of the replay           */
+  const float* pos;          /* [n_walkers][n_atoms][3], host or device memory */
+  int device;                /* 1: pos and the outputs below are device memory */
+  float* force;              /* outputs (any may be NULL): host arrays when    */
+  float* energy;             /* device == 0 (copied at the wait), device       */
+  float* eps;                /* buffers written on the device when device == 1 */
+  float* sigma;
+} rid_replay_request;
+rid_status rid_server_replay(rid_server srv, const rid_replay_request* reqs, int n,
+                             double* latency_us, double* submit_lag_us, double* wall_s);
 rid_status rid_server_stats(rid_server srv, rid_server_stats_t* out);
 void rid_server_reset_stats(rid_server srv);
 void rid_server_destroy(rid_server srv);

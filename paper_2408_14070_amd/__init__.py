@@ -37,7 +37,8 @@ EXPORTS = (
     "rid_cv_apply_force",
     "rid_mf_train_step", "rid_lr_exponential", "rid_mf_label",
     "rid_profile_enable", "rid_profile_read", "rid_mf_loss_grad", "rid_mf_grad",
-    "rid_server_create", "rid_server_register", "rid_server_submit", "rid_server_wait",
+    "rid_server_create", "rid_server_register", "rid_server_submit", "rid_server_submit_device",
+    "rid_server_wait", "rid_server_replay",
     "rid_server_stats", "rid_server_reset_stats", "rid_server_destroy",
 )
 RID_SERVE_FIFO = 1
@@ -50,6 +51,14 @@ class ServerStats(ctypes.Structure):
                 ("mean_batch_walkers", ctypes.c_double), ("p50_us", ctypes.c_double),
                 ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double),
                 ("max_us", ctypes.c_double), ("walker_steps_per_s", ctypes.c_double)]
+class ReplayRequest(ctypes.Structure):
+    _fields_ = [("model_id", ctypes.c_int), ("n_walkers", ctypes.c_int),
+                ("arrival_s", ctypes.c_double), ("pos", ctypes.c_void_p),
+                ("device", ctypes.c_int), ("force", ctypes.c_void_p),
+                ("energy", ctypes.c_void_p), ("eps", ctypes.c_void_p),
+                ("sigma", ctypes.c_void_p)]
+
+
 PROF_CV, PROF_MLP, PROF_SCATTER, PROF_REDUCE, PROF_EMBED, PROF_TRAIN, PROF_LABEL, PROF_HVP = range(8)
 
 
@@ -111,6 +120,8 @@ def lib():
         "rid_server_create": (i, [sz, i, i, i, P(vp)]),
         "rid_server_register": (i, [vp, vp, vp, f, f, P(i)]),
         "rid_server_submit": (i, [vp, i, vp, i, P(i64)]),
+        "rid_server_submit_device": (i, [vp, i, vp, i, vp, vp, vp, vp, P(i64)]),
+        "rid_server_replay": (i, [vp, P(ReplayRequest), i, vp, vp, P(d)]),
         "rid_server_wait": (i, [vp, i64, vp, vp, vp, vp, P(d)]),
         "rid_server_stats": (i, [vp, P(ServerStats)]),
         "rid_server_reset_stats": (None, [vp]),
@@ -481,9 +492,11 @@ def mean_force(s, params, ens: Ensemble):
 
 
 class Server:
-    """Continuous-batching bias-force server (rid_server_*).  Host arrays in,
-    host arrays out; submit() and wait() may be called from several threads
-    (the C calls release the GIL)."""
+    """Continuous-batching bias-force server (rid_server_*).  submit(): host
+    arrays in, host arrays out; submit_device(): device tensors in and out
+    (walker state resident); submit() and wait() may be called from several
+    threads (the C calls release the GIL); replay() drives a whole trace from
+    native threads."""
 
     def __init__(self, hbm_budget_bytes: int, n_streams: int = 4,
                  max_batch_walkers: int = 4096, fifo: bool = False):
@@ -514,17 +527,67 @@ class Server:
         self._tickets[t.value] = (p.shape[0], system.n_atoms)
         return t.value
 
+    def submit_device(self, model_id: int, pos, out: dict) -> int:
+        """rid_server_submit_device: pos [w][N][3] float32 on the device;
+        out: dict of device tensors F [w][N][3] and (optional) E, eps, sigma
+        [w], written by the request's batch.  Keep them alive and pos
+        unchanged until wait()."""
+        system = self._models[model_id][0]
+        w = pos.shape[0]
+        _f32(pos, (w, system.n_atoms, 3), "pos")
+        _f32(out["F"], (w, system.n_atoms, 3), "F")
+        t = ctypes.c_int64()
+        _check(lib().rid_server_submit_device(
+            self.handle, int(model_id), _ptr(pos), int(w), _ptr(out["F"]), _ptr(out.get("E")),
+            _ptr(out.get("eps")), _ptr(out.get("sigma")), ctypes.byref(t)))
+        self._tickets[t.value] = None
+        return t.value
+
     def wait(self, ticket: int):
-        w, N = self._tickets.pop(ticket)
+        dims = self._tickets.pop(ticket)
+        lat = ctypes.c_double()
+        if dims is None:            # device request: results are in its tensors
+            _check(lib().rid_server_wait(self.handle, ctypes.c_int64(ticket), None, None, None,
+                                         None, ctypes.byref(lat)))
+            return dict(latency_us=lat.value)
+        w, N = dims
         F = np.empty((w, N, 3), np.float32)
         E = np.empty(w, np.float32)
         eps = np.empty(w, np.float32)
         sig = np.empty(w, np.float32)
-        lat = ctypes.c_double()
         vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
         _check(lib().rid_server_wait(self.handle, ctypes.c_int64(ticket), vp(F), vp(E),
                                      vp(eps), vp(sig), ctypes.byref(lat)))
         return dict(F=F, E=E, eps=eps, sigma=sig, latency_us=lat.value)
+
+    def replay(self, reqs):
+        """rid_server_replay over a list of dicts (model, arrival_s, pos and,
+        for device requests, F / E / eps / sigma device tensors; host
+        requests give host numpy positions and get no host results).
+        Returns (latency_us, submit_lag_us, wall_s)."""
+        n = len(reqs)
+        arr = (ReplayRequest * n)()
+        keep = []
+        for i, q in enumerate(reqs):
+            pos = q["pos"]
+            dev = not isinstance(pos, np.ndarray)
+            if dev:
+                p = _ptr(pos)
+                out = q.get("out", {})
+                arr[i] = ReplayRequest(int(q["model"]), int(pos.shape[0]), float(q["arrival_s"]),
+                                       p, 1, _ptr(out.get("F")), _ptr(out.get("E")),
+                                       _ptr(out.get("eps")), _ptr(out.get("sigma")))
+            else:
+                a = np.ascontiguousarray(pos, dtype=np.float32)
+                keep.append(a)
+                arr[i] = ReplayRequest(int(q["model"]), int(a.shape[0]), float(q["arrival_s"]),
+                                       a.ctypes.data_as(ctypes.c_void_p), 0, None, None, None, None)
+        lat = np.zeros(n, np.float64)
+        lag = np.zeros(n, np.float64)
+        wall = ctypes.c_double()
+        _check(lib().rid_server_replay(self.handle, arr, n, lat.ctypes.data_as(ctypes.c_void_p),
+                                       lag.ctypes.data_as(ctypes.c_void_p), ctypes.byref(wall)))
+        return lat, lag, wall.value
 
     def stats(self) -> dict:
         st = ServerStats()

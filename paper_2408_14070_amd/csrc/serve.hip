@@ -3,7 +3,11 @@
 //
 // A request is a block of walkers of one registered model (system +
 // ensemble + trust levels).  Ensemble weights and system tables stay
-// resident; each request's positions are staged in pinned host memory.  A
+// resident.  A host request's positions are staged in pinned host memory
+// and its results copied back; a device request's positions are read from
+// the caller's device buffer and its results written to the caller's device
+// buffers (walker state resident in HBM: no PCIe traffic), by one gather and
+// one scatter launch per batch over the batch's device requests.  A
 // scheduler thread forms batches (serve_core.h policy), admits them against
 // an HBM arena of fixed budget, and runs each batch on one of several
 // streams: one host-to-device copy per member request, the MLP kernel fed
@@ -44,23 +48,85 @@ struct ServeModel {
   serve::ModelShape shape;
 };
 
+// Device buffers of a device request (caller owned).
+struct DevIo {
+  const float* pos = nullptr;    // [w][N][3]
+  float* force = nullptr;        // [w][N][3] or null
+  float* energy = nullptr;       // [w] or null
+  float* eps = nullptr;
+  float* sigma = nullptr;
+};
+
 struct Req {
   int model = 0;
   int walkers = 0;
   size_t pin_off = 0;
   float* pin = nullptr;          // [w][N][3] positions, then [w] output records
   bool own_pin = false;          // pinned block outside the staging arena
+  bool dev = false;              // device request: io instead of pin
+  DevIo io;
   clk::time_point arrival, done_at;
   bool done = false;
   rid_status status = RID_OK;
 };
 
+struct Part {
+  float* pin;                    // host request: its pinned block (else null)
+  DevIo io;                      // device request: its buffers
+  int walkers;
+};
+
 struct Batch {
   std::vector<int64_t> tickets;
-  std::vector<std::pair<float*, int>> parts;   // each request's pinned block, walkers
+  std::vector<Part> parts;       // the requests, in the batch's row order
   int model = 0, walkers = 0, slot = 0;
   size_t dev_off = 0;
 };
+
+// Device requests of one gather / scatter launch (kernel arguments).
+constexpr int kMaxDevParts = 32;
+struct DevParts {
+  int n;                         // parts in this launch
+  int row0[kMaxDevParts];        // first batch row of each part
+  int walkers[kMaxDevParts];
+  DevIo io[kMaxDevParts];
+};
+
+// positions of the device parts into the batch's rows: block row y = part
+__global__ void serve_gather_kernel(DevParts p, float* pos, int n3) {
+  const int q = blockIdx.y;
+  const long long count = (long long)p.walkers[q] * n3;
+  const float* src = p.io[q].pos;
+  float* dst = pos + (long long)p.row0[q] * n3;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// the batch's walker records (3N forces, energy, eps, sigma) into the device
+// parts' output buffers
+__global__ void serve_scatter_kernel(DevParts p, const float* rec, int n3) {
+  const int q = blockIdx.y;
+  const int rf = n3 + 3;
+  const long long count = (long long)p.walkers[q] * rf;
+  const float* src = rec + (long long)p.row0[q] * rf;
+  const DevIo& io = p.io[q];
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long w = i / rf;
+    const int j = (int)(i - w * rf);
+    const float v = src[i];
+    if (j < n3) {
+      if (io.force) io.force[w * n3 + j] = v;
+    } else if (j == n3) {
+      if (io.energy) io.energy[w] = v;
+    } else if (j == n3 + 1) {
+      if (io.eps) io.eps[w] = v;
+    } else if (io.sigma) {
+      io.sigma[w] = v;
+    }
+  }
+}
 
 // One walker's output record: 3N forces, energy, eps, sigma.
 inline int rec_floats(int n_atoms) { return 3 * n_atoms + 3; }
@@ -109,6 +175,20 @@ struct Server {
 
   void run_scheduler();
   void run_poller();
+  // queue a filled-in request (under the lock); returns its ticket
+  int64_t enqueue(Req& r) {
+    r.arrival = clk::now();
+    if (!have_first) {
+      first_arrival = r.arrival;
+      have_first = true;
+    }
+    const int64_t t = next_ticket++;
+    const int model = r.model, w = r.walkers;
+    reqs.emplace(t, r);
+    waiting.push_back({t, model, w});
+    cv_sched.notify_all();
+    return t;
+  }
   // finish request t with status st (under the lock)
   void mark(int64_t t, int st) {
     Req& r = reqs[t];
@@ -136,11 +216,33 @@ rid_status Server::launch(const Batch& b, const ServeModel& m) {
   float* g = reinterpret_cast<float*>(take((size_t)W * K * n * 4));
   float* x = reinterpret_cast<float*>(take((size_t)W * 2 * n * 4));
   hipStream_t st = streams[b.slot];
+  // device parts in groups of kMaxDevParts (one gather and one scatter
+  // launch per group), host parts one copy each way
+  std::vector<DevParts> groups;
   int wo = 0;
   for (const auto& pr : b.parts) {
-    RID_HIP(hipMemcpyAsync(pos + (size_t)wo * N * 3, pr.first, (size_t)pr.second * N * 3 * 4,
-                           hipMemcpyHostToDevice, st));
-    wo += pr.second;
+    if (pr.pin) {
+      RID_HIP(hipMemcpyAsync(pos + (size_t)wo * N * 3, pr.pin, (size_t)pr.walkers * N * 3 * 4,
+                             hipMemcpyHostToDevice, st));
+    } else {
+      if (groups.empty() || groups.back().n == kMaxDevParts) groups.push_back(DevParts{});
+      DevParts& g = groups.back();
+      g.row0[g.n] = wo;
+      g.walkers[g.n] = pr.walkers;
+      g.io[g.n] = pr.io;
+      ++g.n;
+    }
+    wo += pr.walkers;
+  }
+  auto grid_for = [&](const DevParts& g, int per_walker) {
+    int most = 0;
+    for (int q = 0; q < g.n; ++q) most = std::max(most, g.walkers[q]);
+    const long long count = (long long)most * per_walker;
+    return dim3((unsigned)std::min<long long>((count + 255) / 256, 1024), (unsigned)g.n);
+  };
+  for (const DevParts& g : groups) {
+    hipLaunchKernelGGL(serve_gather_kernel, grid_for(g, 3 * N), dim3(256), 0, st, g, pos, 3 * N);
+    RID_HIP(hipGetLastError());
   }
   const TorsionInput tin{m.sys, pos};
   rid_status rs = launch_mlp_from_pos(*m.ens, tin, W, A, g, st);
@@ -152,12 +254,18 @@ rid_status Server::launch(const Batch& b, const ServeModel& m) {
   rs = launch_bias_scatter(*m.sys, K, pos, W, A, g, nullptr, m.eps0, m.eps1, rec, rec + 3 * N,
                            rec + 3 * N + 1, rec + 3 * N + 2, flags, st, RF);
   if (rs != RID_OK) return rs;
+  for (const DevParts& g : groups) {
+    hipLaunchKernelGGL(serve_scatter_kernel, grid_for(g, RF), dim3(256), 0, st, g, rec, 3 * N);
+    RID_HIP(hipGetLastError());
+  }
   wo = 0;
   for (const auto& pr : b.parts) {
-    unsigned char* out = reinterpret_cast<unsigned char*>(pr.first) + pin_pos_bytes(pr.second, N);
-    RID_HIP(hipMemcpyAsync(out, rec + (size_t)wo * RF, (size_t)pr.second * RF * 4,
-                           hipMemcpyDeviceToHost, st));
-    wo += pr.second;
+    if (pr.pin) {
+      unsigned char* out = reinterpret_cast<unsigned char*>(pr.pin) + pin_pos_bytes(pr.walkers, N);
+      RID_HIP(hipMemcpyAsync(out, rec + (size_t)wo * RF, (size_t)pr.walkers * RF * 4,
+                             hipMemcpyDeviceToHost, st));
+    }
+    wo += pr.walkers;
   }
   RID_HIP(hipEventRecord(events[b.slot], st));
   return RID_OK;
@@ -210,7 +318,7 @@ void Server::run_scheduler() {
       const int64_t t = waiting[i].ticket;
       b.tickets.push_back(t);
       const Req& r = reqs[t];
-      b.parts.emplace_back(r.pin, r.walkers);
+      b.parts.push_back(Part{r.dev ? nullptr : r.pin, r.io, r.walkers});
     }
     for (auto it = pick.rbegin(); it != pick.rend(); ++it) waiting.erase(waiting.begin() + *it);
     slot_busy[slot] = true;
@@ -399,16 +507,28 @@ rid_status rid_server_submit(rid_server srv, int model_id, const float* host_pos
   lk.unlock();
   std::memcpy(r.pin, host_pos, (size_t)n_walkers * N * 3 * 4);
   lk.lock();
-  r.arrival = clk::now();
-  if (!s.have_first) {
-    s.first_arrival = r.arrival;
-    s.have_first = true;
-  }
-  const int64_t t = s.next_ticket++;
-  s.reqs.emplace(t, r);
-  s.waiting.push_back({t, model_id, n_walkers});
-  *ticket = t;
-  s.cv_sched.notify_all();
+  *ticket = s.enqueue(r);
+  return RID_OK;
+}
+
+rid_status rid_server_submit_device(rid_server srv, int model_id, const float* d_pos,
+                                    int n_walkers, float* d_force, float* d_energy,
+                                    float* d_eps, float* d_sigma, int64_t* ticket) {
+  if (!srv || !d_pos || !ticket) return fail(RID_EINVAL, "NULL argument");
+  Server& s = srv->s;
+  std::lock_guard<std::mutex> lk(s.mu);
+  if (model_id < 0 || model_id >= (int)s.models.size()) return fail(RID_EINVAL, "unknown model id");
+  if (n_walkers < 1) return fail(RID_EINVAL, "n_walkers must be >= 1");
+  if (s.fatal != RID_OK) return fail((rid_status)s.fatal, "server stopped after a device error");
+  if (s.stop) return fail(RID_EINVAL, "server is being destroyed");
+  if (s.models[model_id].shape.batch_bytes(n_walkers) > s.dev.capacity())
+    return fail(RID_ENOMEM, "request larger than the HBM budget");
+  Req r;
+  r.model = model_id;
+  r.walkers = n_walkers;
+  r.dev = true;
+  r.io = DevIo{d_pos, d_force, d_energy, d_eps, d_sigma};
+  *ticket = s.enqueue(r);
   return RID_OK;
 }
 
@@ -430,7 +550,7 @@ rid_status rid_server_wait(rid_server srv, int64_t ticket, float* host_force,
   const Req done = r;   // this waiter owns the finished request from here on
   const int N = s.models[r.model].shape.n_atoms;
   lk.unlock();
-  if (st == RID_OK) {
+  if (st == RID_OK && !done.dev) {
     const int w = done.walkers, RF = rec_floats(N);
     const float* rec = reinterpret_cast<const float*>(
         reinterpret_cast<const unsigned char*>(done.pin) + pin_pos_bytes(w, N));
@@ -452,12 +572,73 @@ rid_status rid_server_wait(rid_server srv, int64_t ticket, float* host_force,
     s.requests_done += 1;
     if (done.done_at > s.last_done) s.last_done = done.done_at;
   }
-  if (!done.own_pin) s.pin.release(done.pin_off);
+  if (!done.dev && !done.own_pin) s.pin.release(done.pin_off);
   s.reqs.erase(ticket);
   --s.waiters;
   if (s.stop) s.cv_done.notify_all();   // wake destroy, which waits for the last waiter
   lk.unlock();
   if (st != RID_OK) return fail(st, "request failed (device error, or the server was destroyed)");
+  return RID_OK;
+}
+
+rid_status rid_server_replay(rid_server srv, const rid_replay_request* reqs, int n,
+                             double* latency_us, double* submit_lag_us, double* wall_s) {
+  if (!srv || !reqs || n < 1) return fail(RID_EINVAL, "need a server and n >= 1 requests");
+  for (int i = 0; i < n; ++i)
+    if (!reqs[i].pos || reqs[i].n_walkers < 1 || !(reqs[i].arrival_s >= 0.0) ||
+        (i > 0 && reqs[i].arrival_s < reqs[i - 1].arrival_s))
+      return fail(RID_EINVAL, "requests need positions, walkers >= 1 and arrival times in order");
+  std::vector<int64_t> tickets(n, 0);
+  std::vector<rid_status> sub(n, RID_OK);
+  std::mutex m;
+  std::condition_variable cv;
+  int submitted = 0;
+  const clk::time_point t0 = clk::now();
+  // the submitting thread releases each request at its arrival time: a
+  // sleep until ~100 us before it, then a spin
+  std::thread producer([&] {
+    for (int i = 0; i < n; ++i) {
+      const rid_replay_request& q = reqs[i];
+      const clk::time_point due =
+          t0 + std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(q.arrival_s));
+      const clk::time_point wake = due - std::chrono::microseconds(100);
+      if (clk::now() < wake) std::this_thread::sleep_until(wake);
+      while (clk::now() < due) std::this_thread::yield();
+      if (submit_lag_us)
+        submit_lag_us[i] = std::chrono::duration<double, std::micro>(clk::now() - due).count();
+      int64_t t = 0;
+      const rid_status rs =
+          q.device ? rid_server_submit_device(srv, q.model_id, q.pos, q.n_walkers, q.force,
+                                              q.energy, q.eps, q.sigma, &t)
+                   : rid_server_submit(srv, q.model_id, q.pos, q.n_walkers, &t);
+      {
+        std::lock_guard<std::mutex> lk(m);
+        tickets[i] = t;
+        sub[i] = rs;
+        submitted = i + 1;
+      }
+      cv.notify_one();
+    }
+  });
+  rid_status first_err = RID_OK;
+  for (int i = 0; i < n; ++i) {
+    {
+      std::unique_lock<std::mutex> lk(m);
+      cv.wait(lk, [&] { return submitted > i; });
+    }
+    double lat = 0.0;
+    rid_status rs = sub[i];
+    if (rs == RID_OK)
+      rs = rid_server_wait(srv, tickets[i], reqs[i].device ? nullptr : reqs[i].force,
+                           reqs[i].device ? nullptr : reqs[i].energy,
+                           reqs[i].device ? nullptr : reqs[i].eps,
+                           reqs[i].device ? nullptr : reqs[i].sigma, &lat);
+    if (latency_us) latency_us[i] = rs == RID_OK ? lat : -1.0;
+    if (rs != RID_OK && first_err == RID_OK) first_err = rs;
+  }
+  producer.join();
+  if (wall_s) *wall_s = std::chrono::duration<double>(clk::now() - t0).count();
+  if (first_err != RID_OK) return fail(first_err, "a replayed request failed");
   return RID_OK;
 }
 

@@ -180,3 +180,76 @@ def test_completion_is_signalled_without_a_poll_timeout(torch, rid):
     med = float(np.median(rt))
     print(f"round trip median {1e6 * med:.0f} us", flush=True)
     assert med < 1e-3
+
+
+def test_device_requests_in_the_mix_are_batch_invariant(torch, rid):
+    """Walker state resident in device memory: every other request is a
+    device request (positions read from and forces written to the caller's
+    device tensors), mixed with host requests in the same batches; each
+    result equals the direct call bit for bit."""
+    ms = _models(rid)
+    srv = rid.Server(2 << 30, n_streams=4, max_batch_walkers=2048)
+    ids = [srv.register(m["S"], m["E"], 2.0, 3.0) for m in ms]
+    rng = np.random.default_rng(9)
+    reqs = []
+    for r in range(80):
+        mi = int(rng.integers(0, len(ms)))
+        w = int(np.clip(np.floor(np.exp(rng.uniform(0, np.log(257)))), 1, 256))
+        reqs.append((mi, ridgen.f32(ridgen.chain_coords(ms[mi]["sys"], w, 300 + r)), r % 2 == 0))
+    outs = []
+    f = dict(dtype=torch.float32, device="cuda")
+    for i, (mi, pos, dev) in enumerate(reqs):
+        if dev:
+            N, w = ms[mi]["sys"].n_atoms, pos.shape[0]
+            o = dict(F=torch.full((w, N, 3), float("nan"), **f), E=torch.empty(w, **f),
+                     eps=torch.empty(w, **f), sigma=torch.empty(w, **f))
+            outs.append((torch.from_numpy(pos).cuda(), o))
+        else:
+            outs.append(None)
+    torch.cuda.synchronize()                  # inputs in place before the server reads them
+    # submitted in one burst, so requests share batches
+    tickets = [srv.submit_device(ids[mi], outs[i][0], outs[i][1]) if dev
+               else srv.submit(ids[mi], pos) for i, (mi, pos, dev) in enumerate(reqs)]
+    results = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    assert st["requests_done"] == len(reqs) and st["batches"] < len(reqs)
+    for i, (mi, pos, dev) in enumerate(reqs):
+        ref = _direct(torch, rid, ms[mi], pos, 2.0, 3.0)
+        if dev:
+            o = outs[i][1]
+            got = {k: o[k].cpu().numpy() for k in ("F", "E", "eps", "sigma")}
+        else:
+            got = results[i]
+        for k in ("F", "E", "eps", "sigma"):
+            assert np.array_equal(got[k], ref[k]), (i, ms[mi]["name"], dev, k)
+    srv.close()
+
+
+def test_native_replay_of_an_open_loop_trace(torch, rid):
+    """rid_server_replay: a Poisson trace submitted and waited from native
+    threads, device requests; every result equals the direct call."""
+    ms = _models(rid)[:4]
+    srv = rid.Server(2 << 30, n_streams=4, max_batch_walkers=4096)
+    ids = [srv.register(m["S"], m["E"], 2.0, 3.0) for m in ms]
+    rng = np.random.default_rng(11)
+    t, reqs, keep = 0.0, [], []
+    f = dict(dtype=torch.float32, device="cuda")
+    for r in range(120):
+        t += float(rng.exponential(2e-4))
+        mi = int(rng.integers(0, len(ms)))
+        w = int(np.clip(np.floor(np.exp(rng.uniform(0, np.log(129)))), 1, 128))
+        pos = ridgen.f32(ridgen.chain_coords(ms[mi]["sys"], w, 500 + r))
+        p = torch.from_numpy(pos).cuda()
+        out = dict(F=torch.empty((w, ms[mi]["sys"].n_atoms, 3), **f), eps=torch.empty(w, **f))
+        keep.append((mi, pos, out))
+        reqs.append(dict(model=ids[mi], arrival_s=t, pos=p, out=out))
+    torch.cuda.synchronize()
+    lat, lag, wall = srv.replay(reqs)
+    print(f"replay: {len(reqs)} requests in {wall * 1e3:.1f} ms, p50 latency "
+          f"{np.median(lat):.0f} us, max submit lag {lag.max():.0f} us", flush=True)
+    assert np.all(lat > 0) and wall > 0
+    for mi, pos, out in keep:
+        ref = _direct(torch, rid, ms[mi], pos, 2.0, 3.0)
+        assert np.array_equal(out["F"].cpu().numpy(), ref["F"])
+        assert np.array_equal(out["eps"].cpu().numpy(), ref["eps"])
+    srv.close()
