@@ -708,88 +708,138 @@ def bench_labels(rid, torch, reps=20):
                          "frac": byts / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}}
 
 
-SERVE_CLASSES = [("dipeptide", ridgen.system_dipeptide, [100] * 3),
-                 ("peptide20", ridgen.system_peptide20, [256] * 4),
-                 ("peptide61", ridgen.system_peptide61, [512] * 4)]
+SERVE_SYSTEMS = (("dipeptide", ridgen.system_dipeptide),     # 2 CVs, 22 atoms
+                 ("peptide20", ridgen.system_peptide20),     # 38 CVs, 200 atoms
+                 ("peptide61", ridgen.system_peptide61))     # 120 CVs, 1000 atoms
+SERVE_WIDTHS = {100: [100] * 3, 256: [256] * 4, 512: [512] * 4}
+SERVE_POOL = 256          # walkers of seeded positions per system class
 
 
-def _serve_models(rid, fp32_only):
-    models = []
-    for ci, (name, mk, widths) in enumerate(SERVE_CLASSES):
+def _serve_models(rid, torch, fp32_only):
+    """One registered model per (system class, width, precision): widths
+    100 / 256 / 512 ([100 x 3], [256 x 4], [512 x 4]), FP32 and BF16 (K = 8
+    for 512-BF16, else 4), so a uniform model draw gives the classes, widths
+    and precisions uniformly.  Each class also gets a device pool of
+    SERVE_POOL walkers' seeded positions that its requests take slices of."""
+    models, pools = [], []
+    for ci, (name, mk) in enumerate(SERVE_SYSTEMS):
         sys_ = mk()
         S = rid.System(sys_.n_atoms, sys_.quads)
-        precs = [rid.RID_FP32] if fp32_only else [rid.RID_FP32, rid.RID_BF16]
-        for prec in precs:
-            K = 8 if (widths[0] == 512 and prec == rid.RID_BF16) else 4
-            E = rid.Ensemble(sys_.n_cv, widths, K,
-                             ridgen.xavier_ensemble(2 * sys_.n_cv, widths, K, 1000 + ci), prec)
-            models.append((sys_, S, E))
-    return models
+        pos = ridgen.f32(ridgen.chain_coords(sys_, SERVE_POOL, 7 + ci))
+        pools.append(dict(sys=sys_, host=pos, dev=torch.from_numpy(pos).cuda()))
+        for width, widths in SERVE_WIDTHS.items():
+            for prec in ([rid.RID_FP32] if fp32_only else [rid.RID_FP32, rid.RID_BF16]):
+                K = 8 if (width == 512 and prec == rid.RID_BF16) else 4
+                E = rid.Ensemble(sys_.n_cv, widths, K,
+                                 ridgen.xavier_ensemble(2 * sys_.n_cv, widths, K, 1000 + ci),
+                                 prec)
+                models.append(dict(cls=ci, S=S, E=E))
+    return models, pools
 
 
-def run_trace(rid, models, fifo, n_req, rate_hz, seed=5):
-    """Open-loop Poisson stream: a submitter thread releases requests at
-    their arrival times, a collector waits them in order."""
-    srv = rid.Server(64 << 30 if not fifo else 8 << 30, n_streams=4, max_batch_walkers=8192,
+def _serve_requests(torch, models, pools, n, seed, device):
+    """n requests: model uniform, walkers log-uniform in [1, 256], a slice of
+    the class's position pool; device requests get their own output slices
+    (forces, eps) of per-class device buffers.  Returns (requests without
+    arrival times, walkers [n], unit-rate Poisson gaps [n])."""
+    rng = np.random.default_rng(seed)
+    mi = rng.integers(0, len(models), size=n)
+    w = np.clip(np.floor(np.exp(rng.uniform(0.0, math.log(257), size=n))), 1, 256).astype(int)
+    off = [int(rng.integers(0, SERVE_POOL - int(w[i]) + 1)) for i in range(n)]
+    gaps = rng.exponential(1.0, size=n)
+    outs = {}
+    if device:
+        for c, pl in enumerate(pools):
+            tot = int(sum(w[i] for i in range(n) if models[mi[i]]["cls"] == c))
+            outs[c] = (torch.empty((max(tot, 1), pl["sys"].n_atoms, 3), dtype=torch.float32,
+                                   device="cuda"),
+                       torch.empty(max(tot, 1), dtype=torch.float32, device="cuda"), [0])
+    reqs = []
+    for i in range(n):
+        m = models[mi[i]]
+        pl = pools[m["cls"]]
+        if device:
+            F, eps, cur = outs[m["cls"]]
+            o = dict(F=F[cur[0]:cur[0] + w[i]], eps=eps[cur[0]:cur[0] + w[i]])
+            cur[0] += int(w[i])
+            reqs.append(dict(model=int(mi[i]), pos=pl["dev"][off[i]:off[i] + w[i]], out=o))
+        else:
+            reqs.append(dict(model=int(mi[i]), pos=pl["host"][off[i]:off[i] + w[i]]))
+    return reqs, w, gaps
+
+
+def _serve_run(rid, torch, models, pools, fifo, device, n_warm=1000, n_meas=20000,
+               loads=(0.25, 0.5, 0.75, 0.9), seed=5):
+    """The serving protocol on one server: n_warm requests to warm up, then
+    n_meas requests closed-loop (all offered at once: the capacity), then
+    the same n_meas requests as a Poisson stream at each fraction of that
+    capacity.  Latency = arrival at the server to results visible (device
+    buffers for device requests)."""
+    srv = rid.Server((8 << 30) if fifo else (64 << 30), n_streams=4, max_batch_walkers=8192,
                      fifo=fifo)
-    ids = [srv.register(S, E, 2.0, 3.0) for (_, S, E) in models]
-    trace = ridgen.poisson_trace(n_req, rate_hz, len(models), seed=seed)
-    poss = [ridgen.f32(ridgen.chain_coords(models[r.model_class][0], r.n_walkers, 7 + i))
-            for i, r in enumerate(trace)]
-    # warm every model once (first-use kernel setup is not part of serving)
-    for mi, (sys_, _, _) in enumerate(models):
-        srv.wait(srv.submit(ids[mi], ridgen.f32(ridgen.chain_coords(sys_, 4, 1))))
-    srv.reset_stats()
-    tickets = [None] * n_req
-    ready = threading.Semaphore(0)
+    ids = [srv.register(m["S"], m["E"], 2.0, 3.0) for m in models]
+    assert ids == list(range(len(models)))
+    warm, _, _ = _serve_requests(torch, models, pools, n_warm, seed + 100, device)
+    reqs, w, gaps = _serve_requests(torch, models, pools, n_meas, seed, device)
+    torch.cuda.synchronize()
+    for q in warm:
+        q["arrival_s"] = 0.0
+    srv.replay(warm)
 
-    def submitter():
-        t0 = time.perf_counter()
-        for i, r in enumerate(trace):
-            dt = r.arrival_s - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            tickets[i] = srv.submit(ids[r.model_class], poss[i])
-            ready.release()
+    def run(arrivals):
+        for q, a in zip(reqs, arrivals):
+            q["arrival_s"] = float(a)
+        srv.reset_stats()
+        lat, lag, wall = srv.replay(reqs)
+        st = srv.stats()
+        return {"requests": n_meas, "p50_us": float(np.percentile(lat, 50)),
+                "p99_us": float(np.percentile(lat, 99)), "mean_us": float(lat.mean()),
+                "walker_steps_per_s": float(w.sum()) / wall, "wall_s": wall,
+                "batches": st["batches"], "mean_batch_walkers": st["mean_batch_walkers"],
+                "max_inflight_batches": st["max_inflight_batches"],
+                "max_submit_lag_us": float(lag.max()), "p99_submit_lag_us": float(np.percentile(lag, 99))}
 
-    th = threading.Thread(target=submitter)
-    t_start = time.perf_counter()
-    th.start()
-    for i in range(n_req):
-        ready.acquire()
-        srv.wait(tickets[i])
-    th.join()
-    wall = time.perf_counter() - t_start
-    st = srv.stats()
+    cap = run(np.zeros(n_meas))
+    cap_req_s = n_meas / cap["wall_s"]
+    out = {"capacity": cap, "capacity_req_per_s": cap_req_s, "loads": []}
+    for f in loads:
+        r = run(np.cumsum(gaps) / (f * cap_req_s))
+        r.update({"load": f, "offered_req_per_s": f * cap_req_s,
+                  "offered_walker_steps_per_s": f * cap["walker_steps_per_s"]})
+        out["loads"].append(r)
     srv.close()
-    walkers = sum(r.n_walkers for r in trace)
-    return {"p50_us": st["p50_us"], "p99_us": st["p99_us"], "mean_us": st["mean_us"],
-            "walker_steps_per_s": walkers / wall, "requests": n_req,
-            "offered_req_per_s": rate_hz, "batches": st["batches"],
-            "mean_batch_walkers": st["mean_batch_walkers"],
-            "max_inflight_batches": st["max_inflight_batches"]}
+    return out
 
 
-def bench_serving(rid, n_req=1500):
-    mixed = _serve_models(rid, fp32_only=False)
-    # closed-loop capacity: everything offered at once
-    cap = run_trace(rid, mixed, False, n_req, 1e9)
-    # requests/s the batched server sustained in the closed loop
-    mean_w = np.mean([r.n_walkers for r in ridgen.poisson_trace(n_req, 1.0, len(mixed), 5)])
-    cap_req_s = cap["walker_steps_per_s"] / mean_w
-    load = run_trace(rid, mixed, False, n_req, 0.5 * cap_req_s)
-    fp32 = _serve_models(rid, fp32_only=True)
-    base_cap = run_trace(rid, fp32, True, n_req // 3, 1e9)
-    base_req_s = base_cap["walker_steps_per_s"] / mean_w
-    base = run_trace(rid, fp32, True, n_req // 3, 0.5 * base_req_s)
+def bench_serving(rid, torch):
+    """Serving form: requests over 3 system classes x widths 100/256/512 x
+    FP32/BF16 (the model drawn uniformly), 1-256 walkers log-uniform, walker
+    state device-resident (positions read from and forces written to device
+    buffers), HBM budget 64 GiB; 1000 warm-up requests, 20 000 measured ones
+    closed-loop for the capacity, then at offered loads 0.25 / 0.5 / 0.75 /
+    0.9 x capacity (Poisson).  Baseline: the same trace over FP32 models
+    served FIFO, one request at a time, at the same fractions of its own
+    capacity.  The trace is replayed by the library's native driver."""
+    mixed, pools = _serve_models(rid, torch, fp32_only=False)
+    log("serving: batched, device-resident")
+    batched = _serve_run(rid, torch, mixed, pools, fifo=False, device=True)
+    log("serving: batched, host-staged capacity")
+    host = _serve_run(rid, torch, mixed, pools, fifo=False, device=False, loads=())
+    fp32, pools32 = _serve_models(rid, torch, fp32_only=True)
+    log("serving: FIFO FP32 baseline")
+    fifo = _serve_run(rid, torch, fp32, pools32, fifo=True, device=True)
+    half = [r for r in batched["loads"] if r["load"] == 0.5][0]
     return {
-        "workload": "Poisson requests over 3 system classes (2 CVs/22 atoms, 38/200, "
-                    "120/1000) x widths 100/256/512 x FP32/BF16 (K=8 for 512-BF16), "
-                    "1-256 walkers log-uniform, weights resident, HBM budget 64 GB",
-        "batched_capacity": cap, "batched_at_half_capacity": load,
-        "fifo_fp32_capacity": base_cap, "fifo_fp32_at_half_capacity": base,
-        "p50_us": load["p50_us"], "p99_us": load["p99_us"],
-        "walker_steps_per_s": cap["walker_steps_per_s"],
+        "workload": "Poisson requests over 3 system classes (2 CVs/22 atoms, 38/200, 120/1000) x "
+                    "widths 100/256/512 x FP32/BF16 (K=8 for 512-BF16), 1-256 walkers "
+                    "log-uniform, weights and walker state resident in HBM, HBM budget 64 GiB; "
+                    "1000 warm-up + 20000 measured requests; loads 0.25/0.5/0.75/0.9 x capacity",
+        "batched": batched, "batched_host_staged": {"capacity": host["capacity"]},
+        "fifo_fp32": fifo,
+        "p50_us": half["p50_us"], "p99_us": half["p99_us"],
+        "walker_steps_per_s": batched["capacity"]["walker_steps_per_s"],
+        "capacity_vs_fifo_fp32": batched["capacity"]["walker_steps_per_s"]
+                                 / fifo["capacity"]["walker_steps_per_s"],
     }
 
 
@@ -930,7 +980,7 @@ def main():
         rec["selection"] = bench_selection(rid, torch)
         if not args.no_serve:
             log("serving")
-            rec["serving"] = bench_serving(rid)
+            rec["serving"] = bench_serving(rid, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline and sampled accuracy")
         rec["cpu_baseline"] = cpu_baseline(case, samples)
