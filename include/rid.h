@@ -145,6 +145,13 @@ int64_t rid_ensemble_step(rid_ensemble ens);
  * residual connections the mask scales each layer's tanh branch, not the
  * skip.  Errors: RID_EINVAL (NULL, p outside [0, 1)). */
 rid_status rid_ensemble_set_dropout(rid_ensemble ens, float rate, uint64_t seed);
+/* Device bytes the training calls (rid_mf_train_step, rid_mf_loss_grad,
+ * rid_mf_grad) may hold for stored activations; a larger batch runs in
+ * chunks of rows (multiples of 64, at least 64 rows however small the
+ * budget).  0 restores the default (512 MiB).  The workspace already
+ * allocated is kept until the ensemble is destroyed.  Errors: RID_EINVAL
+ * (NULL). */
+rid_status rid_ensemble_set_train_budget(rid_ensemble ens, size_t bytes);
 /* rid_ensemble_set_resnet - residual connections (the `resnet` training
  * setting, "Training phase": hidden layers of equal width joined by residual
  * connections).  With enable != 0 every hidden layer after the first adds
@@ -391,6 +398,14 @@ rid_status rid_cv_apply_force(rid_system sys, const float* d_pos,
  *   d_loss    [K] | NULL  loss of each member BEFORE the update
  * The step always runs in FP32 on the FP32 masters; a BF16/FP16 ensemble
  * has its 16-bit copies refreshed before its next evaluation.
+ * Memory: the sweeps keep the activations of every layer (primal, tangent
+ * and adjoint) for the rows of one pass.  A batch whose activations exceed
+ * the ensemble's training budget (rid_ensemble_set_train_budget, 512 MiB by
+ * default) is taken in equal chunks of rows, in row order, and the chunks'
+ * gradient contributions are added in that order: the result depends on
+ * the budget only through that summation order, and is reproducible for a
+ * given budget.  Dropout masks and the 1/B scale are those of the whole
+ * batch.
  * ------------------------------------------------------------------------ */
 rid_status rid_mf_train_step(rid_ensemble ens, const float* d_s,
                              const float* d_F, int B, float lr, float* d_loss,

@@ -30,6 +30,7 @@ EXPORTS = (
     "rid_packed_param_count", "rid_ensemble_create", "rid_ensemble_get_params",
     "rid_ensemble_set_params", "rid_ensemble_load_params", "rid_ensemble_step", "rid_ensemble_set_dropout",
     "rid_ensemble_set_resnet", "rid_ensemble_set_angular_mask", "rid_ensemble_set_cv_bounds",
+    "rid_ensemble_set_train_budget",
     "rid_ensemble_destroy",
     "rid_cv_eval", "rid_model_dev", "rid_cluster_frames", "rid_select", "rid_bias_force",
     "rid_bias_force_conservative", "rid_bias_force_noalloc", "rid_noalloc_scratch_floats",
@@ -98,6 +99,7 @@ def lib():
         "rid_ensemble_set_resnet": (i, [vp, i]),
         "rid_ensemble_set_angular_mask": (i, [vp, vp]),
         "rid_ensemble_set_cv_bounds": (i, [vp, vp, vp]),
+        "rid_ensemble_set_train_budget": (i, [vp, ctypes.c_size_t]),
         "rid_ensemble_destroy": (None, [vp]),
         "rid_cv_eval": (i, [vp, vp, i, vp, vp, vp]),
         "rid_model_dev": (i, [vp, vp, i, vp, vp, vp, vp, vp]),
@@ -254,6 +256,12 @@ class Ensemble:
         if m.shape != (self.n_cv,):
             raise ValueError("angular_mask must be [n_cv]")
         _check(lib().rid_ensemble_set_angular_mask(self.handle, m.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_train_budget(self, nbytes: int = 0):
+        """rid_ensemble_set_train_budget: device bytes of stored activations
+        one training pass may hold (0: the default); larger batches run in
+        chunks of rows."""
+        _check(lib().rid_ensemble_set_train_budget(self.handle, int(nbytes)))
 
     def set_cv_bounds(self, lower=None, upper=None):
         """rid_ensemble_set_cv_bounds: the MCMC box of the raw CVs (host

@@ -426,6 +426,12 @@ rid_status rid_ensemble_set_dropout(rid_ensemble ens, float rate, uint64_t seed)
   return RID_OK;
 }
 
+rid_status rid_ensemble_set_train_budget(rid_ensemble ens, size_t bytes) {
+  if (!ens) return fail(RID_EINVAL, "NULL argument");
+  ens->impl.train_budget = bytes ? bytes : kTrainBudgetDefault;
+  return RID_OK;
+}
+
 rid_status rid_ensemble_set_cv_bounds(rid_ensemble ens, const float* lower,
                                       const float* upper) {
   if (!ens) return fail(RID_EINVAL, "NULL argument");

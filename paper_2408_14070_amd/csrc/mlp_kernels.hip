@@ -1158,7 +1158,10 @@ struct TrainArgs {
   const float* rho;    // [B][K][n] upstream gradient of g, or null
   float* hh[kMaxHidden + 1];   // [K][2B][wd[j]]
   float* sl[kMaxHidden];       // [K][2B][wd[j+1]]
-  float* loss_rows;    // [K][B] or null
+  float* loss_rows;    // row b of member k at loss_rows[k * loss_ld + b], or null
+  long long loss_ld;
+  int row_base;        // batch index of row 0 (dropout counters)
+  int B_norm;          // the whole batch's size (rho scale)
   int B, n, K, L, XP, n_tiles, xcd_grp;
   int wd[kMaxHidden + 1];      // 2n, then the hidden widths
   const unsigned char* frag;
@@ -1225,7 +1228,8 @@ __global__ __launch_bounds__(NW * 64) void train_kernel(TrainArgs p) {
   if (p.drop_p > 0.f) {
     mbits = 0u;
     for (int j = 0; j < L; ++j) {
-      uint32_t c[4] = {(uint32_t)brow, p.step, (uint32_t)(16 * k + j + 1), (uint32_t)(u >> 2)};
+      uint32_t c[4] = {(uint32_t)(p.row_base + brow), p.step, (uint32_t)(16 * k + j + 1),
+                       (uint32_t)(u >> 2)};
       philox4x32_10(c, (uint32_t)(p.drop_seed & 0xFFFFFFFFull), (uint32_t)(p.drop_seed >> 32));
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -1389,7 +1393,7 @@ __global__ __launch_bounds__(NW * 64) void train_kernel(TrainArgs p) {
           const float gi = -sn * u0_at(i, c) + cs * u0_at(i, n + c);
           const float ri = gi - p.F[(size_t)row * n + c];
           acc += ri * ri;
-          rho = 2.f * ri / (float)B;
+          rho = 2.f * ri / (float)p.B_norm;
         }
         rx0 = -sn * rho;
         rx1 = cs * rho;
@@ -1404,7 +1408,7 @@ __global__ __launch_bounds__(NW * 64) void train_kernel(TrainArgs p) {
     if (p.loss_rows && row < B) {
 #pragma unroll
       for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
-      if (lane == 0) p.loss_rows[(size_t)k * B + row] = acc;
+      if (lane == 0) p.loss_rows[(size_t)k * p.loss_ld + row] = acc;
     }
   }
   __syncthreads();
@@ -1880,6 +1884,7 @@ rid_status run_train(const rid_ensemble_impl& e, const TrainIo& io, int B, hipSt
     attr = lds;
   }
   a.s = io.s; a.F = io.F; a.rho = io.rho; a.loss_rows = io.loss_rows;
+  a.loss_ld = io.loss_ld; a.row_base = io.row_base; a.B_norm = io.B_norm;
   for (int j = 0; j <= e.L; ++j) a.hh[j] = io.hh[j];
   for (int j = 0; j < e.L; ++j) a.sl[j] = io.sl[j];
   a.B = B; a.n = e.n_cv; a.K = e.K; a.L = e.L; a.XP = e.XP;

@@ -92,6 +92,8 @@ inline int kf_of(rid_precision p) { return p == RID_FP32 ? 16 : 32; }
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 constexpr int kMaxHidden = 6;
+// default device budget of the training sweeps' stored activations (512 MiB)
+constexpr size_t kTrainBudgetDefault = (size_t)512 << 20;
 constexpr int kMaxWidth = 512;
 
 // ---------------------------------------------------------------------------
@@ -142,6 +144,9 @@ struct rid_ensemble_impl {
   float drop_p = 0.f;                  // training-time dropout rate of the hidden activations
   unsigned long long drop_seed = 0;
   bool resnet = false;                 // residual connections between hidden layers 2..L
+  // device bytes the training sweeps may hold for one pass over the batch:
+  // larger batches are split into chunks of rows that fit it
+  size_t train_budget = kTrainBudgetDefault;
   // angular mask of the inputs: CVs with raw[i] = 1 enter as (s_i, 0)
   std::vector<uint8_t> raw;            // [n_cv] (empty: every CV angular)
   uint8_t* d_raw = nullptr;            // device copy, or null when no CV is raw
@@ -210,7 +215,10 @@ struct TrainIo {
   const float* rho;
   float* hh[kMaxHidden + 1];
   float* sl[kMaxHidden];
-  float* loss_rows;
+  float* loss_rows;                 // row b of member k at loss_rows[k * loss_ld + b]
+  long long loss_ld;
+  int row_base;                     // batch index of row 0 (a chunk of a larger batch)
+  int B_norm;                       // the whole batch's size: rho = 2 (g - F) / B_norm
   float drop_p;                     // dropout rate (0: none)
   unsigned long long drop_seed;
   uint32_t step;                    // training step (mask counter)

@@ -261,11 +261,12 @@ __global__ void train_embed_kernel(const float* s, int B, int n, int K, const ui
 // dropout factor: unit j of sample b of member k is kept when the uniform of
 // word j mod 4 of the Philox4x32-10 block with counter (b, step, 16 k + l,
 // j div 4) and key (seed) is >= p, scaled by 1/(1 - p); 1 without dropout.
-// A thread handles the 4 units of one block.
-__global__ void act_kernel(const float* T, int l, int w, int B, int K, float drop_p,
-                           float drop_inv, unsigned long long seed, uint32_t step,
-                           const float* Hprev, long long slab_prev, float* H, long long slab,
-                           float* D) {
+// b is the sample's index in the whole batch: row r of a chunk is sample
+// row_base + r.  A thread handles the 4 units of one block.
+__global__ void act_kernel(const float* T, int l, int w, int B, int K, int row_base,
+                           float drop_p, float drop_inv, unsigned long long seed,
+                           uint32_t step, const float* Hprev, long long slab_prev, float* H,
+                           long long slab, float* D) {
   const int nq = (w + 3) / 4;
   const long long total = (long long)K * B * nq;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
@@ -273,7 +274,7 @@ __global__ void act_kernel(const float* T, int l, int w, int B, int K, float dro
     const int k = (int)(e / ((long long)B * nq));
     const long long rq = e - (long long)k * B * nq;
     const int b = (int)(rq / nq), q = (int)(rq - (long long)b * nq);
-    uint32_t c[4] = {(uint32_t)b, step, (uint32_t)(16 * k + l), (uint32_t)q};
+    uint32_t c[4] = {(uint32_t)(row_base + b), step, (uint32_t)(16 * k + l), (uint32_t)q};
     if (drop_p > 0.f)
       dev::philox4x32_10(c, (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32));
     for (int u = 0; u < 4; ++u) {
@@ -323,11 +324,14 @@ __global__ void vlast_kernel(const float* DL, const float* master, long long per
 // tangent half of the stacked input slab.  With an upstream gradient
 // rho [B][K][n] given instead of labels, rho_x is built from it directly.
 // One wave per (member, sample) row, lanes over the CVs; the row's squared
-// residual is a fixed-order shuffle sum over the lanes.
+// residual is a fixed-order shuffle sum over the lanes.  B rows of a batch
+// of B_norm samples (rho = 2 (g - F) / B_norm); row b of member k's squared
+// residual goes to loss_rows[k * loss_ld + b].
 constexpr int kResWaves = 4;
 __global__ __launch_bounds__(kResWaves * 64) void residual_kernel(
-    const float* s, const float* F, const float* rho_in, const float* U0, int B, int n,
-    int K, const uint8_t* raw, float* HH0, long long slab, float* loss_rows) {
+    const float* s, const float* F, const float* rho_in, const float* U0, int B, int B_norm,
+    int n, int K, const uint8_t* raw, float* HH0, long long slab, float* loss_rows,
+    long long loss_ld) {
   const long long e = (long long)blockIdx.x * kResWaves + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (e >= (long long)K * B) return;
@@ -350,7 +354,7 @@ __global__ __launch_bounds__(kResWaves * 64) void residual_kernel(
       const float gi = -sn * u[i] + cs * u[n + i];
       const float ri = gi - F[(long long)b * n + i];
       acc += ri * ri;
-      rho = 2.f * ri / (float)B;
+      rho = 2.f * ri / (float)B_norm;
     }
     rx[i] = -sn * rho;
     rx[n + i] = cs * rho;
@@ -358,7 +362,7 @@ __global__ __launch_bounds__(kResWaves * 64) void residual_kernel(
   if (loss_rows) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
-    if (lane == 0) loss_rows[e] = acc;
+    if (lane == 0) loss_rows[(long long)k * loss_ld + b] = acc;
   }
 }
 
@@ -406,12 +410,14 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(const float* X, lon
 }
 
 // Stage 2: out[k][j] = the chunk partials summed in chunk order, into the
-// gradient buffer at grad + k*per_model + dst_off + j.  A block covers 64
-// outputs; each of its 4 waves sums a quarter of the chunks (in order) and
-// the quarters are combined in wave order.
+// gradient buffer at grad + k*per_model + dst_off + j (added to what it
+// holds when accumulate is set).  A block covers 64 outputs; each of its 4
+// waves sums a quarter of the chunks (in order) and the quarters are
+// combined in wave order.
 __global__ __launch_bounds__(256) void colsum_final_kernel(const float* part, int chunks, int w,
                                                            int K, float* grad,
-                                                           long long per_model, int dst_off) {
+                                                           long long per_model, int dst_off,
+                                                           int accumulate) {
   __shared__ float red[4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int e = blockIdx.x * 64 + lane;     // output k*w + j
@@ -426,15 +432,17 @@ __global__ __launch_bounds__(256) void colsum_final_kernel(const float* part, in
   __syncthreads();
   if (wave == 0 && e < K * w) {
     const int k = e / w, j = e - k * w;
-    grad[k * per_model + dst_off + j] =
-        ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    const float v = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    float* o = grad + k * per_model + dst_off + j;
+    *o = accumulate ? *o + v : v;
   }
 }
 
-// dW[k] = sum over split-K slabs (fixed order) -> gradient buffer
+// dW[k] = sum over split-K slabs (fixed order) -> gradient buffer (added to
+// what it holds when accumulate is set)
 __global__ void splitk_reduce_kernel(const float* part, long long slab_s, int ks,
                                      int out, int in, int K, float* grad,
-                                     long long per_model, int w_off) {
+                                     long long per_model, int w_off, int accumulate) {
   const long long total = (long long)K * out * in;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
@@ -442,7 +450,8 @@ __global__ void splitk_reduce_kernel(const float* part, long long slab_s, int ks
     for (int s = 0; s < ks; ++s) acc += part[s * slab_s + e];
     const int k = (int)(e / ((long long)out * in));
     const long long r = e - (long long)k * out * in;
-    grad[k * per_model + w_off + r] = acc;
+    float* o = grad + k * per_model + w_off + r;
+    *o = accumulate ? *o + acc : acc;
   }
 }
 
@@ -518,49 +527,80 @@ rid_status gemm(const GemmArgs& g0, hipStream_t st) {
 }
 
 // out[k][j] = sum_{b<B} X[k*slab + b*w + j] -> grad[k*per_model + dst_off + j]
+// (+= when accumulate)
 rid_status colsum(const float* X, long long slab, int B, int w, int K, float* part,
-                  float* grad, long long per_model, int dst_off, hipStream_t st) {
+                  float* grad, long long per_model, int dst_off, bool accumulate,
+                  hipStream_t st) {
   const int chunks = (B + kColRows - 1) / kColRows;
   hipLaunchKernelGGL(colsum_partial_kernel, dim3((w + 63) / 64, chunks, K), dim3(256), 0, st,
                      X, slab, B, w, part, K);
   RID_HIP(hipGetLastError());
   hipLaunchKernelGGL(colsum_final_kernel, dim3((K * w + 63) / 64), dim3(256), 0, st, part,
-                     chunks, w, K, grad, per_model, dst_off);
+                     chunks, w, K, grad, per_model, dst_off, accumulate ? 1 : 0);
   RID_HIP(hipGetLastError());
   return RID_OK;
+}
+
+// Rows per pass over the batch: all B when the pass's stored activations
+// (floats_per_row floats a row) fit the budget, else equal chunks, each a
+// multiple of 64 rows and at least 64, that do.
+int chunk_rows(long long floats_per_row, int B, size_t budget) {
+  const long long fit = (long long)(budget / (sizeof(float) * (size_t)floats_per_row));
+  if (fit >= B) return B;
+  const long long step = std::max<long long>(64, fit / 64 * 64);
+  const long long chunks = (B + step - 1) / step;
+  return (int)std::min<long long>(step, (B + chunks - 1) / chunks + 63) / 64 * 64;
+}
+
+// Split of the 2R-row weight-gradient contraction of a pass of R rows:
+// enough split-K slabs to fill the chip, each at least 256 rows.
+void wgrad_split(int K, int tiles_max, int R, int* ks, int* kchunk) {
+  int s = 1;
+  while (s < 64 && (long long)K * tiles_max * s < 1024 && 2LL * R / (s * 2) >= 256) s *= 2;
+  *ks = s;
+  *kchunk = round_up((2 * R + s - 1) / s, BK);
 }
 
 // The training step with the sweeps fused into one kernel (train_kernel):
 // it writes [h ; hd] of every layer input and [lam_z ; lam_zd] of every
 // layer, then the batch reductions run as before: dW_l = S_l^T [h ; hd]_{l-1}
-// (split over the 2B rows), db_l = column sums of lam_z, dw_o = column sums
-// of hd_L.  Workspace regions are 256-byte aligned (the kernel stores float4).
+// (split over the 2R rows), db_l = column sums of lam_z, dw_o = column sums
+// of hd_L.  A batch larger than the training budget allows runs in chunks of
+// Bc rows, in row order: each chunk's reductions are added to the gradient
+// in chunk order, so the step stays deterministic, and only one chunk's
+// activations are ever held.  Workspace regions are 256-byte aligned (the
+// kernel stores float4).
 rid_status mf_grad_fused(rid_ensemble_impl& e, const float* s, const float* F,
                          const float* rho, int B, float* loss, float* grad_out,
                          float** grad_used, hipStream_t st, const std::vector<int>& w,
                          const std::vector<long long>& w_off,
-                         const std::vector<long long>& b_off, long long wo_off, int ks,
-                         int kchunk) {
-  const int K = e.K, L = e.L;
+                         const std::vector<long long>& b_off, long long wo_off,
+                         int tiles_max) {
+  const int K = e.K, L = e.L, n = e.n_cv;
   int wmax = 0;
   for (int v : w) wmax = std::max(wmax, v);
+  long long per_row = 0;
+  for (int l = 0; l <= L; ++l) per_row += (long long)K * 2 * w[l] * (l > 0 ? 2 : 1);
+  const int Bc = chunk_rows(per_row, B, e.train_budget);
+  int ks_max, kc;
+  wgrad_split(K, tiles_max, Bc, &ks_max, &kc);
   auto al = [](long long v) { return (v + 63) / 64 * 64; };
   std::vector<long long> hh(L + 1), sl(L);
   long long tot = 0;
   for (int l = 0; l <= L; ++l) {
     hh[l] = tot;
-    tot = al(tot + (long long)K * 2 * B * w[l]);
+    tot = al(tot + (long long)K * 2 * Bc * w[l]);
   }
   for (int l = 1; l <= L; ++l) {
     sl[l - 1] = tot;
-    tot = al(tot + (long long)K * 2 * B * w[l]);
+    tot = al(tot + (long long)K * 2 * Bc * w[l]);
   }
   long long part_slab = 0;
   for (int l = 0; l < L; ++l) part_slab = std::max(part_slab, (long long)K * w[l + 1] * w[l]);
-  const long long part = tot; tot = al(tot + part_slab * ks);
+  const long long part = tot; tot = al(tot + part_slab * ks_max);
   const long long grad = tot; tot = al(tot + (long long)e.n_params);
   const long long lrows = tot; tot = al(tot + (long long)K * B);
-  const long long cpart = tot; tot = al(tot + (long long)((B + kColRows - 1) / kColRows) * K * wmax);
+  const long long cpart = tot; tot = al(tot + (long long)((Bc + kColRows - 1) / kColRows) * K * wmax);
   rid_status rs = e.ws_train.ensure(sizeof(float) * tot);
   if (rs != RID_OK) return rs;
   float* W = e.ws_train.as<float>();
@@ -573,41 +613,50 @@ rid_status mf_grad_fused(rid_ensemble_impl& e, const float* s, const float* F,
     e.frag_dirty = false;
   }
   TrainIo io{};
-  io.s = s;
-  io.F = rho ? nullptr : F;
-  io.rho = rho;
-  io.loss_rows = rho ? nullptr : W + lrows;
+  io.loss_ld = B;
+  io.B_norm = B;
   io.drop_p = e.drop_p;
   io.drop_seed = e.drop_seed;
   io.step = (uint32_t)((unsigned long long)e.step & 0xFFFFFFFFull);
   for (int l = 0; l <= L; ++l) io.hh[l] = W + hh[l];
   for (int l = 0; l < L; ++l) io.sl[l] = W + sl[l];
-  if ((rs = launch_train_sweeps(e, io, B, st)) != RID_OK) return rs;
+  for (int r0 = 0; r0 < B; r0 += Bc) {
+    const int R = std::min(Bc, B - r0);
+    const bool acc = r0 > 0;
+    int ks, kchunk;
+    wgrad_split(K, tiles_max, R, &ks, &kchunk);
+    io.s = s + (size_t)r0 * n;
+    io.F = rho ? nullptr : F + (size_t)r0 * n;
+    io.rho = rho ? rho + (size_t)r0 * K * n : nullptr;
+    io.loss_rows = rho ? nullptr : W + lrows + r0;
+    io.row_base = r0;
+    if ((rs = launch_train_sweeps(e, io, R, st)) != RID_OK) return rs;
+    for (int l = L; l >= 1; --l) {
+      GemmArgs g{};
+      g.A = W + sl[l - 1]; g.sAb = 2LL * R * w[l]; g.sAm = 1; g.sAk = w[l];
+      g.Bm = W + hh[l - 1]; g.sBb = 2LL * R * w[l - 1]; g.sBk = w[l - 1]; g.sBn = 1;
+      g.C = W + part; g.sCb = (long long)w[l] * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
+      g.sCs = (long long)K * w[l] * w[l - 1];
+      g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * R; g.batch = K; g.ksplit = ks; g.kchunk = kchunk;
+      g.mode = EPI_STORE;
+      if ((rs = gemm(g, st)) != RID_OK) return rs;
+      hipLaunchKernelGGL(splitk_reduce_kernel,
+                         dim3(grid1d((long long)K * w[l] * w[l - 1])), dim3(256), 0, st,
+                         W + part, (long long)K * w[l] * w[l - 1], ks, w[l], w[l - 1], K,
+                         G, pm, (int)w_off[l - 1], acc ? 1 : 0);
+      RID_HIP(hipGetLastError());
+      if ((rs = colsum(W + sl[l - 1], 2LL * R * w[l], R, w[l], K, W + cpart, G, pm,
+                       (int)b_off[l - 1], acc, st)) != RID_OK)
+        return rs;
+    }
+    if ((rs = colsum(W + hh[L] + (long long)R * w[L], 2LL * R * w[L], R, w[L], K, W + cpart,
+                     G, pm, (int)wo_off, acc, st)) != RID_OK)
+      return rs;
+  }
   if (!rho) {
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(K), dim3(256), 0, st, W + lrows, B, loss);
     RID_HIP(hipGetLastError());
   }
-  for (int l = L; l >= 1; --l) {
-    GemmArgs g{};
-    g.A = W + sl[l - 1]; g.sAb = 2LL * B * w[l]; g.sAm = 1; g.sAk = w[l];
-    g.Bm = W + hh[l - 1]; g.sBb = 2LL * B * w[l - 1]; g.sBk = w[l - 1]; g.sBn = 1;
-    g.C = W + part; g.sCb = (long long)w[l] * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
-    g.sCs = (long long)K * w[l] * w[l - 1];
-    g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * B; g.batch = K; g.ksplit = ks; g.kchunk = kchunk;
-    g.mode = EPI_STORE;
-    if ((rs = gemm(g, st)) != RID_OK) return rs;
-    hipLaunchKernelGGL(splitk_reduce_kernel,
-                       dim3(grid1d((long long)K * w[l] * w[l - 1])), dim3(256), 0, st,
-                       W + part, (long long)K * w[l] * w[l - 1], ks, w[l], w[l - 1], K,
-                       G, pm, (int)w_off[l - 1]);
-    RID_HIP(hipGetLastError());
-    if ((rs = colsum(W + sl[l - 1], 2LL * B * w[l], B, w[l], K, W + cpart, G, pm,
-                     (int)b_off[l - 1], st)) != RID_OK)
-      return rs;
-  }
-  if ((rs = colsum(W + hh[L] + (long long)B * w[L], 2LL * B * w[L], B, w[L], K, W + cpart, G,
-                   pm, (int)wo_off, st)) != RID_OK)
-    return rs;
   hipLaunchKernelGGL(set_zero_kernel, dim3(1), dim3(64), 0, st, G, pm,
                      (int)(wo_off + w[L]), K);
   RID_HIP(hipGetLastError());
@@ -620,7 +669,9 @@ rid_status mf_grad_fused(rid_ensemble_impl& e, const float* s, const float* F,
 //   F given:   L = sum_k (1/B) sum_b |g_k(s_b) - F_b|^2      (loss[k] written)
 //   rho given: J = sum_k sum_b rho[b][k] . g_k(s_b)
 // into grad_out (or the workspace's gradient slot when grad_out is null).
-// Returns the gradient pointer through *grad_used.
+// Returns the gradient pointer through *grad_used.  Both forms hold at most
+// the ensemble's training budget of activations: a larger batch is taken in
+// chunks of rows whose weight-gradient contributions are added in chunk order.
 rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
                           const float* rho, int B, float* loss, float* grad_out,
                           float** grad_used, hipStream_t st, InputHvp* hvp) {
@@ -646,18 +697,13 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   }
   const long long wo_off = off;
   const long long pm = (long long)e.per_model;
-
-  // split of the 2B-row weight-gradient contraction
   int tiles_max = 0;
   for (int l = 0; l < L; ++l)
     tiles_max = std::max(tiles_max, ((w[l + 1] + BM - 1) / BM) * ((w[l] + BN - 1) / BN));
-  int ks = 1;
-  while (ks < 64 && (long long)K * tiles_max * ks < 1024 && 2LL * B / (ks * 2) >= 256) ks *= 2;
-  const int kchunk = round_up((2 * B + ks - 1) / ks, BK);
 
   if (!input_mode && train_fused_supported(e))
     return mf_grad_fused(e, s, F, rho, B, loss, grad_out, grad_used, st, w, w_off, b_off,
-                         wo_off, ks, kchunk);
+                         wo_off, tiles_max);
 
   // the general form: residual layers, dropout (training only), raw CVs
   const bool res = e.resnet;
@@ -666,31 +712,39 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   const uint8_t* raw = e.raw.empty() ? nullptr : e.d_raw;
   auto skip = [&](int l) { return res && l >= 2; };   // layer l (1-based) adds its input
 
-  // workspace (floats)
+  // rows per pass (input mode hands per-row results back: one pass)
+  long long per_row = (long long)K * (8 + (res ? 2 : 0)) * wmax;
+  for (int l = 0; l <= L; ++l) per_row += (long long)K * w[l] * (l > 0 ? 5 : 2);
+  const int Bc = input_mode ? B : chunk_rows(per_row, B, e.train_budget);
+  int ks_max, kc;
+  wgrad_split(K, tiles_max, Bc, &ks_max, &kc);
+
+  // workspace (floats), sized for Bc rows; a pass of R <= Bc rows uses the
+  // same regions with R-row strides
   std::vector<long long> hh(L + 1), zd(L + 1), tt(L + 1), dd(L + 1);
   long long tot = 0;
   for (int l = 0; l <= L; ++l) {
     hh[l] = tot;
-    tot += (long long)K * 2 * B * w[l];
+    tot += (long long)K * 2 * Bc * w[l];
   }
   for (int l = 1; l <= L; ++l) {
-    zd[l] = tot; tot += (long long)K * B * w[l];
-    tt[l] = tot; tot += (long long)K * B * w[l];
-    dd[l] = tot; tot += (long long)K * B * w[l];
+    zd[l] = tot; tot += (long long)K * Bc * w[l];
+    tt[l] = tot; tot += (long long)K * Bc * w[l];
+    dd[l] = tot; tot += (long long)K * Bc * w[l];
   }
-  const long long vA = tot; tot += (long long)K * B * wmax;
-  const long long vB = tot; tot += (long long)K * B * wmax;
-  const long long uA = tot; tot += res ? (long long)K * B * wmax : 0;
-  const long long uB = tot; tot += res ? (long long)K * B * wmax : 0;
-  const long long lamA = tot; tot += (long long)K * 2 * B * wmax;
-  const long long lamB = tot; tot += (long long)K * 2 * B * wmax;
-  const long long sbuf = tot; tot += (long long)K * 2 * B * wmax;
+  const long long vA = tot; tot += (long long)K * Bc * wmax;
+  const long long vB = tot; tot += (long long)K * Bc * wmax;
+  const long long uA = tot; tot += res ? (long long)K * Bc * wmax : 0;
+  const long long uB = tot; tot += res ? (long long)K * Bc * wmax : 0;
+  const long long lamA = tot; tot += (long long)K * 2 * Bc * wmax;
+  const long long lamB = tot; tot += (long long)K * 2 * Bc * wmax;
+  const long long sbuf = tot; tot += (long long)K * 2 * Bc * wmax;
   long long part_slab = 0;
   for (int l = 0; l < L; ++l) part_slab = std::max(part_slab, (long long)K * w[l + 1] * w[l]);
-  const long long part = tot; tot += part_slab * ks;
+  const long long part = tot; tot += part_slab * ks_max;
   const long long grad = tot; tot += (long long)e.n_params;
   const long long lrows = tot; tot += (long long)K * B;
-  const long long cpart = tot; tot += (long long)((B + kColRows - 1) / kColRows) * K * wmax;
+  const long long cpart = tot; tot += (long long)((Bc + kColRows - 1) / kColRows) * K * wmax;
   rid_status rs = e.ws_train.ensure(sizeof(float) * tot);
   if (rs != RID_OK) return rs;
   float* W = e.ws_train.as<float>();
@@ -700,144 +754,154 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   ProfScope ps(kProfTrain, st);
   const uint32_t step32 = (uint32_t)((unsigned long long)e.step & 0xFFFFFFFFull);
 
-  auto slab = [&](int l) { return 2LL * B * w[l]; };
-  // ---- primal forward: t_l = tanh(W_l h_{l-1} + b_l), then h_l and d_l ----
-  hipLaunchKernelGGL(train_embed_kernel, dim3(grid1d((long long)K * B * n)), dim3(256), 0, st,
-                     s, B, n, K, raw, W + hh[0], slab(0));
-  RID_HIP(hipGetLastError());
-  for (int l = 1; l <= L; ++l) {
-    GemmArgs g{};
-    g.A = W + hh[l - 1]; g.sAb = slab(l - 1); g.sAm = w[l - 1]; g.sAk = 1;
-    g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = 1; g.sBn = w[l - 1];
-    g.C = W + tt[l]; g.sCb = (long long)B * w[l]; g.sCm = w[l]; g.sCn = 1;
-    g.bias = P + b_off[l - 1]; g.sBiasb = pm;
-    g.M = B; g.N = w[l]; g.Kc = w[l - 1]; g.batch = K; g.mode = EPI_BIAS_TANH;
-    if ((rs = gemm(g, st)) != RID_OK) return rs;
-    hipLaunchKernelGGL(act_kernel, dim3(grid1d((long long)K * B * ((w[l] + 3) / 4))), dim3(256),
-                       0, st, W + tt[l], l, w[l], B, K, drop_p, drop_inv, e.drop_seed, step32,
-                       skip(l) ? W + hh[l - 1] : nullptr, slab(l - 1), W + hh[l], slab(l),
-                       W + dd[l]);
+  for (int r0 = 0; r0 < B; r0 += Bc) {
+    const int R = std::min(Bc, B - r0);
+    const bool acc = r0 > 0;
+    int ks, kchunk;
+    wgrad_split(K, tiles_max, R, &ks, &kchunk);
+    const float* sR = s + (size_t)r0 * n;
+    const float* FR = rho ? nullptr : F + (size_t)r0 * n;
+    const float* rhoR = rho ? rho + (size_t)r0 * K * n : nullptr;
+    auto slab = [&](int l) { return 2LL * R * w[l]; };
+    // ---- primal forward: t_l = tanh(W_l h_{l-1} + b_l), then h_l and d_l ----
+    hipLaunchKernelGGL(train_embed_kernel, dim3(grid1d((long long)K * R * n)), dim3(256), 0,
+                       st, sR, R, n, K, raw, W + hh[0], slab(0));
     RID_HIP(hipGetLastError());
-  }
-  // ---- primal backward to u0: v_l = u_l d_l, u_{l-1} = W_l^T v_l (+ u_l) ----
-  hipLaunchKernelGGL(vlast_kernel, dim3(grid1d((long long)K * B * w[L])), dim3(256), 0, st,
-                     W + dd[L], P, pm, (int)wo_off, w[L], B, K, W + vA);
-  RID_HIP(hipGetLastError());
-  long long uin = uA, uout = uB;
-  if (res) {   // u_L = w_o
-    hipLaunchKernelGGL(top_kernel, dim3(grid1d((long long)K * B * w[L])), dim3(256), 0, st, P,
-                       pm, (int)wo_off, w[L], B, K, B, 0, W + uin);
-    RID_HIP(hipGetLastError());
-  }
-  long long vin = vA, vout = vB;
-  for (int l = L; l >= 1; --l) {
-    GemmArgs g{};
-    g.A = W + vin; g.sAb = (long long)B * w[l]; g.sAm = w[l]; g.sAk = 1;
-    g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = w[l - 1]; g.sBn = 1;
-    g.sCb = (long long)B * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
-    g.M = B; g.N = w[l - 1]; g.Kc = w[l]; g.batch = K;
-    if (l > 1) {
-      // v_{l-1} = (W_l^T v_l (+ u_l)) d_{l-1}; with a skip u_{l-1} is kept
-      g.mode = EPI_GEN;
-      g.C = skip(l) ? W + uout : nullptr;
-      g.add = skip(l) ? W + uin : nullptr; g.sAddb = (long long)B * w[l];
-      g.C2 = W + vout; g.sC2b = (long long)B * w[l - 1];
-      g.mul = W + dd[l - 1]; g.sMulb = (long long)B * w[l - 1];
-    } else {
-      g.mode = EPI_STORE;
-      g.C = W + vout;
+    for (int l = 1; l <= L; ++l) {
+      GemmArgs g{};
+      g.A = W + hh[l - 1]; g.sAb = slab(l - 1); g.sAm = w[l - 1]; g.sAk = 1;
+      g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = 1; g.sBn = w[l - 1];
+      g.C = W + tt[l]; g.sCb = (long long)R * w[l]; g.sCm = w[l]; g.sCn = 1;
+      g.bias = P + b_off[l - 1]; g.sBiasb = pm;
+      g.M = R; g.N = w[l]; g.Kc = w[l - 1]; g.batch = K; g.mode = EPI_BIAS_TANH;
+      if ((rs = gemm(g, st)) != RID_OK) return rs;
+      hipLaunchKernelGGL(act_kernel, dim3(grid1d((long long)K * R * ((w[l] + 3) / 4))),
+                         dim3(256), 0, st, W + tt[l], l, w[l], R, K, r0, drop_p, drop_inv,
+                         e.drop_seed, step32, skip(l) ? W + hh[l - 1] : nullptr, slab(l - 1),
+                         W + hh[l], slab(l), W + dd[l]);
+      RID_HIP(hipGetLastError());
     }
-    if ((rs = gemm(g, st)) != RID_OK) return rs;
-    std::swap(vin, vout);
-    if (skip(l)) std::swap(uin, uout);
+    // ---- primal backward to u0: v_l = u_l d_l, u_{l-1} = W_l^T v_l (+ u_l) ----
+    hipLaunchKernelGGL(vlast_kernel, dim3(grid1d((long long)K * R * w[L])), dim3(256), 0, st,
+                       W + dd[L], P, pm, (int)wo_off, w[L], R, K, W + vA);
+    RID_HIP(hipGetLastError());
+    long long uin = uA, uout = uB;
+    if (res) {   // u_L = w_o
+      hipLaunchKernelGGL(top_kernel, dim3(grid1d((long long)K * R * w[L])), dim3(256), 0, st,
+                         P, pm, (int)wo_off, w[L], R, K, R, 0, W + uin);
+      RID_HIP(hipGetLastError());
+    }
+    long long vin = vA, vout = vB;
+    for (int l = L; l >= 1; --l) {
+      GemmArgs g{};
+      g.A = W + vin; g.sAb = (long long)R * w[l]; g.sAm = w[l]; g.sAk = 1;
+      g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = w[l - 1]; g.sBn = 1;
+      g.sCb = (long long)R * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
+      g.M = R; g.N = w[l - 1]; g.Kc = w[l]; g.batch = K;
+      if (l > 1) {
+        // v_{l-1} = (W_l^T v_l (+ u_l)) d_{l-1}; with a skip u_{l-1} is kept
+        g.mode = EPI_GEN;
+        g.C = skip(l) ? W + uout : nullptr;
+        g.add = skip(l) ? W + uin : nullptr; g.sAddb = (long long)R * w[l];
+        g.C2 = W + vout; g.sC2b = (long long)R * w[l - 1];
+        g.mul = W + dd[l - 1]; g.sMulb = (long long)R * w[l - 1];
+      } else {
+        g.mode = EPI_STORE;
+        g.C = W + vout;
+      }
+      if ((rs = gemm(g, st)) != RID_OK) return rs;
+      std::swap(vin, vout);
+      if (skip(l)) std::swap(uin, uout);
+    }
+    // vin now holds u0 [K][R][2n]
+    hipLaunchKernelGGL(residual_kernel,
+                       dim3((unsigned)(((long long)K * R + kResWaves - 1) / kResWaves)),
+                       dim3(kResWaves * 64), 0, st,
+                       sR, FR, rhoR, W + vin, R, B, n, K, raw, W + hh[0], slab(0),
+                       rho ? nullptr : W + lrows + r0, (long long)B);
+    RID_HIP(hipGetLastError());
+    // ---- tangent forward: zd_l = W_l hd_{l-1}, hd_l = d_l zd_l (+ hd_{l-1}) ----
+    for (int l = 1; l <= L; ++l) {
+      GemmArgs g{};
+      g.A = W + hh[l - 1] + (long long)R * w[l - 1]; g.sAb = slab(l - 1); g.sAm = w[l - 1];
+      g.sAk = 1;
+      g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = 1; g.sBn = w[l - 1];
+      g.C = W + zd[l]; g.sCb = (long long)R * w[l]; g.sCm = w[l]; g.sCn = 1;
+      g.C2 = W + hh[l] + (long long)R * w[l]; g.sC2b = slab(l);
+      g.mul = W + dd[l]; g.sMulb = (long long)R * w[l];
+      if (skip(l)) {
+        g.add2 = W + hh[l - 1] + (long long)R * w[l - 1];
+        g.sAdd2b = slab(l - 1);
+      }
+      g.M = R; g.N = w[l]; g.Kc = w[l - 1]; g.batch = K; g.mode = EPI_GEN;
+      if ((rs = gemm(g, st)) != RID_OK) return rs;
+    }
+    // ---- adjoint sweep with weight gradients (or down to the input) ----
+    long long lin = lamA, lout = lamB;
+    // top: lam_h_L = 0, lam_hd_L = w_o (stacked rows [0, R) and [R, 2R))
+    hipLaunchKernelGGL(top_kernel, dim3(grid1d((long long)K * 2 * R * w[L])), dim3(256), 0, st,
+                       P, pm, (int)wo_off, w[L], R, K, 2 * R, R, W + lin);
+    RID_HIP(hipGetLastError());
+    for (int l = L; l >= 1; --l) {
+      hipLaunchKernelGGL(adjoint_kernel, dim3(grid1d((long long)K * R * w[l])), dim3(256), 0,
+                         st, W + tt[l], W + dd[l], W + zd[l], W + lin, 2LL * R * w[l], w[l], R,
+                         K, W + sbuf, 2LL * R * w[l]);
+      RID_HIP(hipGetLastError());
+      // dW_l = S^T [h_{l-1}; hd_{l-1}]  (contraction over 2R rows, split)
+      if (!input_mode) {
+        GemmArgs g{};
+        g.A = W + sbuf; g.sAb = 2LL * R * w[l]; g.sAm = 1; g.sAk = w[l];
+        g.Bm = W + hh[l - 1]; g.sBb = slab(l - 1); g.sBk = w[l - 1]; g.sBn = 1;
+        g.C = W + part; g.sCb = (long long)w[l] * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
+        g.sCs = (long long)K * w[l] * w[l - 1];
+        g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * R; g.batch = K; g.ksplit = ks;
+        g.kchunk = kchunk;
+        g.mode = EPI_STORE;
+        if ((rs = gemm(g, st)) != RID_OK) return rs;
+        hipLaunchKernelGGL(splitk_reduce_kernel,
+                           dim3(grid1d((long long)K * w[l] * w[l - 1])), dim3(256), 0, st,
+                           W + part, (long long)K * w[l] * w[l - 1], ks, w[l], w[l - 1], K,
+                           G, pm, (int)w_off[l - 1], acc ? 1 : 0);
+        RID_HIP(hipGetLastError());
+        // db_l = sum_b lam_z
+        if ((rs = colsum(W + sbuf, 2LL * R * w[l], R, w[l], K, W + cpart, G, pm,
+                         (int)b_off[l - 1], acc, st)) != RID_OK)
+          return rs;
+      }
+      if (l > 1 || input_mode) {
+        // [lam_h ; lam_hd]_{l-1} = [lam_z ; lam_zd] W_l (+ [lam_h ; lam_hd]_l)
+        GemmArgs g{};
+        g.A = W + sbuf; g.sAb = 2LL * R * w[l]; g.sAm = w[l]; g.sAk = 1;
+        g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = w[l - 1]; g.sBn = 1;
+        g.C = W + lout; g.sCb = 2LL * R * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
+        g.M = 2 * R; g.N = w[l - 1]; g.Kc = w[l]; g.batch = K;
+        if (skip(l)) {
+          g.mode = EPI_GEN;
+          g.add = W + lin; g.sAddb = 2LL * R * w[l];
+        } else {
+          g.mode = EPI_STORE;
+        }
+        if ((rs = gemm(g, st)) != RID_OK) return rs;
+        std::swap(lin, lout);
+      }
+    }
+    if (input_mode) {
+      // lin: [lam_h0 ; lam_hd0] per member (rows [0, B): d J / dx); vin: u0
+      hvp->lam_x = W + lin;
+      hvp->u0 = W + vin;
+      hvp->slab_lam = 2LL * B * X;
+      return RID_OK;
+    }
+    // dw_o = sum_b hd_L
+    if ((rs = colsum(W + hh[L] + (long long)R * w[L], slab(L), R, w[L], K, W + cpart, G, pm,
+                     (int)wo_off, acc, st)) != RID_OK)
+      return rs;
   }
-  // vin now holds u0 [K][B][2n]
-  hipLaunchKernelGGL(residual_kernel,
-                     dim3((unsigned)(((long long)K * B + kResWaves - 1) / kResWaves)),
-                     dim3(kResWaves * 64), 0, st,
-                     s, F, rho, W + vin, B, n, K, raw, W + hh[0], slab(0),
-                     rho ? nullptr : W + lrows);
-  RID_HIP(hipGetLastError());
   if (!rho) {
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(K), dim3(256), 0, st, W + lrows, B, loss);
     RID_HIP(hipGetLastError());
   }
-  // ---- tangent forward: zd_l = W_l hd_{l-1}, hd_l = d_l zd_l (+ hd_{l-1}) ----
-  for (int l = 1; l <= L; ++l) {
-    GemmArgs g{};
-    g.A = W + hh[l - 1] + (long long)B * w[l - 1]; g.sAb = slab(l - 1); g.sAm = w[l - 1]; g.sAk = 1;
-    g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = 1; g.sBn = w[l - 1];
-    g.C = W + zd[l]; g.sCb = (long long)B * w[l]; g.sCm = w[l]; g.sCn = 1;
-    g.C2 = W + hh[l] + (long long)B * w[l]; g.sC2b = slab(l);
-    g.mul = W + dd[l]; g.sMulb = (long long)B * w[l];
-    if (skip(l)) {
-      g.add2 = W + hh[l - 1] + (long long)B * w[l - 1];
-      g.sAdd2b = slab(l - 1);
-    }
-    g.M = B; g.N = w[l]; g.Kc = w[l - 1]; g.batch = K; g.mode = EPI_GEN;
-    if ((rs = gemm(g, st)) != RID_OK) return rs;
-  }
-  // ---- adjoint sweep with weight gradients (or down to the input) ----
-  long long lin = lamA, lout = lamB;
-  // top: lam_h_L = 0, lam_hd_L = w_o (stacked rows [0, B) and [B, 2B))
-  hipLaunchKernelGGL(top_kernel, dim3(grid1d((long long)K * 2 * B * w[L])), dim3(256), 0, st, P,
-                     pm, (int)wo_off, w[L], B, K, 2 * B, B, W + lin);
-  RID_HIP(hipGetLastError());
-  for (int l = L; l >= 1; --l) {
-    hipLaunchKernelGGL(adjoint_kernel, dim3(grid1d((long long)K * B * w[l])), dim3(256), 0, st,
-                       W + tt[l], W + dd[l], W + zd[l], W + lin, 2LL * B * w[l], w[l], B, K,
-                       W + sbuf, 2LL * B * w[l]);
-    RID_HIP(hipGetLastError());
-    // dW_l = S^T [h_{l-1}; hd_{l-1}]  (contraction over 2B rows, split)
-    if (!input_mode) {
-      GemmArgs g{};
-      g.A = W + sbuf; g.sAb = 2LL * B * w[l]; g.sAm = 1; g.sAk = w[l];
-      g.Bm = W + hh[l - 1]; g.sBb = slab(l - 1); g.sBk = w[l - 1]; g.sBn = 1;
-      g.C = W + part; g.sCb = (long long)w[l] * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
-      g.sCs = (long long)K * w[l] * w[l - 1];
-      g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * B; g.batch = K; g.ksplit = ks; g.kchunk = kchunk;
-      g.mode = EPI_STORE;
-      if ((rs = gemm(g, st)) != RID_OK) return rs;
-      hipLaunchKernelGGL(splitk_reduce_kernel,
-                         dim3(grid1d((long long)K * w[l] * w[l - 1])), dim3(256), 0, st,
-                         W + part, (long long)K * w[l] * w[l - 1], ks, w[l], w[l - 1], K,
-                         G, pm, (int)w_off[l - 1]);
-      RID_HIP(hipGetLastError());
-    }
-    // db_l = sum_b lam_z
-    if (!input_mode &&
-        (rs = colsum(W + sbuf, 2LL * B * w[l], B, w[l], K, W + cpart, G, pm,
-                     (int)b_off[l - 1], st)) != RID_OK)
-      return rs;
-    if (l > 1 || input_mode) {
-      // [lam_h ; lam_hd]_{l-1} = [lam_z ; lam_zd] W_l (+ [lam_h ; lam_hd]_l)
-      GemmArgs g{};
-      g.A = W + sbuf; g.sAb = 2LL * B * w[l]; g.sAm = w[l]; g.sAk = 1;
-      g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = w[l - 1]; g.sBn = 1;
-      g.C = W + lout; g.sCb = 2LL * B * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
-      g.M = 2 * B; g.N = w[l - 1]; g.Kc = w[l]; g.batch = K;
-      if (skip(l)) {
-        g.mode = EPI_GEN;
-        g.add = W + lin; g.sAddb = 2LL * B * w[l];
-      } else {
-        g.mode = EPI_STORE;
-      }
-      if ((rs = gemm(g, st)) != RID_OK) return rs;
-      std::swap(lin, lout);
-    }
-  }
-  if (input_mode) {
-    // lin: [lam_h0 ; lam_hd0] per member (rows [0, B): d J / dx); vin: u0
-    hvp->lam_x = W + lin;
-    hvp->u0 = W + vin;
-    hvp->slab_lam = 2LL * B * X;
-    return RID_OK;
-  }
-  // dw_o = sum_b hd_L ; db_o = 0
-  if ((rs = colsum(W + hh[L] + (long long)B * w[L], slab(L), B, w[L], K, W + cpart, G, pm,
-                   (int)wo_off, st)) != RID_OK)
-    return rs;
-  // the output bias never reaches grad_s A: its gradient entry is zero
+  // db_o = 0: the output bias never reaches grad_s A
   hipLaunchKernelGGL(set_zero_kernel, dim3(1), dim3(64), 0, st, G, pm,
                      (int)(wo_off + w[L]), K);
   RID_HIP(hipGetLastError());

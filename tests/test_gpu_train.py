@@ -354,3 +354,72 @@ def test_masked_training_parity(torch, rid):
         assert gerr <= GRAD_TOL
     _, unmasked = _grad_ref_general(params, n, widths, K, s, F)
     assert _per_member_err(unmasked, grad_ref) > 100 * GRAD_TOL
+
+
+def test_large_batch_runs_in_chunks_under_the_budget(torch, rid):
+    """Batch 16384 on the training shape (38 CVs, 4 x [256 x 4]): one pass
+    over the whole batch would hold ~1.1 GB of activations, above the
+    default 512 MiB budget, so the step runs in three chunks of rows.  Loss
+    and gradient match the oracle over the whole batch, the device memory
+    the call takes stays under the budget, and a second call is bitwise
+    equal to the first."""
+    n, widths, K, B = 38, [256] * 4, 4, 16384
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 1000, bias_std=0.1)
+    s, F, _ = ridgen.mf_training_set(B, n)
+    E = rid.Ensemble(n, widths, K, params)
+    S_, F_ = _dev(torch, s), _dev(torch, F)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    loss, grad = rid.mf_loss_grad(E, S_, F_)
+    torch.cuda.synchronize()
+    # the training workspace, plus torch's block for the two outputs
+    taken = free0 - torch.cuda.mem_get_info()[0]
+    print(f"B={B}: device memory taken by the call {taken / 2**20:.0f} MiB", flush=True)
+    assert taken <= (512 << 20)
+    l1, g1 = loss.cpu().numpy(), grad.cpu().numpy()
+    loss_ref, grad_ref = _grad_ref(params, n, widths, K, s, F)
+    lerr = np.max(np.abs(l1 - loss_ref) / loss_ref)
+    gerr = _per_member_err(g1, grad_ref)
+    print(f"B={B} chunked: loss rel err {lerr:.2e}, grad err {gerr:.2e}", flush=True)
+    assert lerr <= 1e-5 and gerr <= GRAD_TOL
+    l2, g2 = rid.mf_loss_grad(E, S_, F_)
+    torch.cuda.synchronize()
+    assert np.array_equal(l2.cpu().numpy(), l1) and np.array_equal(g2.cpu().numpy(), g1)
+
+
+# (n, widths, K, B, dropout rate, resnet): the fused sweeps, and the general
+# sweeps with residual layers and dropout, on a ragged batch
+CHUNK_CASES = [(38, [256] * 4, 4, 1000, 0.0, False), (38, [256] * 4, 4, 1000, 0.2, False),
+               (5, [300, 40], 2, 333, 0.1, False), (6, [96] * 3, 3, 500, 0.25, True)]
+
+
+@pytest.mark.parametrize("n,widths,K,B,rate,resnet", CHUNK_CASES)
+def test_chunked_passes_equal_one_pass(torch, rid, n, widths, K, B, rate, resnet):
+    """A budget too small for any pass forces 64-row chunks (the last one
+    ragged): the loss equals the one-pass loss, the gradient differs from it
+    only by the order of the chunk sums, the dropout masks stay those of the
+    whole batch (the oracle's), and so does the upstream-gradient form."""
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 51, bias_std=0.1)
+    s, F, _ = ridgen.mf_training_set(B, n)
+    rho = ridgen.f32(np.random.default_rng(52).normal(size=(B, K, n)))
+    S_, F_, R_ = _dev(torch, s), _dev(torch, F), _dev(torch, rho)
+    out = []
+    for budget in (0, 1):
+        E = rid.Ensemble(n, widths, K, params)
+        if resnet:
+            E.set_resnet(True)
+        E.set_dropout(rate, DROP_SEED)
+        E.set_train_budget(budget)
+        loss, grad = rid.mf_loss_grad(E, S_, F_)
+        vjp = rid.mf_grad(E, S_, R_)
+        torch.cuda.synchronize()
+        out.append((loss.cpu().numpy(), grad.cpu().numpy(), vjp.cpu().numpy()))
+    (l1, g1, v1), (lc, gc, vc) = out
+    assert np.max(np.abs(lc - l1) / l1) <= 1e-6
+    assert _per_member_err(gc, g1.astype(np.float64).reshape(K, -1)) <= 1e-5
+    assert _per_member_err(vc, v1.astype(np.float64).reshape(K, -1)) <= 1e-5
+    loss_ref, grad_ref = _grad_ref_general(params, n, widths, K, s, F, rate, 0, resnet)
+    gerr = _per_member_err(gc, grad_ref)
+    print(f"chunked {widths} rate {rate} resnet {resnet}: loss rel err "
+          f"{np.max(np.abs(lc - loss_ref) / loss_ref):.2e}, grad err {gerr:.2e}", flush=True)
+    assert np.max(np.abs(lc - loss_ref) / loss_ref) <= 1e-5 and gerr <= GRAD_TOL
