@@ -473,6 +473,24 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
   auto wsrc = [&](unsigned off) {
     return WSrc{rsrc, (int)off + jt0 * kFragBytes, JT * kFragBytes};
   };
+  // plain input: the first column batch of the tile's encoding is loaded
+  // before anything else, so its loads return ahead of the weight and bias
+  // loads queued behind them (rows of the tile go to the waves in turn; a
+  // wave's lanes cover a row in float2 columns)
+  constexpr int RW = FROM_POS ? 1 : R / NW;   // rows per wave (R = 16 RT)
+  static_assert(FROM_POS || RW * NW == R, "rows per wave");
+  float2 xv[RW];
+  auto load_x = [&](int cb) {
+    const int col = cb + lane;                // float2 column
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const int row = row0 + wave * RW + j;
+      xv[j] = (col < p.n && row < p.B)
+                  ? *reinterpret_cast<const float2*>(p.x + (size_t)row * X2 + 2 * col)
+                  : make_float2(0.f, 0.f);
+    }
+  };
+  if constexpr (!FROM_POS) load_x(0);
   WRing<PD, CT> wr;                  // first layer
   WRing<PDH, CH> wh;                 // hidden layers (passes of CH tiles)
   ring_preload<PD, CT>(wr, wsrc(p.fwd_off[0]), XP / KF, lane);
@@ -550,28 +568,18 @@ __global__ __launch_bounds__(NW * 64) void mlp_kernel(MlpArgs p) {
     for (int i = wave; i < R; i += NW)
       for (int c = X2 + lane; c < XP; c += 64) act1[i * AS + c] = P1::from_float(0.f);
   } else {
-    // rows of the tile go to the waves in turn; a wave's lanes cover the row
-    // in float2 columns (X2 is even), padding columns [X2, XP) get zeros.
-    // All of a wave's loads are issued before any is used.
-    constexpr int RW = R / NW;                // rows per wave (R = 16 RT)
-    static_assert(RW * NW == R, "rows per wave");
+    // the column batches of the tile (the first one is already in xv);
+    // padding columns [X2, XP) get zeros (X2 is even)
     const int h2 = X2 / 2, hp = XP / 2;
     for (int cb = 0; cb < hp; cb += 64) {
       const int col = cb + lane;              // float2 column
-      float2 v[RW];
-#pragma unroll
-      for (int j = 0; j < RW; ++j) {
-        const int row = row0 + wave * RW + j;
-        v[j] = (col < h2 && row < p.B)
-                   ? *reinterpret_cast<const float2*>(p.x + (size_t)row * X2 + 2 * col)
-                   : make_float2(0.f, 0.f);
-      }
+      if (cb > 0) load_x(cb);
       if (col < hp) {
 #pragma unroll
         for (int j = 0; j < RW; ++j) {
           const int i = wave * RW + j;
-          Pack2<T1>::store(act1 + i * AS + 2 * col, v[j].x, v[j].y);
-          if (col < h2) *reinterpret_cast<float2*>(xs + i * X2 + 2 * col) = v[j];
+          Pack2<T1>::store(act1 + i * AS + 2 * col, xv[j].x, xv[j].y);
+          if (col < h2) *reinterpret_cast<float2*>(xs + i * X2 + 2 * col) = xv[j];
         }
       }
     }
