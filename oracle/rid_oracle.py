@@ -972,28 +972,36 @@ def frame_deviation(models, s, mask=None):
     return model_deviation(g)[1]
 
 
-def cv_distance_sq_f32(a, b, mask=None):
+def cv_distance_sq_f32(a, b, mask=None, weights=None):
     """Squared periodic distance between CV vectors a, b [..., n] (angles in
     [-pi, pi]) in the FP32 arithmetic the clustering decides in: per CV the
     FP32 difference wrapped to (-pi, pi] with FP32 constants, then the
     squares summed in CV order, every product and sum rounded to FP32 (no
     fused multiply-add).  CVs whose angular-mask entry is 0 (distances) are
-    not periodic: their difference is not wrapped."""
+    not periodic: their difference is not wrapped.
+    weights: the per-CV clustering weights of the CV settings ("weights";
+    reading: a weighted Euclidean metric, d^2 = sum_i w_i wrap(a_i - b_i)^2,
+    each square multiplied by its weight in FP32 before it is added); None
+    means every weight is 1."""
     a = np.asarray(a, dtype=np.float32)
     b = np.asarray(b, dtype=np.float32)
     pi = np.float32(math.pi)
     two_pi = np.float32(2.0 * math.pi)
+    w = None if weights is None else np.asarray(weights, dtype=np.float32)
     acc = np.zeros(np.broadcast(a[..., 0], b[..., 0]).shape, dtype=np.float32)
     for i in range(a.shape[-1]):
         d = (a[..., i] - b[..., i]).astype(np.float32)
         if mask is None or mask[i]:
             d = np.where(d > pi, (d - two_pi).astype(np.float32), d)
             d = np.where(d <= -pi, (d + two_pi).astype(np.float32), d)
-        acc = (acc + (d * d).astype(np.float32)).astype(np.float32)
+        sq = (d * d).astype(np.float32)
+        if w is not None:
+            sq = (sq * w[i]).astype(np.float32)
+        acc = (acc + sq).astype(np.float32)
     return acc
 
 
-def leader_cluster(s, threshold, keep=None, max_clusters=None, mask=None):
+def leader_cluster(s, threshold, keep=None, max_clusters=None, mask=None, weights=None):
     """Threshold clustering of CV frames.  Reading (the paper names a cluster
     threshold and a window for the cluster count, not the algorithm): frames
     are taken in order; a kept frame joins the first cluster, in founding
@@ -1015,7 +1023,7 @@ def leader_cluster(s, threshold, keep=None, max_clusters=None, mask=None):
         if keep is not None and not keep[f]:
             continue
         if leaders:
-            hit = np.nonzero(cv_distance_sq_f32(s[leaders], s[f][None, :], mask) <= t2)[0]
+            hit = np.nonzero(cv_distance_sq_f32(s[leaders], s[f][None, :], mask, weights) <= t2)[0]
             if hit.size:
                 labels[f] = hit[0]
                 continue
@@ -1032,14 +1040,14 @@ THRESHOLD_FACTOR = np.float32(1.1)
 
 
 def adapt_threshold(s, threshold, lower, upper, keep=None, max_clusters=None, max_iter=100,
-                    mask=None):
+                    mask=None, weights=None):
     """Reading of the threshold adjustment (first iteration only; the rule is
     not printed): while the cluster count is above `upper` the threshold is
     multiplied by 1.1, while below `lower` divided by 1.1 (FP32), at most
     max_iter adjustments.  Returns (threshold, leader_cluster result)."""
     t = np.float32(threshold)
     for it in range(max_iter + 1):
-        res = leader_cluster(s, t, keep, max_clusters, mask)
+        res = leader_cluster(s, t, keep, max_clusters, mask, weights)
         n = res[2]
         if lower <= n <= upper or it == max_iter:
             return t, res
@@ -1048,7 +1056,7 @@ def adapt_threshold(s, threshold, lower, upper, keep=None, max_clusters=None, ma
 
 
 def select_frames(models, s, eps0, threshold, lower, upper, max_selection, adapt=True,
-                  max_iter=100, mask=None):
+                  max_iter=100, mask=None, weights=None):
     """Selection: the frames whose model deviation reaches the lower trust
     level (eps >= eps0, reading: "high model deviation" relative to the
     trust level) are clustered, the threshold adapted into [lower, upper]
@@ -1060,9 +1068,29 @@ def select_frames(models, s, eps0, threshold, lower, upper, max_selection, adapt
     cap = max(upper, max_selection) + 1
     if adapt:
         t, (labels, leaders, n) = adapt_threshold(s, threshold, lower, upper, keep, cap, max_iter,
-                                                  mask)
+                                                  mask, weights)
     else:
         t = np.float32(threshold)
-        labels, leaders, n = leader_cluster(s, t, keep, cap, mask)
+        labels, leaders, n = leader_cluster(s, t, keep, cap, mask, weights)
     return dict(eps=eps, keep=keep, threshold=t, labels=labels, leaders=leaders,
                 n_clusters=n, selected=list(leaders[:max_selection]))
+
+
+def adjust_trust_levels(n_clusters, numb_cluster_threshold, trust_lvl_1, trust_lvl_2, scale):
+    """Trust levels for the next iteration ("Selection phase",
+    numb_cluster_threshold).  The paper states only that the trust levels
+    are adjusted when the number of clusters found in the current
+    iteration's exploration frames is below numb_cluster_threshold, and
+    (troubleshooting table) that raising them encourages exploration; the
+    rule itself is in a cited paper.  Reading: below the threshold both
+    levels are multiplied by `scale` (> 1, the caller's choice), keeping
+    their ratio; otherwise they are returned unchanged.  FP32 products, as
+    the library computes them."""
+    if scale <= 1.0 or not math.isfinite(scale):
+        raise ValueError("scale must be finite and above 1")
+    if not (0.0 <= trust_lvl_1 < trust_lvl_2):
+        raise ValueError("trust levels must satisfy 0 <= lvl_1 < lvl_2")
+    if n_clusters < numb_cluster_threshold:
+        return (float(np.float32(trust_lvl_1) * np.float32(scale)),
+                float(np.float32(trust_lvl_2) * np.float32(scale)))
+    return float(np.float32(trust_lvl_1)), float(np.float32(trust_lvl_2))

@@ -121,3 +121,93 @@ def test_selection_filters_and_caps():
     same = [models[0]] * 3
     assert np.all(O.frame_deviation(same, s) == 0.0)
     assert O.select_frames(same, s, 1e-9, 0.5, 3, 6, 4)["selected"] == []
+
+
+# --- per-CV clustering weights (CV settings "weights") ---------------------
+
+def test_unit_weights_are_the_unweighted_metric_bit_for_bit():
+    rng = np.random.default_rng(11)
+    a = rng.uniform(-math.pi, math.pi, size=(300, 38)).astype(np.float32)
+    b = rng.uniform(-math.pi, math.pi, size=(300, 38)).astype(np.float32)
+    assert np.array_equal(O.cv_distance_sq_f32(a, b, weights=np.ones(38)),
+                          O.cv_distance_sq_f32(a, b))
+
+
+def test_zero_weight_removes_the_cv_from_the_metric():
+    # a zero weight contributes an exact 0 to the FP32 sum, so the distance
+    # equals the distance over the remaining CVs (in the same order)
+    rng = np.random.default_rng(12)
+    a = rng.uniform(-math.pi, math.pi, size=(200, 9)).astype(np.float32)
+    b = rng.uniform(-math.pi, math.pi, size=(200, 9)).astype(np.float32)
+    w = np.ones(9)
+    w[[2, 7]] = 0.0
+    keep = [i for i in range(9) if w[i] != 0]
+    assert np.array_equal(O.cv_distance_sq_f32(a, b, weights=w),
+                          O.cv_distance_sq_f32(a[:, keep], b[:, keep]))
+
+
+def test_weight_four_on_a_raw_cv_is_the_cv_scaled_by_two():
+    # raw (non-angular) CVs are not wrapped, and multiplying a difference by
+    # 2 or its FP32 square by 4 are both exact: the weighted metric equals
+    # the unweighted metric on the table with that column doubled
+    rng = np.random.default_rng(13)
+    a = rng.uniform(0.3, 1.5, size=(200, 5)).astype(np.float32)
+    b = rng.uniform(0.3, 1.5, size=(200, 5)).astype(np.float32)
+    mask = np.array([1, 0, 1, 0, 1], dtype=np.uint8)
+    w = np.array([1, 4, 1, 1, 1], dtype=np.float32)
+    a2, b2 = a.copy(), b.copy()
+    a2[:, 1] *= 2
+    b2[:, 1] *= 2
+    assert np.array_equal(O.cv_distance_sq_f32(a, b, mask, w), O.cv_distance_sq_f32(a2, b2, mask))
+
+
+def test_weighted_clustering_against_brute_force():
+    # every label is the first leader within the threshold under the
+    # weighted metric, every leader is farther than the threshold from all
+    # earlier leaders, and a heavy weight on one CV splits clusters the
+    # unweighted metric merges
+    rng = np.random.default_rng(14)
+    centers = rng.uniform(-math.pi, math.pi, size=(6, 4))
+    s = (centers[rng.integers(0, 6, 400)] + 0.15 * rng.standard_normal((400, 4)))
+    s = ((s + math.pi) % (2 * math.pi) - math.pi).astype(np.float32)
+    w = np.array([1.0, 0.25, 9.0, 1.0], dtype=np.float32)
+    t = np.float32(0.9)
+    labels, leaders, n = O.leader_cluster(s, t, weights=w)
+    t2 = np.float32(t * t)
+    for f in range(len(s)):
+        d2 = [float(O.cv_distance_sq_f32(s[l], s[f], weights=w)) for l in leaders]
+        within = [j for j, v in enumerate(d2) if v <= t2]
+        assert labels[f] == within[0]
+    for j, l in enumerate(leaders):
+        for l0 in leaders[:j]:
+            assert O.cv_distance_sq_f32(s[l0], s[l], weights=w) > t2
+    _, _, n_flat = O.leader_cluster(s, t)
+    w_heavy = np.array([1, 1, 400, 1], dtype=np.float32)
+    _, _, n_heavy = O.leader_cluster(s, t, weights=w_heavy)
+    assert n_heavy > n_flat
+
+
+# --- trust-level adjustment (numb_cluster_threshold) ----------------------
+
+def test_trust_levels_raised_only_below_the_cluster_threshold():
+    # the paper's example: numb_cluster_threshold 15, trust levels 2 and 3
+    assert O.adjust_trust_levels(14, 15, 2.0, 3.0, 1.5) == (3.0, 4.5)
+    assert O.adjust_trust_levels(0, 15, 2.0, 3.0, 1.5) == (3.0, 4.5)
+    assert O.adjust_trust_levels(15, 15, 2.0, 3.0, 1.5) == (2.0, 3.0)
+    assert O.adjust_trust_levels(45, 15, 2.0, 3.0, 1.5) == (2.0, 3.0)
+    # repeated adjustment compounds and keeps the ratio of the levels
+    l1, l2 = 2.0, 3.0
+    for _ in range(3):
+        l1, l2 = O.adjust_trust_levels(5, 15, l1, l2, 2.0)
+    assert (l1, l2) == (16.0, 24.0)
+    for bad in [(1.0,), (0.5,), (math.inf,), (math.nan,)]:
+        try:
+            O.adjust_trust_levels(5, 15, 2.0, 3.0, *bad)
+            assert False, bad
+        except ValueError:
+            pass
+    try:
+        O.adjust_trust_levels(5, 15, 3.0, 2.0, 1.5)
+        assert False
+    except ValueError:
+        pass
