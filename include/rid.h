@@ -260,7 +260,29 @@ rid_status rid_model_dev(rid_ensemble ens, const float* d_s, int B,
  * nonzero (the workflow's first iteration); the leaders of the first
  * max_selection clusters in d_selected [max_selection] (frame indices,
  * *n_selected of them).  d_labels, n_clusters, threshold_used as above.
+ * The distance uses the ensemble's angular mask (raw CVs unwrapped) and its
+ * clustering weights (rid_ensemble_set_cv_weights): d^2 =
+ * sum_i w_i wrap(a_i - b_i)^2, each FP32 square multiplied by w_i before it
+ * is added (all weights 1: the metric above, bit for bit).
  * Synchronises the stream.  Errors: as above, and max_selection < 1.
+ *
+ * rid_ensemble_set_cv_weights - the per-CV clustering weights of the CV
+ * settings ("CV selection": `weights` weigh each CV in the selection
+ * phase's clustering).  weights: host float [n_cv], finite and >= 0, or
+ * NULL (= all 1).  A weight of 0 removes the CV from the distance.  Used by
+ * rid_select only.  Synchronizes the device.  Errors: RID_EINVAL (NULL
+ * ensemble, a negative or non-finite weight), RID_ENOMEM.
+ *
+ * rid_adjust_trust_levels - the trust levels of the next iteration
+ * ("Selection phase", numb_cluster_threshold): when the number of clusters
+ * of the current iteration's exploration frames (n_clusters, as rid_select
+ * reports it) is below numb_cluster_threshold, both levels are multiplied
+ * by `scale`; otherwise they are left unchanged.  The paper gives the
+ * condition and, in its troubleshooting table, the direction (higher trust
+ * levels encourage exploration), but not the amount: `scale` (> 1) is the
+ * caller's.  trust_lvl_1, trust_lvl_2: host, in/out (eps0 < eps1).  Pure
+ * host arithmetic (FP32 products), no device work.  Errors: RID_EINVAL
+ * (NULL pointer, scale not finite or <= 1, levels not 0 <= lvl_1 < lvl_2).
  * ------------------------------------------------------------------------ */
 rid_status rid_cluster_frames(const float* d_s, int B, int n_cv, const float* d_eps,
                               float eps0, float threshold, int adapt, int lower, int upper,
@@ -270,6 +292,9 @@ rid_status rid_select(rid_ensemble ens, const float* d_s, int B, float eps0, flo
                       int adapt, int lower, int upper, int max_selection, float* d_eps,
                       int* d_labels, int* d_selected, int* n_selected, int* n_clusters,
                       float* threshold_used, rid_stream stream);
+rid_status rid_ensemble_set_cv_weights(rid_ensemble ens, const float* weights);
+rid_status rid_adjust_trust_levels(int n_clusters, int numb_cluster_threshold, float scale,
+                                   float* trust_lvl_1, float* trust_lvl_2);
 
 /* ------------------------------------------------------------------------
  * rid_bias_force - the per-MD-step neural bias of B walkers.

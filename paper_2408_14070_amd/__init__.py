@@ -32,7 +32,8 @@ EXPORTS = (
     "rid_ensemble_set_resnet", "rid_ensemble_set_angular_mask", "rid_ensemble_set_cv_bounds",
     "rid_ensemble_set_train_budget",
     "rid_ensemble_destroy",
-    "rid_cv_eval", "rid_model_dev", "rid_cluster_frames", "rid_select", "rid_bias_force",
+    "rid_cv_eval", "rid_model_dev", "rid_cluster_frames", "rid_select",
+    "rid_ensemble_set_cv_weights", "rid_adjust_trust_levels", "rid_bias_force",
     "rid_bias_force_conservative", "rid_bias_force_noalloc", "rid_noalloc_scratch_floats",
     "rid_mcmc_run",
     "rid_cv_apply_force",
@@ -105,6 +106,8 @@ def lib():
         "rid_model_dev": (i, [vp, vp, i, vp, vp, vp, vp, vp]),
         "rid_cluster_frames": (i, [vp, i, i, vp, f, f, i, i, i, i, vp, vp, P(i), P(f), vp]),
         "rid_select": (i, [vp, vp, i, f, f, i, i, i, i, vp, vp, vp, P(i), P(i), P(f), vp]),
+        "rid_ensemble_set_cv_weights": (i, [vp, vp]),
+        "rid_adjust_trust_levels": (i, [i, i, f, P(f), P(f)]),
         "rid_bias_force": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
         "rid_bias_force_conservative": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
         "rid_bias_force_noalloc": (i, [vp, vp, vp, i, f, f, vp, vp, vp, vp, vp, vp]),
@@ -257,6 +260,17 @@ class Ensemble:
             raise ValueError("angular_mask must be [n_cv]")
         _check(lib().rid_ensemble_set_angular_mask(self.handle, m.ctypes.data_as(ctypes.c_void_p)))
 
+    def set_cv_weights(self, weights=None):
+        """rid_ensemble_set_cv_weights: per-CV weights of the selection
+        phase's clustering distance; None makes every weight 1 again."""
+        if weights is None:
+            _check(lib().rid_ensemble_set_cv_weights(self.handle, None))
+            return
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32))
+        if w.shape != (self.n_cv,):
+            raise ValueError("weights must be [n_cv]")
+        _check(lib().rid_ensemble_set_cv_weights(self.handle, w.ctypes.data_as(ctypes.c_void_p)))
+
     def set_train_budget(self, nbytes: int = 0):
         """rid_ensemble_set_train_budget: device bytes of stored activations
         one training pass may hold (0: the default); larger batches run in
@@ -350,6 +364,16 @@ def select(ens: Ensemble, s, eps0: float, threshold: float, lower: int, upper: i
                             ctypes.byref(nc), ctypes.byref(tu), _stream(stream)))
     return dict(eps=eps, labels=labels, selected=sel[:ns.value], n_clusters=nc.value,
                 threshold=tu.value)
+
+
+def adjust_trust_levels(n_clusters: int, numb_cluster_threshold: int, trust_lvl_1: float,
+                        trust_lvl_2: float, scale: float):
+    """rid_adjust_trust_levels: the trust levels of the next iteration
+    (raised by `scale` when n_clusters < numb_cluster_threshold)."""
+    l1, l2 = ctypes.c_float(trust_lvl_1), ctypes.c_float(trust_lvl_2)
+    _check(lib().rid_adjust_trust_levels(int(n_clusters), int(numb_cluster_threshold),
+                                         float(scale), ctypes.byref(l1), ctypes.byref(l2)))
+    return l1.value, l2.value
 
 
 def bias_force(system: System, ens: Ensemble, pos, eps0: float, eps1: float,

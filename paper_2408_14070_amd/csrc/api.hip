@@ -126,6 +126,7 @@ static void free_ensemble(rid_ensemble_impl& e) {
   dev_free(e.d_bo);
   dev_free(e.d_vscale);
   dev_free(e.d_raw);
+  dev_free(e.d_cvw);
   dev_free(e.d_bounds);
   e.ws_x.release();
   e.ws_A.release();
@@ -483,6 +484,44 @@ rid_status rid_ensemble_set_angular_mask(rid_ensemble ens, const uint8_t* angula
   return RID_OK;
 }
 
+rid_status rid_ensemble_set_cv_weights(rid_ensemble ens, const float* weights) {
+  if (!ens) return fail(RID_EINVAL, "NULL argument");
+  rid_ensemble_impl& e = ens->impl;
+  std::vector<float> w;
+  bool all_one = true;
+  if (weights) {
+    w.assign(weights, weights + e.n_cv);
+    for (float v : w) {
+      if (!std::isfinite(v) || v < 0.f)
+        return fail(RID_EINVAL, "CV weights must be finite and non-negative");
+      all_one = all_one && v == 1.f;
+    }
+  }
+  RID_HIP(hipDeviceSynchronize());   // calls in flight may still read the old weights
+  dev_free(e.d_cvw);
+  e.cvw.clear();
+  if (all_one) return RID_OK;         // every weight 1: the unweighted metric, bit for bit
+  rid_status st = dev_alloc(&e.d_cvw, sizeof(float) * (size_t)e.n_cv);
+  if (st != RID_OK) return st;
+  RID_HIP(hipMemcpy(e.d_cvw, w.data(), sizeof(float) * (size_t)e.n_cv, hipMemcpyHostToDevice));
+  e.cvw = w;
+  return RID_OK;
+}
+
+rid_status rid_adjust_trust_levels(int n_clusters, int numb_cluster_threshold, float scale,
+                                   float* trust_lvl_1, float* trust_lvl_2) {
+  if (!trust_lvl_1 || !trust_lvl_2) return fail(RID_EINVAL, "NULL argument");
+  if (!std::isfinite(scale) || !(scale > 1.f)) return fail(RID_EINVAL, "scale must be finite and > 1");
+  const float l1 = *trust_lvl_1, l2 = *trust_lvl_2;
+  if (!std::isfinite(l1) || !std::isfinite(l2) || !(l1 >= 0.f) || !(l1 < l2))
+    return fail(RID_EINVAL, "trust levels must satisfy 0 <= lvl_1 < lvl_2");
+  if (n_clusters < numb_cluster_threshold) {
+    *trust_lvl_1 = l1 * scale;
+    *trust_lvl_2 = l2 * scale;
+  }
+  return RID_OK;
+}
+
 rid_status rid_ensemble_set_resnet(rid_ensemble ens, int enable) {
   if (!ens) return fail(RID_EINVAL, "NULL argument");
   const rid_ensemble_impl& e = ens->impl;
@@ -544,10 +583,9 @@ rid_status rid_cluster_frames(const float* d_s, int B, int n_cv, const float* d_
     return fail(RID_EINVAL, "threshold must be positive and finite");
   if (max_clusters < 1) return fail(RID_EINVAL, "max_clusters must be >= 1");
   if (adapt && (lower < 1 || upper < lower)) return fail(RID_EINVAL, "need 1 <= lower <= upper");
-  return launch_cluster(d_s, B, n_cv, nullptr, d_eps, eps0, threshold, lower, upper, adapt,
-                        max_clusters,
-                        d_labels, d_leaders, max_clusters, nullptr, n_clusters, threshold_used,
-                        (hipStream_t)stream);
+  return launch_cluster(d_s, B, n_cv, nullptr, nullptr, d_eps, eps0, threshold, lower, upper,
+                        adapt, max_clusters, d_labels, d_leaders, max_clusters, nullptr,
+                        n_clusters, threshold_used, (hipStream_t)stream);
 }
 
 rid_status rid_select(rid_ensemble ens, const float* d_s, int B, float eps0, float threshold,
@@ -564,10 +602,9 @@ rid_status rid_select(rid_ensemble ens, const float* d_s, int B, float eps0, flo
   rid_status r = rid_model_dev(ens, d_s, B, d_eps, nullptr, nullptr, nullptr, stream);
   if (r != RID_OK) return r;
   const int cap = std::max(upper, max_selection) + 1;
-  return launch_cluster(d_s, B, ens->impl.n_cv, ens->impl.d_raw, d_eps, eps0, threshold, lower,
-                        upper, adapt, cap,
-                        d_labels, d_selected, max_selection, n_selected, n_clusters,
-                        threshold_used, (hipStream_t)stream);
+  return launch_cluster(d_s, B, ens->impl.n_cv, ens->impl.d_raw, ens->impl.d_cvw, d_eps, eps0,
+                        threshold, lower, upper, adapt, cap, d_labels, d_selected, max_selection,
+                        n_selected, n_clusters, threshold_used, (hipStream_t)stream);
 }
 
 

@@ -150,6 +150,9 @@ struct rid_ensemble_impl {
   // angular mask of the inputs: CVs with raw[i] = 1 enter as (s_i, 0)
   std::vector<uint8_t> raw;            // [n_cv] (empty: every CV angular)
   uint8_t* d_raw = nullptr;            // device copy, or null when no CV is raw
+  // per-CV clustering weights of the selection metric (empty: all 1)
+  std::vector<float> cvw;              // [n_cv]
+  float* d_cvw = nullptr;              // device copy, or null when every weight is 1
   // MCMC box of the raw CVs: lower [n], then upper [n] (null until set)
   std::vector<float> bounds;
   float* d_bounds = nullptr;
@@ -225,7 +228,8 @@ struct TrainIo {
 };
 // Threshold clustering of CV frames (selection); synchronises the stream.
 // Copies the first min(leaders, leaders_out) leaders' frame indices.
-rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw, const float* eps,
+rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw,
+                          const float* w, const float* eps,
                           float eps0, float threshold, int lower, int upper, int adapt, int cap,
                           int* labels, int* leaders, int leaders_out, int* n_leaders,
                           int* n_clusters, float* t_used, hipStream_t st);

@@ -7,8 +7,10 @@
 // Clustering (the paper names a threshold, not the algorithm): frames in
 // order; a frame joins the first cluster, in founding order, whose leader is
 // within the threshold, otherwise it founds a cluster and leads it.  The
-// distance is periodic in every CV (differences wrapped to (-pi, pi]) and the
-// decision d^2 <= t^2 is taken in FP32 with the squares summed in CV order,
+// distance is periodic in every angular CV (differences wrapped to
+// (-pi, pi]; raw CVs unwrapped), each square optionally weighted by the CV's
+// clustering weight (the CV settings' "weights"), and the decision
+// d^2 <= t^2 is taken in FP32 with the squares summed in CV order,
 // contraction off, so the labels do not depend on the launch shape.
 //
 // GPU form of the sequential rule, exact: frames go in chunks.  A parallel
@@ -47,23 +49,28 @@ struct ClusterArgs {
   int* labels;           // [B]
   unsigned long long* pend;   // [ceil(B/64)] bit f%64 of word f/64: frame f unmatched
   const uint8_t* raw;    // [n] or null: CVs with raw[i] = 1 are not periodic
+  const float* w;        // [n] or null: per-CV weights of the squared differences
 };
 
-// Squared distance leader - frame with non-periodic CVs (raw[i] = 1: the
-// difference is not wrapped); otherwise as leader_d2.
-__device__ inline float leader_d2_masked(const float* lead, long long ls, const float* x, int n,
-                                         const uint8_t* raw) {
+// Squared distance leader - frame with non-periodic CVs (raw non-null:
+// raw[i] = 1 leaves the difference unwrapped) and/or per-CV weights (w
+// non-null: each square is multiplied by w[i] before it is added);
+// otherwise as leader_d2.
+__device__ inline float leader_d2_general(const float* lead, long long ls, const float* x, int n,
+                                          const uint8_t* raw, const float* w) {
 #pragma clang fp contract(off)
   constexpr float kPi = 3.14159265358979f;
   constexpr float kTwoPi = 6.28318530717959f;
   float acc = 0.f;
   for (int i = 0; i < n; ++i) {
     float d = lead[i * ls] - x[i];
-    if (!raw[i]) {
+    if (!raw || !raw[i]) {
       if (d > kPi) d = d - kTwoPi;
       if (d <= -kPi) d = d + kTwoPi;
     }
-    acc = acc + d * d;
+    float sq = d * d;
+    if (w) sq = sq * w[i];
+    acc = acc + sq;
   }
   return acc;
 }
@@ -71,9 +78,9 @@ __device__ inline float leader_d2_masked(const float* lead, long long ls, const 
 // Squared periodic distance leader - frame, the leader's CV i at lead[i * ls],
 // the frame's at x[i]; FP32, CV order, no fused multiply-add.
 __device__ inline float leader_d2(const float* lead, long long ls, const float* x, int n,
-                                  const uint8_t* raw) {
+                                  const uint8_t* raw, const float* w) {
 #pragma clang fp contract(off)
-  if (raw) return leader_d2_masked(lead, ls, x, n, raw);
+  if (raw || w) return leader_d2_general(lead, ls, x, n, raw, w);
   constexpr float kPi = 3.14159265358979f;
   constexpr float kTwoPi = 6.28318530717959f;
   float acc = 0.f;
@@ -113,7 +120,7 @@ __global__ __launch_bounds__(kMatchWaves * kWave) void sel_match_kernel(ClusterA
   int lab = kPending;
   for (int j0 = 0; j0 < nl; j0 += kWave) {
     const int j = j0 + lane;
-    const bool hit = j < nl && leader_d2(a.LT + j, a.cap, xs[wave], n, a.raw) <= a.t2;
+    const bool hit = j < nl && leader_d2(a.LT + j, a.cap, xs[wave], n, a.raw, a.w) <= a.t2;
     const unsigned long long m = __ballot(hit);
     if (m) {
       lab = j0 + __ffsll((long long)m) - 1;
@@ -200,7 +207,7 @@ __global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(Clus
       int hitj = -1;
       for (int j0 = 0; j0 < n_new0 && hitj < 0; j0 += kWave) {
         const int j = j0 + lane;
-        const bool hit = j < n_new0 && leader_d2(NL + (size_t)j * n, 1, XB + (size_t)q * n, n, a.raw) <= a.t2;
+        const bool hit = j < n_new0 && leader_d2(NL + (size_t)j * n, 1, XB + (size_t)q * n, n, a.raw, a.w) <= a.t2;
         const unsigned long long m = __ballot(hit);
         if (m) hitj = j0 + __ffsll((long long)m) - 1;
       }
@@ -252,7 +259,7 @@ __global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(Clus
       if (sh[1] != f_end || start >= g) break;
       const int jn = sh[0] - 1;                  // the leader just founded
       for (int q = start + tid; q < g; q += kResolveWaves * kWave)
-        if (gm[q] < 0 && leader_d2(NL + (size_t)jn * n, 1, XB + (size_t)q * n, n, a.raw) <= a.t2)
+        if (gm[q] < 0 && leader_d2(NL + (size_t)jn * n, 1, XB + (size_t)q * n, n, a.raw, a.w) <= a.t2)
           gm[q] = jn;
       __syncthreads();
     }
@@ -329,7 +336,8 @@ rid_status cluster_once(ClusterArgs a, float t, int nlmax, int gmax, hipStream_t
 
 }  // namespace
 
-rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw, const float* eps,
+rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw, const float* w,
+                          const float* eps,
                           float eps0, float threshold, int lower, int upper, int adapt, int cap,
                           int* labels, int* leaders, int leaders_out, int* n_leaders,
                           int* n_clusters, float* t_used, hipStream_t st) {
@@ -341,6 +349,7 @@ rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw, cons
   ClusterArgs a{};
   a.s = s;
   a.raw = raw;
+  a.w = w;
   a.eps = eps;
   a.eps0 = eps0;
   a.B = B;

@@ -104,3 +104,28 @@ def test_compute_calls_reject_null_handles():
 def test_python_binding_validates_shapes_before_calling():
     with pytest.raises(ValueError):
         rid.System(22, np.zeros((3, 3), np.int32))
+
+
+def test_trust_level_adjustment_matches_oracle_on_host():
+    # pure host arithmetic behind the C ABI: the same FP32 products as the
+    # oracle's reading, and the same argument checks
+    for n, thr, l1, l2, sc in [(14, 15, 2.0, 3.0, 1.5), (15, 15, 2.0, 3.0, 1.5),
+                               (0, 15, 2.0, 3.0, 1.25), (3, 15, 0.0, 0.7, 3.0),
+                               (40, 15, 1.7, 2.9, 1.1)]:
+        assert rid.adjust_trust_levels(n, thr, l1, l2, sc) == O.adjust_trust_levels(n, thr, l1, l2, sc)
+    for bad in [dict(scale=1.0), dict(scale=0.5), dict(scale=float("inf")),
+                dict(scale=float("nan")), dict(l1=3.0, l2=2.0), dict(l1=-1.0, l2=2.0)]:
+        args = dict(l1=2.0, l2=3.0, scale=1.5)
+        args.update(bad)
+        with pytest.raises(rid.RidError) as e:
+            rid.adjust_trust_levels(5, 15, args["l1"], args["l2"], args["scale"])
+        assert e.value.status == rid.RID_EINVAL
+    L = rid.lib()
+    one = ctypes.c_float(1.0)
+    assert L.rid_adjust_trust_levels(1, 2, 1.5, None, ctypes.byref(one)) == rid.RID_EINVAL
+
+
+def test_cv_weights_setter_rejects_null_ensemble():
+    L = rid.lib()
+    w = np.ones(4, np.float32)
+    assert L.rid_ensemble_set_cv_weights(None, w.ctypes.data_as(ctypes.c_void_p)) == rid.RID_EINVAL

@@ -140,6 +140,66 @@ def test_select_benchmarked_workload_matches_oracle(torch, rid):
     assert hashlib.sha256(np.ascontiguousarray(labels).tobytes()).hexdigest() == g["labels_sha256"]
 
 
+@pytest.mark.parametrize("masked", [False, True])
+def test_weighted_select_matches_oracle(torch, rid, masked):
+    """Selection with per-CV clustering weights (CV settings "weights"),
+    alone and with an angular mask: labels, leaders, count and adapted
+    threshold equal to the oracle's; weights of 1 give the unweighted
+    result bit for bit, and the weights change the clustering."""
+    n, widths, K = 38, [64, 64], 4
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 23, bias_std=0.1)
+    models = ridgen.unpack_params(params, 2 * n, widths, K)
+    s = ridgen.exploration_frames(16, 125, n, 30, 0.3, seed=16)
+    mask = None
+    if masked:
+        mask = np.ones(n, np.uint8)
+        mask[1::5] = 0
+        raw = ~mask.astype(bool)
+        s[:, raw] = (1.0 + 1.5 * s[:, raw]).astype(np.float32)
+    w = np.random.default_rng(17).uniform(0.25, 2.0, n).astype(np.float32)
+    w[[3, 11]] = 0.0                          # two CVs left out of the metric
+    eps_ref = O.frame_deviation(models, s.astype(np.float64), mask)
+    e = np.sort(eps_ref)
+    mid = len(e) // 2
+    k = mid - 200 + int(np.argmax(np.diff(e[mid - 200:mid + 200])))
+    eps0 = 0.5 * (e[k] + e[k + 1])
+    gap = e[k + 1] - e[k]
+    assert gap > 1e-4 * e[k]
+    ref = O.select_frames(models, s, eps0, 0.5, 30, 45, 50, adapt=True, mask=mask, weights=w)
+    E = rid.Ensemble(n, widths, K, params)
+    if masked:
+        E.set_angular_mask(mask)
+    E.set_cv_weights(w)
+    sd = torch.from_numpy(s).cuda()
+    out = rid.select(E, sd, eps0, 0.5, 30, 45, 50, adapt=True)
+    torch.cuda.synchronize()
+    eps = out["eps"].cpu().numpy().astype(np.float64)
+    assert np.min(np.abs(eps - eps0)) > 0.25 * gap
+    print(f"weighted selection (mask {masked}): {len(ref['selected'])} of "
+          f"{ref['n_clusters']} clusters, threshold {ref['threshold']}", flush=True)
+    assert np.float32(out["threshold"]) == ref["threshold"]
+    assert out["n_clusters"] == ref["n_clusters"]
+    assert out["selected"].cpu().numpy().tolist() == ref["selected"]
+    assert np.array_equal(out["labels"].cpu().numpy().astype(np.int64), ref["labels"])
+    # the weights matter: the unweighted clustering at the same threshold differs
+    plain = O.leader_cluster(s, ref["threshold"], ref["keep"], 51, mask)
+    assert not np.array_equal(plain[0], ref["labels"])
+    # weights of 1 are the unweighted metric, bit for bit
+    E.set_cv_weights(np.ones(n, np.float32))
+    ones = rid.select(E, sd, eps0, 0.5, 30, 45, 50, adapt=True)
+    E.set_cv_weights(None)
+    none = rid.select(E, sd, eps0, 0.5, 30, 45, 50, adapt=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(ones["labels"].cpu().numpy(), none["labels"].cpu().numpy())
+    assert ones["threshold"] == none["threshold"] and ones["n_clusters"] == none["n_clusters"]
+    ref1 = O.select_frames(models, s, eps0, 0.5, 30, 45, 50, adapt=True, mask=mask)
+    assert np.array_equal(none["labels"].cpu().numpy().astype(np.int64), ref1["labels"])
+    with pytest.raises(rid.RidError):
+        E.set_cv_weights(-w)
+    with pytest.raises(ValueError):
+        E.set_cv_weights(w[:5])
+
+
 def test_cluster_rejects_bad_arguments(torch, rid):
     s = torch.zeros((10, 300), dtype=torch.float32, device="cuda")
     with pytest.raises(rid.RidError):
