@@ -71,6 +71,12 @@ struct GemmArgs {
   long long sAdd2b;
   int M, N, Kc, batch, ksplit, kchunk, mode;
   int modeA, modeB;               // operand load modes (TileLoad), set by gemm()
+  // optional row sums of A over its first csum_rows contraction indices, per
+  // split-K slab: csum[(s * batch + b) * M + m] (the workgroups of the first
+  // column tile add them up from the A tiles they stage; the bias gradient
+  // of the weight-gradient GEMM)
+  float* csum;
+  int csum_rows;
 };
 
 // One operand tile of TR rows x BK contraction into LDS [row][k].  Element
@@ -176,6 +182,14 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < TJ; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
+  // row sums of A (csum): the first column tile's workgroups, over the part
+  // of their k-chunk below csum_rows (every split writes its slab, zeros
+  // when its chunk lies above); each row summed by one thread in k order
+  // (deterministic)
+  const bool csum_wg = g.csum && blockIdx.x == 0;
+  const int csum_end = min(k_end, g.csum_rows);
+  float cs = 0.f;
+
   int buf = 0;
   load(k_begin);
   store(0);
@@ -183,6 +197,16 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
   for (int kb = k_begin; kb < k_end; kb += BK) {
     const bool more = kb + BK < k_end;
     if (more) load(kb + BK);
+    if (csum_wg && tid < TM && kb < csum_end) {
+      const int nk = min(BK, csum_end - kb);
+#pragma unroll
+      for (int q = 0; q < BK / 4; ++q) {
+        const f4 x = *reinterpret_cast<const f4*>(&As[buf][tid][4 * q]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (4 * q + e < nk) cs += x[e];
+      }
+    }
     f4 a[TI], bb[TJ];
 #pragma unroll
     for (int i = 0; i < TI; ++i)
@@ -204,6 +228,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
     }
   }
 
+  if (csum_wg && tid < TM && m0 + tid < g.M)
+    g.csum[((long long)s * g.batch + b) * g.M + m0 + tid] = cs;
   float* C = g.C ? g.C + b * g.sCb + s * g.sCs : nullptr;
 #pragma unroll
   for (int i = 0; i < TI; ++i)
@@ -439,18 +465,29 @@ __global__ __launch_bounds__(256) void colsum_final_kernel(const float* part, in
 }
 
 // dW[k] = sum over split-K slabs (fixed order) -> gradient buffer (added to
-// what it holds when accumulate is set)
+// what it holds when accumulate is set); with bpart, also db[k] = the
+// slabs' bias partials bpart[s][k][out] summed in slab order, to b_off
 __global__ void splitk_reduce_kernel(const float* part, long long slab_s, int ks,
                                      int out, int in, int K, float* grad,
-                                     long long per_model, int w_off, int accumulate) {
+                                     long long per_model, int w_off, int accumulate,
+                                     const float* bpart, int b_off) {
   const long long total = (long long)K * out * in;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+  const long long all = total + (bpart ? (long long)K * out : 0);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < all;
        e += (long long)gridDim.x * blockDim.x) {
     float acc = 0.f;
-    for (int s = 0; s < ks; ++s) acc += part[s * slab_s + e];
-    const int k = (int)(e / ((long long)out * in));
-    const long long r = e - (long long)k * out * in;
-    float* o = grad + k * per_model + w_off + r;
+    float* o;
+    if (e < total) {
+      for (int s = 0; s < ks; ++s) acc += part[s * slab_s + e];
+      const int k = (int)(e / ((long long)out * in));
+      const long long r = e - (long long)k * out * in;
+      o = grad + k * per_model + w_off + r;
+    } else {
+      const long long eb = e - total;                 // k * out + j
+      for (int s = 0; s < ks; ++s) acc += bpart[s * (long long)K * out + eb];
+      const int k = (int)(eb / out);
+      o = grad + k * per_model + b_off + (eb - (long long)k * out);
+    }
     *o = accumulate ? *o + acc : acc;
   }
 }
@@ -601,6 +638,7 @@ rid_status mf_grad_fused(rid_ensemble_impl& e, const float* s, const float* F,
   const long long grad = tot; tot = al(tot + (long long)e.n_params);
   const long long lrows = tot; tot = al(tot + (long long)K * B);
   const long long cpart = tot; tot = al(tot + (long long)((Bc + kColRows - 1) / kColRows) * K * wmax);
+  const long long bpart = tot; tot = al(tot + (long long)ks_max * K * wmax);
   rid_status rs = e.ws_train.ensure(sizeof(float) * tot);
   if (rs != RID_OK) return rs;
   float* W = e.ws_train.as<float>();
@@ -639,15 +677,14 @@ rid_status mf_grad_fused(rid_ensemble_impl& e, const float* s, const float* F,
       g.sCs = (long long)K * w[l] * w[l - 1];
       g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * R; g.batch = K; g.ksplit = ks; g.kchunk = kchunk;
       g.mode = EPI_STORE;
+      // db_l = sum over the primal rows of lam_z: row sums of A in the same pass
+      g.csum = W + bpart; g.csum_rows = R;
       if ((rs = gemm(g, st)) != RID_OK) return rs;
       hipLaunchKernelGGL(splitk_reduce_kernel,
-                         dim3(grid1d((long long)K * w[l] * w[l - 1])), dim3(256), 0, st,
+                         dim3(grid1d((long long)K * w[l] * (w[l - 1] + 1))), dim3(256), 0, st,
                          W + part, (long long)K * w[l] * w[l - 1], ks, w[l], w[l - 1], K,
-                         G, pm, (int)w_off[l - 1], acc ? 1 : 0);
+                         G, pm, (int)w_off[l - 1], acc ? 1 : 0, W + bpart, (int)b_off[l - 1]);
       RID_HIP(hipGetLastError());
-      if ((rs = colsum(W + sl[l - 1], 2LL * R * w[l], R, w[l], K, W + cpart, G, pm,
-                       (int)b_off[l - 1], acc, st)) != RID_OK)
-        return rs;
     }
     if ((rs = colsum(W + hh[L] + (long long)R * w[L], 2LL * R * w[L], R, w[L], K, W + cpart,
                      G, pm, (int)wo_off, acc, st)) != RID_OK)
@@ -745,6 +782,7 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   const long long grad = tot; tot += (long long)e.n_params;
   const long long lrows = tot; tot += (long long)K * B;
   const long long cpart = tot; tot += (long long)((Bc + kColRows - 1) / kColRows) * K * wmax;
+  const long long bpart = tot; tot += (long long)ks_max * K * wmax;
   rid_status rs = e.ws_train.ensure(sizeof(float) * tot);
   if (rs != RID_OK) return rs;
   float* W = e.ws_train.as<float>();
@@ -857,16 +895,15 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
         g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * R; g.batch = K; g.ksplit = ks;
         g.kchunk = kchunk;
         g.mode = EPI_STORE;
+        // db_l = sum over the primal rows of lam_z: row sums of A in the same pass
+        g.csum = W + bpart; g.csum_rows = R;
         if ((rs = gemm(g, st)) != RID_OK) return rs;
         hipLaunchKernelGGL(splitk_reduce_kernel,
-                           dim3(grid1d((long long)K * w[l] * w[l - 1])), dim3(256), 0, st,
+                           dim3(grid1d((long long)K * w[l] * (w[l - 1] + 1))), dim3(256), 0, st,
                            W + part, (long long)K * w[l] * w[l - 1], ks, w[l], w[l - 1], K,
-                           G, pm, (int)w_off[l - 1], acc ? 1 : 0);
+                           G, pm, (int)w_off[l - 1], acc ? 1 : 0, W + bpart,
+                           (int)b_off[l - 1]);
         RID_HIP(hipGetLastError());
-        // db_l = sum_b lam_z
-        if ((rs = colsum(W + sbuf, 2LL * R * w[l], R, w[l], K, W + cpart, G, pm,
-                         (int)b_off[l - 1], acc, st)) != RID_OK)
-          return rs;
       }
       if (l > 1 || input_mode) {
         // [lam_h ; lam_hd]_{l-1} = [lam_z ; lam_zd] W_l (+ [lam_h ; lam_hd]_l)
