@@ -71,12 +71,6 @@ struct GemmArgs {
   long long sAdd2b;
   int M, N, Kc, batch, ksplit, kchunk, mode;
   int modeA, modeB;               // operand load modes (TileLoad), set by gemm()
-  // optional row sums of A over its first csum_rows contraction indices, per
-  // split-K slab: csum[(s * batch + b) * M + m] (the workgroups of the first
-  // column tile add them up from the A tiles they stage; the bias gradient
-  // of the weight-gradient GEMM)
-  float* csum;
-  int csum_rows;
 };
 
 // One operand tile of TR rows x BK contraction into LDS [row][k].  Element
@@ -182,14 +176,6 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < TJ; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // row sums of A (csum): the first column tile's workgroups, over the part
-  // of their k-chunk below csum_rows (every split writes its slab, zeros
-  // when its chunk lies above); each row summed by one thread in k order
-  // (deterministic)
-  const bool csum_wg = g.csum && blockIdx.x == 0;
-  const int csum_end = min(k_end, g.csum_rows);
-  float cs = 0.f;
-
   int buf = 0;
   load(k_begin);
   store(0);
@@ -197,16 +183,6 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
   for (int kb = k_begin; kb < k_end; kb += BK) {
     const bool more = kb + BK < k_end;
     if (more) load(kb + BK);
-    if (csum_wg && tid < TM && kb < csum_end) {
-      const int nk = min(BK, csum_end - kb);
-#pragma unroll
-      for (int q = 0; q < BK / 4; ++q) {
-        const f4 x = *reinterpret_cast<const f4*>(&As[buf][tid][4 * q]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (4 * q + e < nk) cs += x[e];
-      }
-    }
     f4 a[TI], bb[TJ];
 #pragma unroll
     for (int i = 0; i < TI; ++i)
@@ -228,8 +204,6 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
     }
   }
 
-  if (csum_wg && tid < TM && m0 + tid < g.M)
-    g.csum[((long long)s * g.batch + b) * g.M + m0 + tid] = cs;
   float* C = g.C ? g.C + b * g.sCb + s * g.sCs : nullptr;
 #pragma unroll
   for (int i = 0; i < TI; ++i)
@@ -523,6 +497,177 @@ __global__ void adam_kernel(float* theta, float* m, float* v, const float* g,
   }
 }
 
+// Weight-gradient GEMM: C_s[b] = sum over the k-chunk s of A[b][k][m] B[b][k][n]
+// (A: [Kc][M] rows, m contiguous; B: [Kc][N] rows, n contiguous -- the
+// stacked lam and activation slabs, whose contraction index is the row).
+// The 32x32x2 FP32 MFMA takes A as 32 m x 2 k with lane l holding
+// (m = l % 32, k = l / 32), and B likewise, so each lane loads one float of
+// each operand straight from the row-major slabs with coalesced 128-byte
+// row segments: no LDS staging, no transposes, no barriers in the loop.
+// A workgroup owns a 64 x 64 tile of one member and one k-chunk; its four
+// waves take consecutive quarters of the chunk (two rows per k-step, 2 x 2
+// MFMA tiles per wave, loads issued WG_PF k-steps ahead) and their partial
+// tiles are added through LDS in a fixed order ((w0 + w2) + (w1 + w3)), so
+// the result does not depend on timing.  With csum, the workgroups of the
+// first column tile also sum A over the rows below csum_rows (the bias
+// gradient: lam_z over the primal rows), per split slab.
+struct WgradArgs {
+  const float* A;
+  long long sAb;
+  int lda;
+  const float* B;
+  long long sBb;
+  int ldb;
+  float* C;           // partial slab s of member b: C + s*sCs + b*M*N, [M][N]
+  long long sCs;
+  float* csum;        // [ks][batch][M] or null
+  int csum_rows;
+  int M, N, Kc, batch, ksplit, kchunk;
+};
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+constexpr int kWgPF = 8;           // k-steps of loads in flight per wave
+constexpr int kWgLdsStride = 65;   // padded row of a partial tile in LDS
+
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
+  __shared__ float red[2][64][kWgLdsStride];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lo = lane & 31, hi = lane >> 5;
+  const int b = blockIdx.z / g.ksplit, s = blockIdx.z % g.ksplit;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int c_begin = s * g.kchunk, c_end = min(g.Kc, c_begin + g.kchunk);
+  // this wave's quarter of the chunk, in whole k-steps of two rows
+  const int steps = (c_end - c_begin + 1) / 2;
+  const int q = (steps + 3) / 4;
+  const int k_begin = c_begin + 2 * min(steps, wave * q);
+  const int k_end = min(c_end, c_begin + 2 * min(steps, (wave + 1) * q));
+  const float* A = g.A + b * g.sAb;
+  const float* Bp = g.B + b * g.sBb;
+  // the lane's element of a k-step: row k + hi, its column clamped into the
+  // operand.  A lane whose column lies outside only feeds accumulator rows
+  // or columns that are never stored, so its value needs no masking.  Every
+  // wave's range holds an even number of rows (chunks and quarters are
+  // whole k-steps of an even Kc), so row k + hi is always inside it.
+  // Offsets from the (uniform) row start are per-lane constants.
+  const int ma = min(m0 + lo, g.M - 1), mb = min(m0 + 32 + lo, g.M - 1);
+  const int na = min(n0 + lo, g.N - 1), nb = min(n0 + 32 + lo, g.N - 1);
+  const unsigned oa0 = hi * g.lda + ma, oa1 = hi * g.lda + mb;
+  const unsigned ob0 = hi * g.ldb + na, ob1 = hi * g.ldb + nb;
+  const bool csum_wg = g.csum && blockIdx.x == 0;
+  const int csum_end = min(k_end, g.csum_rows);
+
+  f16v acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f16v{};
+  float cs0 = 0.f, cs1 = 0.f;
+  // ring of loaded k-steps: [slot][a0, a1, b0, b1]
+  float ring[kWgPF][4];
+  auto issue = [&](int slot, int k) {
+    const float* ar = A + (long long)k * g.lda;
+    const float* br = Bp + (long long)k * g.ldb;
+    ring[slot][0] = ar[oa0];
+    ring[slot][1] = ar[oa1];
+    ring[slot][2] = br[ob0];
+    ring[slot][3] = br[ob1];
+  };
+  // k-steps of the wave; loads run kWgPF steps ahead through the ring.  The
+  // main loop has no conditional code (a step past the last one re-reads
+  // the last, and is never consumed), so the loads stay in flight.
+  const int nst = (k_end - k_begin) / 2;
+  auto step_row = [&](int t) { return k_begin + 2 * min(t, nst - 1); };
+  auto consume = [&](int p, int t) {
+    const float a0 = ring[p][0], a1 = ring[p][1], b0 = ring[p][2], b1 = ring[p][3];
+    if (csum_wg) {
+      const bool in = k_begin + 2 * t + hi < csum_end;
+      cs0 += in ? a0 : 0.f;
+      cs1 += in ? a1 : 0.f;
+    }
+    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+  };
+  if (nst > 0) {
+#pragma unroll
+    for (int p = 0; p < kWgPF; ++p) issue(p, step_row(p));
+    const int nfull = nst / kWgPF;
+    for (int blk = 0; blk < nfull; ++blk) {
+#pragma unroll
+      for (int p = 0; p < kWgPF; ++p) {
+        const int t = blk * kWgPF + p;
+        consume(p, t);
+        issue(p, step_row(t + kWgPF));
+      }
+    }
+    const int rem = nst - nfull * kWgPF;
+#pragma unroll
+    for (int p = 0; p < kWgPF; ++p)
+      if (p < rem) consume(p, nfull * kWgPF + p);
+  }
+  // accumulator element v of a 32 x 32 tile: row 8 (v / 4) + 4 hi + v % 4,
+  // column lo.  Waves 2, 3 park their tiles; waves 0, 1 add them; wave 1
+  // parks the sum; wave 0 adds it and writes the slab.
+  auto park = [&](int slot) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          red[slot][32 * i + 8 * (v / 4) + 4 * hi + (v % 4)][32 * j + lo] = acc[i][j][v];
+  };
+  auto take = [&](int slot) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          acc[i][j][v] += red[slot][32 * i + 8 * (v / 4) + 4 * hi + (v % 4)][32 * j + lo];
+  };
+  // the bias sums: combine the two row parities of a lane pair, then the
+  // waves in the same fixed order through LDS (column 64 of the tile rows)
+  __shared__ float cred[4][64];
+  if (csum_wg) {
+    cs0 += __shfl_xor(cs0, 32);
+    cs1 += __shfl_xor(cs1, 32);
+    if (hi == 0) {
+      cred[wave][lo] = cs0;
+      cred[wave][32 + lo] = cs1;
+    }
+  }
+  if (wave >= 2) park(wave - 2);
+  __syncthreads();
+  if (wave < 2) take(wave);
+  __syncthreads();
+  if (wave == 1) park(0);
+  __syncthreads();
+  if (wave == 0) {
+    take(0);
+    float* C = g.C + s * g.sCs + (long long)b * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + 32 * j + lo;
+        if (n >= g.N) continue;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int m = m0 + 32 * i + 8 * (v / 4) + 4 * hi + (v % 4);
+          if (m < g.M) C[(long long)m * g.N + n] = acc[i][j][v];
+        }
+      }
+    if (csum_wg) {
+      const int m = m0 + lane;
+      const float v = (cred[0][lane] + cred[2][lane]) + (cred[1][lane] + cred[3][lane]);
+      if (m < g.M) g.csum[((long long)s * g.batch + b) * g.M + m] = v;
+    }
+  }
+}
+
 inline int grid1d(long long total) {
   return (int)std::min<long long>((total + 255) / 256, 4096);
 }
@@ -559,6 +704,17 @@ rid_status gemm(const GemmArgs& g0, hipStream_t st) {
     dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.batch * g.ksplit);
     hipLaunchKernelGGL((gemm_f32_kernel<64, 64>), grid, dim3(kThreads), 0, st, g);
   }
+  RID_HIP(hipGetLastError());
+  return RID_OK;
+}
+
+rid_status wgrad(const WgradArgs& a, hipStream_t st) {
+  // the kernel reads two rows per k-step inside each wave's range: chunks
+  // and the contraction must hold whole k-steps
+  if (a.kchunk % 2 != 0 || a.Kc % 2 != 0 || a.M < 1 || a.N < 1 || a.Kc < 1)
+    return fail(RID_EINVAL, "weight-gradient GEMM: bad shape");
+  const dim3 grid((a.N + 63) / 64, (a.M + 63) / 64, a.batch * a.ksplit);
+  hipLaunchKernelGGL(wgrad_kernel, grid, dim3(256), 0, st, a);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }
@@ -670,16 +826,15 @@ rid_status mf_grad_fused(rid_ensemble_impl& e, const float* s, const float* F,
     io.row_base = r0;
     if ((rs = launch_train_sweeps(e, io, R, st)) != RID_OK) return rs;
     for (int l = L; l >= 1; --l) {
-      GemmArgs g{};
-      g.A = W + sl[l - 1]; g.sAb = 2LL * R * w[l]; g.sAm = 1; g.sAk = w[l];
-      g.Bm = W + hh[l - 1]; g.sBb = 2LL * R * w[l - 1]; g.sBk = w[l - 1]; g.sBn = 1;
-      g.C = W + part; g.sCb = (long long)w[l] * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
-      g.sCs = (long long)K * w[l] * w[l - 1];
-      g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * R; g.batch = K; g.ksplit = ks; g.kchunk = kchunk;
-      g.mode = EPI_STORE;
-      // db_l = sum over the primal rows of lam_z: row sums of A in the same pass
+      // dW_l = S^T [h ; hd]_{l-1} (contraction over the 2R stacked rows);
+      // db_l = sum over the primal rows of lam_z, in the same pass
+      WgradArgs g{};
+      g.A = W + sl[l - 1]; g.sAb = 2LL * R * w[l]; g.lda = w[l];
+      g.B = W + hh[l - 1]; g.sBb = 2LL * R * w[l - 1]; g.ldb = w[l - 1];
+      g.C = W + part; g.sCs = (long long)K * w[l] * w[l - 1];
       g.csum = W + bpart; g.csum_rows = R;
-      if ((rs = gemm(g, st)) != RID_OK) return rs;
+      g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * R; g.batch = K; g.ksplit = ks; g.kchunk = kchunk;
+      if ((rs = wgrad(g, st)) != RID_OK) return rs;
       hipLaunchKernelGGL(splitk_reduce_kernel,
                          dim3(grid1d((long long)K * w[l] * (w[l - 1] + 1))), dim3(256), 0, st,
                          W + part, (long long)K * w[l] * w[l - 1], ks, w[l], w[l - 1], K,
@@ -887,17 +1042,15 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
       RID_HIP(hipGetLastError());
       // dW_l = S^T [h_{l-1}; hd_{l-1}]  (contraction over 2R rows, split)
       if (!input_mode) {
-        GemmArgs g{};
-        g.A = W + sbuf; g.sAb = 2LL * R * w[l]; g.sAm = 1; g.sAk = w[l];
-        g.Bm = W + hh[l - 1]; g.sBb = slab(l - 1); g.sBk = w[l - 1]; g.sBn = 1;
-        g.C = W + part; g.sCb = (long long)w[l] * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
-        g.sCs = (long long)K * w[l] * w[l - 1];
+        WgradArgs g{};
+        g.A = W + sbuf; g.sAb = 2LL * R * w[l]; g.lda = w[l];
+        g.B = W + hh[l - 1]; g.sBb = slab(l - 1); g.ldb = w[l - 1];
+        g.C = W + part; g.sCs = (long long)K * w[l] * w[l - 1];
+        // db_l = sum over the primal rows of lam_z, in the same pass
+        g.csum = W + bpart; g.csum_rows = R;
         g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * R; g.batch = K; g.ksplit = ks;
         g.kchunk = kchunk;
-        g.mode = EPI_STORE;
-        // db_l = sum over the primal rows of lam_z: row sums of A in the same pass
-        g.csum = W + bpart; g.csum_rows = R;
-        if ((rs = gemm(g, st)) != RID_OK) return rs;
+        if ((rs = wgrad(g, st)) != RID_OK) return rs;
         hipLaunchKernelGGL(splitk_reduce_kernel,
                            dim3(grid1d((long long)K * w[l] * (w[l - 1] + 1))), dim3(256), 0, st,
                            W + part, (long long)K * w[l] * w[l - 1], ks, w[l], w[l - 1], K,
