@@ -526,7 +526,10 @@ struct WgradArgs {
 };
 
 typedef float f16v __attribute__((ext_vector_type(16)));
-constexpr int kWgPF = 8;           // k-steps of loads in flight per wave
+#ifndef RID_WG_PF
+#define RID_WG_PF 4
+#endif
+constexpr int kWgPF = RID_WG_PF;   // k-steps of loads in flight per wave
 constexpr int kWgLdsStride = 65;   // padded row of a partial tile in LDS
 
 __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
@@ -550,10 +553,16 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
   // wave's range holds an even number of rows (chunks and quarters are
   // whole k-steps of an even Kc), so row k + hi is always inside it.
   // Offsets from the (uniform) row start are per-lane constants.
+  // Buffer loads: the lane's byte offset in the vector offset, the row's in
+  // the scalar offset, so the loop does no address arithmetic.
   const int ma = min(m0 + lo, g.M - 1), mb = min(m0 + 32 + lo, g.M - 1);
   const int na = min(n0 + lo, g.N - 1), nb = min(n0 + 32 + lo, g.N - 1);
-  const unsigned oa0 = hi * g.lda + ma, oa1 = hi * g.lda + mb;
-  const unsigned ob0 = hi * g.ldb + na, ob1 = hi * g.ldb + nb;
+  const int oa0 = 4 * (hi * g.lda + ma), oa1 = 4 * (hi * g.lda + mb);
+  const int ob0 = 4 * (hi * g.ldb + na), ob1 = 4 * (hi * g.ldb + nb);
+  const __amdgpu_buffer_rsrc_t ra =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(A), (short)0, 0x7FFFFFF0, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rb =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Bp), (short)0, 0x7FFFFFF0, 0x00020000);
   const bool csum_wg = g.csum && blockIdx.x == 0;
   const int csum_end = min(k_end, g.csum_rows);
 
@@ -566,12 +575,11 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
   // ring of loaded k-steps: [slot][a0, a1, b0, b1]
   float ring[kWgPF][4];
   auto issue = [&](int slot, int k) {
-    const float* ar = A + (long long)k * g.lda;
-    const float* br = Bp + (long long)k * g.ldb;
-    ring[slot][0] = ar[oa0];
-    ring[slot][1] = ar[oa1];
-    ring[slot][2] = br[ob0];
-    ring[slot][3] = br[ob1];
+    const int sa = 4 * k * g.lda, sb = 4 * k * g.ldb;   // row byte offsets (uniform)
+    ring[slot][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, oa0, sa, 0));
+    ring[slot][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, oa1, sa, 0));
+    ring[slot][2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, ob0, sb, 0));
+    ring[slot][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, ob1, sb, 0));
   };
   // k-steps of the wave; loads run kWgPF steps ahead through the ring.  The
   // main loop has no conditional code (a step past the last one re-reads
@@ -610,23 +618,29 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
   // accumulator element v of a 32 x 32 tile: row 8 (v / 4) + 4 hi + v % 4,
   // column lo.  Waves 2, 3 park their tiles; waves 0, 1 add them; wave 1
   // parks the sum; wave 0 adds it and writes the slab.
+  // (one accumulator tile at a time: the scheduling barriers keep the
+  // compiler from reading all four tiles into registers at once)
   auto park = [&](int slot) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j) {
 #pragma unroll
         for (int v = 0; v < 16; ++v)
           red[slot][32 * i + 8 * (v / 4) + 4 * hi + (v % 4)][32 * j + lo] = acc[i][j][v];
+        __builtin_amdgcn_sched_barrier(0);
+      }
   };
   auto take = [&](int slot) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j) {
 #pragma unroll
         for (int v = 0; v < 16; ++v)
           acc[i][j][v] += red[slot][32 * i + 8 * (v / 4) + 4 * hi + (v % 4)][32 * j + lo];
+        __builtin_amdgcn_sched_barrier(0);
+      }
   };
   // the bias sums: combine the two row parities of a lane pair, then the
   // waves in the same fixed order through LDS (column 64 of the tile rows)
@@ -647,24 +661,18 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
   __syncthreads();
   if (wave == 0) {
     take(0);
-    float* C = g.C + s * g.sCs + (long long)b * g.M * g.N;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int n = n0 + 32 * j + lo;
-        if (n >= g.N) continue;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int m = m0 + 32 * i + 8 * (v / 4) + 4 * hi + (v % 4);
-          if (m < g.M) C[(long long)m * g.N + n] = acc[i][j][v];
-        }
-      }
-    if (csum_wg) {
-      const int m = m0 + lane;
-      const float v = (cred[0][lane] + cred[2][lane]) + (cred[1][lane] + cred[3][lane]);
-      if (m < g.M) g.csum[((long long)s * g.batch + b) * g.M + m] = v;
-    }
+    park(1);
+  }
+  __syncthreads();
+  // the summed tile, stored by all waves: a row per wave and store, one
+  // column per lane (256-byte row segments)
+  float* Ct = g.C + s * g.sCs + (long long)b * g.M * g.N + (long long)m0 * g.N + n0;
+  for (int r = wave; r < 64 && m0 + r < g.M; r += 4)
+    if (n0 + lane < g.N) Ct[(long long)r * g.N + lane] = red[1][r][lane];
+  if (csum_wg && wave == 0) {
+    const int m = m0 + lane;
+    const float v = (cred[0][lane] + cred[2][lane]) + (cred[1][lane] + cred[3][lane]);
+    if (m < g.M) g.csum[((long long)s * g.batch + b) * g.M + m] = v;
   }
 }
 
