@@ -556,15 +556,12 @@ def bench_training(rid, torch, steps=20, warmup=3):
     for i in range(warmup):
         rid.mf_train_step(E, *batches[i], rid.lr_exponential(E.step))
     torch.cuda.synchronize()
-    rid.profile_enable(True)
     t0 = time.perf_counter()
     losses = []
     for i in range(steps):
         losses.append(rid.mf_train_step(E, *batches[warmup + i], rid.lr_exponential(E.step)))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tot, cnt = rid.profile_read(rid.PROF_TRAIN)
-    rid.profile_enable(False)
     fl = train_flops_per_sample(n, widths, K) * B
     step_s = (t1 - t0) / steps
     # the same step at 4x the batch: its activations exceed the training
