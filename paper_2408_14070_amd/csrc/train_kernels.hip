@@ -721,6 +721,9 @@ rid_status wgrad(const WgradArgs& a, hipStream_t st) {
   // and the contraction must hold whole k-steps
   if (a.kchunk % 2 != 0 || a.Kc % 2 != 0 || a.M < 1 || a.N < 1 || a.Kc < 1)
     return fail(RID_EINVAL, "weight-gradient GEMM: bad shape");
+  // row byte offsets are 32-bit scalar offsets (passes are sized to fit)
+  if ((long long)a.Kc * std::max(a.lda, a.ldb) * 4 > 0x7FFFFFFFLL)
+    return fail(RID_EUNSUPPORTED, "weight-gradient GEMM: slab too large for 32-bit offsets");
   const dim3 grid((a.N + 63) / 64, (a.M + 63) / 64, a.batch * a.ksplit);
   hipLaunchKernelGGL(wgrad_kernel, grid, dim3(256), 0, st, a);
   RID_HIP(hipGetLastError());
@@ -744,9 +747,13 @@ rid_status colsum(const float* X, long long slab, int B, int w, int K, float* pa
 
 // Rows per pass over the batch: all B when the pass's stored activations
 // (floats_per_row floats a row) fit the budget, else equal chunks, each a
-// multiple of 64 rows and at least 64, that do.
-int chunk_rows(long long floats_per_row, int B, size_t budget) {
-  const long long fit = (long long)(budget / (sizeof(float) * (size_t)floats_per_row));
+// multiple of 64 rows and at least 64, that do.  A pass also stays below
+// the rows whose 2R-row slabs of width wmax the weight-gradient kernel can
+// address with 32-bit byte offsets (about 500 k rows at width 512).
+int chunk_rows(long long floats_per_row, int B, size_t budget, int wmax) {
+  const long long cap = ((1LL << 31) - 1) / (8LL * std::max(wmax, 1));
+  const long long fit =
+      std::min(cap, (long long)(budget / (sizeof(float) * (size_t)floats_per_row)));
   if (fit >= B) return B;
   const long long step = std::max<long long>(64, fit / 64 * 64);
   const long long chunks = (B + step - 1) / step;
@@ -789,7 +796,7 @@ rid_status mf_grad_fused(rid_ensemble_impl& e, const float* s, const float* F,
   for (int v : w) wmax = std::max(wmax, v);
   long long per_row = 0;
   for (int l = 0; l <= L; ++l) per_row += (long long)K * 2 * w[l] * (l > 0 ? 2 : 1);
-  const int Bc = chunk_rows(per_row, B, e.train_budget);
+  const int Bc = chunk_rows(per_row, B, e.train_budget, wmax);
   int ks_max, kc;
   wgrad_split(K, tiles_max, Bc, &ks_max, &kc);
   auto al = [](long long v) { return (v + 63) / 64 * 64; };
@@ -922,7 +929,7 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   // rows per pass (input mode hands per-row results back: one pass)
   long long per_row = (long long)K * (8 + (res ? 2 : 0)) * wmax;
   for (int l = 0; l <= L; ++l) per_row += (long long)K * w[l] * (l > 0 ? 5 : 2);
-  const int Bc = input_mode ? B : chunk_rows(per_row, B, e.train_budget);
+  const int Bc = input_mode ? B : chunk_rows(per_row, B, e.train_budget, wmax);
   int ks_max, kc;
   wgrad_split(K, tiles_max, Bc, &ks_max, &kc);
 
