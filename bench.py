@@ -149,6 +149,19 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def train_source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2408_14070_amd", "csrc")
+    for f in ("train_kernels.hip", "mlp_kernels.hip", "device_common.h"):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+# training kernels the counter passes summarize: key, name test
+TRAIN_PMC_KEYS = (("train_kernel_4x256_b4096", lambda n: "train_kernel<" in n),
+                  ("wgrad_kernel_4x256_b4096", lambda n: "wgrad_kernel" in n))
+
+
 def pmc_for(kernel_key):
     """Counter figures of one kernel family from the committed rocprofv3
     summary (profiles/pmc.json), if they were taken on the current kernel
@@ -158,7 +171,9 @@ def pmc_for(kernel_key):
         return None
     try:
         rec = json.load(open(path)).get(kernel_key)
-        if rec and rec.get("source_hash") == kernel_source_hash():
+        want = (train_source_hash() if kernel_key in dict(TRAIN_PMC_KEYS)
+                else kernel_source_hash())
+        if rec and rec.get("source_hash") == want:
             return rec
     except Exception:
         return None
@@ -188,7 +203,9 @@ def pmc_workload(rid, torch, reps=3):
     copy of known size (y = x * 1, reads and writes PMC_COPY_BYTES), then the
     bias path on the 200-atom chain for each PMC_CASES entry (the headline
     FP32 ensemble at 1024 walkers; the precision form's shape at 16384
-    walkers in each arithmetic), `reps` launches each."""
+    walkers in each arithmetic), `reps` launches each; then training steps
+    of the differentiation form (4 x [256 x 4], batch 4096) after as many
+    untimed ones."""
     x = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     for _ in range(reps):
@@ -202,6 +219,15 @@ def pmc_workload(rid, torch, reps=3):
             rid.bias_force(c["S"], c["E"], c["P"], 2.0, 3.0, out=c["out"])
         torch.cuda.synchronize()
         del c
+    n, widths, K, Bt = 38, [256] * 4, 4, 4096
+    s_all, F_all, _ = ridgen.mf_training_set(4 * Bt * reps, n)
+    S = torch.from_numpy(s_all).cuda()
+    F = torch.from_numpy(F_all).cuda()
+    E = rid.Ensemble(n, widths, K, ridgen.xavier_ensemble(2 * n, widths, K, 1000))
+    for i in range(2 * reps):
+        rid.mf_train_step(E, S[i * Bt:(i + 1) * Bt], F[i * Bt:(i + 1) * Bt],
+                          rid.lr_exponential(E.step))
+    torch.cuda.synchronize()
     print("pmc workload done", flush=True)
 
 
@@ -234,6 +260,10 @@ def _read_counters(d):
         con = sqlite3.connect(f)
         rows += [(k, c, float(v)) for k, c, v in
                  con.execute("select kernel_name, counter_name, value from counters_collection")]
+        # each dispatch's duration once, as the pseudo-counter _duration_ns
+        rows += [(k, "_duration_ns", float(v)) for k, v in
+                 con.execute("select kernel_name, max(duration) from counters_collection "
+                             "group by dispatch_id, kernel_name")]
         con.close()
     if not rows:
         raise SystemExit(f"no counter output under {d}")
@@ -387,6 +417,23 @@ def pmc_summary(out_path, *dirs):
         if rec.get("TCC_HIT_sum") is not None and rec.get("TCC_MISS_sum") is not None:
             tot = rec["TCC_HIT_sum"] + rec["TCC_MISS_sum"]
             rec["l2_hit"] = rec["TCC_HIT_sum"] / tot if tot else None
+        res[key] = rec
+    # the training step's kernels (bench.py --pmc-workload runs a few steps):
+    # MFMA busy as above and the effective clock = busy CU cycles per CU /
+    # the dispatch's duration
+    for key, pick in TRAIN_PMC_KEYS:
+        counters = sorted({c for (k, c) in table if pick(k)})
+        if "SQ_VALU_MFMA_BUSY_CYCLES" not in counters:
+            continue
+        rec = {"source_hash": train_source_hash()}
+        for c in counters:
+            rec[c] = mean(pick, c)
+        if rec.get("SQ_BUSY_CU_CYCLES"):
+            rec["mfma_busy"] = rec["SQ_VALU_MFMA_BUSY_CYCLES"] / (N_SIMD * rec["SQ_BUSY_CU_CYCLES"])
+            if rec.get("_duration_ns"):
+                rec["clock_ghz"] = rec["SQ_BUSY_CU_CYCLES"] / N_CU / rec["_duration_ns"]
+        if rec.get("SQ_INSTS_VALU_MFMA_MOPS_F32") is not None:
+            rec["mfma_flop"] = 512.0 * rec["SQ_INSTS_VALU_MFMA_MOPS_F32"]
         res[key] = rec
     with open(out_path, "w") as fh:
         json.dump(res, fh, indent=1)
@@ -583,6 +630,10 @@ def bench_training(rid, torch, steps=20, warmup=3):
         "flop_per_step": fl,
         "achieved_tflops": fl / step_s / 1e12, "frac_fp32_peak": fl / step_s / 1e12 / FP32_PEAK_TFLOPS,
         "loss_first_last": [float(losses[0].mean()), float(losses[-1].mean())],
+        # MFMA busy and effective clock of the step's two MFMA kernels, from
+        # the committed counter passes when they match the current sources
+        "counters": {k: {"mfma_busy": r.get("mfma_busy"), "clock_ghz": r.get("clock_ghz")}
+                     for k, r in ((k, pmc_for(k)) for k, _ in TRAIN_PMC_KEYS) if r} or None,
         "large_batch": {"batch": BL, "value": BL / big_s, "unit": "samples/s",
                         "ms_per_step": 1e3 * big_s,
                         "note": "activations of one pass over the batch (~1.1 GB) exceed "
