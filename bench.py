@@ -499,7 +499,24 @@ def cpu_baseline(case, samples, budget_s=10.0):
         single = {"value": v1, "unit": "walker-steps/s", "threads": 1,
                   "sample": f"{reps1} x 256 walkers"}
     acc = {}
+    tr = samples.get("training")
+    if tr is not None:
+        # the training step's loss and weight gradient (double backward) on
+        # its benchmarked batch against the oracle's, per member: max
+        # |dg| / max |g| over the packed parameters
+        mods = ridgen.unpack_params(tr["params"], 2 * tr["n"], tr["widths"], tr["K"])
+        g = tr["grad"].reshape(tr["K"], -1).astype(np.float64)
+        gerr, lerr = 0.0, 0.0
+        for k, m in enumerate(mods):
+            lo, go = O.train_loss_grad(m, tr["s"].astype(np.float64), tr["F"].astype(np.float64))
+            go = O.flat_grad(go)
+            gerr = max(gerr, float(np.max(np.abs(g[k] - go)) / np.max(np.abs(go))))
+            lerr = max(lerr, abs(float(tr["loss"][k]) - lo) / lo)
+        acc["training_b4096"] = {"samples": int(tr["s"].shape[0]),
+                                 "max_rel_grad_err": gerr, "max_rel_loss_err": lerr}
     for name, smp in samples.items():
+        if name == "training":
+            continue
         sm = smp["sys"]
         mods = ridgen.unpack_params(smp["params"], 2 * sm.n_cv, smp["widths"], smp["K"])
         ref = O.bias_force(smp["pos"].astype(np.float64), sm.quads, mods, 2.0, 3.0)
@@ -591,7 +608,7 @@ def bench_variants(rid, torch, sys20, steps, warmup):
     return res
 
 
-def bench_training(rid, torch, steps=20, warmup=3):
+def bench_training(rid, torch, steps=20, warmup=3, samples=None):
     n, widths, K, B = 38, [256] * 4, 4, 4096
     s_all, F_all, _ = ridgen.mf_training_set(200_000, n)
     S = torch.from_numpy(s_all).cuda()
@@ -609,6 +626,15 @@ def bench_training(rid, torch, steps=20, warmup=3):
         losses.append(rid.mf_train_step(E, *batches[warmup + i], rid.lr_exponential(E.step)))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if samples is not None:
+        # the step's loss and gradient on its last batch at the ensemble's
+        # current weights, for the CPU-baseline leg's oracle comparison
+        sb, Fb = batches[warmup + steps - 1]
+        lg, gg = rid.mf_loss_grad(E, sb, Fb)
+        torch.cuda.synchronize()
+        samples["training"] = dict(params=E.get_params(), n=n, widths=widths, K=K,
+                                   s=sb.cpu().numpy(), F=Fb.cpu().numpy(),
+                                   loss=lg.cpu().numpy(), grad=gg.cpu().numpy())
     fl = train_flops_per_sample(n, widths, K) * B
     step_s = (t1 - t0) / steps
     # the same step at 4x the batch: its activations exceed the training
@@ -1037,7 +1063,7 @@ def main():
         log("mcmc")
         rec["mcmc"] = bench_mcmc(rid, torch)
         log("training")
-        rec["training"] = bench_training(rid, torch)
+        rec["training"] = bench_training(rid, torch, samples=samples)
         log("labels")
         rec["labels"] = bench_labels(rid, torch)
         log("selection")
@@ -1056,6 +1082,8 @@ def main():
                           ("precision_form_fp32", "fp32")):
             if key in rec and name in acc:
                 rec[key]["accuracy"] = acc[name]
+        if "training" in rec and "training_b4096" in acc:
+            rec["training"]["accuracy"] = acc["training_b4096"]
     print(json.dumps(rec), flush=True)
 
 
