@@ -140,6 +140,23 @@ def time_bias(rid, torch, case, steps, warmup, eps0=2.0, eps1=3.0):
     return (t1 - t0), kern
 
 
+def call_percentiles(rid, torch, case, n=400, eps0=2.0, eps1=3.0):
+    """Per-call GPU time of the bias force: n calls, each bracketed by events
+    on the stream it runs on (torch's current stream), after the throughput
+    region; p10 / p50 / p90 in microseconds."""
+    S, E, P, out = case["S"], case["E"], case["P"], case["out"]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n)]
+    for a, b in ev:
+        a.record()
+        rid.bias_force(S, E, P, eps0, eps1, out=out)
+        b.record()
+    torch.cuda.synchronize()
+    t = np.sort(np.array([a.elapsed_time(b) * 1e3 for a, b in ev]))
+    return {"p10": float(np.percentile(t, 10)), "p50": float(np.percentile(t, 50)),
+            "p90": float(np.percentile(t, 90)), "calls": n}
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2408_14070_amd", "csrc")
@@ -553,6 +570,7 @@ def bench_precision(rid, torch, sys20, prec, name, steps, warmup, samples):
     Bb, Kb, wb = 16384, 8, [512] * 4
     cb = build_case(rid, torch, sys20, Bb, Kb, wb, prec)
     el, kern = time_bias(rid, torch, cb, steps, warmup)
+    call_pct = call_percentiles(rid, torch, cb, n=100)
     samples[name.lower()] = sample_outputs(cb, 128)
     fl = mlp_flops_per_walker(sys20.n_cv, wb, Kb) * Bb
     ach = fl / (kern["mlp"] * 1e-3) / 1e12
@@ -561,6 +579,7 @@ def bench_precision(rid, torch, sys20, prec, name, steps, warmup, samples):
         "workload": f"same chain; ensemble 8 x [512 x 4], {PRECISION_ARITH[name]}; 16384 "
                     "walkers (CVs encoded once by cv_eval, then mlp_kernel)",
         "value": Bb * steps / el, "unit": "walker-steps/s", "ms_per_step": 1e3 * el / steps,
+        "call_us_percentiles": call_pct,
         "roofline": {"bound": "mfma", "achieved": ach, "peak": peak,
                      "unit": "TFLOP/s", "frac": ach / peak,
                      "traffic": traffic_for(f"mlp_{name.lower()}_8x512_b16384"),
@@ -1007,6 +1026,7 @@ def main():
     elapsed, kern = time_bias(rid, torch, case, args.steps, args.warmup)
     ms_step = 1e3 * elapsed / args.steps
     log(f"headline: {ms_step * 1e3:.1f} us per step")
+    call_pct = call_percentiles(rid, torch, case)
     value = B * args.steps / elapsed
     flop_launch = mlp_flops_per_walker(sys20.n_cv, widths, K) * B
     achieved = flop_launch / (kern["mlp"] * 1e-3) / 1e12
@@ -1039,6 +1059,7 @@ def main():
         "kernels_us": {k: v * 1e3 for k, v in kern.items()},
         "kernel_events": f"1 call in {EVENT_EVERY} of the timed region",
         "latency_us_per_call": ms_step * 1e3,
+        "call_us_percentiles": call_pct,
     }
     samples = {"fp32_headline": sample_outputs(case, 128)}
     if not args.no_extra:
