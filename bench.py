@@ -668,6 +668,24 @@ def bench_training(rid, torch, steps=20, warmup=3, samples=None):
         rid.mf_train_step(E, *big[1 + i], rid.lr_exponential(E.step))
     torch.cuda.synchronize()
     big_s = (time.perf_counter() - t2) / big_steps
+    # the paper's own Train example (chignolin: 18 torsion CVs, 4 x [300 x 4],
+    # residual connections, dropout 0.1, batch 128): the general sweeps
+    pn, pw, pK, pB = 18, [300] * 4, 4, 128
+    ps_all, pF_all, _ = ridgen.mf_training_set(pB * 64, pn)
+    PS = torch.from_numpy(ps_all).cuda()
+    PF = torch.from_numpy(pF_all).cuda()
+    PE = rid.Ensemble(pn, pw, pK, ridgen.xavier_ensemble(2 * pn, pw, pK, 1000))
+    PE.set_resnet(True)
+    PE.set_dropout(0.1, seed=7)
+    pb = [(PS[i * pB:(i + 1) * pB], PF[i * pB:(i + 1) * pB]) for i in range(64)]
+    for i in range(8):
+        rid.mf_train_step(PE, *pb[i], rid.lr_exponential(PE.step))
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for i in range(8, 64):
+        rid.mf_train_step(PE, *pb[i], rid.lr_exponential(PE.step))
+    torch.cuda.synchronize()
+    paper_s = (time.perf_counter() - t3) / 56
     return {
         "workload": "mean-force fitting, 38 CVs, ensemble 4 x [256 x 4], batch 4096 from "
                     "200k resident samples, double backward + Adam, FP32",
@@ -683,6 +701,10 @@ def bench_training(rid, torch, steps=20, warmup=3, samples=None):
                         "ms_per_step": 1e3 * big_s,
                         "note": "activations of one pass over the batch (~1.1 GB) exceed "
                                 "the 512 MiB training budget: the step runs in row chunks"},
+        "paper_train_example": {"workload": "18 torsion CVs, 4 x [300 x 4], residual, "
+                                            "dropout 0.1, batch 128 (separate GEMM sweeps)",
+                                "value": pB / paper_s, "unit": "samples/s",
+                                "ms_per_step": 1e3 * paper_s},
     }
 
 
