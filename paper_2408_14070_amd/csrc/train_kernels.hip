@@ -78,9 +78,9 @@ struct GemmArgs {
 // k fastest; 1 scalar, rows fastest; 2 float4 along k (sK == 1); 3 float4
 // along rows (sR == 1).  The float4 modes need 16-byte alignment and an
 // extent along the vector that is a multiple of 4 (gemm() checks).
-template <int TR>
+template <int TR, int BKT = BK>
 struct TileLoad {
-  static constexpr int NS = TR * BK / kThreads;   // elements per thread
+  static constexpr int NS = TR * BKT / kThreads;   // elements per thread
   float v[NS];
   __device__ inline void load(const float* X, long long sR, long long sK, int mode, int r0,
                               int R, int kb, int k_end, int tid) {
@@ -90,7 +90,7 @@ struct TileLoad {
       for (int j = 0; j < NS / 4; ++j) {
         const int idx = tid + kThreads * j;
         int r, k;
-        if (mode == 2) { r = idx / (BK / 4); k = (idx % (BK / 4)) * 4; }
+        if (mode == 2) { r = idx / (BKT / 4); k = (idx % (BKT / 4)) * 4; }
         else { k = idx / (TR / 4); r = (idx % (TR / 4)) * 4; }
         const int gr = r0 + r, gk = kb + k;
         f4 x = f4{0.f, 0.f, 0.f, 0.f};
@@ -102,20 +102,20 @@ struct TileLoad {
       for (int j = 0; j < NS; ++j) {
         const int idx = tid + kThreads * j;
         int r, k;
-        if (mode == 0) { k = idx % BK; r = idx / BK; } else { r = idx % TR; k = idx / TR; }
+        if (mode == 0) { k = idx % BKT; r = idx / BKT; } else { r = idx % TR; k = idx / TR; }
         const int gr = r0 + r, gk = kb + k;
         v[j] = (gr < R && gk < k_end) ? X[gr * sR + gk * sK] : 0.f;
       }
     }
   }
-  __device__ inline void store(float (*S)[LDK], int mode, int tid) const {
+  __device__ inline void store(float (*S)[BKT + 4], int mode, int tid) const {
     if (NS < 4 && mode >= 2) mode -= 2;
     if (mode >= 2) {
 #pragma unroll
       for (int j = 0; j < NS / 4; ++j) {
         const int idx = tid + kThreads * j;
         if (mode == 2) {
-          const int r = idx / (BK / 4), k = (idx % (BK / 4)) * 4;
+          const int r = idx / (BKT / 4), k = (idx % (BKT / 4)) * 4;
           *reinterpret_cast<f4*>(&S[r][k]) = f4{v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]};
         } else {
           const int k = idx / (TR / 4), r = (idx % (TR / 4)) * 4;
@@ -128,7 +128,7 @@ struct TileLoad {
       for (int j = 0; j < NS; ++j) {
         const int idx = tid + kThreads * j;
         int r, k;
-        if (mode == 0) { k = idx % BK; r = idx / BK; } else { r = idx % TR; k = idx / TR; }
+        if (mode == 0) { k = idx % BKT; r = idx / BKT; } else { r = idx % TR; k = idx / TR; }
         S[r][k] = v[j];
       }
     }
@@ -141,15 +141,19 @@ __device__ inline float tanh_fast(float z) {
 }
 
 // C[b] = A[b] (M x Kc) * B[b] (Kc x N) on FP32 MFMA, tiles of TM x TN with
-// 4 waves of (TM/2) x (TN/2); operands staged through double-buffered LDS.
-// 128 x 128 tiles (16 accumulator tiles per wave) reuse each LDS operand
-// fragment four times; 64 x 64 tiles serve narrow shapes.
-template <int TM, int TN>
+// 4 waves of (TM/2) x (TN/2); operands staged through double-buffered LDS
+// in contraction blocks of BKT.  128 x 128 tiles (16 accumulator tiles per
+// wave) reuse each LDS operand fragment four times; 64 x 64 tiles serve
+// narrow shapes.  Grids too small to fill the chip (small batches) take
+// 64-deep blocks: each block costs about one memory latency, so a deeper
+// block divides the latency-bound time of such a GEMM by four.
+template <int TM, int TN, int BKT = BK>
 __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
   constexpr int WM = TM / 2, WN = TN / 2;           // wave tile
   constexpr int TI = WM / 16, TJ = WN / 16;         // 16 x 16 MFMA tiles per wave
-  __shared__ __attribute__((aligned(16))) float As[2][TM][LDK];
-  __shared__ __attribute__((aligned(16))) float Bs[2][TN][LDK];
+  static_assert(BKT % 16 == 0, "contraction blocks of whole 16-deep MFMA sets");
+  __shared__ __attribute__((aligned(16))) float As[2][TM][BKT + 4];
+  __shared__ __attribute__((aligned(16))) float Bs[2][TN][BKT + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int b = blockIdx.z / g.ksplit, s = blockIdx.z % g.ksplit;
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
@@ -157,8 +161,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
   const int k_end = min(g.Kc, k_begin + g.kchunk);
   const float* A = g.A + b * g.sAb;
   const float* Bp = g.Bm + b * g.sBb;
-  TileLoad<TM> ta;
-  TileLoad<TN> tb;
+  TileLoad<TM, BKT> ta;
+  TileLoad<TN, BKT> tb;
   auto load = [&](int kb) {
     ta.load(A, g.sAm, g.sAk, g.modeA, m0, g.M, kb, k_end, tid);
     tb.load(Bp, g.sBn, g.sBk, g.modeB, n0, g.N, kb, k_end, tid);
@@ -180,23 +184,27 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
   load(k_begin);
   store(0);
   __syncthreads();
-  for (int kb = k_begin; kb < k_end; kb += BK) {
-    const bool more = kb + BK < k_end;
-    if (more) load(kb + BK);
-    f4 a[TI], bb[TJ];
+  for (int kb = k_begin; kb < k_end; kb += BKT) {
+    const bool more = kb + BKT < k_end;
+    if (more) load(kb + BKT);
 #pragma unroll
-    for (int i = 0; i < TI; ++i)
-      a[i] = *reinterpret_cast<const f4*>(&As[buf][wm + i * 16 + r][4 * gq]);
-#pragma unroll
-    for (int j = 0; j < TJ; ++j)
-      bb[j] = *reinterpret_cast<const f4*>(&Bs[buf][wn + j * 16 + r][4 * gq]);
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int sb = 0; sb < BKT / 16; ++sb) {
+      f4 a[TI], bb[TJ];
 #pragma unroll
       for (int i = 0; i < TI; ++i)
+        a[i] = *reinterpret_cast<const f4*>(&As[buf][wm + i * 16 + r][16 * sb + 4 * gq]);
 #pragma unroll
-        for (int j = 0; j < TJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][e], bb[j][e], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < TJ; ++j)
+        bb[j] = *reinterpret_cast<const f4*>(&Bs[buf][wn + j * 16 + r][16 * sb + 4 * gq]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+            acc[i][j] =
+                __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][e], bb[j][e], acc[i][j], 0, 0, 0);
+    }
     if (more) {
       store(buf ^ 1);
       __syncthreads();
@@ -689,6 +697,9 @@ int load_mode(const float* X, long long sR, long long sK, long long sBatch, int 
   return 0;
 }
 
+#ifndef RID_GEMM_DEEP_WGS
+#define RID_GEMM_DEEP_WGS 256
+#endif
 rid_status gemm(const GemmArgs& g0, hipStream_t st) {
   GemmArgs g = g0;
   if (g.ksplit < 1) g.ksplit = 1;
@@ -707,7 +718,12 @@ rid_status gemm(const GemmArgs& g0, hipStream_t st) {
     hipLaunchKernelGGL((gemm_f32_kernel<128, 128>), grid, dim3(kThreads), 0, st, g);
   } else if (g.M > 32 && tiles64 < 512) {
     dim3 grid((g.N + 63) / 64, (g.M + 31) / 32, g.batch * g.ksplit);
-    hipLaunchKernelGGL((gemm_f32_kernel<32, 64>), grid, dim3(kThreads), 0, st, g);
+    // fewer workgroups than CUs: latency-bound, 64-deep contraction blocks
+    const long long wgs = (long long)grid.x * grid.y * grid.z;
+    if (wgs < RID_GEMM_DEEP_WGS && g.kchunk >= 64)
+      hipLaunchKernelGGL((gemm_f32_kernel<32, 64, 64>), grid, dim3(kThreads), 0, st, g);
+    else
+      hipLaunchKernelGGL((gemm_f32_kernel<32, 64>), grid, dim3(kThreads), 0, st, g);
   } else {
     dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.batch * g.ksplit);
     hipLaunchKernelGGL((gemm_f32_kernel<64, 64>), grid, dim3(kThreads), 0, st, g);
