@@ -526,9 +526,10 @@ struct WgradArgs {
   const float* B;
   long long sBb;
   int ldb;
-  float* C;           // partial slab s of member b: C + s*sCs + b*M*N, [M][N]
-  long long sCs;
-  float* csum;        // [ks][batch][M] or null
+  float* C;           // tile of split s, member b: C + s*sCs + b*sCb, [M][N]
+  long long sCs, sCb;
+  float* csum;        // bias sums of split s, member b: csum + s*csum_ss + b*csum_sb, [M]
+  long long csum_ss, csum_sb;
   int csum_rows;
   int M, N, Kc, batch, ksplit, kchunk;
 };
@@ -674,13 +675,13 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs g) {
   __syncthreads();
   // the summed tile, stored by all waves: a row per wave and store, one
   // column per lane (256-byte row segments)
-  float* Ct = g.C + s * g.sCs + (long long)b * g.M * g.N + (long long)m0 * g.N + n0;
+  float* Ct = g.C + s * g.sCs + b * g.sCb + (long long)m0 * g.N + n0;
   for (int r = wave; r < 64 && m0 + r < g.M; r += 4)
     if (n0 + lane < g.N) Ct[(long long)r * g.N + lane] = red[1][r][lane];
   if (csum_wg && wave == 0) {
     const int m = m0 + lane;
     const float v = (cred[0][lane] + cred[2][lane]) + (cred[1][lane] + cred[3][lane]);
-    if (m < g.M) g.csum[((long long)s * g.batch + b) * g.M + m] = v;
+    if (m < g.M) g.csum[s * g.csum_ss + b * g.csum_sb + m] = v;
   }
 }
 
@@ -742,6 +743,31 @@ rid_status wgrad(const WgradArgs& a, hipStream_t st) {
     return fail(RID_EUNSUPPORTED, "weight-gradient GEMM: slab too large for 32-bit offsets");
   const dim3 grid((a.N + 63) / 64, (a.M + 63) / 64, a.batch * a.ksplit);
   hipLaunchKernelGGL(wgrad_kernel, grid, dim3(256), 0, st, a);
+  RID_HIP(hipGetLastError());
+  return RID_OK;
+}
+
+// dW_l and db_l of one chunk of rows into the gradient (member k at
+// G + k*pm, dW_l at w_off, db_l at b_off).  With one split and no earlier
+// chunk to add to, the kernel writes the gradient itself; otherwise it
+// writes one slab per split (part, bpart) and splitk_reduce_kernel adds them
+// in split order, onto the gradient when accumulate is set.  The operands,
+// shape and split of g are set by the caller.
+rid_status wgrad_into_grad(WgradArgs g, float* part, float* bpart, float* G, long long pm,
+                           long long w_off, long long b_off, bool accumulate, hipStream_t st) {
+  rid_status rs;
+  const long long mn = (long long)g.M * g.N;
+  if (g.ksplit == 1 && !accumulate) {
+    g.C = G + w_off; g.sCs = 0; g.sCb = pm;
+    g.csum = G + b_off; g.csum_ss = 0; g.csum_sb = pm;
+    return wgrad(g, st);
+  }
+  g.C = part; g.sCs = g.batch * mn; g.sCb = mn;
+  g.csum = bpart; g.csum_ss = (long long)g.batch * g.M; g.csum_sb = g.M;
+  if ((rs = wgrad(g, st)) != RID_OK) return rs;
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid1d(g.batch * (long long)g.M * (g.N + 1))),
+                     dim3(256), 0, st, part, g.batch * mn, g.ksplit, g.M, g.N, g.batch, G, pm,
+                     (int)w_off, accumulate ? 1 : 0, bpart, (int)b_off);
   RID_HIP(hipGetLastError());
   return RID_OK;
 }
@@ -869,15 +895,11 @@ rid_status mf_grad_fused(rid_ensemble_impl& e, const float* s, const float* F,
       WgradArgs g{};
       g.A = W + sl[l - 1]; g.sAb = 2LL * R * w[l]; g.lda = w[l];
       g.B = W + hh[l - 1]; g.sBb = 2LL * R * w[l - 1]; g.ldb = w[l - 1];
-      g.C = W + part; g.sCs = (long long)K * w[l] * w[l - 1];
-      g.csum = W + bpart; g.csum_rows = R;
+      g.csum_rows = R;
       g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * R; g.batch = K; g.ksplit = ks; g.kchunk = kchunk;
-      if ((rs = wgrad(g, st)) != RID_OK) return rs;
-      hipLaunchKernelGGL(splitk_reduce_kernel,
-                         dim3(grid1d((long long)K * w[l] * (w[l - 1] + 1))), dim3(256), 0, st,
-                         W + part, (long long)K * w[l] * w[l - 1], ks, w[l], w[l - 1], K,
-                         G, pm, (int)w_off[l - 1], acc ? 1 : 0, W + bpart, (int)b_off[l - 1]);
-      RID_HIP(hipGetLastError());
+      if ((rs = wgrad_into_grad(g, W + part, W + bpart, G, pm, w_off[l - 1], b_off[l - 1], acc,
+                                st)) != RID_OK)
+        return rs;
     }
     if ((rs = colsum(W + hh[L] + (long long)R * w[L], 2LL * R * w[L], R, w[L], K, W + cpart,
                      G, pm, (int)wo_off, acc, st)) != RID_OK)
@@ -1083,18 +1105,13 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
         WgradArgs g{};
         g.A = W + sbuf; g.sAb = 2LL * R * w[l]; g.lda = w[l];
         g.B = W + hh[l - 1]; g.sBb = slab(l - 1); g.ldb = w[l - 1];
-        g.C = W + part; g.sCs = (long long)K * w[l] * w[l - 1];
         // db_l = sum over the primal rows of lam_z, in the same pass
-        g.csum = W + bpart; g.csum_rows = R;
+        g.csum_rows = R;
         g.M = w[l]; g.N = w[l - 1]; g.Kc = 2 * R; g.batch = K; g.ksplit = ks;
         g.kchunk = kchunk;
-        if ((rs = wgrad(g, st)) != RID_OK) return rs;
-        hipLaunchKernelGGL(splitk_reduce_kernel,
-                           dim3(grid1d((long long)K * w[l] * (w[l - 1] + 1))), dim3(256), 0, st,
-                           W + part, (long long)K * w[l] * w[l - 1], ks, w[l], w[l - 1], K,
-                           G, pm, (int)w_off[l - 1], acc ? 1 : 0, W + bpart,
-                           (int)b_off[l - 1]);
-        RID_HIP(hipGetLastError());
+        if ((rs = wgrad_into_grad(g, W + part, W + bpart, G, pm, w_off[l - 1], b_off[l - 1],
+                                  acc, st)) != RID_OK)
+          return rs;
       }
       if (l > 1 || input_mode) {
         // [lam_h ; lam_hd]_{l-1} = [lam_z ; lam_zd] W_l (+ [lam_h ; lam_hd]_l)
