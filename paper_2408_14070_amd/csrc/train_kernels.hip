@@ -474,22 +474,35 @@ __global__ void splitk_reduce_kernel(const float* part, long long slab_s, int ks
   }
 }
 
-__global__ void loss_reduce_kernel(const float* rows, int B, float* loss) {
+// The step's last launch, one block per member k: the loss, the mean of the
+// member's per-row losses rows[k][0:B] (each thread adds its rows in row
+// order, eight loads in flight, then a fixed pairwise tree), and the output
+// bias's gradient set to zero (it never reaches grad_s A).
+__global__ __launch_bounds__(256) void train_finish_kernel(const float* rows, int B, float* loss,
+                                                           float* grad, long long per_model,
+                                                           int zero_off) {
   __shared__ float red[256];
   const int k = blockIdx.x;
+  if (threadIdx.x == 0 && grad) grad[k * per_model + zero_off] = 0.f;
+  if (!rows || !loss) return;     // uniform over the block
+  const float* r = rows + (long long)k * B;
   float acc = 0.f;
-  for (int b = threadIdx.x; b < B; b += 256) acc += rows[(long long)k * B + b];
+  int b = threadIdx.x;
+  for (; b + 7 * 256 < B; b += 8 * 256) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = r[b + j * 256];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += v[j];
+  }
+  for (; b < B; b += 256) acc += r[b];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && loss) loss[k] = red[0] / (float)B;
-}
-
-__global__ void set_zero_kernel(float* grad, long long per_model, int off, int K) {
-  for (int k = threadIdx.x; k < K; k += blockDim.x) grad[k * per_model + off] = 0.f;
+  if (threadIdx.x == 0) loss[k] = red[0] / (float)B;
 }
 
 __global__ void adam_kernel(float* theta, float* m, float* v, const float* g,
@@ -905,12 +918,8 @@ rid_status mf_grad_fused(rid_ensemble_impl& e, const float* s, const float* F,
                      G, pm, (int)wo_off, acc, st)) != RID_OK)
       return rs;
   }
-  if (!rho) {
-    hipLaunchKernelGGL(loss_reduce_kernel, dim3(K), dim3(256), 0, st, W + lrows, B, loss);
-    RID_HIP(hipGetLastError());
-  }
-  hipLaunchKernelGGL(set_zero_kernel, dim3(1), dim3(64), 0, st, G, pm,
-                     (int)(wo_off + w[L]), K);
+  hipLaunchKernelGGL(train_finish_kernel, dim3(K), dim3(256), 0, st,
+                     rho ? nullptr : W + lrows, B, loss, G, pm, (int)(wo_off + w[L]));
   RID_HIP(hipGetLastError());
   return RID_OK;
 }
@@ -1142,13 +1151,9 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
                      (int)wo_off, acc, st)) != RID_OK)
       return rs;
   }
-  if (!rho) {
-    hipLaunchKernelGGL(loss_reduce_kernel, dim3(K), dim3(256), 0, st, W + lrows, B, loss);
-    RID_HIP(hipGetLastError());
-  }
-  // db_o = 0: the output bias never reaches grad_s A
-  hipLaunchKernelGGL(set_zero_kernel, dim3(1), dim3(64), 0, st, G, pm,
-                     (int)(wo_off + w[L]), K);
+  // the loss, and db_o = 0 (the output bias never reaches grad_s A)
+  hipLaunchKernelGGL(train_finish_kernel, dim3(K), dim3(256), 0, st,
+                     rho ? nullptr : W + lrows, B, loss, G, pm, (int)(wo_off + w[L]));
   RID_HIP(hipGetLastError());
   return RID_OK;
 }
