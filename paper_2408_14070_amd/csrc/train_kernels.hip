@@ -457,19 +457,33 @@ __global__ void splitk_reduce_kernel(const float* part, long long slab_s, int ks
   const long long all = total + (bpart ? (long long)K * out : 0);
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < all;
        e += (long long)gridDim.x * blockDim.x) {
-    float acc = 0.f;
     float* o;
+    const float* src;
+    long long stride;
     if (e < total) {
-      for (int s = 0; s < ks; ++s) acc += part[s * slab_s + e];
+      src = part + e;
+      stride = slab_s;
       const int k = (int)(e / ((long long)out * in));
       const long long r = e - (long long)k * out * in;
       o = grad + k * per_model + w_off + r;
     } else {
       const long long eb = e - total;                 // k * out + j
-      for (int s = 0; s < ks; ++s) acc += bpart[s * (long long)K * out + eb];
+      src = bpart + eb;
+      stride = (long long)K * out;
       const int k = (int)(eb / out);
       o = grad + k * per_model + b_off + (eb - (long long)k * out);
     }
+    // slabs added in order, eight loads in flight
+    float acc = 0.f;
+    int s = 0;
+    for (; s + 8 <= ks; s += 8) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = src[(s + j) * stride];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc += v[j];
+    }
+    for (; s < ks; ++s) acc += src[s * stride];
     *o = accumulate ? *o + acc : acc;
   }
 }
