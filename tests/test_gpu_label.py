@@ -52,3 +52,23 @@ def test_label_wrap_edge(torch, rid):
     Fr, _, _ = O.mf_label(traj, s0, np.array([500.0]), np.array([1]), 5.0)
     assert abs(F.item() - Fr[0, 0]) <= 1e-12 * abs(Fr[0, 0])
     assert keep.item() == 1
+
+
+@pytest.mark.parametrize("M,T,n", [(5, 500, 38), (3, 257, 3)])
+def test_label_unaligned_slab(torch, rid, M, T, n):
+    """A trajectory that does not start on 16 bytes gives the same bits as
+    an aligned copy of it."""
+    traj, s0, _ = ridgen.restrained_traj(M, T, n, 500.0, seed=7 * T + n)
+    kappa = np.full(n, 500.0, np.float32)
+    t = torch.from_numpy(traj).cuda()
+    buf = torch.zeros(M * T * n + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = t.reshape(-1)
+    tu = buf[1:].view(M, T, n)
+    assert tu.data_ptr() % 16 != 0
+    s0d = torch.from_numpy(s0).cuda()
+    Fa, sea, ka = rid.mf_label(t, s0d, kappa, None, 1.5)
+    Fu, seu, ku = rid.mf_label(tu, s0d, kappa, None, 1.5)
+    torch.cuda.synchronize()
+    assert torch.equal(Fa, Fu) and torch.equal(sea, seu) and torch.equal(ka, ku)
+    Fr, _, _ = O.mf_label(traj, s0, kappa, np.ones(n, np.uint8), 1.5)
+    assert np.max(np.abs(Fu.cpu().numpy() - Fr) / np.maximum(np.abs(Fr), 1.0)) <= 1e-12
