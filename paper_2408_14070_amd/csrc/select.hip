@@ -142,18 +142,20 @@ __global__ __launch_bounds__(kMatchWaves * kWave) void sel_match_kernel(ClusterA
 // mask words come in one batch of loads, the unmatched frames' CVs in groups
 // of up to gmax frames.  Per group, the four waves first match every frame
 // against the chunk's leaders founded before the group (its first match
-// overall if any, since later leaders only append); wave 0 then walks the
-// group in order and founds a leader at the first frame still unmatched,
-// after which the rest of the group is matched in parallel against that
-// leader before the walk resumes, so every frame meets the leaders founded
-// before it in founding order.  If the LDS holds nlmax new leaders when
+// overall if any, since later leaders only append); the walk then founds a
+// leader at the first frame still unmatched, after which the rest of the
+// group is matched in parallel against that leader before the walk
+// resumes, so every frame meets the leaders founded before it in founding
+// order.  If the cap is full or the LDS holds nlmax new leaders when
 // another is due, the walk stops at that frame and the next chunk starts
 // there.  The mask words read are cleared for the next round.
 constexpr int kResolveWaves = 4;
+constexpr int kXbBatch = 16;
 __global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(ClusterArgs a,
                                                                             int nlmax, int gmax) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ int sh[4];             // new leaders so far, stop frame, over the cap, walk start
+  __shared__ int sh[6];   // new leaders so far, stop frame, over the cap, walk start,
+                          // end of the matched run, the frame founding a leader
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   const int f0 = a.state[1];
   if (f0 >= a.B) return;
@@ -198,9 +200,31 @@ __global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(Clus
     }
     if (g == 0) break;
     __syncthreads();
-    for (int e = tid; e < g * n; e += kResolveWaves * kWave) {
-      const int q = e / n, i = e - q * n;
-      XB[e] = a.s[(size_t)grp[q] * n + i];
+    // the group's CVs into LDS, kXbBatch loads in flight per thread (element
+    // e = q n + i stepped by the thread count without divisions; past the
+    // end, q is clamped to the last frame and the value is not stored)
+    {
+      constexpr int kNT = kResolveWaves * kWave;
+      const int tot = g * n, dq = kNT / n, di = kNT % n;
+      for (int e0 = 0; e0 < tot; e0 += kXbBatch * kNT) {
+        int q = (e0 + tid) / n, i = (e0 + tid) - q * n;
+        float v[kXbBatch];
+#pragma unroll
+        for (int j = 0; j < kXbBatch; ++j) {
+          v[j] = a.s[(size_t)grp[min(q, g - 1)] * n + i];
+          q += dq;
+          i += di;
+          if (i >= n) {
+            i -= n;
+            ++q;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kXbBatch; ++j) {
+          const int e = e0 + tid + j * kNT;
+          if (e < tot) XB[e] = v[j];
+        }
+      }
     }
     __syncthreads();
     for (int q = wave; q < g; q += kResolveWaves) {
@@ -214,53 +238,67 @@ __global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(Clus
       if (lane == 0) gm[q] = hitj;
     }
     __syncthreads();
-    // ordered walk: wave 0 labels matched frames and founds a leader at the
-    // first unmatched one; the rest of the group is then matched in parallel
-    // (a thread per frame) against that new leader before the walk goes on
+    // ordered walk: wave 0 finds the first frame at or after the walk's
+    // start that no leader matches (a ballot per 64 frames); the frames
+    // before it are labelled in parallel, and it founds a leader, after
+    // which the rest of the group is matched in parallel against that
+    // leader before the walk goes on.  With no room for another leader
+    // (the cap is full, or this launch's LDS rows are) the walk stops at
+    // that frame instead, and the next round starts there: its match kernel
+    // then labels every remaining frame against all leaders, in parallel.
     int start = 0;
     for (;;) {
       if (wave == 0) {
-        int n_new = sh[0], over = sh[2], stop = f_end, next = g, founded = 0;
-        for (int q = start; q < g; ++q) {
-          const int fq = grp[q];
-          int out;
-          if (gm[q] >= 0) {
-            out = n_start + gm[q];
-          } else if (n_start + n_new >= a.cap) {
-            out = kOverCap;
-            over = 1;
-          } else if (n_new >= nlmax) {
-            stop = fq;
+        int first = g;
+        for (int q0 = start; q0 < g; q0 += kWave) {
+          const int q = q0 + lane;
+          const unsigned long long m = __ballot(q < g && gm[q] < 0);
+          if (m) {
+            first = q0 + __ffsll((long long)m) - 1;
             break;
-          } else {
-            out = n_start + n_new;
-            const float* xq = XB + (size_t)q * n;
-            for (int i = lane; i < n; i += kWave) {
-              NL[(size_t)n_new * n + i] = xq[i];
-              a.LT[(size_t)i * a.cap + out] = xq[i];
-            }
-            if (lane == 0) a.leader[out] = fq;
-            ++n_new;
-            founded = 1;
-            next = q + 1;
           }
-          if (lane == 0) a.labels[fq] = out;
-          if (founded) break;
         }
         if (lane == 0) {
-          sh[0] = n_new;
-          sh[1] = stop;
-          sh[2] = over;
-          sh[3] = founded ? next : g;
+          const int n_new = sh[0];
+          int next = g, lead = -1;
+          if (first < g) {
+            if (n_start + n_new >= a.cap || n_new >= nlmax) {
+              sh[1] = grp[first];
+              next = first;
+            } else {
+              lead = first;
+              next = first + 1;
+              sh[0] = n_new + 1;
+            }
+          }
+          sh[3] = next;
+          sh[4] = first;
+          sh[5] = lead;
         }
       }
       __syncthreads();
+      const int mend = sh[4], lead = sh[5], jn = sh[0] - 1;
+      for (int q = start + tid; q < mend; q += kResolveWaves * kWave)
+        a.labels[grp[q]] = n_start + gm[q];
+      if (lead >= 0) {
+        const int out = n_start + jn;
+        const float* xl = XB + (size_t)lead * n;
+        for (int i = tid; i < n; i += kResolveWaves * kWave) {
+          NL[(size_t)jn * n + i] = xl[i];
+          a.LT[(size_t)i * a.cap + out] = xl[i];
+        }
+        if (tid == 0) {
+          a.leader[out] = grp[lead];
+          a.labels[grp[lead]] = out;
+        }
+      }
       start = sh[3];
       if (sh[1] != f_end || start >= g) break;
-      const int jn = sh[0] - 1;                  // the leader just founded
+      // (the new leader's CVs are read from the group tile, where they are
+      // already in place for every thread)
+      const float* xl = XB + (size_t)lead * n;
       for (int q = start + tid; q < g; q += kResolveWaves * kWave)
-        if (gm[q] < 0 && leader_d2(NL + (size_t)jn * n, 1, XB + (size_t)q * n, n, a.raw, a.w) <= a.t2)
-          gm[q] = jn;
+        if (gm[q] < 0 && leader_d2(xl, 1, XB + (size_t)q * n, n, a.raw, a.w) <= a.t2) gm[q] = jn;
       __syncthreads();
     }
     __syncthreads();
@@ -308,7 +346,8 @@ rid_status cluster_once(ClusterArgs a, float t, int nlmax, int gmax, hipStream_t
     attr = lds;
   }
   // rounds: chunks growing from 64 frames until they cover B, then one full
-  // chunk per possible LDS stop (each stop founds nlmax leaders) and one more
+  // chunk per possible stop: one per nlmax leaders founded (a launch's LDS
+  // rows), one where the cap fills, and one more
   long long covered = 0;
   int c = 64;
   std::vector<int> chunks;
@@ -318,7 +357,7 @@ rid_status cluster_once(ClusterArgs a, float t, int nlmax, int gmax, hipStream_t
     c = std::min(2 * c, kChunkMax);
   }
   const int stops = (a.cap + nlmax - 1) / nlmax;
-  for (int i = 0; i <= stops; ++i) chunks.push_back(kChunkMax);
+  for (int i = 0; i <= stops + 1; ++i) chunks.push_back(kChunkMax);
   for (int ch : chunks) {
     a.chunk = ch;
     hipLaunchKernelGGL(sel_match_kernel, dim3((ch + kMatchWaves - 1) / kMatchWaves),
