@@ -30,10 +30,19 @@ __global__ __launch_bounds__(kPrepWaves * kWave) void cons_prep_kernel(
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int w = blockIdx.x * kPrepWaves + wave;
   if (w >= B) return;
-  const double e = ensemble_stats(g, K, B, n, w, gbar + (size_t)w * n, lane);
-  double abar = 0.0;
-  for (int k = 0; k < K; ++k) abar += (double)A[(size_t)k * B + w];
-  abar /= K;
+  // the members' results in registers, loaded in one batch, when they fit
+  // (same arithmetic, same order as the load-as-you-go form)
+  const bool reg = K <= kRegMembers && n <= kRegPasses * kWave;
+  WalkerRegs r;
+  double e, abar = 0.0;
+  if (reg) {
+    walker_prefetch(r, A, g, nullptr, K, B, n, w, lane);
+    e = scatter_stats_reg(r, K, n, gbar + (size_t)w * n, abar, lane);
+  } else {
+    e = ensemble_stats(g, K, B, n, w, gbar + (size_t)w * n, lane);
+    for (int k = 0; k < K; ++k) abar += (double)A[(size_t)k * B + w];
+    abar /= K;
+  }
   const float sig = switch_outputs(e, abar, eps0, eps1, w, energy, eps_out, sigma_out, lane, 1);
   double slope = 0.0;
   if (e >= eps0 && e < eps1) {
@@ -45,6 +54,26 @@ __global__ __launch_bounds__(kPrepWaves * kWave) void cons_prep_kernel(
     sig_w[w] = sig;
   }
   const bool on = slope != 0.0 && e > 0.0;
+  if (reg) {
+#pragma unroll
+    for (int p = 0; p < kRegPasses; ++p) {
+      const int i = lane + p * kWave;
+      if (i < n) {
+        double gs = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRegMembers; ++k)
+          if (k < K) gs += (double)r.g[p][k];
+        const double gb = gs / K;
+#pragma unroll
+        for (int k = 0; k < kRegMembers; ++k)
+          if (k < K) {
+            const double d = (double)r.g[p][k] - gb;
+            rho[((size_t)w * K + k) * n + i] = on ? (float)(d / (K * e)) : 0.f;
+          }
+      }
+    }
+    return;
+  }
   for (int i = lane; i < n; i += kWave) {
     double gs = 0.0;
     for (int k = 0; k < K; ++k) gs += (double)g[((size_t)k * B + w) * n + i];
@@ -96,8 +125,19 @@ __global__ void cons_combine_terms_kernel(const float* T, const float* gbar, con
     const int b = (int)(e / n);
     const float cb = coef[b];
     float de = 0.f;
-    if (cb != 0.f)
-      for (int k = 0; k < K; ++k) de += T[k * total + e];
+    if (cb != 0.f) {
+      if (K <= kRegMembers) {
+        // every member's term in flight at once, added in member order
+        float t[kRegMembers];
+#pragma unroll
+        for (int k = 0; k < kRegMembers; ++k) t[k] = T[min(k, K - 1) * total + e];
+#pragma unroll
+        for (int k = 0; k < kRegMembers; ++k)
+          if (k < K) de += t[k];
+      } else {
+        for (int k = 0; k < K; ++k) de += T[k * total + e];
+      }
+    }
     fcv[e] = sig_w[b] * gbar[e] + cb * de;
   }
 }
