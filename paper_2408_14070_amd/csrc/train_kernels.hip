@@ -82,45 +82,64 @@ template <int TR, int BKT = BK>
 struct TileLoad {
   static constexpr int NS = TR * BKT / kThreads;   // elements per thread
   float v[NS];
+  // Branch-free loads (the mode is uniform; the two mappings are selected,
+  // an element outside the operand reads its first one), so every load of a
+  // tile is in flight before anything waits on one.  The outside elements
+  // are zeroed when the tile is stored to LDS, after the block's MFMAs.
+  // VEC: the float4 modes (chosen at compile time, so that no branch joins
+  // the two load paths: a join makes the compiler wait on the loads there).
+  unsigned long long in_mask;
+  template <bool VEC>
   __device__ inline void load(const float* X, long long sR, long long sK, int mode, int r0,
                               int R, int kb, int k_end, int tid) {
-    if (NS < 4 && mode >= 2) mode -= 2;   // too few elements per thread for float4
-    if (mode >= 2) {
+    static_assert(NS <= 64, "one mask bit per element");
+    in_mask = 0ull;
+    if constexpr (VEC && NS >= 4) {
+      const bool kv = mode == 2;
 #pragma unroll
       for (int j = 0; j < NS / 4; ++j) {
         const int idx = tid + kThreads * j;
-        int r, k;
-        if (mode == 2) { r = idx / (BKT / 4); k = (idx % (BKT / 4)) * 4; }
-        else { k = idx / (TR / 4); r = (idx % (TR / 4)) * 4; }
+        const int r = kv ? idx / (BKT / 4) : (idx % (TR / 4)) * 4;
+        const int k = kv ? (idx % (BKT / 4)) * 4 : idx / (TR / 4);
         const int gr = r0 + r, gk = kb + k;
-        f4 x = f4{0.f, 0.f, 0.f, 0.f};
-        if (gr < R && gk < k_end) x = *reinterpret_cast<const f4*>(X + gr * sR + gk * sK);
-        v[4 * j] = x[0]; v[4 * j + 1] = x[1]; v[4 * j + 2] = x[2]; v[4 * j + 3] = x[3];
+        const bool in = gr < R && gk < k_end;
+        in_mask |= (unsigned long long)in << j;
+        const f4 x = *reinterpret_cast<const f4*>(X + (in ? gr * sR + gk * sK : 0));
+        v[4 * j] = x[0];
+        v[4 * j + 1] = x[1];
+        v[4 * j + 2] = x[2];
+        v[4 * j + 3] = x[3];
       }
     } else {
+      const bool kf = (mode & 1) == 0;     // modes 0 and 2: k fastest
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
         const int idx = tid + kThreads * j;
-        int r, k;
-        if (mode == 0) { k = idx % BKT; r = idx / BKT; } else { r = idx % TR; k = idx / TR; }
+        const int k = kf ? idx % BKT : idx / TR;
+        const int r = kf ? idx / BKT : idx % TR;
         const int gr = r0 + r, gk = kb + k;
-        v[j] = (gr < R && gk < k_end) ? X[gr * sR + gk * sK] : 0.f;
+        const bool in = gr < R && gk < k_end;
+        in_mask |= (unsigned long long)in << j;
+        v[j] = X[in ? gr * sR + gk * sK : 0];
       }
     }
   }
+  template <bool VEC>
   __device__ inline void store(float (*S)[BKT + 4], int mode, int tid) const {
-    if (NS < 4 && mode >= 2) mode -= 2;
-    if (mode >= 2) {
+    if constexpr (VEC && NS >= 4) {
 #pragma unroll
       for (int j = 0; j < NS / 4; ++j) {
         const int idx = tid + kThreads * j;
+        const bool in = (in_mask >> j) & 1ull;
+        const f4 x = in ? f4{v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]}
+                        : f4{0.f, 0.f, 0.f, 0.f};
         if (mode == 2) {
           const int r = idx / (BKT / 4), k = (idx % (BKT / 4)) * 4;
-          *reinterpret_cast<f4*>(&S[r][k]) = f4{v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]};
+          *reinterpret_cast<f4*>(&S[r][k]) = x;
         } else {
           const int k = idx / (TR / 4), r = (idx % (TR / 4)) * 4;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) S[r + e][k] = v[4 * j + e];
+          for (int e = 0; e < 4; ++e) S[r + e][k] = x[e];
         }
       }
     } else {
@@ -128,8 +147,8 @@ struct TileLoad {
       for (int j = 0; j < NS; ++j) {
         const int idx = tid + kThreads * j;
         int r, k;
-        if (mode == 0) { k = idx % BKT; r = idx / BKT; } else { r = idx % TR; k = idx / TR; }
-        S[r][k] = v[j];
+        if ((mode & 1) == 0) { k = idx % BKT; r = idx / BKT; } else { r = idx % TR; k = idx / TR; }
+        S[r][k] = ((in_mask >> j) & 1ull) ? v[j] : 0.f;
       }
     }
   }
@@ -147,7 +166,7 @@ __device__ inline float tanh_fast(float z) {
 // narrow shapes.  Grids too small to fill the chip (small batches) take
 // 64-deep blocks: each block costs about one memory latency, so a deeper
 // block divides the latency-bound time of such a GEMM by four.
-template <int TM, int TN, int BKT = BK>
+template <int TM, int TN, int BKT, bool VA, bool VB>
 __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
   constexpr int WM = TM / 2, WN = TN / 2;           // wave tile
   constexpr int TI = WM / 16, TJ = WN / 16;         // 16 x 16 MFMA tiles per wave
@@ -164,12 +183,12 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
   TileLoad<TM, BKT> ta;
   TileLoad<TN, BKT> tb;
   auto load = [&](int kb) {
-    ta.load(A, g.sAm, g.sAk, g.modeA, m0, g.M, kb, k_end, tid);
-    tb.load(Bp, g.sBn, g.sBk, g.modeB, n0, g.N, kb, k_end, tid);
+    ta.template load<VA>(A, g.sAm, g.sAk, g.modeA, m0, g.M, kb, k_end, tid);
+    tb.template load<VB>(Bp, g.sBn, g.sBk, g.modeB, n0, g.N, kb, k_end, tid);
   };
   auto store = [&](int buf) {
-    ta.store(As[buf], g.modeA, tid);
-    tb.store(Bs[buf], g.modeB, tid);
+    ta.template store<VA>(As[buf], g.modeA, tid);
+    tb.template store<VB>(Bs[buf], g.modeB, tid);
   };
 
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
@@ -212,35 +231,67 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmArgs g) {
     }
   }
 
+  // Epilogue, one row of 16 x 16 tiles at a time: the operands it reads
+  // (bias, add, mul, add2) are loaded for all of the row's elements before
+  // any is used (an element outside C reads element 0 and is not stored),
+  // so their loads are in flight together.
   float* C = g.C ? g.C + b * g.sCb + s * g.sCs : nullptr;
+  constexpr int E = TJ * 4;
 #pragma unroll
-  for (int i = 0; i < TI; ++i)
+  for (int i = 0; i < TI; ++i) {
+    long long ci[E];
+    bool in[E];
+    float bi[TJ], ad[E], mu[E], a2[E];
 #pragma unroll
     for (int j = 0; j < TJ; ++j) {
       const int n = n0 + wn + j * 16 + r;
-      if (n >= g.N) continue;
-      const float bias = g.mode == EPI_BIAS_TANH ? g.bias[b * g.sBiasb + n] : 0.f;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int m = m0 + wm + i * 16 + 4 * gq + q;
-        if (m >= g.M) continue;
+        in[4 * j + q] = n < g.N && m < g.M;
+        ci[4 * j + q] = in[4 * j + q] ? m * g.sCm + n * g.sCn : 0;
+      }
+      bi[j] = 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) ad[e] = mu[e] = a2[e] = 0.f;
+    if (g.mode == EPI_BIAS_TANH) {
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) bi[j] = g.bias[b * g.sBiasb + min(n0 + wn + j * 16 + r, g.N - 1)];
+    } else if (g.mode == EPI_GEN) {
+      if (g.add)
+#pragma unroll
+        for (int e = 0; e < E; ++e) ad[e] = g.add[b * g.sAddb + ci[e]];
+      if (g.C2) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) mu[e] = g.mul[b * g.sMulb + ci[e]];
+        if (g.add2)
+#pragma unroll
+          for (int e = 0; e < E; ++e) a2[e] = g.add2[b * g.sAdd2b + ci[e]];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < TJ; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = 4 * j + q;
+        if (!in[e]) continue;
         const float v = acc[i][j][q];
-        const long long ci = m * g.sCm + n * g.sCn;
         if (g.mode == EPI_STORE) {
-          C[ci] = v;
+          C[ci[e]] = v;
         } else if (g.mode == EPI_BIAS_TANH) {
-          C[ci] = tanh_fast(v + bias);
+          C[ci[e]] = tanh_fast(v + bi[j]);
         } else {
-          const float rr = g.add ? v + g.add[b * g.sAddb + ci] : v;
-          if (C) C[ci] = rr;
+          const float rr = g.add ? v + ad[e] : v;
+          if (C) C[ci[e]] = rr;
           if (g.C2) {
-            float o = rr * g.mul[b * g.sMulb + ci];
-            if (g.add2) o += g.add2[b * g.sAdd2b + ci];
-            g.C2[b * g.sC2b + ci] = o;
+            float o = rr * mu[e];
+            if (g.add2) o += a2[e];
+            g.C2[b * g.sC2b + ci[e]] = o;
           }
         }
       }
-    }
+  }
 }
 
 // x = [cos s | sin s] into the primal half of every member's stacked slab
@@ -725,6 +776,21 @@ int load_mode(const float* X, long long sR, long long sK, long long sBatch, int 
   return 0;
 }
 
+// One tile shape, with the float4 load modes of the two operands as
+// compile-time choices.
+template <int TM, int TN, int BKT>
+void launch_gemm_tile(dim3 grid, const GemmArgs& g, hipStream_t st) {
+  const bool va = g.modeA >= 2, vb = g.modeB >= 2;
+  if (va && vb)
+    hipLaunchKernelGGL((gemm_f32_kernel<TM, TN, BKT, true, true>), grid, dim3(kThreads), 0, st, g);
+  else if (va)
+    hipLaunchKernelGGL((gemm_f32_kernel<TM, TN, BKT, true, false>), grid, dim3(kThreads), 0, st, g);
+  else if (vb)
+    hipLaunchKernelGGL((gemm_f32_kernel<TM, TN, BKT, false, true>), grid, dim3(kThreads), 0, st, g);
+  else
+    hipLaunchKernelGGL((gemm_f32_kernel<TM, TN, BKT, false, false>), grid, dim3(kThreads), 0, st, g);
+}
+
 #ifndef RID_GEMM_DEEP_WGS
 #define RID_GEMM_DEEP_WGS 256
 #endif
@@ -743,18 +809,18 @@ rid_status gemm(const GemmArgs& g0, hipStream_t st) {
       (long long)((g.N + 63) / 64) * ((g.M + 63) / 64) * g.batch * g.ksplit;
   if (g.M >= 128 && g.N >= 128 && tiles128 >= 1024) {
     dim3 grid((g.N + 127) / 128, (g.M + 127) / 128, g.batch * g.ksplit);
-    hipLaunchKernelGGL((gemm_f32_kernel<128, 128>), grid, dim3(kThreads), 0, st, g);
+    launch_gemm_tile<128, 128, BK>(grid, g, st);
   } else if (g.M > 32 && tiles64 < 512) {
     dim3 grid((g.N + 63) / 64, (g.M + 31) / 32, g.batch * g.ksplit);
     // fewer workgroups than CUs: latency-bound, 64-deep contraction blocks
     const long long wgs = (long long)grid.x * grid.y * grid.z;
     if (wgs < RID_GEMM_DEEP_WGS && g.kchunk >= 64)
-      hipLaunchKernelGGL((gemm_f32_kernel<32, 64, 64>), grid, dim3(kThreads), 0, st, g);
+      launch_gemm_tile<32, 64, 64>(grid, g, st);
     else
-      hipLaunchKernelGGL((gemm_f32_kernel<32, 64>), grid, dim3(kThreads), 0, st, g);
+      launch_gemm_tile<32, 64, BK>(grid, g, st);
   } else {
     dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.batch * g.ksplit);
-    hipLaunchKernelGGL((gemm_f32_kernel<64, 64>), grid, dim3(kThreads), 0, st, g);
+    launch_gemm_tile<64, 64, BK>(grid, g, st);
   }
   RID_HIP(hipGetLastError());
   return RID_OK;
