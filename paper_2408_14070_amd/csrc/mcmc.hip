@@ -23,7 +23,11 @@
 // needs (member energies, the current state and the proposal, the walker's
 // acceptance count) before it waits, keeps the updated state in registers
 // for the counts and the next proposal, and counts acceptances per walker:
-// one atomic per workgroup adds them to the caller's total at the end.
+// one atomic per workgroup adds them to the caller's total at the end.  The
+// per-CV counts go to one of several private copies of the histograms
+// (walker w to copy w mod copies), so walkers in the same bin rarely hit the
+// same counter; the copies are added to the caller's histograms at the end
+// of the call.
 #include "device_common.h"
 
 namespace rid {
@@ -66,7 +70,8 @@ struct McmcArgs {
   float step;
   unsigned long long seed;
   int proj0, proj1, nbins;
-  unsigned* hist1;          // [n][nbins]
+  unsigned* hist1;          // [copies][n][nbins] private copies of the counts
+  int copies;
   unsigned* hist2;          // [nbins][nbins] or null
   unsigned long long* accepted;
   unsigned long long* acc_count;   // [W] acceptances of this call, per walker
@@ -166,6 +171,7 @@ __global__ __launch_bounds__(kMcmcWaves * kWave) void mcmc_step_kernel(McmcArgs 
   if (w >= a.W) return;
   const int n = a.n;
   const size_t row = (size_t)w * n;
+  unsigned* h1 = a.hist1 + (size_t)(w % a.copies) * n * a.nbins;
   // every load first: member energies (lane k), the walker's Abar and count,
   // the first chunk of the state and of the proposal
   const float ak = lane < a.K ? a.A[(size_t)lane * a.W + w] : 0.f;
@@ -196,7 +202,7 @@ __global__ __launch_bounds__(kMcmcWaves * kWave) void mcmc_step_kernel(McmcArgs 
     }
     if (i < n) {
       if (acc) a.s[row + i] = v;
-      atomicAdd(&a.hist1[(size_t)i * a.nbins + bin_of(a, i, v)], 1u);
+      atomicAdd(&h1[(size_t)i * a.nbins + bin_of(a, i, v)], 1u);
       if (!last) {
         bool in_box;
         const float vp = step_cv(a, i, v, unext, in_box);
@@ -216,6 +222,25 @@ __global__ __launch_bounds__(kMcmcWaves * kWave) void mcmc_step_kernel(McmcArgs 
     if (a.hist2)
       atomicAdd(&a.hist2[(size_t)bin_of(a, a.proj0, p0) * a.nbins + bin_of(a, a.proj1, p1)],
                 1u);
+  }
+}
+
+// Zeroes the private histogram copies (a kernel: the call may be captured in
+// a graph).
+__global__ void mcmc_hist_zero_kernel(unsigned* h, size_t count) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count;
+       e += (size_t)gridDim.x * blockDim.x)
+    h[e] = 0u;
+}
+
+// Adds the private copies to the caller's per-CV histograms.
+__global__ void mcmc_hist_sum_kernel(const unsigned* h, int copies, size_t per_copy,
+                                     unsigned* out) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < per_copy;
+       e += (size_t)gridDim.x * blockDim.x) {
+    unsigned v = 0u;
+    for (int c = 0; c < copies; ++c) v += h[c * per_copy + e];
+    out[e] += v;
   }
 }
 
@@ -244,10 +269,15 @@ rid_status launch_mcmc(rid_ensemble_impl& e, float* s, int W, long long n_steps,
   const int n = e.n_cv, K = e.K;
   rid_status r;
   const size_t wn = (size_t)W * n;
+  // private histogram copies: up to 32, within 16 MiB
+  const size_t per_copy = (size_t)n * nbins;
+  const int copies = (int)std::max<size_t>(
+      1, std::min<size_t>(32, ((size_t)16 << 20) / (sizeof(unsigned) * per_copy)));
   // workspace: Abar (FP64) [W], acceptance counts [W], proposal [W][n], its
-  // encoding [W][2n], the proposals' box flags [W]
-  if ((r = e.ws_cons.ensure(2 * sizeof(double) * (size_t)W + sizeof(float) * 3 * wn +
-                            sizeof(int) * (size_t)W + 256)) != RID_OK)
+  // encoding [W][2n], the proposals' box flags [W], the histogram copies
+  const size_t off_h = (2 * sizeof(double) * (size_t)W + sizeof(float) * 3 * wn +
+                        sizeof(int) * (size_t)W + 255) / 256 * 256;
+  if ((r = e.ws_cons.ensure(off_h + sizeof(unsigned) * per_copy * copies + 256)) != RID_OK)
     return r;
   if ((r = e.ws_A.ensure(sizeof(float) * K * (size_t)W)) != RID_OK) return r;
   if (e.frag_dirty) {
@@ -277,7 +307,8 @@ rid_status launch_mcmc(rid_ensemble_impl& e, float* s, int W, long long n_steps,
   a.proj0 = proj0;
   a.proj1 = proj1;
   a.nbins = nbins;
-  a.hist1 = hist1;
+  a.hist1 = reinterpret_cast<unsigned*>(base + off_h);
+  a.copies = copies;
   a.hist2 = hist2;
   a.accepted = accepted;
   const dim3 grid((W + kMcmcWaves - 1) / kMcmcWaves), block(kMcmcWaves * kWave);
@@ -285,6 +316,10 @@ rid_status launch_mcmc(rid_ensemble_impl& e, float* s, int W, long long n_steps,
   RID_HIP(hipGetLastError());
   if ((r = launch_mlp(e, a.xp, W, e.ws_A.as<float>(), nullptr, st)) != RID_OK) return r;
   if (n_steps == 0) return RID_OK;
+  hipLaunchKernelGGL(mcmc_hist_zero_kernel,
+                     dim3((unsigned)std::min<size_t>((per_copy * copies + 255) / 256, 1024)),
+                     dim3(256), 0, st, a.hist1, per_copy * copies);
+  RID_HIP(hipGetLastError());
   hipLaunchKernelGGL(mcmc_start_kernel, grid, block, 0, st, a, t0);
   RID_HIP(hipGetLastError());
   for (long long t = t0; t < t0 + n_steps; ++t) {
@@ -293,6 +328,10 @@ rid_status launch_mcmc(rid_ensemble_impl& e, float* s, int W, long long n_steps,
                        (int)(t + 1 == t0 + n_steps));
     RID_HIP(hipGetLastError());
   }
+  hipLaunchKernelGGL(mcmc_hist_sum_kernel,
+                     dim3((unsigned)std::min<size_t>((per_copy + 255) / 256, 1024)), dim3(256), 0,
+                     st, a.hist1, copies, per_copy, hist1);
+  RID_HIP(hipGetLastError());
   if (accepted) {
     hipLaunchKernelGGL(mcmc_count_kernel, dim3(std::min((W + 255) / 256, 1024)), dim3(256), 0,
                        st, a.acc_count, W, accepted);
