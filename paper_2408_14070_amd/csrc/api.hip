@@ -129,6 +129,7 @@ static void free_ensemble(rid_ensemble_impl& e) {
   dev_free(e.d_cvw);
   dev_free(e.d_bounds);
   e.ws_x.release();
+  e.wpad.release();
   e.ws_A.release();
   e.ws_g.release();
   e.ws_train.release();

@@ -1980,6 +1980,7 @@ rid_status launch_mlp_from_pos(const rid_ensemble_impl& e, const TorsionInput& t
 }
 
 rid_status pack_ensemble_weights(rid_ensemble_impl& e, hipStream_t st) {
+  ++e.master_gen;     // the masters may have changed: copies made from them are stale
   const int L = e.L;
   PackAll pa{};
   pa.L = L;

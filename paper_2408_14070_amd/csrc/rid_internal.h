@@ -164,6 +164,13 @@ struct rid_ensemble_impl {
   float* d_wo = nullptr;             // [K][NP]
   float* d_bo = nullptr;             // [K]
   float* d_vscale = nullptr;         // [K][2] reverse-vector scale (a power of two), inverse
+  // the layer weights again, each member's block and each layer's matrix
+  // starting on 16 bytes (the general training sweeps read their weight
+  // operand from it with float4 loads); rebuilt when master_gen moves on
+  DevBuf wpad;                       // [K][wpad_pm] floats
+  long long wpad_pm = 0;
+  std::vector<long long> wpad_off;   // [L] offset of W_l inside a member's block
+  unsigned long long master_gen = 1, wpad_gen = 0;
   // scratch
   bool frag_dirty = false;           // masters changed since the last pack
   DevBuf ws_x, ws_A, ws_g, ws_train, ws_cons;

@@ -352,6 +352,28 @@ __global__ void act_kernel(const float* T, int l, int w, int B, int K, int row_b
   }
 }
 
+// The layer weights of every member into the aligned copy: element e of
+// layer l's matrix (row-major [out][in]) from master + k*pm + src[l] to
+// wpad + k*pmp + dst[l].
+struct WpadCopy {
+  long long src[kMaxHidden], dst[kMaxHidden], cnt[kMaxHidden];
+  int L;
+};
+__global__ void wpad_copy_kernel(const float* master, long long pm, float* wpad, long long pmp,
+                                 int K, WpadCopy c) {
+  long long per = 0;
+  for (int l = 0; l < c.L; ++l) per += c.cnt[l];
+  const long long total = (long long)K * per;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(e / per);
+    long long r = e - (long long)k * per;
+    int l = 0;
+    while (r >= c.cnt[l]) r -= c.cnt[l++];
+    wpad[k * pmp + c.dst[l] + r] = master[k * pm + c.src[l] + r];
+  }
+}
+
 // out[k][b][j] = w_o[k][j] (the top of the reverse sweeps: u_L, lam_hd_L),
 // into rows [r0, r0 + B) of a [K][rows][w] slab (the other rows, if any, 0)
 __global__ void top_kernel(const float* master, long long per_model, int wo_off, int w, int B,
@@ -1013,6 +1035,39 @@ rid_status mf_grad_fused(rid_ensemble_impl& e, const float* s, const float* F,
 // Returns the gradient pointer through *grad_used.  Both forms hold at most
 // the ensemble's training budget of activations: a larger batch is taken in
 // chunks of rows whose weight-gradient contributions are added in chunk order.
+// The aligned weight copy of the general sweeps, allocated on first use and
+// refreshed when the masters have changed since it was made.
+rid_status ensure_wpad(rid_ensemble_impl& e, const std::vector<int>& w,
+                       const std::vector<long long>& w_off, hipStream_t st) {
+  const int L = e.L;
+  e.wpad_off.assign(L, 0);
+  long long off = 0;
+  for (int l = 0; l < L; ++l) {
+    e.wpad_off[l] = off;
+    off += ((long long)w[l + 1] * w[l] + 3) / 4 * 4;
+  }
+  e.wpad_pm = off;
+  const void* before = e.wpad.ptr;
+  rid_status rs = e.wpad.ensure(sizeof(float) * (size_t)e.K * e.wpad_pm);
+  if (rs != RID_OK) return rs;
+  if (e.wpad.ptr != before) e.wpad_gen = 0;    // a new buffer holds nothing yet
+  if (e.wpad_gen == e.master_gen) return RID_OK;
+  WpadCopy c{};
+  c.L = L;
+  long long total = 0;
+  for (int l = 0; l < L; ++l) {
+    c.src[l] = w_off[l];
+    c.dst[l] = e.wpad_off[l];
+    c.cnt[l] = (long long)w[l + 1] * w[l];
+    total += c.cnt[l];
+  }
+  hipLaunchKernelGGL(wpad_copy_kernel, dim3(grid1d((long long)e.K * total)), dim3(256), 0, st,
+                     e.d_master, (long long)e.per_model, e.wpad.as<float>(), e.wpad_pm, e.K, c);
+  RID_HIP(hipGetLastError());
+  e.wpad_gen = e.master_gen;
+  return RID_OK;
+}
+
 rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
                           const float* rho, int B, float* loss, float* grad_out,
                           float** grad_used, hipStream_t st, InputHvp* hvp) {
@@ -1095,6 +1150,11 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
   if (grad_used) *grad_used = G;
   ProfScope ps(kProfTrain, st);
   const uint32_t step32 = (uint32_t)((unsigned long long)e.step & 0xFFFFFFFFull);
+  // the weight operands come from the aligned copy (float4 loads)
+  if ((rs = ensure_wpad(e, w, w_off, st)) != RID_OK) return rs;
+  const float* WP = e.wpad.as<float>();
+  const long long pmp = e.wpad_pm;
+  const std::vector<long long>& wq = e.wpad_off;
 
   for (int r0 = 0; r0 < B; r0 += Bc) {
     const int R = std::min(Bc, B - r0);
@@ -1112,7 +1172,7 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
     for (int l = 1; l <= L; ++l) {
       GemmArgs g{};
       g.A = W + hh[l - 1]; g.sAb = slab(l - 1); g.sAm = w[l - 1]; g.sAk = 1;
-      g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = 1; g.sBn = w[l - 1];
+      g.Bm = WP + wq[l - 1]; g.sBb = pmp; g.sBk = 1; g.sBn = w[l - 1];
       g.C = W + tt[l]; g.sCb = (long long)R * w[l]; g.sCm = w[l]; g.sCn = 1;
       g.bias = P + b_off[l - 1]; g.sBiasb = pm;
       g.M = R; g.N = w[l]; g.Kc = w[l - 1]; g.batch = K; g.mode = EPI_BIAS_TANH;
@@ -1137,7 +1197,7 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
     for (int l = L; l >= 1; --l) {
       GemmArgs g{};
       g.A = W + vin; g.sAb = (long long)R * w[l]; g.sAm = w[l]; g.sAk = 1;
-      g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = w[l - 1]; g.sBn = 1;
+      g.Bm = WP + wq[l - 1]; g.sBb = pmp; g.sBk = w[l - 1]; g.sBn = 1;
       g.sCb = (long long)R * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
       g.M = R; g.N = w[l - 1]; g.Kc = w[l]; g.batch = K;
       if (l > 1) {
@@ -1167,7 +1227,7 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
       GemmArgs g{};
       g.A = W + hh[l - 1] + (long long)R * w[l - 1]; g.sAb = slab(l - 1); g.sAm = w[l - 1];
       g.sAk = 1;
-      g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = 1; g.sBn = w[l - 1];
+      g.Bm = WP + wq[l - 1]; g.sBb = pmp; g.sBk = 1; g.sBn = w[l - 1];
       g.C = W + zd[l]; g.sCb = (long long)R * w[l]; g.sCm = w[l]; g.sCn = 1;
       g.C2 = W + hh[l] + (long long)R * w[l]; g.sC2b = slab(l);
       g.mul = W + dd[l]; g.sMulb = (long long)R * w[l];
@@ -1206,7 +1266,7 @@ rid_status launch_mf_grad(rid_ensemble_impl& e, const float* s, const float* F,
         // [lam_h ; lam_hd]_{l-1} = [lam_z ; lam_zd] W_l (+ [lam_h ; lam_hd]_l)
         GemmArgs g{};
         g.A = W + sbuf; g.sAb = 2LL * R * w[l]; g.sAm = w[l]; g.sAk = 1;
-        g.Bm = P + w_off[l - 1]; g.sBb = pm; g.sBk = w[l - 1]; g.sBn = 1;
+        g.Bm = WP + wq[l - 1]; g.sBb = pmp; g.sBk = w[l - 1]; g.sBn = 1;
         g.C = W + lout; g.sCb = 2LL * R * w[l - 1]; g.sCm = w[l - 1]; g.sCn = 1;
         g.M = 2 * R; g.N = w[l - 1]; g.Kc = w[l]; g.batch = K;
         if (skip(l)) {
@@ -1253,6 +1313,7 @@ rid_status launch_train_step(rid_ensemble_impl& e, const float* s, const float* 
   RID_HIP(hipGetLastError());
   e.step += 1;
   e.frag_dirty = true;
+  ++e.master_gen;
   return RID_OK;
 }
 
