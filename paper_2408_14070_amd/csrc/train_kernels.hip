@@ -333,21 +333,31 @@ __global__ void act_kernel(const float* T, int l, int w, int B, int K, int row_b
     const int k = (int)(e / ((long long)B * nq));
     const long long rq = e - (long long)k * B * nq;
     const int b = (int)(rq / nq), q = (int)(rq - (long long)b * nq);
+    // the four units' loads first (units past w re-read the last one, and a
+    // missing Hprev re-reads T; neither is used), the mask bits meanwhile
+    const long long ob = ((long long)k * B + b) * w;               // [K][B][w]
+    const float* hsrc = Hprev ? Hprev + (long long)k * slab_prev + (long long)b * w : T + ob;
+    float tv[4], hv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = min(4 * q + u, w - 1);
+      tv[u] = T[ob + j];
+      hv[u] = hsrc[j];
+    }
     uint32_t c[4] = {(uint32_t)(row_base + b), step, (uint32_t)(16 * k + l), (uint32_t)q};
     if (drop_p > 0.f)
       dev::philox4x32_10(c, (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32));
+#pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int j = 4 * q + u;
       if (j >= w) break;
       const float sc = drop_p > 0.f ? (dev::philox_uniform(c[u]) >= drop_p ? drop_inv : 0.f)
                                     : 1.f;
-      const long long o = ((long long)k * B + b) * w + j;          // [K][B][w]
-      const long long oh = (long long)k * slab + (long long)b * w + j;
-      const float t = T[o];
+      const float t = tv[u];
       float h = sc * t;
-      if (Hprev) h += Hprev[(long long)k * slab_prev + (long long)b * w + j];
-      H[oh] = h;
-      D[o] = sc * (1.f - t * t);
+      if (Hprev) h += hv[u];
+      H[(long long)k * slab + (long long)b * w + j] = h;
+      D[ob + j] = sc * (1.f - t * t);
     }
   }
 }
@@ -420,20 +430,26 @@ __global__ __launch_bounds__(kResWaves * 64) void residual_kernel(
   const float* u = U0 + e * 2 * n;
   float* rx = HH0 + k * slab + ((long long)B + b) * 2 * n;
   float acc = 0.f;
+  // (every load of a CV first, without branches: a null raw table reads the
+  // CV bytes of s instead, unused; F or rho_in, whichever is given)
+  const uint8_t* rawp = raw ? raw : reinterpret_cast<const uint8_t*>(s);
   for (int i = lane; i < n; i += 64) {
+    const float sv = s[(long long)b * n + i];
+    const uint8_t rv = rawp[i];
+    const float ua = u[i], ub = u[n + i];
+    const float fv = rho_in ? rho_in[((long long)b * K + k) * n + i] : F[(long long)b * n + i];
     float sn, cs;
-    sincosf(s[(long long)b * n + i], &sn, &cs);
-    const bool r = raw && raw[i];     // raw CV: x_i = s_i, dx/ds = (1, 0)
-    if (r) {
+    sincosf(sv, &sn, &cs);
+    if (raw && rv) {                  // raw CV: x_i = s_i, dx/ds = (1, 0)
       sn = -1.f;
       cs = 0.f;
     }
     float rho;
     if (rho_in) {
-      rho = rho_in[((long long)b * K + k) * n + i];
+      rho = fv;
     } else {
-      const float gi = -sn * u[i] + cs * u[n + i];
-      const float ri = gi - F[(long long)b * n + i];
+      const float gi = -sn * ua + cs * ub;
+      const float ri = gi - fv;
       acc += ri * ri;
       rho = 2.f * ri / (float)B_norm;
     }
