@@ -362,26 +362,22 @@ __global__ void act_kernel(const float* T, int l, int w, int B, int K, int row_b
   }
 }
 
-// The layer weights of every member into the aligned copy: element e of
-// layer l's matrix (row-major [out][in]) from master + k*pm + src[l] to
-// wpad + k*pmp + dst[l].
+// The layer weights of every member into the aligned copy: block row
+// y = k L + l copies layer l's matrix (row-major [out][in], cnt floats) of
+// member k from master + k*pm + src[l] to wpad + k*pmp + dst[l], its blocks
+// striding over the matrix (contiguous, coalesced, no index arithmetic).
 struct WpadCopy {
   long long src[kMaxHidden], dst[kMaxHidden], cnt[kMaxHidden];
   int L;
 };
 __global__ void wpad_copy_kernel(const float* master, long long pm, float* wpad, long long pmp,
-                                 int K, WpadCopy c) {
-  long long per = 0;
-  for (int l = 0; l < c.L; ++l) per += c.cnt[l];
-  const long long total = (long long)K * per;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int k = (int)(e / per);
-    long long r = e - (long long)k * per;
-    int l = 0;
-    while (r >= c.cnt[l]) r -= c.cnt[l++];
-    wpad[k * pmp + c.dst[l] + r] = master[k * pm + c.src[l] + r];
-  }
+                                 WpadCopy c) {
+  const int k = blockIdx.y / c.L, l = blockIdx.y - k * c.L;
+  const float* src = master + k * pm + c.src[l];
+  float* dst = wpad + k * pmp + c.dst[l];
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < c.cnt[l];
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = src[e];
 }
 
 // out[k][b][j] = w_o[k][j] (the top of the reverse sweeps: u_L, lam_hd_L),
@@ -1070,15 +1066,16 @@ rid_status ensure_wpad(rid_ensemble_impl& e, const std::vector<int>& w,
   if (e.wpad_gen == e.master_gen) return RID_OK;
   WpadCopy c{};
   c.L = L;
-  long long total = 0;
+  long long cmax = 1;
   for (int l = 0; l < L; ++l) {
     c.src[l] = w_off[l];
     c.dst[l] = e.wpad_off[l];
     c.cnt[l] = (long long)w[l + 1] * w[l];
-    total += c.cnt[l];
+    cmax = std::max(cmax, c.cnt[l]);
   }
-  hipLaunchKernelGGL(wpad_copy_kernel, dim3(grid1d((long long)e.K * total)), dim3(256), 0, st,
-                     e.d_master, (long long)e.per_model, e.wpad.as<float>(), e.wpad_pm, e.K, c);
+  const unsigned bx = (unsigned)std::min<long long>((cmax + 255) / 256, 256);
+  hipLaunchKernelGGL(wpad_copy_kernel, dim3(bx, e.K * L), dim3(256), 0, st, e.d_master,
+                     (long long)e.per_model, e.wpad.as<float>(), e.wpad_pm, c);
   RID_HIP(hipGetLastError());
   e.wpad_gen = e.master_gen;
   return RID_OK;
