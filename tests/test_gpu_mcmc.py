@@ -270,3 +270,22 @@ def test_mixed_table_box_walk_step_by_step(torch, rid):
     h1 = h1.cpu().numpy().astype(np.int64)
     assert h1.sum() == W * T * n and int(h2.sum().item()) == W * T
     assert np.abs(h1 - ref["hist1"]).sum() <= 2 * n * lost + 8
+
+
+@pytest.mark.parametrize("nbins,W", [(31, 2048), (4096, 300)])
+def test_histograms_count_every_walker_once_per_step(torch, rid, nbins, W):
+    """Every step counts each walker once per CV and once in the pair
+    histogram, whatever the number of private histogram copies (32 for small
+    tables, fewer when n x nbins is large), and the counts add onto what
+    the caller passes in."""
+    n = 38
+    E, _ = _ensemble(rid, n=n, widths=(64,), K=2)
+    s = torch.from_numpy(ridgen.f32(ridgen.torus_samples(W, n, 12))).cuda()
+    steps = 5
+    h1 = torch.full((n, nbins), 3, dtype=torch.int32, device="cuda")
+    h2 = torch.zeros((nbins, nbins), dtype=torch.int32, device="cuda")
+    out = rid.mcmc_run(E, s, steps, KT_300K, 0.4, 17, nbins=nbins, hist1=h1, hist2=h2)
+    torch.cuda.synchronize()
+    per_cv = out["hist1"].to(torch.int64).sum(dim=1).cpu().numpy()
+    assert np.all(per_cv == steps * W + 3 * nbins)
+    assert int(out["hist2"].to(torch.int64).sum().item()) == steps * W
