@@ -61,6 +61,18 @@ def test_cluster_filter_and_cap(torch, rid):
     assert np.any(gl == -1)
 
 
+def test_cluster_cap_filling_in_a_late_chunk(torch, rid):
+    # 23 clusters at t = 3 with leaders spread over the 3000 frames: a cap of
+    # 20 fills inside a 2048-frame chunk, the walk stops there, and the
+    # following rounds label the remaining frames (joined or over the cap)
+    s = ridgen.exploration_frames(20, 150, 38, 30, 0.3, seed=11)
+    labels, leaders, n = O.leader_cluster(s, 3.0, max_clusters=20)
+    assert n == 21 and leaders[-1] > 1984
+    gl, gld, gn, _ = _gpu_cluster(torch, rid, s, 3.0, max_clusters=20)
+    assert gn == n and gld == leaders and np.array_equal(gl, labels)
+    assert np.any(gl == -1)
+
+
 def test_cluster_many_leaders_restarts_chunks(torch, rid):
     # 256 CVs leave room for 64 new leaders per chunk in LDS; uniform frames
     # at a small threshold found hundreds, so the walk stops and restarts
