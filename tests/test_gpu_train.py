@@ -329,6 +329,33 @@ def test_paper_training_config(torch, rid):
     assert d.max() <= 2.5 * step_scale
 
 
+def test_general_sweeps_follow_new_parameters(torch, rid):
+    """The general sweeps (here: a layer wider than 256) read the layer
+    weights from an aligned copy of the masters (the 70 x 33 matrix is not a
+    whole number of 16-byte rows): after set_params, and after a training
+    step, the gradient is the oracle's for the parameters the ensemble now
+    holds."""
+    n, widths, K, B = 5, [300, 33, 70], 2, 64
+    pa = ridgen.xavier_ensemble(2 * n, widths, K, 71, bias_std=0.1)
+    pb = ridgen.xavier_ensemble(2 * n, widths, K, 72, bias_std=0.1)
+    s, F, _ = ridgen.mf_training_set(B, n)
+    E = rid.Ensemble(n, widths, K, pa)
+    for params in (pa, pb):
+        E.set_params(params)
+        loss, grad = rid.mf_loss_grad(E, _dev(torch, s), _dev(torch, F))
+        torch.cuda.synchronize()
+        loss_ref, grad_ref = _grad_ref_general(params, n, widths, K, s, F)
+        assert np.max(np.abs(loss.cpu().numpy() - loss_ref) / loss_ref) <= 1e-5
+        assert _per_member_err(grad.cpu().numpy(), grad_ref) <= GRAD_TOL
+    rid.mf_train_step(E, _dev(torch, s), _dev(torch, F), 1e-3)
+    pc = E.get_params()
+    loss, grad = rid.mf_loss_grad(E, _dev(torch, s), _dev(torch, F))
+    torch.cuda.synchronize()
+    loss_ref, grad_ref = _grad_ref_general(pc, n, widths, K, s, F)
+    assert np.max(np.abs(loss.cpu().numpy() - loss_ref) / loss_ref) <= 1e-5
+    assert _per_member_err(grad.cpu().numpy(), grad_ref) <= GRAD_TOL
+
+
 def test_masked_training_parity(torch, rid):
     """Training on the mixed table (38 torsions, 6 distances): raw CVs enter
     as (s, 0) and their mean force is dA/dx_i; residual and plain."""
