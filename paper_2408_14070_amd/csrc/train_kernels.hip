@@ -648,7 +648,7 @@ struct WgradArgs {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
 #ifndef RID_WG_PF
-#define RID_WG_PF 4
+#define RID_WG_PF 6
 #endif
 constexpr int kWgPF = RID_WG_PF;   // k-steps of loads in flight per wave
 constexpr int kWgLdsStride = 65;   // padded row of a partial tile in LDS
