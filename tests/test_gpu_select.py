@@ -73,6 +73,24 @@ def test_cluster_cap_filling_in_a_late_chunk(torch, rid):
     assert np.any(gl == -1)
 
 
+@pytest.mark.parametrize("B,n", [(1, 38), (2, 1), (65, 3)])
+def test_cluster_tiny_inputs(torch, rid, B, n):
+    # a single frame founds the only cluster; one CV; a ragged second chunk
+    s = ridgen.f32(ridgen.torus_samples(B, n, 21))
+    for t in (0.3, 10.0):
+        labels, leaders, nc = O.leader_cluster(s, t)
+        gl, gld, gn, _ = _gpu_cluster(torch, rid, s, t)
+        assert gn == nc and gld == leaders and np.array_equal(gl, labels)
+
+
+def test_cluster_every_frame_filtered(torch, rid):
+    # no frame reaches the lower trust level: no cluster, every label -2
+    s = ridgen.f32(ridgen.torus_samples(300, 38, 22))
+    eps = np.full(300, 0.1, np.float32)
+    gl, gld, gn, _ = _gpu_cluster(torch, rid, s, 1.0, eps=eps, eps0=0.5)
+    assert gn == 0 and gld == [] and np.all(gl == -2)
+
+
 def test_cluster_many_leaders_restarts_chunks(torch, rid):
     # 256 CVs leave room for 64 new leaders per chunk in LDS; uniform frames
     # at a small threshold found hundreds, so the walk stops and restarts

@@ -329,6 +329,20 @@ def test_paper_training_config(torch, rid):
     assert d.max() <= 2.5 * step_scale
 
 
+@pytest.mark.parametrize("n,widths,K", [(38, [256] * 4, 4), (5, [300, 40], 2)])
+def test_loss_grad_single_sample(torch, rid, n, widths, K):
+    """A batch of one sample (two stacked rows in every weight-gradient
+    contraction) on the fused and on the general sweeps."""
+    params = ridgen.xavier_ensemble(2 * n, widths, K, 81, bias_std=0.1)
+    s, F, _ = ridgen.mf_training_set(1, n)
+    E = rid.Ensemble(n, widths, K, params)
+    loss, grad = rid.mf_loss_grad(E, _dev(torch, s), _dev(torch, F))
+    torch.cuda.synchronize()
+    loss_ref, grad_ref = _grad_ref_general(params, n, widths, K, s, F)
+    assert np.max(np.abs(loss.cpu().numpy() - loss_ref) / loss_ref) <= 1e-5
+    assert _per_member_err(grad.cpu().numpy(), grad_ref) <= GRAD_TOL
+
+
 def test_general_sweeps_follow_new_parameters(torch, rid):
     """The general sweeps (here: a layer wider than 256) read the layer
     weights from an aligned copy of the masters (the 70 x 33 matrix is not a
