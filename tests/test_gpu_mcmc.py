@@ -272,7 +272,7 @@ def test_mixed_table_box_walk_step_by_step(torch, rid):
     assert np.abs(h1 - ref["hist1"]).sum() <= 2 * n * lost + 8
 
 
-@pytest.mark.parametrize("nbins,W", [(31, 2048), (4096, 300)])
+@pytest.mark.parametrize("nbins,W", [(31, 2048), (4096, 300), (31, 1)])
 def test_histograms_count_every_walker_once_per_step(torch, rid, nbins, W):
     """Every step counts each walker once per CV and once in the pair
     histogram, whatever the number of private histogram copies (32 for small
