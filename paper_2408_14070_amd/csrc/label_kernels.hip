@@ -16,7 +16,7 @@ namespace rid {
 namespace {
 
 constexpr int kBlocks = 10;
-constexpr int kThreads = 256;
+constexpr int kThreads = 384;   // the 10 x 38 (block, CV) tasks of a 38-CV system in one pass
 
 struct LabelArgs {
   const float* traj;   // [M][T][n]
