@@ -37,6 +37,7 @@ constexpr int kMatchWaves = 4;
 constexpr int kMaxSelCv = 256;
 constexpr int kChunkMax = 8192;
 constexpr int kLdsRows = 16384;    // floats for the new leaders, and again for a frame group
+constexpr int kSlots = 16;         // thresholds clustered side by side in one pass
 
 struct ClusterArgs {
   const float* s;        // [B][n] frames
@@ -51,6 +52,27 @@ struct ClusterArgs {
   const uint8_t* raw;    // [n] or null: CVs with raw[i] = 1 are not periodic
   const float* w;        // [n] or null: per-CV weights of the squared differences
 };
+
+// Thresholds clustered in one pass: slot k (blockIdx.y) clusters at t2[k]
+// into its own workspace, the pointers above advanced by k strides.
+struct ClusterSlots {
+  float t2[kSlots];
+  long long sLT, sLabels;   // floats of LT, ints of labels per slot (labels: 0 with one slot)
+  int sLeader, sPend;       // ints of leader, words of pend per slot
+};
+constexpr int kStateInts = 4;   // ints of state per slot
+
+__device__ inline ClusterArgs slot_args(const ClusterArgs& a0, const ClusterSlots& sl) {
+  const int k = blockIdx.y;
+  ClusterArgs a = a0;
+  a.t2 = sl.t2[k];
+  a.LT += k * sl.sLT;
+  a.labels += k * sl.sLabels;
+  a.leader += k * sl.sLeader;
+  a.pend += (size_t)k * sl.sPend;
+  a.state += k * kStateInts;
+  return a;
+}
 
 // Squared distance leader - frame with non-periodic CVs (raw non-null:
 // raw[i] = 1 leaves the difference unwrapped) and/or per-CV weights (w
@@ -96,6 +118,8 @@ __device__ inline float leader_d2(const float* lead, long long ls, const float* 
 
 __global__ void sel_init_kernel(int* state, unsigned long long* pend, int words) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  state += blockIdx.y * kStateInts;
+  pend += (size_t)blockIdx.y * words;
   if (t < 3) state[t] = 0;
   for (int w = t; w < words; w += gridDim.x * blockDim.x) pend[w] = 0ull;
 }
@@ -103,7 +127,9 @@ __global__ void sel_init_kernel(int* state, unsigned long long* pend, int words)
 // Frames [f_next, f_next + chunk): filtered, matched to the first earlier
 // leader within the threshold, over the cap (no match and no room for a new
 // cluster), or marked unmatched in the bit mask.
-__global__ __launch_bounds__(kMatchWaves * kWave) void sel_match_kernel(ClusterArgs a) {
+__global__ __launch_bounds__(kMatchWaves * kWave) void sel_match_kernel(ClusterArgs a0,
+                                                                        ClusterSlots sl) {
+  const ClusterArgs a = slot_args(a0, sl);
   __shared__ float xs[kMatchWaves][kMaxSelCv];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int f0 = a.state[1];
@@ -151,8 +177,10 @@ __global__ __launch_bounds__(kMatchWaves * kWave) void sel_match_kernel(ClusterA
 // there.  The mask words read are cleared for the next round.
 constexpr int kResolveWaves = 4;
 constexpr int kXbBatch = 16;
-__global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(ClusterArgs a,
+__global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(ClusterArgs a0,
+                                                                            ClusterSlots sl,
                                                                             int nlmax, int gmax) {
+  const ClusterArgs a = slot_args(a0, sl);
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int sh[6];   // new leaders so far, stop frame, over the cap, walk start,
                           // end of the matched run, the frame founding a leader
@@ -315,28 +343,32 @@ size_t resolve_lds(int n, int nlmax, int gmax) {
          sizeof(float) * ((size_t)nlmax + gmax) * n;
 }
 
-// Device memory of one clustering call.
+// Device memory of one clustering call: `slots` copies of the per-pass
+// buffers (labels only with more than one slot; one slot writes the caller's).
 struct ClusterWs {
   float* LT = nullptr;
   int* leader = nullptr;
   int* state = nullptr;
+  int* labels = nullptr;
   unsigned long long* pend = nullptr;
   ~ClusterWs() {
     if (LT) (void)hipFree(LT);
     if (leader) (void)hipFree(leader);
     if (state) (void)hipFree(state);
+    if (labels) (void)hipFree(labels);
     if (pend) (void)hipFree(pend);
   }
 };
 
-// One clustering at threshold t; synchronises the stream.  On return
-// state_h = {leaders, next frame, over the cap}.
-rid_status cluster_once(ClusterArgs a, float t, int nlmax, int gmax, hipStream_t st,
-                        int state_h[3]) {
-  a.t2 = t * t;
+// One clustering pass at thresholds t[0..T) side by side (slot k at t[k]);
+// synchronises the stream.  On return st_h[k * kStateInts + 0..2] = {leaders,
+// next frame, over the cap} of slot k.
+rid_status cluster_pass(ClusterArgs a, ClusterSlots sl, const float* t, int T, int nlmax,
+                        int gmax, hipStream_t st, int* st_h) {
+  for (int k = 0; k < T; ++k) sl.t2[k] = t[k] * t[k];
   const int words = (a.B + 63) / 64;
-  hipLaunchKernelGGL(sel_init_kernel, dim3(std::min((words + 255) / 256 + 1, 1024)), dim3(256), 0,
-                     st, a.state, a.pend, words);
+  hipLaunchKernelGGL(sel_init_kernel, dim3(std::min((words + 255) / 256 + 1, 1024), T), dim3(256),
+                     0, st, a.state, a.pend, words);
   RID_HIP(hipGetLastError());
   const size_t lds = resolve_lds(a.n, nlmax, gmax);
   static size_t attr = 0;
@@ -360,16 +392,15 @@ rid_status cluster_once(ClusterArgs a, float t, int nlmax, int gmax, hipStream_t
   for (int i = 0; i <= stops + 1; ++i) chunks.push_back(kChunkMax);
   for (int ch : chunks) {
     a.chunk = ch;
-    hipLaunchKernelGGL(sel_match_kernel, dim3((ch + kMatchWaves - 1) / kMatchWaves),
-                       dim3(kMatchWaves * kWave), 0, st, a);
+    hipLaunchKernelGGL(sel_match_kernel, dim3((ch + kMatchWaves - 1) / kMatchWaves, T),
+                       dim3(kMatchWaves * kWave), 0, st, a, sl);
     RID_HIP(hipGetLastError());
-    hipLaunchKernelGGL(sel_resolve_kernel, dim3(1), dim3(kResolveWaves * kWave), (uint32_t)lds,
-                       st, a, nlmax, gmax);
+    hipLaunchKernelGGL(sel_resolve_kernel, dim3(1, T), dim3(kResolveWaves * kWave), (uint32_t)lds,
+                       st, a, sl, nlmax, gmax);
     RID_HIP(hipGetLastError());
   }
-  RID_HIP(hipMemcpyAsync(state_h, a.state, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+  RID_HIP(hipMemcpyAsync(st_h, a.state, sizeof(int) * kStateInts * T, hipMemcpyDeviceToHost, st));
   RID_HIP(hipStreamSynchronize(st));
-  if (state_h[1] < a.B) return fail(RID_EDEVICE, "clustering did not reach the last frame");
   return RID_OK;
 }
 
@@ -380,11 +411,19 @@ rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw, cons
                           float eps0, float threshold, int lower, int upper, int adapt, int cap,
                           int* labels, int* leaders, int leaders_out, int* n_leaders,
                           int* n_clusters, float* t_used, hipStream_t st) {
+  const int words = (B + 63) / 64;
+  // slots: one without adaptation; with it as many as fit in 256 MiB, at most kSlots
+  const size_t per_slot = sizeof(float) * (size_t)n * cap + sizeof(int) * (size_t)cap +
+                          sizeof(int) * (size_t)B + sizeof(unsigned long long) * words +
+                          sizeof(int) * kStateInts;
+  const int T = adapt ? (int)std::max<size_t>(1, std::min<size_t>(kSlots, (256u << 20) / per_slot))
+                      : 1;
   ClusterWs ws;
-  RID_HIP(hipMalloc(&ws.LT, sizeof(float) * (size_t)n * cap));
-  RID_HIP(hipMalloc(&ws.leader, sizeof(int) * (size_t)cap));
-  RID_HIP(hipMalloc(&ws.state, sizeof(int) * 4));
-  RID_HIP(hipMalloc(&ws.pend, sizeof(unsigned long long) * (size_t)((B + 63) / 64)));
+  RID_HIP(hipMalloc(&ws.LT, sizeof(float) * (size_t)n * cap * T));
+  RID_HIP(hipMalloc(&ws.leader, sizeof(int) * (size_t)cap * T));
+  RID_HIP(hipMalloc(&ws.state, sizeof(int) * kStateInts * T));
+  RID_HIP(hipMalloc(&ws.pend, sizeof(unsigned long long) * (size_t)words * T));
+  if (T > 1) RID_HIP(hipMalloc(&ws.labels, sizeof(int) * (size_t)B * T));
   ClusterArgs a{};
   a.s = s;
   a.raw = raw;
@@ -397,26 +436,55 @@ rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw, cons
   a.LT = ws.LT;
   a.leader = ws.leader;
   a.state = ws.state;
-  a.labels = labels;
+  a.labels = T > 1 ? ws.labels : labels;
   a.pend = ws.pend;
+  ClusterSlots sl{};
+  sl.sLT = (long long)n * cap;
+  sl.sLabels = T > 1 ? B : 0;
+  sl.sLeader = cap;
+  sl.sPend = words;
   const int nlmax = kLdsRows / n;                       // >= 64 for n <= 256
   const int gmax = std::min(256, kLdsRows / n);
   // threshold adjustment (first iteration of the workflow): x1.1 while
-  // above the window, /1.1 while below, at most 100 adjustments
+  // above the window, /1.1 while below, at most 100 adjustments.  The
+  // passes run T thresholds at a time: the next ones the rule would reach
+  // if the count kept its side of the window (both directions around the
+  // first threshold), and the rule then takes its steps over those results
+  // in its own order, so the outcome is that of one threshold per pass.
   constexpr int kMaxAdjust = 100;
   float t = threshold;
-  int state_h[3] = {0, 0, 0};
-  int count = 0;
+  float ts[kSlots];
+  std::vector<int> st_h((size_t)kStateInts * T);
+  int nt = 0, dir = 0, k = 0, count = 0;
   for (int it = 0;; ++it) {
-    rid_status r = cluster_once(a, t, nlmax, gmax, st, state_h);
-    if (r != RID_OK) return r;
-    count = state_h[0] + (state_h[2] ? 1 : 0);
+    k = 0;
+    while (k < nt && !(ts[k] == t)) ++k;
+    if (k == nt) {   // not among the last pass's thresholds
+      nt = T;
+      ts[0] = t;
+      const int up = dir > 0 ? T - 1 : dir < 0 ? 0 : (2 * (T - 1) + 2) / 3;
+      for (int j = 1; j < T; ++j) {
+        if (j <= up) ts[j] = ts[j - 1] * 1.1f;
+        else ts[j] = (j == up + 1 ? ts[0] : ts[j - 1]) / 1.1f;
+      }
+      rid_status r = cluster_pass(a, sl, ts, T, nlmax, gmax, st, st_h.data());
+      if (r != RID_OK) return r;
+      k = 0;
+    }
+    const int* sk = st_h.data() + (size_t)k * kStateInts;
+    if (sk[1] < B) return fail(RID_EDEVICE, "clustering did not reach the last frame");
+    count = sk[0] + (sk[2] ? 1 : 0);
     if (!adapt || (count >= lower && count <= upper) || it == kMaxAdjust) break;
-    t = count > upper ? t * 1.1f : t / 1.1f;
+    dir = count > upper ? 1 : -1;
+    t = dir > 0 ? t * 1.1f : t / 1.1f;
   }
-  const int nl = std::min(state_h[0], leaders_out);
+  const int* sk = st_h.data() + (size_t)k * kStateInts;
+  if (T > 1)
+    RID_HIP(hipMemcpyAsync(labels, ws.labels + (size_t)k * B, sizeof(int) * (size_t)B,
+                           hipMemcpyDeviceToDevice, st));
+  const int nl = std::min(sk[0], leaders_out);
   if (leaders && nl > 0)
-    RID_HIP(hipMemcpyAsync(leaders, ws.leader, sizeof(int) * (size_t)nl,
+    RID_HIP(hipMemcpyAsync(leaders, ws.leader + (size_t)k * cap, sizeof(int) * (size_t)nl,
                            hipMemcpyDeviceToDevice, st));
   RID_HIP(hipStreamSynchronize(st));
   if (n_leaders) *n_leaders = nl;

@@ -110,6 +110,19 @@ def test_threshold_adaptation_matches_oracle(torch, rid, t0):
     assert 30 <= gn <= 45
 
 
+def test_threshold_adaptation_that_never_settles(torch, rid):
+    # 50 frames at equal mutual distance sqrt(2) (frame i has CV i = 1):
+    # below sqrt(2) every frame founds a cluster, at or above it one frame
+    # leads them all, so the count never enters [10, 20]; the threshold
+    # steps back and forth until the 100th adjustment ends the rule
+    s = np.eye(50, dtype=np.float32)
+    for t0 in (1.3, 1.5):
+        t, (labels, leaders, n) = O.adapt_threshold(s, t0, 10, 20)
+        gl, gld, gn, gt = _gpu_cluster(torch, rid, s, t0, adapt=True, lower=10, upper=20)
+        assert n in (1, 50)
+        assert np.float32(gt) == t and gn == n and gld == leaders and np.array_equal(gl, labels)
+
+
 def test_select_matches_oracle(torch, rid):
     n, widths, K = 38, [64, 64], 4
     params = ridgen.xavier_ensemble(2 * n, widths, K, 21, bias_std=0.1)
