@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kMatchWaves * kWave) void sel_match_kernel(ClusterA
 // The chunk's unmatched frames, in order, against the leaders founded in
 // this chunk (LDS, nlmax at most); new leaders are founded here.  The chunk's
 // mask words come in one batch of loads, the unmatched frames' CVs in groups
-// of up to gmax frames.  Per group, the four waves first match every frame
+// of up to gmax frames.  Per group, each thread first matches a frame
 // against the chunk's leaders founded before the group (its first match
 // overall if any, since later leaders only append); the walk then founds a
 // leader at the first frame still unmatched, after which the rest of the
@@ -255,15 +255,16 @@ __global__ __launch_bounds__(kResolveWaves * kWave) void sel_resolve_kernel(Clus
       }
     }
     __syncthreads();
-    for (int q = wave; q < g; q += kResolveWaves) {
+    // a thread per frame, the chunk's leaders in founding order up to the
+    // first within the threshold (few leaders: lanes over them would idle)
+    for (int q = tid; q < g; q += kResolveWaves * kWave) {
       int hitj = -1;
-      for (int j0 = 0; j0 < n_new0 && hitj < 0; j0 += kWave) {
-        const int j = j0 + lane;
-        const bool hit = j < n_new0 && leader_d2(NL + (size_t)j * n, 1, XB + (size_t)q * n, n, a.raw, a.w) <= a.t2;
-        const unsigned long long m = __ballot(hit);
-        if (m) hitj = j0 + __ffsll((long long)m) - 1;
-      }
-      if (lane == 0) gm[q] = hitj;
+      for (int j = 0; j < n_new0; ++j)
+        if (leader_d2(NL + (size_t)j * n, 1, XB + (size_t)q * n, n, a.raw, a.w) <= a.t2) {
+          hitj = j;
+          break;
+        }
+      gm[q] = hitj;
     }
     __syncthreads();
     // ordered walk: wave 0 finds the first frame at or after the walk's
