@@ -344,20 +344,13 @@ size_t resolve_lds(int n, int nlmax, int gmax) {
          sizeof(float) * ((size_t)nlmax + gmax) * n;
 }
 
-// Device memory of one clustering call: `slots` copies of the per-pass
-// buffers (labels only with more than one slot; one slot writes the caller's).
+// Device memory of one clustering call (one allocation): `slots` copies of
+// the per-pass buffers (labels only with more than one slot; one slot
+// writes the caller's).
 struct ClusterWs {
-  float* LT = nullptr;
-  int* leader = nullptr;
-  int* state = nullptr;
-  int* labels = nullptr;
-  unsigned long long* pend = nullptr;
+  void* buf = nullptr;
   ~ClusterWs() {
-    if (LT) (void)hipFree(LT);
-    if (leader) (void)hipFree(leader);
-    if (state) (void)hipFree(state);
-    if (labels) (void)hipFree(labels);
-    if (pend) (void)hipFree(pend);
+    if (buf) (void)hipFree(buf);
   }
 };
 
@@ -419,12 +412,19 @@ rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw, cons
                           sizeof(int) * kStateInts;
   const int T = adapt ? (int)std::max<size_t>(1, std::min<size_t>(kSlots, (256u << 20) / per_slot))
                       : 1;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t b_lt = al(sizeof(float) * (size_t)n * cap * T), b_ld = al(sizeof(int) * (size_t)cap * T),
+               b_st = al(sizeof(int) * kStateInts * T),
+               b_pd = al(sizeof(unsigned long long) * (size_t)words * T),
+               b_lb = T > 1 ? al(sizeof(int) * (size_t)B * T) : 0;
   ClusterWs ws;
-  RID_HIP(hipMalloc(&ws.LT, sizeof(float) * (size_t)n * cap * T));
-  RID_HIP(hipMalloc(&ws.leader, sizeof(int) * (size_t)cap * T));
-  RID_HIP(hipMalloc(&ws.state, sizeof(int) * kStateInts * T));
-  RID_HIP(hipMalloc(&ws.pend, sizeof(unsigned long long) * (size_t)words * T));
-  if (T > 1) RID_HIP(hipMalloc(&ws.labels, sizeof(int) * (size_t)B * T));
+  RID_HIP(hipMalloc(&ws.buf, b_lt + b_ld + b_st + b_pd + b_lb));
+  unsigned char* wp = static_cast<unsigned char*>(ws.buf);
+  float* ws_LT = reinterpret_cast<float*>(wp);
+  int* ws_leader = reinterpret_cast<int*>(wp + b_lt);
+  int* ws_state = reinterpret_cast<int*>(wp + b_lt + b_ld);
+  unsigned long long* ws_pend = reinterpret_cast<unsigned long long*>(wp + b_lt + b_ld + b_st);
+  int* ws_labels = T > 1 ? reinterpret_cast<int*>(wp + b_lt + b_ld + b_st + b_pd) : nullptr;
   ClusterArgs a{};
   a.s = s;
   a.raw = raw;
@@ -434,11 +434,11 @@ rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw, cons
   a.B = B;
   a.n = n;
   a.cap = cap;
-  a.LT = ws.LT;
-  a.leader = ws.leader;
-  a.state = ws.state;
-  a.labels = T > 1 ? ws.labels : labels;
-  a.pend = ws.pend;
+  a.LT = ws_LT;
+  a.leader = ws_leader;
+  a.state = ws_state;
+  a.labels = T > 1 ? ws_labels : labels;
+  a.pend = ws_pend;
   ClusterSlots sl{};
   sl.sLT = (long long)n * cap;
   sl.sLabels = T > 1 ? B : 0;
@@ -481,11 +481,11 @@ rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw, cons
   }
   const int* sk = st_h.data() + (size_t)k * kStateInts;
   if (T > 1)
-    RID_HIP(hipMemcpyAsync(labels, ws.labels + (size_t)k * B, sizeof(int) * (size_t)B,
+    RID_HIP(hipMemcpyAsync(labels, ws_labels + (size_t)k * B, sizeof(int) * (size_t)B,
                            hipMemcpyDeviceToDevice, st));
   const int nl = std::min(sk[0], leaders_out);
   if (leaders && nl > 0)
-    RID_HIP(hipMemcpyAsync(leaders, ws.leader + (size_t)k * cap, sizeof(int) * (size_t)nl,
+    RID_HIP(hipMemcpyAsync(leaders, ws_leader + (size_t)k * cap, sizeof(int) * (size_t)nl,
                            hipMemcpyDeviceToDevice, st));
   RID_HIP(hipStreamSynchronize(st));
   if (n_leaders) *n_leaders = nl;
