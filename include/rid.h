@@ -250,7 +250,7 @@ rid_status rid_model_dev(rid_ensemble ens, const float* d_s, int B,
  *   d_leaders  [max_clusters] device  OUT: frame index of each leader
  *   n_clusters host  OUT: clusters founded (+1 when the cap was hit)
  * Synchronises the stream; allocates and frees its scratch per call (with
- * adapt: up to 16 thresholds' labels, leaders and leader CVs, at most
+ * adapt: up to 24 thresholds' labels, leaders and leader CVs, at most
  * 256 MiB, clustered side by side; the result is the one-threshold-at-a-
  * time result).
  * Errors: RID_EINVAL (NULL pointer, B < 1, n_cv outside [1, 256], threshold

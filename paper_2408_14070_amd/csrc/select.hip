@@ -37,7 +37,7 @@ constexpr int kMatchWaves = 4;
 constexpr int kMaxSelCv = 256;
 constexpr int kChunkMax = 8192;
 constexpr int kLdsRows = 16384;    // floats for the new leaders, and again for a frame group
-constexpr int kSlots = 16;         // thresholds clustered side by side in one pass
+constexpr int kSlots = 24;         // thresholds clustered side by side in one pass
 
 struct ClusterArgs {
   const float* s;        // [B][n] frames
