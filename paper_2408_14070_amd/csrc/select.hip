@@ -24,6 +24,7 @@
 // leaders are found by the single wave over few frames and most frames are
 // then resolved by the parallel kernel.
 #include "device_common.h"
+#include "select_core.h"
 
 namespace rid {
 namespace {
@@ -38,6 +39,7 @@ constexpr int kMaxSelCv = 256;
 constexpr int kChunkMax = 8192;
 constexpr int kLdsRows = 16384;    // floats for the new leaders, and again for a frame group
 constexpr int kSlots = 24;         // thresholds clustered side by side in one pass
+static_assert(kSlots <= selcore::kMaxSlots, "slot count");
 
 struct ClusterArgs {
   const float* s;        // [B][n] frames
@@ -446,39 +448,25 @@ rid_status launch_cluster(const float* s, int B, int n, const uint8_t* raw, cons
   sl.sPend = words;
   const int nlmax = kLdsRows / n;                       // >= 64 for n <= 256
   const int gmax = std::min(256, kLdsRows / n);
-  // threshold adjustment (first iteration of the workflow): x1.1 while
-  // above the window, /1.1 while below, at most 100 adjustments.  The
-  // passes run T thresholds at a time: the next ones the rule would reach
-  // if the count kept its side of the window (both directions around the
-  // first threshold), and the rule then takes its steps over those results
-  // in its own order, so the outcome is that of one threshold per pass.
-  constexpr int kMaxAdjust = 100;
-  float t = threshold;
-  float ts[kSlots];
+  // threshold adjustment (first iteration of the workflow), T thresholds
+  // per pass (select_core.h)
   std::vector<int> st_h((size_t)kStateInts * T);
-  int nt = 0, dir = 0, k = 0, count = 0;
-  for (int it = 0;; ++it) {
-    k = 0;
-    while (k < nt && !(ts[k] == t)) ++k;
-    if (k == nt) {   // not among the last pass's thresholds
-      nt = T;
-      ts[0] = t;
-      const int up = dir > 0 ? T - 1 : dir < 0 ? 0 : (2 * (T - 1) + 2) / 3;
-      for (int j = 1; j < T; ++j) {
-        if (j <= up) ts[j] = ts[j - 1] * 1.1f;
-        else ts[j] = (j == up + 1 ? ts[0] : ts[j - 1]) / 1.1f;
-      }
-      rid_status r = cluster_pass(a, sl, ts, T, nlmax, gmax, st, st_h.data());
-      if (r != RID_OK) return r;
-      k = 0;
+  auto pass = [&](const float* ts, int nts, int* counts) -> int {
+    const rid_status r = cluster_pass(a, sl, ts, nts, nlmax, gmax, st, st_h.data());
+    if (r != RID_OK) return r;
+    for (int j = 0; j < nts; ++j) {
+      const int* sj = st_h.data() + (size_t)j * kStateInts;
+      counts[j] = sj[1] < B ? -1 : sj[0] + (sj[2] ? 1 : 0);
     }
-    const int* sk = st_h.data() + (size_t)k * kStateInts;
-    if (sk[1] < B) return fail(RID_EDEVICE, "clustering did not reach the last frame");
-    count = sk[0] + (sk[2] ? 1 : 0);
-    if (!adapt || (count >= lower && count <= upper) || it == kMaxAdjust) break;
-    dir = count > upper ? 1 : -1;
-    t = dir > 0 ? t * 1.1f : t / 1.1f;
-  }
+    return 0;
+  };
+  selcore::Outcome res;
+  const int rr = selcore::adjust_threshold(threshold, lower, upper, adapt != 0, T, pass, res);
+  if (rr == selcore::kIncomplete)
+    return fail(RID_EDEVICE, "clustering did not reach the last frame");
+  if (rr != 0) return (rid_status)rr;
+  const int k = res.slot, count = res.count;
+  const float t = res.t;
   const int* sk = st_h.data() + (size_t)k * kStateInts;
   if (T > 1)
     RID_HIP(hipMemcpyAsync(labels, ws_labels + (size_t)k * B, sizeof(int) * (size_t)B,
