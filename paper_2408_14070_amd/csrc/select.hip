@@ -22,7 +22,9 @@
 // first match among the earlier leaders is its first match overall, because
 // later leaders only append.  Chunks grow from 64 frames, so the first
 // leaders are found by the single wave over few frames and most frames are
-// then resolved by the parallel kernel.
+// then resolved by the parallel kernel.  With threshold adjustment, one pass
+// clusters up to kSlots thresholds side by side (blockIdx.y = slot, each with
+// its own workspace); select_core.h takes the rule's steps over their counts.
 #include "device_common.h"
 #include "select_core.h"
 
