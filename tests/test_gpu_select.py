@@ -2,6 +2,8 @@
 against the oracle, through the C ABI.  Cluster labels, leaders, counts and
 adapted thresholds are integer / FP32-decided results: both sides decide
 d^2 <= t^2 in the same FP32 arithmetic, so they must agree exactly."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -108,6 +110,24 @@ def test_threshold_adaptation_matches_oracle(torch, rid, t0):
     gl, gld, gn, gt = _gpu_cluster(torch, rid, s, t0, adapt=True, lower=30, upper=45)
     assert np.float32(gt) == t and gn == n and gld == leaders and np.array_equal(gl, labels)
     assert 30 <= gn <= 45
+
+
+@functools.lru_cache(maxsize=None)
+def _adapted_3000():
+    s = ridgen.exploration_frames(20, 150, 38, 30, 0.3, seed=11)
+    return s, O.adapt_threshold(s, 1.5, 30, 45)   # five steps up: 1.5 -> 2.42
+
+
+@pytest.mark.parametrize("max_clusters", [4096, 560_000, 2_000_000])
+def test_threshold_adaptation_with_few_slots(torch, rid, max_clusters):
+    # 38 CVs: a cap of 560k clusters leaves room for 3 thresholds per pass in
+    # the 256 MiB scratch budget, 2M for one (labels then go straight to the
+    # caller's buffer); 4096 takes the full 24.  The cap is never reached.
+    s, (t, (labels, leaders, n)) = _adapted_3000()
+    gl, gld, gn, gt = _gpu_cluster(torch, rid, s, 1.5, adapt=True, lower=30, upper=45,
+                                   max_clusters=max_clusters)
+    print(f"cap {max_clusters}: t={t} n={n}", flush=True)
+    assert np.float32(gt) == t and gn == n and gld == leaders and np.array_equal(gl, labels)
 
 
 def test_threshold_adaptation_that_never_settles(torch, rid):
